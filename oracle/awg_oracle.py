@@ -1,0 +1,582 @@
+"""FP64 CPU oracle of PCG preconditioned by the additive AWG preconditioner.
+
+TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the
+CPU-baseline leg of the benchmark may import this module.  The GPU library
+never calls it, and it shares no code with the GPU library.
+
+What it computes (Gouarin & Spillane, "Fully algebraic domain decomposition
+preconditioners with adaptive spectral bounds"):
+
+    H = H3,ad = H2 + W (W^T A W)^{-1} W^T           (Definition of Pi_3 / H3, Section 4.3)
+    H2 = H^NN_hyb(tau)                               (Theorem for H^NN with GenEO, Section 3.4)
+       = Pi H^NN Pi^T + R0^T E0^{-1} R0,  E0 = R0 A_+ R0^T,
+         Pi = I - R0^T E0^{-1} R0 A_+
+    H^NN = sum_s R^sT D^s (A^s_+)^dagger D^s R^s      (Definition of H^NN, Section 3.3)
+
+The steps follow the paper's order and notation.  Dense LAPACK (numpy /
+scipy) is used for every local and coarse problem; no iterative
+eigensolver is involved.  Readings where the paper is silent:
+
+* zero eigenvalues of B^s (Remark after the A_+ theorem, Section 3.2): an
+  eigenvalue lambda counts as non-positive when lambda <= eps0 * max|lambda|,
+  eps0 = 1e-12 by default; only strictly negative ones (lambda < -eps0 *
+  max|lambda|) give columns of the second coarse space (Remark 1, Section 4.4).
+* GenEO selection is the strict lambda < tau of the Y_L definition (Section 3.4).
+* PCG starts from x0 = 0 and stops at the first k with ||r_k||_2 / ||b||_2 <= tol
+  on the recursively updated residual; the iteration count is the number
+  of products A p.
+"""
+from __future__ import annotations
+
+import dataclasses
+import numpy as np
+import scipy.linalg as sla
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+
+class OracleError(ValueError):
+    """Invalid input for the method (not a bug in the oracle)."""
+
+
+# ---------------------------------------------------------------------------
+# Section 2: subdomains, restriction, partition of unity, coloring
+# ---------------------------------------------------------------------------
+def check_inputs(A: sp.csr_matrix, subs) -> None:
+    """Validate A and the index sets (Definition of a partition and Assumption
+    of minimal overlap, Section 2.1).  Raises OracleError."""
+    n = A.shape[0]
+    if A.shape[0] != A.shape[1]:
+        raise OracleError("A is not square")
+    if abs(A - A.T).max() if A.nnz else 0.0:
+        raise OracleError("A is not symmetric")
+    covered = np.zeros(n, dtype=bool)
+    for s, idx in enumerate(subs):
+        idx = np.asarray(idx)
+        if idx.size == 0:
+            raise OracleError(f"subdomain {s} is empty")
+        if idx.min() < 0 or idx.max() >= n:
+            raise OracleError(f"subdomain {s} has an index out of range")
+        if np.any(np.diff(idx) <= 0):
+            raise OracleError(f"subdomain {s} is not sorted and unique")
+        covered[idx] = True
+    if not covered.all():
+        raise OracleError("the subdomains do not cover [0, n)")
+    cnt = pair_multiplicity(A, subs)
+    if np.any(cnt == 0):
+        raise OracleError("minimal overlap assumption violated")
+
+
+def multiplicity(n: int, subs) -> np.ndarray:
+    """Diagonal of sum_t R^tT R^t: number of subdomains holding each dof (Section 2.2)."""
+    m = np.zeros(n, dtype=np.int64)
+    for idx in subs:
+        m[idx] += 1
+    return m
+
+
+def partition_of_unity(n: int, subs):
+    """D = (sum_t R^tT R^t)^{-1} and D^s = R^s D R^sT (Definition of D^s, Section 2.2).
+
+    Returns the list of diagonals of the D^s.
+    """
+    d = 1.0 / multiplicity(n, subs)
+    return [d[idx] for idx in subs]
+
+
+def coloring_constant(subs, M_pattern: sp.csr_matrix) -> int:
+    """A valid coloring constant N(M) (Definition of the coloring constant, Section 2.2).
+
+    s and t conflict when R^s M R^tT != 0, i.e. when M has a nonzero (i, j)
+    with i in Omega^s and j in Omega^t.  Greedy coloring of that conflict
+    graph; any valid coloring gives a valid bound.
+    """
+    N = len(subs)
+    n = M_pattern.shape[0]
+    P = sp.csr_matrix((np.ones(sum(len(s) for s in subs)),
+                       (np.concatenate([np.full(len(s), k) for k, s in enumerate(subs)]),
+                        np.concatenate(subs))), shape=(N, n))
+    Mb = (abs(M_pattern) > 0).astype(np.float64)
+    C = (P @ Mb @ P.T).toarray() > 0
+    color = -np.ones(N, dtype=np.int64)
+    for s in range(N):
+        used = set(color[np.flatnonzero(C[s])].tolist())
+        c = 0
+        while c in used:
+            c += 1
+        color[s] = c
+    return int(color.max() + 1)
+
+
+# ---------------------------------------------------------------------------
+# Section 3.1: algebraic splitting A = sum_s R^sT B^s R^s
+# ---------------------------------------------------------------------------
+def pair_multiplicity(A: sp.csr_matrix, subs) -> np.ndarray:
+    """M_mu on the pattern of A: for each stored nonzero (i, j) of A (CSR order),
+    the number of subdomains containing both i and j (Definition of B^s and the
+    theorem that follows it, Section 3.1).  Counted directly."""
+    n = A.shape[0]
+    A = A.tocsr()
+    rows = np.repeat(np.arange(n), np.diff(A.indptr))
+    cols = A.indices
+    cnt = np.zeros(A.nnz, dtype=np.int64)
+    mask = np.zeros(n, dtype=bool)
+    for idx in subs:
+        mask[:] = False
+        mask[idx] = True
+        cnt += (mask[rows] & mask[cols])
+    return cnt
+
+
+def algebraic_B(A: sp.csr_matrix, cnt: np.ndarray) -> sp.csr_matrix:
+    """B = A (Hadamard-divided by) M_mu on the pattern of A (Definition of B^s, Section 3.1)."""
+    B = A.tocsr().copy()
+    B.data = A.data / cnt
+    return B
+
+
+def local_block(M: sp.csr_matrix, idx) -> np.ndarray:
+    """Dense R^s M R^sT."""
+    return M[idx][:, idx].toarray()
+
+
+# ---------------------------------------------------------------------------
+# Section 3.2: B^s = A^s_+ - A^s_-, A_+ = sum R^sT A^s_+ R^s
+# ---------------------------------------------------------------------------
+@dataclasses.dataclass
+class LocalSplit:
+    lam: np.ndarray        # all eigenvalues of B^s, ascending
+    V: np.ndarray          # orthonormal eigenvectors (columns)
+    nneg: int              # n^s_-: number of non-positive eigenvalues (incl. numerical zeros)
+    nstrict: int           # number of strictly negative eigenvalues (second coarse space)
+    thr: float             # eps0 * max|lambda|
+
+    @property
+    def V_minus(self):
+        return self.V[:, :self.nneg]
+
+    @property
+    def L_minus(self):
+        return self.lam[:self.nneg]
+
+    @property
+    def V_plus(self):
+        return self.V[:, self.nneg:]
+
+    @property
+    def L_plus(self):
+        return self.lam[self.nneg:]
+
+    def A_plus(self):
+        """A^s_+ = V_+ L_+ V_+^T (Definition of the splitting of B^s, Section 3.2)."""
+        return (self.V_plus * self.L_plus) @ self.V_plus.T
+
+    def A_minus(self):
+        """A^s_- = - V_- L_- V_-^T."""
+        return -(self.V_minus * self.L_minus) @ self.V_minus.T
+
+    def A_plus_pinv(self):
+        """(A^s_+)^dagger = V_+ L_+^{-1} V_+^T (Definition of H^NN, Section 3.3)."""
+        return (self.V_plus / self.L_plus) @ self.V_plus.T
+
+
+def split_local(Bs: np.ndarray, eps0: float = 1e-12) -> LocalSplit:
+    """Diagonalise B^s (eigenvalues ascending) and split off the non-positive part.
+
+    Zero eigenvalues go into L_- as the paper chooses (remark after the
+    A_+ theorem); "zero" means |lambda| <= eps0 * max|lambda|.
+    """
+    lam, V = np.linalg.eigh(Bs)
+    scale = np.max(np.abs(lam)) if lam.size else 0.0
+    thr = eps0 * scale
+    nneg = int(np.count_nonzero(lam <= thr))
+    nstrict = int(np.count_nonzero(lam < -thr))
+    return LocalSplit(lam, V, nneg, nstrict, thr)
+
+
+# ---------------------------------------------------------------------------
+# the whole setup
+# ---------------------------------------------------------------------------
+@dataclasses.dataclass
+class AWGSetup:
+    A: sp.csr_matrix
+    subs: list
+    tau: float
+    Ds: list                      # partition of unity diagonals D^s
+    cnt: np.ndarray               # M_mu on the pattern of A
+    B: sp.csr_matrix
+    split: list                   # LocalSplit per subdomain
+    Y: list                       # GenEO vectors Y^s (n_s x m_s), M_B-normalised
+    geneo_lam: list               # all GenEO eigenvalues per subdomain (ascending)
+    R0T: sp.csr_matrix            # n x n0 coarse basis [R^1T Y^1 | ... ]
+    E0: np.ndarray
+    E0_cho: tuple
+    W: np.ndarray                 # n x n_-
+    EW: np.ndarray
+    EW_cho: tuple
+    Vg: np.ndarray                # prolongated strictly negative eigenvectors
+    w_info: dict
+
+    @property
+    def n(self):
+        return self.A.shape[0]
+
+    @property
+    def n0(self):
+        return self.R0T.shape[1]
+
+    @property
+    def n_minus(self):
+        return self.W.shape[1]
+
+    # -- A_- and A_+ actions (Definition of A_+ and A_-, Section 3.2) -----
+    def A_minus_mv(self, X):
+        """A_- X = sum_s R^sT A^s_- R^s X (A^s_- applied through its eigenvectors)."""
+        X = np.asarray(X)
+        out = np.zeros_like(X, dtype=np.float64)
+        for idx, sp_ in zip(self.subs, self.split):
+            if sp_.nneg == 0:
+                continue
+            Vm = sp_.V_minus
+            out[idx] += -(Vm * sp_.L_minus) @ (Vm.T @ X[idx])
+        return out
+
+    def A_plus_mv(self, X):
+        """A_+ X = A X + A_- X (item (i) of the A_+ theorem, Section 3.2)."""
+        return self.A @ X + self.A_minus_mv(X)
+
+    # -- one-level H^NN (Section 3.3) -----------------------------------
+    def H_NN(self, X):
+        out = np.zeros_like(X, dtype=np.float64)
+        for idx, Ds, sp_ in zip(self.subs, self.Ds, self.split):
+            Xs = X[idx]
+            Xs = Ds[:, None] * Xs if Xs.ndim == 2 else Ds * Xs
+            Ys = sp_.V_plus @ ((sp_.V_plus.T @ Xs) / (sp_.L_plus[:, None] if Xs.ndim == 2 else sp_.L_plus))
+            out[idx] += Ds[:, None] * Ys if Xs.ndim == 2 else Ds * Ys
+        return out
+
+    # -- coarse solve with E0 -------------------------------------------
+    def E0_solve(self, g):
+        return sla.cho_solve(self.E0_cho, g)
+
+    def H2(self, r):
+        """H2 = Pi H^NN Pi^T + R0^T E0^{-1} R0 (Theorem for H^NN_hyb, Section 3.4)."""
+        u0 = self.E0_solve(self.R0T.T @ r)                    # E0^{-1} R0 r
+        t = r - self.A_plus_mv(self.R0T @ u0)                 # Pi^T r
+        y = self.H_NN(t)                                      # H^NN Pi^T r
+        v = self.E0_solve(self.R0T.T @ self.A_plus_mv(y))     # E0^{-1} R0 A_+ y
+        return y - self.R0T @ v + self.R0T @ u0               # Pi y + R0^T E0^{-1} R0 r
+
+    def apply(self, r):
+        """H r with H = H3,ad = H2 + W (W^T A W)^{-1} W^T (Definition, Section 4.3)."""
+        z = self.H2(r)
+        if self.n_minus:
+            z = z + self.W @ sla.cho_solve(self.EW_cho, self.W.T @ r)
+        return z
+
+
+def geneo_local(sp_: LocalSplit, Ds: np.ndarray, MB: np.ndarray, tau: float):
+    """GenEO modes of subdomain s for H^NN_hyb (Theorem, Section 3.4).
+
+    Pencil M_A = (D^s)^{-1} A^s_+ (D^s)^{-1}, M_B = R^s A_+ R^sT.  All
+    M_B-normalised eigenvectors with eigenvalue < tau (strict), ascending
+    (Definition of Y_L).
+    """
+    Dinv = 1.0 / Ds
+    MA = Dinv[:, None] * sp_.A_plus() * Dinv[None, :]
+    MA = 0.5 * (MA + MA.T)
+    MB = 0.5 * (MB + MB.T)
+    lam, Y = sla.eigh(MA, MB)          # M_B-orthonormal, ascending
+    m = int(np.count_nonzero(lam < tau))
+    return Y[:, :m], lam
+
+
+def local_MB(A: sp.csr_matrix, subs, split, s: int) -> np.ndarray:
+    """M_B^s = R^s A_+ R^sT = R^s A R^sT + sum_t (R^s R^tT) A^t_- (R^t R^sT)
+    (Definition of A_+, Section 3.2; written as in Remark 4, Section 4.4)."""
+    idx = subs[s]
+    MB = local_block(A, idx)
+    for t, idt in enumerate(subs):
+        if split[t].nneg == 0:
+            continue
+        common, ps, pt = np.intersect1d(idx, idt, assume_unique=True, return_indices=True)
+        if common.size == 0:
+            continue
+        Vt = split[t].V_minus[pt]                       # rows of V^t_- on the common dofs
+        MB[np.ix_(ps, ps)] += -(Vt * split[t].L_minus) @ Vt.T
+    return MB
+
+
+def setup(A: sp.csr_matrix, subs, tau: float, eps0: float = 1e-12, w_solver: str = "auto",
+          w_rtol: float = 1e-13, w_maxit: int = 500, check: bool = True) -> AWGSetup:
+    """Build every ingredient of H3,ad with H2 = H^NN_hyb(tau)."""
+    A = sp.csr_matrix(A, dtype=np.float64)
+    A.sort_indices()
+    n = A.shape[0]
+    subs = [np.asarray(s, dtype=np.int64) for s in subs]
+    if not (0.0 < tau < 1.0):
+        raise OracleError("tau must lie in (0, 1) for H^NN_hyb")
+    if check:
+        check_inputs(A, subs)
+    Ds = partition_of_unity(n, subs)
+    cnt = pair_multiplicity(A, subs)
+    B = algebraic_B(A, cnt)
+    split = [split_local(local_block(B, idx), eps0) for idx in subs]
+
+    # GenEO coarse space (Theorem for H^NN_hyb, Section 3.4)
+    Ys, glam = [], []
+    for s in range(len(subs)):
+        MB = local_MB(A, subs, split, s)
+        Y, lam = geneo_local(split[s], Ds[s], MB, tau)
+        Ys.append(Y)
+        glam.append(lam)
+    rows, cols, vals = [], [], []
+    off = 0
+    for idx, Y in zip(subs, Ys):
+        m = Y.shape[1]
+        rows.append(np.repeat(idx, m))
+        cols.append(np.tile(np.arange(off, off + m), idx.size))
+        vals.append(Y.ravel())
+        off += m
+    R0T = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                        shape=(n, off))
+
+    st = AWGSetup(A=A, subs=subs, tau=tau, Ds=Ds, cnt=cnt, B=B, split=split, Y=Ys,
+                  geneo_lam=glam, R0T=R0T, E0=None, E0_cho=None, W=np.zeros((n, 0)),
+                  EW=np.zeros((0, 0)), EW_cho=None, Vg=np.zeros((n, 0)), w_info={})
+    # E0 = R0 A_+ R0^T and its Cholesky factor
+    AR0T = st.A_plus_mv(R0T.toarray())
+    E0 = np.asarray(R0T.T @ AR0T)
+    st.E0 = 0.5 * (E0 + E0.T)
+    try:
+        st.E0_cho = sla.cho_factor(st.E0, lower=True)
+    except np.linalg.LinAlgError as e:
+        raise OracleError("E0 is not positive definite") from e
+
+    # second coarse space W = A_+^{-1} [R^1T V^1_- | ... ] with strictly
+    # negative eigenvalues only (Remark 1, Section 4.4)
+    cols = []
+    for idx, sp_ in zip(subs, split):
+        if sp_.nstrict == 0:
+            continue
+        V = np.zeros((n, sp_.nstrict))
+        V[idx] = sp_.V[:, :sp_.nstrict]
+        cols.append(V)
+    Vg = np.concatenate(cols, axis=1) if cols else np.zeros((n, 0))
+    st.Vg = Vg
+    if Vg.shape[1]:
+        if w_solver == "auto":
+            w_solver = "direct"
+        if w_solver == "direct":
+            st.W = solve_A_plus_direct(st, Vg)
+            st.w_info = dict(solver="direct")
+        else:
+            st.W, st.w_info = solve_A_plus_pcg(st, Vg, w_rtol, w_maxit)
+        EW = st.W.T @ (A @ st.W)
+        st.EW = 0.5 * (EW + EW.T)
+        try:
+            st.EW_cho = sla.cho_factor(st.EW, lower=True)
+        except np.linalg.LinAlgError as e:
+            raise OracleError("W^T A W is not positive definite") from e
+    return st
+
+
+def assemble_A_plus(st: AWGSetup) -> sp.csr_matrix:
+    """A_+ = sum_s R^sT A^s_+ R^s assembled as a sparse matrix (Definition, Section 3.2)."""
+    rows, cols, vals = [], [], []
+    for idx, sp_ in zip(st.subs, st.split):
+        Ap = sp_.A_plus()
+        rows.append(np.repeat(idx, idx.size))
+        cols.append(np.tile(idx, idx.size))
+        vals.append(Ap.ravel())
+    n = st.n
+    M = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                      shape=(n, n))
+    M.sum_duplicates()
+    return M
+
+
+def solve_A_plus_direct(st: AWGSetup, RHS: np.ndarray) -> np.ndarray:
+    """A_+^{-1} RHS by direct factorisation.
+
+    Small n: dense Cholesky of the assembled A_+.  Otherwise A_+ = A + U C U^T
+    with U = [R^sT V^s_-] (strictly negative pairs; zero eigenvalues add
+    nothing) and C = |L_-| (Definition of A_-, Section 3.2), and the
+    Woodbury identity (Section 4.1) gives
+    A_+^{-1} = A^{-1} - A^{-1} U (C^{-1} + U^T A^{-1} U)^{-1} U^T A^{-1}
+    on top of a sparse LU factorisation of A.
+    """
+    if st.n <= 4000:
+        Ap = assemble_A_plus(st)
+        return sla.cho_solve(sla.cho_factor(Ap.toarray(), lower=True), RHS)
+    lu = spla.splu(st.A.tocsc())
+    cols, cdiag = [], []
+    for idx, sp_ in zip(st.subs, st.split):
+        if sp_.nstrict == 0:
+            continue
+        U = np.zeros((st.n, sp_.nstrict))
+        U[idx] = sp_.V[:, :sp_.nstrict]
+        cols.append(U)
+        cdiag.append(-sp_.lam[:sp_.nstrict])
+    X = lu.solve(RHS)
+    if not cols:
+        return X
+    U = np.concatenate(cols, axis=1)
+    c = np.concatenate(cdiag)
+    AU = lu.solve(U)
+    cap = np.diag(1.0 / c) + U.T @ AU
+    return X - AU @ np.linalg.solve(cap, U.T @ X)
+
+
+def solve_A_plus_pcg(st: AWGSetup, RHS: np.ndarray, rtol: float, maxit: int, block: int = 256):
+    """A_+^{-1} RHS column by column with PCG preconditioned by H2 (Remark 2,
+    Section 4.4); the columns of a block run side by side, each with its own
+    recurrence and stopping test."""
+    X = np.zeros_like(RHS)
+    its = []
+    for c0 in range(0, RHS.shape[1], block):
+        Bk = RHS[:, c0:c0 + block]
+        Xk, it = pcg_multi(st.A_plus_mv, st.H2, Bk, rtol, maxit)
+        X[:, c0:c0 + block] = Xk
+        its.append(it)
+    its = np.concatenate(its)
+    return X, dict(solver="pcg", rtol=rtol, iters_max=int(its.max()), iters_mean=float(its.mean()))
+
+
+def pcg_multi(Amv, Mmv, Bk, rtol, maxit):
+    """Independent PCG recurrences for every column of Bk (x0 = 0)."""
+    X = np.zeros_like(Bk)
+    R = Bk.copy()
+    bn = np.linalg.norm(Bk, axis=0)
+    bn[bn == 0] = 1.0
+    Z = Mmv(R)
+    P = Z.copy()
+    rz = np.einsum("ij,ij->j", R, Z)
+    active = np.ones(Bk.shape[1], dtype=bool)
+    its = np.zeros(Bk.shape[1], dtype=np.int64)
+    for _ in range(maxit):
+        if not active.any():
+            break
+        a = np.flatnonzero(active)
+        Q = Amv(P[:, a])
+        pq = np.einsum("ij,ij->j", P[:, a], Q)
+        alpha = rz[a] / pq
+        X[:, a] += alpha * P[:, a]
+        R[:, a] -= alpha * Q
+        its[a] += 1
+        rn = np.linalg.norm(R[:, a], axis=0) / bn[a]
+        done = rn <= rtol
+        active[a[done]] = False
+        a = np.flatnonzero(active)
+        if a.size == 0:
+            break
+        Za = Mmv(R[:, a])
+        rz_new = np.einsum("ij,ij->j", R[:, a], Za)
+        beta = rz_new / rz[a]
+        rz[a] = rz_new
+        P[:, a] = Za + beta * P[:, a]
+    return X, its
+
+
+# ---------------------------------------------------------------------------
+# PCG (Saad, Section 9.2, as cited by the paper's introduction)
+# ---------------------------------------------------------------------------
+@dataclasses.dataclass
+class PCGResult:
+    x: np.ndarray
+    iters: int
+    converged: bool
+    res_hist: list            # ||r_k|| / ||b|| for k = 0..iters (recursive residual)
+    alphas: list
+    betas: list
+    rel_res_true: float
+
+    def lanczos_extremes(self):
+        """Extreme Ritz values of HA from the PCG coefficients (Lanczos tridiagonal)."""
+        k = len(self.alphas)
+        if k == 0:
+            return np.nan, np.nan
+        T = np.zeros((k, k))
+        for j in range(k):
+            T[j, j] = 1.0 / self.alphas[j] + (self.betas[j - 1] / self.alphas[j - 1] if j > 0 else 0.0)
+            if j + 1 < k:
+                T[j, j + 1] = T[j + 1, j] = np.sqrt(self.betas[j]) / self.alphas[j]
+        ev = np.linalg.eigvalsh(T)
+        return float(ev[0]), float(ev[-1])
+
+
+def pcg(A, b, M, tol: float = 1e-8, maxit: int = 1000, norm: str = "unpreconditioned") -> PCGResult:
+    """PCG from x0 = 0; stops at the first k with ||r_k||/||b|| <= tol.
+
+    norm="preconditioned" instead tests ||H r_k|| / ||H b|| (the default
+    of PETSc's CG, used only to compare iteration counts with the paper's
+    tables).
+    """
+    b = np.asarray(b, dtype=np.float64)
+    x = np.zeros_like(b)
+    r = b.copy()
+    bn = np.linalg.norm(b)
+    hist = [np.linalg.norm(r) / bn]
+    alphas, betas = [], []
+    if hist[0] <= tol:
+        return PCGResult(x, 0, True, hist, alphas, betas, hist[0])
+    z = M(r)
+    zn0 = np.linalg.norm(z)
+    p = z.copy()
+    rz = r @ z
+    k = 0
+    converged = False
+    while k < maxit:
+        q = A @ p
+        pq = p @ q
+        if not pq > 0:
+            raise OracleError("p^T A p <= 0: A or H is not SPD")
+        alpha = rz / pq
+        x += alpha * p
+        r -= alpha * q
+        k += 1
+        alphas.append(alpha)
+        hist.append(np.linalg.norm(r) / bn)
+        if norm != "preconditioned" and hist[-1] <= tol:
+            converged = True
+            break
+        z = M(r)
+        if norm == "preconditioned" and np.linalg.norm(z) / zn0 <= tol:
+            converged = True
+            break
+        rz_new = r @ z
+        beta = rz_new / rz
+        betas.append(beta)
+        rz = rz_new
+        p = z + beta * p
+    true = np.linalg.norm(b - A @ x) / bn
+    return PCGResult(x, k, converged, hist, alphas, betas, float(true))
+
+
+# ---------------------------------------------------------------------------
+# dense helpers for small problems (tests)
+# ---------------------------------------------------------------------------
+def dense_operator(apply, n: int, block: int = 512) -> np.ndarray:
+    """Dense matrix of a linear operator from its action on unit vectors."""
+    M = np.zeros((n, n))
+    for c0 in range(0, n, block):
+        E = np.zeros((n, min(block, n - c0)))
+        E[np.arange(c0, c0 + E.shape[1]), np.arange(E.shape[1])] = 1.0
+        M[:, c0:c0 + E.shape[1]] = apply(E)
+    return M
+
+
+def spectrum_HA(H: np.ndarray, A: np.ndarray) -> np.ndarray:
+    """Eigenvalues of HA for SPD H and A (via the symmetric L^T H L, A = L L^T)."""
+    L = np.linalg.cholesky(A)
+    S = L.T @ H @ L
+    return np.linalg.eigvalsh(0.5 * (S + S.T))
+
+
+def stats(st: AWGSetup) -> dict:
+    return dict(
+        n=st.n, N=len(st.subs), sum_ns=int(sum(len(s) for s in st.subs)),
+        n_minus=st.n_minus, n0=st.n0,
+        k_s=[sp_.nneg for sp_ in st.split], kstrict_s=[sp_.nstrict for sp_ in st.split],
+        m_s=[Y.shape[1] for Y in st.Y],
+    )

@@ -1,0 +1,362 @@
+"""Pins of the FP64 oracle against mathematics fixed by the paper.
+
+Every check here is independent of the oracle's own formulas: brute-force
+counting, assembled dense matrices, textbook identities (Woodbury, projector
+algebra), theorem bounds, special cases with a known answer.
+"""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+import scipy.sparse as sp
+
+import awg_problems as P
+from awg_problems import partition as part
+from oracle import awg_oracle as O
+
+
+def small_fd(seed=3, nint=12, boxes=(3, 3), delta=1, contrast=1e3):
+    rng = np.random.default_rng(seed)
+    kc = np.where(rng.random((nint + 1, nint + 1)) < 0.3, contrast, 1.0)
+    prob = P.fd5_diffusion(nint, kc)
+    return prob.A, part.box_subdomains(prob, boxes, delta), prob.b
+
+
+def small_elast(hinv=4, L=2):
+    w = P.paper_x0(hinv=hinv, L=L)
+    return w.A, w.subs, w.b
+
+
+def random_spd(seed, n=60, nparts=5, delta=1):
+    """Random sparse SPD matrix (weighted graph Laplacian + positive diagonal)
+    with random parts grown by ``delta`` graph layers."""
+    rng = np.random.default_rng(seed)
+    pts = rng.random((n, 2))
+    d = ((pts[:, None, :] - pts[None, :, :]) ** 2).sum(-1)
+    adj = (d < 0.04) & ~np.eye(n, dtype=bool)
+    adj = adj | adj.T
+    Wt = np.triu(rng.uniform(0.1, 10.0, (n, n)) * adj, 1)
+    Wt = Wt + Wt.T
+    L = np.diag(Wt.sum(1)) - Wt + np.diag(rng.uniform(0.01, 1.0, n))
+    A = sp.csr_matrix(L)
+    A.sort_indices()
+    parts = rng.integers(0, nparts, n)
+    parts[:nparts] = np.arange(nparts)
+    G = (A != 0).astype(np.float64)
+    subs = part.extend_by_layers(G, parts, nparts, delta)
+    return A, [np.asarray(s, dtype=np.int64) for s in subs]
+
+
+CASES = [small_fd, small_elast, lambda: random_spd(11) + (None,), lambda: random_spd(12, 80, 7) + (None,)]
+
+
+@pytest.fixture(scope="module", params=range(len(CASES)))
+def case(request):
+    A, subs, b = CASES[request.param]()
+    st = O.setup(A, subs, 0.1)
+    return A, subs, st
+
+
+# ----------------------------------------------------------------------------
+def test_pair_multiplicity_bruteforce(case):
+    """M_mu counts, for each nonzero, the subdomains holding both indices (Section 3.1)."""
+    A, subs, st = case
+    Ac = A.tocoo()
+    sets = [set(s.tolist()) for s in subs]
+    csr = A.tocsr()
+    for k in range(0, csr.nnz, max(1, csr.nnz // 400)):
+        i = np.searchsorted(csr.indptr, k, side="right") - 1
+        j = csr.indices[k]
+        brute = sum(1 for S in sets if i in S and j in S)
+        assert st.cnt[k] == brute
+    del Ac
+
+
+def test_splitting_sums_to_A(case):
+    """sum_s R^sT B^s R^s = A (Theorem after the definition of B^s, Section 3.1)."""
+    A, subs, st = case
+    n = A.shape[0]
+    S = np.zeros((n, n))
+    for idx in subs:
+        S[np.ix_(idx, idx)] += O.local_block(st.B, idx)
+    Ad = A.toarray()
+    assert np.max(np.abs(S - Ad)) <= 4e-16 * np.max(np.abs(Ad)) * 4
+
+
+def test_A_plus_minus_properties(case):
+    """A = A_+ - A_-, A_- spsd, A_+ spd, rank(A_-) <= sum n_s - n (Section 3.2, 4.1)."""
+    A, subs, st = case
+    n = A.shape[0]
+    Ap = O.assemble_A_plus(st).toarray()
+    Am = np.zeros((n, n))
+    for idx, s_ in zip(subs, st.split):
+        Am[np.ix_(idx, idx)] += s_.A_minus()
+    Ad = A.toarray()
+    scale = np.max(np.abs(Ad))
+    assert np.max(np.abs(Ap - Am - Ad)) <= 1e-12 * scale
+    em = np.linalg.eigvalsh(Am)
+    ep = np.linalg.eigvalsh(Ap)
+    assert em.min() >= -1e-12 * scale
+    assert ep.min() > 0
+    rank = int(np.count_nonzero(em > 1e-10 * scale))
+    assert rank <= sum(len(s) for s in subs) - n
+    # the implicit action used everywhere else agrees with the assembled A_+
+    x = np.random.default_rng(0).standard_normal(n)
+    assert np.allclose(st.A_plus_mv(x), Ap @ x, rtol=1e-12, atol=1e-12 * scale * np.abs(x).max())
+
+
+def test_woodbury_identity(case):
+    """A^{-1} = A_+^{-1} + A_+^{-1} V_- (L_-^{-1} - V_-^T A_+^{-1} V_-)^{-1} V_-^T A_+^{-1}
+    with A_- = V_- L_- V_-^T its diagonalisation without the null part (Section 4.1)."""
+    A, subs, st = case
+    n = A.shape[0]
+    Ap = O.assemble_A_plus(st).toarray()
+    Am = Ap - A.toarray()
+    lam, V = np.linalg.eigh(Am)
+    keep = lam > 1e-9 * np.abs(lam).max()
+    Vm, Lm = V[:, keep], lam[keep]
+    Api = np.linalg.inv(Ap)
+    C = np.diag(1.0 / Lm) - Vm.T @ Api @ Vm
+    wood = Api + Api @ Vm @ np.linalg.solve(C, Vm.T @ Api)
+    Ainv = np.linalg.inv(A.toarray())
+    assert np.linalg.norm(wood - Ainv) <= 1e-8 * np.linalg.norm(Ainv)
+    del n
+
+
+def test_range_of_W(case):
+    """range(A_+^{-1} V_-) = range(A^{-1} V_-) (Lemma, Section 4.3)."""
+    A, subs, st = case
+    if st.n_minus == 0:
+        pytest.skip("no strictly negative local eigenvalue")
+    W2 = np.linalg.solve(A.toarray(), st.Vg)
+    ang = sla.subspace_angles(st.W, W2)
+    assert ang.max() < 1e-8
+
+
+def test_Pi3_projector(case):
+    """Pi_3 is an A-orthogonal projector, A_- Pi_3 = 0, Pi_3 W = 0 (Theorem, Section 4.3)."""
+    A, subs, st = case
+    if st.n_minus == 0:
+        pytest.skip("no strictly negative local eigenvalue")
+    n = A.shape[0]
+    Ad = A.toarray()
+    W = st.W
+    Pi3 = np.eye(n) - W @ np.linalg.solve(W.T @ Ad @ W, W.T @ Ad)
+    assert np.linalg.norm(Pi3 @ Pi3 - Pi3) <= 1e-8 * np.linalg.norm(Pi3)
+    APi = Ad @ Pi3
+    assert np.linalg.norm(APi - APi.T) <= 1e-8 * np.linalg.norm(APi)
+    Am = O.assemble_A_plus(st).toarray() - Ad
+    assert np.linalg.norm(Am @ Pi3) <= 1e-8 * np.linalg.norm(Am) * np.linalg.norm(Pi3)
+    assert np.linalg.norm(Pi3 @ W) <= 1e-8 * np.linalg.norm(W)
+
+
+def test_local_pseudo_inverse_forms(case):
+    """(A^s_+)^dagger three ways: numpy pinv; P B^dagger P with P = I - V_- V_-^T
+    (Remark 3, Section 4.4); and K^{-1} - c^{-1} V_- V_-^T with
+    K = A^s_+ + c V_- V_-^T (the factorisation the GPU uses)."""
+    A, subs, st = case
+    for s_, idx in zip(st.split, subs):
+        G = s_.A_plus_pinv()
+        Bs = O.local_block(st.B, idx)
+        Ap = s_.A_plus()
+        ref = np.linalg.pinv(Ap, rcond=1e-10, hermitian=True)
+        nrm = np.linalg.norm(ref)
+        assert np.linalg.norm(G - ref) <= 1e-8 * nrm
+        Pm = np.eye(len(idx)) - s_.V_minus @ s_.V_minus.T
+        if s_.nneg == s_.nstrict:        # B^s nonsingular: P B^{-1} P
+            assert np.linalg.norm(Pm @ np.linalg.inv(Bs) @ Pm - G) <= 1e-8 * nrm
+        c = float(np.mean(np.diag(Bs)))
+        K = Bs + (s_.V_minus * (c - s_.L_minus)) @ s_.V_minus.T
+        GK = np.linalg.inv(K) - s_.V_minus @ s_.V_minus.T / c
+        assert np.linalg.norm(GK - G) <= 1e-8 * nrm
+
+
+def test_geneo_selection_independent(case):
+    """GenEO count and kernel (Definition of Y_L and the remark on the kernels,
+    Section 3.4): the kernel of M_A is D^s V^s_- of dimension n^s_-, and the
+    number of eigenvalues below tau agrees with an independent dense solve of
+    M_B^{-1} M_A (nonsymmetric eigenvalues)."""
+    A, subs, st = case
+    Ap = O.assemble_A_plus(st)
+    for s, idx in enumerate(subs):
+        s_ = st.split[s]
+        Dinv = 1.0 / st.Ds[s]
+        MA = Dinv[:, None] * s_.A_plus() * Dinv[None, :]
+        MB = O.local_block(Ap, idx)             # R^s A_+ R^sT from the assembled A_+
+        ev = np.sort(np.linalg.eigvals(np.linalg.solve(MB, MA)).real)
+        assert int(np.count_nonzero(ev < st.tau)) == st.Y[s].shape[1]
+        # kernel: D^s V^s_- is annihilated by M_A
+        if s_.nneg:
+            K = st.Ds[s][:, None] * s_.V_minus
+            assert np.linalg.norm(MA @ K) <= 1e-8 * np.linalg.norm(MA) * np.linalg.norm(K)
+        # Y^s is M_B-orthonormal and spans eigenvectors
+        Y = st.Y[s]
+        if Y.shape[1]:
+            assert np.allclose(Y.T @ MB @ Y, np.eye(Y.shape[1]), atol=1e-8)
+            lam = st.geneo_lam[s][:Y.shape[1]]
+            res = MA @ Y - (MB @ Y) * lam
+            assert np.linalg.norm(res) <= 1e-7 * np.linalg.norm(MA)
+
+
+def test_H_spd_and_spectral_bound(case):
+    """H is spd and the spectrum of HA lies in [1, N(A_+)/tau + 1] (Theorem on
+    H^NN_hyb, Section 3.4, and the H3,ad bound, Section 4.3); H2 A_+ lies in
+    [1, N(A_+)/tau]."""
+    A, subs, st = case
+    n = A.shape[0]
+    H = O.dense_operator(st.apply, n)
+    assert np.linalg.norm(H - H.T) <= 1e-9 * np.linalg.norm(H)
+    assert np.linalg.eigvalsh(0.5 * (H + H.T)).min() > 0
+    Ap = O.assemble_A_plus(st)
+    ncol = O.coloring_constant(subs, Ap)
+    ev = O.spectrum_HA(0.5 * (H + H.T), A.toarray())
+    assert ev.min() >= 1 - 1e-8
+    assert ev.max() <= ncol / st.tau + 1 + 1e-8
+    H2 = O.dense_operator(st.H2, n)
+    ev2 = O.spectrum_HA(0.5 * (H2 + H2.T), Ap.toarray())
+    assert ev2.min() >= 1 - 1e-8
+    assert ev2.max() <= ncol / st.tau + 1e-8
+
+
+def test_basis_invariance(case):
+    """H depends on range(R0^T) and range(W) only (Assumption on V0, Section 2.3;
+    Definition of Pi_3 and H3, Section 4.3)."""
+    A, subs, st = case
+    rng = np.random.default_rng(5)
+    r = rng.standard_normal(A.shape[0])
+    z = st.apply(r)
+    import copy
+    st2 = copy.copy(st)
+    R0T = st.R0T.toarray()
+    M0 = np.eye(R0T.shape[1]) + 0.3 * rng.standard_normal((R0T.shape[1],) * 2)
+    R0T2 = R0T @ M0
+    st2.R0T = sp.csr_matrix(R0T2)
+    E0 = R0T2.T @ st.A_plus_mv(R0T2)
+    st2.E0_cho = sla.cho_factor(0.5 * (E0 + E0.T), lower=True)
+    if st.n_minus:
+        Mw = np.eye(st.n_minus) + 0.3 * rng.standard_normal((st.n_minus,) * 2)
+        st2.W = st.W @ Mw
+        EW = st2.W.T @ (A @ st2.W)
+        st2.EW_cho = sla.cho_factor(0.5 * (EW + EW.T), lower=True)
+    z2 = st2.apply(r)
+    assert np.linalg.norm(z2 - z) <= 1e-8 * np.linalg.norm(z)
+
+
+# ----------------------------------------------------------------------------
+# special cases with a known answer
+# ----------------------------------------------------------------------------
+def test_single_subdomain_is_exact():
+    """N = 1, Omega^1 = all dofs: B^1 = A is spd, so n_- = 0 and GenEO keeps
+    nothing; H = H^NN = A^{-1} and PCG converges in one iteration."""
+    A, _, b = small_fd()
+    n = A.shape[0]
+    st = O.setup(A, [np.arange(n)], 0.1)
+    assert st.n_minus == 0 and st.n0 == 0
+    H = O.dense_operator(st.apply, n)
+    assert np.linalg.norm(H - np.linalg.inv(A.toarray())) <= 1e-9 * np.linalg.norm(H)
+    res = O.pcg(A, b, st.apply, tol=1e-10)
+    assert res.iters == 1
+
+
+def test_spd_local_blocks_give_no_second_space():
+    """A diagonally dominant 1D chain with single-node overlaps: every B^s is
+    spd, A_+ = A and W is empty, so H = H2."""
+    n = 31
+    main = np.full(n, 4.0)
+    off = np.full(n - 1, -1.0)
+    A = sp.diags([off, main, off], [-1, 0, 1]).tocsr()
+    A.sort_indices()
+    subs = [np.arange(0, 11), np.arange(10, 21), np.arange(20, 31)]
+    st = O.setup(A, subs, 0.1)
+    assert all(s_.nneg == 0 for s_ in st.split)
+    assert st.n_minus == 0
+    r = np.random.default_rng(1).standard_normal(n)
+    assert np.allclose(st.apply(r), st.H2(r))
+
+
+def test_tau_to_zero_keeps_only_kernels():
+    """As tau -> 0 the GenEO space reduces to the kernels D^s V^s_-, so
+    #V0 = sum_s n^s_- (remark on the kernels, Section 3.4), and n_- does not
+    depend on tau."""
+    A, subs, _ = small_elast()
+    st_small = O.setup(A, subs, 1e-9)
+    st = O.setup(A, subs, 0.1)
+    assert st_small.n0 == sum(s_.nneg for s_ in st_small.split)
+    assert st_small.n_minus == st.n_minus
+    assert st.n0 >= st_small.n0
+
+
+def test_pcg_matches_direct_solve():
+    """The PCG recurrence converges to A^{-1} b within the tolerance."""
+    A, subs, b = small_fd()
+    st = O.setup(A, subs, 0.1)
+    res = O.pcg(A, b, st.apply, tol=1e-12)
+    x = np.linalg.solve(A.toarray(), b)
+    assert res.converged
+    assert np.linalg.norm(res.x - x) <= 1e-9 * np.linalg.norm(x)
+    assert res.rel_res_true <= 1e-11
+
+
+def test_invalid_inputs_rejected():
+    A, subs, _ = small_fd()
+    with pytest.raises(O.OracleError):
+        O.setup(A, subs[:-1], 0.1)                      # coverage gap
+    bad = list(subs)
+    bad[0] = bad[0][::-1].copy()
+    with pytest.raises(O.OracleError):
+        O.setup(A, bad, 0.1)                           # unsorted
+    with pytest.raises(O.OracleError):
+        O.setup(A, subs, 1.5)                          # tau outside (0, 1)
+    # boxes without overlap violate the minimal-overlap assumption
+    prob = P.fd5_diffusion(8, np.ones((9, 9)))
+    G, kept = part.node_graph_of_A(prob)
+    parts = part.box_parts(prob.node_xyz[kept], (2, 2))
+    subs0 = part.nodes_to_dofs(prob, kept, part.extend_by_layers(G, parts, 4, 0))
+    with pytest.raises(O.OracleError):
+        O.setup(prob.A, subs0, 0.1)
+    Au = prob.A.tolil()
+    Au[0, 1] += 1.0
+    with pytest.raises(O.OracleError):
+        O.setup(Au.tocsr(), part.box_subdomains(prob, (2, 2), 1), 0.1)
+
+
+def test_lanczos_extremes_match_dense_spectrum():
+    A, subs, b = small_fd()
+    st = O.setup(A, subs, 0.1)
+    res = O.pcg(A, b, st.apply, tol=1e-14, maxit=500)
+    H = O.dense_operator(st.apply, A.shape[0])
+    ev = O.spectrum_HA(0.5 * (H + H.T), A.toarray())
+    lmin, lmax = res.lanczos_extremes()
+    assert abs(lmax - ev.max()) <= 1e-3 * ev.max()
+    assert abs(lmin - ev.min()) <= 1e-3 * ev.min()
+
+
+def test_W_by_pcg_matches_direct():
+    """W from PCG on A_+ preconditioned by H2 (Remark 2, Section 4.4) spans the
+    same space as the direct solve, so H is the same operator."""
+    A, subs, _ = small_elast(hinv=6, L=2)
+    st_d = O.setup(A, subs, 0.1, w_solver="direct")
+    st_p = O.setup(A, subs, 0.1, w_solver="pcg", w_rtol=1e-13)
+    assert st_p.w_info["iters_max"] < 60
+    ang = sla.subspace_angles(st_d.W, st_p.W)
+    assert ang.max() < 1e-9
+    r = np.random.default_rng(2).standard_normal(A.shape[0])
+    zd, zp = st_d.apply(r), st_p.apply(r)
+    assert np.linalg.norm(zd - zp) <= 1e-9 * np.linalg.norm(zd)
+
+
+def test_woodbury_direct_W_matches_dense():
+    """The large-n direct path (sparse LU of A plus the Woodbury identity)
+    gives the same W as a dense Cholesky solve with the assembled A_+."""
+    A, subs, _ = small_elast(hinv=6, L=2)
+    st = O.setup(A, subs, 0.1)
+    Ap = O.assemble_A_plus(st).toarray()
+    Wd = np.linalg.solve(Ap, st.Vg)
+    n_saved = st.A.shape
+    import scipy.sparse.linalg as spla
+    lu = spla.splu(st.A.tocsc())
+    X = lu.solve(st.Vg)
+    c = np.concatenate([-s_.lam[:s_.nstrict] for s_ in st.split if s_.nstrict])
+    cap = np.diag(1.0 / c) + st.Vg.T @ X
+    Ww = X - X @ np.linalg.solve(cap, st.Vg.T @ X)
+    assert np.linalg.norm(Ww - Wd) <= 1e-9 * np.linalg.norm(Wd)
+    del n_saved
