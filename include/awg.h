@@ -1,0 +1,139 @@
+/*
+ * awg.h -- C ABI of the MI355X (gfx950) AWG-PCG library.
+ *
+ * Solves a sparse symmetric positive definite system A x = b with the
+ * preconditioned conjugate gradient method, preconditioned by the additive
+ * Algebraic-Woodbury-GenEO preconditioner of Gouarin & Spillane, "Fully
+ * algebraic domain decomposition preconditioners with adaptive spectral
+ * bounds":
+ *
+ *     H = H2 + W (W^T A W)^{-1} W^T             (Definition of Pi_3 and H3, Section 4.3)
+ *     H2 = Pi H^NN Pi^T + R0^T E0^{-1} R0        (Theorem on H^NN_hyb(tau), Section 3.4)
+ *     H^NN = sum_s R^sT D^s (A^s_+)^+ D^s R^s     (Definition of H^NN, Section 3.3)
+ *
+ * built only from A and the subdomain index sets (Sections 2 and 3.1-3.2).
+ *
+ * Conventions for every entry point
+ *   - All array arguments are DEVICE pointers (HIP device memory of the
+ *     current device) unless stated otherwise; indices are 0-based; A is
+ *     given in CSR with BOTH triangles stored.
+ *   - Work is stream-ordered on the stream given in awg_options.stream
+ *     (NULL = the default stream).  awg_setup and awg_pcg synchronise that
+ *     stream before returning; awg_apply does not.
+ *   - The caller owns every buffer it passes; the library copies what it
+ *     keeps during awg_setup, so inputs may be freed when it returns.  The
+ *     library owns its internal buffers until awg_destroy.
+ *   - Return value: AWG_OK (0), a positive warning, or a negative error.
+ *     No exception crosses the ABI.  On error, output buffers are left
+ *     untouched and awg_last_error() describes the failure.
+ *   - A context is used by one host thread / one stream at a time.
+ */
+#ifndef AWG_H
+#define AWG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct awg_ctx awg_ctx;
+
+typedef enum {
+  AWG_OK = 0,
+  AWG_NOT_CONVERGED = 1,        /* awg_pcg hit maxit; x holds the last iterate */
+  AWG_ERR_ARG = -1,             /* invalid scalar argument or NULL pointer */
+  AWG_ERR_NOT_SYMMETRIC = -2,   /* A_ij != A_ji for some stored entry */
+  AWG_ERR_PARTITION = -3,       /* subdomain list empty / unsorted / duplicate /
+                                   out of range, or the lists do not cover [0,n)
+                                   (Definition of a partition, Section 2.1) */
+  AWG_ERR_MIN_OVERLAP = -4,     /* some A_ij != 0 has no subdomain holding both
+                                   i and j (Assumption of minimal overlap, Section 2.1) */
+  AWG_ERR_NOT_SPD = -5,         /* a Cholesky factorisation broke down (local
+                                   K^s, M_B^s, E0 or W^T A W) or PCG met p^T A p <= 0 */
+  AWG_ERR_EIGEN = -6,           /* a local eigensolve failed its residual check */
+  AWG_ERR_HIP = -7,             /* a HIP runtime call failed */
+  AWG_ERR_OOM = -8,             /* device allocation failed */
+  AWG_ERR_NONFINITE = -9        /* NaN or Inf in A */
+} awg_status;
+
+enum { AWG_LOCAL_F64 = 0, AWG_LOCAL_F32 = 1 };
+
+typedef struct {
+  double tau;          /* GenEO threshold of H^NN_hyb(tau); 0 < tau < 1 (Theorem, Section 3.4) */
+  double zero_tol;     /* eps0: an eigenvalue lambda of B^s is non-positive when
+                          lambda <= eps0 * max|lambda(B^s)|; default 1e-12 */
+  double w_rtol;       /* relative residual tolerance of the PCG solves with A_+
+                          that build W (Remark 2, Section 4.4); default 1e-12 */
+  int32_t w_maxit;     /* iteration cap of those solves; default 500 */
+  int32_t local_prec;  /* AWG_LOCAL_F64 (default) or AWG_LOCAL_F32: storage and
+                          arithmetic of the per-iteration local solves */
+  void* stream;        /* hipStream_t; NULL = default stream */
+} awg_options;
+
+/* Fill *opt with the defaults above (tau = 0.1).  Host pointer. */
+void awg_default_options(awg_options* opt);
+
+/* Build the preconditioner (every setup step runs on the GPU).
+ *   n, nnz         order of A and number of stored entries (nnz < 2^31)
+ *   rowptr[n+1]    int64 CSR row pointers            (device)
+ *   col[nnz]       int32 column indices, sorted per row (device)
+ *   val[nnz]       float64 values                      (device)
+ *   nsub           number N of subdomains (>= 1)
+ *   sub_ptr[N+1]   int64 offsets of each index list in sub_idx (device)
+ *   sub_idx[..]    int32 dof indices, sorted and unique per subdomain (device)
+ *   opt            host pointer to options (NULL = defaults)
+ * On success *out receives a new context.  On failure *out is set to NULL
+ * and awg_last_error(NULL) explains the failure. */
+int awg_setup(awg_ctx** out, int64_t n, int64_t nnz, const int64_t* rowptr, const int32_t* col,
+              const double* val, int32_t nsub, const int64_t* sub_ptr, const int32_t* sub_idx,
+              const awg_options* opt);
+
+/* z = H r for device vectors of length n (r and z must not alias). */
+int awg_apply(awg_ctx* ctx, const double* r, double* z);
+
+typedef struct {
+  int32_t iters;          /* number of products A p performed */
+  int32_t converged;      /* 1 if ||r_k||/||b|| <= tol was reached */
+  double rel_res;         /* recursively updated ||r_k|| / ||b|| */
+  double rel_res_true;    /* ||b - A x_k|| / ||b|| recomputed at the end */
+  double lmin_est;        /* extreme Ritz values of HA from the PCG coefficients */
+  double lmax_est;
+} awg_pcg_info;
+
+/* PCG (Saad, Section 9.2) from x0 = 0 with the AWG preconditioner; stops at
+ * the first k with ||r_k||_2 / ||b||_2 <= tol on the recursive residual.
+ * b, x: device vectors of length n.  info: host pointer (may be NULL). */
+int awg_pcg(awg_ctx* ctx, const double* b, double* x, double tol, int32_t maxit,
+            awg_pcg_info* info);
+
+/* JSON description of the setup (n, N, n_minus, n0, per-subdomain counts,
+ * per-phase times in ms).  buf: host buffer of cap bytes.  Returns the
+ * number of bytes needed (excluding the terminator) or a negative error. */
+int64_t awg_stats(const awg_ctx* ctx, char* buf, size_t cap);
+
+/* Copy a named internal array to HOST memory (tests and diagnostics).
+ *   "neg_eigs"   float64 [sum_s k_s]  non-positive eigenvalues of each B^s, ascending per s
+ *   "geneo_eigs" float64 [sum_s m_s]  selected GenEO eigenvalues, ascending per s
+ *   "mult"       int32   [n]          multiplicity of each dof
+ *   "pair_count" int32   [nnz]        M_mu on the pattern of A (CSR order)
+ *   "V_minus"    float64 [sum_s n_s k_s] non-positive eigenvectors of each B^s
+ *                                     (n_s x k_s column-major blocks, in subdomain order)
+ *   "Y"          float64 [sum_s n_s m_s] GenEO coarse vectors Y^s (same layout)
+ *   "P_local"    float64 [sum_s n_s^2] local operators D^s (A^s_+)^+ D^s (n_s x n_s blocks)
+ * Returns the number of bytes of the array (copying min(cap, size)), or a
+ * negative error for an unknown name. */
+int64_t awg_export(const awg_ctx* ctx, const char* name, void* host_buf, size_t cap);
+
+/* Message of the last error on this context, or of the last failed
+ * awg_setup when ctx is NULL.  Never returns NULL. */
+const char* awg_last_error(const awg_ctx* ctx);
+
+/* Free every device buffer of the context.  NULL is ignored. */
+void awg_destroy(awg_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* AWG_H */

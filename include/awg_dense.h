@@ -1,0 +1,56 @@
+/*
+ * awg_dense.h -- batched dense building blocks of libawg (gfx950).
+ *
+ * The AWG set-up (Gouarin & Spillane, Sections 3.2-3.4 and 4.3) reduces to
+ * four dense operations on many independent blocks: products (trailing
+ * updates, Gram and projection products), Cholesky factorisations (local
+ * K^s, M_B^s, coarse matrices), triangular solves with many right-hand sides
+ * (explicit inverses, the Cholesky reduction of the GenEO pencil), and
+ * eigenpairs below a threshold of symmetric blocks (the non-positive part of
+ * B^s, the GenEO modes below tau).  These entry points expose them for
+ * uniform batches, as used by the library internally with variable sizes.
+ *
+ * Conventions: float64, column-major blocks, block b of X starts at
+ * X + b * strideX; all arrays are DEVICE pointers unless marked host; work is
+ * ordered on `stream` (hipStream_t, NULL = default) and the call returns
+ * after it completes.  Return AWG_OK (0) or a negative awg_status.
+ */
+#ifndef AWG_DENSE_H
+#define AWG_DENSE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* C_b = alpha op(A_b) op(B_b) + beta C_b;  op(A_b) is m x k, op(B_b) is k x n. */
+int awg_dense_gemm(int32_t batch, int32_t m, int32_t n, int32_t k, int32_t transA, int32_t transB,
+                   double alpha, const double* A, int32_t lda, int64_t strideA, const double* B,
+                   int32_t ldb, int64_t strideB, double beta, double* C, int32_t ldc, int64_t strideC,
+                   void* stream);
+
+/* In-place lower Cholesky A_b = L_b L_b^T (upper triangle left unspecified).
+ * info_host[b] (host, batch entries) = 0 or the 1-based column of the first
+ * non-positive pivot; returns AWG_ERR_NOT_SPD if any block failed. */
+int awg_dense_potrf(int32_t batch, int32_t n, double* A, int32_t lda, int64_t strideA, int32_t* info_host,
+                    void* stream);
+
+/* B_b <- L_b^{-1} B_b (trans = 0) or L_b^{-T} B_b (trans = 1), L_b lower n x n,
+ * B_b n x nrhs. */
+int awg_dense_trsm(int32_t batch, int32_t n, int32_t nrhs, int32_t trans, const double* L, int32_t ldl,
+                   int64_t strideL, double* B, int32_t ldb, int64_t strideB, void* stream);
+
+/* Eigenpairs of the symmetric blocks A_b (destroyed) with eigenvalue < thr,
+ * ascending: count_host[b] (host) receives their number; the first
+ * min(count, max_k) eigenvalues go to lam[b * max_k ...] and the orthonormal
+ * eigenvectors to Z + b * strideZ (n x max_k, leading dimension n).  Returns
+ * AWG_ERR_ARG if some count exceeds max_k (counts are still reported). */
+int awg_dense_low_eigs(int32_t batch, int32_t n, double* A, int32_t lda, int64_t strideA, double thr,
+                       int32_t max_k, int32_t* count_host, double* lam, double* Z, int64_t strideZ,
+                       void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* AWG_DENSE_H */

@@ -1,0 +1,256 @@
+"""ctypes binding of libawg (include/awg.h).
+
+Argument marshalling only: every step of the set-up, the preconditioner and
+PCG runs in the HIP library.  PyTorch provides device memory and the stream.
+The binding refuses to run when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import json
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libawg.so")
+
+AWG_LOCAL_F64 = 0
+AWG_LOCAL_F32 = 1
+
+STATUS = {0: "AWG_OK", 1: "AWG_NOT_CONVERGED", -1: "AWG_ERR_ARG", -2: "AWG_ERR_NOT_SYMMETRIC",
+          -3: "AWG_ERR_PARTITION", -4: "AWG_ERR_MIN_OVERLAP", -5: "AWG_ERR_NOT_SPD", -6: "AWG_ERR_EIGEN",
+          -7: "AWG_ERR_HIP", -8: "AWG_ERR_OOM", -9: "AWG_ERR_NONFINITE"}
+
+EXPORTED = ["awg_default_options", "awg_setup", "awg_apply", "awg_pcg", "awg_stats", "awg_export",
+            "awg_last_error", "awg_destroy",
+            "awg_dense_gemm", "awg_dense_potrf", "awg_dense_trsm", "awg_dense_low_eigs"]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("tau", ctypes.c_double), ("zero_tol", ctypes.c_double), ("w_rtol", ctypes.c_double),
+                ("w_maxit", ctypes.c_int32), ("local_prec", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+
+
+class PCGInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("converged", ctypes.c_int32), ("rel_res", ctypes.c_double),
+                ("rel_res_true", ctypes.c_double), ("lmin_est", ctypes.c_double),
+                ("lmax_est", ctypes.c_double)]
+
+
+class AWGError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+        self.status = STATUS.get(code, str(code))
+
+
+_lib = None
+
+
+def lib():
+    """Load libawg.so (raises if it was not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i64, i32, dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
+    L.awg_default_options.argtypes = [ctypes.POINTER(Options)]
+    L.awg_default_options.restype = None
+    L.awg_setup.argtypes = [ctypes.POINTER(vp), i64, i64, vp, vp, vp, i32, vp, vp, ctypes.POINTER(Options)]
+    L.awg_setup.restype = ctypes.c_int
+    L.awg_apply.argtypes = [vp, vp, vp]
+    L.awg_apply.restype = ctypes.c_int
+    L.awg_pcg.argtypes = [vp, vp, vp, dbl, i32, ctypes.POINTER(PCGInfo)]
+    L.awg_pcg.restype = ctypes.c_int
+    L.awg_stats.argtypes = [vp, ctypes.c_char_p, ctypes.c_size_t]
+    L.awg_stats.restype = i64
+    L.awg_export.argtypes = [vp, ctypes.c_char_p, vp, ctypes.c_size_t]
+    L.awg_export.restype = i64
+    L.awg_last_error.argtypes = [vp]
+    L.awg_last_error.restype = ctypes.c_char_p
+    L.awg_destroy.argtypes = [vp]
+    L.awg_destroy.restype = None
+    L.awg_dense_gemm.argtypes = [i32, i32, i32, i32, i32, i32, dbl, vp, i32, i64, vp, i32, i64, dbl, vp, i32, i64,
+                                 vp]
+    L.awg_dense_gemm.restype = ctypes.c_int
+    L.awg_dense_potrf.argtypes = [i32, i32, vp, i32, i64, vp, vp]
+    L.awg_dense_potrf.restype = ctypes.c_int
+    L.awg_dense_trsm.argtypes = [i32, i32, i32, i32, vp, i32, i64, vp, i32, i64, vp]
+    L.awg_dense_trsm.restype = ctypes.c_int
+    L.awg_dense_low_eigs.argtypes = [i32, i32, vp, i32, i64, dbl, i32, vp, vp, vp, i64, vp]
+    L.awg_dense_low_eigs.restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def default_options() -> Options:
+    o = Options()
+    lib().awg_default_options(ctypes.byref(o))
+    return o
+
+
+class Solver:
+    """AWG-PCG for one sparse SPD system on the current GPU.
+
+    A: scipy CSR matrix (host) or a tuple (rowptr int64, col int32, val f64)
+    of device tensors; subs: list of sorted index arrays or a tuple
+    (sub_ptr int64, sub_idx int32) of device tensors.
+    """
+
+    def __init__(self, A, subs, tau: float = 0.1, local_prec: str = "f64", w_rtol: float = 1e-12,
+                 w_maxit: int = 500, zero_tol: float = 1e-12, device: str = "cuda"):
+        import torch
+        L = lib()
+        self._torch = torch
+        self.device = torch.device(device)
+        if isinstance(A, tuple):
+            rowptr, col, val = A
+            n = rowptr.numel() - 1
+        else:
+            A = A.tocsr()
+            A.sort_indices()
+            n = A.shape[0]
+            rowptr = torch.as_tensor(A.indptr.astype(np.int64), device=self.device)
+            col = torch.as_tensor(A.indices.astype(np.int32), device=self.device)
+            val = torch.as_tensor(A.data.astype(np.float64), device=self.device)
+        if isinstance(subs, tuple):
+            sub_ptr, sub_idx = subs
+            nsub = sub_ptr.numel() - 1
+        else:
+            sizes = np.array([len(s) for s in subs], dtype=np.int64)
+            ptr = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+            idx = np.concatenate([np.asarray(s) for s in subs]).astype(np.int32)
+            sub_ptr = torch.as_tensor(ptr, device=self.device)
+            sub_idx = torch.as_tensor(idx, device=self.device)
+            nsub = len(subs)
+        self.n = int(n)
+        self.nnz = int(col.numel())
+        self._keep = (rowptr, col, val, sub_ptr, sub_idx)
+        opt = default_options()
+        opt.tau = tau
+        opt.zero_tol = zero_tol
+        opt.w_rtol = w_rtol
+        opt.w_maxit = w_maxit
+        opt.local_prec = AWG_LOCAL_F32 if local_prec == "f32" else AWG_LOCAL_F64
+        opt.stream = torch.cuda.current_stream(self.device).cuda_stream
+        self._opt = opt
+        ctx = ctypes.c_void_p()
+        rc = L.awg_setup(ctypes.byref(ctx), self.n, self.nnz, rowptr.data_ptr(), col.data_ptr(), val.data_ptr(),
+                         nsub, sub_ptr.data_ptr(), sub_idx.data_ptr(), ctypes.byref(opt))
+        if rc != 0:
+            raise AWGError(rc, L.awg_last_error(None).decode())
+        self._ctx = ctx
+
+    def _check(self, rc):
+        if rc < 0:
+            raise AWGError(rc, lib().awg_last_error(self._ctx).decode())
+        return rc
+
+    def apply(self, r):
+        """z = H r (device float64 vectors)."""
+        torch = self._torch
+        r = r.to(device=self.device, dtype=torch.float64).contiguous()
+        z = torch.empty_like(r)
+        self._check(lib().awg_apply(self._ctx, r.data_ptr(), z.data_ptr()))
+        return z
+
+    def pcg(self, b, tol: float = 1e-8, maxit: int = 1000, x=None):
+        """Solve A x = b; returns (x, info dict)."""
+        torch = self._torch
+        b = b.to(device=self.device, dtype=torch.float64).contiguous()
+        if x is None:
+            x = torch.empty_like(b)
+        info = PCGInfo()
+        rc = self._check(lib().awg_pcg(self._ctx, b.data_ptr(), x.data_ptr(), tol, maxit, ctypes.byref(info)))
+        d = {k: getattr(info, k) for k, _ in PCGInfo._fields_}
+        d["status"] = STATUS.get(rc, rc)
+        return x, d
+
+    def stats(self) -> dict:
+        L = lib()
+        need = L.awg_stats(self._ctx, None, 0)
+        buf = ctypes.create_string_buffer(int(need) + 1)
+        L.awg_stats(self._ctx, buf, len(buf))
+        return json.loads(buf.value.decode())
+
+    def export(self, name: str):
+        L = lib()
+        nbytes = L.awg_export(self._ctx, name.encode(), None, 0)
+        self._check(nbytes)
+        dt = np.int32 if name in ("mult", "pair_count") else np.float64
+        out = np.empty(int(nbytes) // np.dtype(dt).itemsize, dtype=dt)
+        if nbytes:
+            self._check(L.awg_export(self._ctx, name.encode(), out.ctypes.data, int(nbytes)))
+        return out
+
+    def close(self):
+        if getattr(self, "_ctx", None):
+            lib().awg_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------------------
+# batched dense building blocks (include/awg_dense.h), uniform batches of
+# column-major float64 device tensors shaped (batch, cols, rows)
+# ---------------------------------------------------------------------------
+def _stream():
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+def dense_gemm(A, B, C, alpha=1.0, beta=0.0, transA=False, transB=False):
+    """C_b = alpha op(A_b) op(B_b) + beta C_b; tensors are (batch, cols, rows)."""
+    batch, ka, ma = A.shape
+    _, nb, kb = B.shape
+    m = ka if transA else ma
+    k = ma if transA else ka
+    n = kb if transB else nb
+    rc = lib().awg_dense_gemm(batch, m, n, k, int(transA), int(transB), alpha, A.data_ptr(), ma, ka * ma,
+                              B.data_ptr(), kb, nb * kb, beta, C.data_ptr(), C.shape[2], C.shape[1] * C.shape[2],
+                              _stream())
+    if rc:
+        raise AWGError(rc, "awg_dense_gemm")
+    return C
+
+
+def dense_potrf(A):
+    """In-place Cholesky of (batch, n, n) column-major blocks; returns info array."""
+    batch, n, _ = A.shape
+    info = np.zeros(batch, dtype=np.int32)
+    rc = lib().awg_dense_potrf(batch, n, A.data_ptr(), n, n * n, info.ctypes.data, _stream())
+    if rc not in (0, -5):
+        raise AWGError(rc, "awg_dense_potrf")
+    return info
+
+
+def dense_trsm(L, B, trans=False):
+    batch, n, _ = L.shape
+    nrhs = B.shape[1]
+    rc = lib().awg_dense_trsm(batch, n, nrhs, int(trans), L.data_ptr(), n, n * n, B.data_ptr(), n, nrhs * n,
+                              _stream())
+    if rc:
+        raise AWGError(rc, "awg_dense_trsm")
+    return B
+
+
+def dense_low_eigs(A, thr, max_k):
+    """Eigenpairs below thr of (batch, n, n) symmetric blocks (A destroyed)."""
+    import torch
+    batch, n, _ = A.shape
+    cnt = np.zeros(batch, dtype=np.int32)
+    lam = torch.zeros(batch, max(max_k, 1), dtype=torch.float64, device=A.device)
+    Z = torch.zeros(batch, max(max_k, 1), n, dtype=torch.float64, device=A.device)
+    rc = lib().awg_dense_low_eigs(batch, n, A.data_ptr(), n, n * n, thr, max_k, cnt.ctypes.data,
+                                  lam.data_ptr(), Z.data_ptr(), max(max_k, 1) * n, _stream())
+    if rc not in (0, -1):
+        raise AWGError(rc, "awg_dense_low_eigs")
+    return cnt, lam, Z

@@ -1,0 +1,135 @@
+// Internal declarations shared by the HIP sources of libawg (gfx950 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+namespace awg {
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+struct Error : std::runtime_error {
+  int code;
+  Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define AWG_HIP(call)                                                                  \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      throw ::awg::Error(e_ == hipErrorOutOfMemory ? -8 : -7,                          \
+                         std::string(#call) + ": " + hipGetErrorString(e_));           \
+  } while (0)
+
+#define AWG_LAUNCH_CHECK() AWG_HIP(hipGetLastError())
+
+inline unsigned cdiv(long a, long b) { return (unsigned)((a + b - 1) / b); }
+
+// ---------------------------------------------------------------------------
+// device buffers
+// ---------------------------------------------------------------------------
+template <class T>
+struct DBuf {
+  T* p = nullptr;
+  size_t n = 0;
+  DBuf() = default;
+  DBuf(const DBuf&) = delete;
+  DBuf& operator=(const DBuf&) = delete;
+  ~DBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  void alloc(size_t count) {
+    release();
+    if (count == 0) return;
+    AWG_HIP(hipMalloc((void**)&p, count * sizeof(T)));
+    n = count;
+  }
+  void zero(hipStream_t s) {
+    if (p) AWG_HIP(hipMemsetAsync(p, 0, n * sizeof(T), s));
+  }
+  void upload(const std::vector<T>& h, hipStream_t s) {
+    alloc(h.size());
+    if (!h.empty()) AWG_HIP(hipMemcpyAsync(p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
+  }
+  std::vector<T> download(hipStream_t s, size_t count = (size_t)-1) const {
+    if (count == (size_t)-1) count = n;
+    std::vector<T> h(count);
+    if (count) {
+      AWG_HIP(hipMemcpyAsync(h.data(), p, count * sizeof(T), hipMemcpyDeviceToHost, s));
+      AWG_HIP(hipStreamSynchronize(s));
+    }
+    return h;
+  }
+  operator T*() const { return p; }
+};
+
+// ---------------------------------------------------------------------------
+// batched dense descriptors (column-major blocks)
+// ---------------------------------------------------------------------------
+struct GemmDesc {
+  const double* A;
+  const double* B;
+  double* C;
+  int m, n, k;
+  int lda, ldb, ldc;
+};
+
+struct MatDesc {         // one square or rectangular column-major block
+  double* A;
+  int m, n, ld;
+  int pad;
+};
+
+// ---------------------------------------------------------------------------
+// kernel launchers (implemented in k_*.hip)
+// ---------------------------------------------------------------------------
+// C = alpha * op(A) op(B) + beta * C for every descriptor; lower != 0 skips
+// 64x64 output tiles lying strictly above the diagonal.
+void gemm_batched(const GemmDesc* d_desc, int batch, int max_m, int max_n, bool transA, bool transB,
+                  double alpha, double beta, bool lower, hipStream_t s);
+// y = alpha * op(A) x + beta * y per descriptor, with the GEMM convention
+// (n == 1: A = matrix, B = x, C = y; op(A) is m x k).
+void gemv_batched(const GemmDesc* d_desc, int batch, int max_m, int max_k, bool transA, double alpha,
+                  double beta, hipStream_t s);
+
+// Cholesky A = L L^T (lower, in place) of every block; info[b] = 0 or the
+// 1-based column of the first non-positive pivot.
+void potrf_batched(const MatDesc* d_mats, const std::vector<int>& h_n, int* d_info, hipStream_t s,
+                   GemmDesc* d_scratch_desc);
+// Solve L X = B (trans = false) or L^T X = B (trans = true) with the lower
+// factor L of block b (n_b x n_b) and B_b (n_b x ncols_b); X overwrites B.
+void trsm_batched(const MatDesc* d_L, const MatDesc* d_B, const std::vector<int>& h_n,
+                  const std::vector<int>& h_ncols, bool trans, hipStream_t s, GemmDesc* d_scratch_desc);
+
+// Householder tridiagonalisation of symmetric blocks (full storage,
+// destroyed).  d, e, tau: per-block arrays at offsets off[b] (size n_b).
+void sytrd_batched(const MatDesc* d_mats, const std::vector<int>& h_n, double* d, double* e,
+                   double* tau, const long* d_off, double* work, hipStream_t s);
+// Eigenvalues < thr of the tridiagonal T_b: count, values and eigenvectors.
+struct TriEigArgs {
+  const double* d;
+  const double* e;
+  const long* off;        // per block: offset of d/e
+  const int* n;           // per block order
+  int nb;
+};
+// thr_mode 0: thr[b] is absolute (count lambda < thr[b]);
+// thr_mode 1: thr[b] = eps0 * max|lambda| computed here, counting lambda <= thr.
+void tri_count(const TriEigArgs& a, const double* thr_in, int thr_mode, double eps0, double* thr_out,
+               int* count, double* lam_minmax, hipStream_t s);
+void tri_eigvecs(const TriEigArgs& a, const int* count, const long* lam_off, double* lam,
+                 const MatDesc* d_Z, double* work, const long* work_off, double* resid,
+                 int* nstrict, const double* thr, hipStream_t s);
+// Z_b <- Q_b Z_b with the reflectors stored by sytrd_batched.
+void ormtr_batched(const MatDesc* d_mats, const MatDesc* d_Z, const double* tau, const long* d_off,
+                   const std::vector<int>& h_n, const std::vector<int>& h_k, hipStream_t s);
+
+}  // namespace awg

@@ -1,0 +1,1092 @@
+// AWG preconditioner and PCG on one MI355X: set-up pipeline, application,
+// solver and the C ABI (include/awg.h).
+//
+// Method (Gouarin & Spillane): H = H2 + W (W^T A W)^{-1} W^T with
+// H2 = Pi H^NN Pi^T + R0^T E0^{-1} R0 (Sections 3.3-3.4, 4.3).  Every step
+// runs as a HIP kernel on the context's stream; the host only sequences the
+// launches, sizes buffers from counts read back between phases, and tests
+// convergence.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <sstream>
+
+#include "awg.h"
+#include "awg_common.h"
+#include "awg_sparse.h"
+
+using namespace awg;
+
+namespace {
+
+thread_local std::string g_setup_error = "no error";
+
+double now_ms() {
+  using namespace std::chrono;
+  return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+// per-subdomain column blocks (n_s x c_s, leading dimension n_s)
+struct ColLayout {
+  std::vector<int> c;        // columns per subdomain
+  std::vector<long> eoff;    // element offset of block s
+  std::vector<long> coff;    // offset of the columns of s in the concatenation
+  long elems = 0, cols = 0;
+  DBuf<long> d_eoff, d_coff;
+  void build(const std::vector<int>& ns, const std::vector<int>& cs, hipStream_t s) {
+    c = cs;
+    eoff.assign(ns.size() + 1, 0);
+    coff.assign(ns.size() + 1, 0);
+    for (size_t i = 0; i < ns.size(); ++i) {
+      eoff[i + 1] = eoff[i] + (long)ns[i] * cs[i];
+      coff[i + 1] = coff[i] + cs[i];
+    }
+    elems = eoff.back();
+    cols = coff.back();
+    d_eoff.upload(eoff, s);
+    d_coff.upload(coff, s);
+  }
+};
+
+}  // namespace
+
+// workspace for applying the operators to b columns at once
+struct MultiWS {
+  int b = 0;
+  DBuf<double> R, Z, T1, T2;          // n x b
+  DBuf<double> Xs, Os;                // sum n_s x b (per-subdomain blocks)
+  DBuf<double> Tk;                    // sum k_s x b
+  DBuf<double> G0, G1, G2;            // n0 x b
+  DBuf<double> H0, H1;                // n_minus x b
+  DBuf<GemmDesc> dVt, dV, dYt, dY, dP, dE0a, dE0b, dWt, dEW, dW;
+  int maxk = 0, maxm = 0, maxns = 0;
+};
+
+struct awg_ctx {
+  hipStream_t s = nullptr;
+  awg_options opt{};
+  int n = 0, nnz = 0, N = 0;
+  long sumns = 0;
+  std::string err = "no error";
+  // inputs (copied)
+  DBuf<int> rowptr, col;
+  DBuf<double> val;
+  std::vector<long> h_subptr;
+  std::vector<int> ns;
+  DBuf<long> subptr;
+  DBuf<int> subidx, entsub;
+  // maps
+  DBuf<int> mult, invptr, invsub, invloc, cnt;
+  DBuf<double> bval, dw;
+  // dense blocks: one "arena" holds every n_s x n_s block
+  std::vector<long> sqoff;
+  DBuf<long> d_sqoff;
+  long sqtot = 0;
+  int maxns = 0;
+  // local results
+  std::vector<int> ks, kstrict, ms;
+  ColLayout LV, LY;
+  DBuf<double> V, lamV, Y, lamY;
+  DBuf<double> P;
+  DBuf<float> P32;
+  int n0 = 0, nminus = 0;
+  DBuf<double> E0inv, W, EWinv;
+  MultiWS ws1;           // single-vector workspace (apply / PCG)
+  DBuf<double> pcg_buf;  // x r z p q of the main PCG
+  DBuf<double> scal;     // device scalars
+  std::map<std::string, double> tms;
+  int w_iters = 0;
+  double w_time = 0.0;
+  std::vector<double> eig_resid_max;
+};
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// small device kernels used only here
+// ---------------------------------------------------------------------------
+__global__ void k_scale_rows_blocks(double* T, const long* coff, const double* lam, int N, int b) {
+  // T: concatenation of k_s x b blocks at coff[s]*b; row r of block s scaled by |lam[coff[s]+r]|
+  const int s = blockIdx.y;
+  const long a = coff[s], ks = coff[s + 1] - a;
+  const long tot = ks * b;
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += (long)gridDim.x * blockDim.x) {
+    const long r = e % ks;
+    T[a * b + e] *= fabs(lam[a + r]);
+  }
+}
+
+__global__ void k_identity_cols(double* G, int n0, int b, int c0) {
+  const long tot = (long)n0 * b;
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += (long)gridDim.x * blockDim.x) {
+    const int r = (int)(e % n0), c = (int)(e / n0);
+    G[e] = (r == c0 + c) ? 1.0 : 0.0;
+  }
+}
+
+__global__ void k_copy_cols(const double* src, long lds, double* dst, long ldd, int m, int b) {
+  const long tot = (long)m * b;
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += (long)gridDim.x * blockDim.x) {
+    const int r = (int)(e % m), c = (int)(e / m);
+    dst[r + c * ldd] = src[r + c * lds];
+  }
+}
+
+// prolongated strictly negative eigenvectors: Vg[:, off_s + j] = R^sT V^s[:, j], j < kstrict_s
+__global__ void k_build_vg(const long* sub_ptr, const int* sub_idx, const double* V, const long* veoff,
+                           const long* gcoff, int N, double* Vg, long ldv, int c0, int b) {
+  const int s = blockIdx.y;
+  const long a = sub_ptr[s], ns = sub_ptr[s + 1] - a;
+  const long g0 = gcoff[s], kst = gcoff[s + 1] - g0;
+  const long tot = ns * kst;
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += (long)gridDim.x * blockDim.x) {
+    const long l = e % ns, j = e / ns;
+    const long gc = g0 + j - c0;
+    if (gc < 0 || gc >= b) continue;
+    Vg[sub_idx[a + l] + gc * ldv] = V[veoff[s] + l + j * ns];
+  }
+}
+
+__global__ void k_pcg_scalars(double* sc, int it, int mode) {
+  // sc layout: [0] rz, [1] pq, [2] alpha, [3] rz_new, [4] beta, [5] rr
+  // alpha/beta histories at sc[16 + 2*it], sc[17 + 2*it]
+  if (threadIdx.x != 0) return;
+  if (mode == 0) {
+    const double a = sc[0] / sc[1];
+    sc[2] = a;
+    sc[16 + 2 * it] = a;
+  } else {
+    const double bta = sc[3] / sc[0];
+    sc[4] = bta;
+    sc[0] = sc[3];
+    sc[17 + 2 * it] = bta;
+  }
+}
+
+__global__ void k_pcg_update_xr(int n, double* x, double* r, const double* p, const double* q, const double* sc) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double a = sc[2];
+  x[i] += a * p[i];
+  r[i] -= a * q[i];
+}
+
+__global__ void k_pcg_update_p(int n, double* p, const double* z, const double* sc) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  p[i] = z[i] + sc[4] * p[i];
+}
+
+__global__ void k_f32_from_f64(long tot, const double* a, float* b) {
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += (long)gridDim.x * blockDim.x)
+    b[e] = (float)a[e];
+}
+
+// FP32 local solve: Os_s = P32_s Xs_s (FP32 matrix, FP64 vectors and sums)
+__global__ __launch_bounds__(256) void k_gemv_f32(const float* P, const long* sqoff, const long* subptr,
+                                                  const double* Xs, double* Os) {
+  const int s = blockIdx.y;
+  const long a = subptr[s];
+  const int ns = (int)(subptr[s + 1] - a);
+  const int r = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int i = blockIdx.x * 64 + r;
+  __shared__ double part[4][64];
+  double acc = 0.0;
+  if (i < ns) {
+    const float* pa = P + sqoff[s] + i;
+    const double* x = Xs + a;
+    for (int j = g; j < ns; j += 4) acc += (double)pa[(long)j * ns] * x[j];
+  }
+  part[g][r] = acc;
+  __syncthreads();
+  if (g == 0 && i < ns) Os[a + i] = (part[0][r] + part[1][r]) + (part[2][r] + part[3][r]);
+}
+
+int errbits_to_status(int e, std::string& msg) {
+  if (e & 16) { msg = "A is not a valid CSR matrix (column out of range, unsorted or duplicate)"; return AWG_ERR_ARG; }
+  if (e & 1) { msg = "subdomain lists are not a partition: empty, unsorted, duplicate, out of range or not covering [0,n)"; return AWG_ERR_PARTITION; }
+  if (e & 8) { msg = "A holds a NaN or Inf"; return AWG_ERR_NONFINITE; }
+  if (e & 2) { msg = "A is not symmetric"; return AWG_ERR_NOT_SYMMETRIC; }
+  if (e & 4) { msg = "minimal overlap assumption violated: some A_ij != 0 has no subdomain holding both i and j"; return AWG_ERR_MIN_OVERLAP; }
+  return AWG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// helpers
+// ---------------------------------------------------------------------------
+std::vector<MatDesc> square_descs(const awg_ctx& c, double* arena) {
+  std::vector<MatDesc> v(c.N);
+  for (int s = 0; s < c.N; ++s) v[s] = MatDesc{arena + c.sqoff[s], c.ns[s], c.ns[s], c.ns[s], 0};
+  return v;
+}
+
+std::vector<MatDesc> col_descs(const awg_ctx& c, double* base, const ColLayout& L) {
+  std::vector<MatDesc> v(c.N);
+  for (int s = 0; s < c.N; ++s) v[s] = MatDesc{base + L.eoff[s], c.ns[s], L.c[s], c.ns[s], 0};
+  return v;
+}
+
+void bmm(const DBuf<GemmDesc>& d, int batch, int maxm, int maxn, int maxk, bool tA, double alpha, double beta,
+         int b, hipStream_t s) {
+  if (batch == 0) return;
+  if (b == 1) gemv_batched(d, batch, maxm, maxk, tA, alpha, beta, s);
+  else gemm_batched(d, batch, maxm, maxn, tA, false, alpha, beta, false, s);
+}
+
+void gemm_upload(DBuf<GemmDesc>& d, const std::vector<GemmDesc>& h, hipStream_t s) { d.upload(h, s); }
+
+// build the b-column workspace and its descriptors
+void build_ws(awg_ctx& c, MultiWS& w, int b) {
+  hipStream_t s = c.s;
+  w.b = b;
+  const long n = c.n;
+  w.R.alloc(n * b);
+  w.Z.alloc(n * b);
+  w.T1.alloc(n * b);
+  w.T2.alloc(n * b);
+  w.Xs.alloc(c.sumns * b);
+  w.Os.alloc(c.sumns * b);
+  w.Tk.alloc(std::max<long>(1, c.LV.cols) * b);
+  w.G0.alloc(std::max(1, c.n0) * (long)b);
+  w.G1.alloc(std::max(1, c.n0) * (long)b);
+  w.G2.alloc(std::max(1, c.n0) * (long)b);
+  w.H0.alloc(std::max(1, c.nminus) * (long)b);
+  w.H1.alloc(std::max(1, c.nminus) * (long)b);
+  std::vector<GemmDesc> vt(c.N), vv(c.N), yt(c.N), yy(c.N), pp(c.N);
+  w.maxk = w.maxm = w.maxns = 0;
+  for (int q = 0; q < c.N; ++q) {
+    const int nsq = c.ns[q];
+    const long so = c.h_subptr[q] * b;
+    const int kq = c.ks[q], mq = c.ms[q];
+    w.maxk = std::max(w.maxk, kq);
+    w.maxm = std::max(w.maxm, mq);
+    w.maxns = std::max(w.maxns, nsq);
+    vt[q] = GemmDesc{c.V + c.LV.eoff[q], w.Xs + so, w.Tk + c.LV.coff[q] * b, kq, b, nsq, nsq, nsq, std::max(1, kq)};
+    vv[q] = GemmDesc{c.V + c.LV.eoff[q], w.Tk + c.LV.coff[q] * b, w.Os + so, nsq, b, kq, nsq, std::max(1, kq), nsq};
+    yt[q] = GemmDesc{c.Y + c.LY.eoff[q], w.Xs + so, w.G0 + c.LY.coff[q], mq, b, nsq, nsq, nsq, std::max(1, c.n0)};
+    yy[q] = GemmDesc{c.Y + c.LY.eoff[q], w.G1 + c.LY.coff[q], w.Os + so, nsq, b, mq, nsq, std::max(1, c.n0), nsq};
+    pp[q] = GemmDesc{c.P + c.sqoff[q], w.Xs + so, w.Os + so, nsq, b, nsq, nsq, nsq, nsq};
+  }
+  gemm_upload(w.dVt, vt, s);
+  gemm_upload(w.dV, vv, s);
+  gemm_upload(w.dYt, yt, s);
+  gemm_upload(w.dY, yy, s);
+  gemm_upload(w.dP, pp, s);
+  const int n0 = std::max(1, c.n0), nm = std::max(1, c.nminus);
+  gemm_upload(w.dE0a, {GemmDesc{c.E0inv, w.G0, w.G1, c.n0, b, c.n0, n0, n0, n0}}, s);
+  gemm_upload(w.dE0b, {GemmDesc{c.E0inv, w.G0, w.G2, c.n0, b, c.n0, n0, n0, n0}}, s);
+  gemm_upload(w.dWt, {GemmDesc{c.W, w.R, w.H0, c.nminus, b, c.n, c.n, c.n, nm}}, s);
+  gemm_upload(w.dEW, {GemmDesc{c.EWinv, w.H0, w.H1, c.nminus, b, c.nminus, nm, nm, nm}}, s);
+  gemm_upload(w.dW, {GemmDesc{c.W, w.H1, w.Z, c.n, b, c.nminus, c.n, nm, c.n}}, s);
+}
+
+// Y = beta Y + A_- X   (A_- = sum_s R^sT V^s |L^s_-| V^sT R^s; Definition of A_-, Section 3.2)
+void op_aminus(awg_ctx& c, MultiWS& w, const double* X, double* Yo, double beta) {
+  const int b = w.b;
+  if (c.LV.cols == 0) {
+    if (beta == 0.0) AWG_HIP(hipMemsetAsync(Yo, 0, sizeof(double) * c.n * (size_t)b, c.s));
+    return;
+  }
+  l_gather(c.sumns, c.subidx, c.entsub, c.subptr, X, c.n, b, nullptr, w.Xs, c.s);
+  bmm(w.dVt, c.N, w.maxk, b, w.maxns, true, 1.0, 0.0, b, c.s);
+  hipLaunchKernelGGL(k_scale_rows_blocks, dim3(64, c.N), dim3(256), 0, c.s, w.Tk.p, c.LV.d_coff.p, c.lamV.p, c.N, b);
+  AWG_LAUNCH_CHECK();
+  bmm(w.dV, c.N, w.maxns, b, w.maxk, false, 1.0, 0.0, b, c.s);
+  l_scatter(c.n, c.invptr, c.invsub, c.invloc, c.subptr, w.Os, b, nullptr, Yo, c.n, 1.0, beta, c.s);
+}
+
+// Y = A_+ X = A X + A_- X (item (i) of the A_+ theorem, Section 3.2)
+void op_aplus(awg_ctx& c, MultiWS& w, const double* X, double* Yo) {
+  l_spmm(c.n, c.rowptr, c.col, c.val, X, c.n, Yo, c.n, w.b, 1.0, 0.0, c.s);
+  op_aminus(c, w, X, Yo, 1.0);
+}
+
+// G0 = R0 X  (R0^T = [R^1T Y^1 | ... | R^NT Y^N])
+void op_r0(awg_ctx& c, MultiWS& w, const double* X) {
+  l_gather(c.sumns, c.subidx, c.entsub, c.subptr, X, c.n, w.b, nullptr, w.Xs, c.s);
+  bmm(w.dYt, c.N, w.maxm, w.b, w.maxns, true, 1.0, 0.0, w.b, c.s);
+}
+
+// Yo = beta Yo + R0^T G1
+void op_r0t(awg_ctx& c, MultiWS& w, double* Yo, double beta) {
+  bmm(w.dY, c.N, w.maxns, w.b, w.maxm, false, 1.0, 0.0, w.b, c.s);
+  l_scatter(c.n, c.invptr, c.invsub, c.invloc, c.subptr, w.Os, w.b, nullptr, Yo, c.n, 1.0, beta, c.s);
+}
+
+// Yo = H^NN X = sum_s R^sT P^s R^s X with P^s = D^s (A^s_+)^+ D^s (Definition of H^NN, Section 3.3)
+void op_hnn(awg_ctx& c, MultiWS& w, const double* X, double* Yo, bool f32) {
+  l_gather(c.sumns, c.subidx, c.entsub, c.subptr, X, c.n, w.b, nullptr, w.Xs, c.s);
+  if (f32 && w.b == 1) {
+    hipLaunchKernelGGL(k_gemv_f32, dim3(cdiv(w.maxns, 64), c.N), dim3(256), 0, c.s, c.P32.p, c.d_sqoff.p,
+                       c.subptr.p, w.Xs.p, w.Os.p);
+    AWG_LAUNCH_CHECK();
+  } else {
+    bmm(w.dP, c.N, w.maxns, w.b, w.maxns, false, 1.0, 0.0, w.b, c.s);
+  }
+  l_scatter(c.n, c.invptr, c.invsub, c.invloc, c.subptr, w.Os, w.b, nullptr, Yo, c.n, 1.0, 0.0, c.s);
+}
+
+}  // namespace
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// H2 and H on the b columns of w.R -> w.Z
+// ---------------------------------------------------------------------------
+// H2 = Pi H^NN Pi^T + R0^T E0^{-1} R0 (Theorem on H^NN_hyb, Section 3.4):
+//   u0 = E0^{-1} R0 r; t = r - A_+ R0^T u0; y = H^NN t;
+//   v = E0^{-1} R0 A_+ y; z = y + R0^T (u0 - v)
+void op_h2(awg_ctx& c, MultiWS& w, bool f32) {
+  const int b = w.b;
+  if (c.n0 == 0) {
+    op_hnn(c, w, w.R, w.Z, f32);
+    return;
+  }
+  op_r0(c, w, w.R);                                                      // G0 = R0 r
+  bmm(w.dE0a, 1, c.n0, b, c.n0, false, 1.0, 0.0, b, c.s);                // G1 = u0
+  op_r0t(c, w, w.T1, 0.0);                                               // T1 = R0^T u0
+  op_aplus(c, w, w.T1, w.T2);                                            // T2 = A_+ R0^T u0
+  l_colaxpby(c.n, b, w.R, c.n, nullptr, w.T2, c.n, nullptr, 1.0, -1.0, c.s);  // T2 = r - T2
+  op_hnn(c, w, w.T2, w.Z, f32);                                          // Z = y
+  op_aplus(c, w, w.Z, w.T1);                                             // T1 = A_+ y
+  op_r0(c, w, w.T1);                                                     // G0 = R0 A_+ y
+  bmm(w.dE0b, 1, c.n0, b, c.n0, false, 1.0, 0.0, b, c.s);                // G2 = v
+  l_colaxpby(c.n0, b, w.G2, c.n0, nullptr, w.G1, c.n0, nullptr, -1.0, 1.0, c.s);  // G1 = u0 - v
+  op_r0t(c, w, w.Z, 1.0);                                                // Z += R0^T (u0 - v)
+}
+
+// H = H3,ad = H2 + W (W^T A W)^{-1} W^T (Definition of Pi_3 and H3, Section 4.3)
+void op_h(awg_ctx& c, MultiWS& w, bool f32) {
+  op_h2(c, w, f32);
+  if (c.nminus == 0) return;
+  const int b = w.b;
+  bmm(w.dWt, 1, c.nminus, b, c.n, true, 1.0, 0.0, b, c.s);               // H0 = W^T r
+  bmm(w.dEW, 1, c.nminus, b, c.nminus, false, 1.0, 0.0, b, c.s);         // H1 = E_W^{-1} H0
+  bmm(w.dW, 1, c.n, b, c.nminus, false, 1.0, 1.0, b, c.s);               // Z += W H1
+}
+
+void sync(awg_ctx& c) { AWG_HIP(hipStreamSynchronize(c.s)); }
+
+struct PhaseTimer {
+  awg_ctx& c;
+  std::string name;
+  double t0;
+  PhaseTimer(awg_ctx& c_, const char* nm) : c(c_), name(nm) {
+    sync(c);
+    t0 = now_ms();
+  }
+  ~PhaseTimer() {
+    (void)hipStreamSynchronize(c.s);
+    c.tms[name] += now_ms() - t0;
+  }
+};
+
+__global__ void k_rowptr32(int n, const int64_t* rp, int* out, long nnz, int* err) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i > n) return;
+  const int64_t v = rp[i];
+  if (v < 0 || v > nnz) atomicOr(err, 16);
+  if (i == 0 && v != 0) atomicOr(err, 16);
+  if (i == n && v != nnz) atomicOr(err, 16);
+  if (i < n && rp[i + 1] < v) atomicOr(err, 16);
+  out[i] = (int)v;
+}
+
+__global__ void k_fill(double* p, long n, double v) {
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) p[e] = v;
+}
+
+void check_info(awg_ctx& c, DBuf<int>& info, const char* what) {
+  auto h = info.download(c.s);
+  for (size_t s = 0; s < h.size(); ++s)
+    if (h[s] != 0) {
+      std::ostringstream o;
+      o << what << ": Cholesky breakdown in block " << s << " at column " << h[s];
+      throw Error(AWG_ERR_NOT_SPD, o.str());
+    }
+}
+
+// ---------------------------------------------------------------------------
+// set-up phases
+// ---------------------------------------------------------------------------
+// Definition of a partition, minimal overlap (Section 2.1); partition of unity
+// (Section 2.2); M_mu and B (Section 3.1).
+void phase_maps(awg_ctx& c, const int64_t* rowptr, const int32_t* col, const double* val, const int64_t* sub_ptr,
+                const int32_t* sub_idx) {
+  PhaseTimer t(c, "maps");
+  hipStream_t s = c.s;
+  DBuf<int> err;
+  err.alloc(1);
+  err.zero(s);
+  c.rowptr.alloc(c.n + 1);
+  hipLaunchKernelGGL(k_rowptr32, dim3(cdiv(c.n + 1, 256)), dim3(256), 0, s, c.n, rowptr, c.rowptr.p, (long)c.nnz,
+                     err.p);
+  AWG_LAUNCH_CHECK();
+  c.col.alloc(c.nnz);
+  c.val.alloc(c.nnz);
+  AWG_HIP(hipMemcpyAsync(c.col.p, col, sizeof(int) * c.nnz, hipMemcpyDeviceToDevice, s));
+  AWG_HIP(hipMemcpyAsync(c.val.p, val, sizeof(double) * c.nnz, hipMemcpyDeviceToDevice, s));
+  c.h_subptr.resize(c.N + 1);
+  AWG_HIP(hipMemcpyAsync(c.h_subptr.data(), sub_ptr, sizeof(int64_t) * (c.N + 1), hipMemcpyDeviceToHost, s));
+  sync(c);
+  if (c.h_subptr[0] != 0) throw Error(AWG_ERR_PARTITION, "sub_ptr[0] must be 0");
+  for (int q = 0; q < c.N; ++q)
+    if (c.h_subptr[q + 1] <= c.h_subptr[q]) throw Error(AWG_ERR_PARTITION, "empty subdomain or decreasing sub_ptr");
+  c.sumns = c.h_subptr[c.N];
+  if (c.sumns >= (1L << 31)) throw Error(AWG_ERR_ARG, "sum of subdomain sizes must be < 2^31");
+  c.ns.resize(c.N);
+  c.maxns = 0;
+  for (int q = 0; q < c.N; ++q) {
+    c.ns[q] = (int)(c.h_subptr[q + 1] - c.h_subptr[q]);
+    c.maxns = std::max(c.maxns, c.ns[q]);
+  }
+  c.subptr.upload(c.h_subptr, s);
+  c.subidx.alloc(c.sumns);
+  AWG_HIP(hipMemcpyAsync(c.subidx.p, sub_idx, sizeof(int) * c.sumns, hipMemcpyDeviceToDevice, s));
+  c.entsub.alloc(c.sumns);
+  l_entry_owner(c.N, c.subptr, c.entsub, s);
+  l_validate_subs(c.N, c.subptr, c.subidx, c.n, err, s);
+  {
+    int e = err.download(s)[0];
+    std::string msg;
+    int st = errbits_to_status(e, msg);
+    if (st) throw Error(st, msg);
+  }
+  c.mult.alloc(c.n);
+  c.mult.zero(s);
+  l_mult(c.sumns, c.subidx, c.mult, s);
+  l_check_cover(c.n, c.mult, err, s);
+  c.invptr.alloc(c.n + 1);
+  l_scan(c.n, c.mult, c.invptr, s);
+  DBuf<int> fill;
+  fill.alloc(c.n);
+  fill.zero(s);
+  c.invsub.alloc(c.sumns);
+  c.invloc.alloc(c.sumns);
+  l_fill_inv(c.N, c.subptr, c.subidx, c.invptr, fill, c.invsub, c.invloc, s);
+  l_sort_inv(c.n, c.invptr, c.invsub, c.invloc, s);
+  c.cnt.alloc(c.nnz);
+  c.bval.alloc(c.nnz);
+  l_pairs(c.n, c.rowptr, c.col, c.val, c.invptr, c.invsub, c.cnt, c.bval, err, s);
+  c.dw.alloc(c.sumns);
+  l_pou(c.sumns, c.subidx, c.mult, c.dw, s);
+  int e = err.download(s)[0];
+  std::string msg;
+  int st = errbits_to_status(e, msg);
+  if (st) throw Error(st, msg);
+  c.sqoff.assign(c.N + 1, 0);
+  for (int q = 0; q < c.N; ++q) c.sqoff[q + 1] = c.sqoff[q] + (long)c.ns[q] * c.ns[q];
+  c.sqtot = c.sqoff[c.N];
+  c.d_sqoff.upload(c.sqoff, s);
+}
+
+// Batched eigenvalues below a threshold of dense symmetric blocks (destroys
+// X).  Returns counts; fills lam / vectors in the layout built from them.
+struct EigOut {
+  std::vector<int> count, nstrict;
+  double resid_max = 0.0;
+};
+
+EigOut batched_low_eigs(awg_ctx& c, DBuf<MatDesc>& dX, int thr_mode, double thr_value, ColLayout& L,
+                        DBuf<double>& vecs, DBuf<double>& lam, bool want_strict) {
+  hipStream_t s = c.s;
+  DBuf<double> d, e, tau, work, thr, minmax;
+  d.alloc(c.sumns);
+  e.alloc(c.sumns);
+  tau.alloc(c.sumns);
+  work.alloc(6 * c.sumns);
+  thr.alloc(c.N);
+  minmax.alloc(2 * c.N);
+  sytrd_batched(dX, c.ns, d, e, tau, c.subptr, work, s);
+  DBuf<int> nd, cnt, nst;
+  nd.upload(c.ns, s);
+  cnt.alloc(c.N);
+  nst.alloc(c.N);
+  TriEigArgs a{d, e, c.subptr, nd, c.N};
+  if (thr_mode == 0) {
+    hipLaunchKernelGGL(k_fill, dim3(cdiv(c.N, 256)), dim3(256), 0, s, thr.p, (long)c.N, thr_value);
+    AWG_LAUNCH_CHECK();
+  }
+  tri_count(a, thr, thr_mode, thr_value, thr, cnt, minmax, s);
+  EigOut out;
+  out.count = cnt.download(s);
+  L.build(c.ns, out.count, s);
+  vecs.alloc(std::max<long>(1, L.elems));
+  lam.alloc(std::max<long>(1, L.cols));
+  DBuf<double> resid;
+  resid.alloc(std::max<long>(1, L.cols));
+  std::vector<long> w6(c.N);
+  for (int q = 0; q < c.N; ++q) w6[q] = 6 * c.h_subptr[q];
+  DBuf<long> dw6;
+  dw6.upload(w6, s);
+  auto zd = col_descs(c, vecs, L);
+  DBuf<MatDesc> dZ;
+  dZ.upload(zd, s);
+  tri_eigvecs(a, cnt, L.d_coff, lam, dZ, work, dw6, resid, want_strict ? nst.p : nullptr, thr, s);
+  ormtr_batched(dX, dZ, tau, c.subptr, c.ns, out.count, s);
+  if (want_strict) out.nstrict = nst.download(s);
+  if (L.cols) {
+    auto r = resid.download(s, L.cols);
+    for (double v : r) out.resid_max = std::max(out.resid_max, v);
+  }
+  if (!(out.resid_max <= 1e-8))
+    throw Error(AWG_ERR_EIGEN, "tridiagonal inverse iteration did not converge (residual " +
+                                   std::to_string(out.resid_max) + ")");
+  return out;
+}
+
+// B^s, its non-positive eigenpairs (splitting of B^s, Section 3.2), the local
+// factor and P^s = D^s (A^s_+)^+ D^s, the GenEO coarse vectors Y^s
+// (Theorem on H^NN_hyb, Section 3.4).
+void phase_local(awg_ctx& c) {
+  hipStream_t s = c.s;
+  DBuf<double> X1, X2, X3;
+  X1.alloc(c.sqtot);
+  X2.alloc(c.sqtot);
+  X3.alloc(c.sqtot);
+  DBuf<MatDesc> d1, d2, d3;
+  d1.upload(square_descs(c, X1), s);
+  d2.upload(square_descs(c, X2), s);
+  d3.upload(square_descs(c, X3), s);
+  DBuf<int> info;
+  info.alloc(c.N);
+  {
+    PhaseTimer t(c, "local_split");
+    X1.zero(s);
+    l_extract(c.N, c.subptr, c.subidx, c.rowptr, c.col, c.bval, d1, s);          // B^s
+    l_copy_mat(d1, d2, c.N, s);
+    EigOut eo = batched_low_eigs(c, d2, 1, c.opt.zero_tol, c.LV, c.V, c.lamV, true);
+    c.ks = eo.count;
+    c.kstrict = eo.nstrict;
+    c.eig_resid_max.push_back(eo.resid_max);
+  }
+  DBuf<double> cs, U;
+  cs.alloc(c.N);
+  U.alloc(std::max<long>(1, c.LV.elems));
+  auto vdesc = col_descs(c, c.V, c.LV);
+  auto udesc = col_descs(c, U, c.LV);
+  DBuf<MatDesc> dV, dU;
+  dV.upload(vdesc, s);
+  dU.upload(udesc, s);
+  std::vector<GemmDesc> g(c.N);
+  DBuf<GemmDesc> dg;
+  int maxk = 0;
+  for (int q = 0; q < c.N; ++q) maxk = std::max(maxk, c.ks[q]);
+  auto lowrank_into = [&](double* arena, double alpha) {
+    // arena_s += alpha * U_s V_s^T
+    for (int q = 0; q < c.N; ++q)
+      g[q] = GemmDesc{U.p + c.LV.eoff[q], c.V.p + c.LV.eoff[q], arena + c.sqoff[q], c.ns[q], c.ns[q], c.ks[q],
+                      c.ns[q], c.ns[q], c.ns[q]};
+    dg.upload(g, s);
+    if (maxk > 0) gemm_batched(dg, c.N, c.maxns, c.maxns, false, true, alpha, 1.0, false, s);
+  };
+  {
+    PhaseTimer t(c, "local_factor");
+    // K^s = B^s + V_-(c_s - L_-)V_-^T (spd), c_s = mean diag B^s
+    l_diag_mean(d1, c.N, cs, s);
+    if (c.LV.elems) AWG_HIP(hipMemcpyAsync(U.p, c.V.p, sizeof(double) * c.LV.elems, hipMemcpyDeviceToDevice, s));
+    l_scale_cols(dU, c.N, c.LV.d_coff, c.lamV, 1.0, cs, 2, s);
+    l_copy_mat(d1, d3, c.N, s);
+    lowrank_into(X3, 1.0);
+    info.zero(s);
+    potrf_batched(d3, c.ns, info, s, nullptr);
+    check_info(c, info, "local factor K^s");
+    // K^{-1} = L^{-T} L^{-1}
+    l_set_identity(d2, c.N, s);
+    trsm_batched(d3, d2, c.ns, c.ns, false, s, nullptr);
+    trsm_batched(d3, d2, c.ns, c.ns, true, s, nullptr);
+    // (A^s_+)^+ = K^{-1} - c_s^{-1} V_- V_-^T, then D^s (.) D^s
+    if (c.LV.elems) AWG_HIP(hipMemcpyAsync(U.p, c.V.p, sizeof(double) * c.LV.elems, hipMemcpyDeviceToDevice, s));
+    l_scale_cols(dU, c.N, c.LV.d_coff, c.lamV, 1.0, cs, 3, s);
+    lowrank_into(X2, -1.0);
+    l_scale_sym(d2, c.N, c.subptr, c.dw, false, true, s);
+    std::swap(c.P.p, X2.p);
+    std::swap(c.P.n, X2.n);
+    if (c.opt.local_prec == AWG_LOCAL_F32) {
+      c.P32.alloc(c.sqtot);
+      hipLaunchKernelGGL(k_f32_from_f64, dim3(4096), dim3(256), 0, s, (long)c.sqtot, c.P.p, c.P32.p);
+      AWG_LAUNCH_CHECK();
+    }
+  }
+  {
+    PhaseTimer t(c, "geneo");
+    // U = V_- |L_-|
+    if (c.LV.elems) AWG_HIP(hipMemcpyAsync(U.p, c.V.p, sizeof(double) * c.LV.elems, hipMemcpyDeviceToDevice, s));
+    l_scale_cols(dU, c.N, c.LV.d_coff, c.lamV, 1.0, nullptr, 1, s);
+    // M_A = D^{-1} A^s_+ D^{-1}, A^s_+ = B^s + V_- |L_-| V_-^T  (in X3)
+    l_copy_mat(d1, d3, c.N, s);
+    lowrank_into(X3, 1.0);
+    l_scale_sym(d3, c.N, c.subptr, c.dw, true, true, s);
+    // M_B = R^s A R^sT + sum_t R^s R^tT V^t |L^t| V^tT R^t R^sT  (in X1)
+    X1.zero(s);
+    l_extract(c.N, c.subptr, c.subidx, c.rowptr, c.col, c.val, d1, s);
+    lowrank_into(X1, 1.0);
+    l_mb_neighbours(c.N, c.subptr, c.subidx, c.mult, c.invptr, c.invsub, c.invloc, d1, c.V, c.LV.d_eoff, c.lamV,
+                    c.LV.d_coff, s);
+    l_scale_sym(d1, c.N, nullptr, nullptr, false, true, s);
+    info.zero(s);
+    potrf_batched(d1, c.ns, info, s, nullptr);
+    check_info(c, info, "GenEO M_B^s");
+    // C = L^{-1} M_A L^{-T}
+    trsm_batched(d1, d3, c.ns, c.ns, false, s, nullptr);
+    l_transpose_inplace(d3, c.N, s);
+    trsm_batched(d1, d3, c.ns, c.ns, false, s, nullptr);
+    l_scale_sym(d3, c.N, nullptr, nullptr, false, true, s);
+    EigOut eo = batched_low_eigs(c, d3, 0, c.opt.tau, c.LY, c.Y, c.lamY, false);
+    c.ms = eo.count;
+    c.eig_resid_max.push_back(eo.resid_max);
+    // Y = L^{-T} Z
+    DBuf<MatDesc> dY;
+    dY.upload(col_descs(c, c.Y, c.LY), s);
+    trsm_batched(d1, dY, c.ns, c.ms, true, s, nullptr);
+    c.n0 = (int)c.LY.cols;
+  }
+}
+
+// explicit inverse of one dense spd matrix M (n x n, in place in M's buffer
+// replaced by the inverse in Minv)
+void spd_inverse(awg_ctx& c, double* M, int n, DBuf<double>& Minv, const char* what) {
+  hipStream_t s = c.s;
+  Minv.alloc((long)n * n);
+  DBuf<MatDesc> dm, di;
+  dm.upload({MatDesc{M, n, n, n, 0}}, s);
+  di.upload({MatDesc{Minv.p, n, n, n, 0}}, s);
+  l_scale_sym(dm, 1, nullptr, nullptr, false, true, s);
+  DBuf<int> info;
+  info.alloc(1);
+  info.zero(s);
+  potrf_batched(dm, {n}, info, s, nullptr);
+  check_info(c, info, what);
+  l_set_identity(di, 1, s);
+  trsm_batched(dm, di, {n}, {n}, false, s, nullptr);
+  trsm_batched(dm, di, {n}, {n}, true, s, nullptr);
+  l_scale_sym(di, 1, nullptr, nullptr, false, true, s);
+}
+
+// E0 = R0 A_+ R0^T and its inverse (Theorem on H^NN_hyb, Section 3.4)
+void phase_coarse0(awg_ctx& c) {
+  PhaseTimer t(c, "coarse0");
+  if (c.n0 == 0) return;
+  hipStream_t s = c.s;
+  const int b = std::min(c.n0, 512);
+  MultiWS w;
+  build_ws(c, w, b);
+  DBuf<double> E0;
+  E0.alloc((long)c.n0 * c.n0);
+  for (int c0 = 0; c0 < c.n0; c0 += b) {
+    const int bc = std::min(b, c.n0 - c0);
+    hipLaunchKernelGGL(k_identity_cols, dim3(256), dim3(256), 0, s, w.G1.p, c.n0, b, c0);
+    AWG_LAUNCH_CHECK();
+    op_r0t(c, w, w.T1, 0.0);          // R0^T e_j
+    op_aplus(c, w, w.T1, w.T2);       // A_+ R0^T e_j
+    op_r0(c, w, w.T2);                // R0 A_+ R0^T e_j  -> G0
+    hipLaunchKernelGGL(k_copy_cols, dim3(256), dim3(256), 0, s, w.G0.p, (long)c.n0, E0.p + (long)c0 * c.n0,
+                       (long)c.n0, c.n0, bc);
+    AWG_LAUNCH_CHECK();
+  }
+  spd_inverse(c, E0, c.n0, c.E0inv, "coarse matrix E0");
+}
+
+// W = A_+^{-1} [R^1T V^1_- | ... ] (strictly negative pairs; Remark 1 and 2,
+// Section 4.4) by PCG on A_+ preconditioned with H2, all columns side by side.
+void phase_W(awg_ctx& c) {
+  PhaseTimer t(c, "second_coarse_W");
+  c.nminus = 0;
+  for (int q = 0; q < c.N; ++q) c.nminus += c.kstrict[q];
+  if (c.nminus == 0) return;
+  hipStream_t s = c.s;
+  std::vector<long> gcoff(c.N + 1, 0);
+  for (int q = 0; q < c.N; ++q) gcoff[q + 1] = gcoff[q] + c.kstrict[q];
+  DBuf<long> dgcoff;
+  dgcoff.upload(gcoff, s);
+  c.W.alloc((long)c.n * c.nminus);
+  const int b = std::min(c.nminus, 1024);
+  MultiWS w;
+  build_ws(c, w, b);
+  DBuf<double> X, Pm, Q, dots;
+  X.alloc((long)c.n * b);
+  Pm.alloc((long)c.n * b);
+  Q.alloc((long)c.n * b);
+  dots.alloc(2 * b);
+  DBuf<double> alpha_d;
+  alpha_d.alloc(b);
+  std::vector<double> bn(b), rz(b), alpha(b), beta(b);
+  std::vector<char> active(b);
+  int itmax = 0;
+  for (int c0 = 0; c0 < c.nminus; c0 += b) {
+    const int bc = std::min(b, c.nminus - c0);
+    w.R.zero(s);
+    hipLaunchKernelGGL(k_build_vg, dim3(64, c.N), dim3(256), 0, s, c.subptr.p, c.subidx.p, c.V.p, c.LV.d_eoff.p,
+                       dgcoff.p, c.N, w.R.p, (long)c.n, c0, b);
+    AWG_LAUNCH_CHECK();
+    X.zero(s);
+    l_coldot(c.n, b, w.R, c.n, w.R, c.n, dots, s);
+    auto h = dots.download(s, b);
+    for (int j = 0; j < b; ++j) {
+      bn[j] = std::sqrt(h[j]);
+      active[j] = (j < bc && bn[j] > 0.0) ? 1 : 0;
+    }
+    op_h2(c, w, false);
+    AWG_HIP(hipMemcpyAsync(Pm.p, w.Z.p, sizeof(double) * c.n * b, hipMemcpyDeviceToDevice, s));
+    l_coldot(c.n, b, w.R, c.n, w.Z, c.n, dots, s);
+    h = dots.download(s, b);
+    for (int j = 0; j < b; ++j) rz[j] = h[j];
+    int it = 0;
+    for (; it < c.opt.w_maxit; ++it) {
+      op_aplus(c, w, Pm, Q);
+      l_coldot(c.n, b, Pm, c.n, Q, c.n, dots, s);
+      h = dots.download(s, b);
+      for (int j = 0; j < b; ++j) {
+        if (active[j] && !(h[j] > 0.0)) throw Error(AWG_ERR_NOT_SPD, "PCG with A_+ met p^T A_+ p <= 0");
+        alpha[j] = active[j] ? rz[j] / h[j] : 0.0;
+      }
+      AWG_HIP(hipMemcpyAsync(alpha_d.p, alpha.data(), sizeof(double) * b, hipMemcpyHostToDevice, s));
+      l_colaxpby(c.n, b, Pm, c.n, alpha_d, X, c.n, nullptr, 1.0, 1.0, s);
+      l_colaxpby(c.n, b, Q, c.n, alpha_d, w.R, c.n, nullptr, -1.0, 1.0, s);
+      l_coldot(c.n, b, w.R, c.n, w.R, c.n, dots, s);
+      h = dots.download(s, b);
+      int nact = 0;
+      for (int j = 0; j < b; ++j) {
+        if (active[j] && std::sqrt(h[j]) <= c.opt.w_rtol * bn[j]) active[j] = 0;
+        nact += active[j];
+      }
+      if (nact == 0) { ++it; break; }
+      op_h2(c, w, false);
+      l_coldot(c.n, b, w.R, c.n, w.Z, c.n, dots, s);
+      h = dots.download(s, b);
+      for (int j = 0; j < b; ++j) {
+        beta[j] = active[j] ? h[j] / rz[j] : 0.0;
+        if (active[j]) rz[j] = h[j];
+      }
+      AWG_HIP(hipMemcpyAsync(alpha_d.p, beta.data(), sizeof(double) * b, hipMemcpyHostToDevice, s));
+      l_colaxpby(c.n, b, w.Z, c.n, nullptr, Pm, c.n, alpha_d, 1.0, 1.0, s);   // P = Z + beta P
+      sync(c);   // beta buffer reused next iteration
+    }
+    itmax = std::max(itmax, it);
+    for (int j = 0; j < bc; ++j)
+      if (active[j]) throw Error(AWG_ERR_NOT_SPD, "PCG with A_+ for W did not converge within w_maxit");
+    hipLaunchKernelGGL(k_copy_cols, dim3(1024), dim3(256), 0, s, X.p, (long)c.n, c.W.p + (long)c0 * c.n, (long)c.n,
+                       c.n, bc);
+    AWG_LAUNCH_CHECK();
+  }
+  c.w_iters = itmax;
+}
+
+// E_W = W^T A W and its inverse (Definition of H3,ad, Section 4.3)
+void phase_EW(awg_ctx& c) {
+  PhaseTimer t(c, "second_coarse_EW");
+  if (c.nminus == 0) return;
+  hipStream_t s = c.s;
+  DBuf<double> AW, EW;
+  AW.alloc((long)c.n * c.nminus);
+  EW.alloc((long)c.nminus * c.nminus);
+  for (int c0 = 0; c0 < c.nminus; c0 += 32768)
+    l_spmm(c.n, c.rowptr, c.col, c.val, c.W.p + (long)c0 * c.n, c.n, AW.p + (long)c0 * c.n, c.n,
+           std::min(32768, c.nminus - c0), 1.0, 0.0, s);
+  DBuf<GemmDesc> g;
+  g.upload({GemmDesc{c.W.p, AW.p, EW.p, c.nminus, c.nminus, c.n, c.n, c.n, c.nminus}}, s);
+  gemm_batched(g, 1, c.nminus, c.nminus, true, false, 1.0, 0.0, false, s);
+  spd_inverse(c, EW, c.nminus, c.EWinv, "second coarse matrix W^T A W");
+}
+
+void do_setup(awg_ctx& c, const int64_t* rowptr, const int32_t* col, const double* val, const int64_t* sub_ptr,
+              const int32_t* sub_idx) {
+  const double t0 = now_ms();
+  phase_maps(c, rowptr, col, val, sub_ptr, sub_idx);
+  phase_local(c);
+  phase_coarse0(c);
+  {
+    // the W solves and the main solves use H2 / H with the workspace below
+  }
+  phase_W(c);
+  phase_EW(c);
+  {
+    PhaseTimer t(c, "workspace");
+    build_ws(c, c.ws1, 1);
+    c.pcg_buf.alloc(3L * c.n);
+  }
+  sync(c);
+  c.tms["total"] = now_ms() - t0;
+}
+
+// host-side symmetric tridiagonal extremes (Lanczos estimate from the PCG
+// coefficients; diagnostics only)
+void lanczos_extremes(const std::vector<double>& al, const std::vector<double>& be, double& lmin, double& lmax) {
+  const int k = (int)al.size();
+  if (k == 0) { lmin = lmax = NAN; return; }
+  std::vector<double> d(k), e(k > 1 ? k - 1 : 1, 0.0);
+  for (int j = 0; j < k; ++j) {
+    d[j] = 1.0 / al[j] + (j > 0 ? be[j - 1] / al[j - 1] : 0.0);
+    if (j + 1 < k) e[j] = std::sqrt(std::max(0.0, be[j])) / al[j];
+  }
+  auto count = [&](double x) {
+    int cnum = 0;
+    double q = d[0] - x;
+    if (q == 0.0) q = -1e-300;
+    if (q < 0) ++cnum;
+    for (int i = 1; i < k; ++i) {
+      q = d[i] - x - e[i - 1] * e[i - 1] / q;
+      if (q == 0.0) q = -1e-300;
+      if (q < 0) ++cnum;
+    }
+    return cnum;
+  };
+  double gl = 1e300, gu = -1e300;
+  for (int i = 0; i < k; ++i) {
+    const double r = (i > 0 ? std::fabs(e[i - 1]) : 0.0) + (i + 1 < k ? std::fabs(e[i]) : 0.0);
+    gl = std::min(gl, d[i] - r);
+    gu = std::max(gu, d[i] + r);
+  }
+  auto bis = [&](int idx) {
+    double lo = gl, hi = gu;
+    for (int it = 0; it < 200; ++it) {
+      const double mid = 0.5 * (lo + hi);
+      if (count(mid) <= idx) lo = mid; else hi = mid;
+    }
+    return 0.5 * (lo + hi);
+  };
+  lmin = bis(0);
+  lmax = bis(k - 1);
+}
+
+int do_pcg(awg_ctx& c, const double* b, double* x, double tol, int maxit, awg_pcg_info* info) {
+  hipStream_t s = c.s;
+  MultiWS& w = c.ws1;
+  const bool f32 = c.opt.local_prec == AWG_LOCAL_F32;
+  const int n = c.n;
+  double* xx = c.pcg_buf.p;
+  double* p = xx + n;
+  double* q = p + n;
+  c.scal.alloc(16 + 2 * (size_t)std::max(maxit, 1) + 2);
+  c.scal.zero(s);
+  double* sc = c.scal.p;
+  AWG_HIP(hipMemcpyAsync(w.R.p, b, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+  AWG_HIP(hipMemsetAsync(xx, 0, sizeof(double) * n, s));
+  l_coldot(n, 1, w.R, n, w.R, n, sc + 6, s);
+  double h6;
+  AWG_HIP(hipMemcpyAsync(&h6, sc + 6, sizeof(double), hipMemcpyDeviceToHost, s));
+  sync(c);
+  const double bn = std::sqrt(h6);
+  awg_pcg_info inf{};
+  int status = AWG_OK;
+  int it = 0;
+  if (bn == 0.0) {
+    inf.converged = 1;
+  } else {
+    op_h(c, w, f32);
+    AWG_HIP(hipMemcpyAsync(p, w.Z.p, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    l_coldot(n, 1, w.R, n, w.Z, n, sc + 0, s);
+    const unsigned g = cdiv(n, 256);
+    double hs[6];
+    for (;;) {
+      l_spmm(n, c.rowptr, c.col, c.val, p, n, q, n, 1, 1.0, 0.0, s);
+      l_coldot(n, 1, p, n, q, n, sc + 1, s);
+      hipLaunchKernelGGL(k_pcg_scalars, dim3(1), dim3(64), 0, s, sc, it, 0);
+      hipLaunchKernelGGL(k_pcg_update_xr, dim3(g), dim3(256), 0, s, n, xx, w.R.p, p, q, sc);
+      l_coldot(n, 1, w.R, n, w.R, n, sc + 5, s);
+      AWG_HIP(hipMemcpyAsync(hs, sc, sizeof(double) * 6, hipMemcpyDeviceToHost, s));
+      sync(c);
+      ++it;
+      if (!(hs[1] > 0.0)) {
+        status = AWG_ERR_NOT_SPD;
+        c.err = "PCG breakdown: p^T A p <= 0 (A or H not spd)";
+        break;
+      }
+      inf.rel_res = std::sqrt(hs[5]) / bn;
+      if (inf.rel_res <= tol) { inf.converged = 1; break; }
+      if (it >= maxit) break;
+      op_h(c, w, f32);
+      l_coldot(n, 1, w.R, n, w.Z, n, sc + 3, s);
+      hipLaunchKernelGGL(k_pcg_scalars, dim3(1), dim3(64), 0, s, sc, it - 1, 1);
+      hipLaunchKernelGGL(k_pcg_update_p, dim3(g), dim3(256), 0, s, n, p, w.Z.p, sc);
+    }
+  }
+  inf.iters = it;
+  if (status == AWG_OK) {
+    AWG_HIP(hipMemcpyAsync(x, xx, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    // true residual
+    l_spmm(n, c.rowptr, c.col, c.val, xx, n, q, n, 1, -1.0, 0.0, s);
+    l_colaxpby(n, 1, b, n, nullptr, q, n, nullptr, 1.0, 1.0, s);
+    l_coldot(n, 1, q, n, q, n, sc + 7, s);
+    std::vector<double> hist(16 + 2 * (size_t)std::max(maxit, 1));
+    AWG_HIP(hipMemcpyAsync(hist.data(), sc, sizeof(double) * hist.size(), hipMemcpyDeviceToHost, s));
+    sync(c);
+    inf.rel_res_true = bn > 0 ? std::sqrt(hist[7]) / bn : 0.0;
+    std::vector<double> al, be;
+    for (int j = 0; j < it; ++j) al.push_back(hist[16 + 2 * j]);
+    for (int j = 0; j + 1 < it; ++j) be.push_back(hist[17 + 2 * j]);
+    lanczos_extremes(al, be, inf.lmin_est, inf.lmax_est);
+    if (!inf.converged) status = AWG_NOT_CONVERGED;
+  }
+  if (info) *info = inf;
+  return status;
+}
+
+std::string stats_json(const awg_ctx& c) {
+  std::ostringstream o;
+  o.precision(17);
+  auto arr = [&](const char* k, const std::vector<int>& v) {
+    o << "\"" << k << "\":[";
+    for (size_t i = 0; i < v.size(); ++i) o << (i ? "," : "") << v[i];
+    o << "]";
+  };
+  o << "{\"n\":" << c.n << ",\"nnz\":" << c.nnz << ",\"N\":" << c.N << ",\"sum_ns\":" << c.sumns
+    << ",\"n_minus\":" << c.nminus << ",\"n0\":" << c.n0 << ",\"w_iters\":" << c.w_iters
+    << ",\"local_prec\":" << c.opt.local_prec << ",\"tau\":" << c.opt.tau << ",";
+  arr("k_s", c.ks);
+  o << ",";
+  arr("kstrict_s", c.kstrict);
+  o << ",";
+  arr("m_s", c.ms);
+  o << ",\"eig_resid_max\":[";
+  for (size_t i = 0; i < c.eig_resid_max.size(); ++i) o << (i ? "," : "") << c.eig_resid_max[i];
+  o << "],\"ms\":{";
+  bool first = true;
+  for (auto& kv : c.tms) {
+    o << (first ? "" : ",") << "\"" << kv.first << "\":" << kv.second;
+    first = false;
+  }
+  o << "}}";
+  return o.str();
+}
+
+int fail(awg_ctx* c, const Error& e) {
+  if (c) c->err = e.what();
+  return e.code;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+void awg_default_options(awg_options* opt) {
+  if (!opt) return;
+  opt->tau = 0.1;
+  opt->zero_tol = 1e-12;
+  opt->w_rtol = 1e-12;
+  opt->w_maxit = 500;
+  opt->local_prec = AWG_LOCAL_F64;
+  opt->stream = nullptr;
+}
+
+int awg_setup(awg_ctx** out, int64_t n, int64_t nnz, const int64_t* rowptr, const int32_t* col, const double* val,
+              int32_t nsub, const int64_t* sub_ptr, const int32_t* sub_idx, const awg_options* opt) {
+  if (!out) {
+    g_setup_error = "awg_setup: out is NULL";
+    return AWG_ERR_ARG;
+  }
+  *out = nullptr;
+  awg_options o;
+  awg_default_options(&o);
+  if (opt) o = *opt;
+  if (n <= 0 || n >= (1L << 31) || nnz <= 0 || nnz >= (1L << 31) || nsub <= 0 || !rowptr || !col || !val ||
+      !sub_ptr || !sub_idx) {
+    g_setup_error = "awg_setup: invalid sizes or NULL pointer";
+    return AWG_ERR_ARG;
+  }
+  if (!(o.tau > 0.0 && o.tau < 1.0)) {
+    g_setup_error = "awg_setup: tau must lie in (0, 1)";
+    return AWG_ERR_ARG;
+  }
+  if (!(o.zero_tol >= 0.0) || !(o.w_rtol > 0.0) || o.w_maxit <= 0 ||
+      (o.local_prec != AWG_LOCAL_F64 && o.local_prec != AWG_LOCAL_F32)) {
+    g_setup_error = "awg_setup: invalid option value";
+    return AWG_ERR_ARG;
+  }
+  awg_ctx* c = new (std::nothrow) awg_ctx();
+  if (!c) {
+    g_setup_error = "awg_setup: host allocation failed";
+    return AWG_ERR_OOM;
+  }
+  c->opt = o;
+  c->s = (hipStream_t)o.stream;
+  c->n = (int)n;
+  c->nnz = (int)nnz;
+  c->N = nsub;
+  try {
+    do_setup(*c, rowptr, col, val, sub_ptr, sub_idx);
+  } catch (const Error& e) {
+    g_setup_error = e.what();
+    (void)hipStreamSynchronize(c->s);
+    delete c;
+    return e.code;
+  } catch (const std::exception& e) {
+    g_setup_error = e.what();
+    (void)hipStreamSynchronize(c->s);
+    delete c;
+    return AWG_ERR_HIP;
+  }
+  *out = c;
+  return AWG_OK;
+}
+
+int awg_apply(awg_ctx* c, const double* r, double* z) {
+  if (!c || !r || !z) return AWG_ERR_ARG;
+  try {
+    AWG_HIP(hipMemcpyAsync(c->ws1.R.p, r, sizeof(double) * c->n, hipMemcpyDeviceToDevice, c->s));
+    op_h(*c, c->ws1, c->opt.local_prec == AWG_LOCAL_F32);
+    AWG_HIP(hipMemcpyAsync(z, c->ws1.Z.p, sizeof(double) * c->n, hipMemcpyDeviceToDevice, c->s));
+  } catch (const Error& e) {
+    return fail(c, e);
+  }
+  return AWG_OK;
+}
+
+int awg_pcg(awg_ctx* c, const double* b, double* x, double tol, int32_t maxit, awg_pcg_info* info) {
+  if (!c || !b || !x || !(tol > 0.0) || maxit <= 0) {
+    if (c) c->err = "awg_pcg: invalid argument";
+    return AWG_ERR_ARG;
+  }
+  try {
+    return do_pcg(*c, b, x, tol, maxit, info);
+  } catch (const Error& e) {
+    return fail(c, e);
+  }
+}
+
+int64_t awg_stats(const awg_ctx* c, char* buf, size_t cap) {
+  if (!c) return AWG_ERR_ARG;
+  const std::string js = stats_json(*c);
+  if (buf && cap) {
+    const size_t k = std::min(cap - 1, js.size());
+    std::memcpy(buf, js.data(), k);
+    buf[k] = '\0';
+  }
+  return (int64_t)js.size();
+}
+
+int64_t awg_export(const awg_ctx* c, const char* name, void* buf, size_t cap) {
+  if (!c || !name) return AWG_ERR_ARG;
+  const void* src = nullptr;
+  size_t bytes = 0;
+  const std::string nm(name);
+  if (nm == "neg_eigs") { src = c->lamV.p; bytes = sizeof(double) * c->LV.cols; }
+  else if (nm == "geneo_eigs") { src = c->lamY.p; bytes = sizeof(double) * c->LY.cols; }
+  else if (nm == "mult") { src = c->mult.p; bytes = sizeof(int) * c->n; }
+  else if (nm == "pair_count") { src = c->cnt.p; bytes = sizeof(int) * c->nnz; }
+  else if (nm == "V_minus") { src = c->V.p; bytes = sizeof(double) * c->LV.elems; }
+  else if (nm == "Y") { src = c->Y.p; bytes = sizeof(double) * c->LY.elems; }
+  else if (nm == "P_local") { src = c->P.p; bytes = sizeof(double) * c->sqtot; }
+  else return AWG_ERR_ARG;
+  if (buf && cap && bytes) {
+    if (hipMemcpyAsync(buf, src, std::min(cap, bytes), hipMemcpyDeviceToHost, c->s) != hipSuccess ||
+        hipStreamSynchronize(c->s) != hipSuccess)
+      return AWG_ERR_HIP;
+  }
+  return (int64_t)bytes;
+}
+
+const char* awg_last_error(const awg_ctx* c) { return c ? c->err.c_str() : g_setup_error.c_str(); }
+
+void awg_destroy(awg_ctx* c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->s);
+  delete c;
+}
+
+}  // extern "C"

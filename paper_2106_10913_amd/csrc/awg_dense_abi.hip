@@ -1,0 +1,140 @@
+// C ABI of the batched dense building blocks (include/awg_dense.h).
+#include <algorithm>
+
+#include "awg.h"
+#include "awg_common.h"
+#include "awg_dense.h"
+
+using namespace awg;
+
+namespace {
+
+std::vector<MatDesc> uniform(double* A, int batch, int m, int n, int ld, long stride) {
+  std::vector<MatDesc> v(batch);
+  for (int b = 0; b < batch; ++b) v[b] = MatDesc{A + b * stride, m, n, ld, 0};
+  return v;
+}
+
+template <class F>
+int guarded(hipStream_t s, F&& f) {
+  try {
+    f();
+    AWG_HIP(hipStreamSynchronize(s));
+  } catch (const Error& e) {
+    (void)hipStreamSynchronize(s);
+    return e.code;
+  }
+  return AWG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int awg_dense_gemm(int32_t batch, int32_t m, int32_t n, int32_t k, int32_t transA, int32_t transB, double alpha,
+                   const double* A, int32_t lda, int64_t strideA, const double* B, int32_t ldb, int64_t strideB,
+                   double beta, double* C, int32_t ldc, int64_t strideC, void* stream) {
+  if (batch <= 0 || m < 0 || n < 0 || k < 0 || !A || !B || !C) return AWG_ERR_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  return guarded(s, [&] {
+    std::vector<GemmDesc> h(batch);
+    for (int b = 0; b < batch; ++b)
+      h[b] = GemmDesc{A + b * strideA, B + b * strideB, C + b * strideC, m, n, k, lda, ldb, ldc};
+    DBuf<GemmDesc> d;
+    d.upload(h, s);
+    gemm_batched(d, batch, m, n, transA != 0, transB != 0, alpha, beta, false, s);
+    AWG_HIP(hipStreamSynchronize(s));
+  });
+}
+
+int awg_dense_potrf(int32_t batch, int32_t n, double* A, int32_t lda, int64_t strideA, int32_t* info_host,
+                    void* stream) {
+  if (batch <= 0 || n <= 0 || lda < n || !A) return AWG_ERR_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  bool bad = false;
+  int rc = guarded(s, [&] {
+    DBuf<MatDesc> d;
+    d.upload(uniform(A, batch, n, n, lda, strideA), s);
+    DBuf<int> info;
+    info.alloc(batch);
+    info.zero(s);
+    potrf_batched(d, std::vector<int>(batch, n), info, s, nullptr);
+    auto h = info.download(s);
+    for (int b = 0; b < batch; ++b) {
+      if (info_host) info_host[b] = h[b];
+      bad |= h[b] != 0;
+    }
+  });
+  return rc ? rc : (bad ? AWG_ERR_NOT_SPD : AWG_OK);
+}
+
+int awg_dense_trsm(int32_t batch, int32_t n, int32_t nrhs, int32_t trans, const double* L, int32_t ldl,
+                   int64_t strideL, double* B, int32_t ldb, int64_t strideB, void* stream) {
+  if (batch <= 0 || n <= 0 || nrhs < 0 || ldl < n || ldb < n || !L || !B) return AWG_ERR_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  return guarded(s, [&] {
+    DBuf<MatDesc> dl, db;
+    dl.upload(uniform(const_cast<double*>(L), batch, n, n, ldl, strideL), s);
+    db.upload(uniform(B, batch, n, nrhs, ldb, strideB), s);
+    trsm_batched(dl, db, std::vector<int>(batch, n), std::vector<int>(batch, nrhs), trans != 0, s, nullptr);
+  });
+}
+
+int awg_dense_low_eigs(int32_t batch, int32_t n, double* A, int32_t lda, int64_t strideA, double thr,
+                       int32_t max_k, int32_t* count_host, double* lam, double* Z, int64_t strideZ, void* stream) {
+  if (batch <= 0 || n <= 0 || lda < n || max_k < 0 || !A || !count_host) return AWG_ERR_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  bool over = false;
+  int rc = guarded(s, [&] {
+    DBuf<MatDesc> dA;
+    dA.upload(uniform(A, batch, n, n, lda, strideA), s);
+    std::vector<int> hn(batch, n);
+    std::vector<long> off(batch + 1);
+    for (int b = 0; b <= batch; ++b) off[b] = (long)b * n;
+    DBuf<long> doff, w6;
+    doff.upload(off, s);
+    std::vector<long> o6(batch);
+    for (int b = 0; b < batch; ++b) o6[b] = 6L * b * n;
+    w6.upload(o6, s);
+    DBuf<double> d, e, tau, work, thrv, mm;
+    d.alloc((long)batch * n);
+    e.alloc((long)batch * n);
+    tau.alloc((long)batch * n);
+    work.alloc(6L * batch * n);
+    thrv.alloc(batch);
+    mm.alloc(2 * batch);
+    std::vector<double> ht(batch, thr);
+    thrv.upload(ht, s);
+    sytrd_batched(dA, hn, d, e, tau, doff, work, s);
+    DBuf<int> nd, cnt;
+    nd.upload(hn, s);
+    cnt.alloc(batch);
+    TriEigArgs a{d, e, doff, nd, batch};
+    tri_count(a, thrv, 0, 0.0, thrv, cnt, mm, s);
+    auto hc = cnt.download(s);
+    std::vector<int> kk(batch);
+    for (int b = 0; b < batch; ++b) {
+      count_host[b] = hc[b];
+      kk[b] = std::min(hc[b], max_k);
+      over |= hc[b] > max_k;
+    }
+    cnt.upload(kk, s);
+    std::vector<long> loff(batch + 1);
+    for (int b = 0; b <= batch; ++b) loff[b] = (long)b * max_k;
+    DBuf<long> dlo;
+    dlo.upload(loff, s);
+    DBuf<MatDesc> dZ;
+    std::vector<MatDesc> zd(batch);
+    for (int b = 0; b < batch; ++b) zd[b] = MatDesc{Z + b * strideZ, n, kk[b], n, 0};
+    dZ.upload(zd, s);
+    DBuf<double> resid;
+    resid.alloc(std::max(1L, (long)batch * max_k));
+    if (max_k > 0 && lam && Z) {
+      tri_eigvecs(a, cnt, dlo, lam, dZ, work, w6, resid, nullptr, thrv, s);
+      ormtr_batched(dA, dZ, tau, doff, hn, kk, s);
+    }
+  });
+  return rc ? rc : (over ? AWG_ERR_ARG : AWG_OK);
+}
+
+}  // extern "C"

@@ -1,0 +1,40 @@
+// Launchers of the sparse / vector / set-up kernels (k_sparse.hip).
+#pragma once
+#include "awg_common.h"
+
+namespace awg {
+void l_validate_subs(int N, const long* sub_ptr, const int* sub_idx, int n, int* err, hipStream_t s);
+void l_entry_owner(int N, const long* sub_ptr, int* ent_sub, hipStream_t s);
+void l_mult(long tot, const int* sub_idx, int* mult, hipStream_t s);
+void l_check_cover(int n, const int* mult, int* err, hipStream_t s);
+void l_scan(int n, const int* in, int* out, hipStream_t s);
+void l_fill_inv(int N, const long* sub_ptr, const int* sub_idx, const int* inv_ptr, int* fill, int* inv_sub,
+                int* inv_loc, hipStream_t s);
+void l_sort_inv(int n, const int* inv_ptr, int* inv_sub, int* inv_loc, hipStream_t s);
+void l_pairs(int n, const int* rowptr, const int* col, const double* val, const int* inv_ptr, const int* inv_sub,
+             int* cnt, double* bval, int* err, hipStream_t s);
+void l_pou(long tot, const int* sub_idx, const int* mult, double* dw, hipStream_t s);
+void l_extract(int N, const long* sub_ptr, const int* sub_idx, const int* rowptr, const int* col,
+               const double* vals, const MatDesc* mats, hipStream_t s);
+void l_spmm(int n, const int* rowptr, const int* col, const double* val, const double* X, long ldx, double* Y,
+            long ldy, int b, double alpha, double beta, hipStream_t s);
+void l_gather(long tot, const int* sub_idx, const int* ent_sub, const long* sub_ptr, const double* X, long ldx,
+              int b, const double* scale, double* Xs, hipStream_t s);
+void l_scatter(int n, const int* inv_ptr, const int* inv_sub, const int* inv_loc, const long* sub_ptr,
+               const double* Zs, int b, const double* scale, double* Y, long ldy, double alpha, double beta,
+               hipStream_t s);
+void l_coldot(int n, int b, const double* X, long ldx, const double* Y, long ldy, double* out, hipStream_t s);
+void l_colaxpby(int n, int b, const double* X, long ldx, const double* a, double* Y, long ldy, const double* bb,
+                double sa, double sb, hipStream_t s);
+void l_set_identity(const MatDesc* mats, int batch, hipStream_t s);
+void l_copy_mat(const MatDesc* src, const MatDesc* dst, int batch, hipStream_t s);
+void l_scale_sym(const MatDesc* mats, int batch, const long* voff, const double* d, bool inv, bool symmetrize,
+                 hipStream_t s);
+void l_transpose_inplace(const MatDesc* mats, int batch, hipStream_t s);
+void l_scale_cols(const MatDesc* mats, int batch, const long* coff, const double* f, double alpha,
+                  const double* shift, int mode, hipStream_t s);
+void l_diag_mean(const MatDesc* mats, int batch, double* out, hipStream_t s);
+void l_mb_neighbours(int N, const long* sub_ptr, const int* sub_idx, const int* mult, const int* inv_ptr,
+                     const int* inv_sub, const int* inv_loc, const MatDesc* mats, const double* V, const long* voff,
+                     const double* lam, const long* loff, hipStream_t s);
+}  // namespace awg

@@ -1,0 +1,386 @@
+// Batched dense kernels for variable-size column-major blocks (gfx950).
+//
+//  * k_gemm     : C = alpha op(A) op(B) + beta C, FP64 MFMA (v_mfma_f64_16x16x4),
+//                 64x64 output tile per 256-thread workgroup, K staged in LDS.
+//  * k_gemv     : memory-bound y = alpha op(A) x + beta y.
+//  * potrf      : right-looking blocked Cholesky (32-wide panels): LDS panel
+//                 factorisation, row-parallel panel solve, MFMA trailing update.
+//  * trsm       : blocked forward / backward substitution with many right-hand
+//                 sides: 64x64 diagonal solve in LDS + MFMA update of the rest.
+#include "awg_common.h"
+
+namespace awg {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------------------
+// descriptor providers
+// ---------------------------------------------------------------------------
+struct DescArray {
+  const GemmDesc* d;
+  __device__ GemmDesc operator()(int b) const { return d[b]; }
+};
+
+// trailing update of the Cholesky panel step at column j (panel width nb):
+// A[j+nb:, j+nb:] -= A[j+nb:, j:j+nb] * A[j+nb:, j:j+nb]^T
+struct CholUpdate {
+  const MatDesc* m;
+  int j, nb;
+  __device__ GemmDesc operator()(int b) const {
+    MatDesc M = m[b];
+    GemmDesc g;
+    int r0 = j + nb;
+    int rem = M.n - r0;
+    if (rem < 0) rem = 0;
+    g.A = M.A + r0 + (long)j * M.ld;
+    g.B = g.A;
+    g.C = M.A + r0 + (long)r0 * M.ld;
+    g.m = rem;
+    g.n = rem;
+    g.k = nb;
+    g.lda = g.ldb = g.ldc = M.ld;
+    return g;
+  }
+};
+
+// trsm update at block row j (block height nb):
+//  forward : B[j+nb:, :] -= L[j+nb:, j:j+nb] * B[j:j+nb, :]
+//  backward: B[0:j, :]   -= L[j:j+nb, 0:j]^T * B[j:j+nb, :]
+struct TrsmUpdate {
+  const MatDesc* L;
+  const MatDesc* B;
+  int j, nb;
+  bool backward;
+  __device__ GemmDesc operator()(int b) const {
+    MatDesc l = L[b], x = B[b];
+    GemmDesc g;
+    int n = l.n;
+    int jb = n - j < nb ? n - j : nb;
+    g.n = x.n;
+    g.ldb = x.ld;
+    g.ldc = x.ld;
+    g.lda = l.ld;
+    if (jb <= 0) {
+      g.m = 0; g.k = 0; g.A = l.A; g.B = x.A; g.C = x.A;
+      return g;
+    }
+    if (!backward) {
+      g.A = l.A + (j + jb) + (long)j * l.ld;
+      g.B = x.A + j;
+      g.C = x.A + (j + jb);
+      g.m = n - j - jb;
+      g.k = jb;
+    } else {
+      g.A = l.A + j;                // rows j..j+jb of L, columns 0..j; used transposed
+      g.B = x.A + j;
+      g.C = x.A;
+      g.m = j;
+      g.k = jb;
+    }
+    return g;
+  }
+};
+
+// ---------------------------------------------------------------------------
+// GEMM, FP64 MFMA
+// ---------------------------------------------------------------------------
+// MFMA f64 16x16x4 operand layout (one wavefront of 64 lanes):
+//   A (16x4): lane l holds A[l % 16][l / 16]
+//   B (4x16): lane l holds B[l / 16][l % 16]
+//   D (16x16): lane l holds D[l/16 + 4*r][l % 16], r = 0..3 (checked on gfx950)
+template <class DF, bool TA, bool TB>
+__global__ __launch_bounds__(256) void k_gemm(DF df, double alpha, double beta, int lower) {
+  const GemmDesc d = df(blockIdx.z);
+  const int m0 = blockIdx.x * 64, n0 = blockIdx.y * 64;
+  if (m0 >= d.m || n0 >= d.n) return;
+  if (lower && m0 + 64 <= n0) return;
+  __shared__ double As[16][66];
+  __shared__ double Bs[16][66];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
+  v4d acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = (v4d){0.0, 0.0, 0.0, 0.0};
+
+  for (int k0 = 0; k0 < d.k; k0 += 16) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int e = tid + r * 256;
+      int i, kk;
+      if (!TA) { i = e & 63; kk = e >> 6; } else { kk = e & 15; i = e >> 4; }
+      const int gi = m0 + i, gk = k0 + kk;
+      double v = 0.0;
+      if (gi < d.m && gk < d.k) v = TA ? d.A[gk + (long)gi * d.lda] : d.A[gi + (long)gk * d.lda];
+      As[kk][i] = v;
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int e = tid + r * 256;
+      int j, kk;
+      if (!TB) { kk = e & 15; j = e >> 4; } else { j = e & 63; kk = e >> 6; }
+      const int gj = n0 + j, gk = k0 + kk;
+      double v = 0.0;
+      if (gj < d.n && gk < d.k) v = TB ? d.B[gj + (long)gk * d.ldb] : d.B[gk + (long)gj * d.ldb];
+      Bs[kk][j] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 16; kk += 4) {
+      const int kr = kk + (lane >> 4), c = lane & 15;
+      const double a0 = As[kr][wm + c], a1 = As[kr][wm + 16 + c];
+      const double b0 = Bs[kr][wn + c], b1 = Bs[kr][wn + 16 + c];
+      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = m0 + wm + a * 16 + (lane >> 4) + 4 * r;
+        const int j = n0 + wn + b * 16 + (lane & 15);
+        if (i < d.m && j < d.n) {
+          double* c = d.C + i + (long)j * d.ldc;
+          const double v = alpha * acc[a][b][r];
+          *c = (beta == 0.0) ? v : v + beta * *c;
+        }
+      }
+}
+
+template <class DF>
+static void launch_gemm(DF df, int batch, int max_m, int max_n, bool tA, bool tB, double alpha, double beta,
+                        bool lower, hipStream_t s) {
+  if (batch <= 0 || max_m <= 0 || max_n <= 0) return;
+  dim3 grid(cdiv(max_m, 64), cdiv(max_n, 64), batch);
+  if (!tA && !tB) hipLaunchKernelGGL((k_gemm<DF, false, false>), grid, dim3(256), 0, s, df, alpha, beta, (int)lower);
+  else if (tA && !tB) hipLaunchKernelGGL((k_gemm<DF, true, false>), grid, dim3(256), 0, s, df, alpha, beta, (int)lower);
+  else if (!tA && tB) hipLaunchKernelGGL((k_gemm<DF, false, true>), grid, dim3(256), 0, s, df, alpha, beta, (int)lower);
+  else hipLaunchKernelGGL((k_gemm<DF, true, true>), grid, dim3(256), 0, s, df, alpha, beta, (int)lower);
+  AWG_LAUNCH_CHECK();
+}
+
+void gemm_batched(const GemmDesc* d_desc, int batch, int max_m, int max_n, bool transA, bool transB,
+                  double alpha, double beta, bool lower, hipStream_t s) {
+  launch_gemm(DescArray{d_desc}, batch, max_m, max_n, transA, transB, alpha, beta, lower, s);
+}
+
+// ---------------------------------------------------------------------------
+// GEMV (memory bound)
+// ---------------------------------------------------------------------------
+// notrans: y[i] = alpha sum_j A[i,j] x[j] + beta y[i]; 64 rows x 4 column
+// groups per workgroup, partial sums combined in LDS (deterministic).
+__global__ __launch_bounds__(256) void k_gemv_n(const GemmDesc* descs, double alpha, double beta) {
+  const GemmDesc d = descs[blockIdx.y];
+  const int r = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int i = blockIdx.x * 64 + r;
+  __shared__ double part[4][64];
+  double acc = 0.0;
+  if (i < d.m) {
+    const double* a = d.A + i;
+    double a0 = 0.0, a1 = 0.0;
+    int j = g;
+    for (; j + 4 < d.k; j += 8) {
+      a0 += a[(long)j * d.lda] * d.B[j];
+      a1 += a[(long)(j + 4) * d.lda] * d.B[j + 4];
+    }
+    for (; j < d.k; j += 4) a0 += a[(long)j * d.lda] * d.B[j];
+    acc = a0 + a1;
+  }
+  part[g][r] = acc;
+  __syncthreads();
+  if (g == 0 && i < d.m) {
+    const double v = alpha * ((part[0][r] + part[1][r]) + (part[2][r] + part[3][r]));
+    d.C[i] = (beta == 0.0) ? v : v + beta * d.C[i];
+  }
+}
+
+// trans: y[j] = alpha sum_i A[i,j] x[i] + beta y[j] with A stored k x m
+// (op(A) = A^T is m x k, as for the GEMM); one wavefront per output.
+__global__ __launch_bounds__(256) void k_gemv_t(const GemmDesc* descs, double alpha, double beta) {
+  const GemmDesc d = descs[blockIdx.y];
+  const int lane = threadIdx.x & 63;
+  const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (j >= d.m) return;
+  const double* a = d.A + (long)j * d.lda;
+  double acc = 0.0;
+  for (int i = lane; i < d.k; i += 64) acc += a[i] * d.B[i];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  if (lane == 0) {
+    const double v = alpha * acc;
+    d.C[j] = (beta == 0.0) ? v : v + beta * d.C[j];
+  }
+}
+
+void gemv_batched(const GemmDesc* d_desc, int batch, int max_m, int max_k, bool transA, double alpha,
+                  double beta, hipStream_t s) {
+  if (batch <= 0) return;
+  if (!transA) {
+    if (max_m <= 0) return;
+    hipLaunchKernelGGL(k_gemv_n, dim3(cdiv(max_m, 64), batch), dim3(256), 0, s, d_desc, alpha, beta);
+  } else {
+    if (max_m <= 0 || max_k <= 0) return;
+    hipLaunchKernelGGL(k_gemv_t, dim3(cdiv(max_m, 4), batch), dim3(256), 0, s, d_desc, alpha, beta);
+  }
+  AWG_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------------------
+// Cholesky
+// ---------------------------------------------------------------------------
+constexpr int CHOL_NB = 32;
+
+// factor the diagonal block A[j:j+jb, j:j+jb] in LDS
+__global__ __launch_bounds__(256) void k_potf2(const MatDesc* mats, int j, int* info) {
+  const MatDesc M = mats[blockIdx.x];
+  const int jb = min(CHOL_NB, M.n - j);
+  if (jb <= 0) return;
+  __shared__ double L[CHOL_NB][CHOL_NB + 1];
+  const int tid = threadIdx.x;
+  for (int e = tid; e < jb * jb; e += 256) {
+    const int r = e % jb, c = e / jb;
+    L[r][c] = M.A[(j + r) + (long)(j + c) * M.ld];
+  }
+  __syncthreads();
+  for (int c = 0; c < jb; ++c) {
+    if (tid == 0) {
+      const double piv = L[c][c];
+      if (!(piv > 0.0)) {
+        if (info[blockIdx.x] == 0) info[blockIdx.x] = j + c + 1;
+        L[c][c] = __builtin_nan("");
+      } else {
+        L[c][c] = sqrt(piv);
+      }
+    }
+    __syncthreads();
+    const double dc = L[c][c];
+    for (int r = c + 1 + tid; r < jb; r += 256) L[r][c] /= dc;
+    __syncthreads();
+    const int rem = jb - c - 1;
+    for (int e = tid; e < rem * rem; e += 256) {
+      const int r = c + 1 + e % rem, q = c + 1 + e / rem;
+      if (q <= r) L[r][q] -= L[r][c] * L[q][c];
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < jb * jb; e += 256) {
+    const int r = e % jb, c = e / jb;
+    if (r >= c) M.A[(j + r) + (long)(j + c) * M.ld] = L[r][c];
+  }
+}
+
+// rows below the diagonal block: X L_jj^T = A[j+jb:, j:j+jb]
+__global__ __launch_bounds__(256) void k_chol_panel(const MatDesc* mats, int j) {
+  const MatDesc M = mats[blockIdx.y];
+  const int jb = min(CHOL_NB, M.n - j);
+  if (jb <= 0) return;
+  __shared__ double L[CHOL_NB][CHOL_NB + 1];
+  for (int e = threadIdx.x; e < jb * jb; e += 256) {
+    const int r = e % jb, c = e / jb;
+    L[r][c] = (r >= c) ? M.A[(j + r) + (long)(j + c) * M.ld] : 0.0;
+  }
+  __syncthreads();
+  const int i = j + jb + blockIdx.x * 256 + threadIdx.x;
+  if (i >= M.n) return;
+  double x[CHOL_NB];
+#pragma unroll
+  for (int c = 0; c < CHOL_NB; ++c) {
+    if (c < jb) {
+      double v = M.A[i + (long)(j + c) * M.ld];
+      for (int t = 0; t < c; ++t) v -= x[t] * L[c][t];
+      x[c] = v / L[c][c];
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < CHOL_NB; ++c)
+    if (c < jb) M.A[i + (long)(j + c) * M.ld] = x[c];
+}
+
+void potrf_batched(const MatDesc* d_mats, const std::vector<int>& h_n, int* d_info, hipStream_t s,
+                   GemmDesc* /*unused*/) {
+  const int batch = (int)h_n.size();
+  if (batch == 0) return;
+  int maxn = 0;
+  for (int v : h_n) maxn = v > maxn ? v : maxn;
+  for (int j = 0; j < maxn; j += CHOL_NB) {
+    hipLaunchKernelGGL(k_potf2, dim3(batch), dim3(256), 0, s, d_mats, j, d_info);
+    AWG_LAUNCH_CHECK();
+    const int rem = maxn - j - CHOL_NB;
+    if (rem <= 0) break;
+    hipLaunchKernelGGL(k_chol_panel, dim3(cdiv(rem, 256), batch), dim3(256), 0, s, d_mats, j);
+    AWG_LAUNCH_CHECK();
+    launch_gemm(CholUpdate{d_mats, j, CHOL_NB}, batch, rem, rem, false, true, -1.0, 1.0, true, s);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// triangular solves with many right-hand sides
+// ---------------------------------------------------------------------------
+constexpr int TRSM_NB = 64;
+
+// Solve the diagonal block: forward  X_j = L_jj^{-1} B_j
+//                           backward X_j = L_jj^{-T} B_j
+// one wavefront per 64 right-hand sides; L_jj and the B tile live in LDS.
+__global__ __launch_bounds__(64) void k_trsm_diag(const MatDesc* Ls, const MatDesc* Bs, int j, int backward) {
+  const MatDesc l = Ls[blockIdx.y], b = Bs[blockIdx.y];
+  const int jb = min(TRSM_NB, l.n - j);
+  const int c0 = blockIdx.x * 64;
+  if (jb <= 0 || c0 >= b.n) return;
+  __shared__ double L[TRSM_NB][TRSM_NB + 1];
+  __shared__ double X[TRSM_NB][TRSM_NB + 1];   // X[row][col]
+  const int lane = threadIdx.x;
+  for (int c = 0; c < jb; ++c) L[lane][c] = (lane < jb && lane >= c) ? l.A[(j + lane) + (long)(j + c) * l.ld] : 0.0;
+  const int nc = min(64, b.n - c0);
+  for (int c = 0; c < nc; ++c) X[lane][c] = (lane < jb) ? b.A[(j + lane) + (long)(c0 + c) * b.ld] : 0.0;
+  __syncthreads();
+  if (lane < nc) {
+    const int c = lane;
+    if (!backward) {
+      for (int r = 0; r < jb; ++r) {
+        double v = X[r][c];
+        for (int t = 0; t < r; ++t) v -= L[r][t] * X[t][c];
+        X[r][c] = v / L[r][r];
+      }
+    } else {
+      for (int r = jb - 1; r >= 0; --r) {
+        double v = X[r][c];
+        for (int t = r + 1; t < jb; ++t) v -= L[t][r] * X[t][c];
+        X[r][c] = v / L[r][r];
+      }
+    }
+  }
+  __syncthreads();
+  if (lane < jb)
+    for (int c = 0; c < nc; ++c) b.A[(j + lane) + (long)(c0 + c) * b.ld] = X[lane][c];
+}
+
+void trsm_batched(const MatDesc* d_L, const MatDesc* d_B, const std::vector<int>& h_n,
+                  const std::vector<int>& h_ncols, bool trans, hipStream_t s, GemmDesc* /*unused*/) {
+  const int batch = (int)h_n.size();
+  if (batch == 0) return;
+  int maxn = 0, maxc = 0;
+  for (size_t b = 0; b < h_n.size(); ++b) {
+    maxn = h_n[b] > maxn ? h_n[b] : maxn;
+    maxc = h_ncols[b] > maxc ? h_ncols[b] : maxc;
+  }
+  if (maxn == 0 || maxc == 0) return;
+  const int nblk = cdiv(maxn, TRSM_NB);
+  for (int t = 0; t < nblk; ++t) {
+    const int blk = trans ? nblk - 1 - t : t;
+    const int j = blk * TRSM_NB;
+    hipLaunchKernelGGL(k_trsm_diag, dim3(cdiv(maxc, 64), batch), dim3(64), 0, s, d_L, d_B, j, (int)trans);
+    AWG_LAUNCH_CHECK();
+    const int mrows = trans ? j : maxn - j - TRSM_NB;
+    if (mrows > 0)
+      launch_gemm(TrsmUpdate{d_L, d_B, j, TRSM_NB, trans}, batch, mrows, maxc, trans, false, -1.0, 1.0, false, s);
+  }
+}
+
+}  // namespace awg

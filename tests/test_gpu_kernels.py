@@ -1,0 +1,115 @@
+"""Batched dense building blocks (include/awg_dense.h) against numpy FP64.
+
+Sizes are chosen to span several 64x64 tiles, 32-wide Cholesky panels and
+64-row triangular-solve blocks, with ragged tails.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+def to_dev(M):
+    """numpy (batch, rows, cols) -> torch (batch, cols, rows) = column-major blocks."""
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(M.transpose(0, 2, 1)), device="cuda")
+
+
+def from_dev(T):
+    return T.cpu().numpy().transpose(0, 2, 1)
+
+
+def spd(rng, batch, n, cond=1e3):
+    out = np.empty((batch, n, n))
+    for b in range(batch):
+        Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+        ev = np.logspace(0, np.log10(cond), n)
+        out[b] = (Q * ev) @ Q.T
+        out[b] = 0.5 * (out[b] + out[b].T)
+    return out
+
+
+@pytest.mark.parametrize("tA", [False, True])
+@pytest.mark.parametrize("tB", [False, True])
+@pytest.mark.parametrize("mnk", [(100, 70, 37), (64, 64, 16), (1, 130, 5), (131, 1, 200), (7, 9, 1)])
+def test_gemm(gpu_lib, tA, tB, mnk):
+    m, n, k = mnk
+    rng = np.random.default_rng(m * 7 + n * 3 + k)
+    batch = 3
+    A = rng.standard_normal((batch, k, m) if tA else (batch, m, k))
+    B = rng.standard_normal((batch, n, k) if tB else (batch, k, n))
+    C = rng.standard_normal((batch, m, n))
+    ref = np.stack([(-0.5) * ((A[b].T if tA else A[b]) @ (B[b].T if tB else B[b])) + 2.0 * C[b]
+                    for b in range(batch)])
+    Cd = to_dev(C)
+    gpu_lib.dense_gemm(to_dev(A), to_dev(B), Cd, alpha=-0.5, beta=2.0, transA=tA, transB=tB)
+    out = from_dev(Cd)
+    assert np.max(np.abs(out - ref)) <= 1e-13 * max(1.0, np.max(np.abs(ref))) * k
+
+
+@pytest.mark.parametrize("n", [1, 31, 33, 64, 100, 257])
+def test_potrf(gpu_lib, n):
+    rng = np.random.default_rng(n)
+    M = spd(rng, 2, n)
+    Ad = to_dev(M)
+    info = gpu_lib.dense_potrf(Ad)
+    assert np.all(info == 0)
+    L = np.tril(from_dev(Ad))
+    for b in range(2):
+        ref = np.linalg.cholesky(M[b])
+        assert np.max(np.abs(L[b] - ref)) <= 1e-12 * np.max(np.abs(ref)) * n
+
+
+def test_potrf_reports_breakdown(gpu_lib):
+    rng = np.random.default_rng(1)
+    M = spd(rng, 2, 80)
+    M[1, 50, 50] = -1e6                      # indefinite second block
+    info = gpu_lib.dense_potrf(to_dev(M))
+    assert info[0] == 0 and 1 <= info[1] <= 51
+
+
+@pytest.mark.parametrize("n,nrhs", [(100, 37), (64, 64), (130, 1), (65, 200)])
+@pytest.mark.parametrize("trans", [False, True])
+def test_trsm(gpu_lib, n, nrhs, trans):
+    rng = np.random.default_rng(n + nrhs)
+    L = np.tril(rng.standard_normal((2, n, n))) + 4.0 * np.eye(n)
+    B = rng.standard_normal((2, n, nrhs))
+    Bd = to_dev(B)
+    gpu_lib.dense_trsm(to_dev(L), Bd, trans=trans)
+    X = from_dev(Bd)
+    for b in range(2):
+        ref = np.linalg.solve(L[b].T if trans else L[b], B[b])
+        assert np.max(np.abs(X[b] - ref)) <= 1e-11 * max(1.0, np.max(np.abs(ref)))
+
+
+@pytest.mark.parametrize("n", [2, 3, 40, 97, 200])
+def test_low_eigs_against_eigh(gpu_lib, n):
+    rng = np.random.default_rng(n)
+    batch = 3
+    M = np.empty((batch, n, n))
+    for b in range(batch):
+        Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+        ev = rng.uniform(-1.0, 4.0, n)
+        if n >= 40:
+            ev[:6] = -0.5                     # a repeated negative eigenvalue
+            ev[6:9] = [1e-9, -1e-9, 0.0]      # a tight cluster at zero
+        M[b] = (Q * ev) @ Q.T
+        M[b] = 0.5 * (M[b] + M[b].T)
+    thr = 0.25
+    maxk = n
+    cnt, lam, Z = gpu_lib.dense_low_eigs(to_dev(M), thr, maxk)
+    lam = lam.cpu().numpy()
+    Z = Z.cpu().numpy()                       # (batch, k, n): row j = eigenvector j
+    for b in range(batch):
+        ev, V = np.linalg.eigh(M[b])
+        k = int(np.count_nonzero(ev < thr))
+        assert cnt[b] == k
+        assert np.max(np.abs(lam[b, :k] - ev[:k]), initial=0.0) <= 1e-12 * np.abs(ev).max() * n
+        Zb = Z[b, :k].T
+        assert np.max(np.abs(Zb.T @ Zb - np.eye(k)), initial=0.0) <= 1e-10
+        res = M[b] @ Zb - Zb * lam[b, :k]
+        assert np.max(np.abs(res), initial=0.0) <= 1e-10 * np.abs(ev).max()
+        # same invariant subspace as LAPACK
+        Pg = Zb @ Zb.T
+        Pr = V[:, :k] @ V[:, :k].T
+        assert np.max(np.abs(Pg - Pr), initial=0.0) <= 1e-8

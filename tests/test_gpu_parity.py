@@ -1,0 +1,138 @@
+"""GPU (HIP, gfx950) path against the FP64 oracle, through the C ABI.
+
+Ladder: integer maps (bit-exact) -> local eigenvalue counts and values ->
+coarse-space sizes -> H r -> PCG iterate and iteration count.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import awg_problems as P
+from awg_problems import partition as part
+from oracle import awg_oracle as O
+
+pytestmark = pytest.mark.gpu
+
+# The stated bar is 1e-10 relative on the PCG iterate x.  For H r itself the
+# bar is derived from the arithmetic: the local pseudo-inverse (A^s_+)^+ is
+# computed by two different backward-stable algorithms (eigendecomposition in
+# the oracle, Cholesky of K^s = A^s_+ + c V_- V_-^T on the GPU), whose
+# forward errors are O(eps * kappa(A^s_+)) with kappa taken on the range of
+# A^s_+; two FP64 formulas of the same operator already differ by that much.
+X_RTOL = 1e-10
+EPS = np.finfo(np.float64).eps
+
+
+def h_rtol(st):
+    kap = max(sp_.L_plus.max() / sp_.L_plus.min() for sp_ in st.split)
+    return max(1e-10, 10.0 * EPS * kap)
+
+
+def small_cases():
+    rng = np.random.default_rng(7)
+    kc = np.where(rng.random((17, 17)) < 0.3, 1e3, 1.0)
+    fd16 = P.fd5_diffusion(16, kc)
+    return {
+        "fd5_32": P.fd5_32(),
+        "fd16_uneven": P.configs.Workload(fd16, part.box_subdomains(fd16, (3, 2), 1), 0.1, 1e-8, "fd16"),
+        "elast_x0_small": P.paper_x0(hinv=6, L=2),
+        "q1_2d_32_rcb": P.q1_2d(m=32, partition="rcb", nparts=6, delta=1),
+    }
+
+
+CASES = small_cases()
+
+
+@pytest.fixture(scope="module", params=sorted(CASES))
+def pair(request, gpu_lib):
+    w = CASES[request.param]
+    print(f"\n[gpu case] {request.param} n={w.A.shape[0]} N={len(w.subs)}", flush=True)
+    st = O.setup(w.A, w.subs, w.tau)
+    solver = gpu_lib.Solver(w.A, w.subs, tau=w.tau)
+    yield w, st, solver
+    solver.close()
+
+
+def test_maps_bit_exact(pair):
+    w, st, solver = pair
+    assert np.array_equal(solver.export("mult"), O.multiplicity(w.A.shape[0], w.subs))
+    assert np.array_equal(solver.export("pair_count"), st.cnt)
+
+
+def test_local_counts_and_eigenvalues(pair):
+    w, st, solver = pair
+    s = solver.stats()
+    assert s["k_s"] == [sp_.nneg for sp_ in st.split]
+    assert s["kstrict_s"] == [sp_.nstrict for sp_ in st.split]
+    neg = solver.export("neg_eigs")
+    ref = np.concatenate([sp_.L_minus for sp_ in st.split]) if neg.size else neg
+    scale = max(np.abs(sp_.lam).max() for sp_ in st.split)
+    assert np.max(np.abs(neg - ref), initial=0.0) <= 1e-11 * scale
+    assert s["m_s"] == [Y.shape[1] for Y in st.Y]
+    ge = solver.export("geneo_eigs")
+    gref = np.concatenate([lam[:Y.shape[1]] for lam, Y in zip(st.geneo_lam, st.Y)])
+    assert np.max(np.abs(ge - gref), initial=0.0) <= 1e-9
+    assert s["n_minus"] == st.n_minus and s["n0"] == st.n0
+
+
+def test_apply_matches_oracle(pair):
+    import torch
+    w, st, solver = pair
+    rng = np.random.default_rng(3)
+    for _ in range(3):
+        r = rng.standard_normal(w.A.shape[0])
+        z = solver.apply(torch.as_tensor(r, device="cuda")).cpu().numpy()
+        zr = st.apply(r)
+        assert np.linalg.norm(z - zr) <= h_rtol(st) * np.linalg.norm(zr)
+
+
+def test_pcg_matches_oracle(pair):
+    import torch
+    w, st, solver = pair
+    b = torch.as_tensor(w.b, device="cuda")
+    x, info = solver.pcg(b, tol=w.tol, maxit=500)
+    ref = O.pcg(w.A, w.b, st.apply, tol=w.tol)
+    assert info["converged"] == 1 and ref.converged
+    assert abs(info["iters"] - ref.iters) <= 1
+    xg = x.cpu().numpy()
+    assert np.linalg.norm(xg - ref.x) <= X_RTOL * np.linalg.norm(ref.x)
+    assert info["rel_res_true"] <= 2 * w.tol
+
+
+def test_apply_is_deterministic(pair):
+    import torch
+    w, st, solver = pair
+    r = torch.as_tensor(np.random.default_rng(9).standard_normal(w.A.shape[0]), device="cuda")
+    z1 = solver.apply(r)
+    z2 = solver.apply(r)
+    assert torch.equal(z1, z2)
+
+
+def test_local_operators(pair):
+    """V^s_- spans the oracle's non-positive eigenspace; P^s = D^s (A^s_+)^+ D^s
+    and the GenEO vectors Y^s span the oracle's selected space."""
+    w, st, solver = pair
+    V = solver.export("V_minus")
+    Pl = solver.export("P_local")
+    Y = solver.export("Y")
+    ov = op = oy = 0
+    for s, idx in enumerate(w.subs):
+        ns = len(idx)
+        sp_ = st.split[s]
+        k = sp_.nneg
+        Vs = V[ov:ov + ns * k].reshape(k, ns).T
+        ov += ns * k
+        Pg = Vs @ Vs.T
+        Pr = sp_.V_minus @ sp_.V_minus.T
+        assert np.max(np.abs(Pg - Pr), initial=0.0) <= 1e-8, f"V_minus subdomain {s}"
+        Ps = Pl[op:op + ns * ns].reshape(ns, ns).T
+        op += ns * ns
+        D = st.Ds[s]
+        ref = D[:, None] * sp_.A_plus_pinv() * D[None, :]
+        assert np.linalg.norm(Ps - ref) <= 1e-8 * np.linalg.norm(ref), f"P subdomain {s}"
+        m = st.Y[s].shape[1]
+        Ys = Y[oy:oy + ns * m].reshape(m, ns).T
+        oy += ns * m
+        if m:
+            import scipy.linalg as sla
+            assert np.max(sla.subspace_angles(Ys, st.Y[s])) <= 1e-7, f"Y subdomain {s}"
