@@ -125,6 +125,8 @@ struct TriEigArgs {
 // thr_mode 1: thr[b] = eps0 * max|lambda| computed here, counting lambda <= thr.
 void tri_count(const TriEigArgs& a, const double* thr_in, int thr_mode, double eps0, double* thr_out,
                int* count, double* lam_minmax, hipStream_t s);
+// Work: 384 * n_b doubles per block at work_off[b] (see k_eig.hip).
+constexpr long TRIVEC_WORK_PER_ROW = 6 * 64;
 void tri_eigvecs(const TriEigArgs& a, const int* count, const long* lam_off, double* lam,
                  const MatDesc* d_Z, double* work, const long* work_off, double* resid,
                  int* nstrict, const double* thr, hipStream_t s);

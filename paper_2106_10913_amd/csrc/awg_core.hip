@@ -496,7 +496,7 @@ EigOut batched_low_eigs(awg_ctx& c, DBuf<MatDesc>& dX, int thr_mode, double thr_
   d.alloc(c.sumns);
   e.alloc(c.sumns);
   tau.alloc(c.sumns);
-  work.alloc(6 * c.sumns);
+  work.alloc(std::max<long>(5, TRIVEC_WORK_PER_ROW) * c.sumns);
   thr.alloc(c.N);
   minmax.alloc(2 * c.N);
   sytrd_batched(dX, c.ns, d, e, tau, c.subptr, work, s);
@@ -518,7 +518,7 @@ EigOut batched_low_eigs(awg_ctx& c, DBuf<MatDesc>& dX, int thr_mode, double thr_
   DBuf<double> resid;
   resid.alloc(std::max<long>(1, L.cols));
   std::vector<long> w6(c.N);
-  for (int q = 0; q < c.N; ++q) w6[q] = 6 * c.h_subptr[q];
+  for (int q = 0; q < c.N; ++q) w6[q] = TRIVEC_WORK_PER_ROW * c.h_subptr[q];
   DBuf<long> dw6;
   dw6.upload(w6, s);
   auto zd = col_descs(c, vecs, L);

@@ -94,13 +94,13 @@ int awg_dense_low_eigs(int32_t batch, int32_t n, double* A, int32_t lda, int64_t
     DBuf<long> doff, w6;
     doff.upload(off, s);
     std::vector<long> o6(batch);
-    for (int b = 0; b < batch; ++b) o6[b] = 6L * b * n;
+    for (int b = 0; b < batch; ++b) o6[b] = TRIVEC_WORK_PER_ROW * b * n;
     w6.upload(o6, s);
     DBuf<double> d, e, tau, work, thrv, mm;
     d.alloc((long)batch * n);
     e.alloc((long)batch * n);
     tau.alloc((long)batch * n);
-    work.alloc(6L * batch * n);
+    work.alloc(TRIVEC_WORK_PER_ROW * batch * n);
     thrv.alloc(batch);
     mm.alloc(2 * batch);
     std::vector<double> ht(batch, thr);

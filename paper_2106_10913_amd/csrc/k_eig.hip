@@ -54,6 +54,10 @@ __global__ __launch_bounds__(256) void k_trd_hh(const MatDesc* mats, int k, doub
                                                 double* tau, const long* off, double* work) {
   const MatDesc M = mats[blockIdx.x];
   const int n = M.n;
+  if (n == 1 && k == 0 && threadIdx.x == 0) {
+    dd[off[blockIdx.x]] = M.A[0];
+    tau[off[blockIdx.x]] = 0.0;
+  }
   if (k > n - 2) return;
   __shared__ double sh[4];
   const long o = off[blockIdx.x];
@@ -176,8 +180,8 @@ void sytrd_batched(const MatDesc* d_mats, const std::vector<int>& h_n, double* d
   int maxn = 0;
   for (int v : h_n) maxn = v > maxn ? v : maxn;
   if (batch == 0 || maxn == 0) return;
-  // 1x1 blocks: T = A
-  for (int k = 0; k <= maxn - 2; ++k) {
+  // (1x1 blocks are copied by the k = 0 launch)
+  for (int k = 0; k <= (maxn > 2 ? maxn - 2 : 0); ++k) {
     hipLaunchKernelGGL(k_trd_hh, dim3(batch), dim3(256), 0, s, d_mats, k, d, e, tau, d_off, work);
     AWG_LAUNCH_CHECK();
     if (k <= maxn - 3) {
@@ -243,66 +247,99 @@ __device__ double bisect_eig(const double* d, const double* e, int n, int i, dou
   return 0.5 * (lo + hi);
 }
 
-__global__ void k_tri_count(TriEigArgs a, const double* thr_in, int thr_mode, double eps0, double* thr_out,
-                            int* count, double* minmax) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= a.nb) return;
+// idx-th smallest eigenvalue (0-based) by multisection: the 64 lanes of a
+// wavefront evaluate 64 interior points of [lo, hi] at once, so every step
+// narrows the bracket 65-fold.  Called by all lanes of the wavefront.
+__device__ double multisect_eig(const double* d, const double* e, int n, int idx, double lo, double hi,
+                                double pivmin) {
+  const int lane = threadIdx.x & 63;
+  for (int it = 0; it < 48; ++it) {
+    if (hi - lo <= 2.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi)) + pivmin) break;
+    const double w = hi - lo;
+    const double x = lo + w * (double)(lane + 1) / 65.0;
+    const int c = sturm_count(d, e, n, x, pivmin);
+    const unsigned long long m = __ballot(c <= idx);     // lanes whose point lies at or below lambda_idx
+    const int nb = __popcll(m);
+    const double nlo = nb > 0 ? lo + w * (double)nb / 65.0 : lo;
+    const double nhi = nb < 64 ? lo + w * (double)(nb + 1) / 65.0 : hi;
+    if (!(nlo < nhi)) break;
+    lo = nlo;
+    hi = nhi;
+  }
+  return 0.5 * (lo + hi);
+}
+
+// one wavefront per block
+__global__ __launch_bounds__(64) void k_tri_count(TriEigArgs a, const double* thr_in, int thr_mode, double eps0,
+                                                  double* thr_out, int* count, double* minmax) {
+  const int b = blockIdx.x;
   const int n = a.n[b];
+  if (n == 0) {
+    if (threadIdx.x == 0) count[b] = 0;
+    return;
+  }
   const double* d = a.d + a.off[b];
   const double* e = a.e + a.off[b];
-  if (n == 0) { count[b] = 0; return; }
   const TriInfo t = tri_info(d, e, n);
   double thr;
   if (thr_mode == 1) {
-    const double lmin = bisect_eig(d, e, n, 0, t.gl, t.gu, t.pivmin);
-    const double lmax = bisect_eig(d, e, n, n - 1, t.gl, t.gu, t.pivmin);
-    minmax[2 * b] = lmin;
-    minmax[2 * b + 1] = lmax;
+    const double lmin = multisect_eig(d, e, n, 0, t.gl, t.gu, t.pivmin);
+    const double lmax = multisect_eig(d, e, n, n - 1, t.gl, t.gu, t.pivmin);
+    if (threadIdx.x == 0) {
+      minmax[2 * b] = lmin;
+      minmax[2 * b + 1] = lmax;
+    }
     thr = eps0 * fmax(fabs(lmin), fabs(lmax));
   } else {
     thr = thr_in[b];
   }
-  thr_out[b] = thr;
-  count[b] = sturm_count(d, e, n, thr, t.pivmin);
+  if (threadIdx.x == 0) {
+    thr_out[b] = thr;
+    count[b] = sturm_count(d, e, n, thr, t.pivmin);
+  }
 }
 
 void tri_count(const TriEigArgs& a, const double* thr_in, int thr_mode, double eps0, double* thr_out, int* count,
                double* lam_minmax, hipStream_t s) {
   if (a.nb == 0) return;
-  hipLaunchKernelGGL(k_tri_count, dim3(cdiv(a.nb, 64)), dim3(64), 0, s, a, thr_in, thr_mode, eps0, thr_out, count,
+  hipLaunchKernelGGL(k_tri_count, dim3(a.nb), dim3(64), 0, s, a, thr_in, thr_mode, eps0, thr_out, count,
                      lam_minmax);
   AWG_LAUNCH_CHECK();
 }
 
 // ---------------------------------------------------------------------------
-// eigenvectors of T by inverse iteration (one wavefront per block)
+// eigenvectors of T by inverse iteration, one lane per eigenvalue
 // ---------------------------------------------------------------------------
 constexpr int INVIT_SWEEPS = 4;
+constexpr int INVIT_LANES = 64;
 
-// work per block: 6 n doubles (u0,u1,u2,l,piv,x) at work_off[b]
+// Work per block (doubles): 6 arrays of n x 64, interleaved so that step i of
+// all 64 lanes is one contiguous 512-byte row: u0, u1, u2 (U of the LU with
+// partial pivoting), l (multipliers), pivot flags, x (iterates).
 __global__ __launch_bounds__(64) void k_tri_vecs(TriEigArgs a, const int* count, const long* lam_off, double* lam,
                                                   const MatDesc* Zs, double* work, const long* work_off,
                                                   double* resid, int* nstrict, const double* thr) {
   const int b = blockIdx.x;
   const int n = a.n[b];
   const int k = count[b];
+  const int lane = threadIdx.x;
   if (n == 0 || k == 0) {
-    if (threadIdx.x == 0 && nstrict) nstrict[b] = 0;
+    if (lane == 0 && nstrict) nstrict[b] = 0;
     return;
   }
   const double* d = a.d + a.off[b];
   const double* e = a.e + a.off[b];
   double* L = lam + lam_off[b];
   const MatDesc Z = Zs[b];
+  const long W = INVIT_LANES;
   double* wk = work + work_off[b];
-  double* u0 = wk;
-  double* u1 = wk + n;
-  double* u2 = wk + 2 * n;
-  double* lf = wk + 3 * n;
-  double* pv = wk + 4 * n;
-  const int lane = threadIdx.x;
+  double* U0 = wk;
+  double* U1 = wk + W * n;
+  double* U2 = wk + 2 * W * n;
+  double* LF = wk + 3 * W * n;
+  double* PV = wk + 4 * W * n;
+  double* X = wk + 5 * W * n;
   const TriInfo t = tri_info(d, e, n);
-  // eigenvalues, one per lane
   for (int j = lane; j < k; j += 64) L[j] = bisect_eig(d, e, n, j, t.gl, t.gu, t.pivmin);
   __syncthreads();
   if (lane == 0 && nstrict) {
@@ -311,88 +348,110 @@ __global__ __launch_bounds__(64) void k_tri_vecs(TriEigArgs a, const int* count,
     nstrict[b] = c;
   }
   const double pert = DBL_EPSILON * fmax(t.tnorm, DBL_MIN);
-  for (int j = 0; j < k; ++j) {
-    const double lj = L[j];
-    double* x = Z.A + (long)j * Z.ld;
-    // LU factorisation of T - lj I with partial pivoting (lane 0)
-    if (lane == 0) {
+  for (int j0 = 0; j0 < k; j0 += 64) {
+    const int jc = j0 + lane;
+    const bool act = jc < k;
+    const int kc = min(64, k - j0);
+    const double lj = act ? L[jc] : 0.0;
+    // LU of T - lj I with partial pivoting (each lane its own shift)
+    if (act) {
       double cd = d[0] - lj, cs = n > 1 ? e[0] : 0.0;
       for (int i = 0; i < n - 1; ++i) {
         const double sub = e[i];
         const double nd = d[i + 1] - lj;
         const double ns = (i + 1 < n - 1) ? e[i + 1] : 0.0;
+        const long o = i * W + lane;
         if (fabs(cd) >= fabs(sub)) {
           if (cd == 0.0) cd = pert;
           const double l = sub / cd;
-          u0[i] = cd; u1[i] = cs; u2[i] = 0.0; lf[i] = l; pv[i] = 0.0;
+          U0[o] = cd; U1[o] = cs; U2[o] = 0.0; LF[o] = l; PV[o] = 0.0;
           cd = nd - l * cs;
           cs = ns;
         } else {
           const double l = cd / sub;
-          u0[i] = sub; u1[i] = nd; u2[i] = ns; lf[i] = l; pv[i] = 1.0;
+          U0[o] = sub; U1[o] = nd; U2[o] = ns; LF[o] = l; PV[o] = 1.0;
           cd = cs - l * nd;
           cs = -l * ns;
         }
       }
       if (fabs(cd) < pert) cd = cd < 0.0 ? -pert : pert;
-      u0[n - 1] = cd;
+      U0[(n - 1) * W + lane] = cd;
+      // deterministic pseudo-random start vector
+      for (int i = 0; i < n; ++i) {
+        unsigned h = (unsigned)(i * 2654435761u) ^ (unsigned)((jc + 1) * 40503u) ^ 0x9e3779b9u;
+        h ^= h >> 16; h *= 0x7feb352du; h ^= h >> 15; h *= 0x846ca68bu; h ^= h >> 16;
+        X[i * W + lane] = (double)(h & 0xffffff) / 16777216.0 - 0.5;
+      }
     }
-    // deterministic pseudo-random start vector
-    for (int i = lane; i < n; i += 64) {
-      unsigned h = (unsigned)(i * 2654435761u) ^ (unsigned)((j + 1) * 40503u) ^ 0x9e3779b9u;
-      h ^= h >> 16; h *= 0x7feb352du; h ^= h >> 15; h *= 0x846ca68bu; h ^= h >> 16;
-      x[i] = (double)(h & 0xffffff) / 16777216.0 - 0.5;
-    }
-    __syncthreads();
     for (int sweep = 0; sweep < INVIT_SWEEPS; ++sweep) {
-      // solve (T - lj I) y = x  (lane 0)
-      if (lane == 0) {
+      if (act) {
+        // solve (T - lj I) y = x in place, then scale to unit max norm
+        double xi = X[lane];
         for (int i = 0; i < n - 1; ++i) {
-          if (pv[i] != 0.0) { const double tt = x[i]; x[i] = x[i + 1]; x[i + 1] = tt; }
-          x[i + 1] -= lf[i] * x[i];
+          const long o = i * W + lane;
+          double xn = X[o + W];
+          if (PV[o] != 0.0) { const double tt = xi; xi = xn; xn = tt; }
+          X[o] = xi;
+          xi = xn - LF[o] * xi;
         }
-        x[n - 1] /= u0[n - 1];
-        if (n > 1) x[n - 2] = (x[n - 2] - u1[n - 2] * x[n - 1]) / u0[n - 2];
-        for (int i = n - 3; i >= 0; --i) x[i] = (x[i] - u1[i] * x[i + 1] - u2[i] * x[i + 2]) / u0[i];
+        X[(n - 1) * W + lane] = xi;
+        double x1 = xi / U0[(n - 1) * W + lane];
+        X[(n - 1) * W + lane] = x1;
+        double x2 = 0.0;
+        double mx = fabs(x1);
+        for (int i = n - 2; i >= 0; --i) {
+          const long o = i * W + lane;
+          const double v = (X[o] - U1[o] * x1 - U2[o] * x2) / U0[o];
+          X[o] = v;
+          x2 = x1;
+          x1 = v;
+          mx = fmax(mx, fabs(v));
+        }
+        const double inv = mx > 0.0 ? 1.0 / mx : 1.0;
+        for (int i = 0; i < n; ++i) X[i * W + lane] *= inv;
       }
       __syncthreads();
-      // scale to unit max norm to keep numbers in range
-      double mx = 0.0;
-      for (int i = lane; i < n; i += 64) mx = fmax(mx, fabs(x[i]));
-#pragma unroll
-      for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
-      const double inv = mx > 0.0 ? 1.0 / mx : 1.0;
-      for (int i = lane; i < n; i += 64) x[i] *= inv;
-      __syncthreads();
-      // modified Gram-Schmidt against the vectors already found (twice)
-      for (int pass = 0; pass < 2; ++pass) {
-        for (int q = 0; q < j; ++q) {
+      // against the vectors of earlier chunks (already in Z), twice
+      for (int pass = 0; pass < 2 && act; ++pass)
+        for (int q = 0; q < j0; ++q) {
           const double* zq = Z.A + (long)q * Z.ld;
-          double dot = 0.0;
-          for (int i = lane; i < n; i += 64) dot += zq[i] * x[i];
-          dot = wave_sum(dot);
-          for (int i = lane; i < n; i += 64) x[i] -= dot * zq[i];
-          __syncthreads();
+          double dt = 0.0;
+          for (int i = 0; i < n; ++i) dt += zq[i] * X[i * W + lane];
+          for (int i = 0; i < n; ++i) X[i * W + lane] -= dt * zq[i];
         }
-      }
-      double nr = 0.0;
-      for (int i = lane; i < n; i += 64) nr += x[i] * x[i];
-      nr = wave_sum(nr);
-      const double inr = nr > 0.0 ? 1.0 / sqrt(nr) : 0.0;
-      for (int i = lane; i < n; i += 64) x[i] *= inr;
       __syncthreads();
+      // modified Gram-Schmidt inside the chunk, in eigenvalue order, twice;
+      // the wavefront cooperates on one vector at a time
+      for (int jj = 0; jj < kc; ++jj) {
+        for (int pass = 0; pass < 2; ++pass)
+          for (int q = 0; q < jj; ++q) {
+            double dt = 0.0;
+            for (int i = lane; i < n; i += 64) dt += X[i * W + q] * X[i * W + jj];
+            dt = wave_sum(dt);
+            for (int i = lane; i < n; i += 64) X[i * W + jj] -= dt * X[i * W + q];
+            __syncthreads();
+          }
+        double nr = 0.0;
+        for (int i = lane; i < n; i += 64) nr += X[i * W + jj] * X[i * W + jj];
+        nr = wave_sum(nr);
+        const double inr = nr > 0.0 ? 1.0 / sqrt(nr) : 0.0;
+        for (int i = lane; i < n; i += 64) X[i * W + jj] *= inr;
+        __syncthreads();
+      }
     }
-    // residual ||T x - lj x||_inf
-    double rmax = 0.0;
-    for (int i = lane; i < n; i += 64) {
-      double v = (d[i] - lj) * x[i];
-      if (i > 0) v += e[i - 1] * x[i - 1];
-      if (i < n - 1) v += e[i] * x[i + 1];
-      rmax = fmax(rmax, fabs(v));
+    if (act) {
+      // residual ||T x - lj x||_inf / ||T|| and copy out
+      double rmax = 0.0;
+      for (int i = 0; i < n; ++i) {
+        const double xv = X[i * W + lane];
+        double v = (d[i] - lj) * xv;
+        if (i > 0) v += e[i - 1] * X[(i - 1) * W + lane];
+        if (i < n - 1) v += e[i] * X[(i + 1) * W + lane];
+        rmax = fmax(rmax, fabs(v));
+        Z.A[i + (long)jc * Z.ld] = xv;
+      }
+      resid[lam_off[b] + jc] = rmax / fmax(t.tnorm, DBL_MIN);
     }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) rmax = fmax(rmax, __shfl_xor(rmax, o, 64));
-    if (lane == 0) resid[lam_off[b] + j] = rmax / fmax(t.tnorm, DBL_MIN);
     __syncthreads();
   }
 }

@@ -169,16 +169,37 @@ __global__ void k_extract(const long* sub_ptr, const int* sub_idx, const int* ro
 // ---------------------------------------------------------------------------
 // multi-column vector kernels
 // ---------------------------------------------------------------------------
-__global__ void k_spmm(int n, const int* rowptr, const int* col, const double* val, const double* X, long ldx,
-                       double* Y, long ldy, double alpha, double beta) {
+// Y = alpha A X + beta Y for b columns: one thread per row and SPMM_CB
+// columns, so each row's nonzeros are read once per column block.
+constexpr int SPMM_CB = 8;
+__global__ __launch_bounds__(256) void k_spmm(int n, const int* rowptr, const int* col, const double* val,
+                                              const double* X, long ldx, double* Y, long ldy, int b, double alpha,
+                                              double beta) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const int c = blockIdx.y;
-  const double* x = X + c * ldx;
-  double acc = 0.0;
-  for (int p = rowptr[i]; p < rowptr[i + 1]; ++p) acc += val[p] * x[col[p]];
-  double* y = Y + c * ldy + i;
-  *y = (beta == 0.0) ? alpha * acc : alpha * acc + beta * *y;
+  const int c0 = blockIdx.y * SPMM_CB;
+  const int nc = min(SPMM_CB, b - c0);
+  const double* x = X + c0 * ldx;
+  double acc[SPMM_CB];
+#pragma unroll
+  for (int c = 0; c < SPMM_CB; ++c) acc[c] = 0.0;
+  const int pe = rowptr[i + 1];
+  if (nc == SPMM_CB) {
+    for (int p = rowptr[i]; p < pe; ++p) {
+      const double v = val[p];
+      const long j = col[p];
+#pragma unroll
+      for (int c = 0; c < SPMM_CB; ++c) acc[c] += v * x[j + c * ldx];
+    }
+  } else {
+    for (int p = rowptr[i]; p < pe; ++p) {
+      const double v = val[p];
+      const long j = col[p];
+      for (int c = 0; c < nc; ++c) acc[c] += v * x[j + c * ldx];
+    }
+  }
+  double* y = Y + c0 * ldy + i;
+  for (int c = 0; c < nc; ++c) y[c * ldy] = (beta == 0.0) ? alpha * acc[c] : alpha * acc[c] + beta * y[c * ldy];
 }
 
 __global__ void k_gather(long tot, const int* sub_idx, const int* ent_sub, const long* sub_ptr, const double* X,
@@ -422,7 +443,8 @@ void l_extract(int N, const long* sub_ptr, const int* sub_idx, const int* rowptr
 void l_spmm(int n, const int* rowptr, const int* col, const double* val, const double* X, long ldx, double* Y,
             long ldy, int b, double alpha, double beta, hipStream_t s) {
   if (n == 0 || b == 0) return;
-  hipLaunchKernelGGL(k_spmm, dim3(grid1(n), b), dim3(256), 0, s, n, rowptr, col, val, X, ldx, Y, ldy, alpha, beta);
+  hipLaunchKernelGGL(k_spmm, dim3(grid1(n), cdiv(b, SPMM_CB)), dim3(256), 0, s, n, rowptr, col, val, X, ldx, Y, ldy, b,
+                     alpha, beta);
   AWG_LAUNCH_CHECK();
 }
 void l_gather(long tot, const int* sub_idx, const int* ent_sub, const long* sub_ptr, const double* X, long ldx,

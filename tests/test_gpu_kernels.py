@@ -82,7 +82,7 @@ def test_trsm(gpu_lib, n, nrhs, trans):
         assert np.max(np.abs(X[b] - ref)) <= 1e-11 * max(1.0, np.max(np.abs(ref)))
 
 
-@pytest.mark.parametrize("n", [2, 3, 40, 97, 200])
+@pytest.mark.parametrize("n", [1, 2, 3, 40, 97, 200])
 def test_low_eigs_against_eigh(gpu_lib, n):
     rng = np.random.default_rng(n)
     batch = 3
