@@ -89,6 +89,31 @@ def cpu_baseline(w, budget_subdomains: int = 6):
     }
 
 
+# kernels whose roofline is the matrix cores (FP64 MFMA); every other
+# instrumented kernel is HBM bound
+MFMA_KERNELS = ("k_gemm",)
+
+
+def roofline(kt: dict, steps: int) -> dict:
+    """Roofline of the kernel with the largest total time in the timed steps.
+
+    achieved = algorithmic bytes (or flops) of all its launches / their total
+    duration (HIP events on the launching stream).
+    """
+    name, rec = max(kt.items(), key=lambda kv: kv[1]["ms"])
+    avg_us = rec["ms"] * 1e3 / rec["calls"]
+    if name.startswith(MFMA_KERNELS):
+        achieved = rec["flops"] / (rec["ms"] * 1e-3) / 1e12
+        return {"kernel": name, "bound": "mfma", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": None,
+                "calls_per_step": rec["calls"] / steps, "avg_launch_us": round(avg_us, 2),
+                "flops_per_launch": rec["flops"] / rec["calls"]}
+    achieved = rec["bytes"] / (rec["ms"] * 1e-3) / 1e9
+    return {"kernel": name, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "calls_per_step": rec["calls"] / steps,
+            "avg_launch_us": round(avg_us, 2), "bytes_per_launch": rec["bytes"] / rec["calls"]}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -125,6 +150,9 @@ def main():
         print(f"# warmup {i}: iters={info['iters']} setup_ms={st['ms']['total']:.1f}", file=sys.stderr,
               flush=True)
     torch.cuda.synchronize()
+    # per-kernel HIP events on the library's stream during the timed steps
+    awg.kernel_times(reset=True)
+    awg.kernel_timing(True)
     t0 = time.perf_counter()
     infos, stats = [], []
     for i in range(args.steps):
@@ -135,6 +163,8 @@ def main():
               flush=True)
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    awg.kernel_timing(False)
+    kt = awg.kernel_times(reset=True)
 
     st = stats[-1]
     info = infos[-1]
@@ -160,6 +190,9 @@ def main():
                   "w_iters": st["w_iters"]},
         "phases_ms": phases,
     }
+    out["roofline"] = roofline(kt, args.steps)
+    out["kernels_ms_per_step"] = {k: round(v["ms"] / args.steps, 3) for k, v in
+                                  sorted(kt.items(), key=lambda kv: -kv[1]["ms"])}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out))

@@ -130,6 +130,19 @@ int64_t awg_export(const awg_ctx* ctx, const char* name, void* host_buf, size_t 
  * awg_setup when ctx is NULL.  Never returns NULL. */
 const char* awg_last_error(const awg_ctx* ctx);
 
+/* Kernel timing for performance reports: when enabled, HIP events are
+ * recorded on the launching stream around the main kernels of every
+ * context, and per-kernel launch counts, elapsed milliseconds and the
+ * algorithmic bytes / flops of each launch are accumulated.  Off by default
+ * (it adds one event pair per launch). */
+int awg_kernel_timing(int32_t enable);
+
+/* JSON {"kernel": {"calls", "ms", "bytes", "flops"}, ...} of the accumulated
+ * kernel times (synchronises the pending events).  buf: host buffer of cap
+ * bytes; reset != 0 clears the accumulators.  Returns the bytes needed or a
+ * negative error. */
+int64_t awg_kernel_times(char* buf, size_t cap, int32_t reset);
+
 /* Free every device buffer of the context.  NULL is ignored. */
 void awg_destroy(awg_ctx* ctx);
 

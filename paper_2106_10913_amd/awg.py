@@ -23,7 +23,7 @@ STATUS = {0: "AWG_OK", 1: "AWG_NOT_CONVERGED", -1: "AWG_ERR_ARG", -2: "AWG_ERR_N
           -7: "AWG_ERR_HIP", -8: "AWG_ERR_OOM", -9: "AWG_ERR_NONFINITE"}
 
 EXPORTED = ["awg_default_options", "awg_setup", "awg_apply", "awg_pcg", "awg_stats", "awg_export",
-            "awg_last_error", "awg_destroy",
+            "awg_last_error", "awg_destroy", "awg_kernel_timing", "awg_kernel_times",
             "awg_dense_gemm", "awg_dense_potrf", "awg_dense_trsm", "awg_dense_low_eigs"]
 
 
@@ -73,6 +73,10 @@ def lib():
     L.awg_last_error.restype = ctypes.c_char_p
     L.awg_destroy.argtypes = [vp]
     L.awg_destroy.restype = None
+    L.awg_kernel_timing.argtypes = [i32]
+    L.awg_kernel_timing.restype = ctypes.c_int
+    L.awg_kernel_times.argtypes = [ctypes.c_char_p, ctypes.c_size_t, i32]
+    L.awg_kernel_times.restype = i64
     L.awg_dense_gemm.argtypes = [i32, i32, i32, i32, i32, i32, dbl, vp, i32, i64, vp, i32, i64, dbl, vp, i32, i64,
                                  vp]
     L.awg_dense_gemm.restype = ctypes.c_int
@@ -84,6 +88,22 @@ def lib():
     L.awg_dense_low_eigs.restype = ctypes.c_int
     _lib = L
     return L
+
+
+def kernel_timing(enable: bool) -> None:
+    rc = lib().awg_kernel_timing(int(enable))
+    if rc:
+        raise AWGError(rc, "awg_kernel_timing")
+
+
+def kernel_times(reset: bool = False) -> dict:
+    L = lib()
+    need = L.awg_kernel_times(None, 0, 0)
+    if need < 0:
+        raise AWGError(int(need), "awg_kernel_times")
+    buf = ctypes.create_string_buffer(int(need) + 64)
+    L.awg_kernel_times(buf, len(buf), int(reset))
+    return json.loads(buf.value.decode())
 
 
 def default_options() -> Options:

@@ -72,6 +72,23 @@ struct DBuf {
 };
 
 // ---------------------------------------------------------------------------
+// kernel timing (off by default): HIP events around instrumented launches,
+// accumulated per kernel with the algorithmic bytes and flops of each launch
+// ---------------------------------------------------------------------------
+struct KScope {
+  int slot = -1;
+  KScope(const char* name, hipStream_t s, double bytes, double flops);
+  ~KScope();
+  KScope(const KScope&) = delete;
+  KScope& operator=(const KScope&) = delete;
+ private:
+  hipStream_t s_ = nullptr;
+};
+void ktimer_enable(bool on);
+bool ktimer_on();
+std::string ktimer_json(bool reset);
+
+// ---------------------------------------------------------------------------
 // batched dense descriptors (column-major blocks)
 // ---------------------------------------------------------------------------
 struct GemmDesc {
@@ -93,12 +110,13 @@ struct MatDesc {         // one square or rectangular column-major block
 // ---------------------------------------------------------------------------
 // C = alpha * op(A) op(B) + beta * C for every descriptor; lower != 0 skips
 // 64x64 output tiles lying strictly above the diagonal.
+// flops: algorithmic flop count of the whole batch (for the kernel timer only)
 void gemm_batched(const GemmDesc* d_desc, int batch, int max_m, int max_n, bool transA, bool transB,
-                  double alpha, double beta, bool lower, hipStream_t s);
+                  double alpha, double beta, bool lower, hipStream_t s, double flops = 0.0);
 // y = alpha * op(A) x + beta * y per descriptor, with the GEMM convention
 // (n == 1: A = matrix, B = x, C = y; op(A) is m x k).
 void gemv_batched(const GemmDesc* d_desc, int batch, int max_m, int max_k, bool transA, double alpha,
-                  double beta, hipStream_t s);
+                  double beta, hipStream_t s, double bytes = 0.0);
 
 // Cholesky A = L L^T (lower, in place) of every block; info[b] = 0 or the
 // 1-based column of the first non-positive pivot.

@@ -19,6 +19,85 @@
 
 using namespace awg;
 
+// ---------------------------------------------------------------------------
+// kernel timer
+// ---------------------------------------------------------------------------
+namespace awg {
+namespace {
+struct KRec {
+  std::string name;
+  hipEvent_t a, b;
+  double bytes, flops;
+};
+struct KAcc {
+  double calls = 0, ms = 0, bytes = 0, flops = 0;
+};
+bool g_kt_on = false;
+std::vector<KRec> g_kt_pending;
+std::vector<hipEvent_t> g_kt_pool;
+std::map<std::string, KAcc> g_kt_acc;
+
+hipEvent_t kt_event() {
+  if (!g_kt_pool.empty()) {
+    hipEvent_t e = g_kt_pool.back();
+    g_kt_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  AWG_HIP(hipEventCreate(&e));
+  return e;
+}
+
+void kt_flush() {
+  for (auto& r : g_kt_pending) {
+    AWG_HIP(hipEventSynchronize(r.b));
+    float ms = 0.f;
+    AWG_HIP(hipEventElapsedTime(&ms, r.a, r.b));
+    KAcc& a = g_kt_acc[r.name];
+    a.calls += 1;
+    a.ms += ms;
+    a.bytes += r.bytes;
+    a.flops += r.flops;
+    g_kt_pool.push_back(r.a);
+    g_kt_pool.push_back(r.b);
+  }
+  g_kt_pending.clear();
+}
+}  // namespace
+
+KScope::KScope(const char* name, hipStream_t s, double bytes, double flops) : s_(s) {
+  if (!g_kt_on) return;
+  if (g_kt_pending.size() >= 8192) kt_flush();
+  KRec r{name, kt_event(), kt_event(), bytes, flops};
+  AWG_HIP(hipEventRecord(r.a, s));
+  slot = (int)g_kt_pending.size();
+  g_kt_pending.push_back(r);
+}
+
+KScope::~KScope() {
+  if (slot >= 0) (void)hipEventRecord(g_kt_pending[slot].b, s_);
+}
+
+void ktimer_enable(bool on) { g_kt_on = on; }
+bool ktimer_on() { return g_kt_on; }
+
+std::string ktimer_json(bool reset) {
+  kt_flush();
+  std::ostringstream o;
+  o.precision(10);
+  o << "{";
+  bool first = true;
+  for (auto& kv : g_kt_acc) {
+    o << (first ? "" : ",") << "\"" << kv.first << "\":{\"calls\":" << kv.second.calls << ",\"ms\":" << kv.second.ms
+      << ",\"bytes\":" << kv.second.bytes << ",\"flops\":" << kv.second.flops << "}";
+    first = false;
+  }
+  o << "}";
+  if (reset) g_kt_acc.clear();
+  return o.str();
+}
+}  // namespace awg
+
 namespace {
 
 thread_local std::string g_setup_error = "no error";
@@ -62,6 +141,7 @@ struct MultiWS {
   DBuf<double> H0, H1;                // n_minus x b
   DBuf<GemmDesc> dVt, dV, dYt, dY, dP, dE0a, dE0b, dWt, dEW, dW;
   int maxk = 0, maxm = 0, maxns = 0;
+  double flV = 0, flY = 0, flP = 0, flE0 = 0, flW = 0, flEW = 0;   // algorithmic flops per product
 };
 
 struct awg_ctx {
@@ -228,11 +308,12 @@ std::vector<MatDesc> col_descs(const awg_ctx& c, double* base, const ColLayout& 
   return v;
 }
 
+// flops: algorithmic flops of the whole batched product (2 m n k summed)
 void bmm(const DBuf<GemmDesc>& d, int batch, int maxm, int maxn, int maxk, bool tA, double alpha, double beta,
-         int b, hipStream_t s) {
+         int b, hipStream_t s, double flops) {
   if (batch == 0) return;
-  if (b == 1) gemv_batched(d, batch, maxm, maxk, tA, alpha, beta, s);
-  else gemm_batched(d, batch, maxm, maxn, tA, false, alpha, beta, false, s);
+  if (b == 1) gemv_batched(d, batch, maxm, maxk, tA, alpha, beta, s, 4.0 * flops);
+  else gemm_batched(d, batch, maxm, maxn, tA, false, alpha, beta, false, s, flops);
 }
 
 void gemm_upload(DBuf<GemmDesc>& d, const std::vector<GemmDesc>& h, hipStream_t s) { d.upload(h, s); }
@@ -256,8 +337,12 @@ void build_ws(awg_ctx& c, MultiWS& w, int b) {
   w.H1.alloc(std::max(1, c.nminus) * (long)b);
   std::vector<GemmDesc> vt(c.N), vv(c.N), yt(c.N), yy(c.N), pp(c.N);
   w.maxk = w.maxm = w.maxns = 0;
+  w.flV = w.flY = w.flP = 0;
   for (int q = 0; q < c.N; ++q) {
     const int nsq = c.ns[q];
+    w.flV += 2.0 * nsq * c.ks[q] * b;
+    w.flY += 2.0 * nsq * c.ms[q] * b;
+    w.flP += 2.0 * nsq * (double)nsq * b;
     const long so = c.h_subptr[q] * b;
     const int kq = c.ks[q], mq = c.ms[q];
     w.maxk = std::max(w.maxk, kq);
@@ -275,6 +360,9 @@ void build_ws(awg_ctx& c, MultiWS& w, int b) {
   gemm_upload(w.dY, yy, s);
   gemm_upload(w.dP, pp, s);
   const int n0 = std::max(1, c.n0), nm = std::max(1, c.nminus);
+  w.flE0 = 2.0 * c.n0 * (double)c.n0 * b;
+  w.flW = 2.0 * c.n * (double)c.nminus * b;
+  w.flEW = 2.0 * c.nminus * (double)c.nminus * b;
   gemm_upload(w.dE0a, {GemmDesc{c.E0inv, w.G0, w.G1, c.n0, b, c.n0, n0, n0, n0}}, s);
   gemm_upload(w.dE0b, {GemmDesc{c.E0inv, w.G0, w.G2, c.n0, b, c.n0, n0, n0, n0}}, s);
   gemm_upload(w.dWt, {GemmDesc{c.W, w.R, w.H0, c.nminus, b, c.n, c.n, c.n, nm}}, s);
@@ -290,29 +378,29 @@ void op_aminus(awg_ctx& c, MultiWS& w, const double* X, double* Yo, double beta)
     return;
   }
   l_gather(c.sumns, c.subidx, c.entsub, c.subptr, X, c.n, b, nullptr, w.Xs, c.s);
-  bmm(w.dVt, c.N, w.maxk, b, w.maxns, true, 1.0, 0.0, b, c.s);
+  bmm(w.dVt, c.N, w.maxk, b, w.maxns, true, 1.0, 0.0, b, c.s, w.flV);
   hipLaunchKernelGGL(k_scale_rows_blocks, dim3(64, c.N), dim3(256), 0, c.s, w.Tk.p, c.LV.d_coff.p, c.lamV.p, c.N, b);
   AWG_LAUNCH_CHECK();
-  bmm(w.dV, c.N, w.maxns, b, w.maxk, false, 1.0, 0.0, b, c.s);
-  l_scatter(c.n, c.invptr, c.invsub, c.invloc, c.subptr, w.Os, b, nullptr, Yo, c.n, 1.0, beta, c.s);
+  bmm(w.dV, c.N, w.maxns, b, w.maxk, false, 1.0, 0.0, b, c.s, w.flV);
+  l_scatter(c.n, c.sumns, c.invptr, c.invsub, c.invloc, c.subptr, w.Os, b, nullptr, Yo, c.n, 1.0, beta, c.s);
 }
 
 // Y = A_+ X = A X + A_- X (item (i) of the A_+ theorem, Section 3.2)
 void op_aplus(awg_ctx& c, MultiWS& w, const double* X, double* Yo) {
-  l_spmm(c.n, c.rowptr, c.col, c.val, X, c.n, Yo, c.n, w.b, 1.0, 0.0, c.s);
+  l_spmm(c.n, c.nnz, c.rowptr, c.col, c.val, X, c.n, Yo, c.n, w.b, 1.0, 0.0, c.s);
   op_aminus(c, w, X, Yo, 1.0);
 }
 
 // G0 = R0 X  (R0^T = [R^1T Y^1 | ... | R^NT Y^N])
 void op_r0(awg_ctx& c, MultiWS& w, const double* X) {
   l_gather(c.sumns, c.subidx, c.entsub, c.subptr, X, c.n, w.b, nullptr, w.Xs, c.s);
-  bmm(w.dYt, c.N, w.maxm, w.b, w.maxns, true, 1.0, 0.0, w.b, c.s);
+  bmm(w.dYt, c.N, w.maxm, w.b, w.maxns, true, 1.0, 0.0, w.b, c.s, w.flY);
 }
 
 // Yo = beta Yo + R0^T G1
 void op_r0t(awg_ctx& c, MultiWS& w, double* Yo, double beta) {
-  bmm(w.dY, c.N, w.maxns, w.b, w.maxm, false, 1.0, 0.0, w.b, c.s);
-  l_scatter(c.n, c.invptr, c.invsub, c.invloc, c.subptr, w.Os, w.b, nullptr, Yo, c.n, 1.0, beta, c.s);
+  bmm(w.dY, c.N, w.maxns, w.b, w.maxm, false, 1.0, 0.0, w.b, c.s, w.flY);
+  l_scatter(c.n, c.sumns, c.invptr, c.invsub, c.invloc, c.subptr, w.Os, w.b, nullptr, Yo, c.n, 1.0, beta, c.s);
 }
 
 // Yo = H^NN X = sum_s R^sT P^s R^s X with P^s = D^s (A^s_+)^+ D^s (Definition of H^NN, Section 3.3)
@@ -323,9 +411,9 @@ void op_hnn(awg_ctx& c, MultiWS& w, const double* X, double* Yo, bool f32) {
                        c.subptr.p, w.Xs.p, w.Os.p);
     AWG_LAUNCH_CHECK();
   } else {
-    bmm(w.dP, c.N, w.maxns, w.b, w.maxns, false, 1.0, 0.0, w.b, c.s);
+    bmm(w.dP, c.N, w.maxns, w.b, w.maxns, false, 1.0, 0.0, w.b, c.s, w.flP);
   }
-  l_scatter(c.n, c.invptr, c.invsub, c.invloc, c.subptr, w.Os, w.b, nullptr, Yo, c.n, 1.0, 0.0, c.s);
+  l_scatter(c.n, c.sumns, c.invptr, c.invsub, c.invloc, c.subptr, w.Os, w.b, nullptr, Yo, c.n, 1.0, 0.0, c.s);
 }
 
 }  // namespace
@@ -345,14 +433,14 @@ void op_h2(awg_ctx& c, MultiWS& w, bool f32) {
     return;
   }
   op_r0(c, w, w.R);                                                      // G0 = R0 r
-  bmm(w.dE0a, 1, c.n0, b, c.n0, false, 1.0, 0.0, b, c.s);                // G1 = u0
+  bmm(w.dE0a, 1, c.n0, b, c.n0, false, 1.0, 0.0, b, c.s, w.flE0);                // G1 = u0
   op_r0t(c, w, w.T1, 0.0);                                               // T1 = R0^T u0
   op_aplus(c, w, w.T1, w.T2);                                            // T2 = A_+ R0^T u0
   l_colaxpby(c.n, b, w.R, c.n, nullptr, w.T2, c.n, nullptr, 1.0, -1.0, c.s);  // T2 = r - T2
   op_hnn(c, w, w.T2, w.Z, f32);                                          // Z = y
   op_aplus(c, w, w.Z, w.T1);                                             // T1 = A_+ y
   op_r0(c, w, w.T1);                                                     // G0 = R0 A_+ y
-  bmm(w.dE0b, 1, c.n0, b, c.n0, false, 1.0, 0.0, b, c.s);                // G2 = v
+  bmm(w.dE0b, 1, c.n0, b, c.n0, false, 1.0, 0.0, b, c.s, w.flE0);                // G2 = v
   l_colaxpby(c.n0, b, w.G2, c.n0, nullptr, w.G1, c.n0, nullptr, -1.0, 1.0, c.s);  // G1 = u0 - v
   op_r0t(c, w, w.Z, 1.0);                                                // Z += R0^T (u0 - v)
 }
@@ -362,9 +450,9 @@ void op_h(awg_ctx& c, MultiWS& w, bool f32) {
   op_h2(c, w, f32);
   if (c.nminus == 0) return;
   const int b = w.b;
-  bmm(w.dWt, 1, c.nminus, b, c.n, true, 1.0, 0.0, b, c.s);               // H0 = W^T r
-  bmm(w.dEW, 1, c.nminus, b, c.nminus, false, 1.0, 0.0, b, c.s);         // H1 = E_W^{-1} H0
-  bmm(w.dW, 1, c.n, b, c.nminus, false, 1.0, 1.0, b, c.s);               // Z += W H1
+  bmm(w.dWt, 1, c.nminus, b, c.n, true, 1.0, 0.0, b, c.s, w.flW);               // H0 = W^T r
+  bmm(w.dEW, 1, c.nminus, b, c.nminus, false, 1.0, 0.0, b, c.s, w.flEW);         // H1 = E_W^{-1} H0
+  bmm(w.dW, 1, c.n, b, c.nminus, false, 1.0, 1.0, b, c.s, w.flW);               // Z += W H1
 }
 
 void sync(awg_ctx& c) { AWG_HIP(hipStreamSynchronize(c.s)); }
@@ -580,7 +668,9 @@ void phase_local(awg_ctx& c) {
       g[q] = GemmDesc{U.p + c.LV.eoff[q], c.V.p + c.LV.eoff[q], arena + c.sqoff[q], c.ns[q], c.ns[q], c.ks[q],
                       c.ns[q], c.ns[q], c.ns[q]};
     dg.upload(g, s);
-    if (maxk > 0) gemm_batched(dg, c.N, c.maxns, c.maxns, false, true, alpha, 1.0, false, s);
+    double fl = 0.0;
+    for (int q = 0; q < c.N; ++q) fl += 2.0 * c.ns[q] * (double)c.ns[q] * c.ks[q];
+    if (maxk > 0) gemm_batched(dg, c.N, c.maxns, c.maxns, false, true, alpha, 1.0, false, s, fl);
   };
   {
     PhaseTimer t(c, "local_factor");
@@ -783,11 +873,11 @@ void phase_EW(awg_ctx& c) {
   AW.alloc((long)c.n * c.nminus);
   EW.alloc((long)c.nminus * c.nminus);
   for (int c0 = 0; c0 < c.nminus; c0 += 32768)
-    l_spmm(c.n, c.rowptr, c.col, c.val, c.W.p + (long)c0 * c.n, c.n, AW.p + (long)c0 * c.n, c.n,
+    l_spmm(c.n, c.nnz, c.rowptr, c.col, c.val, c.W.p + (long)c0 * c.n, c.n, AW.p + (long)c0 * c.n, c.n,
            std::min(32768, c.nminus - c0), 1.0, 0.0, s);
   DBuf<GemmDesc> g;
   g.upload({GemmDesc{c.W.p, AW.p, EW.p, c.nminus, c.nminus, c.n, c.n, c.n, c.nminus}}, s);
-  gemm_batched(g, 1, c.nminus, c.nminus, true, false, 1.0, 0.0, false, s);
+  gemm_batched(g, 1, c.nminus, c.nminus, true, false, 1.0, 0.0, false, s, 2.0 * c.n * (double)c.nminus * c.nminus);
   spd_inverse(c, EW, c.nminus, c.EWinv, "second coarse matrix W^T A W");
 }
 
@@ -881,7 +971,7 @@ int do_pcg(awg_ctx& c, const double* b, double* x, double tol, int maxit, awg_pc
     const unsigned g = cdiv(n, 256);
     double hs[6];
     for (;;) {
-      l_spmm(n, c.rowptr, c.col, c.val, p, n, q, n, 1, 1.0, 0.0, s);
+      l_spmm(n, c.nnz, c.rowptr, c.col, c.val, p, n, q, n, 1, 1.0, 0.0, s);
       l_coldot(n, 1, p, n, q, n, sc + 1, s);
       hipLaunchKernelGGL(k_pcg_scalars, dim3(1), dim3(64), 0, s, sc, it, 0);
       hipLaunchKernelGGL(k_pcg_update_xr, dim3(g), dim3(256), 0, s, n, xx, w.R.p, p, q, sc);
@@ -907,7 +997,7 @@ int do_pcg(awg_ctx& c, const double* b, double* x, double tol, int maxit, awg_pc
   if (status == AWG_OK) {
     AWG_HIP(hipMemcpyAsync(x, xx, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
     // true residual
-    l_spmm(n, c.rowptr, c.col, c.val, xx, n, q, n, 1, -1.0, 0.0, s);
+    l_spmm(n, c.nnz, c.rowptr, c.col, c.val, xx, n, q, n, 1, -1.0, 0.0, s);
     l_colaxpby(n, 1, b, n, nullptr, q, n, nullptr, 1.0, 1.0, s);
     l_coldot(n, 1, q, n, q, n, sc + 7, s);
     std::vector<double> hist(16 + 2 * (size_t)std::max(maxit, 1));
@@ -1082,6 +1172,31 @@ int64_t awg_export(const awg_ctx* c, const char* name, void* buf, size_t cap) {
 }
 
 const char* awg_last_error(const awg_ctx* c) { return c ? c->err.c_str() : g_setup_error.c_str(); }
+
+int awg_kernel_timing(int32_t enable) {
+  try {
+    if (!enable) awg::ktimer_json(false);   // drain pending records
+  } catch (const Error& e) {
+    return e.code;
+  }
+  awg::ktimer_enable(enable != 0);
+  return AWG_OK;
+}
+
+int64_t awg_kernel_times(char* buf, size_t cap, int32_t reset) {
+  std::string js;
+  try {
+    js = awg::ktimer_json(reset != 0);
+  } catch (const Error& e) {
+    return e.code;
+  }
+  if (buf && cap) {
+    const size_t k = std::min(cap - 1, js.size());
+    std::memcpy(buf, js.data(), k);
+    buf[k] = '\0';
+  }
+  return (int64_t)js.size();
+}
 
 void awg_destroy(awg_ctx* c) {
   if (!c) return;

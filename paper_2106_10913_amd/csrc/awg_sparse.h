@@ -16,11 +16,11 @@ void l_pairs(int n, const int* rowptr, const int* col, const double* val, const 
 void l_pou(long tot, const int* sub_idx, const int* mult, double* dw, hipStream_t s);
 void l_extract(int N, const long* sub_ptr, const int* sub_idx, const int* rowptr, const int* col,
                const double* vals, const MatDesc* mats, hipStream_t s);
-void l_spmm(int n, const int* rowptr, const int* col, const double* val, const double* X, long ldx, double* Y,
-            long ldy, int b, double alpha, double beta, hipStream_t s);
+void l_spmm(int n, long nnz, const int* rowptr, const int* col, const double* val, const double* X, long ldx,
+            double* Y, long ldy, int b, double alpha, double beta, hipStream_t s);
 void l_gather(long tot, const int* sub_idx, const int* ent_sub, const long* sub_ptr, const double* X, long ldx,
               int b, const double* scale, double* Xs, hipStream_t s);
-void l_scatter(int n, const int* inv_ptr, const int* inv_sub, const int* inv_loc, const long* sub_ptr,
+void l_scatter(int n, long tot, const int* inv_ptr, const int* inv_sub, const int* inv_loc, const long* sub_ptr,
                const double* Zs, int b, const double* scale, double* Y, long ldy, double alpha, double beta,
                hipStream_t s);
 void l_coldot(int n, int b, const double* X, long ldx, const double* Y, long ldy, double* out, hipStream_t s);

@@ -7,6 +7,8 @@
 //                 factorisation, row-parallel panel solve, MFMA trailing update.
 //  * trsm       : blocked forward / backward substitution with many right-hand
 //                 sides: 64x64 diagonal solve in LDS + MFMA update of the rest.
+#include <algorithm>
+
 #include "awg_common.h"
 
 namespace awg {
@@ -155,10 +157,22 @@ __global__ __launch_bounds__(256) void k_gemm(DF df, double alpha, double beta, 
 }
 
 template <class DF>
+static const char* gemm_name(bool tA, bool tB);
+template <>
+const char* gemm_name<DescArray>(bool tA, bool tB) {
+  return tA ? (tB ? "k_gemm<DescArray,T,T>" : "k_gemm<DescArray,T,N>") : (tB ? "k_gemm<DescArray,N,T>" : "k_gemm<DescArray,N,N>");
+}
+template <>
+const char* gemm_name<CholUpdate>(bool, bool) { return "k_gemm<CholUpdate,N,T>"; }
+template <>
+const char* gemm_name<TrsmUpdate>(bool tA, bool) { return tA ? "k_gemm<TrsmUpdate,T,N>" : "k_gemm<TrsmUpdate,N,N>"; }
+
+template <class DF>
 static void launch_gemm(DF df, int batch, int max_m, int max_n, bool tA, bool tB, double alpha, double beta,
-                        bool lower, hipStream_t s) {
+                        bool lower, hipStream_t s, double flops = 0.0) {
   if (batch <= 0 || max_m <= 0 || max_n <= 0) return;
   dim3 grid(cdiv(max_m, 64), cdiv(max_n, 64), batch);
+  KScope kt(gemm_name<DF>(tA, tB), s, 0.0, flops);
   if (!tA && !tB) hipLaunchKernelGGL((k_gemm<DF, false, false>), grid, dim3(256), 0, s, df, alpha, beta, (int)lower);
   else if (tA && !tB) hipLaunchKernelGGL((k_gemm<DF, true, false>), grid, dim3(256), 0, s, df, alpha, beta, (int)lower);
   else if (!tA && tB) hipLaunchKernelGGL((k_gemm<DF, false, true>), grid, dim3(256), 0, s, df, alpha, beta, (int)lower);
@@ -167,8 +181,8 @@ static void launch_gemm(DF df, int batch, int max_m, int max_n, bool tA, bool tB
 }
 
 void gemm_batched(const GemmDesc* d_desc, int batch, int max_m, int max_n, bool transA, bool transB,
-                  double alpha, double beta, bool lower, hipStream_t s) {
-  launch_gemm(DescArray{d_desc}, batch, max_m, max_n, transA, transB, alpha, beta, lower, s);
+                  double alpha, double beta, bool lower, hipStream_t s, double flops) {
+  launch_gemm(DescArray{d_desc}, batch, max_m, max_n, transA, transB, alpha, beta, lower, s, flops);
 }
 
 // ---------------------------------------------------------------------------
@@ -220,8 +234,9 @@ __global__ __launch_bounds__(256) void k_gemv_t(const GemmDesc* descs, double al
 }
 
 void gemv_batched(const GemmDesc* d_desc, int batch, int max_m, int max_k, bool transA, double alpha,
-                  double beta, hipStream_t s) {
+                  double beta, hipStream_t s, double bytes) {
   if (batch <= 0) return;
+  KScope kt(transA ? "k_gemv_t" : "k_gemv_n", s, bytes, bytes / 4.0);
   if (!transA) {
     if (max_m <= 0) return;
     hipLaunchKernelGGL(k_gemv_n, dim3(cdiv(max_m, 64), batch), dim3(256), 0, s, d_desc, alpha, beta);
@@ -316,7 +331,13 @@ void potrf_batched(const MatDesc* d_mats, const std::vector<int>& h_n, int* d_in
     if (rem <= 0) break;
     hipLaunchKernelGGL(k_chol_panel, dim3(cdiv(rem, 256), batch), dim3(256), 0, s, d_mats, j);
     AWG_LAUNCH_CHECK();
-    launch_gemm(CholUpdate{d_mats, j, CHOL_NB}, batch, rem, rem, false, true, -1.0, 1.0, true, s);
+    double fl = 0.0;
+    if (ktimer_on())
+      for (int v : h_n) {
+        const double r = v - j - CHOL_NB;
+        if (r > 0) fl += r * r * CHOL_NB;      // lower triangle of the rank-32 update
+      }
+    launch_gemm(CholUpdate{d_mats, j, CHOL_NB}, batch, rem, rem, false, true, -1.0, 1.0, true, s, fl);
   }
 }
 
@@ -378,8 +399,17 @@ void trsm_batched(const MatDesc* d_L, const MatDesc* d_B, const std::vector<int>
     hipLaunchKernelGGL(k_trsm_diag, dim3(cdiv(maxc, 64), batch), dim3(64), 0, s, d_L, d_B, j, (int)trans);
     AWG_LAUNCH_CHECK();
     const int mrows = trans ? j : maxn - j - TRSM_NB;
+    double fl = 0.0;
+    if (ktimer_on())
+      for (size_t b = 0; b < h_n.size(); ++b) {
+        const int jb = std::min(TRSM_NB, h_n[b] - j);
+        if (jb <= 0) continue;
+        const double m = trans ? j : h_n[b] - j - jb;
+        fl += 2.0 * m * h_ncols[b] * jb;
+      }
     if (mrows > 0)
-      launch_gemm(TrsmUpdate{d_L, d_B, j, TRSM_NB, trans}, batch, mrows, maxc, trans, false, -1.0, 1.0, false, s);
+      launch_gemm(TrsmUpdate{d_L, d_B, j, TRSM_NB, trans}, batch, mrows, maxc, trans, false, -1.0, 1.0, false, s,
+                  fl);
   }
 }
 

@@ -186,6 +186,13 @@ void sytrd_batched(const MatDesc* d_mats, const std::vector<int>& h_n, double* d
     AWG_LAUNCH_CHECK();
     if (k <= maxn - 3) {
       const int rows = maxn - k - 1;
+      double tb = 0.0;
+      if (ktimer_on())
+        for (int nb : h_n) {
+          const double r = nb - k - 1;
+          if (nb - k - 3 >= 0) tb += r * r * (k > 0 ? 16.0 : 8.0);
+        }
+      KScope kt("k_trd_upd", s, tb, tb / 8.0 * (k > 0 ? 3.0 : 2.0));
       hipLaunchKernelGGL(k_trd_upd, dim3(cdiv(rows, TRD_ROWS), batch), dim3(256), 0, s, d_mats, k, d_off, work);
       AWG_LAUNCH_CHECK();
       hipLaunchKernelGGL(k_trd_w, dim3(batch), dim3(256), 0, s, d_mats, k, tau, d_off, work);

@@ -440,9 +440,12 @@ void l_extract(int N, const long* sub_ptr, const int* sub_idx, const int* rowptr
   hipLaunchKernelGGL(k_extract, dim3(N), dim3(256), 0, s, sub_ptr, sub_idx, rowptr, col, vals, mats);
   AWG_LAUNCH_CHECK();
 }
-void l_spmm(int n, const int* rowptr, const int* col, const double* val, const double* X, long ldx, double* Y,
-            long ldy, int b, double alpha, double beta, hipStream_t s) {
+void l_spmm(int n, long nnz, const int* rowptr, const int* col, const double* val, const double* X, long ldx,
+            double* Y, long ldy, int b, double alpha, double beta, hipStream_t s) {
   if (n == 0 || b == 0) return;
+  KScope kt("k_spmm", s,
+            12.0 * nnz + 4.0 * (n + 1) + 16.0 * n * (double)b + (beta != 0.0 ? 8.0 * n * (double)b : 0.0),
+            2.0 * nnz * (double)b);
   hipLaunchKernelGGL(k_spmm, dim3(grid1(n), cdiv(b, SPMM_CB)), dim3(256), 0, s, n, rowptr, col, val, X, ldx, Y, ldy, b,
                      alpha, beta);
   AWG_LAUNCH_CHECK();
@@ -450,14 +453,17 @@ void l_spmm(int n, const int* rowptr, const int* col, const double* val, const d
 void l_gather(long tot, const int* sub_idx, const int* ent_sub, const long* sub_ptr, const double* X, long ldx,
               int b, const double* scale, double* Xs, hipStream_t s) {
   if (tot == 0 || b == 0) return;
+  KScope kt("k_gather", s, 8.0 * tot * (double)b + 8.0 * tot + 8.0 * (double)tot * b, 0.0);
   hipLaunchKernelGGL(k_gather, dim3(grid1(tot), b), dim3(256), 0, s, tot, sub_idx, ent_sub, sub_ptr, X, ldx, b,
                      scale, Xs);
   AWG_LAUNCH_CHECK();
 }
-void l_scatter(int n, const int* inv_ptr, const int* inv_sub, const int* inv_loc, const long* sub_ptr,
+void l_scatter(int n, long tot, const int* inv_ptr, const int* inv_sub, const int* inv_loc, const long* sub_ptr,
                const double* Zs, int b, const double* scale, double* Y, long ldy, double alpha, double beta,
                hipStream_t s) {
   if (n == 0 || b == 0) return;
+  KScope kt("k_scatter", s, 8.0 * (double)tot * b + 8.0 * tot + 4.0 * n + 8.0 * n * (double)b * (beta != 0.0 ? 2.0 : 1.0),
+            (double)tot * b);
   hipLaunchKernelGGL(k_scatter, dim3(grid1(n), b), dim3(256), 0, s, n, inv_ptr, inv_sub, inv_loc, sub_ptr, Zs, b,
                      scale, Y, ldy, alpha, beta);
   AWG_LAUNCH_CHECK();
