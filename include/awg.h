@@ -65,7 +65,8 @@ typedef struct {
   double zero_tol;     /* eps0: an eigenvalue lambda of B^s is non-positive when
                           lambda <= eps0 * max|lambda(B^s)|; default 1e-12 */
   double w_rtol;       /* relative residual tolerance of the PCG solves with A_+
-                          that build W (Remark 2, Section 4.4); default 1e-12 */
+                          that build W (Remark 2, Section 4.4); default 1e-10,
+                          the value of the paper's experiments (Section 5) */
   int32_t w_maxit;     /* iteration cap of those solves; default 500 */
   int32_t local_prec;  /* AWG_LOCAL_F64 (default) or AWG_LOCAL_F32: storage and
                           arithmetic of the per-iteration local solves */

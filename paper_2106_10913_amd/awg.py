@@ -120,7 +120,7 @@ class Solver:
     (sub_ptr int64, sub_idx int32) of device tensors.
     """
 
-    def __init__(self, A, subs, tau: float = 0.1, local_prec: str = "f64", w_rtol: float = 1e-12,
+    def __init__(self, A, subs, tau: float = 0.1, local_prec: str = "f64", w_rtol: float = 1e-10,
                  w_maxit: int = 500, zero_tol: float = 1e-12, device: str = "cuda"):
         import torch
         L = lib()

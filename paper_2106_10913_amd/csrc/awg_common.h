@@ -127,8 +127,15 @@ void potrf_batched(const MatDesc* d_mats, const std::vector<int>& h_n, int* d_in
 void trsm_batched(const MatDesc* d_L, const MatDesc* d_B, const std::vector<int>& h_n,
                   const std::vector<int>& h_ncols, bool trans, hipStream_t s, GemmDesc* d_scratch_desc);
 
+// A[r0:, r0:] -= V W^T + W V^T for the panel at p0 of the blocked
+// tridiagonalisation (two MFMA products; see k_eig.hip)
+void syr2k_panel_update(const MatDesc* d_mats, const double* V, const double* W, const long* d_off, int p0, int nbw,
+                        int max_rem, int batch, hipStream_t s, double flops);
 // Householder tridiagonalisation of symmetric blocks (full storage,
 // destroyed).  d, e, tau: per-block arrays at offsets off[b] (size n_b).
+// work: TRD_WORK_PER_ROW * n_b doubles per block at off[b] * TRD_WORK_PER_ROW.
+constexpr int TRD_NB = 32;
+constexpr long TRD_WORK_PER_ROW = 2 * TRD_NB + 2;
 void sytrd_batched(const MatDesc* d_mats, const std::vector<int>& h_n, double* d, double* e,
                    double* tau, const long* d_off, double* work, hipStream_t s);
 // Eigenvalues < thr of the tridiagonal T_b: count, values and eigenvectors.

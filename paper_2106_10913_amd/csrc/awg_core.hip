@@ -131,14 +131,16 @@ struct ColLayout {
 
 }  // namespace
 
-// workspace for applying the operators to b columns at once
+// workspace for applying the operators to b columns at once; every n x b,
+// sum_s n_s x b, k x b array is row-major (the b values of a row contiguous)
 struct MultiWS {
   int b = 0;
   DBuf<double> R, Z, T1, T2;          // n x b
-  DBuf<double> Xs, Os;                // sum n_s x b (per-subdomain blocks)
+  DBuf<double> Xs, Os;                // sum n_s x b (restricted rows, subdomain order)
   DBuf<double> Tk;                    // sum k_s x b
   DBuf<double> G0, G1, G2;            // n0 x b
   DBuf<double> H0, H1;                // n_minus x b
+  DBuf<double> dotpart, dots;         // column dot products
   DBuf<GemmDesc> dVt, dV, dYt, dY, dP, dE0a, dE0b, dWt, dEW, dW;
   int maxk = 0, maxm = 0, maxns = 0;
   double flV = 0, flY = 0, flP = 0, flE0 = 0, flW = 0, flEW = 0;   // algorithmic flops per product
@@ -187,36 +189,35 @@ namespace {
 // ---------------------------------------------------------------------------
 // small device kernels used only here
 // ---------------------------------------------------------------------------
-__global__ void k_scale_rows_blocks(double* T, const long* coff, const double* lam, int N, int b) {
-  // T: concatenation of k_s x b blocks at coff[s]*b; row r of block s scaled by |lam[coff[s]+r]|
-  const int s = blockIdx.y;
-  const long a = coff[s], ks = coff[s + 1] - a;
-  const long tot = ks * b;
-  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += (long)gridDim.x * blockDim.x) {
-    const long r = e % ks;
-    T[a * b + e] *= fabs(lam[a + r]);
-  }
+// rows of the k_s x b blocks of T (V^T X) scaled by |lambda|: row r of
+// block s is row coff[s] + r of the row-major concatenation
+__global__ void k_scale_rows(double* T, const double* lam, long rows, int b) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= rows * b) return;
+  T[e] *= fabs(lam[e / b]);
 }
 
+// G (n0 x b, row-major) = columns c0 .. c0+b-1 of the identity
 __global__ void k_identity_cols(double* G, int n0, int b, int c0) {
-  const long tot = (long)n0 * b;
-  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += (long)gridDim.x * blockDim.x) {
-    const int r = (int)(e % n0), c = (int)(e / n0);
-    G[e] = (r == c0 + c) ? 1.0 : 0.0;
-  }
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long)n0 * b) return;
+  const int r = (int)(e / b), c = (int)(e % b);
+  G[e] = (r == c0 + c) ? 1.0 : 0.0;
 }
 
-__global__ void k_copy_cols(const double* src, long lds, double* dst, long ldd, int m, int b) {
-  const long tot = (long)m * b;
-  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += (long)gridDim.x * blockDim.x) {
-    const int r = (int)(e % m), c = (int)(e / m);
-    dst[r + c * ldd] = src[r + c * lds];
-  }
+// dst[r * ldd + c0 + c] = src[r * b + c] for c < bc (row-major column block copy)
+__global__ void k_copy_cols(const double* src, int b, double* dst, long ldd, long rows, int c0, int bc) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= rows * bc) return;
+  const long r = e / bc;
+  const int c = (int)(e % bc);
+  dst[r * ldd + c0 + c] = src[r * b + c];
 }
 
-// prolongated strictly negative eigenvectors: Vg[:, off_s + j] = R^sT V^s[:, j], j < kstrict_s
+// right-hand sides of W, row-major n x b: column gc = g0_s + j - c0 holds
+// R^sT V^s[:, j] for the strictly negative pairs j < kstrict_s
 __global__ void k_build_vg(const long* sub_ptr, const int* sub_idx, const double* V, const long* veoff,
-                           const long* gcoff, int N, double* Vg, long ldv, int c0, int b) {
+                           const long* gcoff, double* Vg, int c0, int b) {
   const int s = blockIdx.y;
   const long a = sub_ptr[s], ns = sub_ptr[s + 1] - a;
   const long g0 = gcoff[s], kst = gcoff[s + 1] - g0;
@@ -225,7 +226,7 @@ __global__ void k_build_vg(const long* sub_ptr, const int* sub_idx, const double
     const long l = e % ns, j = e / ns;
     const long gc = g0 + j - c0;
     if (gc < 0 || gc >= b) continue;
-    Vg[sub_idx[a + l] + gc * ldv] = V[veoff[s] + l + j * ns];
+    Vg[(long)sub_idx[a + l] * b + gc] = V[veoff[s] + l + j * ns];
   }
 }
 
@@ -308,12 +309,22 @@ std::vector<MatDesc> col_descs(const awg_ctx& c, double* base, const ColLayout& 
   return v;
 }
 
+// Products of b row-major columns by a matrix M.  With X^T the b x k
+// column-major view of a row-major k x b array X, every product of the
+// method is written  Y^T = X^T op(M)  (op = identity or transpose): a GEMM
+// with the column count b as its M dimension.  For b = 1 it is the GEMV
+// y = op(M)^T x.
+GemmDesc mk(const double* X, const double* M, int ldm, double* Y, int nout, int k, bool transM, int b) {
+  if (b > 1) return GemmDesc{X, M, Y, b, nout, k, b, ldm, b};
+  return GemmDesc{M, X, Y, nout, 1, k, ldm, 1, 1};
+}
+
 // flops: algorithmic flops of the whole batched product (2 m n k summed)
-void bmm(const DBuf<GemmDesc>& d, int batch, int maxm, int maxn, int maxk, bool tA, double alpha, double beta,
-         int b, hipStream_t s, double flops) {
+void bmm(const DBuf<GemmDesc>& d, int batch, int maxout, int maxk, bool transM, double alpha, double beta, int b,
+         hipStream_t s, double flops) {
   if (batch == 0) return;
-  if (b == 1) gemv_batched(d, batch, maxm, maxk, tA, alpha, beta, s, 4.0 * flops);
-  else gemm_batched(d, batch, maxm, maxn, tA, false, alpha, beta, false, s, flops);
+  if (b == 1) gemv_batched(d, batch, maxout, maxk, !transM, alpha, beta, s, 4.0 * flops);
+  else gemm_batched(d, batch, b, maxout, false, transM, alpha, beta, false, s, flops);
 }
 
 void gemm_upload(DBuf<GemmDesc>& d, const std::vector<GemmDesc>& h, hipStream_t s) { d.upload(h, s); }
@@ -335,24 +346,29 @@ void build_ws(awg_ctx& c, MultiWS& w, int b) {
   w.G2.alloc(std::max(1, c.n0) * (long)b);
   w.H0.alloc(std::max(1, c.nminus) * (long)b);
   w.H1.alloc(std::max(1, c.nminus) * (long)b);
+  w.dotpart.alloc((long)DOT_CHUNKS_H * b);
+  w.dots.alloc(2L * b);
   std::vector<GemmDesc> vt(c.N), vv(c.N), yt(c.N), yy(c.N), pp(c.N);
   w.maxk = w.maxm = w.maxns = 0;
   w.flV = w.flY = w.flP = 0;
   for (int q = 0; q < c.N; ++q) {
     const int nsq = c.ns[q];
-    w.flV += 2.0 * nsq * c.ks[q] * b;
-    w.flY += 2.0 * nsq * c.ms[q] * b;
-    w.flP += 2.0 * nsq * (double)nsq * b;
     const long so = c.h_subptr[q] * b;
     const int kq = c.ks[q], mq = c.ms[q];
+    w.flV += 2.0 * nsq * kq * b;
+    w.flY += 2.0 * nsq * mq * b;
+    w.flP += 2.0 * nsq * (double)nsq * b;
     w.maxk = std::max(w.maxk, kq);
     w.maxm = std::max(w.maxm, mq);
     w.maxns = std::max(w.maxns, nsq);
-    vt[q] = GemmDesc{c.V + c.LV.eoff[q], w.Xs + so, w.Tk + c.LV.coff[q] * b, kq, b, nsq, nsq, nsq, std::max(1, kq)};
-    vv[q] = GemmDesc{c.V + c.LV.eoff[q], w.Tk + c.LV.coff[q] * b, w.Os + so, nsq, b, kq, nsq, std::max(1, kq), nsq};
-    yt[q] = GemmDesc{c.Y + c.LY.eoff[q], w.Xs + so, w.G0 + c.LY.coff[q], mq, b, nsq, nsq, nsq, std::max(1, c.n0)};
-    yy[q] = GemmDesc{c.Y + c.LY.eoff[q], w.G1 + c.LY.coff[q], w.Os + so, nsq, b, mq, nsq, std::max(1, c.n0), nsq};
-    pp[q] = GemmDesc{c.P + c.sqoff[q], w.Xs + so, w.Os + so, nsq, b, nsq, nsq, nsq, nsq};
+    const double* Vq = c.V.p + c.LV.eoff[q];
+    const double* Yq = c.Y.p + c.LY.eoff[q];
+    // T_q = V_q^T X_q ;  O_q = V_q T_q ;  G0_q = Y_q^T X_q ;  O_q = Y_q G1_q ;  O_q = P_q X_q
+    vt[q] = mk(w.Xs.p + so, Vq, nsq, w.Tk.p + c.LV.coff[q] * b, kq, nsq, false, b);
+    vv[q] = mk(w.Tk.p + c.LV.coff[q] * b, Vq, nsq, w.Os.p + so, nsq, kq, true, b);
+    yt[q] = mk(w.Xs.p + so, Yq, nsq, w.G0.p + c.LY.coff[q] * b, mq, nsq, false, b);
+    yy[q] = mk(w.G1.p + c.LY.coff[q] * b, Yq, nsq, w.Os.p + so, nsq, mq, true, b);
+    pp[q] = mk(w.Xs.p + so, c.P.p + c.sqoff[q], nsq, w.Os.p + so, nsq, nsq, false, b);
   }
   gemm_upload(w.dVt, vt, s);
   gemm_upload(w.dV, vv, s);
@@ -363,11 +379,12 @@ void build_ws(awg_ctx& c, MultiWS& w, int b) {
   w.flE0 = 2.0 * c.n0 * (double)c.n0 * b;
   w.flW = 2.0 * c.n * (double)c.nminus * b;
   w.flEW = 2.0 * c.nminus * (double)c.nminus * b;
-  gemm_upload(w.dE0a, {GemmDesc{c.E0inv, w.G0, w.G1, c.n0, b, c.n0, n0, n0, n0}}, s);
-  gemm_upload(w.dE0b, {GemmDesc{c.E0inv, w.G0, w.G2, c.n0, b, c.n0, n0, n0, n0}}, s);
-  gemm_upload(w.dWt, {GemmDesc{c.W, w.R, w.H0, c.nminus, b, c.n, c.n, c.n, nm}}, s);
-  gemm_upload(w.dEW, {GemmDesc{c.EWinv, w.H0, w.H1, c.nminus, b, c.nminus, nm, nm, nm}}, s);
-  gemm_upload(w.dW, {GemmDesc{c.W, w.H1, w.Z, c.n, b, c.nminus, c.n, nm, c.n}}, s);
+  // E0inv and EWinv are symmetric; W is stored row-major (n_minus values per dof)
+  gemm_upload(w.dE0a, {mk(w.G0, c.E0inv, n0, w.G1, c.n0, c.n0, false, b)}, s);
+  gemm_upload(w.dE0b, {mk(w.G0, c.E0inv, n0, w.G2, c.n0, c.n0, false, b)}, s);
+  gemm_upload(w.dWt, {mk(w.R, c.W, nm, w.H0, c.nminus, c.n, true, b)}, s);
+  gemm_upload(w.dEW, {mk(w.H0, c.EWinv, nm, w.H1, c.nminus, c.nminus, false, b)}, s);
+  gemm_upload(w.dW, {mk(w.H1, c.W, nm, w.Z, c.n, c.nminus, false, b)}, s);
 }
 
 // Y = beta Y + A_- X   (A_- = sum_s R^sT V^s |L^s_-| V^sT R^s; Definition of A_-, Section 3.2)
@@ -377,43 +394,44 @@ void op_aminus(awg_ctx& c, MultiWS& w, const double* X, double* Yo, double beta)
     if (beta == 0.0) AWG_HIP(hipMemsetAsync(Yo, 0, sizeof(double) * c.n * (size_t)b, c.s));
     return;
   }
-  l_gather(c.sumns, c.subidx, c.entsub, c.subptr, X, c.n, b, nullptr, w.Xs, c.s);
-  bmm(w.dVt, c.N, w.maxk, b, w.maxns, true, 1.0, 0.0, b, c.s, w.flV);
-  hipLaunchKernelGGL(k_scale_rows_blocks, dim3(64, c.N), dim3(256), 0, c.s, w.Tk.p, c.LV.d_coff.p, c.lamV.p, c.N, b);
+  l_gather(c.sumns, c.subidx, X, b, w.Xs, c.s);
+  bmm(w.dVt, c.N, w.maxk, w.maxns, false, 1.0, 0.0, b, c.s, w.flV);
+  hipLaunchKernelGGL(k_scale_rows, dim3(cdiv(c.LV.cols * b, 256)), dim3(256), 0, c.s, w.Tk.p, c.lamV.p,
+                     (long)c.LV.cols, b);
   AWG_LAUNCH_CHECK();
-  bmm(w.dV, c.N, w.maxns, b, w.maxk, false, 1.0, 0.0, b, c.s, w.flV);
-  l_scatter(c.n, c.sumns, c.invptr, c.invsub, c.invloc, c.subptr, w.Os, b, nullptr, Yo, c.n, 1.0, beta, c.s);
+  bmm(w.dV, c.N, w.maxns, w.maxk, true, 1.0, 0.0, b, c.s, w.flV);
+  l_scatter(c.n, c.sumns, c.invptr, c.invsub, c.invloc, c.subptr, w.Os, b, Yo, 1.0, beta, c.s);
 }
 
 // Y = A_+ X = A X + A_- X (item (i) of the A_+ theorem, Section 3.2)
 void op_aplus(awg_ctx& c, MultiWS& w, const double* X, double* Yo) {
-  l_spmm(c.n, c.nnz, c.rowptr, c.col, c.val, X, c.n, Yo, c.n, w.b, 1.0, 0.0, c.s);
+  l_spmm(c.n, c.nnz, c.rowptr, c.col, c.val, X, Yo, w.b, 1.0, 0.0, c.s);
   op_aminus(c, w, X, Yo, 1.0);
 }
 
 // G0 = R0 X  (R0^T = [R^1T Y^1 | ... | R^NT Y^N])
 void op_r0(awg_ctx& c, MultiWS& w, const double* X) {
-  l_gather(c.sumns, c.subidx, c.entsub, c.subptr, X, c.n, w.b, nullptr, w.Xs, c.s);
-  bmm(w.dYt, c.N, w.maxm, w.b, w.maxns, true, 1.0, 0.0, w.b, c.s, w.flY);
+  l_gather(c.sumns, c.subidx, X, w.b, w.Xs, c.s);
+  bmm(w.dYt, c.N, w.maxm, w.maxns, false, 1.0, 0.0, w.b, c.s, w.flY);
 }
 
 // Yo = beta Yo + R0^T G1
 void op_r0t(awg_ctx& c, MultiWS& w, double* Yo, double beta) {
-  bmm(w.dY, c.N, w.maxns, w.b, w.maxm, false, 1.0, 0.0, w.b, c.s, w.flY);
-  l_scatter(c.n, c.sumns, c.invptr, c.invsub, c.invloc, c.subptr, w.Os, w.b, nullptr, Yo, c.n, 1.0, beta, c.s);
+  bmm(w.dY, c.N, w.maxns, w.maxm, true, 1.0, 0.0, w.b, c.s, w.flY);
+  l_scatter(c.n, c.sumns, c.invptr, c.invsub, c.invloc, c.subptr, w.Os, w.b, Yo, 1.0, beta, c.s);
 }
 
 // Yo = H^NN X = sum_s R^sT P^s R^s X with P^s = D^s (A^s_+)^+ D^s (Definition of H^NN, Section 3.3)
 void op_hnn(awg_ctx& c, MultiWS& w, const double* X, double* Yo, bool f32) {
-  l_gather(c.sumns, c.subidx, c.entsub, c.subptr, X, c.n, w.b, nullptr, w.Xs, c.s);
+  l_gather(c.sumns, c.subidx, X, w.b, w.Xs, c.s);
   if (f32 && w.b == 1) {
     hipLaunchKernelGGL(k_gemv_f32, dim3(cdiv(w.maxns, 64), c.N), dim3(256), 0, c.s, c.P32.p, c.d_sqoff.p,
                        c.subptr.p, w.Xs.p, w.Os.p);
     AWG_LAUNCH_CHECK();
   } else {
-    bmm(w.dP, c.N, w.maxns, w.b, w.maxns, false, 1.0, 0.0, w.b, c.s, w.flP);
+    bmm(w.dP, c.N, w.maxns, w.maxns, false, 1.0, 0.0, w.b, c.s, w.flP);
   }
-  l_scatter(c.n, c.sumns, c.invptr, c.invsub, c.invloc, c.subptr, w.Os, w.b, nullptr, Yo, c.n, 1.0, 0.0, c.s);
+  l_scatter(c.n, c.sumns, c.invptr, c.invsub, c.invloc, c.subptr, w.Os, w.b, Yo, 1.0, 0.0, c.s);
 }
 
 }  // namespace
@@ -433,15 +451,15 @@ void op_h2(awg_ctx& c, MultiWS& w, bool f32) {
     return;
   }
   op_r0(c, w, w.R);                                                      // G0 = R0 r
-  bmm(w.dE0a, 1, c.n0, b, c.n0, false, 1.0, 0.0, b, c.s, w.flE0);                // G1 = u0
+  bmm(w.dE0a, 1, c.n0, c.n0, false, 1.0, 0.0, b, c.s, w.flE0);           // G1 = u0
   op_r0t(c, w, w.T1, 0.0);                                               // T1 = R0^T u0
   op_aplus(c, w, w.T1, w.T2);                                            // T2 = A_+ R0^T u0
-  l_colaxpby(c.n, b, w.R, c.n, nullptr, w.T2, c.n, nullptr, 1.0, -1.0, c.s);  // T2 = r - T2
+  l_colaxpby(c.n, b, w.R, nullptr, w.T2, nullptr, 1.0, -1.0, c.s);       // T2 = r - T2
   op_hnn(c, w, w.T2, w.Z, f32);                                          // Z = y
   op_aplus(c, w, w.Z, w.T1);                                             // T1 = A_+ y
   op_r0(c, w, w.T1);                                                     // G0 = R0 A_+ y
-  bmm(w.dE0b, 1, c.n0, b, c.n0, false, 1.0, 0.0, b, c.s, w.flE0);                // G2 = v
-  l_colaxpby(c.n0, b, w.G2, c.n0, nullptr, w.G1, c.n0, nullptr, -1.0, 1.0, c.s);  // G1 = u0 - v
+  bmm(w.dE0b, 1, c.n0, c.n0, false, 1.0, 0.0, b, c.s, w.flE0);           // G2 = v
+  l_colaxpby(c.n0, b, w.G2, nullptr, w.G1, nullptr, -1.0, 1.0, c.s);     // G1 = u0 - v
   op_r0t(c, w, w.Z, 1.0);                                                // Z += R0^T (u0 - v)
 }
 
@@ -450,9 +468,9 @@ void op_h(awg_ctx& c, MultiWS& w, bool f32) {
   op_h2(c, w, f32);
   if (c.nminus == 0) return;
   const int b = w.b;
-  bmm(w.dWt, 1, c.nminus, b, c.n, true, 1.0, 0.0, b, c.s, w.flW);               // H0 = W^T r
-  bmm(w.dEW, 1, c.nminus, b, c.nminus, false, 1.0, 0.0, b, c.s, w.flEW);         // H1 = E_W^{-1} H0
-  bmm(w.dW, 1, c.n, b, c.nminus, false, 1.0, 1.0, b, c.s, w.flW);               // Z += W H1
+  bmm(w.dWt, 1, c.nminus, c.n, true, 1.0, 0.0, b, c.s, w.flW);           // H0 = W^T r
+  bmm(w.dEW, 1, c.nminus, c.nminus, false, 1.0, 0.0, b, c.s, w.flEW);    // H1 = E_W^{-1} H0
+  bmm(w.dW, 1, c.n, c.nminus, false, 1.0, 1.0, b, c.s, w.flW);           // Z += W H1
 }
 
 void sync(awg_ctx& c) { AWG_HIP(hipStreamSynchronize(c.s)); }
@@ -755,32 +773,41 @@ void spd_inverse(awg_ctx& c, double* M, int n, DBuf<double>& Minv, const char* w
   l_scale_sym(di, 1, nullptr, nullptr, false, true, s);
 }
 
+// number of columns per pass: at most cap, balanced over the passes
+int balanced_chunk(int total, int cap) {
+  const int passes = (total + cap - 1) / cap;
+  return (total + passes - 1) / passes;
+}
+
 // E0 = R0 A_+ R0^T and its inverse (Theorem on H^NN_hyb, Section 3.4)
 void phase_coarse0(awg_ctx& c) {
   PhaseTimer t(c, "coarse0");
   if (c.n0 == 0) return;
   hipStream_t s = c.s;
-  const int b = std::min(c.n0, 512);
+  const int b = balanced_chunk(c.n0, 2048);
   MultiWS w;
   build_ws(c, w, b);
   DBuf<double> E0;
   E0.alloc((long)c.n0 * c.n0);
   for (int c0 = 0; c0 < c.n0; c0 += b) {
     const int bc = std::min(b, c.n0 - c0);
-    hipLaunchKernelGGL(k_identity_cols, dim3(256), dim3(256), 0, s, w.G1.p, c.n0, b, c0);
+    hipLaunchKernelGGL(k_identity_cols, dim3(cdiv((long)c.n0 * b, 256)), dim3(256), 0, s, w.G1.p, c.n0, b, c0);
     AWG_LAUNCH_CHECK();
     op_r0t(c, w, w.T1, 0.0);          // R0^T e_j
     op_aplus(c, w, w.T1, w.T2);       // A_+ R0^T e_j
-    op_r0(c, w, w.T2);                // R0 A_+ R0^T e_j  -> G0
-    hipLaunchKernelGGL(k_copy_cols, dim3(256), dim3(256), 0, s, w.G0.p, (long)c.n0, E0.p + (long)c0 * c.n0,
-                       (long)c.n0, c.n0, bc);
+    op_r0(c, w, w.T2);                // R0 A_+ R0^T e_j  -> G0 (n0 x b)
+    // E0 is symmetric: row r of G0 holds E0[r, c0 + c]; store as column-major E0 rows
+    hipLaunchKernelGGL(k_copy_cols, dim3(cdiv((long)c.n0 * bc, 256)), dim3(256), 0, s, w.G0.p, b, E0.p,
+                       (long)c.n0, (long)c.n0, c0, bc);
     AWG_LAUNCH_CHECK();
   }
   spd_inverse(c, E0, c.n0, c.E0inv, "coarse matrix E0");
 }
 
 // W = A_+^{-1} [R^1T V^1_- | ... ] (strictly negative pairs; Remark 1 and 2,
-// Section 4.4) by PCG on A_+ preconditioned with H2, all columns side by side.
+// Section 4.4) by PCG on A_+ preconditioned with H2, all columns side by
+// side, each with its own recurrence and stopping test.  W is stored
+// row-major: the n_minus values of a dof are contiguous.
 void phase_W(awg_ctx& c) {
   PhaseTimer t(c, "second_coarse_W");
   c.nminus = 0;
@@ -792,51 +819,54 @@ void phase_W(awg_ctx& c) {
   DBuf<long> dgcoff;
   dgcoff.upload(gcoff, s);
   c.W.alloc((long)c.n * c.nminus);
-  const int b = std::min(c.nminus, 1024);
+  const int b = balanced_chunk(c.nminus, 2048);
   MultiWS w;
   build_ws(c, w, b);
-  DBuf<double> X, Pm, Q, dots;
+  DBuf<double> X, Pm, Q;
   X.alloc((long)c.n * b);
   Pm.alloc((long)c.n * b);
   Q.alloc((long)c.n * b);
-  dots.alloc(2 * b);
+  double* dots = w.dots.p;
   DBuf<double> alpha_d;
   alpha_d.alloc(b);
   std::vector<double> bn(b), rz(b), alpha(b), beta(b);
   std::vector<char> active(b);
   int itmax = 0;
+  auto coldot = [&](const double* A, const double* B) {
+    l_coldot(c.n, b, A, B, w.dotpart, dots, s);
+    std::vector<double> h(b);
+    AWG_HIP(hipMemcpyAsync(h.data(), dots, sizeof(double) * b, hipMemcpyDeviceToHost, s));
+    AWG_HIP(hipStreamSynchronize(s));
+    return h;
+  };
   for (int c0 = 0; c0 < c.nminus; c0 += b) {
     const int bc = std::min(b, c.nminus - c0);
     w.R.zero(s);
     hipLaunchKernelGGL(k_build_vg, dim3(64, c.N), dim3(256), 0, s, c.subptr.p, c.subidx.p, c.V.p, c.LV.d_eoff.p,
-                       dgcoff.p, c.N, w.R.p, (long)c.n, c0, b);
+                       dgcoff.p, w.R.p, c0, b);
     AWG_LAUNCH_CHECK();
     X.zero(s);
-    l_coldot(c.n, b, w.R, c.n, w.R, c.n, dots, s);
-    auto h = dots.download(s, b);
+    auto h = coldot(w.R, w.R);
     for (int j = 0; j < b; ++j) {
       bn[j] = std::sqrt(h[j]);
       active[j] = (j < bc && bn[j] > 0.0) ? 1 : 0;
     }
     op_h2(c, w, false);
     AWG_HIP(hipMemcpyAsync(Pm.p, w.Z.p, sizeof(double) * c.n * b, hipMemcpyDeviceToDevice, s));
-    l_coldot(c.n, b, w.R, c.n, w.Z, c.n, dots, s);
-    h = dots.download(s, b);
+    h = coldot(w.R, w.Z);
     for (int j = 0; j < b; ++j) rz[j] = h[j];
     int it = 0;
     for (; it < c.opt.w_maxit; ++it) {
       op_aplus(c, w, Pm, Q);
-      l_coldot(c.n, b, Pm, c.n, Q, c.n, dots, s);
-      h = dots.download(s, b);
+      h = coldot(Pm, Q);
       for (int j = 0; j < b; ++j) {
         if (active[j] && !(h[j] > 0.0)) throw Error(AWG_ERR_NOT_SPD, "PCG with A_+ met p^T A_+ p <= 0");
         alpha[j] = active[j] ? rz[j] / h[j] : 0.0;
       }
       AWG_HIP(hipMemcpyAsync(alpha_d.p, alpha.data(), sizeof(double) * b, hipMemcpyHostToDevice, s));
-      l_colaxpby(c.n, b, Pm, c.n, alpha_d, X, c.n, nullptr, 1.0, 1.0, s);
-      l_colaxpby(c.n, b, Q, c.n, alpha_d, w.R, c.n, nullptr, -1.0, 1.0, s);
-      l_coldot(c.n, b, w.R, c.n, w.R, c.n, dots, s);
-      h = dots.download(s, b);
+      l_colaxpby(c.n, b, Pm, alpha_d, X, nullptr, 1.0, 1.0, s);
+      l_colaxpby(c.n, b, Q, alpha_d, w.R, nullptr, -1.0, 1.0, s);
+      h = coldot(w.R, w.R);
       int nact = 0;
       for (int j = 0; j < b; ++j) {
         if (active[j] && std::sqrt(h[j]) <= c.opt.w_rtol * bn[j]) active[j] = 0;
@@ -844,21 +874,20 @@ void phase_W(awg_ctx& c) {
       }
       if (nact == 0) { ++it; break; }
       op_h2(c, w, false);
-      l_coldot(c.n, b, w.R, c.n, w.Z, c.n, dots, s);
-      h = dots.download(s, b);
+      h = coldot(w.R, w.Z);
       for (int j = 0; j < b; ++j) {
         beta[j] = active[j] ? h[j] / rz[j] : 0.0;
         if (active[j]) rz[j] = h[j];
       }
       AWG_HIP(hipMemcpyAsync(alpha_d.p, beta.data(), sizeof(double) * b, hipMemcpyHostToDevice, s));
-      l_colaxpby(c.n, b, w.Z, c.n, nullptr, Pm, c.n, alpha_d, 1.0, 1.0, s);   // P = Z + beta P
-      sync(c);   // beta buffer reused next iteration
+      l_colaxpby(c.n, b, w.Z, nullptr, Pm, alpha_d, 1.0, 1.0, s);   // P = Z + beta P
+      sync(c);   // the host buffer of beta is reused next iteration
     }
     itmax = std::max(itmax, it);
     for (int j = 0; j < bc; ++j)
       if (active[j]) throw Error(AWG_ERR_NOT_SPD, "PCG with A_+ for W did not converge within w_maxit");
-    hipLaunchKernelGGL(k_copy_cols, dim3(1024), dim3(256), 0, s, X.p, (long)c.n, c.W.p + (long)c0 * c.n, (long)c.n,
-                       c.n, bc);
+    hipLaunchKernelGGL(k_copy_cols, dim3(cdiv((long)c.n * bc, 256)), dim3(256), 0, s, X.p, b, c.W.p, (long)c.nminus,
+                       (long)c.n, c0, bc);
     AWG_LAUNCH_CHECK();
   }
   c.w_iters = itmax;
@@ -872,12 +901,11 @@ void phase_EW(awg_ctx& c) {
   DBuf<double> AW, EW;
   AW.alloc((long)c.n * c.nminus);
   EW.alloc((long)c.nminus * c.nminus);
-  for (int c0 = 0; c0 < c.nminus; c0 += 32768)
-    l_spmm(c.n, c.nnz, c.rowptr, c.col, c.val, c.W.p + (long)c0 * c.n, c.n, AW.p + (long)c0 * c.n, c.n,
-           std::min(32768, c.nminus - c0), 1.0, 0.0, s);
+  l_spmm(c.n, c.nnz, c.rowptr, c.col, c.val, c.W.p, AW.p, c.nminus, 1.0, 0.0, s);   // row-major A W
+  // E_W = W^T (A W): column-major views W_rm (n_minus x n) and AW_rm -> W_rm AW_rm^T
   DBuf<GemmDesc> g;
-  g.upload({GemmDesc{c.W.p, AW.p, EW.p, c.nminus, c.nminus, c.n, c.n, c.n, c.nminus}}, s);
-  gemm_batched(g, 1, c.nminus, c.nminus, true, false, 1.0, 0.0, false, s, 2.0 * c.n * (double)c.nminus * c.nminus);
+  g.upload({GemmDesc{c.W.p, AW.p, EW.p, c.nminus, c.nminus, c.n, c.nminus, c.nminus, c.nminus}}, s);
+  gemm_batched(g, 1, c.nminus, c.nminus, false, true, 1.0, 0.0, false, s, 2.0 * c.n * (double)c.nminus * c.nminus);
   spd_inverse(c, EW, c.nminus, c.EWinv, "second coarse matrix W^T A W");
 }
 
@@ -954,7 +982,7 @@ int do_pcg(awg_ctx& c, const double* b, double* x, double tol, int maxit, awg_pc
   double* sc = c.scal.p;
   AWG_HIP(hipMemcpyAsync(w.R.p, b, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
   AWG_HIP(hipMemsetAsync(xx, 0, sizeof(double) * n, s));
-  l_coldot(n, 1, w.R, n, w.R, n, sc + 6, s);
+  l_coldot(n, 1, w.R, w.R, w.dotpart, sc + 6, s);
   double h6;
   AWG_HIP(hipMemcpyAsync(&h6, sc + 6, sizeof(double), hipMemcpyDeviceToHost, s));
   sync(c);
@@ -967,15 +995,15 @@ int do_pcg(awg_ctx& c, const double* b, double* x, double tol, int maxit, awg_pc
   } else {
     op_h(c, w, f32);
     AWG_HIP(hipMemcpyAsync(p, w.Z.p, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
-    l_coldot(n, 1, w.R, n, w.Z, n, sc + 0, s);
+    l_coldot(n, 1, w.R, w.Z, w.dotpart, sc + 0, s);
     const unsigned g = cdiv(n, 256);
     double hs[6];
     for (;;) {
-      l_spmm(n, c.nnz, c.rowptr, c.col, c.val, p, n, q, n, 1, 1.0, 0.0, s);
-      l_coldot(n, 1, p, n, q, n, sc + 1, s);
+      l_spmm(n, c.nnz, c.rowptr, c.col, c.val, p, q, 1, 1.0, 0.0, s);
+      l_coldot(n, 1, p, q, w.dotpart, sc + 1, s);
       hipLaunchKernelGGL(k_pcg_scalars, dim3(1), dim3(64), 0, s, sc, it, 0);
       hipLaunchKernelGGL(k_pcg_update_xr, dim3(g), dim3(256), 0, s, n, xx, w.R.p, p, q, sc);
-      l_coldot(n, 1, w.R, n, w.R, n, sc + 5, s);
+      l_coldot(n, 1, w.R, w.R, w.dotpart, sc + 5, s);
       AWG_HIP(hipMemcpyAsync(hs, sc, sizeof(double) * 6, hipMemcpyDeviceToHost, s));
       sync(c);
       ++it;
@@ -988,7 +1016,7 @@ int do_pcg(awg_ctx& c, const double* b, double* x, double tol, int maxit, awg_pc
       if (inf.rel_res <= tol) { inf.converged = 1; break; }
       if (it >= maxit) break;
       op_h(c, w, f32);
-      l_coldot(n, 1, w.R, n, w.Z, n, sc + 3, s);
+      l_coldot(n, 1, w.R, w.Z, w.dotpart, sc + 3, s);
       hipLaunchKernelGGL(k_pcg_scalars, dim3(1), dim3(64), 0, s, sc, it - 1, 1);
       hipLaunchKernelGGL(k_pcg_update_p, dim3(g), dim3(256), 0, s, n, p, w.Z.p, sc);
     }
@@ -997,9 +1025,9 @@ int do_pcg(awg_ctx& c, const double* b, double* x, double tol, int maxit, awg_pc
   if (status == AWG_OK) {
     AWG_HIP(hipMemcpyAsync(x, xx, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
     // true residual
-    l_spmm(n, c.nnz, c.rowptr, c.col, c.val, xx, n, q, n, 1, -1.0, 0.0, s);
-    l_colaxpby(n, 1, b, n, nullptr, q, n, nullptr, 1.0, 1.0, s);
-    l_coldot(n, 1, q, n, q, n, sc + 7, s);
+    l_spmm(n, c.nnz, c.rowptr, c.col, c.val, xx, q, 1, -1.0, 0.0, s);
+    l_colaxpby(n, 1, b, nullptr, q, nullptr, 1.0, 1.0, s);
+    l_coldot(n, 1, q, q, w.dotpart, sc + 7, s);
     std::vector<double> hist(16 + 2 * (size_t)std::max(maxit, 1));
     AWG_HIP(hipMemcpyAsync(hist.data(), sc, sizeof(double) * hist.size(), hipMemcpyDeviceToHost, s));
     sync(c);
@@ -1058,7 +1086,7 @@ void awg_default_options(awg_options* opt) {
   if (!opt) return;
   opt->tau = 0.1;
   opt->zero_tol = 1e-12;
-  opt->w_rtol = 1e-12;
+  opt->w_rtol = 1e-10;
   opt->w_maxit = 500;
   opt->local_prec = AWG_LOCAL_F64;
   opt->stream = nullptr;

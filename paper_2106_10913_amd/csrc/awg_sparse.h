@@ -16,16 +16,17 @@ void l_pairs(int n, const int* rowptr, const int* col, const double* val, const 
 void l_pou(long tot, const int* sub_idx, const int* mult, double* dw, hipStream_t s);
 void l_extract(int N, const long* sub_ptr, const int* sub_idx, const int* rowptr, const int* col,
                const double* vals, const MatDesc* mats, hipStream_t s);
-void l_spmm(int n, long nnz, const int* rowptr, const int* col, const double* val, const double* X, long ldx,
-            double* Y, long ldy, int b, double alpha, double beta, hipStream_t s);
-void l_gather(long tot, const int* sub_idx, const int* ent_sub, const long* sub_ptr, const double* X, long ldx,
-              int b, const double* scale, double* Xs, hipStream_t s);
+// multi-column vectors are row-major (b contiguous values per row)
+void l_spmm(int n, long nnz, const int* rowptr, const int* col, const double* val, const double* X, double* Y, int b,
+            double alpha, double beta, hipStream_t s);
+void l_gather(long tot, const int* sub_idx, const double* X, int b, double* Xs, hipStream_t s);
 void l_scatter(int n, long tot, const int* inv_ptr, const int* inv_sub, const int* inv_loc, const long* sub_ptr,
-               const double* Zs, int b, const double* scale, double* Y, long ldy, double alpha, double beta,
-               hipStream_t s);
-void l_coldot(int n, int b, const double* X, long ldx, const double* Y, long ldy, double* out, hipStream_t s);
-void l_colaxpby(int n, int b, const double* X, long ldx, const double* a, double* Y, long ldy, const double* bb,
-                double sa, double sb, hipStream_t s);
+               const double* Zs, int b, double* Y, double alpha, double beta, hipStream_t s);
+// part: DOT_CHUNKS * b scratch doubles
+constexpr int DOT_CHUNKS_H = 128;
+void l_coldot(int n, int b, const double* X, const double* Y, double* part, double* out, hipStream_t s);
+void l_colaxpby(long rows, int b, const double* X, const double* a, double* Y, const double* bb, double sa, double sb,
+                hipStream_t s);
 void l_set_identity(const MatDesc* mats, int batch, hipStream_t s);
 void l_copy_mat(const MatDesc* src, const MatDesc* dst, int batch, hipStream_t s);
 void l_scale_sym(const MatDesc* mats, int batch, const long* voff, const double* d, bool inv, bool symmetrize,

@@ -83,6 +83,35 @@ struct TrsmUpdate {
   }
 };
 
+// panel update of the blocked tridiagonalisation at panel start p0:
+// A[r0:, r0:] -= X[r0:, 0:kb] Y[r0:, 0:kb]^T with r0 = p0 + kb and
+// (X, Y) = (V, W) or (W, V); V and W are n x TRD_NB per block at voff/woff.
+struct Syr2kUpdate {
+  const MatDesc* m;
+  const double* X;
+  const double* Y;
+  const long* off;     // per block: element offset of its n x nbw work panels
+  int p0, nbw;
+  __device__ GemmDesc operator()(int b) const {
+    MatDesc M = m[b];
+    GemmDesc g;
+    int kb = M.n - 2 - p0;
+    kb = kb < 0 ? 0 : (kb > nbw ? nbw : kb);
+    const int r0 = p0 + kb;
+    const int rem = kb > 0 ? M.n - r0 : 0;
+    const long o = off[b] * (long)nbw;
+    g.A = X + o + r0;
+    g.B = Y + o + r0;
+    g.C = M.A + r0 + (long)r0 * M.ld;
+    g.m = rem;
+    g.n = rem;
+    g.k = kb;
+    g.lda = g.ldb = M.n;
+    g.ldc = M.ld;
+    return g;
+  }
+};
+
 // ---------------------------------------------------------------------------
 // GEMM, FP64 MFMA
 // ---------------------------------------------------------------------------
@@ -156,6 +185,93 @@ __global__ __launch_bounds__(256) void k_gemm(DF df, double alpha, double beta, 
       }
 }
 
+// 128x128 output tile per workgroup (each wavefront a 64x64 quarter = 4x4
+// MFMA blocks), K staged in LDS in steps of 16 with the next step's global
+// loads held in registers while the current one is multiplied.
+template <class DF, bool TA, bool TB>
+__global__ __launch_bounds__(256) void k_gemm128(DF df, double alpha, double beta, int lower) {
+  const GemmDesc d = df(blockIdx.z);
+  const int m0 = blockIdx.x * 128, n0 = blockIdx.y * 128;
+  if (m0 >= d.m || n0 >= d.n) return;
+  if (lower && m0 + 128 <= n0) return;
+  __shared__ double As[2][16][132];
+  __shared__ double Bs[2][16][132];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wm = (wave & 1) * 64, wn = (wave >> 1) * 64;
+  v4d acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = (v4d){0.0, 0.0, 0.0, 0.0};
+  double ra[8], rb[8];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const int e = tid + r * 256;
+      int i, kk;
+      if (!TA) { i = e & 127; kk = e >> 7; } else { kk = e & 15; i = e >> 4; }
+      const int gi = m0 + i, gk = k0 + kk;
+      ra[r] = (gi < d.m && gk < d.k) ? (TA ? d.A[gk + (long)gi * d.lda] : d.A[gi + (long)gk * d.lda]) : 0.0;
+      int j, kb;
+      if (!TB) { kb = e & 15; j = e >> 4; } else { j = e & 127; kb = e >> 7; }
+      const int gj = n0 + j, gkb = k0 + kb;
+      rb[r] = (gj < d.n && gkb < d.k) ? (TB ? d.B[gj + (long)gkb * d.ldb] : d.B[gkb + (long)gj * d.ldb]) : 0.0;
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const int e = tid + r * 256;
+      int i, kk;
+      if (!TA) { i = e & 127; kk = e >> 7; } else { kk = e & 15; i = e >> 4; }
+      As[buf][kk][i] = ra[r];
+      int j, kb;
+      if (!TB) { kb = e & 15; j = e >> 4; } else { j = e & 127; kb = e >> 7; }
+      Bs[buf][kb][j] = rb[r];
+    }
+  };
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  int buf = 0;
+  for (int k0 = 0; k0 < d.k; k0 += 16) {
+    const bool more = k0 + 16 < d.k;
+    if (more) gload(k0 + 16);
+#pragma unroll
+    for (int kk = 0; kk < 16; kk += 4) {
+      const int kr = kk + (lane >> 4), c = lane & 15;
+      double a[4], b[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        a[q] = As[buf][kr][wm + q * 16 + c];
+        b[q] = Bs[buf][kr][wn + q * 16 + c];
+      }
+#pragma unroll
+      for (int qa = 0; qa < 4; ++qa)
+#pragma unroll
+        for (int qb = 0; qb < 4; ++qb)
+          acc[qa][qb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[qa], b[qb], acc[qa][qb], 0, 0, 0);
+    }
+    if (more) sstore(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+#pragma unroll
+  for (int qa = 0; qa < 4; ++qa)
+#pragma unroll
+    for (int qb = 0; qb < 4; ++qb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = m0 + wm + qa * 16 + (lane >> 4) + 4 * r;
+        const int j = n0 + wn + qb * 16 + (lane & 15);
+        if (i < d.m && j < d.n) {
+          double* cp = d.C + i + (long)j * d.ldc;
+          const double v = alpha * acc[qa][qb][r];
+          *cp = (beta == 0.0) ? v : v + beta * *cp;
+        }
+      }
+}
+
 template <class DF>
 static const char* gemm_name(bool tA, bool tB);
 template <>
@@ -166,18 +282,44 @@ template <>
 const char* gemm_name<CholUpdate>(bool, bool) { return "k_gemm<CholUpdate,N,T>"; }
 template <>
 const char* gemm_name<TrsmUpdate>(bool tA, bool) { return tA ? "k_gemm<TrsmUpdate,T,N>" : "k_gemm<TrsmUpdate,N,N>"; }
+template <>
+const char* gemm_name<Syr2kUpdate>(bool, bool) { return "k_gemm<Syr2kUpdate,N,T>"; }
+
+// 128x128 tiles pay off for the long-k products with explicit descriptors;
+// the k = 32/64 updates inside the factorisations keep 64x64 tiles
+template <class DF>
+static bool use_big_tiles() { return false; }
+template <>
+bool use_big_tiles<DescArray>() { return true; }
 
 template <class DF>
 static void launch_gemm(DF df, int batch, int max_m, int max_n, bool tA, bool tB, double alpha, double beta,
                         bool lower, hipStream_t s, double flops = 0.0) {
   if (batch <= 0 || max_m <= 0 || max_n <= 0) return;
-  dim3 grid(cdiv(max_m, 64), cdiv(max_n, 64), batch);
   KScope kt(gemm_name<DF>(tA, tB), s, 0.0, flops);
+  if (use_big_tiles<DF>() && max_m >= 128) {
+    dim3 grid(cdiv(max_m, 128), cdiv(max_n, 128), batch);
+    if (!tA && !tB) hipLaunchKernelGGL((k_gemm128<DF, false, false>), grid, dim3(256), 0, s, df, alpha, beta, (int)lower);
+    else if (tA && !tB) hipLaunchKernelGGL((k_gemm128<DF, true, false>), grid, dim3(256), 0, s, df, alpha, beta, (int)lower);
+    else if (!tA && tB) hipLaunchKernelGGL((k_gemm128<DF, false, true>), grid, dim3(256), 0, s, df, alpha, beta, (int)lower);
+    else hipLaunchKernelGGL((k_gemm128<DF, true, true>), grid, dim3(256), 0, s, df, alpha, beta, (int)lower);
+    AWG_LAUNCH_CHECK();
+    return;
+  }
+  dim3 grid(cdiv(max_m, 64), cdiv(max_n, 64), batch);
   if (!tA && !tB) hipLaunchKernelGGL((k_gemm<DF, false, false>), grid, dim3(256), 0, s, df, alpha, beta, (int)lower);
   else if (tA && !tB) hipLaunchKernelGGL((k_gemm<DF, true, false>), grid, dim3(256), 0, s, df, alpha, beta, (int)lower);
   else if (!tA && tB) hipLaunchKernelGGL((k_gemm<DF, false, true>), grid, dim3(256), 0, s, df, alpha, beta, (int)lower);
   else hipLaunchKernelGGL((k_gemm<DF, true, true>), grid, dim3(256), 0, s, df, alpha, beta, (int)lower);
   AWG_LAUNCH_CHECK();
+}
+
+void syr2k_panel_update(const MatDesc* d_mats, const double* V, const double* W, const long* d_off, int p0, int nbw,
+                        int max_rem, int batch, hipStream_t s, double flops) {
+  launch_gemm(Syr2kUpdate{d_mats, V, W, d_off, p0, nbw}, batch, max_rem, max_rem, false, true, -1.0, 1.0, false, s,
+              0.5 * flops);
+  launch_gemm(Syr2kUpdate{d_mats, W, V, d_off, p0, nbw}, batch, max_rem, max_rem, false, true, -1.0, 1.0, false, s,
+              0.5 * flops);
 }
 
 void gemm_batched(const GemmDesc* d_desc, int batch, int max_m, int max_n, bool transA, bool transB,
@@ -233,9 +375,56 @@ __global__ __launch_bounds__(256) void k_gemv_t(const GemmDesc* descs, double al
   }
 }
 
+// notrans with few rows and a long k (single descriptor): the columns are
+// split into GEMV_KSPLIT ranges whose partial sums are added in a fixed order
+constexpr int GEMV_KSPLIT = 64;
+__global__ __launch_bounds__(256) void k_gemv_n_part(const GemmDesc* descs, double* part) {
+  const GemmDesc d = descs[0];
+  const int r = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int i = blockIdx.x * 64 + r;
+  const int ks = blockIdx.y;
+  const int j0 = (int)((long)d.k * ks / GEMV_KSPLIT), j1 = (int)((long)d.k * (ks + 1) / GEMV_KSPLIT);
+  __shared__ double sh[4][64];
+  double acc = 0.0;
+  if (i < d.m)
+    for (int j = j0 + g; j < j1; j += 4) acc += d.A[i + (long)j * d.lda] * d.B[j];
+  sh[g][r] = acc;
+  __syncthreads();
+  if (g == 0 && i < d.m) part[(long)ks * d.m + i] = (sh[0][r] + sh[1][r]) + (sh[2][r] + sh[3][r]);
+}
+
+__global__ void k_gemv_n_sum(const GemmDesc* descs, const double* part, double alpha, double beta) {
+  const GemmDesc d = descs[0];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= d.m) return;
+  double acc = 0.0;
+  for (int ks = 0; ks < GEMV_KSPLIT; ++ks) acc += part[(long)ks * d.m + i];
+  const double v = alpha * acc;
+  d.C[i] = (beta == 0.0) ? v : v + beta * d.C[i];
+}
+
 void gemv_batched(const GemmDesc* d_desc, int batch, int max_m, int max_k, bool transA, double alpha,
                   double beta, hipStream_t s, double bytes) {
   if (batch <= 0) return;
+  if (!transA && batch == 1 && max_m <= 16384 && max_k >= 16 * max_m) {
+    // partial-sum buffer, grown on demand and kept for the life of the process
+    static double* part = nullptr;
+    static size_t cap = 0;
+    if (cap < (size_t)GEMV_KSPLIT * max_m) {
+      AWG_HIP(hipStreamSynchronize(s));
+      if (part) AWG_HIP(hipFree(part));
+      part = nullptr;
+      cap = 0;
+      AWG_HIP(hipMalloc((void**)&part, sizeof(double) * GEMV_KSPLIT * max_m));
+      cap = (size_t)GEMV_KSPLIT * max_m;
+    }
+    KScope kt("k_gemv_n_part", s, bytes, bytes / 4.0);
+    hipLaunchKernelGGL(k_gemv_n_part, dim3(cdiv(max_m, 64), GEMV_KSPLIT), dim3(256), 0, s, d_desc, part);
+    AWG_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_gemv_n_sum, dim3(cdiv(max_m, 256)), dim3(256), 0, s, d_desc, part, alpha, beta);
+    AWG_LAUNCH_CHECK();
+    return;
+  }
   KScope kt(transA ? "k_gemv_t" : "k_gemv_n", s, bytes, bytes / 4.0);
   if (!transA) {
     if (max_m <= 0) return;

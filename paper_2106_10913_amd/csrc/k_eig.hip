@@ -17,19 +17,11 @@
 
 #include <float.h>
 
+#include <algorithm>
+
 namespace awg {
 
 constexpr int TRD_ROWS = 64;
-
-// Per-block work layout (doubles), offset work_off[b]:
-//   v0[n] w0[n] v1[n] w1[n] p[n]   (reflector / w of the two last steps, product)
-struct TrdWork {
-  double* base;
-  int n;
-  __device__ double* v(int par) const { return base + (par ? 2 * n : 0); }
-  __device__ double* w(int par) const { return base + (par ? 3 * n : n); }
-  __device__ double* p() const { return base + 4 * n; }
-};
 
 __device__ inline double wave_sum(double v) {
 #pragma unroll
@@ -48,157 +40,201 @@ __device__ double block_sum256(double v, double* sh) {
   return r;
 }
 
-// Step k, part 1: bring column k up to date with the previous rank-2 update
-// and build the Householder reflector of its subdiagonal part.
-__global__ __launch_bounds__(256) void k_trd_hh(const MatDesc* mats, int k, double* dd, double* ee,
-                                                double* tau, const long* off, double* work) {
+// Blocked Householder tridiagonalisation (lower, full symmetric storage).
+// Panels of TRD_NB columns; inside a panel the trailing matrix is not
+// updated: column j is brought up to date from the panel's reflectors V and
+// vectors W, and A22 v is corrected by V (W^T v) + W (V^T v).  After the
+// panel, A22 -= V W^T + W V^T as two MFMA products.
+// Work layout (sumns = total rows of all blocks): V at [0, sumns*NB),
+// W at [sumns*NB, 2 sumns*NB) (block b at off[b]*NB, n_b x NB, ld n_b),
+// p (A22 v) at 2 sumns*NB + off[b].
+struct TrdWork {
+  double* V;
+  double* W;
+  double* p;
+  __device__ TrdWork(double* work, long sumns, long o) {
+    V = work + o * TRD_NB;
+    W = work + sumns * TRD_NB + o * TRD_NB;
+    p = work + 2 * sumns * TRD_NB + o;
+  }
+};
+
+// column j = p0 + jj: update from the panel, reflector, d_j, e_j, tau_j
+__global__ __launch_bounds__(256) void k_trd_col(const MatDesc* mats, int p0, int jj, double* dd, double* ee,
+                                                 double* tau, const long* off, double* work, long sumns) {
   const MatDesc M = mats[blockIdx.x];
   const int n = M.n;
-  if (n == 1 && k == 0 && threadIdx.x == 0) {
-    dd[off[blockIdx.x]] = M.A[0];
-    tau[off[blockIdx.x]] = 0.0;
-  }
-  if (k > n - 2) return;
+  const int j = p0 + jj;
+  if (j > n - 3) return;
   __shared__ double sh[4];
   const long o = off[blockIdx.x];
-  TrdWork W{work + 5 * o, n};
-  const int par = k & 1;
-  const double* vp = W.v(par ^ 1);
-  const double* wp = W.w(par ^ 1);
-  double* vc = W.v(par);
-  double* col = M.A + (long)k * M.ld;
-  const bool upd = k > 0;
-  const double vk = upd ? vp[k] : 0.0, wk = upd ? wp[k] : 0.0;
-  // updated column entries rows k..n-1
+  TrdWork T(work, sumns, o);
+  double* col = M.A + (long)j * M.ld;
+  // rows j..n-1 of column j minus V[:, t] W[j, t] + W[:, t] V[j, t], t < jj
   double ss = 0.0;
-  for (int i = k + 2 + threadIdx.x; i < n; i += 256) {
+  for (int i = j + threadIdx.x; i < n; i += 256) {
     double a = col[i];
-    if (upd) a -= __dadd_rn(__dmul_rn(vp[i], wk), __dmul_rn(wp[i], vk));
+    for (int t = 0; t < jj; ++t) a -= T.V[i + (long)t * n] * T.W[j + (long)t * n] + T.W[i + (long)t * n] * T.V[j + (long)t * n];
     col[i] = a;
-    ss += a * a;
+    if (i >= j + 2) ss += a * a;
   }
   ss = block_sum256(ss, sh);
   if (threadIdx.x == 0) {
-    double dkk = col[k], alpha = col[k + 1];
-    if (upd) {
-      dkk -= __dadd_rn(__dmul_rn(vk, wk), __dmul_rn(wk, vk));
-      alpha -= __dadd_rn(__dmul_rn(vp[k + 1], wk), __dmul_rn(wp[k + 1], vk));
-    }
-    dd[o + k] = dkk;
-    if (k == n - 2) {
-      double last = M.A[(k + 1) + (long)(k + 1) * M.ld];
-      if (upd) last -= __dadd_rn(__dmul_rn(vp[k + 1], wp[k + 1]), __dmul_rn(wp[k + 1], vp[k + 1]));
-      dd[o + k + 1] = last;
-      ee[o + k] = alpha;
-      tau[o + k] = 0.0;
-      col[k + 1] = 1.0;
+    const double dkk = col[j], alpha = col[j + 1];
+    dd[o + j] = dkk;
+    if (ss == 0.0) {
+      ee[o + j] = alpha;
+      tau[o + j] = 0.0;
       sh[0] = 0.0;
-    } else if (ss == 0.0) {
-      ee[o + k] = alpha;
-      tau[o + k] = 0.0;
-      col[k + 1] = 1.0;
-      sh[0] = 0.0;       // v = e1 scaled by 0: rest of v stays as the (zero) column
     } else {
       const double beta = -copysign(sqrt(alpha * alpha + ss), alpha);
-      tau[o + k] = (beta - alpha) / beta;
-      ee[o + k] = beta;
-      col[k + 1] = 1.0;
+      tau[o + j] = (beta - alpha) / beta;
+      ee[o + j] = beta;
       sh[0] = 1.0 / (alpha - beta);
     }
   }
   __syncthreads();
-  if (k == n - 2) return;
   const double scale = sh[0];
-  for (int i = k + 1 + threadIdx.x; i < n; i += 256) {
-    double v = (i == k + 1) ? 1.0 : col[i] * scale;
-    if (i > k + 1) col[i] = v;
-    vc[i] = v;
+  for (int i = j + 1 + threadIdx.x; i < n; i += 256) {
+    const double v = (i == j + 1) ? 1.0 : col[i] * scale;
+    col[i] = v;
+    T.V[i + (long)jj * n] = v;
   }
+  for (int i = threadIdx.x; i <= j; i += 256) T.V[i + (long)jj * n] = 0.0;
 }
 
-// Step k, part 2: A22 <- A22 - v_{k-1} w_{k-1}^T - w_{k-1} v_{k-1}^T on rows and
-// columns k+1..n-1 (fused), then p = A22 v_k.  64 rows per workgroup, 4
-// column groups; partial sums combined in LDS.
-__global__ __launch_bounds__(256) void k_trd_upd(const MatDesc* mats, int k, const long* off, double* work) {
+// p = A[j+1:, j+1:] v (read only): 64 rows per workgroup, 4 column groups
+__global__ __launch_bounds__(256) void k_trd_symv(const MatDesc* mats, int p0, int jj, const long* off, double* work,
+                                                  long sumns) {
   const MatDesc M = mats[blockIdx.y];
   const int n = M.n;
-  if (k > n - 3) return;
-  const int i0 = k + 1 + blockIdx.x * TRD_ROWS;
+  const int j = p0 + jj;
+  if (j > n - 3) return;
+  const int i0 = j + 1 + blockIdx.x * TRD_ROWS;
   if (i0 >= n) return;
-  const long o = off[blockIdx.y];
-  TrdWork W{work + 5 * o, n};
-  const int par = k & 1;
-  const double* vp = W.v(par ^ 1);
-  const double* wp = W.w(par ^ 1);
-  const double* vc = W.v(par);
-  const bool upd = k > 0;
+  TrdWork T(work, sumns, off[blockIdx.y]);
+  const double* v = T.V + (long)jj * n;
   const int r = threadIdx.x & 63, g = threadIdx.x >> 6;
   const int i = i0 + r;
   __shared__ double part[4][TRD_ROWS];
-  double acc = 0.0;
+  double a0 = 0.0, a1 = 0.0;
   if (i < n) {
-    const double vi = upd ? vp[i] : 0.0, wi = upd ? wp[i] : 0.0;
-    double* a = M.A + i;
-    for (int j = k + 1 + g; j < n; j += 4) {
-      double x = a[(long)j * M.ld];
-      if (upd) {
-        x -= __dadd_rn(__dmul_rn(vi, wp[j]), __dmul_rn(wi, vp[j]));
-        a[(long)j * M.ld] = x;
-      }
-      acc += x * vc[j];
+    const double* a = M.A + i;
+    int c = j + 1 + g;
+    for (; c + 4 < n; c += 8) {
+      a0 += a[(long)c * M.ld] * v[c];
+      a1 += a[(long)(c + 4) * M.ld] * v[c + 4];
     }
+    for (; c < n; c += 4) a0 += a[(long)c * M.ld] * v[c];
   }
-  part[g][r] = acc;
+  part[g][r] = a0 + a1;
   __syncthreads();
-  if (g == 0 && i < n) W.p()[i] = (part[0][r] + part[1][r]) + (part[2][r] + part[3][r]);
+  if (g == 0 && i < n) T.p[i] = (part[0][r] + part[1][r]) + (part[2][r] + part[3][r]);
 }
 
-// Step k, part 3: w = tau p - (tau^2/2)(p.v) v.
-__global__ __launch_bounds__(256) void k_trd_w(const MatDesc* mats, int k, const double* tau, const long* off,
-                                               double* work) {
+// w = tau (p - V (W^T v) - W (V^T v)); w += -tau/2 (w.v) v   (stored as W[:, jj]).
+// The 2 jj dot products are spread over the four wavefronts (one vector at a
+// time per wavefront, lanes over rows); the update loops over rows.
+__global__ __launch_bounds__(256) void k_trd_w(const MatDesc* mats, int p0, int jj, const double* tau,
+                                               const long* off, double* work, long sumns) {
   const MatDesc M = mats[blockIdx.x];
   const int n = M.n;
-  if (k > n - 3) return;
+  const int j = p0 + jj;
+  if (j > n - 3) return;
   __shared__ double sh[4];
+  __shared__ double y[2 * TRD_NB];
   const long o = off[blockIdx.x];
-  TrdWork W{work + 5 * o, n};
-  const int par = k & 1;
-  const double* vc = W.v(par);
-  double* wc = W.w(par);
-  const double* p = W.p();
-  const double t = tau[o + k];
-  double s = 0.0;
-  for (int i = k + 1 + threadIdx.x; i < n; i += 256) s += p[i] * vc[i];
-  s = block_sum256(s, sh);
-  const double alpha = -0.5 * t * t * s;
-  for (int i = k + 1 + threadIdx.x; i < n; i += 256) wc[i] = t * p[i] + alpha * vc[i];
+  TrdWork T(work, sumns, o);
+  const double* __restrict__ v = T.V + (long)jj * n;
+  double* __restrict__ w = T.W + (long)jj * n;
+  const double t = tau[o + j];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  // y[q] = W[:, q]^T v and y[NB + q] = V[:, q]^T v over rows j+1..n-1
+  for (int q = wid; q < 2 * jj; q += 4) {
+    const double* __restrict__ col = (q < jj) ? T.W + (long)q * n : T.V + (long)(q - jj) * n;
+    double acc = 0.0;
+    for (int i = j + 1 + lane; i < n; i += 64) acc += col[i] * v[i];
+    acc = wave_sum(acc);
+    if (lane == 0) y[q < jj ? q : TRD_NB + (q - jj)] = acc;
+  }
+  __syncthreads();
+  double sv = 0.0;
+  for (int i = j + 1 + threadIdx.x; i < n; i += 256) {
+    double x = T.p[i];
+    for (int q = 0; q < jj; ++q) x -= T.V[i + (long)q * n] * y[q] + T.W[i + (long)q * n] * y[TRD_NB + q];
+    x *= t;
+    w[i] = x;
+    sv += x * v[i];
+  }
+  sv = block_sum256(sv, sh);
+  const double alpha = -0.5 * t * sv;
+  for (int i = j + 1 + threadIdx.x; i < n; i += 256) w[i] += alpha * v[i];
+  for (int i = threadIdx.x; i <= j; i += 256) w[i] = 0.0;
+}
+
+// last 2x2 (or 1x1) block after every reflector has been applied
+__global__ void k_trd_fin(const MatDesc* mats, double* dd, double* ee, double* tau, const long* off, int nb) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nb) return;
+  const MatDesc M = mats[b];
+  const int n = M.n;
+  const long o = off[b];
+  if (n == 1) {
+    dd[o] = M.A[0];
+    tau[o] = 0.0;
+    return;
+  }
+  const int k = n - 2;
+  dd[o + k] = M.A[k + (long)k * M.ld];
+  dd[o + k + 1] = M.A[(k + 1) + (long)(k + 1) * M.ld];
+  ee[o + k] = M.A[(k + 1) + (long)k * M.ld];
+  tau[o + k] = 0.0;
+  tau[o + k + 1] = 0.0;
+  M.A[(k + 1) + (long)k * M.ld] = 1.0;     // unit reflector slot read by the back-transformation
 }
 
 void sytrd_batched(const MatDesc* d_mats, const std::vector<int>& h_n, double* d, double* e, double* tau,
                    const long* d_off, double* work, hipStream_t s) {
   const int batch = (int)h_n.size();
   int maxn = 0;
-  for (int v : h_n) maxn = v > maxn ? v : maxn;
+  long sumns = 0;
+  for (int v : h_n) {
+    maxn = v > maxn ? v : maxn;
+    sumns += v;
+  }
   if (batch == 0 || maxn == 0) return;
-  // (1x1 blocks are copied by the k = 0 launch)
-  for (int k = 0; k <= (maxn > 2 ? maxn - 2 : 0); ++k) {
-    hipLaunchKernelGGL(k_trd_hh, dim3(batch), dim3(256), 0, s, d_mats, k, d, e, tau, d_off, work);
-    AWG_LAUNCH_CHECK();
-    if (k <= maxn - 3) {
-      const int rows = maxn - k - 1;
+  for (int p0 = 0; p0 <= maxn - 3; p0 += TRD_NB) {
+    const int nbp = std::min(TRD_NB, maxn - 2 - p0);
+    for (int jj = 0; jj < nbp; ++jj) {
+      const int j = p0 + jj;
+      hipLaunchKernelGGL(k_trd_col, dim3(batch), dim3(256), 0, s, d_mats, p0, jj, d, e, tau, d_off, work, sumns);
+      AWG_LAUNCH_CHECK();
+      const int rows = maxn - j - 1;
       double tb = 0.0;
       if (ktimer_on())
-        for (int nb : h_n) {
-          const double r = nb - k - 1;
-          if (nb - k - 3 >= 0) tb += r * r * (k > 0 ? 16.0 : 8.0);
-        }
-      KScope kt("k_trd_upd", s, tb, tb / 8.0 * (k > 0 ? 3.0 : 2.0));
-      hipLaunchKernelGGL(k_trd_upd, dim3(cdiv(rows, TRD_ROWS), batch), dim3(256), 0, s, d_mats, k, d_off, work);
-      AWG_LAUNCH_CHECK();
-      hipLaunchKernelGGL(k_trd_w, dim3(batch), dim3(256), 0, s, d_mats, k, tau, d_off, work);
+        for (int nbk : h_n)
+          if (j <= nbk - 3) tb += 8.0 * (double)(nbk - j - 1) * (nbk - j - 1);
+      {
+        KScope kt("k_trd_symv", s, tb, tb / 4.0);
+        hipLaunchKernelGGL(k_trd_symv, dim3(cdiv(rows, TRD_ROWS), batch), dim3(256), 0, s, d_mats, p0, jj, d_off,
+                           work, sumns);
+        AWG_LAUNCH_CHECK();
+      }
+      hipLaunchKernelGGL(k_trd_w, dim3(batch), dim3(256), 0, s, d_mats, p0, jj, tau, d_off, work, sumns);
       AWG_LAUNCH_CHECK();
     }
+    const int rem = maxn - p0 - nbp;
+    double fl = 0.0;
+    if (ktimer_on())
+      for (int nbk : h_n) {
+        const int kb = std::min(TRD_NB, nbk - 2 - p0);
+        if (kb > 0) fl += 4.0 * (double)(nbk - p0 - kb) * (nbk - p0 - kb) * kb;
+      }
+    if (rem > 0)
+      syr2k_panel_update(d_mats, work, work + sumns * TRD_NB, d_off, p0, TRD_NB, rem, batch, s, fl);
   }
+  hipLaunchKernelGGL(k_trd_fin, dim3(cdiv(batch, 64)), dim3(64), 0, s, d_mats, d, e, tau, d_off, batch);
+  AWG_LAUNCH_CHECK();
 }
 
 // ---------------------------------------------------------------------------
@@ -241,13 +277,16 @@ __device__ TriInfo tri_info(const double* d, const double* e, int n) {
   return t;
 }
 
-// i-th smallest eigenvalue (0-based) by bisection on [lo, hi]
+// i-th smallest eigenvalue (0-based) by bisection on [lo, hi], to the
+// absolute accuracy 2 eps ||T|| (the accuracy a backward-stable reduction to
+// T provides, and all that the shifted solves of inverse iteration need)
 __device__ double bisect_eig(const double* d, const double* e, int n, int i, double lo, double hi,
                              double pivmin) {
+  const double atol = 2.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi)) + pivmin;
   for (int it = 0; it < 256; ++it) {
     const double mid = 0.5 * (lo + hi);
     if (mid <= lo || mid >= hi) break;
-    if (hi - lo <= 2.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi)) + pivmin) break;
+    if (hi - lo <= atol) break;
     if (sturm_count(d, e, n, mid, pivmin) <= i) lo = mid;
     else hi = mid;
   }
@@ -260,8 +299,9 @@ __device__ double bisect_eig(const double* d, const double* e, int n, int i, dou
 __device__ double multisect_eig(const double* d, const double* e, int n, int idx, double lo, double hi,
                                 double pivmin) {
   const int lane = threadIdx.x & 63;
+  const double atol = 2.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi)) + pivmin;
   for (int it = 0; it < 48; ++it) {
-    if (hi - lo <= 2.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi)) + pivmin) break;
+    if (hi - lo <= atol) break;
     const double w = hi - lo;
     const double x = lo + w * (double)(lane + 1) / 65.0;
     const int c = sturm_count(d, e, n, x, pivmin);
@@ -340,12 +380,12 @@ __global__ __launch_bounds__(64) void k_tri_vecs(TriEigArgs a, const int* count,
   const MatDesc Z = Zs[b];
   const long W = INVIT_LANES;
   double* wk = work + work_off[b];
-  double* U0 = wk;
-  double* U1 = wk + W * n;
-  double* U2 = wk + 2 * W * n;
-  double* LF = wk + 3 * W * n;
-  double* PV = wk + 4 * W * n;
-  double* X = wk + 5 * W * n;
+  double* __restrict__ U0 = wk;
+  double* __restrict__ U1 = wk + W * n;
+  double* __restrict__ U2 = wk + 2 * W * n;
+  double* __restrict__ LF = wk + 3 * W * n;
+  double* __restrict__ PV = wk + 4 * W * n;
+  double* __restrict__ X = wk + 5 * W * n;
   const TriInfo t = tri_info(d, e, n);
   for (int j = lane; j < k; j += 64) L[j] = bisect_eig(d, e, n, j, t.gl, t.gu, t.pivmin);
   __syncthreads();
@@ -393,26 +433,40 @@ __global__ __launch_bounds__(64) void k_tri_vecs(TriEigArgs a, const int* count,
     for (int sweep = 0; sweep < INVIT_SWEEPS; ++sweep) {
       if (act) {
         // solve (T - lj I) y = x in place, then scale to unit max norm
+        // forward: the loads of row i+1 are issued before row i is finished
         double xi = X[lane];
+        double xn_next = n > 1 ? X[W + lane] : 0.0;
+        double pv_next = PV[lane], lf_next = LF[lane];
         for (int i = 0; i < n - 1; ++i) {
           const long o = i * W + lane;
-          double xn = X[o + W];
-          if (PV[o] != 0.0) { const double tt = xi; xi = xn; xn = tt; }
+          double xn = xn_next;
+          const double pv = pv_next, lf = lf_next;
+          if (i + 2 < n) xn_next = X[o + 2 * W];
+          if (i + 1 < n - 1) { pv_next = PV[o + W]; lf_next = LF[o + W]; }
+          if (pv != 0.0) { const double tt = xi; xi = xn; xn = tt; }
           X[o] = xi;
-          xi = xn - LF[o] * xi;
+          xi = xn - lf * xi;
         }
-        X[(n - 1) * W + lane] = xi;
         double x1 = xi / U0[(n - 1) * W + lane];
         X[(n - 1) * W + lane] = x1;
         double x2 = 0.0;
         double mx = fabs(x1);
-        for (int i = n - 2; i >= 0; --i) {
-          const long o = i * W + lane;
-          const double v = (X[o] - U1[o] * x1 - U2[o] * x2) / U0[o];
-          X[o] = v;
-          x2 = x1;
-          x1 = v;
-          mx = fmax(mx, fabs(v));
+        if (n > 1) {
+          long o = (long)(n - 2) * W + lane;
+          double xo = X[o], u0 = U0[o], u1 = U1[o], u2 = U2[o];
+          for (int i = n - 2; i >= 0; --i) {
+            const double cx = xo, c0 = u0, c1 = u1, c2 = u2;
+            const long oc = o;
+            if (i > 0) {
+              o -= W;
+              xo = X[o]; u0 = U0[o]; u1 = U1[o]; u2 = U2[o];
+            }
+            const double v = (cx - c1 * x1 - c2 * x2) / c0;
+            X[oc] = v;
+            x2 = x1;
+            x1 = v;
+            mx = fmax(mx, fabs(v));
+          }
         }
         const double inv = mx > 0.0 ? 1.0 / mx : 1.0;
         for (int i = 0; i < n; ++i) X[i * W + lane] *= inv;

@@ -1,11 +1,11 @@
 // Sparse, gather/scatter, reduction and integer set-up kernels (gfx950).
 //
-// Multi-column vectors are column-major n x b with leading dimension ld.
-// Per-subdomain blocks ("restricted" vectors R^s X) are stored back to back:
-// block s starts at sub_off[s] * b and is n_s x b with leading dimension n_s.
-// The prolongation (sum_s R^sT X_s) is computed as a gather over the inverse
-// map dof -> (s, local index), so every output is written by one thread and the
-// sum order is fixed (no atomics, bitwise reproducible).
+// Multi-column vectors X (n x b) are stored row-major: the b values of a row
+// are contiguous, X[i * b + c].  Restricted vectors R^s X are stored back to
+// back in subdomain order: row l of block s is entry p = sub_off[s] + l, at
+// Xs[p * b + c].  The prolongation sum_s R^sT X_s is computed as a gather over
+// the inverse map dof -> (s, local index), so every output is written by one
+// thread and the sum order is fixed (no atomics, bitwise reproducible).
 #include "awg_sparse.h"
 
 namespace awg {
@@ -169,97 +169,89 @@ __global__ void k_extract(const long* sub_ptr, const int* sub_idx, const int* ro
 // ---------------------------------------------------------------------------
 // multi-column vector kernels
 // ---------------------------------------------------------------------------
-// Y = alpha A X + beta Y for b columns: one thread per row and SPMM_CB
-// columns, so each row's nonzeros are read once per column block.
-constexpr int SPMM_CB = 8;
-__global__ __launch_bounds__(256) void k_spmm(int n, const int* rowptr, const int* col, const double* val,
-                                              const double* X, long ldx, double* Y, long ldy, int b, double alpha,
-                                              double beta) {
+// y = alpha A x + beta y (one column): one thread per row.
+__global__ __launch_bounds__(256) void k_spmv(int n, const int* rowptr, const int* col, const double* val,
+                                              const double* x, double* y, double alpha, double beta) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const int c0 = blockIdx.y * SPMM_CB;
-  const int nc = min(SPMM_CB, b - c0);
-  const double* x = X + c0 * ldx;
-  double acc[SPMM_CB];
-#pragma unroll
-  for (int c = 0; c < SPMM_CB; ++c) acc[c] = 0.0;
-  const int pe = rowptr[i + 1];
-  if (nc == SPMM_CB) {
-    for (int p = rowptr[i]; p < pe; ++p) {
-      const double v = val[p];
-      const long j = col[p];
-#pragma unroll
-      for (int c = 0; c < SPMM_CB; ++c) acc[c] += v * x[j + c * ldx];
-    }
-  } else {
-    for (int p = rowptr[i]; p < pe; ++p) {
-      const double v = val[p];
-      const long j = col[p];
-      for (int c = 0; c < nc; ++c) acc[c] += v * x[j + c * ldx];
-    }
-  }
-  double* y = Y + c0 * ldy + i;
-  for (int c = 0; c < nc; ++c) y[c * ldy] = (beta == 0.0) ? alpha * acc[c] : alpha * acc[c] + beta * y[c * ldy];
-}
-
-__global__ void k_gather(long tot, const int* sub_idx, const int* ent_sub, const long* sub_ptr, const double* X,
-                         long ldx, int b, const double* scale, double* Xs) {
-  const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= tot) return;
-  const int c = blockIdx.y;
-  const int s = ent_sub[p];
-  const long a = sub_ptr[s];
-  const long ns = sub_ptr[s + 1] - a;
-  double v = X[sub_idx[p] + c * ldx];
-  if (scale) v *= scale[p];
-  Xs[a * b + c * ns + (p - a)] = v;
-}
-
-__global__ void k_scatter(int n, const int* inv_ptr, const int* inv_sub, const int* inv_loc, const long* sub_ptr,
-                          const double* Zs, int b, const double* scale, double* Y, long ldy, double alpha,
-                          double beta) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int c = blockIdx.y;
   double acc = 0.0;
-  for (int q = inv_ptr[i]; q < inv_ptr[i + 1]; ++q) {
-    const int s = inv_sub[q];
-    const long a = sub_ptr[s];
-    const long ns = sub_ptr[s + 1] - a;
-    double v = Zs[a * b + c * ns + inv_loc[q]];
-    if (scale) v *= scale[a + inv_loc[q]];
-    acc += v;
-  }
-  double* y = Y + c * ldy + i;
+  const int pe = rowptr[i + 1];
+  for (int p = rowptr[i]; p < pe; ++p) acc += val[p] * x[col[p]];
+  y[i] = (beta == 0.0) ? alpha * acc : alpha * acc + beta * y[i];
+}
+
+// Y = alpha A X + beta Y, X and Y row-major n x b: one wavefront per row and
+// 64 columns; the row's nonzeros are wave-uniform loads and every X row
+// segment is a contiguous 512-byte read.
+__global__ __launch_bounds__(256) void k_spmm_rm(int n, const int* rowptr, const int* col, const double* val,
+                                                 const double* X, double* Y, int b, double alpha, double beta) {
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int c = blockIdx.y * 64 + (threadIdx.x & 63);
+  if (i >= n || c >= b) return;
+  double acc = 0.0;
+  const int pe = rowptr[i + 1];
+  for (int p = rowptr[i]; p < pe; ++p) acc += val[p] * X[(long)col[p] * b + c];
+  double* y = Y + (long)i * b + c;
   *y = (beta == 0.0) ? alpha * acc : alpha * acc + beta * *y;
 }
 
-// out[c] = sum_i X[i,c] Y[i,c] (one workgroup per column, fixed order)
-__global__ __launch_bounds__(256) void k_coldot(int n, const double* X, long ldx, const double* Y, long ldy,
-                                                double* out) {
-  const int c = blockIdx.x;
-  const double* x = X + c * ldx;
-  const double* y = Y + c * ldy;
-  double acc = 0.0;
-  for (int i = threadIdx.x; i < n; i += 256) acc += x[i] * y[i];
-  __shared__ double sh[4];
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
-  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
-  __syncthreads();
-  if (threadIdx.x == 0) out[c] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+// Xs[p, :] = X[sub_idx[p], :]  (row copies)
+__global__ void k_gather(long tot, const int* sub_idx, const double* X, int b, double* Xs) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= tot * b) return;
+  const long p = e / b;
+  const int c = (int)(e - p * b);
+  Xs[e] = X[(long)sub_idx[p] * b + c];
 }
 
-// Y[:,c] = sa a[c] X[:,c] + sb b[c] Y[:,c]   (a or b may be null: 1)
-__global__ void k_colaxpby(int n, const double* X, long ldx, const double* a, double* Y, long ldy, const double* bb,
-                           double sa, double sb) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int c = blockIdx.y;
+// Y[i, :] = beta Y[i, :] + alpha sum over (s, l) holding i of Zs[sub_off[s] + l, :]
+__global__ void k_scatter(int n, const int* inv_ptr, const int* inv_sub, const int* inv_loc, const long* sub_ptr,
+                          const double* Zs, int b, double* Y, double alpha, double beta) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long)n * b) return;
+  const int i = (int)(e / b);
+  const int c = (int)(e - (long)i * b);
+  double acc = 0.0;
+  for (int q = inv_ptr[i]; q < inv_ptr[i + 1]; ++q)
+    acc += Zs[(sub_ptr[inv_sub[q]] + inv_loc[q]) * b + c];
+  Y[e] = (beta == 0.0) ? alpha * acc : alpha * acc + beta * Y[e];
+}
+
+// per-column dot products of row-major X, Y (n x b), two passes with a fixed
+// order: partial sums over DOT_CHUNKS row ranges, then their sum.
+constexpr int DOT_CHUNKS = 128;
+__global__ __launch_bounds__(256) void k_coldot_part(int n, int b, const double* X, const double* Y,
+                                                     double* part) {
+  const int cl = threadIdx.x & 63, rl = threadIdx.x >> 6;
+  const int c = blockIdx.x * 64 + cl;
+  const int chunk = blockIdx.y;
+  const int r0 = (int)((long)n * chunk / DOT_CHUNKS), r1 = (int)((long)n * (chunk + 1) / DOT_CHUNKS);
+  double acc = 0.0;
+  if (c < b)
+    for (int i = r0 + rl; i < r1; i += 4) acc += X[(long)i * b + c] * Y[(long)i * b + c];
+  __shared__ double sh[4][64];
+  sh[rl][cl] = acc;
+  __syncthreads();
+  if (rl == 0 && c < b) part[(long)chunk * b + c] = (sh[0][cl] + sh[1][cl]) + (sh[2][cl] + sh[3][cl]);
+}
+
+__global__ void k_coldot_sum(int b, const double* part, double* out) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= b) return;
+  double acc = 0.0;
+  for (int k = 0; k < DOT_CHUNKS; ++k) acc += part[(long)k * b + c];
+  out[c] = acc;
+}
+
+// Y[i, c] = sa a[c] X[i, c] + sb bb[c] Y[i, c]   (a or bb may be null: 1)
+__global__ void k_colaxpby(long tot, int b, const double* X, const double* a, double* Y, const double* bb, double sa,
+                           double sb) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= tot) return;
+  const int c = (int)(e % b);
   const double ac = (a ? a[c] : 1.0) * sa;
   const double bc = (bb ? bb[c] : 1.0) * sb;
-  double* y = Y + c * ldy + i;
-  *y = ac * X[c * ldx + i] + bc * *y;
+  Y[e] = ac * X[e] + bc * Y[e];
 }
 
 // ---------------------------------------------------------------------------
@@ -440,43 +432,46 @@ void l_extract(int N, const long* sub_ptr, const int* sub_idx, const int* rowptr
   hipLaunchKernelGGL(k_extract, dim3(N), dim3(256), 0, s, sub_ptr, sub_idx, rowptr, col, vals, mats);
   AWG_LAUNCH_CHECK();
 }
-void l_spmm(int n, long nnz, const int* rowptr, const int* col, const double* val, const double* X, long ldx,
-            double* Y, long ldy, int b, double alpha, double beta, hipStream_t s) {
+void l_spmm(int n, long nnz, const int* rowptr, const int* col, const double* val, const double* X, double* Y, int b,
+            double alpha, double beta, hipStream_t s) {
   if (n == 0 || b == 0) return;
-  KScope kt("k_spmm", s,
+  KScope kt(b == 1 ? "k_spmv" : "k_spmm_rm", s,
             12.0 * nnz + 4.0 * (n + 1) + 16.0 * n * (double)b + (beta != 0.0 ? 8.0 * n * (double)b : 0.0),
             2.0 * nnz * (double)b);
-  hipLaunchKernelGGL(k_spmm, dim3(grid1(n), cdiv(b, SPMM_CB)), dim3(256), 0, s, n, rowptr, col, val, X, ldx, Y, ldy, b,
-                     alpha, beta);
+  if (b == 1)
+    hipLaunchKernelGGL(k_spmv, dim3(grid1(n)), dim3(256), 0, s, n, rowptr, col, val, X, Y, alpha, beta);
+  else
+    hipLaunchKernelGGL(k_spmm_rm, dim3(cdiv(n, 4), cdiv(b, 64)), dim3(256), 0, s, n, rowptr, col, val, X, Y, b,
+                       alpha, beta);
   AWG_LAUNCH_CHECK();
 }
-void l_gather(long tot, const int* sub_idx, const int* ent_sub, const long* sub_ptr, const double* X, long ldx,
-              int b, const double* scale, double* Xs, hipStream_t s) {
+void l_gather(long tot, const int* sub_idx, const double* X, int b, double* Xs, hipStream_t s) {
   if (tot == 0 || b == 0) return;
-  KScope kt("k_gather", s, 8.0 * tot * (double)b + 8.0 * tot + 8.0 * (double)tot * b, 0.0);
-  hipLaunchKernelGGL(k_gather, dim3(grid1(tot), b), dim3(256), 0, s, tot, sub_idx, ent_sub, sub_ptr, X, ldx, b,
-                     scale, Xs);
+  KScope kt("k_gather", s, 16.0 * tot * (double)b + 4.0 * tot, 0.0);
+  hipLaunchKernelGGL(k_gather, dim3(grid1(tot * b)), dim3(256), 0, s, tot, sub_idx, X, b, Xs);
   AWG_LAUNCH_CHECK();
 }
 void l_scatter(int n, long tot, const int* inv_ptr, const int* inv_sub, const int* inv_loc, const long* sub_ptr,
-               const double* Zs, int b, const double* scale, double* Y, long ldy, double alpha, double beta,
-               hipStream_t s) {
+               const double* Zs, int b, double* Y, double alpha, double beta, hipStream_t s) {
   if (n == 0 || b == 0) return;
-  KScope kt("k_scatter", s, 8.0 * (double)tot * b + 8.0 * tot + 4.0 * n + 8.0 * n * (double)b * (beta != 0.0 ? 2.0 : 1.0),
+  KScope kt("k_scatter", s,
+            8.0 * (double)tot * b + 8.0 * tot + 4.0 * n + 8.0 * n * (double)b * (beta != 0.0 ? 2.0 : 1.0),
             (double)tot * b);
-  hipLaunchKernelGGL(k_scatter, dim3(grid1(n), b), dim3(256), 0, s, n, inv_ptr, inv_sub, inv_loc, sub_ptr, Zs, b,
-                     scale, Y, ldy, alpha, beta);
+  hipLaunchKernelGGL(k_scatter, dim3(grid1((long)n * b)), dim3(256), 0, s, n, inv_ptr, inv_sub, inv_loc, sub_ptr, Zs,
+                     b, Y, alpha, beta);
   AWG_LAUNCH_CHECK();
 }
-void l_coldot(int n, int b, const double* X, long ldx, const double* Y, long ldy, double* out, hipStream_t s) {
+void l_coldot(int n, int b, const double* X, const double* Y, double* part, double* out, hipStream_t s) {
   if (b == 0) return;
-  hipLaunchKernelGGL(k_coldot, dim3(b), dim3(256), 0, s, n, X, ldx, Y, ldy, out);
+  hipLaunchKernelGGL(k_coldot_part, dim3(cdiv(b, 64), DOT_CHUNKS), dim3(256), 0, s, n, b, X, Y, part);
+  AWG_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_coldot_sum, dim3(cdiv(b, 256)), dim3(256), 0, s, b, part, out);
   AWG_LAUNCH_CHECK();
 }
-void l_colaxpby(int n, int b, const double* X, long ldx, const double* a, double* Y, long ldy, const double* bb,
-                double sa, double sb, hipStream_t s) {
-  if (n == 0 || b == 0) return;
-  hipLaunchKernelGGL(k_colaxpby, dim3(grid1(n), b), dim3(256), 0, s, n, X, ldx, a, Y, ldy, bb, sa, sb);
+void l_colaxpby(long rows, int b, const double* X, const double* a, double* Y, const double* bb, double sa, double sb,
+                hipStream_t s) {
+  if (rows == 0 || b == 0) return;
+  hipLaunchKernelGGL(k_colaxpby, dim3(grid1(rows * b)), dim3(256), 0, s, rows * b, b, X, a, Y, bb, sa, sb);
   AWG_LAUNCH_CHECK();
 }
 void l_set_identity(const MatDesc* mats, int batch, hipStream_t s) {

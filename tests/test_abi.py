@@ -33,7 +33,7 @@ def test_library_exports_every_declared_symbol():
 def test_default_options_and_setup_argument_errors():
     """Host-side argument checks run before any GPU work."""
     o = awg.default_options()
-    assert o.tau == 0.1 and o.zero_tol == 1e-12 and o.local_prec == 0
+    assert o.tau == 0.1 and o.zero_tol == 1e-12 and o.w_rtol == 1e-10 and o.local_prec == 0
     L = awg.lib()
     ctx = ctypes.c_void_p()
     assert L.awg_setup(None, 1, 1, None, None, None, 1, None, None, None) == -1

@@ -31,7 +31,8 @@ def spd(rng, batch, n, cond=1e3):
 
 @pytest.mark.parametrize("tA", [False, True])
 @pytest.mark.parametrize("tB", [False, True])
-@pytest.mark.parametrize("mnk", [(100, 70, 37), (64, 64, 16), (1, 130, 5), (131, 1, 200), (7, 9, 1)])
+@pytest.mark.parametrize("mnk", [(100, 70, 37), (64, 64, 16), (1, 130, 5), (131, 1, 200), (7, 9, 1),
+                                 (300, 260, 70), (128, 128, 16), (257, 129, 33), (130, 700, 3)])
 def test_gemm(gpu_lib, tA, tB, mnk):
     m, n, k = mnk
     rng = np.random.default_rng(m * 7 + n * 3 + k)
