@@ -1,0 +1,104 @@
+"""The bench workload at full size (Q1 256x256, n = 65,792, 64 subdomains),
+in the launch configuration bench.py times (default options).
+
+The oracle's full run takes minutes, so its results are stored in
+tests/golden/q1_2d_256.json by tests/golden/make_q1_2d_256.py (oracle only);
+per-subdomain quantities are recomputed here by the oracle on a sample.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import awg_problems as P
+from oracle import awg_oracle as O
+
+pytestmark = pytest.mark.gpu
+GOLD_PATH = os.path.join(os.path.dirname(__file__), "golden", "q1_2d_256.json")
+
+
+@pytest.fixture(scope="module")
+def run(gpu_lib):
+    import torch
+    if not os.path.exists(GOLD_PATH):
+        pytest.skip("golden file missing")
+    gold = json.load(open(GOLD_PATH))
+    w = P.q1_2d(256)
+    print(f"\n[gpu case] q1_2d_256 n={w.A.shape[0]} N={len(w.subs)}", flush=True)
+    solver = gpu_lib.Solver(w.A, w.subs, tau=w.tau)
+    x, info = solver.pcg(torch.as_tensor(w.b, device="cuda"), tol=w.tol, maxit=1000)
+    yield w, gold, solver, x.cpu().numpy(), info
+    solver.close()
+
+
+def test_coarse_sizes_exact(run):
+    w, gold, solver, x, info = run
+    s = solver.stats()
+    assert s["n_minus"] == gold["n_minus"] and s["n0"] == gold["n0"]
+    assert s["k_s"] == gold["k_s"] and s["kstrict_s"] == gold["kstrict_s"] and s["m_s"] == gold["m_s"]
+
+
+def test_pcg_iterate_and_count(run):
+    w, gold, solver, x, info = run
+    assert info["converged"] == 1
+    assert abs(info["iters"] - gold["iters"]) <= 1
+    xs = x[np.array(gold["x_idx"])]
+    ref = np.array(gold["x_val"])
+    # sampled entries against the oracle, scaled by the oracle's ||x||
+    assert np.max(np.abs(xs - ref)) <= 1e-10 * gold["x_norm"]
+    assert info["rel_res_true"] <= 2 * w.tol
+
+
+def coloring_constant_Aplus(subs, n):
+    """Greedy coloring of the conflict graph of A_+ = sum_u R^uT A^u_+ R^u:
+    s and t conflict when some Omega^u meets both (Definition of the coloring
+    constant, Section 2.2)."""
+    import scipy.sparse as sp
+    N = len(subs)
+    rows = np.concatenate([np.full(len(t), k) for k, t in enumerate(subs)])
+    Pm = sp.csr_matrix((np.ones(rows.size), (rows, np.concatenate(subs))), shape=(N, n))
+    Ov = (Pm @ Pm.T).toarray() > 0
+    C = (Ov.astype(float) @ Ov.astype(float)) > 0
+    color = -np.ones(N, dtype=int)
+    for s in range(N):
+        used = set(color[np.flatnonzero(C[s])].tolist())
+        c = 0
+        while c in used:
+            c += 1
+        color[s] = c
+    return int(color.max() + 1)
+
+
+def test_spectral_estimates_inside_theorem_bound(run):
+    """Lanczos estimates of spec(HA) from the GPU's PCG coefficients lie in
+    [1, N(A_+)/tau + 1] (Thm on H^NN_hyb, Section 3.4, and the H3,ad bound)
+    and agree with the oracle's."""
+    w, gold, solver, x, info = run
+    ncol = coloring_constant_Aplus(w.subs, w.A.shape[0])
+    assert info["lmin_est"] >= 1 - 1e-6
+    assert info["lmax_est"] <= ncol / w.tau + 1
+    assert abs(info["lmax_est"] - gold["lmax"]) <= 1e-3 * gold["lmax"]
+    assert abs(info["lmin_est"] - gold["lmin"]) <= 1e-3
+
+
+@pytest.mark.parametrize("s", [0, 9, 27, 63])
+def test_sampled_subdomains(run, s):
+    """Non-positive eigenpairs of B^s and the local operator P^s on sampled
+    subdomains, recomputed by the oracle one by one."""
+    w, gold, solver, x, info = run
+    cnt = O.pair_multiplicity(w.A, w.subs)
+    B = O.algebraic_B(w.A, cnt)
+    sp_ = O.split_local(O.local_block(B, w.subs[s]))
+    ns = [len(t) for t in w.subs]
+    neg = solver.export("neg_eigs")
+    koff = int(np.sum(gold["k_s"][:s]))
+    k = gold["k_s"][s]
+    assert k == sp_.nneg
+    assert np.max(np.abs(neg[koff:koff + k] - sp_.L_minus)) <= 1e-11 * np.abs(sp_.lam).max()
+    Pl = solver.export("P_local")
+    off = int(np.sum(np.array(ns[:s], dtype=np.int64) ** 2))
+    Ps = Pl[off:off + ns[s] ** 2].reshape(ns[s], ns[s]).T
+    D = O.partition_of_unity(w.A.shape[0], w.subs)[s]
+    ref = D[:, None] * sp_.A_plus_pinv() * D[None, :]
+    assert np.linalg.norm(Ps - ref) <= 1e-8 * np.linalg.norm(ref)
