@@ -35,6 +35,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--local-prec", default="f64", choices=["f64", "f32"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fast-form", action="store_true")
     ap.add_argument("--m", type=int, default=256, help="cells per side (256 = the bench workload)")
     return ap.parse_args()
 
@@ -138,8 +139,8 @@ def main():
     bd = torch.as_tensor(w.b, device=dev)
     x = torch.empty_like(bd)
 
-    def step():
-        solver = awg.Solver(Ad, Sd, tau=w.tau, local_prec=args.local_prec)
+    def step(local_prec=args.local_prec):
+        solver = awg.Solver(Ad, Sd, tau=w.tau, local_prec=local_prec)
         _, info = solver.pcg(bd, tol=w.tol, maxit=1000, x=x)
         st = solver.stats()
         solver.close()
@@ -190,6 +191,20 @@ def main():
                   "w_iters": st["w_iters"]},
         "phases_ms": phases,
     }
+    if not args.no_fast_form and args.local_prec == "f64":
+        # the same workload with FP32 local operators (eigen-setup, coarse
+        # spaces, PCG and W recurrences stay FP64)
+        step("f32")
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for i in range(args.steps):
+            info32, st32 = step("f32")
+        torch.cuda.synchronize()
+        ms32 = (time.perf_counter() - t1) * 1e3 / args.steps
+        out["fast_form"] = {"local_prec": "f32", "ms_per_step": round(ms32, 3), "iters": info32["iters"],
+                            "rel_res_true": info32["rel_res_true"], "n_minus": st32["n_minus"], "n0": st32["n0"],
+                            "w_iters": st32["w_iters"], "speedup_vs_f64": round(ms / ms32, 3),
+                            "phases_ms": {k: round(v, 3) for k, v in st32["ms"].items()}}
     out["roofline"] = roofline(kt, args.steps)
     out["kernels_ms_per_step"] = {k: round(v["ms"] / args.steps, 3) for k, v in
                                   sorted(kt.items(), key=lambda kv: -kv[1]["ms"])}

@@ -99,6 +99,14 @@ struct GemmDesc {
   int lda, ldb, ldc;
 };
 
+struct GemmDescMix {     // FP64 A, FP32 B, FP64 C (FP32 local operators)
+  const double* A;
+  const float* B;
+  double* C;
+  int m, n, k;
+  int lda, ldb, ldc;
+};
+
 struct MatDesc {         // one square or rectangular column-major block
   double* A;
   int m, n, ld;
@@ -113,6 +121,9 @@ struct MatDesc {         // one square or rectangular column-major block
 // flops: algorithmic flop count of the whole batch (for the kernel timer only)
 void gemm_batched(const GemmDesc* d_desc, int batch, int max_m, int max_n, bool transA, bool transB,
                   double alpha, double beta, bool lower, hipStream_t s, double flops = 0.0);
+// C = alpha A B + beta C with FP32 B (A rounded to FP32, FP32 MFMA and accumulation)
+void gemm_mix_batched(const GemmDescMix* d_desc, int batch, int max_m, int max_n, double alpha, double beta,
+                      hipStream_t s, double flops);
 // y = alpha * op(A) x + beta * y per descriptor, with the GEMM convention
 // (n == 1: A = matrix, B = x, C = y; op(A) is m x k).
 void gemv_batched(const GemmDesc* d_desc, int batch, int max_m, int max_k, bool transA, double alpha,

@@ -142,6 +142,7 @@ struct MultiWS {
   DBuf<double> H0, H1;                // n_minus x b
   DBuf<double> dotpart, dots;         // column dot products
   DBuf<GemmDesc> dVt, dV, dYt, dY, dP, dE0a, dE0b, dWt, dEW, dW;
+  DBuf<GemmDescMix> dP32;             // FP32 local operators (b > 1)
   int maxk = 0, maxm = 0, maxns = 0;
   double flV = 0, flY = 0, flP = 0, flE0 = 0, flW = 0, flEW = 0;   // algorithmic flops per product
 };
@@ -375,6 +376,15 @@ void build_ws(awg_ctx& c, MultiWS& w, int b) {
   gemm_upload(w.dYt, yt, s);
   gemm_upload(w.dY, yy, s);
   gemm_upload(w.dP, pp, s);
+  if (c.P32.p && b > 1) {
+    std::vector<GemmDescMix> pm(c.N);
+    for (int q = 0; q < c.N; ++q) {
+      const int nsq = c.ns[q];
+      const long so = c.h_subptr[q] * b;
+      pm[q] = GemmDescMix{w.Xs.p + so, c.P32.p + c.sqoff[q], w.Os.p + so, b, nsq, nsq, b, nsq, b};
+    }
+    w.dP32.upload(pm, s);
+  }
   const int n0 = std::max(1, c.n0), nm = std::max(1, c.nminus);
   w.flE0 = 2.0 * c.n0 * (double)c.n0 * b;
   w.flW = 2.0 * c.n * (double)c.nminus * b;
@@ -415,19 +425,22 @@ void op_r0(awg_ctx& c, MultiWS& w, const double* X) {
   bmm(w.dYt, c.N, w.maxm, w.maxns, false, 1.0, 0.0, w.b, c.s, w.flY);
 }
 
-// Yo = beta Yo + R0^T G1
-void op_r0t(awg_ctx& c, MultiWS& w, double* Yo, double beta) {
+// Yo = beta Yo + alpha R0^T G1
+void op_r0t(awg_ctx& c, MultiWS& w, double* Yo, double beta, double alpha = 1.0) {
   bmm(w.dY, c.N, w.maxns, w.maxm, true, 1.0, 0.0, w.b, c.s, w.flY);
-  l_scatter(c.n, c.sumns, c.invptr, c.invsub, c.invloc, c.subptr, w.Os, w.b, Yo, 1.0, beta, c.s);
+  l_scatter(c.n, c.sumns, c.invptr, c.invsub, c.invloc, c.subptr, w.Os, w.b, Yo, alpha, beta, c.s);
 }
 
 // Yo = H^NN X = sum_s R^sT P^s R^s X with P^s = D^s (A^s_+)^+ D^s (Definition of H^NN, Section 3.3)
 void op_hnn(awg_ctx& c, MultiWS& w, const double* X, double* Yo, bool f32) {
   l_gather(c.sumns, c.subidx, X, w.b, w.Xs, c.s);
   if (f32 && w.b == 1) {
+    KScope kt("k_gemv_f32", c.s, 4.0 * c.sqtot, 2.0 * c.sqtot);
     hipLaunchKernelGGL(k_gemv_f32, dim3(cdiv(w.maxns, 64), c.N), dim3(256), 0, c.s, c.P32.p, c.d_sqoff.p,
                        c.subptr.p, w.Xs.p, w.Os.p);
     AWG_LAUNCH_CHECK();
+  } else if (f32) {
+    gemm_mix_batched(w.dP32, c.N, w.b, w.maxns, 1.0, 0.0, c.s, w.flP);
   } else {
     bmm(w.dP, c.N, w.maxns, w.maxns, false, 1.0, 0.0, w.b, c.s, w.flP);
   }
@@ -839,20 +852,24 @@ void phase_W(awg_ctx& c) {
     AWG_HIP(hipStreamSynchronize(s));
     return h;
   };
+  const bool f32 = c.opt.local_prec == AWG_LOCAL_F32;
+  DBuf<double> Zold;
+  if (f32) Zold.alloc((long)c.n * b);
   for (int c0 = 0; c0 < c.nminus; c0 += b) {
     const int bc = std::min(b, c.nminus - c0);
     w.R.zero(s);
     hipLaunchKernelGGL(k_build_vg, dim3(64, c.N), dim3(256), 0, s, c.subptr.p, c.subidx.p, c.V.p, c.LV.d_eoff.p,
                        dgcoff.p, w.R.p, c0, b);
     AWG_LAUNCH_CHECK();
-    X.zero(s);
     auto h = coldot(w.R, w.R);
     for (int j = 0; j < b; ++j) {
       bn[j] = std::sqrt(h[j]);
       active[j] = (j < bc && bn[j] > 0.0) ? 1 : 0;
     }
-    op_h2(c, w, false);
+    X.zero(s);
+    op_h2(c, w, f32);
     AWG_HIP(hipMemcpyAsync(Pm.p, w.Z.p, sizeof(double) * c.n * b, hipMemcpyDeviceToDevice, s));
+    if (f32) AWG_HIP(hipMemcpyAsync(Zold.p, w.Z.p, sizeof(double) * c.n * b, hipMemcpyDeviceToDevice, s));
     h = coldot(w.R, w.Z);
     for (int j = 0; j < b; ++j) rz[j] = h[j];
     int it = 0;
@@ -873,12 +890,16 @@ void phase_W(awg_ctx& c) {
         nact += active[j];
       }
       if (nact == 0) { ++it; break; }
-      op_h2(c, w, false);
+      op_h2(c, w, f32);
       h = coldot(w.R, w.Z);
+      std::vector<double> hz;
+      if (f32) hz = coldot(w.R, Zold);   // flexible (Polak-Ribiere) beta for the FP32 local operators
       for (int j = 0; j < b; ++j) {
-        beta[j] = active[j] ? h[j] / rz[j] : 0.0;
+        const double num = f32 ? h[j] - hz[j] : h[j];
+        beta[j] = active[j] ? num / rz[j] : 0.0;
         if (active[j]) rz[j] = h[j];
       }
+      if (f32) AWG_HIP(hipMemcpyAsync(Zold.p, w.Z.p, sizeof(double) * c.n * b, hipMemcpyDeviceToDevice, s));
       AWG_HIP(hipMemcpyAsync(alpha_d.p, beta.data(), sizeof(double) * b, hipMemcpyHostToDevice, s));
       l_colaxpby(c.n, b, w.Z, nullptr, Pm, alpha_d, 1.0, 1.0, s);   // P = Z + beta P
       sync(c);   // the host buffer of beta is reused next iteration

@@ -272,6 +272,99 @@ __global__ __launch_bounds__(256) void k_gemm128(DF df, double alpha, double bet
       }
 }
 
+// ---------------------------------------------------------------------------
+// mixed-precision GEMM for FP32 local operators: C (FP64) = alpha A B + beta C
+// with A FP64 (rounded to FP32 when staged in LDS), B FP32, FP32 MFMA
+// 16x16x4 and FP32 accumulation.  FP32 16x16x4 output layout (checked on
+// gfx950): lane l holds D[4*(l/16) + r][l % 16].
+// ---------------------------------------------------------------------------
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(256) void k_gemm128_mix(const GemmDescMix* descs, double alpha, double beta) {
+  const GemmDescMix d = descs[blockIdx.z];
+  const int m0 = blockIdx.x * 128, n0 = blockIdx.y * 128;
+  if (m0 >= d.m || n0 >= d.n) return;
+  __shared__ float As[2][16][132];
+  __shared__ float Bs[2][16][132];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wm = (wave & 1) * 64, wn = (wave >> 1) * 64;
+  v4f acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = (v4f){0.f, 0.f, 0.f, 0.f};
+  float ra[8], rb[8];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const int e = tid + r * 256;
+      const int i = e & 127, kk = e >> 7;
+      const int gi = m0 + i, gk = k0 + kk;
+      ra[r] = (gi < d.m && gk < d.k) ? (float)d.A[gi + (long)gk * d.lda] : 0.f;
+      const int kb = e & 15, j = e >> 4;
+      const int gj = n0 + j, gkb = k0 + kb;
+      rb[r] = (gj < d.n && gkb < d.k) ? d.B[gkb + (long)gj * d.ldb] : 0.f;
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const int e = tid + r * 256;
+      As[buf][e >> 7][e & 127] = ra[r];
+      Bs[buf][e & 15][e >> 4] = rb[r];
+    }
+  };
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  int buf = 0;
+  for (int k0 = 0; k0 < d.k; k0 += 16) {
+    const bool more = k0 + 16 < d.k;
+    if (more) gload(k0 + 16);
+#pragma unroll
+    for (int kk = 0; kk < 16; kk += 4) {
+      const int kr = kk + (lane >> 4), c = lane & 15;
+      float a[4], b[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        a[q] = As[buf][kr][wm + q * 16 + c];
+        b[q] = Bs[buf][kr][wn + q * 16 + c];
+      }
+#pragma unroll
+      for (int qa = 0; qa < 4; ++qa)
+#pragma unroll
+        for (int qb = 0; qb < 4; ++qb)
+          acc[qa][qb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[qa], b[qb], acc[qa][qb], 0, 0, 0);
+    }
+    if (more) sstore(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+#pragma unroll
+  for (int qa = 0; qa < 4; ++qa)
+#pragma unroll
+    for (int qb = 0; qb < 4; ++qb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = m0 + wm + qa * 16 + 4 * (lane >> 4) + r;
+        const int j = n0 + wn + qb * 16 + (lane & 15);
+        if (i < d.m && j < d.n) {
+          double* cp = d.C + i + (long)j * d.ldc;
+          const double v = alpha * (double)acc[qa][qb][r];
+          *cp = (beta == 0.0) ? v : v + beta * *cp;
+        }
+      }
+}
+
+void gemm_mix_batched(const GemmDescMix* d_desc, int batch, int max_m, int max_n, double alpha, double beta,
+                      hipStream_t s, double flops) {
+  if (batch <= 0 || max_m <= 0 || max_n <= 0) return;
+  KScope kt("k_gemm128_mix", s, 0.0, flops);
+  hipLaunchKernelGGL(k_gemm128_mix, dim3(cdiv(max_m, 128), cdiv(max_n, 128), batch), dim3(256), 0, s, d_desc, alpha,
+                     beta);
+  AWG_LAUNCH_CHECK();
+}
+
 template <class DF>
 static const char* gemm_name(bool tA, bool tB);
 template <>
@@ -296,8 +389,10 @@ template <class DF>
 static void launch_gemm(DF df, int batch, int max_m, int max_n, bool tA, bool tB, double alpha, double beta,
                         bool lower, hipStream_t s, double flops = 0.0) {
   if (batch <= 0 || max_m <= 0 || max_n <= 0) return;
-  KScope kt(gemm_name<DF>(tA, tB), s, 0.0, flops);
-  if (use_big_tiles<DF>() && max_m >= 128) {
+  const bool big = use_big_tiles<DF>() && max_m >= 128;
+  const std::string nm = std::string(big ? "k_gemm128" : "k_gemm") + (gemm_name<DF>(tA, tB) + 6);
+  KScope kt(nm.c_str(), s, 0.0, flops);
+  if (big) {
     dim3 grid(cdiv(max_m, 128), cdiv(max_n, 128), batch);
     if (!tA && !tB) hipLaunchKernelGGL((k_gemm128<DF, false, false>), grid, dim3(256), 0, s, df, alpha, beta, (int)lower);
     else if (tA && !tB) hipLaunchKernelGGL((k_gemm128<DF, true, false>), grid, dim3(256), 0, s, df, alpha, beta, (int)lower);

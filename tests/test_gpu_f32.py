@@ -1,0 +1,36 @@
+"""FP32 local operators (local_prec = f32): the eigen-setup stays FP64, so the
+coarse spaces are identical; the local products run in FP32 (mixed GEMM in
+the W solves, FP32 GEMV in PCG).  Judged by the true final residual and the
+iteration increase over the FP64 form (no element-wise parity: the operator
+itself differs by FP32 rounding)."""
+import numpy as np
+import pytest
+
+import awg_problems as P
+
+pytestmark = pytest.mark.gpu
+
+CASES = {"fd5_32": P.fd5_32, "q1_2d_64": lambda: P.q1_2d(m=64, boxes=(2, 2))}
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_f32_local_converges(gpu_lib, name):
+    import torch
+    w = CASES[name]()
+    print(f"\n[gpu case] f32 {name} n={w.A.shape[0]}", flush=True)
+    b = torch.as_tensor(w.b, device="cuda")
+    s64 = gpu_lib.Solver(w.A, w.subs, tau=w.tau, local_prec="f64")
+    s32 = gpu_lib.Solver(w.A, w.subs, tau=w.tau, local_prec="f32")
+    st64, st32 = s64.stats(), s32.stats()
+    assert st32["n_minus"] == st64["n_minus"] and st32["n0"] == st64["n0"]
+    x64, i64 = s64.pcg(b, tol=w.tol)
+    x32, i32 = s32.pcg(b, tol=w.tol)
+    assert i32["converged"] == 1
+    assert i32["rel_res_true"] <= 2 * w.tol
+    assert i32["iters"] <= i64["iters"] + 3
+    r = torch.as_tensor(np.random.default_rng(0).standard_normal(w.A.shape[0]), device="cuda")
+    z64, z32 = s64.apply(r), s32.apply(r)
+    rel = (torch.linalg.norm(z32 - z64) / torch.linalg.norm(z64)).item()
+    assert rel <= 1e-3
+    s64.close()
+    s32.close()
