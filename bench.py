@@ -101,7 +101,8 @@ def roofline(kt: dict, steps: int) -> dict:
     achieved = algorithmic bytes (or flops) of all its launches / their total
     duration (HIP events on the launching stream).
     """
-    name, rec = max(kt.items(), key=lambda kv: kv[1]["ms"])
+    kernels = {k: v for k, v in kt.items() if not k.startswith("graph:")}
+    name, rec = max(kernels.items(), key=lambda kv: kv[1]["ms"])
     avg_us = rec["ms"] * 1e3 / rec["calls"]
     if name.startswith(MFMA_KERNELS):
         achieved = rec["flops"] / (rec["ms"] * 1e-3) / 1e12

@@ -105,9 +105,16 @@ typedef struct {
 
 /* PCG (Saad, Section 9.2) from x0 = 0 with the AWG preconditioner; stops at
  * the first k with ||r_k||_2 / ||b||_2 <= tol on the recursive residual.
- * b, x: device vectors of length n.  info: host pointer (may be NULL). */
+ * b, x: device vectors of length n.  info: host pointer (may be NULL).
+ * maxit > 4095 is treated as 4095 (size of the coefficient history). */
 int awg_pcg(awg_ctx* ctx, const double* b, double* x, double tol, int32_t maxit,
             awg_pcg_info* info);
+
+/* awg_pcg runs each iteration as one captured HIP graph (default, enable != 0)
+ * or as eager launches of the same kernels (enable = 0).  Convergence is
+ * decided on the device; the host checks it every few iterations, and
+ * iterations launched after convergence leave x unchanged. */
+int awg_pcg_graph(awg_ctx* ctx, int32_t enable);
 
 /* JSON description of the setup (n, N, n_minus, n0, per-subdomain counts,
  * per-phase times in ms).  buf: host buffer of cap bytes.  Returns the

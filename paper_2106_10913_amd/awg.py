@@ -23,7 +23,7 @@ STATUS = {0: "AWG_OK", 1: "AWG_NOT_CONVERGED", -1: "AWG_ERR_ARG", -2: "AWG_ERR_N
           -7: "AWG_ERR_HIP", -8: "AWG_ERR_OOM", -9: "AWG_ERR_NONFINITE"}
 
 EXPORTED = ["awg_default_options", "awg_setup", "awg_apply", "awg_pcg", "awg_stats", "awg_export",
-            "awg_last_error", "awg_destroy", "awg_kernel_timing", "awg_kernel_times",
+            "awg_last_error", "awg_destroy", "awg_kernel_timing", "awg_kernel_times", "awg_pcg_graph",
             "awg_dense_gemm", "awg_dense_potrf", "awg_dense_trsm", "awg_dense_low_eigs"]
 
 
@@ -73,6 +73,8 @@ def lib():
     L.awg_last_error.restype = ctypes.c_char_p
     L.awg_destroy.argtypes = [vp]
     L.awg_destroy.restype = None
+    L.awg_pcg_graph.argtypes = [vp, i32]
+    L.awg_pcg_graph.restype = ctypes.c_int
     L.awg_kernel_timing.argtypes = [i32]
     L.awg_kernel_timing.restype = ctypes.c_int
     L.awg_kernel_times.argtypes = [ctypes.c_char_p, ctypes.c_size_t, i32]
@@ -188,6 +190,9 @@ class Solver:
         d = {k: getattr(info, k) for k, _ in PCGInfo._fields_}
         d["status"] = STATUS.get(rc, rc)
         return x, d
+
+    def use_graph(self, enable: bool) -> None:
+        self._check(lib().awg_pcg_graph(self._ctx, int(enable)))
 
     def stats(self) -> dict:
         L = lib()

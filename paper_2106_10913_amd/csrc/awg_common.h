@@ -85,6 +85,7 @@ struct KScope {
   hipStream_t s_ = nullptr;
 };
 void ktimer_enable(bool on);
+void ktimer_capturing(bool on);
 bool ktimer_on();
 std::string ktimer_json(bool reset);
 
@@ -125,9 +126,14 @@ void gemm_batched(const GemmDesc* d_desc, int batch, int max_m, int max_n, bool 
 void gemm_mix_batched(const GemmDescMix* d_desc, int batch, int max_m, int max_n, double alpha, double beta,
                       hipStream_t s, double flops);
 // y = alpha * op(A) x + beta * y per descriptor, with the GEMM convention
-// (n == 1: A = matrix, B = x, C = y; op(A) is m x k).
+// (n == 1: A = matrix, B = x, C = y; op(A) is m x k).  A single long
+// non-transposed product (k >= 16 m) splits k over GEMV_KSPLIT ranges when the
+// caller passes `part`, a device buffer of GEMV_KSPLIT * max_m doubles owned
+// by the caller's workspace (so concurrent solvers and captured graphs never
+// share it).
+constexpr int GEMV_KSPLIT = 64;
 void gemv_batched(const GemmDesc* d_desc, int batch, int max_m, int max_k, bool transA, double alpha,
-                  double beta, hipStream_t s, double bytes = 0.0);
+                  double beta, hipStream_t s, double bytes = 0.0, double* part = nullptr);
 
 // Cholesky A = L L^T (lower, in place) of every block; info[b] = 0 or the
 // 1-based column of the first non-positive pivot.

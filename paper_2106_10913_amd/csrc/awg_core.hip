@@ -33,6 +33,7 @@ struct KAcc {
   double calls = 0, ms = 0, bytes = 0, flops = 0;
 };
 bool g_kt_on = false;
+bool g_kt_capturing = false;   // no event records while a graph is being captured
 std::vector<KRec> g_kt_pending;
 std::vector<hipEvent_t> g_kt_pool;
 std::map<std::string, KAcc> g_kt_acc;
@@ -66,7 +67,7 @@ void kt_flush() {
 }  // namespace
 
 KScope::KScope(const char* name, hipStream_t s, double bytes, double flops) : s_(s) {
-  if (!g_kt_on) return;
+  if (!g_kt_on || g_kt_capturing) return;
   if (g_kt_pending.size() >= 8192) kt_flush();
   KRec r{name, kt_event(), kt_event(), bytes, flops};
   AWG_HIP(hipEventRecord(r.a, s));
@@ -79,6 +80,7 @@ KScope::~KScope() {
 }
 
 void ktimer_enable(bool on) { g_kt_on = on; }
+void ktimer_capturing(bool on) { g_kt_capturing = on; }
 bool ktimer_on() { return g_kt_on; }
 
 std::string ktimer_json(bool reset) {
@@ -141,6 +143,7 @@ struct MultiWS {
   DBuf<double> G0, G1, G2;            // n0 x b
   DBuf<double> H0, H1;                // n_minus x b
   DBuf<double> dotpart, dots;         // column dot products
+  DBuf<double> gvpart;                // split-k partial sums of W^T r (b == 1)
   DBuf<GemmDesc> dVt, dV, dYt, dY, dP, dE0a, dE0b, dWt, dEW, dW;
   DBuf<GemmDescMix> dP32;             // FP32 local operators (b > 1)
   int maxk = 0, maxm = 0, maxns = 0;
@@ -179,6 +182,13 @@ struct awg_ctx {
   MultiWS ws1;           // single-vector workspace (apply / PCG)
   DBuf<double> pcg_buf;  // x r z p q of the main PCG
   DBuf<double> scal;     // device scalars
+  hipGraphExec_t pcg_graph = nullptr;   // one PCG iteration, captured on first use
+  hipStream_t cap_stream = nullptr;
+  int use_graph = 1;
+  ~awg_ctx() {
+    if (pcg_graph) (void)hipGraphExecDestroy(pcg_graph);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+  }
   std::map<std::string, double> tms;
   int w_iters = 0;
   double w_time = 0.0;
@@ -229,6 +239,37 @@ __global__ void k_build_vg(const long* sub_ptr, const int* sub_idx, const double
     if (gc < 0 || gc >= b) continue;
     Vg[(long)sub_idx[a + l] * b + gc] = V[veoff[s] + l + j * ns];
   }
+}
+
+// Device-side PCG control.  sc layout: [0] rz, [1] pq, [2] alpha, [3] rz_new,
+// [4] beta, [5] rr, [6] ||b||^2, [7] scratch, [8] (tol ||b||)^2, [9] done flag
+// (1 converged, 2 breakdown, 3 maxit), [10] iterations, [11] maxit;
+// alpha_k at sc[16 + 2k], beta_k at sc[17 + 2k].  Once done is set, alpha and
+// beta are 0, so further launches leave x, r and p unchanged.
+__global__ void k_pcg_alpha(double* sc) {
+  if (threadIdx.x != 0) return;
+  if (sc[9] != 0.0) { sc[2] = 0.0; return; }
+  if (!(sc[1] > 0.0)) { sc[9] = 2.0; sc[2] = 0.0; return; }
+  const double a = sc[0] / sc[1];
+  sc[2] = a;
+  sc[16 + 2 * (long)sc[10]] = a;
+}
+
+__global__ void k_pcg_check(double* sc) {
+  if (threadIdx.x != 0) return;
+  if (sc[9] != 0.0) return;
+  sc[10] += 1.0;
+  if (sc[5] <= sc[8]) sc[9] = 1.0;
+  else if (sc[10] >= sc[11]) sc[9] = 3.0;
+}
+
+__global__ void k_pcg_beta(double* sc) {
+  if (threadIdx.x != 0) return;
+  if (sc[9] != 0.0) { sc[4] = 0.0; return; }
+  const double bta = sc[3] / sc[0];
+  sc[4] = bta;
+  sc[0] = sc[3];
+  sc[17 + 2 * ((long)sc[10] - 1)] = bta;
 }
 
 __global__ void k_pcg_scalars(double* sc, int it, int mode) {
@@ -322,9 +363,9 @@ GemmDesc mk(const double* X, const double* M, int ldm, double* Y, int nout, int 
 
 // flops: algorithmic flops of the whole batched product (2 m n k summed)
 void bmm(const DBuf<GemmDesc>& d, int batch, int maxout, int maxk, bool transM, double alpha, double beta, int b,
-         hipStream_t s, double flops) {
+         hipStream_t s, double flops, double* gemv_part = nullptr) {
   if (batch == 0) return;
-  if (b == 1) gemv_batched(d, batch, maxout, maxk, !transM, alpha, beta, s, 4.0 * flops);
+  if (b == 1) gemv_batched(d, batch, maxout, maxk, !transM, alpha, beta, s, 4.0 * flops, gemv_part);
   else gemm_batched(d, batch, b, maxout, false, transM, alpha, beta, false, s, flops);
 }
 
@@ -349,6 +390,7 @@ void build_ws(awg_ctx& c, MultiWS& w, int b) {
   w.H1.alloc(std::max(1, c.nminus) * (long)b);
   w.dotpart.alloc((long)DOT_CHUNKS_H * b);
   w.dots.alloc(2L * b);
+  if (b == 1) w.gvpart.alloc((long)GEMV_KSPLIT * std::max(1, c.nminus));
   std::vector<GemmDesc> vt(c.N), vv(c.N), yt(c.N), yy(c.N), pp(c.N);
   w.maxk = w.maxm = w.maxns = 0;
   w.flV = w.flY = w.flP = 0;
@@ -481,7 +523,7 @@ void op_h(awg_ctx& c, MultiWS& w, bool f32) {
   op_h2(c, w, f32);
   if (c.nminus == 0) return;
   const int b = w.b;
-  bmm(w.dWt, 1, c.nminus, c.n, true, 1.0, 0.0, b, c.s, w.flW);           // H0 = W^T r
+  bmm(w.dWt, 1, c.nminus, c.n, true, 1.0, 0.0, b, c.s, w.flW, w.gvpart.p);  // H0 = W^T r
   bmm(w.dEW, 1, c.nminus, c.nminus, false, 1.0, 0.0, b, c.s, w.flEW);    // H1 = E_W^{-1} H0
   bmm(w.dW, 1, c.n, c.nminus, false, 1.0, 1.0, b, c.s, w.flW);           // Z += W H1
 }
@@ -990,17 +1032,44 @@ void lanczos_extremes(const std::vector<double>& al, const std::vector<double>& 
   lmax = bis(k - 1);
 }
 
+// one PCG iteration (device-side control; see k_pcg_alpha)
+void pcg_iteration(awg_ctx& c, bool f32) {
+  MultiWS& w = c.ws1;
+  const int n = c.n;
+  hipStream_t s = c.s;
+  double* xx = c.pcg_buf.p;
+  double* p = xx + n;
+  double* q = p + n;
+  double* sc = c.scal.p;
+  const unsigned g = cdiv(n, 256);
+  l_spmm(n, c.nnz, c.rowptr, c.col, c.val, p, q, 1, 1.0, 0.0, s);
+  l_coldot(n, 1, p, q, w.dotpart, sc + 1, s);
+  hipLaunchKernelGGL(k_pcg_alpha, dim3(1), dim3(64), 0, s, sc);
+  hipLaunchKernelGGL(k_pcg_update_xr, dim3(g), dim3(256), 0, s, n, xx, w.R.p, p, q, sc);
+  l_coldot(n, 1, w.R, w.R, w.dotpart, sc + 5, s);
+  hipLaunchKernelGGL(k_pcg_check, dim3(1), dim3(64), 0, s, sc);
+  op_h(c, w, f32);
+  l_coldot(n, 1, w.R, w.Z, w.dotpart, sc + 3, s);
+  hipLaunchKernelGGL(k_pcg_beta, dim3(1), dim3(64), 0, s, sc);
+  hipLaunchKernelGGL(k_pcg_update_p, dim3(g), dim3(256), 0, s, n, p, w.Z.p, sc);
+  AWG_LAUNCH_CHECK();
+}
+
+constexpr int PCG_HIST = 4096;     // capacity of the alpha/beta history
+constexpr int PCG_AHEAD = 4;       // iterations launched between two host checks
+
 int do_pcg(awg_ctx& c, const double* b, double* x, double tol, int maxit, awg_pcg_info* info) {
   hipStream_t s = c.s;
   MultiWS& w = c.ws1;
   const bool f32 = c.opt.local_prec == AWG_LOCAL_F32;
   const int n = c.n;
+  maxit = std::min(maxit, PCG_HIST - 1);
   double* xx = c.pcg_buf.p;
   double* p = xx + n;
   double* q = p + n;
-  c.scal.alloc(16 + 2 * (size_t)std::max(maxit, 1) + 2);
-  c.scal.zero(s);
+  if (!c.scal.p) c.scal.alloc(16 + 2 * (size_t)PCG_HIST + 2);
   double* sc = c.scal.p;
+  AWG_HIP(hipMemsetAsync(sc, 0, sizeof(double) * 16, s));
   AWG_HIP(hipMemcpyAsync(w.R.p, b, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
   AWG_HIP(hipMemsetAsync(xx, 0, sizeof(double) * n, s));
   l_coldot(n, 1, w.R, w.R, w.dotpart, sc + 6, s);
@@ -1013,33 +1082,60 @@ int do_pcg(awg_ctx& c, const double* b, double* x, double tol, int maxit, awg_pc
   int it = 0;
   if (bn == 0.0) {
     inf.converged = 1;
+  } else if (maxit <= 0) {
+    inf.rel_res = 1.0;
   } else {
+    const double ctl[4] = {tol * tol * h6, 0.0, 0.0, (double)maxit};
+    AWG_HIP(hipMemcpyAsync(sc + 8, ctl, sizeof(ctl), hipMemcpyHostToDevice, s));
     op_h(c, w, f32);
     AWG_HIP(hipMemcpyAsync(p, w.Z.p, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
     l_coldot(n, 1, w.R, w.Z, w.dotpart, sc + 0, s);
-    const unsigned g = cdiv(n, 256);
-    double hs[6];
-    for (;;) {
-      l_spmm(n, c.nnz, c.rowptr, c.col, c.val, p, q, 1, 1.0, 0.0, s);
-      l_coldot(n, 1, p, q, w.dotpart, sc + 1, s);
-      hipLaunchKernelGGL(k_pcg_scalars, dim3(1), dim3(64), 0, s, sc, it, 0);
-      hipLaunchKernelGGL(k_pcg_update_xr, dim3(g), dim3(256), 0, s, n, xx, w.R.p, p, q, sc);
-      l_coldot(n, 1, w.R, w.R, w.dotpart, sc + 5, s);
-      AWG_HIP(hipMemcpyAsync(hs, sc, sizeof(double) * 6, hipMemcpyDeviceToHost, s));
+    if (c.use_graph && !c.pcg_graph) {
+      // capture one iteration on a private stream (default priority)
+      if (!c.cap_stream) AWG_HIP(hipStreamCreateWithFlags(&c.cap_stream, hipStreamNonBlocking));
       sync(c);
-      ++it;
-      if (!(hs[1] > 0.0)) {
-        status = AWG_ERR_NOT_SPD;
-        c.err = "PCG breakdown: p^T A p <= 0 (A or H not spd)";
-        break;
+      hipStream_t user = c.s;
+      c.s = c.cap_stream;
+      ktimer_capturing(true);
+      hipGraph_t graph = nullptr;
+      try {
+        AWG_HIP(hipStreamBeginCapture(c.s, hipStreamCaptureModeThreadLocal));
+        pcg_iteration(c, f32);
+        AWG_HIP(hipStreamEndCapture(c.s, &graph));
+        AWG_HIP(hipGraphInstantiate(&c.pcg_graph, graph, nullptr, nullptr, 0));
+        (void)hipGraphDestroy(graph);
+      } catch (...) {
+        hipGraph_t g2 = nullptr;
+        (void)hipStreamEndCapture(c.s, &g2);
+        if (g2) (void)hipGraphDestroy(g2);
+        if (graph) (void)hipGraphDestroy(graph);
+        c.pcg_graph = nullptr;
+        c.use_graph = 0;                  // fall back to eager launches of the same kernels
+        (void)hipGetLastError();
       }
-      inf.rel_res = std::sqrt(hs[5]) / bn;
-      if (inf.rel_res <= tol) { inf.converged = 1; break; }
-      if (it >= maxit) break;
-      op_h(c, w, f32);
-      l_coldot(n, 1, w.R, w.Z, w.dotpart, sc + 3, s);
-      hipLaunchKernelGGL(k_pcg_scalars, dim3(1), dim3(64), 0, s, sc, it - 1, 1);
-      hipLaunchKernelGGL(k_pcg_update_p, dim3(g), dim3(256), 0, s, n, p, w.Z.p, sc);
+      ktimer_capturing(false);
+      c.s = user;
+    }
+    double hs[12];
+    for (;;) {
+      for (int k = 0; k < PCG_AHEAD; ++k) {
+        if (c.pcg_graph) {
+          KScope kt("graph:pcg_iteration", s, 0.0, 0.0);
+          AWG_HIP(hipGraphLaunch(c.pcg_graph, s));
+        } else {
+          pcg_iteration(c, f32);
+        }
+      }
+      AWG_HIP(hipMemcpyAsync(hs, sc, sizeof(hs), hipMemcpyDeviceToHost, s));
+      sync(c);
+      if (hs[9] != 0.0) break;
+    }
+    it = (int)hs[10];
+    inf.rel_res = std::sqrt(hs[5]) / bn;
+    if (hs[9] == 1.0) inf.converged = 1;
+    if (hs[9] == 2.0) {
+      status = AWG_ERR_NOT_SPD;
+      c.err = "PCG breakdown: p^T A p <= 0 (A or H not spd)";
     }
   }
   inf.iters = it;
@@ -1049,7 +1145,7 @@ int do_pcg(awg_ctx& c, const double* b, double* x, double tol, int maxit, awg_pc
     l_spmm(n, c.nnz, c.rowptr, c.col, c.val, xx, q, 1, -1.0, 0.0, s);
     l_colaxpby(n, 1, b, nullptr, q, nullptr, 1.0, 1.0, s);
     l_coldot(n, 1, q, q, w.dotpart, sc + 7, s);
-    std::vector<double> hist(16 + 2 * (size_t)std::max(maxit, 1));
+    std::vector<double> hist(16 + 2 * (size_t)std::max(it, 1) + 2);
     AWG_HIP(hipMemcpyAsync(hist.data(), sc, sizeof(double) * hist.size(), hipMemcpyDeviceToHost, s));
     sync(c);
     inf.rel_res_true = bn > 0 ? std::sqrt(hist[7]) / bn : 0.0;
@@ -1221,6 +1317,12 @@ int64_t awg_export(const awg_ctx* c, const char* name, void* buf, size_t cap) {
 }
 
 const char* awg_last_error(const awg_ctx* c) { return c ? c->err.c_str() : g_setup_error.c_str(); }
+
+int awg_pcg_graph(awg_ctx* c, int32_t enable) {
+  if (!c) return AWG_ERR_ARG;
+  c->use_graph = enable ? 1 : 0;
+  return AWG_OK;
+}
 
 int awg_kernel_timing(int32_t enable) {
   try {

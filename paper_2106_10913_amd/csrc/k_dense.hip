@@ -472,7 +472,6 @@ __global__ __launch_bounds__(256) void k_gemv_t(const GemmDesc* descs, double al
 
 // notrans with few rows and a long k (single descriptor): the columns are
 // split into GEMV_KSPLIT ranges whose partial sums are added in a fixed order
-constexpr int GEMV_KSPLIT = 64;
 __global__ __launch_bounds__(256) void k_gemv_n_part(const GemmDesc* descs, double* part) {
   const GemmDesc d = descs[0];
   const int r = threadIdx.x & 63, g = threadIdx.x >> 6;
@@ -499,20 +498,9 @@ __global__ void k_gemv_n_sum(const GemmDesc* descs, const double* part, double a
 }
 
 void gemv_batched(const GemmDesc* d_desc, int batch, int max_m, int max_k, bool transA, double alpha,
-                  double beta, hipStream_t s, double bytes) {
+                  double beta, hipStream_t s, double bytes, double* part) {
   if (batch <= 0) return;
-  if (!transA && batch == 1 && max_m <= 16384 && max_k >= 16 * max_m) {
-    // partial-sum buffer, grown on demand and kept for the life of the process
-    static double* part = nullptr;
-    static size_t cap = 0;
-    if (cap < (size_t)GEMV_KSPLIT * max_m) {
-      AWG_HIP(hipStreamSynchronize(s));
-      if (part) AWG_HIP(hipFree(part));
-      part = nullptr;
-      cap = 0;
-      AWG_HIP(hipMalloc((void**)&part, sizeof(double) * GEMV_KSPLIT * max_m));
-      cap = (size_t)GEMV_KSPLIT * max_m;
-    }
+  if (part && !transA && batch == 1 && max_m > 0 && max_k >= 16 * max_m) {
     KScope kt("k_gemv_n_part", s, bytes, bytes / 4.0);
     hipLaunchKernelGGL(k_gemv_n_part, dim3(cdiv(max_m, 64), GEMV_KSPLIT), dim3(256), 0, s, d_desc, part);
     AWG_LAUNCH_CHECK();

@@ -109,6 +109,42 @@ def test_pcg_matches_oracle(pair):
     assert info["rel_res_true"] <= 2 * w.tol
 
 
+def test_pcg_graph_matches_eager(pair):
+    """The captured PCG iteration and eager launches of the same kernels give
+    the same iterate bit for bit; a second solve reuses the graph."""
+    import torch
+    w, st, solver = pair
+    b = torch.as_tensor(w.b, device="cuda")
+    xg, ig = solver.pcg(b, tol=w.tol, maxit=500)
+    xg = xg.clone()
+    solver.use_graph(False)
+    try:
+        xe, ie = solver.pcg(b, tol=w.tol, maxit=500)
+    finally:
+        solver.use_graph(True)
+    assert torch.equal(xg, xe)
+    assert ig["iters"] == ie["iters"] and ig["rel_res"] == ie["rel_res"]
+    b2 = np.random.default_rng(11).standard_normal(w.A.shape[0])
+    x2, i2 = solver.pcg(torch.as_tensor(b2, device="cuda"), tol=w.tol, maxit=500)
+    ref = O.pcg(w.A, b2, st.apply, tol=w.tol)
+    assert i2["converged"] == 1 and abs(i2["iters"] - ref.iters) <= 1
+    assert np.linalg.norm(x2.cpu().numpy() - ref.x) <= X_RTOL * np.linalg.norm(ref.x)
+
+
+@pytest.mark.parametrize("maxit", [1, 2, 5])
+def test_pcg_stops_at_maxit(pair, maxit):
+    """Iterations launched after the device-side stop leave x unchanged."""
+    import torch
+    w, st, solver = pair
+    b = torch.as_tensor(w.b, device="cuda")
+    x, info = solver.pcg(b, tol=1e-300, maxit=maxit)
+    assert info["iters"] == maxit and info["converged"] == 0 and info["status"] == "AWG_NOT_CONVERGED"
+    ref = O.pcg(w.A, w.b, st.apply, tol=1e-300, maxit=maxit)
+    assert ref.iters == maxit
+    xr = ref.x
+    assert np.linalg.norm(x.cpu().numpy() - xr) <= 100 * h_rtol(st) * np.linalg.norm(xr)
+
+
 def test_apply_is_deterministic(pair):
     import torch
     w, st, solver = pair
