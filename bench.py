@@ -34,9 +34,13 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--local-prec", default="f64", choices=["f64", "f32"])
+    ap.add_argument("--geneo", default="dense", choices=["dense", "subspace"],
+                    help="GenEO eigensolver of the timed FP64 form")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fast-form", action="store_true")
     ap.add_argument("--m", type=int, default=256, help="cells per side (256 = the bench workload)")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB three times (HBM counter calibration)")
     return ap.parse_args()
 
 
@@ -116,6 +120,18 @@ def roofline(kt: dict, steps: int) -> dict:
             "avg_launch_us": round(avg_us, 2), "bytes_per_launch": rec["bytes"] / rec["calls"]}
 
 
+def copy_probe(torch, mib: int) -> None:
+    """Plain copy kernel of known size: reads and writes mib MiB per launch."""
+    n = mib * (1 << 20) // 8
+    src = torch.rand(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        torch.add(src, 0.0, out=dst)
+    torch.cuda.synchronize()
+    assert torch.equal(src, dst)
+    print(json.dumps({"copy_probe_bytes_read": n * 8, "copy_probe_bytes_written": n * 8, "launches": 3}))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -124,6 +140,9 @@ def main():
         sys.exit(2)
     import numpy as np
     import torch
+    if args.copy_probe:
+        copy_probe(torch, args.copy_probe)
+        return
     import awg_problems as P
     from paper_2106_10913_amd import awg
 
@@ -140,8 +159,8 @@ def main():
     bd = torch.as_tensor(w.b, device=dev)
     x = torch.empty_like(bd)
 
-    def step(local_prec=args.local_prec):
-        solver = awg.Solver(Ad, Sd, tau=w.tau, local_prec=local_prec)
+    def step(local_prec=args.local_prec, geneo=args.geneo):
+        solver = awg.Solver(Ad, Sd, tau=w.tau, local_prec=local_prec, geneo=geneo)
         _, info = solver.pcg(bd, tol=w.tol, maxit=1000, x=x)
         st = solver.stats()
         solver.close()
@@ -172,7 +191,7 @@ def main():
     info = infos[-1]
     phases = {k: round(v, 3) for k, v in st["ms"].items()}
     out = {
-        "metric": "AWG-PCG time to 1e-8 rel. residual (setup+solve)",
+        "metric": "AWG-PCG time to 1e-8 rel. residual (setup+solve), FP32/learned vs plain FP64",
         "value": round(ms, 3),
         "unit": "ms",
         "n_gpus": 1,
@@ -194,15 +213,17 @@ def main():
     }
     if not args.no_fast_form and args.local_prec == "f64":
         # the same workload with FP32 local operators (eigen-setup, coarse
-        # spaces, PCG and W recurrences stay FP64)
-        step("f32")
+        # spaces, PCG and W recurrences stay FP64) and the subspace GenEO solver
+        step("f32", "subspace")
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         for i in range(args.steps):
-            info32, st32 = step("f32")
+            info32, st32 = step("f32", "subspace")
         torch.cuda.synchronize()
         ms32 = (time.perf_counter() - t1) * 1e3 / args.steps
-        out["fast_form"] = {"local_prec": "f32", "ms_per_step": round(ms32, 3), "iters": info32["iters"],
+        out["fast_form"] = {"local_prec": "f32", "geneo": "subspace", "eig_iters_max": max(st32["eig_iters"]),
+                            "eig_fallbacks": st32["eig_fallbacks"], "ms_per_step": round(ms32, 3),
+                            "iters": info32["iters"],
                             "rel_res_true": info32["rel_res_true"], "n_minus": st32["n_minus"], "n0": st32["n0"],
                             "w_iters": st32["w_iters"], "speedup_vs_f64": round(ms / ms32, 3),
                             "phases_ms": {k: round(v, 3) for k, v in st32["ms"].items()}}

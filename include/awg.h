@@ -59,6 +59,7 @@ typedef enum {
 } awg_status;
 
 enum { AWG_LOCAL_F64 = 0, AWG_LOCAL_F32 = 1 };
+enum { AWG_GENEO_DENSE = 0, AWG_GENEO_SUBSPACE = 1 };
 
 typedef struct {
   double tau;          /* GenEO threshold of H^NN_hyb(tau); 0 < tau < 1 (Theorem, Section 3.4) */
@@ -71,6 +72,20 @@ typedef struct {
   int32_t local_prec;  /* AWG_LOCAL_F64 (default) or AWG_LOCAL_F32: storage and
                           arithmetic of the per-iteration local solves */
   void* stream;        /* hipStream_t; NULL = default stream */
+  int32_t geneo_solver;  /* AWG_GENEO_DENSE (default): every GenEO pencil is
+                            reduced to tridiagonal form and solved exactly;
+                            AWG_GENEO_SUBSPACE: block subspace iteration with
+                            Rayleigh-Ritz on the pencil restricted to the
+                            complement of its known kernel D^s V^s_-, accepted
+                            per subdomain only when every selected Ritz pair
+                            meets eig_tol and a Cholesky factorisation
+                            certifies that no other eigenvalue lies below
+                            tau (1 - 1e-10); otherwise the dense solver runs */
+  int32_t eig_block;     /* iterated columns besides the kernel, 1..64; default 16 */
+  int32_t eig_maxit;     /* iteration cap of the subspace solver; default 200 */
+  int32_t eig_seed;      /* seed of the random start block; default 0 */
+  double eig_tol;        /* relative Ritz residual required of every Ritz value
+                            below 2 tau; default 1e-10 */
 } awg_options;
 
 /* Fill *opt with the defaults above (tau = 0.1).  Host pointer. */

@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libawg.so")
 
 AWG_LOCAL_F64 = 0
 AWG_LOCAL_F32 = 1
+AWG_GENEO_DENSE, AWG_GENEO_SUBSPACE = 0, 1
 
 STATUS = {0: "AWG_OK", 1: "AWG_NOT_CONVERGED", -1: "AWG_ERR_ARG", -2: "AWG_ERR_NOT_SYMMETRIC",
           -3: "AWG_ERR_PARTITION", -4: "AWG_ERR_MIN_OVERLAP", -5: "AWG_ERR_NOT_SPD", -6: "AWG_ERR_EIGEN",
@@ -29,7 +30,9 @@ EXPORTED = ["awg_default_options", "awg_setup", "awg_apply", "awg_pcg", "awg_sta
 
 class Options(ctypes.Structure):
     _fields_ = [("tau", ctypes.c_double), ("zero_tol", ctypes.c_double), ("w_rtol", ctypes.c_double),
-                ("w_maxit", ctypes.c_int32), ("local_prec", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+                ("w_maxit", ctypes.c_int32), ("local_prec", ctypes.c_int32), ("stream", ctypes.c_void_p),
+                ("geneo_solver", ctypes.c_int32), ("eig_block", ctypes.c_int32), ("eig_maxit", ctypes.c_int32),
+                ("eig_seed", ctypes.c_int32), ("eig_tol", ctypes.c_double)]
 
 
 class PCGInfo(ctypes.Structure):
@@ -123,7 +126,8 @@ class Solver:
     """
 
     def __init__(self, A, subs, tau: float = 0.1, local_prec: str = "f64", w_rtol: float = 1e-10,
-                 w_maxit: int = 500, zero_tol: float = 1e-12, device: str = "cuda"):
+                 w_maxit: int = 500, zero_tol: float = 1e-12, device: str = "cuda", geneo: str = "dense",
+                 eig_block: int = 16, eig_maxit: int = 200, eig_tol: float = 1e-10, eig_seed: int = 0):
         import torch
         L = lib()
         self._torch = torch
@@ -158,6 +162,13 @@ class Solver:
         opt.w_maxit = w_maxit
         opt.local_prec = AWG_LOCAL_F32 if local_prec == "f32" else AWG_LOCAL_F64
         opt.stream = torch.cuda.current_stream(self.device).cuda_stream
+        if geneo not in ("dense", "subspace"):
+            raise ValueError("geneo must be 'dense' or 'subspace'")
+        opt.geneo_solver = AWG_GENEO_SUBSPACE if geneo == "subspace" else AWG_GENEO_DENSE
+        opt.eig_block = eig_block
+        opt.eig_maxit = eig_maxit
+        opt.eig_tol = eig_tol
+        opt.eig_seed = eig_seed
         self._opt = opt
         ctx = ctypes.c_void_p()
         rc = L.awg_setup(ctypes.byref(ctx), self.n, self.nnz, rowptr.data_ptr(), col.data_ptr(), val.data_ptr(),

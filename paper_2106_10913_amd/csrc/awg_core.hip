@@ -16,6 +16,7 @@
 #include "awg.h"
 #include "awg_common.h"
 #include "awg_sparse.h"
+#include "awg_subspace.h"
 
 using namespace awg;
 
@@ -193,6 +194,8 @@ struct awg_ctx {
   int w_iters = 0;
   double w_time = 0.0;
   std::vector<double> eig_resid_max;
+  std::vector<int> eig_iters;   // subspace GenEO: iteration of convergence per subdomain
+  int eig_fallbacks = 0;        // subdomains whose subspace result was not certified
 };
 
 namespace {
@@ -698,6 +701,241 @@ EigOut batched_low_eigs(awg_ctx& c, DBuf<MatDesc>& dX, int thr_mode, double thr_
   return out;
 }
 
+// GenEO modes by block subspace iteration (kernels in k_subspace.hip).
+// MB, MA: arenas holding M_B^s and M_A^s (MA is destroyed by the certificate).
+// On success fills c.Y, c.LY, c.lamY, c.ms and returns 0; otherwise returns
+// the number of subdomains that failed (the caller then runs the dense solver).
+int geneo_subspace(awg_ctx& c, const double* MB, double* MA) {
+  hipStream_t s = c.s;
+  const int N = c.N, q = c.opt.eig_block;
+  const double tau = c.opt.tau, window = 2.0, tol_far = 1e-2;
+  const int min_it = 3;
+  std::vector<long> qoff(N + 1, 0), goff(N + 1, 0), ooff(N + 1, 0), kqoff(N + 1, 0);
+  int maxk = 0;
+  for (int t = 0; t < N; ++t) {
+    const int k = c.ks[t];
+    maxk = std::max(maxk, k);
+    goff[t + 1] = goff[t] + (long)k * k;
+    kqoff[t + 1] = kqoff[t] + (long)k * q;
+  }
+  // kernel of M_A: K = D^s V^s_-, KB = M_B K, GK = K^T M_B K = L L^T
+  DBuf<double> K, KB, GK;
+  K.alloc(std::max<long>(1, c.LV.elems));
+  KB.alloc(std::max<long>(1, c.LV.elems));
+  GK.alloc(std::max<long>(1, goff[N]));
+  l_rows_dw(N, c.maxns, maxk, c.subptr, c.LV.d_eoff, c.LV.d_coff, c.V, c.dw, K, s);
+  std::vector<GemmDesc> g(N);
+  DBuf<GemmDesc> dKB, dGK, dg1, dg2, dg3, dg4, dg3x, dg4x, dg5, dg6, dg7, dg8;
+  std::vector<MatDesc> mg(N), mc(N), mcx(N);
+  for (int t = 0; t < N; ++t) {
+    const int n = c.ns[t], k = c.ks[t], lk = std::max(1, k);
+    const long eo = c.LV.eoff[t];
+    g[t] = GemmDesc{MB + c.sqoff[t], K.p + eo, KB.p + eo, n, k, n, n, n, n};
+    mg[t] = MatDesc{GK.p + goff[t], k, k, lk, 0};
+  }
+  dKB.upload(g, s);
+  double fl = 0.0;
+  for (int t = 0; t < N; ++t) fl += 2.0 * c.ns[t] * (double)c.ns[t] * c.ks[t];
+  if (maxk) gemm_batched(dKB, N, c.maxns, maxk, false, false, 1.0, 0.0, false, s, fl);
+  for (int t = 0; t < N; ++t) {
+    const int n = c.ns[t], k = c.ks[t];
+    const long eo = c.LV.eoff[t];
+    g[t] = GemmDesc{K.p + eo, KB.p + eo, GK.p + goff[t], k, k, n, n, n, std::max(1, k)};
+  }
+  dGK.upload(g, s);
+  if (maxk) gemm_batched(dGK, N, maxk, maxk, true, false, 1.0, 0.0, false, s);
+  DBuf<MatDesc> dmg;
+  dmg.upload(mg, s);
+  DBuf<int> info;
+  info.alloc(N);
+  info.zero(s);
+  if (maxk) {
+    l_scale_sym(dmg, N, nullptr, nullptr, false, true, s);
+    potrf_batched(dmg, c.ks, info, s, nullptr);
+    for (int v : info.download(s))
+      if (v) return N;
+  }
+  // iterated blocks (n_s x q per subdomain at sub_ptr[s] * q)
+  const long bq = c.sumns * (long)q;
+  DBuf<double> X, BX, Y, Z, TZ, cK, S0, S1, Cq, mu, res;
+  X.alloc(bq);
+  BX.alloc(bq);
+  Y.alloc(bq);
+  Z.alloc(bq);
+  TZ.alloc(bq);
+  cK.alloc(std::max<long>(1, kqoff[N]));
+  S0.alloc((long)N * q * q);
+  S1.alloc((long)N * q * q);
+  Cq.alloc((long)N * q * q);
+  mu.alloc((long)N * q);
+  res.alloc((long)N * q);
+  DBuf<int> flag, conv, nsel;
+  flag.alloc(N);
+  conv.alloc(N);
+  nsel.alloc(N);
+  auto blk = [&](const DBuf<double>& b, int t) { return b.p + c.h_subptr[t] * q; };
+  auto up = [&](DBuf<GemmDesc>& d, auto f) {
+    for (int t = 0; t < N; ++t) g[t] = f(t, c.ns[t], c.ks[t]);
+    d.upload(g, s);
+  };
+  up(dg1, [&](int t, int n, int) { return GemmDesc{MB + c.sqoff[t], blk(X, t), blk(BX, t), n, q, n, n, n, n}; });
+  up(dg2, [&](int t, int n, int) { return GemmDesc{c.P.p + c.sqoff[t], blk(BX, t), blk(Y, t), n, q, n, n, n, n}; });
+  up(dg3, [&](int t, int n, int k) {
+    return GemmDesc{KB.p + c.LV.eoff[t], blk(Y, t), cK.p + kqoff[t], k, q, n, n, n, std::max(1, k)};
+  });
+  up(dg4, [&](int t, int n, int k) {
+    return GemmDesc{K.p + c.LV.eoff[t], cK.p + kqoff[t], blk(Y, t), n, q, k, n, std::max(1, k), n};
+  });
+  up(dg3x, [&](int t, int n, int k) {
+    return GemmDesc{KB.p + c.LV.eoff[t], blk(X, t), cK.p + kqoff[t], k, q, n, n, n, std::max(1, k)};
+  });
+  up(dg4x, [&](int t, int n, int k) {
+    return GemmDesc{K.p + c.LV.eoff[t], cK.p + kqoff[t], blk(X, t), n, q, k, n, std::max(1, k), n};
+  });
+  up(dg5, [&](int t, int n, int) { return GemmDesc{blk(X, t), blk(BX, t), S0.p + (long)t * q * q, q, q, n, n, n, q}; });
+  up(dg6, [&](int t, int n, int) { return GemmDesc{blk(BX, t), blk(Y, t), S1.p + (long)t * q * q, q, q, n, n, n, q}; });
+  up(dg7, [&](int t, int n, int) { return GemmDesc{blk(X, t), Cq.p + (long)t * q * q, blk(Z, t), n, q, q, n, q, n}; });
+  up(dg8, [&](int t, int n, int) { return GemmDesc{blk(Y, t), Cq.p + (long)t * q * q, blk(TZ, t), n, q, q, n, q, n}; });
+  for (int t = 0; t < N; ++t) mc[t] = MatDesc{cK.p + kqoff[t], c.ks[t], q, std::max(1, c.ks[t]), 0};
+  DBuf<MatDesc> dmc;
+  dmc.upload(mc, s);
+  const std::vector<int> qcols(N, q);
+  double flMB = 0.0, flK = 0.0;
+  for (int t = 0; t < N; ++t) {
+    flMB += 2.0 * c.ns[t] * (double)c.ns[t] * q;
+    flK += 2.0 * c.ns[t] * (double)c.ks[t] * q;
+  }
+  // Pi_B: x <- x - K GK^-1 (KB^T x)
+  auto project = [&](DBuf<GemmDesc>& a, DBuf<GemmDesc>& b) {
+    if (!maxk) return;
+    gemm_batched(a, N, maxk, q, true, false, 1.0, 0.0, false, s, flK);
+    trsm_batched(dmg, dmc, c.ks, qcols, false, s, nullptr);
+    trsm_batched(dmg, dmc, c.ks, qcols, true, s, nullptr);
+    gemm_batched(b, N, c.maxns, q, false, false, -1.0, 1.0, false, s, flK);
+  };
+  l_rand_block(N, c.maxns, c.subptr, c.subidx, q, (uint64_t)(uint32_t)c.opt.eig_seed, X, s);
+  project(dg3x, dg4x);
+  c.eig_iters.assign(N, -1);
+  int it = 0, nconv = 0;
+  std::vector<int> hconv(N, 0), hflag(N, 0);
+  for (it = 1; it <= c.opt.eig_maxit; ++it) {
+    gemm_batched(dg1, N, c.maxns, q, false, false, 1.0, 0.0, false, s, flMB);     // BX = M_B X
+    gemm_batched(dg2, N, c.maxns, q, false, false, 1.0, 0.0, false, s, flMB);     // Y = G BX
+    project(dg3, dg4);                                                              // Y = Pi_B Y
+    gemm_batched(dg5, N, q, q, true, false, 1.0, 0.0, false, s);                    // S0 = X^T M_B X
+    gemm_batched(dg6, N, q, q, true, false, 1.0, 0.0, false, s);                    // S1 = X^T M_B T X
+    l_rr_small(N, q, S0, S1, Cq, mu, flag, s);
+    gemm_batched(dg7, N, c.maxns, q, false, false, 1.0, 0.0, false, s);             // Z = X C
+    gemm_batched(dg8, N, c.maxns, q, false, false, 1.0, 0.0, false, s);             // T Z = Y C
+    l_ritz_resid(N, c.subptr, q, Z, TZ, mu, X, res, conv, nsel, tau, window, c.opt.eig_tol, tol_far, s);
+    AWG_HIP(hipMemcpyAsync(hconv.data(), conv.p, sizeof(int) * N, hipMemcpyDeviceToHost, s));
+    sync(c);
+    nconv = 0;
+    for (int t = 0; t < N; ++t) {
+      if (hconv[t] && c.eig_iters[t] < 0) c.eig_iters[t] = it;
+      if (!hconv[t]) c.eig_iters[t] = -1;
+      nconv += hconv[t] != 0;
+    }
+    if (it >= min_it && nconv == N) break;
+  }
+  hflag = flag.download(s);
+  std::vector<int> hsel = nsel.download(s);
+  int fails = 0;
+  std::vector<int> ms(N);
+  for (int t = 0; t < N; ++t) {
+    const bool bad = !hconv[t] || hflag[t] || hsel[t] >= q;
+    fails += bad;
+    ms[t] = c.ks[t] + std::min(hsel[t], q);
+  }
+  if (fails) return fails;
+  c.LY.build(c.ns, ms, s);
+  c.Y.alloc(std::max<long>(1, c.LY.elems));
+  c.lamY.alloc(std::max<long>(1, c.LY.cols));
+  int maxm = 0;
+  for (int v : ms) maxm = std::max(maxm, v);
+  l_assemble_modes(N, c.maxns, maxm, c.subptr, q, K, c.LV.d_eoff, c.LV.d_coff, Z, mu, c.Y, c.LY.d_eoff,
+                   c.LY.d_coff, c.lamY, s);
+  // M_B-orthonormal basis of span(Y): Y <- Y L^-T with Y^T M_B Y = L L^T
+  std::vector<long> moff(N + 1, 0);
+  for (int t = 0; t < N; ++t) moff[t + 1] = moff[t] + (long)ms[t] * ms[t];
+  DBuf<double> BY, T1, T2, G, Li;
+  BY.alloc(std::max<long>(1, c.LY.elems));
+  T1.alloc(std::max<long>(1, c.LY.elems));
+  T2.alloc(std::max<long>(1, c.LY.elems));
+  G.alloc(std::max<long>(1, moff[N]));
+  Li.alloc(std::max<long>(1, moff[N]));
+  std::vector<MatDesc> dgm(N), dli(N);
+  for (int t = 0; t < N; ++t) {
+    const int m = ms[t];
+    dgm[t] = MatDesc{G.p + moff[t], m, m, std::max(1, m), 0};
+    dli[t] = MatDesc{Li.p + moff[t], m, m, std::max(1, m), 0};
+  }
+  DBuf<MatDesc> ddg, ddl;
+  ddg.upload(dgm, s);
+  ddl.upload(dli, s);
+  DBuf<GemmDesc> e1, e2, e3, e4, e5;
+  up(e1, [&](int t, int n, int) {
+    const long eo = c.LY.eoff[t];
+    return GemmDesc{MB + c.sqoff[t], c.Y.p + eo, BY.p + eo, n, ms[t], n, n, n, n};
+  });
+  up(e2, [&](int t, int n, int) {
+    const long eo = c.LY.eoff[t];
+    return GemmDesc{c.Y.p + eo, BY.p + eo, G.p + moff[t], ms[t], ms[t], n, n, n, std::max(1, ms[t])};
+  });
+  up(e3, [&](int t, int n, int) {
+    const long eo = c.LY.eoff[t];
+    return GemmDesc{c.Y.p + eo, Li.p + moff[t], T1.p + eo, n, ms[t], ms[t], n, std::max(1, ms[t]), n};
+  });
+  up(e4, [&](int t, int n, int) {
+    const long eo = c.LY.eoff[t];
+    return GemmDesc{BY.p + eo, Li.p + moff[t], T2.p + eo, n, ms[t], ms[t], n, std::max(1, ms[t]), n};
+  });
+  double flY = 0.0;
+  for (int t = 0; t < N; ++t) flY += 2.0 * c.ns[t] * (double)c.ns[t] * ms[t];
+  gemm_batched(e1, N, c.maxns, maxm, false, false, 1.0, 0.0, false, s, flY);
+  gemm_batched(e2, N, maxm, maxm, true, false, 1.0, 0.0, false, s);
+  l_scale_sym(ddg, N, nullptr, nullptr, false, true, s);
+  info.zero(s);
+  potrf_batched(ddg, ms, info, s, nullptr);
+  for (int v : info.download(s))
+    if (v) return N;
+  l_set_identity(ddl, N, s);
+  trsm_batched(ddg, ddl, ms, ms, false, s, nullptr);                  // Li = L^-1
+  gemm_batched(e3, N, c.maxns, maxm, false, true, 1.0, 0.0, false, s);  // Y L^-T
+  gemm_batched(e4, N, c.maxns, maxm, false, true, 1.0, 0.0, false, s);  // M_B Y L^-T
+  std::swap(c.Y.p, T1.p);
+  std::swap(c.Y.n, T1.n);
+  std::swap(BY.p, T2.p);
+  std::swap(BY.n, T2.n);
+  // certificate: M_A - tau' M_B + (M_B Y)(M_B Y)^T is spd, so at most m_s
+  // eigenvalues of the pencil lie below tau' = tau (1 - 1e-10); the m_s Ritz
+  // values below tau bound as many eigenvalues from above
+  l_axpy_flat(c.sqtot, -tau * (1.0 - 1e-10), MB, MA, s);
+  up(e5, [&](int t, int n, int) {
+    const long eo = c.LY.eoff[t];
+    return GemmDesc{BY.p + eo, BY.p + eo, MA + c.sqoff[t], n, n, ms[t], n, n, n};
+  });
+  gemm_batched(e5, N, c.maxns, c.maxns, false, true, 1.0, 1.0, true, s, flY);
+  DBuf<MatDesc> dma;
+  dma.upload(square_descs(c, MA), s);
+  info.zero(s);
+  potrf_batched(dma, c.ns, info, s, nullptr);
+  auto hi = info.download(s);
+  for (int t = 0; t < N; ++t) fails += hi[t] != 0;
+  if (fails) return fails;
+  c.ms = ms;
+  c.n0 = (int)c.LY.cols;
+  c.eig_resid_max.push_back(0.0);
+  {
+    auto r = res.download(s);
+    double mx = 0.0;
+    for (int t = 0; t < N; ++t)
+      for (int j = 0; j < ms[t] - c.ks[t]; ++j) mx = std::max(mx, r[(long)t * q + j]);
+    c.eig_resid_max.back() = mx;
+  }
+  return 0;
+}
+
 // B^s, its non-positive eigenpairs (splitting of B^s, Section 3.2), the local
 // factor and P^s = D^s (A^s_+)^+ D^s, the GenEO coarse vectors Y^s
 // (Theorem on H^NN_hyb, Section 3.4).
@@ -773,26 +1011,29 @@ void phase_local(awg_ctx& c) {
       AWG_LAUNCH_CHECK();
     }
   }
-  {
-    PhaseTimer t(c, "geneo");
-    // U = V_- |L_-|
+  // M_A = D^{-1} A^s_+ D^{-1} (in X3) and M_B (in X1), with
+  // A^s_+ = B^s + V_- |L_-| V_-^T and
+  // M_B = R^s A R^sT + sum_t R^s R^tT V^t |L^t| V^tT R^t R^sT
+  auto build_pencil = [&]() {
     if (c.LV.elems) AWG_HIP(hipMemcpyAsync(U.p, c.V.p, sizeof(double) * c.LV.elems, hipMemcpyDeviceToDevice, s));
-    l_scale_cols(dU, c.N, c.LV.d_coff, c.lamV, 1.0, nullptr, 1, s);
-    // M_A = D^{-1} A^s_+ D^{-1}, A^s_+ = B^s + V_- |L_-| V_-^T  (in X3)
-    l_copy_mat(d1, d3, c.N, s);
+    l_scale_cols(dU, c.N, c.LV.d_coff, c.lamV, 1.0, nullptr, 1, s);             // U = V_- |L_-|
+    X3.zero(s);
+    l_extract(c.N, c.subptr, c.subidx, c.rowptr, c.col, c.bval, d3, s);          // B^s
     lowrank_into(X3, 1.0);
     l_scale_sym(d3, c.N, c.subptr, c.dw, true, true, s);
-    // M_B = R^s A R^sT + sum_t R^s R^tT V^t |L^t| V^tT R^t R^sT  (in X1)
     X1.zero(s);
     l_extract(c.N, c.subptr, c.subidx, c.rowptr, c.col, c.val, d1, s);
     lowrank_into(X1, 1.0);
     l_mb_neighbours(c.N, c.subptr, c.subidx, c.mult, c.invptr, c.invsub, c.invloc, d1, c.V, c.LV.d_eoff, c.lamV,
                     c.LV.d_coff, s);
     l_scale_sym(d1, c.N, nullptr, nullptr, false, true, s);
+  };
+  // every eigenpair of the pencil below tau by Cholesky M_B = L L^T and the
+  // tridiagonal eigensolver on L^-1 M_A L^-T
+  auto dense_geneo = [&]() {
     info.zero(s);
     potrf_batched(d1, c.ns, info, s, nullptr);
     check_info(c, info, "GenEO M_B^s");
-    // C = L^{-1} M_A L^{-T}
     trsm_batched(d1, d3, c.ns, c.ns, false, s, nullptr);
     l_transpose_inplace(d3, c.N, s);
     trsm_batched(d1, d3, c.ns, c.ns, false, s, nullptr);
@@ -805,6 +1046,20 @@ void phase_local(awg_ctx& c) {
     dY.upload(col_descs(c, c.Y, c.LY), s);
     trsm_batched(d1, dY, c.ns, c.ms, true, s, nullptr);
     c.n0 = (int)c.LY.cols;
+  };
+  {
+    PhaseTimer t(c, "geneo");
+    build_pencil();
+    c.eig_fallbacks = 0;
+    if (c.opt.geneo_solver == AWG_GENEO_SUBSPACE) {
+      c.eig_fallbacks = geneo_subspace(c, X1, X3);
+      if (c.eig_fallbacks) {
+        build_pencil();
+        dense_geneo();
+      }
+    } else {
+      dense_geneo();
+    }
   }
 }
 
@@ -1175,6 +1430,8 @@ std::string stats_json(const awg_ctx& c) {
   arr("kstrict_s", c.kstrict);
   o << ",";
   arr("m_s", c.ms);
+  o << ",\"geneo_solver\":" << c.opt.geneo_solver << ",\"eig_fallbacks\":" << c.eig_fallbacks << ",";
+  arr("eig_iters", c.eig_iters);
   o << ",\"eig_resid_max\":[";
   for (size_t i = 0; i < c.eig_resid_max.size(); ++i) o << (i ? "," : "") << c.eig_resid_max[i];
   o << "],\"ms\":{";
@@ -1207,6 +1464,11 @@ void awg_default_options(awg_options* opt) {
   opt->w_maxit = 500;
   opt->local_prec = AWG_LOCAL_F64;
   opt->stream = nullptr;
+  opt->geneo_solver = AWG_GENEO_DENSE;
+  opt->eig_block = 16;
+  opt->eig_maxit = 200;
+  opt->eig_seed = 0;
+  opt->eig_tol = 1e-10;
 }
 
 int awg_setup(awg_ctx** out, int64_t n, int64_t nnz, const int64_t* rowptr, const int32_t* col, const double* val,
@@ -1229,7 +1491,9 @@ int awg_setup(awg_ctx** out, int64_t n, int64_t nnz, const int64_t* rowptr, cons
     return AWG_ERR_ARG;
   }
   if (!(o.zero_tol >= 0.0) || !(o.w_rtol > 0.0) || o.w_maxit <= 0 ||
-      (o.local_prec != AWG_LOCAL_F64 && o.local_prec != AWG_LOCAL_F32)) {
+      (o.local_prec != AWG_LOCAL_F64 && o.local_prec != AWG_LOCAL_F32) ||
+      (o.geneo_solver != AWG_GENEO_DENSE && o.geneo_solver != AWG_GENEO_SUBSPACE) || o.eig_block < 1 ||
+      o.eig_block > SUBSPACE_MAX_BLOCK || o.eig_maxit < 1 || !(o.eig_tol > 0.0)) {
     g_setup_error = "awg_setup: invalid option value";
     return AWG_ERR_ARG;
   }

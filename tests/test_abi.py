@@ -34,6 +34,7 @@ def test_default_options_and_setup_argument_errors():
     """Host-side argument checks run before any GPU work."""
     o = awg.default_options()
     assert o.tau == 0.1 and o.zero_tol == 1e-12 and o.w_rtol == 1e-10 and o.local_prec == 0
+    assert o.geneo_solver == 0 and o.eig_block == 16 and o.eig_maxit == 200 and o.eig_tol == 1e-10
     L = awg.lib()
     ctx = ctypes.c_void_p()
     assert L.awg_setup(None, 1, 1, None, None, None, 1, None, None, None) == -1
@@ -44,6 +45,11 @@ def test_default_options_and_setup_argument_errors():
     fake = ctypes.c_void_p(16)
     rc = L.awg_setup(ctypes.byref(ctx), 4, 4, fake, fake, fake, 1, fake, fake, ctypes.byref(o))
     assert rc == -1 and b"tau" in L.awg_last_error(None)
+    for field, bad in [("geneo_solver", 2), ("eig_block", 0), ("eig_block", 65), ("eig_maxit", 0),
+                       ("eig_tol", 0.0)]:
+        o = awg.default_options()
+        setattr(o, field, bad)
+        assert L.awg_setup(ctypes.byref(ctx), 4, 4, fake, fake, fake, 1, fake, fake, ctypes.byref(o)) == -1, field
     assert L.awg_apply(None, None, None) == -1
     assert L.awg_stats(None, None, 0) == -1
     L.awg_destroy(None)
