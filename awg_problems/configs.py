@@ -46,6 +46,11 @@ class Workload:
     def b(self):
         return self.prob.b
 
+    @property
+    def coords(self):
+        """(n, dim) coordinates of the node of every dof."""
+        return self.prob.node_xyz[self.prob.node_of_dof]
+
 
 def cell_centroids(shape_cells, h):
     """Centroids of the cells in the element order used by the assemblers."""

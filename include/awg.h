@@ -86,6 +86,15 @@ typedef struct {
   int32_t eig_seed;      /* seed of the random start block; default 0 */
   double eig_tol;        /* relative Ritz residual required of every Ritz value
                             below 2 tau; default 1e-10 */
+  const struct awg_mlp* eig_init;  /* learned start (awg_mlp.h): the network's
+                            outputs on the per-dof features fill the first
+                            out_channels columns of the start block (the rest
+                            stays random); needs in_features = AWG_MLP_FEATURES
+                            and out_channels <= eig_block.  NULL (default):
+                            random start.  Not owned; used during awg_setup only */
+  const double* coords;  /* optional node coordinates of every dof, device,
+                            n x coord_dim row-major (features 0-2); NULL (default) */
+  int32_t coord_dim;     /* 1..3 when coords is given */
 } awg_options;
 
 /* Fill *opt with the defaults above (tau = 0.1).  Host pointer. */

@@ -25,14 +25,18 @@ STATUS = {0: "AWG_OK", 1: "AWG_NOT_CONVERGED", -1: "AWG_ERR_ARG", -2: "AWG_ERR_N
 
 EXPORTED = ["awg_default_options", "awg_setup", "awg_apply", "awg_pcg", "awg_stats", "awg_export",
             "awg_last_error", "awg_destroy", "awg_kernel_timing", "awg_kernel_times", "awg_pcg_graph",
-            "awg_dense_gemm", "awg_dense_potrf", "awg_dense_trsm", "awg_dense_low_eigs"]
+            "awg_dense_gemm", "awg_dense_potrf", "awg_dense_trsm", "awg_dense_low_eigs",
+            "awg_mlp_create", "awg_mlp_num_params", "awg_mlp_get_params", "awg_mlp_set_params", "awg_mlp_forward",
+            "awg_mlp_loss_grad", "awg_mlp_get_grads", "awg_mlp_adam_step", "awg_mlp_last_error", "awg_mlp_destroy"]
+MLP_FEATURES = 12
 
 
 class Options(ctypes.Structure):
     _fields_ = [("tau", ctypes.c_double), ("zero_tol", ctypes.c_double), ("w_rtol", ctypes.c_double),
                 ("w_maxit", ctypes.c_int32), ("local_prec", ctypes.c_int32), ("stream", ctypes.c_void_p),
                 ("geneo_solver", ctypes.c_int32), ("eig_block", ctypes.c_int32), ("eig_maxit", ctypes.c_int32),
-                ("eig_seed", ctypes.c_int32), ("eig_tol", ctypes.c_double)]
+                ("eig_seed", ctypes.c_int32), ("eig_tol", ctypes.c_double), ("eig_init", ctypes.c_void_p),
+                ("coords", ctypes.c_void_p), ("coord_dim", ctypes.c_int32)]
 
 
 class PCGInfo(ctypes.Structure):
@@ -91,6 +95,23 @@ def lib():
     L.awg_dense_trsm.restype = ctypes.c_int
     L.awg_dense_low_eigs.argtypes = [i32, i32, vp, i32, i64, dbl, i32, vp, vp, vp, i64, vp]
     L.awg_dense_low_eigs.restype = ctypes.c_int
+    L.awg_mlp_create.argtypes = [ctypes.POINTER(vp), i32, i32, i32, i32, ctypes.c_uint64]
+    L.awg_mlp_create.restype = ctypes.c_int
+    L.awg_mlp_num_params.argtypes = [vp]
+    L.awg_mlp_num_params.restype = i64
+    for nm in ("awg_mlp_get_params", "awg_mlp_set_params", "awg_mlp_get_grads"):
+        getattr(L, nm).argtypes = [vp, vp, i64]
+        getattr(L, nm).restype = ctypes.c_int
+    L.awg_mlp_forward.argtypes = [vp, i64, vp, vp, i32, vp]
+    L.awg_mlp_forward.restype = ctypes.c_int
+    L.awg_mlp_loss_grad.argtypes = [vp, i64, vp, i32, vp, vp, vp, vp, dbl, ctypes.POINTER(dbl), vp]
+    L.awg_mlp_loss_grad.restype = ctypes.c_int
+    L.awg_mlp_adam_step.argtypes = [vp, dbl, dbl, dbl, dbl, vp]
+    L.awg_mlp_adam_step.restype = ctypes.c_int
+    L.awg_mlp_last_error.argtypes = [vp]
+    L.awg_mlp_last_error.restype = ctypes.c_char_p
+    L.awg_mlp_destroy.argtypes = [vp]
+    L.awg_mlp_destroy.restype = None
     _lib = L
     return L
 
@@ -127,7 +148,8 @@ class Solver:
 
     def __init__(self, A, subs, tau: float = 0.1, local_prec: str = "f64", w_rtol: float = 1e-10,
                  w_maxit: int = 500, zero_tol: float = 1e-12, device: str = "cuda", geneo: str = "dense",
-                 eig_block: int = 16, eig_maxit: int = 200, eig_tol: float = 1e-10, eig_seed: int = 0):
+                 eig_block: int = 16, eig_maxit: int = 200, eig_tol: float = 1e-10, eig_seed: int = 0,
+                 eig_init: "MLP | None" = None, coords=None):
         import torch
         L = lib()
         self._torch = torch
@@ -169,6 +191,16 @@ class Solver:
         opt.eig_maxit = eig_maxit
         opt.eig_tol = eig_tol
         opt.eig_seed = eig_seed
+        if eig_init is not None:
+            opt.eig_init = eig_init._h
+        if coords is not None:
+            coords = torch.as_tensor(np.asarray(coords, dtype=np.float64) if not torch.is_tensor(coords) else coords,
+                                     dtype=torch.float64, device=self.device).contiguous()
+            if coords.dim() == 1:
+                coords = coords[:, None]
+            opt.coords = coords.data_ptr()
+            opt.coord_dim = coords.shape[1]
+            self._coords = coords
         self._opt = opt
         ctx = ctypes.c_void_p()
         rc = L.awg_setup(ctypes.byref(ctx), self.n, self.nnz, rowptr.data_ptr(), col.data_ptr(), val.data_ptr(),
@@ -216,7 +248,8 @@ class Solver:
         L = lib()
         nbytes = L.awg_export(self._ctx, name.encode(), None, 0)
         self._check(nbytes)
-        dt = np.int32 if name in ("mult", "pair_count") else np.float64
+        dt = (np.int32 if name in ("mult", "pair_count") else np.float32 if name == "mlp_features"
+              else np.float64)
         out = np.empty(int(nbytes) // np.dtype(dt).itemsize, dtype=dt)
         if nbytes:
             self._check(L.awg_export(self._ctx, name.encode(), out.ctypes.data, int(nbytes)))
@@ -290,3 +323,72 @@ def dense_low_eigs(A, thr, max_k):
     if rc not in (0, -1):
         raise AWGError(rc, "awg_dense_low_eigs")
     return cnt, lam, Z
+
+
+# ---------------------------------------------------------------------------
+# warm-start network (include/awg_mlp.h)
+# ---------------------------------------------------------------------------
+class MLP:
+    """Per-dof perceptron on the GPU; FP32 parameters, FP32 training, BF16 or
+    FP32 inference.  Tensors passed in are device tensors."""
+
+    def __init__(self, in_features: int = MLP_FEATURES, width: int = 256, hidden_layers: int = 3,
+                 out_channels: int = 8, seed: int = 0):
+        h = ctypes.c_void_p()
+        rc = lib().awg_mlp_create(ctypes.byref(h), in_features, width, hidden_layers, out_channels, seed)
+        if rc:
+            raise AWGError(rc, lib().awg_mlp_last_error(None).decode())
+        self._h = h
+        self.dims = [in_features] + [width] * hidden_layers + [out_channels]
+
+    @property
+    def num_params(self) -> int:
+        return int(lib().awg_mlp_num_params(self._h))
+
+    def _check(self, rc):
+        if rc:
+            raise AWGError(rc, lib().awg_mlp_last_error(self._h).decode())
+
+    def get_params(self) -> np.ndarray:
+        out = np.empty(self.num_params, dtype=np.float32)
+        self._check(lib().awg_mlp_get_params(self._h, out.ctypes.data, out.size))
+        return out
+
+    def set_params(self, vec) -> None:
+        vec = np.ascontiguousarray(vec, dtype=np.float32)
+        self._check(lib().awg_mlp_set_params(self._h, vec.ctypes.data, vec.size))
+
+    def get_grads(self) -> np.ndarray:
+        out = np.empty(self.num_params, dtype=np.float32)
+        self._check(lib().awg_mlp_get_grads(self._h, out.ctypes.data, out.size))
+        return out
+
+    def forward(self, X, bf16: bool = True):
+        import torch
+        X = X.to(dtype=torch.float32).contiguous()
+        Y = torch.empty(X.shape[0], self.dims[-1], dtype=torch.float32, device=X.device)
+        self._check(lib().awg_mlp_forward(self._h, X.shape[0], X.data_ptr(), Y.data_ptr(), int(bf16), _stream()))
+        return Y
+
+    def loss_grad(self, X, row_ptr, tgt_off, tgt_cols, T, ridge: float = 1e-4) -> float:
+        """Loss over the subdomains (row_ptr int64, tgt_off int64, tgt_cols int32,
+        T float32: device tensors); the gradient stays in the model."""
+        loss = ctypes.c_double()
+        self._check(lib().awg_mlp_loss_grad(self._h, X.shape[0], X.data_ptr(), row_ptr.numel() - 1,
+                                            row_ptr.data_ptr(), tgt_off.data_ptr(), tgt_cols.data_ptr(),
+                                            T.data_ptr(), ridge, ctypes.byref(loss), _stream()))
+        return loss.value
+
+    def adam_step(self, lr: float = 1e-3, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8) -> None:
+        self._check(lib().awg_mlp_adam_step(self._h, lr, beta1, beta2, eps, _stream()))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().awg_mlp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

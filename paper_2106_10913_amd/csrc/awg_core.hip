@@ -17,6 +17,8 @@
 #include "awg_common.h"
 #include "awg_sparse.h"
 #include "awg_subspace.h"
+#include "awg_mlp.h"
+#include "awg_mlp_impl.h"
 
 using namespace awg;
 
@@ -196,6 +198,11 @@ struct awg_ctx {
   std::vector<double> eig_resid_max;
   std::vector<int> eig_iters;   // subspace GenEO: iteration of convergence per subdomain
   int eig_fallbacks = 0;        // subdomains whose subspace result was not certified
+  int eig_learned = 0;          // start block came from the network
+  DBuf<double> ritzZ, ritzMu;   // last Ritz block (sum n_s x q) and values mu = 1/lambda
+  int ritz_q = 0;
+  DBuf<double> coords;          // optional node coordinates (n x cdim)
+  int cdim = 0;
 };
 
 namespace {
@@ -814,6 +821,21 @@ int geneo_subspace(awg_ctx& c, const double* MB, double* MA) {
     gemm_batched(b, N, c.maxns, q, false, false, -1.0, 1.0, false, s, flK);
   };
   l_rand_block(N, c.maxns, c.subptr, c.subidx, q, (uint64_t)(uint32_t)c.opt.eig_seed, X, s);
+  c.eig_learned = 0;
+  if (c.opt.eig_init) {
+    // learned start: network outputs on the per-dof features fill the first p columns
+    awg_mlp& net = *const_cast<awg_mlp*>(c.opt.eig_init);
+    const int p = net.dims.back();
+    DBuf<float> feat, out;
+    feat.alloc((size_t)c.sumns * MLP_FEATURES);
+    out.alloc((size_t)c.sumns * p);
+    l_mlp_features(N, c.n, c.maxns, c.subptr, c.subidx, c.rowptr, c.col, c.val, c.invptr, c.invsub, c.invloc,
+                   c.mult, c.V, c.LV.d_eoff, c.LV.d_coff, c.P, c.d_sqoff, c.coords.p, c.cdim, feat, s);
+    mlp_forward(net, c.sumns, feat, out, true, s);
+    l_block_from_rows(N, c.maxns, c.subptr, q, p, out, X, s);
+    sync(c);
+    c.eig_learned = 1;
+  }
   project(dg3x, dg4x);
   c.eig_iters.assign(N, -1);
   int it = 0, nconv = 0;
@@ -840,6 +862,13 @@ int geneo_subspace(awg_ctx& c, const double* MB, double* MA) {
   }
   hflag = flag.download(s);
   std::vector<int> hsel = nsel.download(s);
+  std::swap(c.ritzZ.p, Z.p);
+  std::swap(c.ritzZ.n, Z.n);
+  std::swap(c.ritzMu.p, mu.p);
+  std::swap(c.ritzMu.n, mu.n);
+  c.ritz_q = q;
+  const double* Zk = c.ritzZ.p;
+  const double* muk = c.ritzMu.p;
   int fails = 0;
   std::vector<int> ms(N);
   for (int t = 0; t < N; ++t) {
@@ -853,7 +882,7 @@ int geneo_subspace(awg_ctx& c, const double* MB, double* MA) {
   c.lamY.alloc(std::max<long>(1, c.LY.cols));
   int maxm = 0;
   for (int v : ms) maxm = std::max(maxm, v);
-  l_assemble_modes(N, c.maxns, maxm, c.subptr, q, K, c.LV.d_eoff, c.LV.d_coff, Z, mu, c.Y, c.LY.d_eoff,
+  l_assemble_modes(N, c.maxns, maxm, c.subptr, q, K, c.LV.d_eoff, c.LV.d_coff, Zk, muk, c.Y, c.LY.d_eoff,
                    c.LY.d_coff, c.lamY, s);
   // M_B-orthonormal basis of span(Y): Y <- Y L^-T with Y^T M_B Y = L L^T
   std::vector<long> moff(N + 1, 0);
@@ -1430,7 +1459,8 @@ std::string stats_json(const awg_ctx& c) {
   arr("kstrict_s", c.kstrict);
   o << ",";
   arr("m_s", c.ms);
-  o << ",\"geneo_solver\":" << c.opt.geneo_solver << ",\"eig_fallbacks\":" << c.eig_fallbacks << ",";
+  o << ",\"geneo_solver\":" << c.opt.geneo_solver << ",\"eig_fallbacks\":" << c.eig_fallbacks
+    << ",\"eig_learned\":" << c.eig_learned << ",\"eig_block\":" << c.opt.eig_block << ",";
   arr("eig_iters", c.eig_iters);
   o << ",\"eig_resid_max\":[";
   for (size_t i = 0; i < c.eig_resid_max.size(); ++i) o << (i ? "," : "") << c.eig_resid_max[i];
@@ -1493,8 +1523,13 @@ int awg_setup(awg_ctx** out, int64_t n, int64_t nnz, const int64_t* rowptr, cons
   if (!(o.zero_tol >= 0.0) || !(o.w_rtol > 0.0) || o.w_maxit <= 0 ||
       (o.local_prec != AWG_LOCAL_F64 && o.local_prec != AWG_LOCAL_F32) ||
       (o.geneo_solver != AWG_GENEO_DENSE && o.geneo_solver != AWG_GENEO_SUBSPACE) || o.eig_block < 1 ||
-      o.eig_block > SUBSPACE_MAX_BLOCK || o.eig_maxit < 1 || !(o.eig_tol > 0.0)) {
+      o.eig_block > SUBSPACE_MAX_BLOCK || o.eig_maxit < 1 || !(o.eig_tol > 0.0) ||
+      (o.coords && (o.coord_dim < 1 || o.coord_dim > 3))) {
     g_setup_error = "awg_setup: invalid option value";
+    return AWG_ERR_ARG;
+  }
+  if (o.eig_init && (o.eig_init->dims.front() != MLP_FEATURES || o.eig_init->dims.back() > o.eig_block)) {
+    g_setup_error = "awg_setup: eig_init needs in_features = AWG_MLP_FEATURES and out_channels <= eig_block";
     return AWG_ERR_ARG;
   }
   awg_ctx* c = new (std::nothrow) awg_ctx();
@@ -1508,6 +1543,11 @@ int awg_setup(awg_ctx** out, int64_t n, int64_t nnz, const int64_t* rowptr, cons
   c->nnz = (int)nnz;
   c->N = nsub;
   try {
+    if (o.coords) {
+      c->cdim = o.coord_dim;
+      c->coords.alloc((size_t)n * o.coord_dim);
+      AWG_HIP(hipMemcpyAsync(c->coords.p, o.coords, sizeof(double) * n * o.coord_dim, hipMemcpyDeviceToDevice, c->s));
+    }
     do_setup(*c, rowptr, col, val, sub_ptr, sub_idx);
   } catch (const Error& e) {
     g_setup_error = e.what();
@@ -1571,6 +1611,25 @@ int64_t awg_export(const awg_ctx* c, const char* name, void* buf, size_t cap) {
   else if (nm == "V_minus") { src = c->V.p; bytes = sizeof(double) * c->LV.elems; }
   else if (nm == "Y") { src = c->Y.p; bytes = sizeof(double) * c->LY.elems; }
   else if (nm == "P_local") { src = c->P.p; bytes = sizeof(double) * c->sqtot; }
+  else if (nm == "ritz_vectors") { src = c->ritzZ.p; bytes = sizeof(double) * c->sumns * c->ritz_q; }
+  else if (nm == "ritz_values") { src = c->ritzMu.p; bytes = sizeof(double) * c->N * c->ritz_q; }
+  else if (nm == "mlp_features") {
+    bytes = sizeof(float) * c->sumns * MLP_FEATURES;
+    if (buf && cap && bytes) {
+      try {
+        DBuf<float> f;
+        f.alloc((size_t)c->sumns * MLP_FEATURES);
+        l_mlp_features(c->N, c->n, c->maxns, c->subptr, c->subidx, c->rowptr, c->col, c->val, c->invptr, c->invsub,
+                       c->invloc, c->mult, c->V, c->LV.d_eoff, c->LV.d_coff, c->P, c->d_sqoff, c->coords.p, c->cdim,
+                       f, c->s);
+        AWG_HIP(hipMemcpyAsync(buf, f.p, std::min(cap, bytes), hipMemcpyDeviceToHost, c->s));
+        AWG_HIP(hipStreamSynchronize(c->s));
+      } catch (const Error& e) {
+        return e.code;
+      }
+    }
+    return (int64_t)bytes;
+  }
   else return AWG_ERR_ARG;
   if (buf && cap && bytes) {
     if (hipMemcpyAsync(buf, src, std::min(cap, bytes), hipMemcpyDeviceToHost, c->s) != hipSuccess ||
