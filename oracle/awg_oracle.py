@@ -197,6 +197,30 @@ def split_local(Bs: np.ndarray, eps0: float = 1e-12) -> LocalSplit:
 # ---------------------------------------------------------------------------
 # the whole setup
 # ---------------------------------------------------------------------------
+def gram_keep(E: np.ndarray, tol: float = 1e-10) -> np.ndarray:
+    """Columns of a (possibly dependent) basis kept for a Gram matrix E.
+
+    Reading of the basis assumption of Section 2 (a basis of V0 is assumed,
+    none is constructed) and of Remark 1, Section 4.4 (dependent columns of
+    the second coarse space may have to be removed): a left-to-right Cholesky
+    factorisation deletes column k when its pivot (the squared norm, in the
+    inner product of E, of the part of basis vector k outside the span of the
+    kept earlier ones) is <= tol * E_kk.  The projection onto the span is then
+    X_keep E_keep^{-1} X_keep^T.
+    """
+    n = E.shape[0]
+    L = np.zeros((n, n))
+    keep = []
+    for k in range(n):
+        d = E[k, k] - L[k, keep] @ L[k, keep]
+        if not d > tol * E[k, k]:
+            continue
+        L[k, k] = np.sqrt(d)
+        L[k + 1:, k] = (E[k + 1:, k] - L[k + 1:, keep] @ L[k, keep]) / L[k, k]
+        keep.append(k)
+    return np.array(keep, dtype=np.int64)
+
+
 @dataclasses.dataclass
 class AWGSetup:
     A: sp.csr_matrix
@@ -216,6 +240,8 @@ class AWGSetup:
     EW_cho: tuple
     Vg: np.ndarray                # prolongated strictly negative eigenvectors
     w_info: dict
+    E0_keep: np.ndarray = None    # kept coarse vectors (gram_keep); all unless dependent
+    EW_keep: np.ndarray = None
 
     @property
     def n(self):
@@ -228,6 +254,14 @@ class AWGSetup:
     @property
     def n_minus(self):
         return self.W.shape[1]
+
+    @property
+    def n0_rank(self):
+        return int(self.E0_keep.size)
+
+    @property
+    def n_minus_rank(self):
+        return int(self.EW_keep.size)
 
     # -- A_- and A_+ actions (Definition of A_+ and A_-, Section 3.2) -----
     def A_minus_mv(self, X):
@@ -257,7 +291,15 @@ class AWGSetup:
 
     # -- coarse solve with E0 -------------------------------------------
     def E0_solve(self, g):
-        return sla.cho_solve(self.E0_cho, g)
+        """E0^+ g on the kept coarse vectors (zero on the deleted ones)."""
+        out = np.zeros_like(g, dtype=np.float64)
+        out[self.E0_keep] = sla.cho_solve(self.E0_cho, g[self.E0_keep])
+        return out
+
+    def EW_solve(self, g):
+        out = np.zeros_like(g, dtype=np.float64)
+        out[self.EW_keep] = sla.cho_solve(self.EW_cho, g[self.EW_keep])
+        return out
 
     def H2(self, r):
         """H2 = Pi H^NN Pi^T + R0^T E0^{-1} R0 (Theorem for H^NN_hyb, Section 3.4)."""
@@ -271,7 +313,7 @@ class AWGSetup:
         """H r with H = H3,ad = H2 + W (W^T A W)^{-1} W^T (Definition, Section 4.3)."""
         z = self.H2(r)
         if self.n_minus:
-            z = z + self.W @ sla.cho_solve(self.EW_cho, self.W.T @ r)
+            z = z + self.W @ self.EW_solve(self.W.T @ r)
         return z
 
 
@@ -348,10 +390,12 @@ def setup(A: sp.csr_matrix, subs, tau: float, eps0: float = 1e-12, w_solver: str
     AR0T = st.A_plus_mv(R0T.toarray())
     E0 = np.asarray(R0T.T @ AR0T)
     st.E0 = 0.5 * (E0 + E0.T)
+    st.E0_keep = gram_keep(st.E0)
+    st.EW_keep = np.zeros(0, dtype=np.int64)
     try:
-        st.E0_cho = sla.cho_factor(st.E0, lower=True)
+        st.E0_cho = sla.cho_factor(st.E0[np.ix_(st.E0_keep, st.E0_keep)], lower=True)
     except np.linalg.LinAlgError as e:
-        raise OracleError("E0 is not positive definite") from e
+        raise OracleError("E0 is not positive semi-definite") from e
 
     # second coarse space W = A_+^{-1} [R^1T V^1_- | ... ] with strictly
     # negative eigenvalues only (Remark 1, Section 4.4)
@@ -374,10 +418,11 @@ def setup(A: sp.csr_matrix, subs, tau: float, eps0: float = 1e-12, w_solver: str
             st.W, st.w_info = solve_A_plus_pcg(st, Vg, w_rtol, w_maxit)
         EW = st.W.T @ (A @ st.W)
         st.EW = 0.5 * (EW + EW.T)
+        st.EW_keep = gram_keep(st.EW)
         try:
-            st.EW_cho = sla.cho_factor(st.EW, lower=True)
+            st.EW_cho = sla.cho_factor(st.EW[np.ix_(st.EW_keep, st.EW_keep)], lower=True)
         except np.linalg.LinAlgError as e:
-            raise OracleError("W^T A W is not positive definite") from e
+            raise OracleError("W^T A W is not positive semi-definite") from e
     return st
 
 

@@ -136,9 +136,12 @@ void gemv_batched(const GemmDesc* d_desc, int batch, int max_m, int max_k, bool 
                   double beta, hipStream_t s, double bytes = 0.0, double* part = nullptr);
 
 // Cholesky A = L L^T (lower, in place) of every block; info[b] = 0 or the
-// 1-based column of the first non-positive pivot.
+// 1-based column of the first non-positive pivot.  With dropped != NULL (a
+// single block only): columns whose pivot is <= tol * diag0[c] are deleted
+// (dropped[c] = 1, unit diagonal, zero column below), see k_potf2.
 void potrf_batched(const MatDesc* d_mats, const std::vector<int>& h_n, int* d_info, hipStream_t s,
-                   GemmDesc* d_scratch_desc);
+                   GemmDesc* d_scratch_desc, const double* diag0 = nullptr, int* dropped = nullptr,
+                   double tol = 0.0);
 // Solve L X = B (trans = false) or L^T X = B (trans = true) with the lower
 // factor L of block b (n_b x n_b) and B_b (n_b x ncols_b); X overwrites B.
 void trsm_batched(const MatDesc* d_L, const MatDesc* d_B, const std::vector<int>& h_n,

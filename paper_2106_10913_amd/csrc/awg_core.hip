@@ -138,6 +138,10 @@ struct ColLayout {
 
 // workspace for applying the operators to b columns at once; every n x b,
 // sum_s n_s x b, k x b array is row-major (the b values of a row contiguous)
+// relative pivot below which a basis vector of a coarse space counts as
+// dependent on the previous ones (Gram matrices E0 and W^T A W)
+constexpr double GRAM_DROP_TOL = 1e-10;
+
 struct MultiWS {
   int b = 0;
   DBuf<double> R, Z, T1, T2;          // n x b
@@ -199,6 +203,8 @@ struct awg_ctx {
   std::vector<int> eig_iters;   // subspace GenEO: iteration of convergence per subdomain
   int eig_fallbacks = 0;        // subdomains whose subspace result was not certified
   int eig_learned = 0;          // start block came from the network
+  int n0_dropped = 0;           // dependent coarse vectors deleted from E0 (rank = n0 - n0_dropped)
+  int nminus_dropped = 0;       // dependent W columns deleted from W^T A W
   DBuf<double> ritzZ, ritzMu;   // last Ritz block (sum n_s x q) and values mu = 1/lambda
   int ritz_q = 0;
   DBuf<double> coords;          // optional node coordinates (n x cdim)
@@ -1092,24 +1098,64 @@ void phase_local(awg_ctx& c) {
   }
 }
 
-// explicit inverse of one dense spd matrix M (n x n, in place in M's buffer
-// replaced by the inverse in Minv)
-void spd_inverse(awg_ctx& c, double* M, int n, DBuf<double>& Minv, const char* what) {
+__global__ void k_get_diag(const double* M, int n, double* d) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) d[i] = M[i + (long)i * n];
+}
+
+// rows of deleted columns of the factor: zero left of the diagonal
+__global__ void k_zero_dropped_rows(double* L, int n, const int* dropped) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long)n * n) return;
+  const int r = (int)(e % n), c = (int)(e / n);
+  if (c < r && dropped[r]) L[e] = 0.0;
+}
+
+// rows and columns of deleted indices of the inverse
+__global__ void k_zero_dropped_rc(double* M, int n, const int* dropped) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long)n * n) return;
+  const int r = (int)(e % n), c = (int)(e / n);
+  if (dropped[r] || dropped[c]) M[e] = 0.0;
+}
+
+// Pseudo-inverse of a dense symmetric positive semi-definite Gram matrix M
+// (n x n, destroyed) of a possibly dependent basis: Cholesky with deletion of
+// every column whose pivot is <= 1e-10 times its diagonal (its basis vector
+// lies in the span of the previous ones to that relative accuracy), inverse
+// of the kept principal submatrix, zero rows and columns for the deleted
+// ones.  Applied as X E^+ X^T this is the projection onto the span.  Returns
+// the number of deleted columns.
+int spd_inverse(awg_ctx& c, double* M, int n, DBuf<double>& Minv, const char* what) {
   hipStream_t s = c.s;
   Minv.alloc((long)n * n);
   DBuf<MatDesc> dm, di;
   dm.upload({MatDesc{M, n, n, n, 0}}, s);
   di.upload({MatDesc{Minv.p, n, n, n, 0}}, s);
   l_scale_sym(dm, 1, nullptr, nullptr, false, true, s);
-  DBuf<int> info;
+  DBuf<double> d0;
+  DBuf<int> info, drop;
+  d0.alloc(n);
+  drop.alloc(n);
+  drop.zero(s);
+  hipLaunchKernelGGL(k_get_diag, dim3(cdiv(n, 256)), dim3(256), 0, s, M, n, d0.p);
+  AWG_LAUNCH_CHECK();
   info.alloc(1);
   info.zero(s);
-  potrf_batched(dm, {n}, info, s, nullptr);
+  potrf_batched(dm, {n}, info, s, nullptr, d0, drop, GRAM_DROP_TOL);
   check_info(c, info, what);
+  const unsigned g = cdiv((long)n * n, 256);
+  hipLaunchKernelGGL(k_zero_dropped_rows, dim3(g), dim3(256), 0, s, M, n, drop.p);
+  AWG_LAUNCH_CHECK();
   l_set_identity(di, 1, s);
   trsm_batched(dm, di, {n}, {n}, false, s, nullptr);
   trsm_batched(dm, di, {n}, {n}, true, s, nullptr);
   l_scale_sym(di, 1, nullptr, nullptr, false, true, s);
+  hipLaunchKernelGGL(k_zero_dropped_rc, dim3(g), dim3(256), 0, s, Minv.p, n, drop.p);
+  AWG_LAUNCH_CHECK();
+  int nd = 0;
+  for (int v : drop.download(s)) nd += v;
+  return nd;
 }
 
 // number of columns per pass: at most cap, balanced over the passes
@@ -1140,7 +1186,7 @@ void phase_coarse0(awg_ctx& c) {
                        (long)c.n0, (long)c.n0, c0, bc);
     AWG_LAUNCH_CHECK();
   }
-  spd_inverse(c, E0, c.n0, c.E0inv, "coarse matrix E0");
+  c.n0_dropped = spd_inverse(c, E0, c.n0, c.E0inv, "coarse matrix E0");
 }
 
 // W = A_+^{-1} [R^1T V^1_- | ... ] (strictly negative pairs; Remark 1 and 2,
@@ -1253,7 +1299,7 @@ void phase_EW(awg_ctx& c) {
   DBuf<GemmDesc> g;
   g.upload({GemmDesc{c.W.p, AW.p, EW.p, c.nminus, c.nminus, c.n, c.nminus, c.nminus, c.nminus}}, s);
   gemm_batched(g, 1, c.nminus, c.nminus, false, true, 1.0, 0.0, false, s, 2.0 * c.n * (double)c.nminus * c.nminus);
-  spd_inverse(c, EW, c.nminus, c.EWinv, "second coarse matrix W^T A W");
+  c.nminus_dropped = spd_inverse(c, EW, c.nminus, c.EWinv, "second coarse matrix W^T A W");
 }
 
 void do_setup(awg_ctx& c, const int64_t* rowptr, const int32_t* col, const double* val, const int64_t* sub_ptr,
@@ -1460,7 +1506,8 @@ std::string stats_json(const awg_ctx& c) {
   o << ",";
   arr("m_s", c.ms);
   o << ",\"geneo_solver\":" << c.opt.geneo_solver << ",\"eig_fallbacks\":" << c.eig_fallbacks
-    << ",\"eig_learned\":" << c.eig_learned << ",\"eig_block\":" << c.opt.eig_block << ",";
+    << ",\"eig_learned\":" << c.eig_learned << ",\"eig_block\":" << c.opt.eig_block
+    << ",\"n0_dropped\":" << c.n0_dropped << ",\"nminus_dropped\":" << c.nminus_dropped << ",";
   arr("eig_iters", c.eig_iters);
   o << ",\"eig_resid_max\":[";
   for (size_t i = 0; i < c.eig_resid_max.size(); ++i) o << (i ? "," : "") << c.eig_resid_max[i];

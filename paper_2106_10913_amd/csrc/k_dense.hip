@@ -525,11 +525,17 @@ void gemv_batched(const GemmDesc* d_desc, int batch, int max_m, int max_k, bool 
 constexpr int CHOL_NB = 32;
 
 // factor the diagonal block A[j:j+jb, j:j+jb] in LDS
-__global__ __launch_bounds__(256) void k_potf2(const MatDesc* mats, int j, int* info) {
+// With dropped != NULL (one matrix): a column whose Schur-complement pivot is
+// <= tol times its original diagonal diag0 is numerically dependent on the
+// previous ones; it is deleted (unit pivot, zero column) and flagged, so the
+// factor of the kept columns is the Cholesky factor of their principal submatrix.
+__global__ __launch_bounds__(256) void k_potf2(const MatDesc* mats, int j, int* info, const double* diag0,
+                                               int* dropped, double tol) {
   const MatDesc M = mats[blockIdx.x];
   const int jb = min(CHOL_NB, M.n - j);
   if (jb <= 0) return;
   __shared__ double L[CHOL_NB][CHOL_NB + 1];
+  __shared__ int drop_c;
   const int tid = threadIdx.x;
   for (int e = tid; e < jb * jb; e += 256) {
     const int r = e % jb, c = e / jb;
@@ -539,7 +545,12 @@ __global__ __launch_bounds__(256) void k_potf2(const MatDesc* mats, int j, int* 
   for (int c = 0; c < jb; ++c) {
     if (tid == 0) {
       const double piv = L[c][c];
-      if (!(piv > 0.0)) {
+      drop_c = 0;
+      if (dropped && piv == piv && !(piv > tol * diag0[j + c])) {
+        dropped[j + c] = 1;
+        drop_c = 1;
+        L[c][c] = 1.0;
+      } else if (!(piv > 0.0)) {
         if (info[blockIdx.x] == 0) info[blockIdx.x] = j + c + 1;
         L[c][c] = __builtin_nan("");
       } else {
@@ -548,7 +559,7 @@ __global__ __launch_bounds__(256) void k_potf2(const MatDesc* mats, int j, int* 
     }
     __syncthreads();
     const double dc = L[c][c];
-    for (int r = c + 1 + tid; r < jb; r += 256) L[r][c] /= dc;
+    for (int r = c + 1 + tid; r < jb; r += 256) L[r][c] = drop_c ? 0.0 : L[r][c] / dc;
     __syncthreads();
     const int rem = jb - c - 1;
     for (int e = tid; e < rem * rem; e += 256) {
@@ -564,7 +575,7 @@ __global__ __launch_bounds__(256) void k_potf2(const MatDesc* mats, int j, int* 
 }
 
 // rows below the diagonal block: X L_jj^T = A[j+jb:, j:j+jb]
-__global__ __launch_bounds__(256) void k_chol_panel(const MatDesc* mats, int j) {
+__global__ __launch_bounds__(256) void k_chol_panel(const MatDesc* mats, int j, const int* dropped) {
   const MatDesc M = mats[blockIdx.y];
   const int jb = min(CHOL_NB, M.n - j);
   if (jb <= 0) return;
@@ -582,7 +593,7 @@ __global__ __launch_bounds__(256) void k_chol_panel(const MatDesc* mats, int j) 
     if (c < jb) {
       double v = M.A[i + (long)(j + c) * M.ld];
       for (int t = 0; t < c; ++t) v -= x[t] * L[c][t];
-      x[c] = v / L[c][c];
+      x[c] = (dropped && dropped[j + c]) ? 0.0 : v / L[c][c];
     }
   }
 #pragma unroll
@@ -591,17 +602,18 @@ __global__ __launch_bounds__(256) void k_chol_panel(const MatDesc* mats, int j) 
 }
 
 void potrf_batched(const MatDesc* d_mats, const std::vector<int>& h_n, int* d_info, hipStream_t s,
-                   GemmDesc* /*unused*/) {
+                   GemmDesc* /*unused*/, const double* diag0, int* dropped, double tol) {
   const int batch = (int)h_n.size();
   if (batch == 0) return;
   int maxn = 0;
   for (int v : h_n) maxn = v > maxn ? v : maxn;
   for (int j = 0; j < maxn; j += CHOL_NB) {
-    hipLaunchKernelGGL(k_potf2, dim3(batch), dim3(256), 0, s, d_mats, j, d_info);
+    hipLaunchKernelGGL(k_potf2, dim3(batch), dim3(256), 0, s, d_mats, j, d_info, diag0, dropped, tol);
     AWG_LAUNCH_CHECK();
     const int rem = maxn - j - CHOL_NB;
     if (rem <= 0) break;
-    hipLaunchKernelGGL(k_chol_panel, dim3(cdiv(rem, 256), batch), dim3(256), 0, s, d_mats, j);
+    hipLaunchKernelGGL(k_chol_panel, dim3(cdiv(rem, 256), batch), dim3(256), 0, s, d_mats, j,
+                       (const int*)dropped);
     AWG_LAUNCH_CHECK();
     double fl = 0.0;
     if (ktimer_on())

@@ -231,11 +231,13 @@ def test_basis_invariance(case):
     R0T2 = R0T @ M0
     st2.R0T = sp.csr_matrix(R0T2)
     E0 = R0T2.T @ st.A_plus_mv(R0T2)
+    st2.E0_keep = np.arange(R0T2.shape[1])
     st2.E0_cho = sla.cho_factor(0.5 * (E0 + E0.T), lower=True)
     if st.n_minus:
         Mw = np.eye(st.n_minus) + 0.3 * rng.standard_normal((st.n_minus,) * 2)
         st2.W = st.W @ Mw
         EW = st2.W.T @ (A @ st2.W)
+        st2.EW_keep = np.arange(st.n_minus)
         st2.EW_cho = sla.cho_factor(0.5 * (EW + EW.T), lower=True)
     z2 = st2.apply(r)
     assert np.linalg.norm(z2 - z) <= 1e-8 * np.linalg.norm(z)
@@ -360,3 +362,33 @@ def test_woodbury_direct_W_matches_dense():
     Ww = X - X @ np.linalg.solve(cap, st.Vg.T @ X)
     assert np.linalg.norm(Ww - Wd) <= 1e-9 * np.linalg.norm(Wd)
     del n_saved
+
+
+# ----------------------------------------------------------------------------
+# dependent coarse vectors (reading of the basis assumption, Section 2)
+# ----------------------------------------------------------------------------
+def test_gram_keep_drops_exactly_the_dependent_columns():
+    rng = np.random.default_rng(8)
+    a, b, c = rng.standard_normal((3, 40))
+    X = np.stack([a, b, a + b, c, 2.0 * a, b - c, rng.standard_normal(40)], axis=1)
+    keep = O.gram_keep(X.T @ X)
+    assert keep.tolist() == [0, 1, 3, 6]
+    # independent columns: nothing deleted
+    Y = rng.standard_normal((30, 12))
+    assert O.gram_keep(Y.T @ Y).tolist() == list(range(12))
+
+
+def test_gram_keep_projection_is_the_projector_onto_the_span():
+    rng = np.random.default_rng(9)
+    B = rng.standard_normal((50, 6))
+    X = np.concatenate([B, B @ rng.standard_normal((6, 4))], axis=1)[:, rng.permutation(10)]
+    Mh = rng.standard_normal((50, 50))
+    M = Mh @ Mh.T + 50 * np.eye(50)                 # the inner product of the Gram matrix
+    keep = O.gram_keep(X.T @ M @ X)
+    assert keep.size == 6
+    Xk = X[:, keep]
+    Pk = Xk @ np.linalg.solve(Xk.T @ M @ Xk, Xk.T @ M)
+    Q, _ = np.linalg.qr(B)
+    # M-orthogonal projector onto span(B): B (B^T M B)^{-1} B^T M
+    Pr = B @ np.linalg.solve(B.T @ M @ B, B.T @ M)
+    assert np.max(np.abs(Pk - Pr)) <= 1e-9
