@@ -38,7 +38,8 @@ def parse():
                     help="GenEO eigensolver of the timed FP64 form")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fast-form", action="store_true")
-    ap.add_argument("--m", type=int, default=256, help="cells per side (256 = the bench workload)")
+    ap.add_argument("--workload", default="q1_2d_256", choices=sorted(WORKLOADS),
+                    help="q1_2d_256 is the headline workload; the others are the larger synthetic configurations")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (HBM counter calibration)")
     return ap.parse_args()
@@ -146,6 +147,36 @@ def roofline(kt: dict, steps: int, workload: str) -> dict:
             "avg_launch_us": round(avg_us, 2), "bytes_per_launch": rec["bytes"] / rec["calls"]}
 
 
+# workload name -> (generator, config string, network file of its family or None)
+def _q1_2d_256(P):
+    return P.q1_2d(m=256)
+
+
+def _q1_2d_512_rcb(P):
+    return P.q1_2d(m=512, seed=2, partition="rcb", nparts=256, delta=2)
+
+
+def _elast3d_40(P):
+    return P.configs.elast3d(40)
+
+
+def _diff3d_64(P):
+    return P.configs.diff3d_grf(65, seed=2000)
+
+
+WORKLOADS = {
+    "q1_2d_256": (_q1_2d_256, "q1_2d_diffusion_256x256_box8x8_overlap2_tau0.1", "geneo_q1_2d.npz"),
+    "q1_2d_512_rcb": (_q1_2d_512_rcb, "q1_2d_diffusion_512x512_rcb256_overlap2_tau0.1", "geneo_q1_2d.npz"),
+    "elast3d_40": (_elast3d_40, "q1_elasticity_40^3_spheres10pct_box8^3_overlap1_tau0.05", None),
+    "diff3d_64": (_diff3d_64, "q1_diffusion_64^3_grf_box8^3_overlap1_tau0.1", "geneo_diff3d.npz"),
+}
+
+
+def make_workload(name: str):
+    import awg_problems as P
+    return WORKLOADS[name][0](P)
+
+
 def copy_probe(torch, mib: int) -> None:
     """Plain copy kernel of known size: reads and writes mib MiB per launch."""
     n = mib * (1 << 20) // 8
@@ -173,7 +204,7 @@ def main():
     from paper_2106_10913_amd import awg
 
     dev = torch.device("cuda:0")
-    w = P.q1_2d(m=args.m)
+    w = make_workload(args.workload)
     A = w.A
     sizes = np.array([len(s) for s in w.subs], dtype=np.int64)
     ptr = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
@@ -184,9 +215,14 @@ def main():
     Sd = (torch.as_tensor(ptr, device=dev), torch.as_tensor(idx, device=dev))
     bd = torch.as_tensor(w.b, device=dev)
     x = torch.empty_like(bd)
+    coords = torch.as_tensor(w.coords, device=dev)
+    from paper_2106_10913_amd import learned
+    wfile = WORKLOADS[args.workload][2]
+    net = learned.load(os.path.join(ROOT, "paper_2106_10913_amd", "weights", wfile)) if wfile else None
 
-    def step(local_prec=args.local_prec, geneo=args.geneo):
-        solver = awg.Solver(Ad, Sd, tau=w.tau, local_prec=local_prec, geneo=geneo)
+    def step(local_prec=args.local_prec, geneo=args.geneo, init=None):
+        solver = awg.Solver(Ad, Sd, tau=w.tau, local_prec=local_prec, geneo=geneo, eig_init=init,
+                            coords=coords if init is not None else None)
         _, info = solver.pcg(bd, tol=w.tol, maxit=1000, x=x)
         st = solver.stats()
         solver.close()
@@ -229,7 +265,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if args.local_prec == "f64" else "f64+f32local",
         "data": "synthetic",
-        "config": {"workload": f"q1_2d_diffusion_{args.m}x{args.m}_box8x8_overlap2_tau0.1",
+        "config": {"workload": WORKLOADS[args.workload][1],
                    "n": int(A.shape[0]), "nnz": int(A.nnz), "N": len(w.subs), "tol": w.tol,
                    "local_prec": args.local_prec},
         "solve": {"iters": info["iters"], "rel_res_true": info["rel_res_true"],
@@ -239,24 +275,28 @@ def main():
     }
     if not args.no_fast_form and args.local_prec == "f64":
         # the same workload with FP32 local operators (eigen-setup, coarse
-        # spaces, PCG and W recurrences stay FP64) and the subspace GenEO solver
-        step("f32", "subspace")
+        # spaces, PCG and W recurrences stay FP64), the subspace GenEO solver
+        # and the learned start (network trained on other seeds of this family)
+        step("f32", "subspace", net)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         for i in range(args.steps):
-            info32, st32 = step("f32", "subspace")
+            info32, st32 = step("f32", "subspace", net)
         torch.cuda.synchronize()
         ms32 = (time.perf_counter() - t1) * 1e3 / args.steps
-        out["fast_form"] = {"local_prec": "f32", "geneo": "subspace", "eig_iters_max": max(st32["eig_iters"]),
+        out["fast_form"] = {"local_prec": "f32", "geneo": "subspace", "eig_learned": st32["eig_learned"],
+                            "network": wfile,
+                            "eig_iters_max": max(st32["eig_iters"]),
                             "eig_fallbacks": st32["eig_fallbacks"], "ms_per_step": round(ms32, 3),
                             "iters": info32["iters"],
                             "rel_res_true": info32["rel_res_true"], "n_minus": st32["n_minus"], "n0": st32["n0"],
                             "w_iters": st32["w_iters"], "speedup_vs_f64": round(ms / ms32, 3),
                             "phases_ms": {k: round(v, 3) for k, v in st32["ms"].items()}}
     out["roofline"] = roofline(kt, args.steps, out["config"]["workload"])
+    out["autotune"] = {k: v["variant"] for k, v in awg.tune_report().items()}
     out["kernels_ms_per_step"] = {k: round(v["ms"] / args.steps, 3) for k, v in
                                   sorted(kt.items(), key=lambda kv: -kv[1]["ms"])}
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.workload == "q1_2d_256":
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out))
 

@@ -124,13 +124,18 @@ typedef struct {
   double rel_res;         /* recursively updated ||r_k|| / ||b|| */
   double rel_res_true;    /* ||b - A x_k|| / ||b|| recomputed at the end */
   double lmin_est;        /* extreme Ritz values of HA from the PCG coefficients */
-  double lmax_est;
+  double lmax_est;        /* (of the first run of the recurrence) */
+  int32_t restarts;       /* restarts from the true residual (see awg_pcg) */
 } awg_pcg_info;
 
 /* PCG (Saad, Section 9.2) from x0 = 0 with the AWG preconditioner; stops at
  * the first k with ||r_k||_2 / ||b||_2 <= tol on the recursive residual.
  * b, x: device vectors of length n.  info: host pointer (may be NULL).
- * maxit > 4095 is treated as 4095 (size of the coefficient history). */
+ * maxit > 4095 is treated as 4095 (size of the coefficient history).
+ * When the recursive residual meets tol but the true residual b - A x does
+ * not (finite-precision drift on ill-conditioned A), the recurrence restarts
+ * from the true residual (at most 5 times, iterations keep counting);
+ * converged = 1 requires both residuals <= tol. */
 int awg_pcg(awg_ctx* ctx, const double* b, double* x, double tol, int32_t maxit,
             awg_pcg_info* info);
 

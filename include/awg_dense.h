@@ -18,6 +18,7 @@
 #ifndef AWG_DENSE_H
 #define AWG_DENSE_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -49,6 +50,23 @@ int awg_dense_trsm(int32_t batch, int32_t n, int32_t nrhs, int32_t trans, const 
 int awg_dense_low_eigs(int32_t batch, int32_t n, double* A, int32_t lda, int64_t strideA, double thr,
                        int32_t max_k, int32_t* count_host, double* lam, double* Z, int64_t strideZ,
                        void* stream);
+
+/* Y = alpha A X + beta Y for a CSR matrix A (n x n, 0-based, rowptr int64 with
+ * nnz < 2^31) and row-major n x b blocks X, Y (the multi-column product of the
+ * W solves).  variant: -1 = the autotuned launch variant for this shape
+ * (measured on the first call with beta = 0), 0..4 = a fixed variant; every
+ * variant returns bit-identical results. */
+int awg_csr_spmm(int32_t n, int64_t nnz, const int64_t* rowptr, const int32_t* col, const double* val,
+                 const double* X, double* Y, int32_t b, double alpha, double beta, int32_t variant, void* stream);
+
+/* Autotuner of launch variants: enable (default) or disable measurement
+ * (disabled: variant 0 everywhere).  Choices persist as JSON lines in the file
+ * named by the environment variable AWG_TUNE_CACHE when it is set. */
+int awg_autotune(int32_t enable);
+/* JSON object {key: {"variant": v, "us": [time per variant]}} of this
+ * process's choices into buf (host, cap bytes, NUL-terminated); returns the
+ * full length. */
+int64_t awg_tune_report(char* buf, size_t cap);
 
 #ifdef __cplusplus
 }

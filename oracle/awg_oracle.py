@@ -535,6 +535,7 @@ class PCGResult:
     alphas: list
     betas: list
     rel_res_true: float
+    restarts: int = 0         # restarts from the true residual
 
     def lanczos_extremes(self):
         """Extreme Ritz values of HA from the PCG coefficients (Lanczos tridiagonal)."""
@@ -550,8 +551,16 @@ class PCGResult:
         return float(ev[0]), float(ev[-1])
 
 
-def pcg(A, b, M, tol: float = 1e-8, maxit: int = 1000, norm: str = "unpreconditioned") -> PCGResult:
+def pcg(A, b, M, tol: float = 1e-8, maxit: int = 1000, norm: str = "unpreconditioned",
+        max_restarts: int = 5) -> PCGResult:
     """PCG from x0 = 0; stops at the first k with ||r_k||/||b|| <= tol.
+
+    The textbook recurrence (Saad, Iterative Methods for Sparse Linear
+    Systems, Algorithm 9.1).  Reading of the stopping rule (the paper states a
+    relative residual tolerance only): when the recursive residual meets tol
+    but the true residual b - A x_k does not (rounding drift on
+    ill-conditioned A), the recurrence restarts from the true residual
+    (at most max_restarts times; iterations keep counting).
 
     norm="preconditioned" instead tests ||H r_k|| / ||H b|| (the default
     of PETSc's CG, used only to compare iteration counts with the paper's
@@ -571,6 +580,7 @@ def pcg(A, b, M, tol: float = 1e-8, maxit: int = 1000, norm: str = "unpreconditi
     rz = r @ z
     k = 0
     converged = False
+    restarts = 0
     while k < maxit:
         q = A @ p
         pq = p @ q
@@ -580,22 +590,32 @@ def pcg(A, b, M, tol: float = 1e-8, maxit: int = 1000, norm: str = "unpreconditi
         x += alpha * p
         r -= alpha * q
         k += 1
-        alphas.append(alpha)
+        if restarts == 0:
+            alphas.append(alpha)
         hist.append(np.linalg.norm(r) / bn)
         if norm != "preconditioned" and hist[-1] <= tol:
-            converged = True
-            break
+            rt = b - A @ x
+            if np.linalg.norm(rt) / bn <= tol or restarts >= max_restarts or k >= maxit:
+                converged = np.linalg.norm(rt) / bn <= tol
+                break
+            restarts += 1
+            r = rt
+            z = M(r)
+            p = z.copy()
+            rz = r @ z
+            continue
         z = M(r)
         if norm == "preconditioned" and np.linalg.norm(z) / zn0 <= tol:
             converged = True
             break
         rz_new = r @ z
         beta = rz_new / rz
-        betas.append(beta)
+        if restarts == 0:
+            betas.append(beta)
         rz = rz_new
         p = z + beta * p
     true = np.linalg.norm(b - A @ x) / bn
-    return PCGResult(x, k, converged, hist, alphas, betas, float(true))
+    return PCGResult(x, k, converged, hist, alphas, betas, float(true), restarts)
 
 
 # ---------------------------------------------------------------------------

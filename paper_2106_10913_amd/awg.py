@@ -27,7 +27,8 @@ EXPORTED = ["awg_default_options", "awg_setup", "awg_apply", "awg_pcg", "awg_sta
             "awg_last_error", "awg_destroy", "awg_kernel_timing", "awg_kernel_times", "awg_pcg_graph",
             "awg_dense_gemm", "awg_dense_potrf", "awg_dense_trsm", "awg_dense_low_eigs",
             "awg_mlp_create", "awg_mlp_num_params", "awg_mlp_get_params", "awg_mlp_set_params", "awg_mlp_forward",
-            "awg_mlp_loss_grad", "awg_mlp_get_grads", "awg_mlp_adam_step", "awg_mlp_last_error", "awg_mlp_destroy"]
+            "awg_mlp_loss_grad", "awg_mlp_get_grads", "awg_mlp_adam_step", "awg_mlp_last_error", "awg_mlp_destroy",
+            "awg_csr_spmm", "awg_autotune", "awg_tune_report"]
 MLP_FEATURES = 12
 
 
@@ -42,7 +43,7 @@ class Options(ctypes.Structure):
 class PCGInfo(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("converged", ctypes.c_int32), ("rel_res", ctypes.c_double),
                 ("rel_res_true", ctypes.c_double), ("lmin_est", ctypes.c_double),
-                ("lmax_est", ctypes.c_double)]
+                ("lmax_est", ctypes.c_double), ("restarts", ctypes.c_int32)]
 
 
 class AWGError(RuntimeError):
@@ -112,6 +113,12 @@ def lib():
     L.awg_mlp_last_error.restype = ctypes.c_char_p
     L.awg_mlp_destroy.argtypes = [vp]
     L.awg_mlp_destroy.restype = None
+    L.awg_csr_spmm.argtypes = [i32, i64, vp, vp, vp, vp, vp, i32, dbl, dbl, i32, vp]
+    L.awg_csr_spmm.restype = ctypes.c_int
+    L.awg_autotune.argtypes = [i32]
+    L.awg_autotune.restype = ctypes.c_int
+    L.awg_tune_report.argtypes = [ctypes.c_char_p, ctypes.c_size_t]
+    L.awg_tune_report.restype = i64
     _lib = L
     return L
 
@@ -130,6 +137,28 @@ def kernel_times(reset: bool = False) -> dict:
     buf = ctypes.create_string_buffer(int(need) + 64)
     L.awg_kernel_times(buf, len(buf), int(reset))
     return json.loads(buf.value.decode())
+
+
+def autotune(enable: bool) -> None:
+    lib().awg_autotune(int(enable))
+
+
+def tune_report() -> dict:
+    L = lib()
+    need = L.awg_tune_report(None, 0)
+    buf = ctypes.create_string_buffer(int(need) + 64)
+    L.awg_tune_report(buf, len(buf))
+    return json.loads(buf.value.decode())
+
+
+def csr_spmm(rowptr, col, val, X, Y, alpha=1.0, beta=0.0, variant=-1):
+    """Y = alpha A X + beta Y (device tensors; X, Y row-major n x b float64)."""
+    n = rowptr.numel() - 1
+    rc = lib().awg_csr_spmm(n, col.numel(), rowptr.data_ptr(), col.data_ptr(), val.data_ptr(), X.data_ptr(),
+                            Y.data_ptr(), X.shape[1], alpha, beta, variant, _stream())
+    if rc:
+        raise AWGError(rc, "awg_csr_spmm")
+    return Y
 
 
 def default_options() -> Options:

@@ -1387,6 +1387,7 @@ void pcg_iteration(awg_ctx& c, bool f32) {
 
 constexpr int PCG_HIST = 4096;     // capacity of the alpha/beta history
 constexpr int PCG_AHEAD = 4;       // iterations launched between two host checks
+constexpr int PCG_MAX_RESTARTS = 5;
 
 int do_pcg(awg_ctx& c, const double* b, double* x, double tol, int maxit, awg_pcg_info* info) {
   hipStream_t s = c.s;
@@ -1410,10 +1411,12 @@ int do_pcg(awg_ctx& c, const double* b, double* x, double tol, int maxit, awg_pc
   awg_pcg_info inf{};
   int status = AWG_OK;
   int it = 0;
-  if (bn == 0.0) {
-    inf.converged = 1;
-  } else if (maxit <= 0) {
-    inf.rel_res = 1.0;
+  if (bn == 0.0 || maxit <= 0) {
+    inf.converged = bn == 0.0;
+    inf.rel_res = bn == 0.0 ? 0.0 : 1.0;
+    inf.rel_res_true = inf.rel_res;
+    AWG_HIP(hipMemsetAsync(x, 0, sizeof(double) * n, s));
+    sync(c);
   } else {
     const double ctl[4] = {tol * tol * h6, 0.0, 0.0, (double)maxit};
     AWG_HIP(hipMemcpyAsync(sc + 8, ctl, sizeof(ctl), hipMemcpyHostToDevice, s));
@@ -1447,44 +1450,64 @@ int do_pcg(awg_ctx& c, const double* b, double* x, double tol, int maxit, awg_pc
       c.s = user;
     }
     double hs[12];
+    int first_seg = -1;     // iterations of the first segment (Lanczos estimates)
     for (;;) {
-      for (int k = 0; k < PCG_AHEAD; ++k) {
-        if (c.pcg_graph) {
-          KScope kt("graph:pcg_iteration", s, 0.0, 0.0);
-          AWG_HIP(hipGraphLaunch(c.pcg_graph, s));
-        } else {
-          pcg_iteration(c, f32);
+      for (;;) {
+        for (int k = 0; k < PCG_AHEAD; ++k) {
+          if (c.pcg_graph) {
+            KScope kt("graph:pcg_iteration", s, 0.0, 0.0);
+            AWG_HIP(hipGraphLaunch(c.pcg_graph, s));
+          } else {
+            pcg_iteration(c, f32);
+          }
         }
+        AWG_HIP(hipMemcpyAsync(hs, sc, sizeof(hs), hipMemcpyDeviceToHost, s));
+        sync(c);
+        if (hs[9] != 0.0) break;
       }
-      AWG_HIP(hipMemcpyAsync(hs, sc, sizeof(hs), hipMemcpyDeviceToHost, s));
+      it = (int)hs[10];
+      if (first_seg < 0) first_seg = it;
+      inf.rel_res = std::sqrt(hs[5]) / bn;
+      if (hs[9] == 2.0) {
+        status = AWG_ERR_NOT_SPD;
+        c.err = "PCG breakdown: p^T A p <= 0 (A or H not spd)";
+        break;
+      }
+      // true residual q = b - A x
+      l_spmm(n, c.nnz, c.rowptr, c.col, c.val, xx, q, 1, -1.0, 0.0, s);
+      l_colaxpby(n, 1, b, nullptr, q, nullptr, 1.0, 1.0, s);
+      l_coldot(n, 1, q, q, w.dotpart, sc + 7, s);
+      double h7;
+      AWG_HIP(hipMemcpyAsync(&h7, sc + 7, sizeof(double), hipMemcpyDeviceToHost, s));
       sync(c);
-      if (hs[9] != 0.0) break;
+      inf.rel_res_true = std::sqrt(h7) / bn;
+      inf.converged = hs[9] == 1.0 && inf.rel_res_true <= tol;
+      if (hs[9] != 1.0 || inf.converged || inf.restarts >= PCG_MAX_RESTARTS) break;
+      // the recursive residual met tol but the true one did not (finite
+      // precision drift): restart the recurrence from the true residual
+      ++inf.restarts;
+      AWG_HIP(hipMemcpyAsync(w.R.p, q, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+      op_h(c, w, f32);
+      AWG_HIP(hipMemcpyAsync(p, w.Z.p, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+      l_coldot(n, 1, w.R, w.Z, w.dotpart, sc + 0, s);
+      const double zero = 0.0;
+      AWG_HIP(hipMemcpyAsync(sc + 9, &zero, sizeof(double), hipMemcpyHostToDevice, s));
+      sync(c);
     }
-    it = (int)hs[10];
-    inf.rel_res = std::sqrt(hs[5]) / bn;
-    if (hs[9] == 1.0) inf.converged = 1;
-    if (hs[9] == 2.0) {
-      status = AWG_ERR_NOT_SPD;
-      c.err = "PCG breakdown: p^T A p <= 0 (A or H not spd)";
+    if (status == AWG_OK) {
+      AWG_HIP(hipMemcpyAsync(x, xx, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+      const int nh = std::max(first_seg, 1);
+      std::vector<double> hist(16 + 2 * (size_t)nh + 2);
+      AWG_HIP(hipMemcpyAsync(hist.data(), sc, sizeof(double) * hist.size(), hipMemcpyDeviceToHost, s));
+      sync(c);
+      std::vector<double> al, be;
+      for (int j = 0; j < first_seg; ++j) al.push_back(hist[16 + 2 * j]);
+      for (int j = 0; j + 1 < first_seg; ++j) be.push_back(hist[17 + 2 * j]);
+      lanczos_extremes(al, be, inf.lmin_est, inf.lmax_est);
     }
   }
   inf.iters = it;
-  if (status == AWG_OK) {
-    AWG_HIP(hipMemcpyAsync(x, xx, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
-    // true residual
-    l_spmm(n, c.nnz, c.rowptr, c.col, c.val, xx, q, 1, -1.0, 0.0, s);
-    l_colaxpby(n, 1, b, nullptr, q, nullptr, 1.0, 1.0, s);
-    l_coldot(n, 1, q, q, w.dotpart, sc + 7, s);
-    std::vector<double> hist(16 + 2 * (size_t)std::max(it, 1) + 2);
-    AWG_HIP(hipMemcpyAsync(hist.data(), sc, sizeof(double) * hist.size(), hipMemcpyDeviceToHost, s));
-    sync(c);
-    inf.rel_res_true = bn > 0 ? std::sqrt(hist[7]) / bn : 0.0;
-    std::vector<double> al, be;
-    for (int j = 0; j < it; ++j) al.push_back(hist[16 + 2 * j]);
-    for (int j = 0; j + 1 < it; ++j) be.push_back(hist[17 + 2 * j]);
-    lanczos_extremes(al, be, inf.lmin_est, inf.lmax_est);
-    if (!inf.converged) status = AWG_NOT_CONVERGED;
-  }
+  if (status == AWG_OK && !inf.converged) status = AWG_NOT_CONVERGED;
   if (info) *info = inf;
   return status;
 }

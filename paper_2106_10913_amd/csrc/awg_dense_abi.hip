@@ -1,9 +1,12 @@
 // C ABI of the batched dense building blocks (include/awg_dense.h).
 #include <algorithm>
+#include <cstring>
 
 #include "awg.h"
 #include "awg_common.h"
 #include "awg_dense.h"
+#include "awg_sparse.h"
+#include "awg_tune.h"
 
 using namespace awg;
 
@@ -27,7 +30,17 @@ int guarded(hipStream_t s, F&& f) {
   return AWG_OK;
 }
 
+__global__ void k_rowptr_to32(int n, const int64_t* in, int* out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i <= n) out[i] = (int)in[i];
+}
+
 }  // namespace
+
+namespace awg {
+void spmm_variant(int v, int n, const int* rowptr, const int* col, const double* val, const double* X, double* Y,
+                  int b, double alpha, double beta, hipStream_t s);
+}
 
 extern "C" {
 
@@ -135,6 +148,40 @@ int awg_dense_low_eigs(int32_t batch, int32_t n, double* A, int32_t lda, int64_t
     }
   });
   return rc ? rc : (over ? AWG_ERR_ARG : AWG_OK);
+}
+
+int awg_csr_spmm(int32_t n, int64_t nnz, const int64_t* rowptr, const int32_t* col, const double* val,
+                 const double* X, double* Y, int32_t b, double alpha, double beta, int32_t variant, void* stream) {
+  if (n <= 0 || nnz < 0 || nnz >= (1LL << 31) || b <= 0 || variant < -1 || variant > 4 || !rowptr ||
+      (nnz && (!col || !val)) || !X || !Y)
+    return AWG_ERR_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  return guarded(s, [&] {
+    DBuf<int> rp;
+    rp.alloc(n + 1);
+    hipLaunchKernelGGL(k_rowptr_to32, dim3(cdiv(n + 1, 256)), dim3(256), 0, s, n, rowptr, rp.p);
+    AWG_LAUNCH_CHECK();
+    if (variant < 0)
+      l_spmm(n, nnz, rp, col, val, X, Y, b, alpha, beta, s);
+    else
+      spmm_variant(variant, n, rp, col, val, X, Y, b, alpha, beta, s);
+    AWG_HIP(hipStreamSynchronize(s));
+  });
+}
+
+int awg_autotune(int32_t enable) {
+  tune_enable(enable != 0);
+  return AWG_OK;
+}
+
+int64_t awg_tune_report(char* buf, size_t cap) {
+  const std::string js = tune_json();
+  if (buf && cap) {
+    const size_t k = std::min(cap - 1, js.size());
+    std::memcpy(buf, js.data(), k);
+    buf[k] = '\0';
+  }
+  return (int64_t)js.size();
 }
 
 }  // extern "C"

@@ -114,3 +114,37 @@ def test_low_eigs_against_eigh(gpu_lib, n):
         Pg = Zb @ Zb.T
         Pr = V[:, :k] @ V[:, :k].T
         assert np.max(np.abs(Pg - Pr), initial=0.0) <= 1e-8
+
+
+@pytest.mark.parametrize("b", [2, 17, 64, 130])
+def test_csr_spmm_variants_bit_identical(gpu_lib, b):
+    """Every SpMM launch variant (and the autotuned one) gives the same bits,
+    within rounding of the exact product; beta != 0 accumulates."""
+    import torch
+    import awg_problems as P
+    A = P.q1_2d(m=24, partition="rcb", nparts=4, delta=1).A.tocsr()
+    A.sort_indices()
+    n = A.shape[0]
+    rng = np.random.default_rng(b)
+    X = rng.standard_normal((n, b))
+    Y0 = rng.standard_normal((n, b))
+    rp = torch.as_tensor(A.indptr.astype(np.int64), device="cuda")
+    ci = torch.as_tensor(A.indices.astype(np.int32), device="cuda")
+    va = torch.as_tensor(A.data, device="cuda")
+    Xd = torch.as_tensor(X, device="cuda")
+    ref = -0.5 * (A @ X) + 2.0 * Y0
+    outs = []
+    for v in [-1, 0, 1, 2, 3, 4]:
+        Yd = torch.as_tensor(Y0, device="cuda")
+        gpu_lib.csr_spmm(rp, ci, va, Xd, Yd, alpha=-0.5, beta=2.0, variant=v)
+        outs.append(Yd.cpu().numpy())
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+    assert np.max(np.abs(outs[0] - ref)) <= 1e-13 * np.max(np.abs(ref))
+    # first tuned call with beta = 0 measures the variants on this shape
+    Yd = torch.empty((n, b), dtype=torch.float64, device="cuda")
+    gpu_lib.csr_spmm(rp, ci, va, Xd, Yd, alpha=1.0, beta=0.0, variant=-1)
+    assert np.max(np.abs(Yd.cpu().numpy() - A @ X)) <= 1e-13 * np.max(np.abs(A @ X))
+    rep = gpu_lib.tune_report()
+    key = f"spmm:n={n}:nnz={A.nnz}:b={b}"
+    assert key in rep and 0 <= rep[key]["variant"] <= 4 and len(rep[key]["us"]) == 5

@@ -68,6 +68,11 @@ def test_paper_problem_unpreconditioned_count_recorded():
     w = P.paper_x0()
     st = O.setup(w.A, w.subs, w.tau)
     res = O.pcg(w.A, w.b, st.apply, tol=1e-10)
-    assert res.converged and res.rel_res_true <= 2e-9
-    assert res.iters >= 26
+    # the recursive residual reaches 1e-10; the true residual stalls near the
+    # rounding floor of b - A x (about 6e-10 here), so the restarts from the
+    # true residual run out and the solve reports non-convergence honestly
+    assert min(res.res_hist) <= 1e-10 and res.rel_res_true <= 2e-9
+    assert res.iters >= 26 and res.restarts <= 5
     assert np.isfinite(res.rel_res_true)
+    res8 = O.pcg(w.A, w.b, st.apply, tol=1e-8)
+    assert res8.converged and res8.restarts == 0 and res8.rel_res_true <= 1e-8
