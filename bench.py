@@ -279,11 +279,15 @@ def main():
         # and the learned start (network trained on other seeds of this family)
         step("f32", "subspace", net)
         torch.cuda.synchronize()
+        awg.kernel_times(reset=True)
+        awg.kernel_timing(True)
         t1 = time.perf_counter()
         for i in range(args.steps):
             info32, st32 = step("f32", "subspace", net)
         torch.cuda.synchronize()
         ms32 = (time.perf_counter() - t1) * 1e3 / args.steps
+        awg.kernel_timing(False)
+        kt32 = awg.kernel_times(reset=True)
         out["fast_form"] = {"local_prec": "f32", "geneo": "subspace", "eig_learned": st32["eig_learned"],
                             "network": wfile,
                             "eig_iters_max": max(st32["eig_iters"]),
@@ -291,7 +295,9 @@ def main():
                             "iters": info32["iters"],
                             "rel_res_true": info32["rel_res_true"], "n_minus": st32["n_minus"], "n0": st32["n0"],
                             "w_iters": st32["w_iters"], "speedup_vs_f64": round(ms / ms32, 3),
-                            "phases_ms": {k: round(v, 3) for k, v in st32["ms"].items()}}
+                            "phases_ms": {k: round(v, 3) for k, v in st32["ms"].items()},
+                            "kernels_ms_per_step": {k: round(v["ms"] / args.steps, 3) for k, v in
+                                                    sorted(kt32.items(), key=lambda kv: -kv[1]["ms"])[:12]}}
     out["roofline"] = roofline(kt, args.steps, out["config"]["workload"])
     out["autotune"] = {k: v["variant"] for k, v in awg.tune_report().items()}
     out["kernels_ms_per_step"] = {k: round(v["ms"] / args.steps, 3) for k, v in

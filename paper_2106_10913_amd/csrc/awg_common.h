@@ -120,8 +120,11 @@ struct MatDesc {         // one square or rectangular column-major block
 // C = alpha * op(A) op(B) + beta * C for every descriptor; lower != 0 skips
 // 64x64 output tiles lying strictly above the diagonal.
 // flops: algorithmic flop count of the whole batch (for the kernel timer only)
+// tag: name of the call site (kernel timer label suffix and autotuning key;
+// tagged products choose their tile size by measurement)
 void gemm_batched(const GemmDesc* d_desc, int batch, int max_m, int max_n, bool transA, bool transB,
-                  double alpha, double beta, bool lower, hipStream_t s, double flops = 0.0);
+                  double alpha, double beta, bool lower, hipStream_t s, double flops = 0.0,
+                  const char* tag = nullptr);
 // C = alpha A B + beta C with FP32 B (A rounded to FP32, FP32 MFMA and accumulation)
 void gemm_mix_batched(const GemmDescMix* d_desc, int batch, int max_m, int max_n, double alpha, double beta,
                       hipStream_t s, double flops);

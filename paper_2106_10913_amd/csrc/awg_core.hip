@@ -379,10 +379,10 @@ GemmDesc mk(const double* X, const double* M, int ldm, double* Y, int nout, int 
 
 // flops: algorithmic flops of the whole batched product (2 m n k summed)
 void bmm(const DBuf<GemmDesc>& d, int batch, int maxout, int maxk, bool transM, double alpha, double beta, int b,
-         hipStream_t s, double flops, double* gemv_part = nullptr) {
+         hipStream_t s, double flops, double* gemv_part = nullptr, const char* tag = nullptr) {
   if (batch == 0) return;
   if (b == 1) gemv_batched(d, batch, maxout, maxk, !transM, alpha, beta, s, 4.0 * flops, gemv_part);
-  else gemm_batched(d, batch, b, maxout, false, transM, alpha, beta, false, s, flops);
+  else gemm_batched(d, batch, b, maxout, false, transM, alpha, beta, false, s, flops, tag);
 }
 
 void gemm_upload(DBuf<GemmDesc>& d, const std::vector<GemmDesc>& h, hipStream_t s) { d.upload(h, s); }
@@ -463,11 +463,11 @@ void op_aminus(awg_ctx& c, MultiWS& w, const double* X, double* Yo, double beta)
     return;
   }
   l_gather(c.sumns, c.subidx, X, b, w.Xs, c.s);
-  bmm(w.dVt, c.N, w.maxk, w.maxns, false, 1.0, 0.0, b, c.s, w.flV);
+  bmm(w.dVt, c.N, w.maxk, w.maxns, false, 1.0, 0.0, b, c.s, w.flV, nullptr, "Vt");
   hipLaunchKernelGGL(k_scale_rows, dim3(cdiv(c.LV.cols * b, 256)), dim3(256), 0, c.s, w.Tk.p, c.lamV.p,
                      (long)c.LV.cols, b);
   AWG_LAUNCH_CHECK();
-  bmm(w.dV, c.N, w.maxns, w.maxk, true, 1.0, 0.0, b, c.s, w.flV);
+  bmm(w.dV, c.N, w.maxns, w.maxk, true, 1.0, 0.0, b, c.s, w.flV, nullptr, "V");
   l_scatter(c.n, c.sumns, c.invptr, c.invsub, c.invloc, c.subptr, w.Os, b, Yo, 1.0, beta, c.s);
 }
 
@@ -480,12 +480,12 @@ void op_aplus(awg_ctx& c, MultiWS& w, const double* X, double* Yo) {
 // G0 = R0 X  (R0^T = [R^1T Y^1 | ... | R^NT Y^N])
 void op_r0(awg_ctx& c, MultiWS& w, const double* X) {
   l_gather(c.sumns, c.subidx, X, w.b, w.Xs, c.s);
-  bmm(w.dYt, c.N, w.maxm, w.maxns, false, 1.0, 0.0, w.b, c.s, w.flY);
+  bmm(w.dYt, c.N, w.maxm, w.maxns, false, 1.0, 0.0, w.b, c.s, w.flY, nullptr, "Yt");
 }
 
 // Yo = beta Yo + alpha R0^T G1
 void op_r0t(awg_ctx& c, MultiWS& w, double* Yo, double beta, double alpha = 1.0) {
-  bmm(w.dY, c.N, w.maxns, w.maxm, true, 1.0, 0.0, w.b, c.s, w.flY);
+  bmm(w.dY, c.N, w.maxns, w.maxm, true, 1.0, 0.0, w.b, c.s, w.flY, nullptr, "Y");
   l_scatter(c.n, c.sumns, c.invptr, c.invsub, c.invloc, c.subptr, w.Os, w.b, Yo, alpha, beta, c.s);
 }
 
@@ -500,7 +500,7 @@ void op_hnn(awg_ctx& c, MultiWS& w, const double* X, double* Yo, bool f32) {
   } else if (f32) {
     gemm_mix_batched(w.dP32, c.N, w.b, w.maxns, 1.0, 0.0, c.s, w.flP);
   } else {
-    bmm(w.dP, c.N, w.maxns, w.maxns, false, 1.0, 0.0, w.b, c.s, w.flP);
+    bmm(w.dP, c.N, w.maxns, w.maxns, false, 1.0, 0.0, w.b, c.s, w.flP, nullptr, "P");
   }
   l_scatter(c.n, c.sumns, c.invptr, c.invsub, c.invloc, c.subptr, w.Os, w.b, Yo, 1.0, 0.0, c.s);
 }
@@ -522,14 +522,14 @@ void op_h2(awg_ctx& c, MultiWS& w, bool f32) {
     return;
   }
   op_r0(c, w, w.R);                                                      // G0 = R0 r
-  bmm(w.dE0a, 1, c.n0, c.n0, false, 1.0, 0.0, b, c.s, w.flE0);           // G1 = u0
+  bmm(w.dE0a, 1, c.n0, c.n0, false, 1.0, 0.0, b, c.s, w.flE0, nullptr, "E0");           // G1 = u0
   op_r0t(c, w, w.T1, 0.0);                                               // T1 = R0^T u0
   op_aplus(c, w, w.T1, w.T2);                                            // T2 = A_+ R0^T u0
   l_colaxpby(c.n, b, w.R, nullptr, w.T2, nullptr, 1.0, -1.0, c.s);       // T2 = r - T2
   op_hnn(c, w, w.T2, w.Z, f32);                                          // Z = y
   op_aplus(c, w, w.Z, w.T1);                                             // T1 = A_+ y
   op_r0(c, w, w.T1);                                                     // G0 = R0 A_+ y
-  bmm(w.dE0b, 1, c.n0, c.n0, false, 1.0, 0.0, b, c.s, w.flE0);           // G2 = v
+  bmm(w.dE0b, 1, c.n0, c.n0, false, 1.0, 0.0, b, c.s, w.flE0, nullptr, "E0");           // G2 = v
   l_colaxpby(c.n0, b, w.G2, nullptr, w.G1, nullptr, -1.0, 1.0, c.s);     // G1 = u0 - v
   op_r0t(c, w, w.Z, 1.0);                                                // Z += R0^T (u0 - v)
 }
@@ -539,9 +539,9 @@ void op_h(awg_ctx& c, MultiWS& w, bool f32) {
   op_h2(c, w, f32);
   if (c.nminus == 0) return;
   const int b = w.b;
-  bmm(w.dWt, 1, c.nminus, c.n, true, 1.0, 0.0, b, c.s, w.flW, w.gvpart.p);  // H0 = W^T r
-  bmm(w.dEW, 1, c.nminus, c.nminus, false, 1.0, 0.0, b, c.s, w.flEW);    // H1 = E_W^{-1} H0
-  bmm(w.dW, 1, c.n, c.nminus, false, 1.0, 1.0, b, c.s, w.flW);           // Z += W H1
+  bmm(w.dWt, 1, c.nminus, c.n, true, 1.0, 0.0, b, c.s, w.flW, w.gvpart.p, "Wt");  // H0 = W^T r
+  bmm(w.dEW, 1, c.nminus, c.nminus, false, 1.0, 0.0, b, c.s, w.flEW, nullptr, "EW");    // H1 = E_W^{-1} H0
+  bmm(w.dW, 1, c.n, c.nminus, false, 1.0, 1.0, b, c.s, w.flW, nullptr, "W");           // Z += W H1
 }
 
 void sync(awg_ctx& c) { AWG_HIP(hipStreamSynchronize(c.s)); }
@@ -1158,10 +1158,13 @@ int spd_inverse(awg_ctx& c, double* M, int n, DBuf<double>& Minv, const char* wh
   return nd;
 }
 
-// number of columns per pass: at most cap, balanced over the passes
+// number of columns per pass: at most cap (even), balanced over the passes and
+// rounded up to even (16-byte rows for the vectorised gather / scatter); the
+// columns past the total are kept at zero
 int balanced_chunk(int total, int cap) {
   const int passes = (total + cap - 1) / cap;
-  return (total + passes - 1) / passes;
+  const int b = (total + passes - 1) / passes;
+  return std::min(cap, b + (b & 1));
 }
 
 // E0 = R0 A_+ R0^T and its inverse (Theorem on H^NN_hyb, Section 3.4)

@@ -10,6 +10,7 @@
 #include <algorithm>
 
 #include "awg_common.h"
+#include "awg_tune.h"
 
 namespace awg {
 
@@ -359,7 +360,7 @@ __global__ __launch_bounds__(256) void k_gemm128_mix(const GemmDescMix* descs, d
 void gemm_mix_batched(const GemmDescMix* d_desc, int batch, int max_m, int max_n, double alpha, double beta,
                       hipStream_t s, double flops) {
   if (batch <= 0 || max_m <= 0 || max_n <= 0) return;
-  KScope kt("k_gemm128_mix", s, 0.0, flops);
+  KScope kt("k_gemm128_mix:P", s, 0.0, flops);
   hipLaunchKernelGGL(k_gemm128_mix, dim3(cdiv(max_m, 128), cdiv(max_n, 128), batch), dim3(256), 0, s, d_desc, alpha,
                      beta);
   AWG_LAUNCH_CHECK();
@@ -386,12 +387,8 @@ template <>
 bool use_big_tiles<DescArray>() { return true; }
 
 template <class DF>
-static void launch_gemm(DF df, int batch, int max_m, int max_n, bool tA, bool tB, double alpha, double beta,
-                        bool lower, hipStream_t s, double flops = 0.0) {
-  if (batch <= 0 || max_m <= 0 || max_n <= 0) return;
-  const bool big = use_big_tiles<DF>() && max_m >= 128;
-  const std::string nm = std::string(big ? "k_gemm128" : "k_gemm") + (gemm_name<DF>(tA, tB) + 6);
-  KScope kt(nm.c_str(), s, 0.0, flops);
+static void launch_tiles(DF df, int batch, int max_m, int max_n, bool tA, bool tB, double alpha, double beta,
+                         bool lower, hipStream_t s, bool big) {
   if (big) {
     dim3 grid(cdiv(max_m, 128), cdiv(max_n, 128), batch);
     if (!tA && !tB) hipLaunchKernelGGL((k_gemm128<DF, false, false>), grid, dim3(256), 0, s, df, alpha, beta, (int)lower);
@@ -409,6 +406,31 @@ static void launch_gemm(DF df, int batch, int max_m, int max_n, bool tA, bool tB
   AWG_LAUNCH_CHECK();
 }
 
+// 64x64 or 128x128 output tiles.  Both kernels take the k loop in the same
+// order with the same MFMA, so they give bit-identical results; for the
+// explicit-descriptor products the faster one is measured per shape (tag =
+// the call site) on the first call with beta = 0, otherwise 128x128 tiles
+// when max_m >= 128.
+template <class DF>
+static void launch_gemm(DF df, int batch, int max_m, int max_n, bool tA, bool tB, double alpha, double beta,
+                        bool lower, hipStream_t s, double flops = 0.0, const char* tag = nullptr) {
+  if (batch <= 0 || max_m <= 0 || max_n <= 0) return;
+  bool big = use_big_tiles<DF>() && max_m >= 128;
+  if (use_big_tiles<DF>() && tag) {
+    const std::string key = std::string("gemm:") + tag + (tA ? ":T" : ":N") + (tB ? "T" : "N") + ":m=" +
+                            std::to_string(max_m) + ":n=" + std::to_string(max_n) + ":batch=" + std::to_string(batch);
+    int v = tune_lookup(key);
+    if (v < 0 && beta == 0.0 && !lower)
+      v = tune_pick(key, 2, [&](int w) { launch_tiles(df, batch, max_m, max_n, tA, tB, alpha, beta, lower, s, w == 1); },
+                    s);
+    if (v >= 0) big = v == 1;
+  }
+  std::string nm = std::string(big ? "k_gemm128" : "k_gemm") + (gemm_name<DF>(tA, tB) + 6);
+  if (tag) nm += std::string(":") + tag;
+  KScope kt(nm.c_str(), s, 0.0, flops);
+  launch_tiles(df, batch, max_m, max_n, tA, tB, alpha, beta, lower, s, big);
+}
+
 void syr2k_panel_update(const MatDesc* d_mats, const double* V, const double* W, const long* d_off, int p0, int nbw,
                         int max_rem, int batch, hipStream_t s, double flops) {
   launch_gemm(Syr2kUpdate{d_mats, V, W, d_off, p0, nbw}, batch, max_rem, max_rem, false, true, -1.0, 1.0, false, s,
@@ -418,8 +440,8 @@ void syr2k_panel_update(const MatDesc* d_mats, const double* V, const double* W,
 }
 
 void gemm_batched(const GemmDesc* d_desc, int batch, int max_m, int max_n, bool transA, bool transB,
-                  double alpha, double beta, bool lower, hipStream_t s, double flops) {
-  launch_gemm(DescArray{d_desc}, batch, max_m, max_n, transA, transB, alpha, beta, lower, s, flops);
+                  double alpha, double beta, bool lower, hipStream_t s, double flops, const char* tag) {
+  launch_gemm(DescArray{d_desc}, batch, max_m, max_n, transA, transB, alpha, beta, lower, s, flops, tag);
 }
 
 // ---------------------------------------------------------------------------

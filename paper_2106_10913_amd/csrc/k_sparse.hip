@@ -246,6 +246,47 @@ __global__ void k_gather(long tot, const int* sub_idx, const double* X, int b, d
   Xs[e] = X[(long)sub_idx[p] * b + c];
 }
 
+// Vectorised forms for an even column count b (16-byte aligned rows): one
+// wavefront per (row, 128 columns), each lane moving a double2; the row's
+// index data are loaded once per wavefront.
+__global__ __launch_bounds__(256) void k_gather2(long tot, const int* __restrict__ sub_idx,
+                                                 const double2* __restrict__ X, int b2, double2* Xs, int nchunk) {
+  const long w = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const long p = w / nchunk;
+  if (p >= tot) return;
+  const int c = (int)(w - p * nchunk) * 64 + (threadIdx.x & 63);
+  if (c >= b2) return;
+  Xs[p * b2 + c] = X[(long)sub_idx[p] * b2 + c];
+}
+
+__global__ __launch_bounds__(256) void k_scatter2(int n, const int* __restrict__ inv_ptr, const int* __restrict__ inv_sub,
+                                                  const int* __restrict__ inv_loc, const long* __restrict__ sub_ptr,
+                                                  const double2* __restrict__ Zs, int b2, double2* Y, double alpha,
+                                                  double beta, int nchunk) {
+  const long w = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const long i = w / nchunk;
+  if (i >= n) return;
+  const int c = (int)(w - i * nchunk) * 64 + (threadIdx.x & 63);
+  if (c >= b2) return;
+  double ax = 0.0, ay = 0.0;
+  for (int q = inv_ptr[i]; q < inv_ptr[i + 1]; ++q) {
+    const double2 z = Zs[(sub_ptr[inv_sub[q]] + inv_loc[q]) * b2 + c];
+    ax += z.x;
+    ay += z.y;
+  }
+  double2* y = Y + i * b2 + c;
+  double2 o;
+  if (beta == 0.0) {
+    o.x = alpha * ax;
+    o.y = alpha * ay;
+  } else {
+    const double2 v = *y;
+    o.x = alpha * ax + beta * v.x;
+    o.y = alpha * ay + beta * v.y;
+  }
+  *y = o;
+}
+
 // Y[i, :] = beta Y[i, :] + alpha sum over (s, l) holding i of Zs[sub_off[s] + l, :]
 __global__ void k_scatter(int n, const int* inv_ptr, const int* inv_sub, const int* inv_loc, const long* sub_ptr,
                           const double* Zs, int b, double* Y, double alpha, double beta) {
@@ -527,6 +568,13 @@ void l_spmm(int n, long nnz, const int* rowptr, const int* col, const double* va
 void l_gather(long tot, const int* sub_idx, const double* X, int b, double* Xs, hipStream_t s) {
   if (tot == 0 || b == 0) return;
   KScope kt("k_gather", s, 16.0 * tot * (double)b + 4.0 * tot, 0.0);
+  if ((b & 1) == 0 && ((uintptr_t)X & 15) == 0 && ((uintptr_t)Xs & 15) == 0) {
+    const int b2 = b / 2, nchunk = (int)cdiv(b2, 64);
+    hipLaunchKernelGGL(k_gather2, dim3(cdiv(tot * nchunk, 4)), dim3(256), 0, s, tot, sub_idx, (const double2*)X, b2,
+                       (double2*)Xs, nchunk);
+    AWG_LAUNCH_CHECK();
+    return;
+  }
   hipLaunchKernelGGL(k_gather, dim3(grid1(tot * b)), dim3(256), 0, s, tot, sub_idx, X, b, Xs);
   AWG_LAUNCH_CHECK();
 }
@@ -536,6 +584,13 @@ void l_scatter(int n, long tot, const int* inv_ptr, const int* inv_sub, const in
   KScope kt("k_scatter", s,
             8.0 * (double)tot * b + 8.0 * tot + 4.0 * n + 8.0 * n * (double)b * (beta != 0.0 ? 2.0 : 1.0),
             (double)tot * b);
+  if ((b & 1) == 0 && ((uintptr_t)Zs & 15) == 0 && ((uintptr_t)Y & 15) == 0) {
+    const int b2 = b / 2, nchunk = (int)cdiv(b2, 64);
+    hipLaunchKernelGGL(k_scatter2, dim3(cdiv((long)n * nchunk, 4)), dim3(256), 0, s, n, inv_ptr, inv_sub, inv_loc,
+                       sub_ptr, (const double2*)Zs, b2, (double2*)Y, alpha, beta, nchunk);
+    AWG_LAUNCH_CHECK();
+    return;
+  }
   hipLaunchKernelGGL(k_scatter, dim3(grid1((long)n * b)), dim3(256), 0, s, n, inv_ptr, inv_sub, inv_loc, sub_ptr, Zs,
                      b, Y, alpha, beta);
   AWG_LAUNCH_CHECK();
