@@ -55,7 +55,7 @@ int awg_dense_gemm(int32_t batch, int32_t m, int32_t n, int32_t k, int32_t trans
       h[b] = GemmDesc{A + b * strideA, B + b * strideB, C + b * strideC, m, n, k, lda, ldb, ldc};
     DBuf<GemmDesc> d;
     d.upload(h, s);
-    gemm_batched(d, batch, m, n, transA != 0, transB != 0, alpha, beta, false, s);
+    gemm_batched(d, batch, m, n, transA != 0, transB != 0, alpha, beta, false, s, 0.0, "dense");
     AWG_HIP(hipStreamSynchronize(s));
   });
 }

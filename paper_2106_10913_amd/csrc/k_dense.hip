@@ -273,6 +273,93 @@ __global__ __launch_bounds__(256) void k_gemm128(DF df, double alpha, double bet
       }
 }
 
+// 128x128 tiles with eight wavefronts (2 x 4, each 64 x 32): half the
+// accumulators per lane of k_gemm128, so more wavefronts fit per SIMD to hide
+// the global-load latency.  Same k order and MFMA as the other tile shapes
+// (bit-identical results).
+template <class DF, bool TA, bool TB>
+__global__ __launch_bounds__(512, 4) void k_gemm128w8(DF df, double alpha, double beta, int lower) {
+  const GemmDesc d = df(blockIdx.z);
+  const int m0 = blockIdx.x * 128, n0 = blockIdx.y * 128;
+  if (m0 >= d.m || n0 >= d.n) return;
+  if (lower && m0 + 128 <= n0) return;
+  __shared__ double As[2][16][132];
+  __shared__ double Bs[2][16][132];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wm = (wave & 1) * 64, wn = (wave >> 1) * 32;
+  v4d acc[4][2];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = (v4d){0.0, 0.0, 0.0, 0.0};
+  double ra[4], rb[4];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int e = tid + r * 512;
+      int i, kk;
+      if (!TA) { i = e & 127; kk = e >> 7; } else { kk = e & 15; i = e >> 4; }
+      const int gi = m0 + i, gk = k0 + kk;
+      ra[r] = (gi < d.m && gk < d.k) ? (TA ? d.A[gk + (long)gi * d.lda] : d.A[gi + (long)gk * d.lda]) : 0.0;
+      int j, kb;
+      if (!TB) { kb = e & 15; j = e >> 4; } else { j = e & 127; kb = e >> 7; }
+      const int gj = n0 + j, gkb = k0 + kb;
+      rb[r] = (gj < d.n && gkb < d.k) ? (TB ? d.B[gj + (long)gkb * d.ldb] : d.B[gkb + (long)gj * d.ldb]) : 0.0;
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int e = tid + r * 512;
+      int i, kk;
+      if (!TA) { i = e & 127; kk = e >> 7; } else { kk = e & 15; i = e >> 4; }
+      As[buf][kk][i] = ra[r];
+      int j, kb;
+      if (!TB) { kb = e & 15; j = e >> 4; } else { j = e & 127; kb = e >> 7; }
+      Bs[buf][kb][j] = rb[r];
+    }
+  };
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  int buf = 0;
+  for (int k0 = 0; k0 < d.k; k0 += 16) {
+    const bool more = k0 + 16 < d.k;
+    if (more) gload(k0 + 16);
+#pragma unroll
+    for (int kk = 0; kk < 16; kk += 4) {
+      const int kr = kk + (lane >> 4), c = lane & 15;
+      double a[4], b[2];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) a[q] = As[buf][kr][wm + q * 16 + c];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) b[q] = Bs[buf][kr][wn + q * 16 + c];
+#pragma unroll
+      for (int qa = 0; qa < 4; ++qa)
+#pragma unroll
+        for (int qb = 0; qb < 2; ++qb)
+          acc[qa][qb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[qa], b[qb], acc[qa][qb], 0, 0, 0);
+    }
+    if (more) sstore(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+#pragma unroll
+  for (int qa = 0; qa < 4; ++qa)
+#pragma unroll
+    for (int qb = 0; qb < 2; ++qb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = m0 + wm + qa * 16 + (lane >> 4) + 4 * r;
+        const int j = n0 + wn + qb * 16 + (lane & 15);
+        if (i < d.m && j < d.n) {
+          double* cp = d.C + i + (long)j * d.ldc;
+          const double v = alpha * acc[qa][qb][r];
+          *cp = (beta == 0.0) ? v : v + beta * *cp;
+        }
+      }
+}
+
 // ---------------------------------------------------------------------------
 // mixed-precision GEMM for FP32 local operators: C (FP64) = alpha A B + beta C
 // with A FP64 (rounded to FP32 when staged in LDS), B FP32, FP32 MFMA
@@ -357,13 +444,99 @@ __global__ __launch_bounds__(256) void k_gemm128_mix(const GemmDescMix* descs, d
       }
 }
 
+// eight-wavefront form of k_gemm128_mix (2 x 4 wavefronts of 64 x 32), same
+// k order (bit-identical results)
+__global__ __launch_bounds__(512, 4) void k_gemm128_mix_w8(const GemmDescMix* descs, double alpha, double beta) {
+  const GemmDescMix d = descs[blockIdx.z];
+  const int m0 = blockIdx.x * 128, n0 = blockIdx.y * 128;
+  if (m0 >= d.m || n0 >= d.n) return;
+  __shared__ float As[2][16][132];
+  __shared__ float Bs[2][16][132];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wm = (wave & 1) * 64, wn = (wave >> 1) * 32;
+  v4f acc[4][2];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = (v4f){0.f, 0.f, 0.f, 0.f};
+  float ra[4], rb[4];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int e = tid + r * 512;
+      const int i = e & 127, kk = e >> 7;
+      const int gi = m0 + i, gk = k0 + kk;
+      ra[r] = (gi < d.m && gk < d.k) ? (float)d.A[gi + (long)gk * d.lda] : 0.f;
+      const int kb = e & 15, j = e >> 4;
+      const int gj = n0 + j, gkb = k0 + kb;
+      rb[r] = (gj < d.n && gkb < d.k) ? d.B[gkb + (long)gj * d.ldb] : 0.f;
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int e = tid + r * 512;
+      As[buf][e >> 7][e & 127] = ra[r];
+      Bs[buf][e & 15][e >> 4] = rb[r];
+    }
+  };
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  int buf = 0;
+  for (int k0 = 0; k0 < d.k; k0 += 16) {
+    const bool more = k0 + 16 < d.k;
+    if (more) gload(k0 + 16);
+#pragma unroll
+    for (int kk = 0; kk < 16; kk += 4) {
+      const int kr = kk + (lane >> 4), c = lane & 15;
+      float a[4], b[2];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) a[q] = As[buf][kr][wm + q * 16 + c];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) b[q] = Bs[buf][kr][wn + q * 16 + c];
+#pragma unroll
+      for (int qa = 0; qa < 4; ++qa)
+#pragma unroll
+        for (int qb = 0; qb < 2; ++qb)
+          acc[qa][qb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[qa], b[qb], acc[qa][qb], 0, 0, 0);
+    }
+    if (more) sstore(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+#pragma unroll
+  for (int qa = 0; qa < 4; ++qa)
+#pragma unroll
+    for (int qb = 0; qb < 2; ++qb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = m0 + wm + qa * 16 + 4 * (lane >> 4) + r;
+        const int j = n0 + wn + qb * 16 + (lane & 15);
+        if (i < d.m && j < d.n) {
+          double* cp = d.C + i + (long)j * d.ldc;
+          const double v = alpha * (double)acc[qa][qb][r];
+          *cp = (beta == 0.0) ? v : v + beta * *cp;
+        }
+      }
+}
+
 void gemm_mix_batched(const GemmDescMix* d_desc, int batch, int max_m, int max_n, double alpha, double beta,
                       hipStream_t s, double flops) {
   if (batch <= 0 || max_m <= 0 || max_n <= 0) return;
-  KScope kt("k_gemm128_mix:P", s, 0.0, flops);
-  hipLaunchKernelGGL(k_gemm128_mix, dim3(cdiv(max_m, 128), cdiv(max_n, 128), batch), dim3(256), 0, s, d_desc, alpha,
-                     beta);
-  AWG_LAUNCH_CHECK();
+  const dim3 grid(cdiv(max_m, 128), cdiv(max_n, 128), batch);
+  auto run = [&](int v) {
+    if (v == 1) hipLaunchKernelGGL(k_gemm128_mix_w8, grid, dim3(512), 0, s, d_desc, alpha, beta);
+    else hipLaunchKernelGGL(k_gemm128_mix, grid, dim3(256), 0, s, d_desc, alpha, beta);
+    AWG_LAUNCH_CHECK();
+  };
+  const std::string key = "gemm_mix:P:m=" + std::to_string(max_m) + ":n=" + std::to_string(max_n) + ":batch=" +
+                          std::to_string(batch);
+  int v = tune_lookup(key);
+  if (v < 0 && beta == 0.0) v = tune_pick(key, 2, run, s);
+  if (v < 0) v = 1;
+  KScope kt(v == 1 ? "k_gemm128_mix_w8:P" : "k_gemm128_mix:P", s, 0.0, flops);
+  run(v);
 }
 
 template <class DF>
@@ -388,7 +561,17 @@ bool use_big_tiles<DescArray>() { return true; }
 
 template <class DF>
 static void launch_tiles(DF df, int batch, int max_m, int max_n, bool tA, bool tB, double alpha, double beta,
-                         bool lower, hipStream_t s, bool big) {
+                         bool lower, hipStream_t s, int variant) {
+  if (variant == 2) {
+    dim3 grid(cdiv(max_m, 128), cdiv(max_n, 128), batch);
+    if (!tA && !tB) hipLaunchKernelGGL((k_gemm128w8<DF, false, false>), grid, dim3(512), 0, s, df, alpha, beta, (int)lower);
+    else if (tA && !tB) hipLaunchKernelGGL((k_gemm128w8<DF, true, false>), grid, dim3(512), 0, s, df, alpha, beta, (int)lower);
+    else if (!tA && tB) hipLaunchKernelGGL((k_gemm128w8<DF, false, true>), grid, dim3(512), 0, s, df, alpha, beta, (int)lower);
+    else hipLaunchKernelGGL((k_gemm128w8<DF, true, true>), grid, dim3(512), 0, s, df, alpha, beta, (int)lower);
+    AWG_LAUNCH_CHECK();
+    return;
+  }
+  const bool big = variant == 1;
   if (big) {
     dim3 grid(cdiv(max_m, 128), cdiv(max_n, 128), batch);
     if (!tA && !tB) hipLaunchKernelGGL((k_gemm128<DF, false, false>), grid, dim3(256), 0, s, df, alpha, beta, (int)lower);
@@ -415,20 +598,20 @@ template <class DF>
 static void launch_gemm(DF df, int batch, int max_m, int max_n, bool tA, bool tB, double alpha, double beta,
                         bool lower, hipStream_t s, double flops = 0.0, const char* tag = nullptr) {
   if (batch <= 0 || max_m <= 0 || max_n <= 0) return;
-  bool big = use_big_tiles<DF>() && max_m >= 128;
+  int variant = (use_big_tiles<DF>() && max_m >= 128) ? 1 : 0;
   if (use_big_tiles<DF>() && tag) {
     const std::string key = std::string("gemm:") + tag + (tA ? ":T" : ":N") + (tB ? "T" : "N") + ":m=" +
                             std::to_string(max_m) + ":n=" + std::to_string(max_n) + ":batch=" + std::to_string(batch);
     int v = tune_lookup(key);
     if (v < 0 && beta == 0.0 && !lower)
-      v = tune_pick(key, 2, [&](int w) { launch_tiles(df, batch, max_m, max_n, tA, tB, alpha, beta, lower, s, w == 1); },
-                    s);
-    if (v >= 0) big = v == 1;
+      v = tune_pick(key, 3, [&](int w) { launch_tiles(df, batch, max_m, max_n, tA, tB, alpha, beta, lower, s, w); }, s);
+    if (v >= 0) variant = v;
   }
-  std::string nm = std::string(big ? "k_gemm128" : "k_gemm") + (gemm_name<DF>(tA, tB) + 6);
+  static const char* const prefix[3] = {"k_gemm", "k_gemm128", "k_gemm128w8"};
+  std::string nm = std::string(prefix[variant]) + (gemm_name<DF>(tA, tB) + 6);
   if (tag) nm += std::string(":") + tag;
   KScope kt(nm.c_str(), s, 0.0, flops);
-  launch_tiles(df, batch, max_m, max_n, tA, tB, alpha, beta, lower, s, big);
+  launch_tiles(df, batch, max_m, max_n, tA, tB, alpha, beta, lower, s, variant);
 }
 
 void syr2k_panel_update(const MatDesc* d_mats, const double* V, const double* W, const long* d_off, int p0, int nbw,
