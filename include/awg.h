@@ -172,6 +172,10 @@ const char* awg_last_error(const awg_ctx* ctx);
  * context, and per-kernel launch counts, elapsed milliseconds and the
  * algorithmic bytes / flops of each launch are accumulated.  Off by default
  * (it adds one event pair per launch). */
+/* Restrict the timing to kernels whose label starts with prefix (NULL or ""
+ * = every instrumented kernel); per-launch events cost a few microseconds, so
+ * a benchmark times only the kernel it reports. */
+int awg_kernel_timing_filter(const char* prefix);
 int awg_kernel_timing(int32_t enable);
 
 /* JSON {"kernel": {"calls", "ms", "bytes", "flops"}, ...} of the accumulated

@@ -28,7 +28,7 @@ EXPORTED = ["awg_default_options", "awg_setup", "awg_apply", "awg_pcg", "awg_sta
             "awg_dense_gemm", "awg_dense_potrf", "awg_dense_trsm", "awg_dense_low_eigs",
             "awg_mlp_create", "awg_mlp_num_params", "awg_mlp_get_params", "awg_mlp_set_params", "awg_mlp_forward",
             "awg_mlp_loss_grad", "awg_mlp_get_grads", "awg_mlp_adam_step", "awg_mlp_last_error", "awg_mlp_destroy",
-            "awg_csr_spmm", "awg_autotune", "awg_tune_report"]
+            "awg_csr_spmm", "awg_autotune", "awg_tune_report", "awg_kernel_timing_filter"]
 MLP_FEATURES = 12
 
 
@@ -83,6 +83,8 @@ def lib():
     L.awg_destroy.restype = None
     L.awg_pcg_graph.argtypes = [vp, i32]
     L.awg_pcg_graph.restype = ctypes.c_int
+    L.awg_kernel_timing_filter.argtypes = [ctypes.c_char_p]
+    L.awg_kernel_timing_filter.restype = ctypes.c_int
     L.awg_kernel_timing.argtypes = [i32]
     L.awg_kernel_timing.restype = ctypes.c_int
     L.awg_kernel_times.argtypes = [ctypes.c_char_p, ctypes.c_size_t, i32]
@@ -127,6 +129,10 @@ def kernel_timing(enable: bool) -> None:
     rc = lib().awg_kernel_timing(int(enable))
     if rc:
         raise AWGError(rc, "awg_kernel_timing")
+
+
+def kernel_timing_filter(prefix: str = "") -> None:
+    lib().awg_kernel_timing_filter(prefix.encode() if prefix else None)
 
 
 def kernel_times(reset: bool = False) -> dict:

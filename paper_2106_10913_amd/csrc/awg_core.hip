@@ -37,6 +37,7 @@ struct KAcc {
 };
 bool g_kt_on = false;
 bool g_kt_capturing = false;   // no event records while a graph is being captured
+std::string g_kt_filter;       // when not empty: time only kernels whose label starts with it
 std::vector<KRec> g_kt_pending;
 std::vector<hipEvent_t> g_kt_pool;
 std::map<std::string, KAcc> g_kt_acc;
@@ -71,6 +72,7 @@ void kt_flush() {
 
 KScope::KScope(const char* name, hipStream_t s, double bytes, double flops) : s_(s) {
   if (!g_kt_on || g_kt_capturing) return;
+  if (!g_kt_filter.empty() && std::strncmp(name, g_kt_filter.c_str(), g_kt_filter.size()) != 0) return;
   if (g_kt_pending.size() >= 8192) kt_flush();
   KRec r{name, kt_event(), kt_event(), bytes, flops};
   AWG_HIP(hipEventRecord(r.a, s));
@@ -1717,6 +1719,11 @@ const char* awg_last_error(const awg_ctx* c) { return c ? c->err.c_str() : g_set
 int awg_pcg_graph(awg_ctx* c, int32_t enable) {
   if (!c) return AWG_ERR_ARG;
   c->use_graph = enable ? 1 : 0;
+  return AWG_OK;
+}
+
+int awg_kernel_timing_filter(const char* prefix) {
+  awg::g_kt_filter = prefix ? prefix : "";
   return AWG_OK;
 }
 

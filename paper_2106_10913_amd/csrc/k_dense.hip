@@ -616,10 +616,11 @@ static void launch_gemm(DF df, int batch, int max_m, int max_n, bool tA, bool tB
 
 void syr2k_panel_update(const MatDesc* d_mats, const double* V, const double* W, const long* d_off, int p0, int nbw,
                         int max_rem, int batch, hipStream_t s, double flops) {
-  launch_gemm(Syr2kUpdate{d_mats, V, W, d_off, p0, nbw}, batch, max_rem, max_rem, false, true, -1.0, 1.0, false, s,
-              0.5 * flops);
-  launch_gemm(Syr2kUpdate{d_mats, W, V, d_off, p0, nbw}, batch, max_rem, max_rem, false, true, -1.0, 1.0, false, s,
-              0.5 * flops);
+  // only the lower triangle of the trailing matrix is read afterwards
+  launch_gemm(Syr2kUpdate{d_mats, V, W, d_off, p0, nbw}, batch, max_rem, max_rem, false, true, -1.0, 1.0, true, s,
+              0.25 * flops);
+  launch_gemm(Syr2kUpdate{d_mats, W, V, d_off, p0, nbw}, batch, max_rem, max_rem, false, true, -1.0, 1.0, true, s,
+              0.25 * flops);
 }
 
 void gemm_batched(const GemmDesc* d_desc, int batch, int max_m, int max_n, bool transA, bool transB,

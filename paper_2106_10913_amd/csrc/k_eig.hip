@@ -103,40 +103,77 @@ __global__ __launch_bounds__(256) void k_trd_col(const MatDesc* mats, int p0, in
   for (int i = threadIdx.x; i <= j; i += 256) T.V[i + (long)jj * n] = 0.0;
 }
 
-// p = A[j+1:, j+1:] v (read only): 64 rows per workgroup, 4 column groups
-__global__ __launch_bounds__(256) void k_trd_symv(const MatDesc* mats, int p0, int jj, const long* off, double* work,
-                                                  long sumns) {
+// p = A22 v reading only the lower triangle of A22 = A[j+1:, j+1:] (the
+// trailing matrix is kept up to date in its lower triangle only).  A22 is cut
+// into 64 x 64 tiles (I, C), I >= C, one workgroup each; an off-diagonal tile
+// gives the row part A_IC v_C and, by symmetry, the column part A_IC^T v_I;
+// a diagonal tile is mirrored in LDS.  Partial vectors go to
+// part[(I * ntmax + C) * 64 + r] and are summed over C in a fixed order by
+// k_trd_w (deterministic).
+constexpr int SYMV_T = 64;
+
+__global__ __launch_bounds__(256) void k_trd_symv_lo(const MatDesc* mats, int p0, int jj, const long* off,
+                                                     double* work, long sumns, double* part, int ntmax) {
   const MatDesc M = mats[blockIdx.y];
   const int n = M.n;
   const int j = p0 + jj;
   if (j > n - 3) return;
-  const int i0 = j + 1 + blockIdx.x * TRD_ROWS;
-  if (i0 >= n) return;
+  const int base = j + 1, m = n - base;
+  const int nt = (m + SYMV_T - 1) / SYMV_T;
+  const int t = blockIdx.x;
+  if (t >= nt * (nt + 1) / 2) return;
+  int I = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+  while ((I + 1) * (I + 2) / 2 <= t) ++I;
+  while (I * (I + 1) / 2 > t) --I;
+  const int C = t - I * (I + 1) / 2;
   TrdWork T(work, sumns, off[blockIdx.y]);
   const double* v = T.V + (long)jj * n;
-  const int r = threadIdx.x & 63, g = threadIdx.x >> 6;
-  const int i = i0 + r;
-  __shared__ double part[4][TRD_ROWS];
-  double a0 = 0.0, a1 = 0.0;
-  if (i < n) {
-    const double* a = M.A + i;
-    int c = j + 1 + g;
-    for (; c + 4 < n; c += 8) {
-      a0 += a[(long)c * M.ld] * v[c];
-      a1 += a[(long)(c + 4) * M.ld] * v[c + 4];
-    }
-    for (; c < n; c += 4) a0 += a[(long)c * M.ld] * v[c];
+  __shared__ double L[SYMV_T][SYMV_T + 1];
+  __shared__ double vr[SYMV_T], vc[SYMV_T];
+  __shared__ double red[4][SYMV_T];
+  const int tid = threadIdx.x;
+  const int r0 = base + I * SYMV_T, c0 = base + C * SYMV_T;
+  for (int e = tid; e < SYMV_T * SYMV_T; e += 256) {
+    const int r = e % SYMV_T, c = e / SYMV_T;
+    const int gr = r0 + r, gc = c0 + c;
+    double a = 0.0;
+    if (gr < n && gc < n && (I != C || r >= c)) a = M.A[gr + (long)gc * M.ld];
+    L[r][c] = a;
   }
-  part[g][r] = a0 + a1;
+  if (tid < SYMV_T) {
+    vr[tid] = (r0 + tid < n) ? v[r0 + tid] : 0.0;
+    vc[tid] = (c0 + tid < n) ? v[c0 + tid] : 0.0;
+  }
   __syncthreads();
-  if (g == 0 && i < n) T.p[i] = (part[0][r] + part[1][r]) + (part[2][r] + part[3][r]);
+  if (I == C) {
+    for (int e = tid; e < SYMV_T * SYMV_T; e += 256) {
+      const int r = e % SYMV_T, c = e / SYMV_T;
+      if (r < c) L[r][c] = L[c][r];
+    }
+    __syncthreads();
+  }
+  const int lane = tid & 63, g = tid >> 6;
+  double* out = part + (long)blockIdx.y * ntmax * ntmax * SYMV_T;
+  double a = 0.0;
+  for (int c = g; c < SYMV_T; c += 4) a += L[lane][c] * vc[c];
+  red[g][lane] = a;
+  __syncthreads();
+  if (g == 0) out[((long)I * ntmax + C) * SYMV_T + lane] = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
+  if (I == C) return;
+  __syncthreads();
+  a = 0.0;
+  for (int r = g; r < SYMV_T; r += 4) a += L[r][lane] * vr[r];
+  red[g][lane] = a;
+  __syncthreads();
+  if (g == 0) out[((long)C * ntmax + I) * SYMV_T + lane] = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
 }
 
 // w = tau (p - V (W^T v) - W (V^T v)); w += -tau/2 (w.v) v   (stored as W[:, jj]).
 // The 2 jj dot products are spread over the four wavefronts (one vector at a
 // time per wavefront, lanes over rows); the update loops over rows.
 __global__ __launch_bounds__(256) void k_trd_w(const MatDesc* mats, int p0, int jj, const double* tau,
-                                               const long* off, double* work, long sumns) {
+                                               const long* off, double* work, long sumns, const double* part,
+                                               int ntmax) {
   const MatDesc M = mats[blockIdx.x];
   const int n = M.n;
   const int j = p0 + jj;
@@ -149,18 +186,42 @@ __global__ __launch_bounds__(256) void k_trd_w(const MatDesc* mats, int p0, int 
   double* __restrict__ w = T.W + (long)jj * n;
   const double t = tau[o + j];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  // y[q] = W[:, q]^T v and y[NB + q] = V[:, q]^T v over rows j+1..n-1
-  for (int q = wid; q < 2 * jj; q += 4) {
-    const double* __restrict__ col = (q < jj) ? T.W + (long)q * n : T.V + (long)(q - jj) * n;
-    double acc = 0.0;
-    for (int i = j + 1 + lane; i < n; i += 64) acc += col[i] * v[i];
-    acc = wave_sum(acc);
-    if (lane == 0) y[q < jj ? q : TRD_NB + (q - jj)] = acc;
+  // y[q] = W[:, q]^T v and y[NB + q] = V[:, q]^T v over rows j+1..n-1: wavefront
+  // wid takes q = wid, wid + 4, ... (at most 2 NB / 4), one pass over the rows
+  // with independent loads for all its q
+  {
+    constexpr int QW = 2 * TRD_NB / 4;
+    double acc[QW];
+#pragma unroll
+    for (int k = 0; k < QW; ++k) acc[k] = 0.0;
+    for (int i = j + 1 + lane; i < n; i += 64) {
+      const double vi = v[i];
+#pragma unroll
+      for (int k = 0; k < QW; ++k) {
+        const int q = wid + 4 * k;
+        if (q < 2 * jj) {
+          const double* __restrict__ col = (q < jj) ? T.W + (long)q * n : T.V + (long)(q - jj) * n;
+          acc[k] += col[i] * vi;
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < QW; ++k) {
+      const int q = wid + 4 * k;
+      if (q < 2 * jj) {
+        const double a = wave_sum(acc[k]);
+        if (lane == 0) y[q < jj ? q : TRD_NB + (q - jj)] = a;
+      }
+    }
   }
   __syncthreads();
   double sv = 0.0;
+  const double* pp = part + (long)blockIdx.x * ntmax * ntmax * SYMV_T;
+  const int nt = (n - j - 1 + SYMV_T - 1) / SYMV_T;
   for (int i = j + 1 + threadIdx.x; i < n; i += 256) {
-    double x = T.p[i];
+    const int I = (i - j - 1) / SYMV_T, r = (i - j - 1) % SYMV_T;
+    double x = 0.0;
+    for (int C = 0; C < nt; ++C) x += pp[((long)I * ntmax + C) * SYMV_T + r];
     for (int q = 0; q < jj; ++q) x -= T.V[i + (long)q * n] * y[q] + T.W[i + (long)q * n] * y[TRD_NB + q];
     x *= t;
     w[i] = x;
@@ -170,6 +231,196 @@ __global__ __launch_bounds__(256) void k_trd_w(const MatDesc* mats, int p0, int 
   const double alpha = -0.5 * t * sv;
   for (int i = j + 1 + threadIdx.x; i < n; i += 256) w[i] += alpha * v[i];
   for (int i = threadIdx.x; i <= j; i += 256) w[i] = 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// Row-parallel forms of the per-column steps (many workgroups per matrix;
+// the single-workgroup kernels above leave most of the GPU idle when the
+// batch is small).  Reductions go through per-block partial sums added in a
+// fixed order.
+// ---------------------------------------------------------------------------
+constexpr int TRD_RB = 256;     // rows per workgroup
+constexpr int TRD_YCH = 512;    // rows per workgroup of the dot products
+
+// column j updated from the panel (rows j..n-1); partial sums of squares of
+// rows >= j + 2; block 0 keeps d_j = A[j][j] and alpha = A[j+1][j]
+__global__ __launch_bounds__(256) void k_trd_cu(const MatDesc* mats, int p0, int jj, const long* off, double* work,
+                                                long sumns, double* red, double* aux, int nblkmax) {
+  const MatDesc M = mats[blockIdx.y];
+  const int n = M.n;
+  const int j = p0 + jj;
+  if (j > n - 3 || (int)blockIdx.x * TRD_RB >= n - j) return;
+  __shared__ double sh[4];
+  TrdWork T(work, sumns, off[blockIdx.y]);
+  double* col = M.A + (long)j * M.ld;
+  const int i = j + blockIdx.x * TRD_RB + threadIdx.x;
+  double ss = 0.0;
+  if (i < n) {
+    double a = col[i];
+    for (int t = 0; t < jj; ++t)
+      a -= T.V[i + (long)t * n] * T.W[j + (long)t * n] + T.W[i + (long)t * n] * T.V[j + (long)t * n];
+    col[i] = a;
+    if (i >= j + 2) ss = a * a;
+    if (i == j) aux[2 * blockIdx.y] = a;
+    if (i == j + 1) aux[2 * blockIdx.y + 1] = a;
+  }
+  ss = block_sum256(ss, sh);
+  if (threadIdx.x == 0) red[(long)blockIdx.y * nblkmax + blockIdx.x] = ss;
+}
+
+// Householder vector of column j: d_j, e_j, tau_j; v (unit first entry)
+// replaces rows j+1.. of the column and is stored as V[:, jj] (zero above)
+__global__ __launch_bounds__(256) void k_trd_cf(const MatDesc* mats, int p0, int jj, double* dd, double* ee,
+                                                double* tau, const long* off, double* work, long sumns,
+                                                const double* red, const double* aux, int nblkmax) {
+  const MatDesc M = mats[blockIdx.y];
+  const int n = M.n;
+  const int j = p0 + jj;
+  if (j > n - 3 || (int)blockIdx.x * TRD_RB >= n) return;
+  __shared__ double scale_s;
+  const long o = off[blockIdx.y];
+  TrdWork T(work, sumns, o);
+  if (threadIdx.x == 0) {
+    const int nb = (n - j + TRD_RB - 1) / TRD_RB;
+    double ss = 0.0;
+    for (int b = 0; b < nb; ++b) ss += red[(long)blockIdx.y * nblkmax + b];
+    const double dkk = aux[2 * blockIdx.y], alpha = aux[2 * blockIdx.y + 1];
+    double sc;
+    if (ss == 0.0) {
+      sc = 0.0;
+      if (blockIdx.x == 0) {
+        ee[o + j] = alpha;
+        tau[o + j] = 0.0;
+      }
+    } else {
+      const double beta = -copysign(sqrt(alpha * alpha + ss), alpha);
+      sc = 1.0 / (alpha - beta);
+      if (blockIdx.x == 0) {
+        tau[o + j] = (beta - alpha) / beta;
+        ee[o + j] = beta;
+      }
+    }
+    if (blockIdx.x == 0) dd[o + j] = dkk;
+    scale_s = sc;
+  }
+  __syncthreads();
+  const double scale = scale_s;
+  const int i = blockIdx.x * TRD_RB + threadIdx.x;
+  if (i >= n) return;
+  double* col = M.A + (long)j * M.ld;
+  if (i <= j) {
+    T.V[i + (long)jj * n] = 0.0;
+  } else {
+    const double v = (i == j + 1) ? 1.0 : col[i] * scale;
+    col[i] = v;
+    T.V[i + (long)jj * n] = v;
+  }
+}
+
+// partial dot products y[q] = W[:, q]^T v, y[NB + q] = V[:, q]^T v over a chunk of rows
+__global__ __launch_bounds__(256) void k_trd_wy(const MatDesc* mats, int p0, int jj, const long* off, double* work,
+                                                long sumns, double* ypart, int nchmax) {
+  const MatDesc M = mats[blockIdx.y];
+  const int n = M.n;
+  const int j = p0 + jj;
+  if (j > n - 3 || (int)blockIdx.x * TRD_YCH >= n - j - 1) return;
+  TrdWork T(work, sumns, off[blockIdx.y]);
+  const double* __restrict__ v = T.V + (long)jj * n;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int r0 = j + 1 + blockIdx.x * TRD_YCH, r1 = min(n, r0 + TRD_YCH);
+  constexpr int QW = 2 * TRD_NB / 4;
+  double acc[QW];
+#pragma unroll
+  for (int k = 0; k < QW; ++k) acc[k] = 0.0;
+  for (int i = r0 + lane; i < r1; i += 64) {
+    const double vi = v[i];
+#pragma unroll
+    for (int k = 0; k < QW; ++k) {
+      const int q = wid + 4 * k;
+      if (q < 2 * jj) {
+        const double* __restrict__ c = (q < jj) ? T.W + (long)q * n : T.V + (long)(q - jj) * n;
+        acc[k] += c[i] * vi;
+      }
+    }
+  }
+  double* yp = ypart + ((long)blockIdx.y * nchmax + blockIdx.x) * 2 * TRD_NB;
+#pragma unroll
+  for (int k = 0; k < QW; ++k) {
+    const int q = wid + 4 * k;
+    if (q < 2 * jj) {
+      const double a = wave_sum(acc[k]);
+      if (lane == 0) yp[q < jj ? q : TRD_NB + (q - jj)] = a;
+    }
+  }
+}
+
+// x = tau (p - V y_W - W y_V) on a block of rows, p summed from the symv
+// partials; partial sums of x . v
+__global__ __launch_bounds__(256) void k_trd_wx(const MatDesc* mats, int p0, int jj, const double* tau,
+                                                const long* off, double* work, long sumns, const double* part,
+                                                int ntmax, const double* ypart, int nchmax, double* svpart,
+                                                int nblkmax) {
+  const MatDesc M = mats[blockIdx.y];
+  const int n = M.n;
+  const int j = p0 + jj;
+  if (j > n - 3 || (int)blockIdx.x * TRD_RB >= n - j - 1) return;
+  __shared__ double y[2 * TRD_NB];
+  __shared__ double sh[4];
+  const long o = off[blockIdx.y];
+  TrdWork T(work, sumns, o);
+  const int nch = (n - j - 1 + TRD_YCH - 1) / TRD_YCH;
+  if (threadIdx.x < 2 * TRD_NB) {
+    const int q = threadIdx.x;
+    const bool used = (q < TRD_NB) ? q < jj : (q - TRD_NB) < jj;
+    double a = 0.0;
+    if (used)
+      for (int ch = 0; ch < nch; ++ch) a += ypart[((long)blockIdx.y * nchmax + ch) * 2 * TRD_NB + q];
+    y[q] = a;
+  }
+  __syncthreads();
+  const double t = tau[o + j];
+  const double* __restrict__ v = T.V + (long)jj * n;
+  double* __restrict__ w = T.W + (long)jj * n;
+  const double* pp = part + (long)blockIdx.y * ntmax * ntmax * SYMV_T;
+  const int nt = (n - j - 1 + SYMV_T - 1) / SYMV_T;
+  const int i = j + 1 + blockIdx.x * TRD_RB + threadIdx.x;
+  double sv = 0.0;
+  if (i < n) {
+    const int I = (i - j - 1) / SYMV_T, r = (i - j - 1) % SYMV_T;
+    double x = 0.0;
+    for (int C = 0; C < nt; ++C) x += pp[((long)I * ntmax + C) * SYMV_T + r];
+    for (int q = 0; q < jj; ++q) x -= T.V[i + (long)q * n] * y[q] + T.W[i + (long)q * n] * y[TRD_NB + q];
+    x *= t;
+    w[i] = x;
+    sv = x * v[i];
+  }
+  sv = block_sum256(sv, sh);
+  if (threadIdx.x == 0) svpart[(long)blockIdx.y * nblkmax + blockIdx.x] = sv;
+}
+
+// w += -tau/2 (x . v) v below row j, zero at and above it
+__global__ __launch_bounds__(256) void k_trd_wfix(const MatDesc* mats, int p0, int jj, const double* tau,
+                                                  const long* off, double* work, long sumns, const double* svpart,
+                                                  int nblkmax) {
+  const MatDesc M = mats[blockIdx.y];
+  const int n = M.n;
+  const int j = p0 + jj;
+  if (j > n - 3 || (int)blockIdx.x * TRD_RB >= n) return;
+  __shared__ double alpha_s;
+  const long o = off[blockIdx.y];
+  TrdWork T(work, sumns, o);
+  if (threadIdx.x == 0) {
+    const int nb = (n - j - 1 + TRD_RB - 1) / TRD_RB;
+    double sv = 0.0;
+    for (int b = 0; b < nb; ++b) sv += svpart[(long)blockIdx.y * nblkmax + b];
+    alpha_s = -0.5 * tau[o + j] * sv;
+  }
+  __syncthreads();
+  const int i = blockIdx.x * TRD_RB + threadIdx.x;
+  if (i >= n) return;
+  double* w = T.W + (long)jj * n;
+  if (i <= j) w[i] = 0.0;
+  else w[i] += alpha_s * T.V[i + (long)jj * n];
 }
 
 // last 2x2 (or 1x1) block after every reflector has been applied
@@ -203,25 +454,52 @@ void sytrd_batched(const MatDesc* d_mats, const std::vector<int>& h_n, double* d
     sumns += v;
   }
   if (batch == 0 || maxn == 0) return;
+  const int ntmax = (maxn + SYMV_T - 1) / SYMV_T;
+  DBuf<double> part;
+  part.alloc((size_t)batch * ntmax * ntmax * SYMV_T);
+  const int nblkmax = (int)cdiv(maxn, TRD_RB) + 1;
+  const int nchmax = (int)cdiv(maxn, TRD_YCH) + 1;
+  DBuf<double> red, aux, ypart, svpart;
+  red.alloc((size_t)batch * nblkmax);
+  aux.alloc((size_t)batch * 2);
+  ypart.alloc((size_t)batch * nchmax * 2 * TRD_NB);
+  svpart.alloc((size_t)batch * nblkmax);
   for (int p0 = 0; p0 <= maxn - 3; p0 += TRD_NB) {
     const int nbp = std::min(TRD_NB, maxn - 2 - p0);
     for (int jj = 0; jj < nbp; ++jj) {
       const int j = p0 + jj;
-      hipLaunchKernelGGL(k_trd_col, dim3(batch), dim3(256), 0, s, d_mats, p0, jj, d, e, tau, d_off, work, sumns);
-      AWG_LAUNCH_CHECK();
+      const unsigned gb = cdiv(maxn, TRD_RB);
+      {
+        KScope kt("k_trd_col", s, 0.0, 0.0);
+        hipLaunchKernelGGL(k_trd_cu, dim3(gb, batch), dim3(256), 0, s, d_mats, p0, jj, d_off, work, sumns, red.p,
+                           aux.p, nblkmax);
+        hipLaunchKernelGGL(k_trd_cf, dim3(gb, batch), dim3(256), 0, s, d_mats, p0, jj, d, e, tau, d_off, work, sumns,
+                           red.p, aux.p, nblkmax);
+        AWG_LAUNCH_CHECK();
+      }
       const int rows = maxn - j - 1;
       double tb = 0.0;
       if (ktimer_on())
         for (int nbk : h_n)
           if (j <= nbk - 3) tb += 8.0 * (double)(nbk - j - 1) * (nbk - j - 1);
       {
-        KScope kt("k_trd_symv", s, tb, tb / 4.0);
-        hipLaunchKernelGGL(k_trd_symv, dim3(cdiv(rows, TRD_ROWS), batch), dim3(256), 0, s, d_mats, p0, jj, d_off,
-                           work, sumns);
+        const int ntr = (rows + SYMV_T - 1) / SYMV_T;
+        KScope kt("k_trd_symv", s, 0.5 * tb, tb / 4.0);
+        hipLaunchKernelGGL(k_trd_symv_lo, dim3(std::max(1, ntr * (ntr + 1) / 2), batch), dim3(256), 0, s, d_mats, p0,
+                           jj, d_off, work, sumns, part.p, ntmax);
         AWG_LAUNCH_CHECK();
       }
-      hipLaunchKernelGGL(k_trd_w, dim3(batch), dim3(256), 0, s, d_mats, p0, jj, tau, d_off, work, sumns);
-      AWG_LAUNCH_CHECK();
+      {
+        KScope ktw("k_trd_w", s, 0.0, 0.0);
+        if (jj > 0)
+          hipLaunchKernelGGL(k_trd_wy, dim3(cdiv(std::max(1, rows), TRD_YCH), batch), dim3(256), 0, s, d_mats, p0, jj,
+                             d_off, work, sumns, ypart.p, nchmax);
+        hipLaunchKernelGGL(k_trd_wx, dim3(cdiv(std::max(1, rows), TRD_RB), batch), dim3(256), 0, s, d_mats, p0, jj,
+                           tau, d_off, work, sumns, part.p, ntmax, ypart.p, nchmax, svpart.p, nblkmax);
+        hipLaunchKernelGGL(k_trd_wfix, dim3(gb, batch), dim3(256), 0, s, d_mats, p0, jj, tau, d_off, work, sumns,
+                           svpart.p, nblkmax);
+        AWG_LAUNCH_CHECK();
+      }
     }
     const int rem = maxn - p0 - nbp;
     double fl = 0.0;
@@ -349,6 +627,7 @@ __global__ __launch_bounds__(64) void k_tri_count(TriEigArgs a, const double* th
 void tri_count(const TriEigArgs& a, const double* thr_in, int thr_mode, double eps0, double* thr_out, int* count,
                double* lam_minmax, hipStream_t s) {
   if (a.nb == 0) return;
+  KScope kt("k_tri_count", s, 0.0, 0.0);
   hipLaunchKernelGGL(k_tri_count, dim3(a.nb), dim3(64), 0, s, a, thr_in, thr_mode, eps0, thr_out, count,
                      lam_minmax);
   AWG_LAUNCH_CHECK();
@@ -521,6 +800,7 @@ void tri_eigvecs(const TriEigArgs& a, const int* count, const long* lam_off, dou
                  double* work, const long* work_off, double* resid, int* nstrict, const double* thr,
                  hipStream_t s) {
   if (a.nb == 0) return;
+  KScope kt("k_tri_vecs", s, 0.0, 0.0);
   hipLaunchKernelGGL(k_tri_vecs, dim3(a.nb), dim3(64), 0, s, a, count, lam_off, lam, d_Z, work, work_off, resid,
                      nstrict, thr);
   AWG_LAUNCH_CHECK();
@@ -590,6 +870,7 @@ void ormtr_batched(const MatDesc* d_mats, const MatDesc* d_Z, const double* tau,
   if (batch == 0 || maxk == 0 || maxn < 3) return;
   const size_t lds = (size_t)ORM_COLS * maxn * sizeof(double);
   if (lds > 150 * 1024) throw Error(-1, "ormtr: block too large for the LDS-resident back-transformation");
+  KScope kt("k_ormtr", s, 0.0, 0.0);
   hipLaunchKernelGGL(k_ormtr, dim3(cdiv(maxk, ORM_COLS), batch), dim3(256), lds, s, d_mats, d_Z, tau, d_off);
   AWG_LAUNCH_CHECK();
 }
