@@ -174,10 +174,11 @@ struct TriEigArgs {
 void tri_count(const TriEigArgs& a, const double* thr_in, int thr_mode, double eps0, double* thr_out,
                int* count, double* lam_minmax, hipStream_t s);
 // Work: 384 * n_b doubles per block at work_off[b] (see k_eig.hip).
-constexpr long TRIVEC_WORK_PER_ROW = 6 * 64;
+constexpr long TRIVEC_WORK_PER_ROW = 7 * 64;
+// maxn: largest block order (d and e are staged in LDS when it is <= 6144)
 void tri_eigvecs(const TriEigArgs& a, const int* count, const long* lam_off, double* lam,
                  const MatDesc* d_Z, double* work, const long* work_off, double* resid,
-                 int* nstrict, const double* thr, hipStream_t s);
+                 int* nstrict, const double* thr, hipStream_t s, int maxn = 0);
 // Z_b <- Q_b Z_b with the reflectors stored by sytrd_batched.
 void ormtr_batched(const MatDesc* d_mats, const MatDesc* d_Z, const double* tau, const long* d_off,
                    const std::vector<int>& h_n, const std::vector<int>& h_k, hipStream_t s);

@@ -703,7 +703,7 @@ EigOut batched_low_eigs(awg_ctx& c, DBuf<MatDesc>& dX, int thr_mode, double thr_
   auto zd = col_descs(c, vecs, L);
   DBuf<MatDesc> dZ;
   dZ.upload(zd, s);
-  tri_eigvecs(a, cnt, L.d_coff, lam, dZ, work, dw6, resid, want_strict ? nst.p : nullptr, thr, s);
+  tri_eigvecs(a, cnt, L.d_coff, lam, dZ, work, dw6, resid, want_strict ? nst.p : nullptr, thr, s, c.maxns);
   ormtr_batched(dX, dZ, tau, c.subptr, c.ns, out.count, s);
   if (want_strict) out.nstrict = nst.download(s);
   if (L.cols) {

@@ -143,7 +143,7 @@ int awg_dense_low_eigs(int32_t batch, int32_t n, double* A, int32_t lda, int64_t
     DBuf<double> resid;
     resid.alloc(std::max(1L, (long)batch * max_k));
     if (max_k > 0 && lam && Z) {
-      tri_eigvecs(a, cnt, dlo, lam, dZ, work, w6, resid, nullptr, thrv, s);
+      tri_eigvecs(a, cnt, dlo, lam, dZ, work, w6, resid, nullptr, thrv, s, n);
       ormtr_batched(dA, dZ, tau, doff, hn, kk, s);
     }
   });

@@ -642,9 +642,12 @@ constexpr int INVIT_LANES = 64;
 // Work per block (doubles): 6 arrays of n x 64, interleaved so that step i of
 // all 64 lanes is one contiguous 512-byte row: u0, u1, u2 (U of the LU with
 // partial pivoting), l (multipliers), pivot flags, x (iterates).
+// d and e are staged in LDS when use_lds (dynamic shared memory of 2 n
+// doubles): the bisection and the LU factorisations walk them sequentially.
 __global__ __launch_bounds__(64) void k_tri_vecs(TriEigArgs a, const int* count, const long* lam_off, double* lam,
                                                   const MatDesc* Zs, double* work, const long* work_off,
-                                                  double* resid, int* nstrict, const double* thr) {
+                                                  double* resid, int* nstrict, const double* thr, int use_lds) {
+  extern __shared__ double tri_lds[];
   const int b = blockIdx.x;
   const int n = a.n[b];
   const int k = count[b];
@@ -655,6 +658,15 @@ __global__ __launch_bounds__(64) void k_tri_vecs(TriEigArgs a, const int* count,
   }
   const double* d = a.d + a.off[b];
   const double* e = a.e + a.off[b];
+  if (use_lds) {
+    for (int i = lane; i < n; i += 64) {
+      tri_lds[i] = d[i];
+      tri_lds[n + i] = i < n - 1 ? e[i] : 0.0;
+    }
+    __syncthreads();
+    d = tri_lds;
+    e = tri_lds + n;
+  }
   double* L = lam + lam_off[b];
   const MatDesc Z = Zs[b];
   const long W = INVIT_LANES;
@@ -665,6 +677,8 @@ __global__ __launch_bounds__(64) void k_tri_vecs(TriEigArgs a, const int* count,
   double* __restrict__ LF = wk + 3 * W * n;
   double* __restrict__ PV = wk + 4 * W * n;
   double* __restrict__ X = wk + 5 * W * n;
+  double* __restrict__ XT = wk + 6 * W * n;    // the chunk with each vector contiguous (Gram-Schmidt)
+  __shared__ double tile[64][65];
   const TriInfo t = tri_info(d, e, n);
   for (int j = lane; j < k; j += 64) L[j] = bisect_eig(d, e, n, j, t.gl, t.gu, t.pivmin);
   __syncthreads();
@@ -760,22 +774,41 @@ __global__ __launch_bounds__(64) void k_tri_vecs(TriEigArgs a, const int* count,
           for (int i = 0; i < n; ++i) X[i * W + lane] -= dt * zq[i];
         }
       __syncthreads();
-      // modified Gram-Schmidt inside the chunk, in eigenvalue order, twice;
-      // the wavefront cooperates on one vector at a time
+      // modified Gram-Schmidt inside the chunk, in eigenvalue order, twice, on
+      // a transposed copy (vector j contiguous at XT + j n) so that the
+      // wavefront's loads over rows are coalesced; 64 x 64 tiles through LDS
+      for (int i0 = 0; i0 < n; i0 += 64) {
+        const int ni = min(64, n - i0);
+        for (int r = 0; r < ni; ++r) tile[r][lane] = X[(long)(i0 + r) * W + lane];
+        __syncthreads();
+        for (int jq = 0; jq < kc; ++jq)
+          if (lane < ni) XT[(long)jq * n + i0 + lane] = tile[lane][jq];
+        __syncthreads();
+      }
       for (int jj = 0; jj < kc; ++jj) {
+        double* __restrict__ xj = XT + (long)jj * n;
         for (int pass = 0; pass < 2; ++pass)
           for (int q = 0; q < jj; ++q) {
+            const double* __restrict__ xq = XT + (long)q * n;
             double dt = 0.0;
-            for (int i = lane; i < n; i += 64) dt += X[i * W + q] * X[i * W + jj];
+            for (int i = lane; i < n; i += 64) dt += xq[i] * xj[i];
             dt = wave_sum(dt);
-            for (int i = lane; i < n; i += 64) X[i * W + jj] -= dt * X[i * W + q];
-            __syncthreads();
+            for (int i = lane; i < n; i += 64) xj[i] -= dt * xq[i];
           }
         double nr = 0.0;
-        for (int i = lane; i < n; i += 64) nr += X[i * W + jj] * X[i * W + jj];
+        for (int i = lane; i < n; i += 64) nr += xj[i] * xj[i];
         nr = wave_sum(nr);
         const double inr = nr > 0.0 ? 1.0 / sqrt(nr) : 0.0;
-        for (int i = lane; i < n; i += 64) X[i * W + jj] *= inr;
+        for (int i = lane; i < n; i += 64) xj[i] *= inr;
+      }
+      __syncthreads();
+      for (int i0 = 0; i0 < n; i0 += 64) {
+        const int ni = min(64, n - i0);
+        for (int jq = 0; jq < kc; ++jq)
+          if (lane < ni) tile[lane][jq] = XT[(long)jq * n + i0 + lane];
+        __syncthreads();
+        for (int r = 0; r < ni; ++r)
+          if (lane < kc) X[(long)(i0 + r) * W + lane] = tile[r][lane];
         __syncthreads();
       }
     }
@@ -798,11 +831,12 @@ __global__ __launch_bounds__(64) void k_tri_vecs(TriEigArgs a, const int* count,
 
 void tri_eigvecs(const TriEigArgs& a, const int* count, const long* lam_off, double* lam, const MatDesc* d_Z,
                  double* work, const long* work_off, double* resid, int* nstrict, const double* thr,
-                 hipStream_t s) {
+                 hipStream_t s, int maxn) {
   if (a.nb == 0) return;
+  const bool lds = maxn > 0 && maxn <= 6144;
   KScope kt("k_tri_vecs", s, 0.0, 0.0);
-  hipLaunchKernelGGL(k_tri_vecs, dim3(a.nb), dim3(64), 0, s, a, count, lam_off, lam, d_Z, work, work_off, resid,
-                     nstrict, thr);
+  hipLaunchKernelGGL(k_tri_vecs, dim3(a.nb), dim3(64), lds ? sizeof(double) * 2 * maxn : 0, s, a, count, lam_off,
+                     lam, d_Z, work, work_off, resid, nstrict, thr, (int)lds);
   AWG_LAUNCH_CHECK();
 }
 
