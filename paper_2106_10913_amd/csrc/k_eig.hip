@@ -168,6 +168,91 @@ __global__ __launch_bounds__(256) void k_trd_symv_lo(const MatDesc* mats, int p0
   if (g == 0) out[((long)C * ntmax + I) * SYMV_T + lane] = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
 }
 
+// Pipelined form of k_trd_symv_lo: a workgroup walks tiles t = blockIdx.x,
+// blockIdx.x + gridDim.x, ... of its matrix and loads the next tile into
+// registers while it works on the current one in LDS (loads stay in flight).
+__device__ inline void symv_tile_decode(int t, int& I, int& C) {
+  I = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+  while ((I + 1) * (I + 2) / 2 <= t) ++I;
+  while (I * (I + 1) / 2 > t) --I;
+  C = t - I * (I + 1) / 2;
+}
+
+__global__ __launch_bounds__(256) void k_trd_symv_pipe(const MatDesc* mats, int p0, int jj, const long* off,
+                                                       double* work, long sumns, double* part, int ntmax) {
+  const MatDesc M = mats[blockIdx.y];
+  const int n = M.n;
+  const int j = p0 + jj;
+  if (j > n - 3) return;
+  const int base = j + 1, m = n - base;
+  const int nt = (m + SYMV_T - 1) / SYMV_T;
+  const int ntiles = nt * (nt + 1) / 2;
+  int t = blockIdx.x;
+  if (t >= ntiles) return;
+  TrdWork T(work, sumns, off[blockIdx.y]);
+  const double* v = T.V + (long)jj * n;
+  __shared__ double L[SYMV_T][SYMV_T + 1];
+  __shared__ double vr[SYMV_T], vc[SYMV_T];
+  __shared__ double red[4][SYMV_T];
+  const int tid = threadIdx.x, lane = tid & 63, g = tid >> 6;
+  double* out = part + (long)blockIdx.y * ntmax * ntmax * SYMV_T;
+  double cur[16];
+  auto load = [&](int tt, double* buf) {
+    int I, C;
+    symv_tile_decode(tt, I, C);
+    const int r0 = base + I * SYMV_T, c0 = base + C * SYMV_T;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int e = tid + q * 256;
+      const int r = e % SYMV_T, c = e / SYMV_T;
+      const int gr = r0 + r, gc = c0 + c;
+      buf[q] = (gr < n && gc < n && (I != C || r >= c)) ? M.A[gr + (long)gc * M.ld] : 0.0;
+    }
+  };
+  load(t, cur);
+  for (;;) {
+    int I, C;
+    symv_tile_decode(t, I, C);
+    const int r0 = base + I * SYMV_T, c0 = base + C * SYMV_T;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int e = tid + q * 256;
+      L[e % SYMV_T][e / SYMV_T] = cur[q];
+    }
+    if (tid < SYMV_T) {
+      vr[tid] = (r0 + tid < n) ? v[r0 + tid] : 0.0;
+      vc[tid] = (c0 + tid < n) ? v[c0 + tid] : 0.0;
+    }
+    const int tn = t + gridDim.x;
+    if (tn < ntiles) load(tn, cur);      // next tile in flight during the work below
+    __syncthreads();
+    if (I == C) {
+      for (int e = tid; e < SYMV_T * SYMV_T; e += 256) {
+        const int r = e % SYMV_T, c = e / SYMV_T;
+        if (r < c) L[r][c] = L[c][r];
+      }
+      __syncthreads();
+    }
+    double a = 0.0;
+    for (int c = g; c < SYMV_T; c += 4) a += L[lane][c] * vc[c];
+    red[g][lane] = a;
+    __syncthreads();
+    if (g == 0) out[((long)I * ntmax + C) * SYMV_T + lane] = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
+    __syncthreads();
+    if (I != C) {
+      a = 0.0;
+      for (int r = g; r < SYMV_T; r += 4) a += L[r][lane] * vr[r];
+      red[g][lane] = a;
+      __syncthreads();
+      if (g == 0)
+        out[((long)C * ntmax + I) * SYMV_T + lane] = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
+      __syncthreads();
+    }
+    if (tn >= ntiles) break;
+    t = tn;
+  }
+}
+
 // w = tau (p - V (W^T v) - W (V^T v)); w += -tau/2 (w.v) v   (stored as W[:, jj]).
 // The 2 jj dot products are spread over the four wavefronts (one vector at a
 // time per wavefront, lanes over rows); the update loops over rows.
@@ -484,9 +569,12 @@ void sytrd_batched(const MatDesc* d_mats, const std::vector<int>& h_n, double* d
           if (j <= nbk - 3) tb += 8.0 * (double)(nbk - j - 1) * (nbk - j - 1);
       {
         const int ntr = (rows + SYMV_T - 1) / SYMV_T;
+        const int ntiles = std::max(1, ntr * (ntr + 1) / 2);
+        // about 4 tiles per workgroup once the trailing matrices are large
+        const int gx = ntiles <= 64 ? ntiles : (ntiles + 3) / 4;
         KScope kt("k_trd_symv", s, 0.5 * tb, tb / 4.0);
-        hipLaunchKernelGGL(k_trd_symv_lo, dim3(std::max(1, ntr * (ntr + 1) / 2), batch), dim3(256), 0, s, d_mats, p0,
-                           jj, d_off, work, sumns, part.p, ntmax);
+        hipLaunchKernelGGL(k_trd_symv_pipe, dim3(gx, batch), dim3(256), 0, s, d_mats, p0, jj, d_off, work, sumns,
+                           part.p, ntmax);
         AWG_LAUNCH_CHECK();
       }
       {
