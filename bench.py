@@ -104,10 +104,10 @@ MFMA_KERNELS = ("k_gemm",)
 # (factors 2.0 and 1.0).  Valid only for the kernel source and workload they
 # were taken on; otherwise the bench reports traffic = null.
 TRAFFIC = {
-    "k_trd_symv": {
-        "bytes_per_launch": 1.7273e8,
-        "source": "paper_2106_10913_amd/csrc/k_eig.hip",
-        "sha256": "bdbc892df0e2ad51eb0af0573b6d8ca6452f751c4d5817fcda19d4955c9736ea",
+    "k_gemm128w8<DescArray,N,N>:P": {
+        "bytes_per_launch": 1.6233e10,
+        "source": "paper_2106_10913_amd/csrc/k_dense.hip",
+        "sha256": "f6e02f80b505881fdbb25c6124ca466b5e86375f70563d122634727f7a610ef0",
         "workload": "q1_2d_diffusion_256x256_box8x8_overlap2_tau0.1",
     },
 }
