@@ -26,6 +26,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
+FP32_PEAK_TFLOPS = 157.3
 
 
 def parse():
@@ -122,6 +123,25 @@ def measured_traffic(name: str, workload: str):
         if hashlib.sha256(f.read()).hexdigest() != rec["sha256"]:
             return None
     return rec["bytes_per_launch"]
+
+
+def kernel_rates(kt: dict, top: int = 20) -> dict:
+    """Achieved rate of each instrumented kernel over the warm-up step: HBM
+    kernels as algorithmic GB/s and fraction of the HBM peak, MFMA kernels as
+    TFLOP/s and fraction of the FP64 (or FP32 for the FP32 local product) peak.
+    """
+    out = {}
+    for name, rec in sorted(kt.items(), key=lambda kv: -kv[1]["ms"])[:top]:
+        if name.startswith("graph:") or rec["ms"] <= 0:
+            continue
+        if name.startswith(MFMA_KERNELS) and rec["flops"] > 0:
+            peak = FP32_PEAK_TFLOPS if "_mix" in name else FP64_PEAK_TFLOPS
+            tf = rec["flops"] / (rec["ms"] * 1e-3) / 1e12
+            out[name] = {"TFLOP/s": round(tf, 2), "frac": round(tf / peak, 3), "calls": rec["calls"]}
+        elif rec["bytes"] > 0:
+            gbs = rec["bytes"] / (rec["ms"] * 1e-3) / 1e9
+            out[name] = {"GB/s": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 3), "calls": rec["calls"]}
+    return out
 
 
 def roofline(kt: dict, steps: int, workload: str) -> dict:
@@ -308,11 +328,13 @@ def main():
                             "w_iters": st32["w_iters"], "speedup_vs_f64": round(ms / ms32, 3),
                             "phases_ms": {k: round(v, 3) for k, v in st32["ms"].items()},
                             "kernels_ms_per_warmup_step": {k: round(v["ms"], 3) for k, v in
-                                                           sorted(kt32.items(), key=lambda kv: -kv[1]["ms"])[:12]}}
+                                                           sorted(kt32.items(), key=lambda kv: -kv[1]["ms"])[:12]},
+                            "kernel_rates_warmup": kernel_rates(kt32, top=12)}
     out["roofline"] = roofline(kt, args.steps, out["config"]["workload"])
     out["autotune"] = {k: v["variant"] for k, v in awg.tune_report().items()}
     out["kernels_ms_per_warmup_step"] = {k: round(v["ms"] / nwarm, 3) for k, v in
                                          sorted(kt_warm.items(), key=lambda kv: -kv[1]["ms"])[:20]}
+    out["kernel_rates_warmup"] = kernel_rates(kt_warm)
     if not args.no_cpu_baseline and args.workload == "q1_2d_256":
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out))

@@ -31,6 +31,24 @@ int awg_dense_gemm(int32_t batch, int32_t m, int32_t n, int32_t k, int32_t trans
                    int32_t ldb, int64_t strideB, double beta, double* C, int32_t ldc, int64_t strideC,
                    void* stream);
 
+/* awg_dense_gemm with a chosen launch variant and an optional row gather of
+ * the A operands (the form the multi-column products of the W solves use).
+ * variant: -1 = autotuned (measured on the first call with beta = 0 for this
+ * shape), 0 = 64x64 tiles, 1 = 128x128 tiles with 4 wavefronts, 2 = 128x128
+ * tiles with 8 wavefronts, 3 and 4 = 32x32 blocks per wavefront without LDS
+ * with 16 or 32 k values per load batch (only for transA = transB = 0;
+ * otherwise variant 2 runs).  Every variant returns bit-identical results.
+ * arows: NULL, or a device array of batch x k int32 (requires transA = 0):
+ * column j of A_b is then A + arows[b k + j] * lda (strideA is ignored), i.e.
+ * row arows[b k + j] of a row-major matrix with lda columns; the caller
+ * guarantees that every index addresses memory inside A.
+ * Returns AWG_ERR_ARG for negative sizes, null pointers, a variant outside
+ * -1..4, or arows with transA = 1. */
+int awg_dense_gemm_ex(int32_t batch, int32_t m, int32_t n, int32_t k, int32_t transA, int32_t transB,
+                      double alpha, const double* A, int32_t lda, int64_t strideA, const int32_t* arows,
+                      const double* B, int32_t ldb, int64_t strideB, double beta, double* C, int32_t ldc,
+                      int64_t strideC, int32_t variant, void* stream);
+
 /* In-place lower Cholesky A_b = L_b L_b^T (upper triangle left unspecified).
  * info_host[b] (host, batch entries) = 0 or the 1-based column of the first
  * non-positive pivot; returns AWG_ERR_NOT_SPD if any block failed. */
@@ -54,7 +72,8 @@ int awg_dense_low_eigs(int32_t batch, int32_t n, double* A, int32_t lda, int64_t
 /* Y = alpha A X + beta Y for a CSR matrix A (n x n, 0-based, rowptr int64 with
  * nnz < 2^31) and row-major n x b blocks X, Y (the multi-column product of the
  * W solves).  variant: -1 = the autotuned launch variant for this shape
- * (measured on the first call with beta = 0), 0..4 = a fixed variant; every
+ * (measured on the first call with beta = 0), 0..8 = a fixed variant (5..8
+ * need an even b and 16-byte aligned X and Y, else they run variant 1); every
  * variant returns bit-identical results. */
 int awg_csr_spmm(int32_t n, int64_t nnz, const int64_t* rowptr, const int32_t* col, const double* val,
                  const double* X, double* Y, int32_t b, double alpha, double beta, int32_t variant, void* stream);

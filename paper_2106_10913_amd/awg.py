@@ -25,7 +25,7 @@ STATUS = {0: "AWG_OK", 1: "AWG_NOT_CONVERGED", -1: "AWG_ERR_ARG", -2: "AWG_ERR_N
 
 EXPORTED = ["awg_default_options", "awg_setup", "awg_apply", "awg_pcg", "awg_stats", "awg_export",
             "awg_last_error", "awg_destroy", "awg_kernel_timing", "awg_kernel_times", "awg_pcg_graph",
-            "awg_dense_gemm", "awg_dense_potrf", "awg_dense_trsm", "awg_dense_low_eigs",
+            "awg_dense_gemm", "awg_dense_gemm_ex", "awg_dense_potrf", "awg_dense_trsm", "awg_dense_low_eigs",
             "awg_mlp_create", "awg_mlp_num_params", "awg_mlp_get_params", "awg_mlp_set_params", "awg_mlp_forward",
             "awg_mlp_loss_grad", "awg_mlp_get_grads", "awg_mlp_adam_step", "awg_mlp_last_error", "awg_mlp_destroy",
             "awg_csr_spmm", "awg_autotune", "awg_tune_report", "awg_kernel_timing_filter"]
@@ -92,6 +92,9 @@ def lib():
     L.awg_dense_gemm.argtypes = [i32, i32, i32, i32, i32, i32, dbl, vp, i32, i64, vp, i32, i64, dbl, vp, i32, i64,
                                  vp]
     L.awg_dense_gemm.restype = ctypes.c_int
+    L.awg_dense_gemm_ex.argtypes = [i32, i32, i32, i32, i32, i32, dbl, vp, i32, i64, vp, vp, i32, i64, dbl, vp, i32,
+                                    i64, i32, vp]
+    L.awg_dense_gemm_ex.restype = ctypes.c_int
     L.awg_dense_potrf.argtypes = [i32, i32, vp, i32, i64, vp, vp]
     L.awg_dense_potrf.restype = ctypes.c_int
     L.awg_dense_trsm.argtypes = [i32, i32, i32, i32, vp, i32, i64, vp, i32, i64, vp]
@@ -323,6 +326,30 @@ def dense_gemm(A, B, C, alpha=1.0, beta=0.0, transA=False, transB=False):
                               _stream())
     if rc:
         raise AWGError(rc, "awg_dense_gemm")
+    return C
+
+
+def dense_gemm_ex(A, B, C, alpha=1.0, beta=0.0, transA=False, transB=False, variant=-1, arows=None, k=None):
+    """dense_gemm with a chosen launch variant; with arows (int32 tensor of
+    batch x k row indices) A is one row-major matrix (rows, lda) whose rows
+    arows[b] form the columns of A_b."""
+    _, nb, kb = B.shape
+    if arows is None:
+        batch, ka, ma = A.shape
+        m = ka if transA else ma
+        kk = ma if transA else ka
+        lda, sa, rows = ma, ka * ma, 0
+    else:
+        batch = B.shape[0]
+        kk = arows.shape[1]
+        m = lda = A.shape[1]
+        sa, rows = 0, arows.data_ptr()
+    n = kb if transB else nb
+    rc = lib().awg_dense_gemm_ex(batch, m, n, kk, int(transA), int(transB), alpha, A.data_ptr(), lda, sa, rows,
+                                 B.data_ptr(), kb, nb * kb, beta, C.data_ptr(), C.shape[2], C.shape[1] * C.shape[2],
+                                 variant, _stream())
+    if rc:
+        raise AWGError(rc, "awg_dense_gemm_ex")
     return C
 
 

@@ -92,12 +92,15 @@ std::string ktimer_json(bool reset);
 // ---------------------------------------------------------------------------
 // batched dense descriptors (column-major blocks)
 // ---------------------------------------------------------------------------
+// acol (untransposed A only): when set, column k of A starts at
+// A + acol[k] * lda instead of A + k * lda (a row gather fused into the load)
 struct GemmDesc {
   const double* A;
   const double* B;
   double* C;
   int m, n, k;
   int lda, ldb, ldc;
+  const int* acol = nullptr;
 };
 
 struct GemmDescMix {     // FP64 A, FP32 B, FP64 C (FP32 local operators)
@@ -106,6 +109,7 @@ struct GemmDescMix {     // FP64 A, FP32 B, FP64 C (FP32 local operators)
   double* C;
   int m, n, k;
   int lda, ldb, ldc;
+  const int* acol = nullptr;
 };
 
 struct MatDesc {         // one square or rectangular column-major block
@@ -126,8 +130,22 @@ void gemm_batched(const GemmDesc* d_desc, int batch, int max_m, int max_n, bool 
                   double alpha, double beta, bool lower, hipStream_t s, double flops = 0.0,
                   const char* tag = nullptr);
 // C = alpha A B + beta C with FP32 B (A rounded to FP32, FP32 MFMA and accumulation)
+// Batched products whose untransposed A operands are row gathers of one
+// row-major multi-vector X (n x lda): batch entry q reads its column k from
+// row idx[off[q] + k] of X (A and acol of the descriptors are replaced).
+void gemm_batched_gather(const GemmDesc* d_desc, const double* X, const int* idx, const long* off, int batch,
+                         int max_m, int max_n, bool transB, double alpha, double beta, hipStream_t s, double flops,
+                         const char* tag);
+// one fixed launch variant (0..3) of gemm_batched (X == nullptr) or of
+// gemm_batched_gather (transA must then be false)
+void gemm_batched_fixed(const GemmDesc* d_desc, const double* X, const int* idx, const long* off, int batch,
+                        int max_m, int max_n, bool transA, bool transB, double alpha, double beta, hipStream_t s,
+                        int variant);
+// X, idx, off (optional): the same row gather of the A operands as in
+// gemm_batched_gather
 void gemm_mix_batched(const GemmDescMix* d_desc, int batch, int max_m, int max_n, double alpha, double beta,
-                      hipStream_t s, double flops);
+                      hipStream_t s, double flops, const double* X = nullptr, const int* idx = nullptr,
+                      const long* off = nullptr);
 // y = alpha * op(A) x + beta * y per descriptor, with the GEMM convention
 // (n == 1: A = matrix, B = x, C = y; op(A) is m x k).  A single long
 // non-transposed product (k >= 16 m) splits k over GEMV_KSPLIT ranges when the

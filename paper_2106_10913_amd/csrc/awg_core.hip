@@ -10,6 +10,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <sstream>
 
@@ -17,6 +18,7 @@
 #include "awg_common.h"
 #include "awg_sparse.h"
 #include "awg_subspace.h"
+#include "awg_tune.h"
 #include "awg_mlp.h"
 #include "awg_mlp_impl.h"
 
@@ -424,12 +426,13 @@ void build_ws(awg_ctx& c, MultiWS& w, int b) {
     w.maxns = std::max(w.maxns, nsq);
     const double* Vq = c.V.p + c.LV.eoff[q];
     const double* Yq = c.Y.p + c.LY.eoff[q];
+    const double* xs = w.Xs.p + so;   // replaced by the rows of X in the in-place form
     // T_q = V_q^T X_q ;  O_q = V_q T_q ;  G0_q = Y_q^T X_q ;  O_q = Y_q G1_q ;  O_q = P_q X_q
-    vt[q] = mk(w.Xs.p + so, Vq, nsq, w.Tk.p + c.LV.coff[q] * b, kq, nsq, false, b);
+    vt[q] = mk(xs, Vq, nsq, w.Tk.p + c.LV.coff[q] * b, kq, nsq, false, b);
     vv[q] = mk(w.Tk.p + c.LV.coff[q] * b, Vq, nsq, w.Os.p + so, nsq, kq, true, b);
-    yt[q] = mk(w.Xs.p + so, Yq, nsq, w.G0.p + c.LY.coff[q] * b, mq, nsq, false, b);
+    yt[q] = mk(xs, Yq, nsq, w.G0.p + c.LY.coff[q] * b, mq, nsq, false, b);
     yy[q] = mk(w.G1.p + c.LY.coff[q] * b, Yq, nsq, w.Os.p + so, nsq, mq, true, b);
-    pp[q] = mk(w.Xs.p + so, c.P.p + c.sqoff[q], nsq, w.Os.p + so, nsq, nsq, false, b);
+    pp[q] = mk(xs, c.P.p + c.sqoff[q], nsq, w.Os.p + so, nsq, nsq, false, b);
   }
   gemm_upload(w.dVt, vt, s);
   gemm_upload(w.dV, vv, s);
@@ -457,6 +460,36 @@ void build_ws(awg_ctx& c, MultiWS& w, int b) {
   gemm_upload(w.dW, {mk(w.H1, c.W, nm, w.Z, c.n, c.nminus, false, b)}, s);
 }
 
+// Products with the restricted multi-vector R^q X (b > 1) as their A operand
+// come in two forms with identical results: the restriction written out by
+// l_gather and a plain batched GEMM, or the GEMM reading the rows
+// sub_idx[sub_ptr[q] ..] of X in place.  In-place reads save the restricted
+// block's write and re-read but scatter the GEMM's loads over all of X; the
+// faster form per call site and shape is measured on the first call.
+void restricted_product(awg_ctx& c, MultiWS& w, const char* tag, const double* X,
+                        const std::function<void(bool fused)>& run) {
+  const std::string key = std::string("restrict:") + tag + ":b=" + std::to_string(w.b) + ":sumns=" +
+                          std::to_string(c.sumns) + ":N=" + std::to_string(c.N);
+  int v = tune_lookup(key);
+  if (v < 0) v = tune_pick(key, 2, [&](int f) {
+    if (!f) l_gather(c.sumns, c.subidx, X, w.b, w.Xs, c.s);
+    run(f != 0);
+  }, c.s);
+  if (v == 0) l_gather(c.sumns, c.subidx, X, w.b, w.Xs, c.s);
+  run(v != 0);
+}
+
+// restricted product through the explicit descriptors d (A = the restricted block)
+void bmm_restricted(awg_ctx& c, MultiWS& w, const DBuf<GemmDesc>& d, const double* X, int maxout, int maxk,
+                    double flops, const char* tag) {
+  restricted_product(c, w, tag, X, [&](bool fused) {
+    if (fused)
+      gemm_batched_gather(d, X, c.subidx.p, c.subptr.p, c.N, w.b, maxout, false, 1.0, 0.0, c.s, flops, tag);
+    else
+      gemm_batched(d, c.N, w.b, maxout, false, false, 1.0, 0.0, false, c.s, flops, tag);
+  });
+}
+
 // Y = beta Y + A_- X   (A_- = sum_s R^sT V^s |L^s_-| V^sT R^s; Definition of A_-, Section 3.2)
 void op_aminus(awg_ctx& c, MultiWS& w, const double* X, double* Yo, double beta) {
   const int b = w.b;
@@ -464,8 +497,12 @@ void op_aminus(awg_ctx& c, MultiWS& w, const double* X, double* Yo, double beta)
     if (beta == 0.0) AWG_HIP(hipMemsetAsync(Yo, 0, sizeof(double) * c.n * (size_t)b, c.s));
     return;
   }
-  l_gather(c.sumns, c.subidx, X, b, w.Xs, c.s);
-  bmm(w.dVt, c.N, w.maxk, w.maxns, false, 1.0, 0.0, b, c.s, w.flV, nullptr, "Vt");
+  if (b > 1) {
+    bmm_restricted(c, w, w.dVt, X, w.maxk, w.maxns, w.flV, "Vt");
+  } else {
+    l_gather(c.sumns, c.subidx, X, b, w.Xs, c.s);
+    bmm(w.dVt, c.N, w.maxk, w.maxns, false, 1.0, 0.0, b, c.s, w.flV, nullptr, "Vt");
+  }
   hipLaunchKernelGGL(k_scale_rows, dim3(cdiv(c.LV.cols * b, 256)), dim3(256), 0, c.s, w.Tk.p, c.lamV.p,
                      (long)c.LV.cols, b);
   AWG_LAUNCH_CHECK();
@@ -481,6 +518,10 @@ void op_aplus(awg_ctx& c, MultiWS& w, const double* X, double* Yo) {
 
 // G0 = R0 X  (R0^T = [R^1T Y^1 | ... | R^NT Y^N])
 void op_r0(awg_ctx& c, MultiWS& w, const double* X) {
+  if (w.b > 1) {
+    bmm_restricted(c, w, w.dYt, X, w.maxm, w.maxns, w.flY, "Yt");
+    return;
+  }
   l_gather(c.sumns, c.subidx, X, w.b, w.Xs, c.s);
   bmm(w.dYt, c.N, w.maxm, w.maxns, false, 1.0, 0.0, w.b, c.s, w.flY, nullptr, "Yt");
 }
@@ -493,14 +534,19 @@ void op_r0t(awg_ctx& c, MultiWS& w, double* Yo, double beta, double alpha = 1.0)
 
 // Yo = H^NN X = sum_s R^sT P^s R^s X with P^s = D^s (A^s_+)^+ D^s (Definition of H^NN, Section 3.3)
 void op_hnn(awg_ctx& c, MultiWS& w, const double* X, double* Yo, bool f32) {
-  l_gather(c.sumns, c.subidx, X, w.b, w.Xs, c.s);
+  if (w.b == 1) l_gather(c.sumns, c.subidx, X, w.b, w.Xs, c.s);
   if (f32 && w.b == 1) {
     KScope kt("k_gemv_f32", c.s, 4.0 * c.sqtot, 2.0 * c.sqtot);
     hipLaunchKernelGGL(k_gemv_f32, dim3(cdiv(w.maxns, 64), c.N), dim3(256), 0, c.s, c.P32.p, c.d_sqoff.p,
                        c.subptr.p, w.Xs.p, w.Os.p);
     AWG_LAUNCH_CHECK();
   } else if (f32) {
-    gemm_mix_batched(w.dP32, c.N, w.b, w.maxns, 1.0, 0.0, c.s, w.flP);
+    restricted_product(c, w, "P32", X, [&](bool fused) {
+      if (fused) gemm_mix_batched(w.dP32, c.N, w.b, w.maxns, 1.0, 0.0, c.s, w.flP, X, c.subidx.p, c.subptr.p);
+      else gemm_mix_batched(w.dP32, c.N, w.b, w.maxns, 1.0, 0.0, c.s, w.flP);
+    });
+  } else if (w.b > 1) {
+    bmm_restricted(c, w, w.dP, X, w.maxns, w.maxns, w.flP, "P");
   } else {
     bmm(w.dP, c.N, w.maxns, w.maxns, false, 1.0, 0.0, w.b, c.s, w.flP, nullptr, "P");
   }

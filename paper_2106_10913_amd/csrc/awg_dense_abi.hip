@@ -60,6 +60,36 @@ int awg_dense_gemm(int32_t batch, int32_t m, int32_t n, int32_t k, int32_t trans
   });
 }
 
+int awg_dense_gemm_ex(int32_t batch, int32_t m, int32_t n, int32_t k, int32_t transA, int32_t transB,
+                      double alpha, const double* A, int32_t lda, int64_t strideA, const int32_t* arows,
+                      const double* B, int32_t ldb, int64_t strideB, double beta, double* C, int32_t ldc,
+                      int64_t strideC, int32_t variant, void* stream) {
+  if (batch <= 0 || m < 0 || n < 0 || k < 0 || !A || !B || !C || variant < -1 || variant > 4 ||
+      (arows && transA))
+    return AWG_ERR_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  return guarded(s, [&] {
+    std::vector<GemmDesc> h(batch);
+    std::vector<long> off(batch);
+    for (int b = 0; b < batch; ++b) {
+      h[b] = GemmDesc{A + (arows ? 0 : b * strideA), B + b * strideB, C + b * strideC, m, n, k, lda, ldb, ldc};
+      off[b] = (long)b * k;
+    }
+    DBuf<GemmDesc> d;
+    d.upload(h, s);
+    DBuf<long> doff;
+    doff.upload(off, s);
+    if (variant < 0 && arows)
+      gemm_batched_gather(d, A, arows, doff, batch, m, n, transB != 0, alpha, beta, s, 0.0, "dense_gather");
+    else if (variant < 0)
+      gemm_batched(d, batch, m, n, transA != 0, transB != 0, alpha, beta, false, s, 0.0, "dense");
+    else
+      gemm_batched_fixed(d, arows ? A : nullptr, arows, doff, batch, m, n, transA != 0, transB != 0, alpha, beta, s,
+                         variant);
+    AWG_HIP(hipStreamSynchronize(s));
+  });
+}
+
 int awg_dense_potrf(int32_t batch, int32_t n, double* A, int32_t lda, int64_t strideA, int32_t* info_host,
                     void* stream) {
   if (batch <= 0 || n <= 0 || lda < n || !A) return AWG_ERR_ARG;
@@ -152,7 +182,7 @@ int awg_dense_low_eigs(int32_t batch, int32_t n, double* A, int32_t lda, int64_t
 
 int awg_csr_spmm(int32_t n, int64_t nnz, const int64_t* rowptr, const int32_t* col, const double* val,
                  const double* X, double* Y, int32_t b, double alpha, double beta, int32_t variant, void* stream) {
-  if (n <= 0 || nnz < 0 || nnz >= (1LL << 31) || b <= 0 || variant < -1 || variant > 4 || !rowptr ||
+  if (n <= 0 || nnz < 0 || nnz >= (1LL << 31) || b <= 0 || variant < -1 || variant > 8 || !rowptr ||
       (nnz && (!col || !val)) || !X || !Y)
     return AWG_ERR_ARG;
   hipStream_t s = (hipStream_t)stream;

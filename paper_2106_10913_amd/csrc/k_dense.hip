@@ -24,6 +24,55 @@ struct DescArray {
   __device__ GemmDesc operator()(int b) const { return d[b]; }
 };
 
+// explicit descriptors whose A operands are row gathers of X (see
+// gemm_batched_gather)
+struct DescGather {
+  const GemmDesc* d;
+  const double* X;
+  const int* idx;
+  const long* off;
+  __device__ GemmDesc operator()(int b) const {
+    GemmDesc g = d[b];
+    g.A = X;
+    g.acol = idx + off[b];
+    return g;
+  }
+};
+
+template <class DF>
+struct gathers_a {
+  static constexpr bool value = false;
+};
+template <>
+struct gathers_a<DescGather> {
+  static constexpr bool value = true;
+};
+
+// Gathered A operands: the workgroup copies the first ACOL_LDS column indices
+// into LDS once, so the A loads of the k loop do not wait on a global index
+// load (columns beyond ACOL_LDS read the index from global memory).
+constexpr int ACOL_LDS = 2048;
+
+template <class DF>
+struct AcolTable {
+  int* s;   // LDS table (gathered instantiations only)
+  __device__ long operator()(const GemmDesc& d, int k) const {
+    if (!gathers_a<DF>::value) return (long)k * d.lda;
+    return (long)(k < ACOL_LDS ? s[k] : d.acol[k]) * d.lda;
+  }
+};
+
+// fills the LDS table; every thread of the workgroup must call it (barrier)
+template <class DF>
+__device__ inline AcolTable<DF> acol_table(int* s, const GemmDesc& d) {
+  if (gathers_a<DF>::value) {
+    const int kn = d.k < ACOL_LDS ? d.k : ACOL_LDS;
+    for (int k = threadIdx.x; k < kn; k += blockDim.x) s[k] = d.acol[k];
+    __syncthreads();
+  }
+  return AcolTable<DF>{s};
+}
+
 // trailing update of the Cholesky panel step at column j (panel width nb):
 // A[j+nb:, j+nb:] -= A[j+nb:, j:j+nb] * A[j+nb:, j:j+nb]^T
 struct CholUpdate {
@@ -128,6 +177,8 @@ __global__ __launch_bounds__(256) void k_gemm(DF df, double alpha, double beta, 
   if (lower && m0 + 64 <= n0) return;
   __shared__ double As[16][66];
   __shared__ double Bs[16][66];
+  __shared__ int s_acol[gathers_a<DF>::value ? ACOL_LDS : 1];
+  const AcolTable<DF> a_col = acol_table<DF>(s_acol, d);
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
   v4d acc[2][2];
@@ -144,7 +195,7 @@ __global__ __launch_bounds__(256) void k_gemm(DF df, double alpha, double beta, 
       if (!TA) { i = e & 63; kk = e >> 6; } else { kk = e & 15; i = e >> 4; }
       const int gi = m0 + i, gk = k0 + kk;
       double v = 0.0;
-      if (gi < d.m && gk < d.k) v = TA ? d.A[gk + (long)gi * d.lda] : d.A[gi + (long)gk * d.lda];
+      if (gi < d.m && gk < d.k) v = TA ? d.A[gk + (long)gi * d.lda] : d.A[gi + a_col(d, gk)];
       As[kk][i] = v;
     }
 #pragma unroll
@@ -197,6 +248,8 @@ __global__ __launch_bounds__(256) void k_gemm128(DF df, double alpha, double bet
   if (lower && m0 + 128 <= n0) return;
   __shared__ double As[2][16][132];
   __shared__ double Bs[2][16][132];
+  __shared__ int s_acol[gathers_a<DF>::value ? ACOL_LDS : 1];
+  const AcolTable<DF> a_col = acol_table<DF>(s_acol, d);
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int wm = (wave & 1) * 64, wn = (wave >> 1) * 64;
   v4d acc[4][4];
@@ -212,7 +265,7 @@ __global__ __launch_bounds__(256) void k_gemm128(DF df, double alpha, double bet
       int i, kk;
       if (!TA) { i = e & 127; kk = e >> 7; } else { kk = e & 15; i = e >> 4; }
       const int gi = m0 + i, gk = k0 + kk;
-      ra[r] = (gi < d.m && gk < d.k) ? (TA ? d.A[gk + (long)gi * d.lda] : d.A[gi + (long)gk * d.lda]) : 0.0;
+      ra[r] = (gi < d.m && gk < d.k) ? (TA ? d.A[gk + (long)gi * d.lda] : d.A[gi + a_col(d, gk)]) : 0.0;
       int j, kb;
       if (!TB) { kb = e & 15; j = e >> 4; } else { j = e & 127; kb = e >> 7; }
       const int gj = n0 + j, gkb = k0 + kb;
@@ -285,6 +338,8 @@ __global__ __launch_bounds__(512, 4) void k_gemm128w8(DF df, double alpha, doubl
   if (lower && m0 + 128 <= n0) return;
   __shared__ double As[2][16][132];
   __shared__ double Bs[2][16][132];
+  __shared__ int s_acol[gathers_a<DF>::value ? ACOL_LDS : 1];
+  const AcolTable<DF> a_col = acol_table<DF>(s_acol, d);
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int wm = (wave & 1) * 64, wn = (wave >> 1) * 32;
   v4d acc[4][2];
@@ -300,7 +355,7 @@ __global__ __launch_bounds__(512, 4) void k_gemm128w8(DF df, double alpha, doubl
       int i, kk;
       if (!TA) { i = e & 127; kk = e >> 7; } else { kk = e & 15; i = e >> 4; }
       const int gi = m0 + i, gk = k0 + kk;
-      ra[r] = (gi < d.m && gk < d.k) ? (TA ? d.A[gk + (long)gi * d.lda] : d.A[gi + (long)gk * d.lda]) : 0.0;
+      ra[r] = (gi < d.m && gk < d.k) ? (TA ? d.A[gk + (long)gi * d.lda] : d.A[gi + a_col(d, gk)]) : 0.0;
       int j, kb;
       if (!TB) { kb = e & 15; j = e >> 4; } else { j = e & 127; kb = e >> 7; }
       const int gj = n0 + j, gkb = k0 + kb;
@@ -360,6 +415,91 @@ __global__ __launch_bounds__(512, 4) void k_gemm128w8(DF df, double alpha, doubl
       }
 }
 
+// Skinny products (N small, untransposed operands): each wavefront computes a
+// 32 x 32 output block on its own, loading its A and B operands from global
+// memory straight into the MFMA register layout (no LDS, no barrier), with the
+// next k step's loads in flight while the current one is multiplied and the
+// gathered column indices fetched one step further ahead.  Same k order and
+// MFMA as the tile kernels (bit-identical results).
+template <class DF, int KB>
+__global__ __launch_bounds__(256) void k_gemm_skinny(DF df, double alpha, double beta) {
+  constexpr int T = KB / 4;   // groups of 4 k values per load batch
+  const GemmDesc d = df(blockIdx.z);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int m0 = blockIdx.x * 128 + wave * 32, n0 = blockIdx.y * 32;
+  if (m0 >= d.m || n0 >= d.n) return;
+  const int r16 = lane & 15, kq = lane >> 4;
+  v4d acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = (v4d){0.0, 0.0, 0.0, 0.0};
+  // column offsets of A for the k values k0 + 4 t + kq of a batch
+  auto colofs = [&](int k0, long* o) {
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+      const int k = k0 + 4 * t + kq;
+      o[t] = k < d.k ? (gathers_a<DF>::value ? (long)d.acol[k] * d.lda : (long)k * d.lda) : -1;
+    }
+  };
+  auto load = [&](int k0, const long* o, double* ra, double* rb) {
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+      const int k = k0 + 4 * t + kq;
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int m = m0 + 16 * q + r16, n = n0 + 16 * q + r16;
+        ra[2 * t + q] = (o[t] >= 0 && m < d.m) ? d.A[m + o[t]] : 0.0;
+        rb[2 * t + q] = (k < d.k && n < d.n) ? d.B[k + (long)n * d.ldb] : 0.0;
+      }
+    }
+  };
+  long oc[T], on[T];
+  double ca[2 * T], cb[2 * T], na[2 * T], nb[2 * T];
+  colofs(0, oc);
+  load(0, oc, ca, cb);
+  colofs(KB, on);
+  // k is taken in steps of 16 like the tile kernels; KB = 32 loads two steps at once
+  const int kend = (d.k + 15) & ~15;
+  for (int k0 = 0; k0 < kend; k0 += KB) {
+    const bool more = k0 + KB < kend;
+    if (more) {
+      load(k0 + KB, on, na, nb);
+      colofs(k0 + 2 * KB, on);
+    }
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+      if (KB == 32 && t == 4 && k0 + 16 >= kend) break;
+#pragma unroll
+      for (int qa = 0; qa < 2; ++qa)
+#pragma unroll
+        for (int qb = 0; qb < 2; ++qb)
+          acc[qa][qb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ca[2 * t + qa], cb[2 * t + qb], acc[qa][qb], 0, 0, 0);
+    }
+    if (more) {
+#pragma unroll
+      for (int r = 0; r < 2 * T; ++r) {
+        ca[r] = na[r];
+        cb[r] = nb[r];
+      }
+    }
+  }
+#pragma unroll
+  for (int qa = 0; qa < 2; ++qa)
+#pragma unroll
+    for (int qb = 0; qb < 2; ++qb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = m0 + qa * 16 + kq + 4 * r;
+        const int j = n0 + qb * 16 + r16;
+        if (i < d.m && j < d.n) {
+          double* cp = d.C + i + (long)j * d.ldc;
+          const double v = alpha * acc[qa][qb][r];
+          *cp = (beta == 0.0) ? v : v + beta * *cp;
+        }
+      }
+}
+
 // ---------------------------------------------------------------------------
 // mixed-precision GEMM for FP32 local operators: C (FP64) = alpha A B + beta C
 // with A FP64 (rounded to FP32 when staged in LDS), B FP32, FP32 MFMA
@@ -368,12 +508,29 @@ __global__ __launch_bounds__(512, 4) void k_gemm128w8(DF df, double alpha, doubl
 // ---------------------------------------------------------------------------
 typedef float v4f __attribute__((ext_vector_type(4)));
 
-__global__ __launch_bounds__(256) void k_gemm128_mix(const GemmDescMix* descs, double alpha, double beta) {
-  const GemmDescMix d = descs[blockIdx.z];
+__device__ inline GemmDescMix mix_desc(const GemmDescMix* descs, int z, const double* gX, const int* gidx,
+                                       const long* goff) {
+  GemmDescMix d = descs[z];
+  if (gX) {
+    d.A = gX;
+    d.acol = gidx + goff[z];
+  }
+  return d;
+}
+
+__global__ __launch_bounds__(256) void k_gemm128_mix(const GemmDescMix* descs, double alpha, double beta,
+                                                     const double* gX, const int* gidx, const long* goff) {
+  const GemmDescMix d = mix_desc(descs, blockIdx.z, gX, gidx, goff);
   const int m0 = blockIdx.x * 128, n0 = blockIdx.y * 128;
   if (m0 >= d.m || n0 >= d.n) return;
   __shared__ float As[2][16][132];
   __shared__ float Bs[2][16][132];
+  __shared__ int s_acol[ACOL_LDS];
+  if (d.acol) {
+    const int kn = d.k < ACOL_LDS ? d.k : ACOL_LDS;
+    for (int k = threadIdx.x; k < kn; k += blockDim.x) s_acol[k] = d.acol[k];
+    __syncthreads();
+  }
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int wm = (wave & 1) * 64, wn = (wave >> 1) * 64;
   v4f acc[4][4];
@@ -388,7 +545,7 @@ __global__ __launch_bounds__(256) void k_gemm128_mix(const GemmDescMix* descs, d
       const int e = tid + r * 256;
       const int i = e & 127, kk = e >> 7;
       const int gi = m0 + i, gk = k0 + kk;
-      ra[r] = (gi < d.m && gk < d.k) ? (float)d.A[gi + (long)gk * d.lda] : 0.f;
+      ra[r] = (gi < d.m && gk < d.k) ? (float)d.A[gi + (d.acol ? (long)(gk < ACOL_LDS ? s_acol[gk] : d.acol[gk]) : (long)gk) * d.lda] : 0.f;
       const int kb = e & 15, j = e >> 4;
       const int gj = n0 + j, gkb = k0 + kb;
       rb[r] = (gj < d.n && gkb < d.k) ? d.B[gkb + (long)gj * d.ldb] : 0.f;
@@ -446,12 +603,19 @@ __global__ __launch_bounds__(256) void k_gemm128_mix(const GemmDescMix* descs, d
 
 // eight-wavefront form of k_gemm128_mix (2 x 4 wavefronts of 64 x 32), same
 // k order (bit-identical results)
-__global__ __launch_bounds__(512, 4) void k_gemm128_mix_w8(const GemmDescMix* descs, double alpha, double beta) {
-  const GemmDescMix d = descs[blockIdx.z];
+__global__ __launch_bounds__(512, 4) void k_gemm128_mix_w8(const GemmDescMix* descs, double alpha, double beta,
+                                                           const double* gX, const int* gidx, const long* goff) {
+  const GemmDescMix d = mix_desc(descs, blockIdx.z, gX, gidx, goff);
   const int m0 = blockIdx.x * 128, n0 = blockIdx.y * 128;
   if (m0 >= d.m || n0 >= d.n) return;
   __shared__ float As[2][16][132];
   __shared__ float Bs[2][16][132];
+  __shared__ int s_acol[ACOL_LDS];
+  if (d.acol) {
+    const int kn = d.k < ACOL_LDS ? d.k : ACOL_LDS;
+    for (int k = threadIdx.x; k < kn; k += blockDim.x) s_acol[k] = d.acol[k];
+    __syncthreads();
+  }
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int wm = (wave & 1) * 64, wn = (wave >> 1) * 32;
   v4f acc[4][2];
@@ -466,7 +630,7 @@ __global__ __launch_bounds__(512, 4) void k_gemm128_mix_w8(const GemmDescMix* de
       const int e = tid + r * 512;
       const int i = e & 127, kk = e >> 7;
       const int gi = m0 + i, gk = k0 + kk;
-      ra[r] = (gi < d.m && gk < d.k) ? (float)d.A[gi + (long)gk * d.lda] : 0.f;
+      ra[r] = (gi < d.m && gk < d.k) ? (float)d.A[gi + (d.acol ? (long)(gk < ACOL_LDS ? s_acol[gk] : d.acol[gk]) : (long)gk) * d.lda] : 0.f;
       const int kb = e & 15, j = e >> 4;
       const int gj = n0 + j, gkb = k0 + kb;
       rb[r] = (gj < d.n && gkb < d.k) ? d.B[gkb + (long)gj * d.ldb] : 0.f;
@@ -522,16 +686,16 @@ __global__ __launch_bounds__(512, 4) void k_gemm128_mix_w8(const GemmDescMix* de
 }
 
 void gemm_mix_batched(const GemmDescMix* d_desc, int batch, int max_m, int max_n, double alpha, double beta,
-                      hipStream_t s, double flops) {
+                      hipStream_t s, double flops, const double* X, const int* idx, const long* off) {
   if (batch <= 0 || max_m <= 0 || max_n <= 0) return;
   const dim3 grid(cdiv(max_m, 128), cdiv(max_n, 128), batch);
   auto run = [&](int v) {
-    if (v == 1) hipLaunchKernelGGL(k_gemm128_mix_w8, grid, dim3(512), 0, s, d_desc, alpha, beta);
-    else hipLaunchKernelGGL(k_gemm128_mix, grid, dim3(256), 0, s, d_desc, alpha, beta);
+    if (v == 1) hipLaunchKernelGGL(k_gemm128_mix_w8, grid, dim3(512), 0, s, d_desc, alpha, beta, X, idx, off);
+    else hipLaunchKernelGGL(k_gemm128_mix, grid, dim3(256), 0, s, d_desc, alpha, beta, X, idx, off);
     AWG_LAUNCH_CHECK();
   };
-  const std::string key = "gemm_mix:P:m=" + std::to_string(max_m) + ":n=" + std::to_string(max_n) + ":batch=" +
-                          std::to_string(batch);
+  const std::string key = std::string(X ? "gemm_mix:Pg" : "gemm_mix:P") + ":m=" + std::to_string(max_m) +
+                          ":n=" + std::to_string(max_n) + ":batch=" + std::to_string(batch);
   int v = tune_lookup(key);
   if (v < 0 && beta == 0.0) v = tune_pick(key, 2, run, s);
   if (v < 0) v = 1;
@@ -546,6 +710,10 @@ const char* gemm_name<DescArray>(bool tA, bool tB) {
   return tA ? (tB ? "k_gemm<DescArray,T,T>" : "k_gemm<DescArray,T,N>") : (tB ? "k_gemm<DescArray,N,T>" : "k_gemm<DescArray,N,N>");
 }
 template <>
+const char* gemm_name<DescGather>(bool, bool tB) {
+  return tB ? "k_gemm<DescGather,N,T>" : "k_gemm<DescGather,N,N>";
+}
+template <>
 const char* gemm_name<CholUpdate>(bool, bool) { return "k_gemm<CholUpdate,N,T>"; }
 template <>
 const char* gemm_name<TrsmUpdate>(bool tA, bool) { return tA ? "k_gemm<TrsmUpdate,T,N>" : "k_gemm<TrsmUpdate,N,N>"; }
@@ -558,10 +726,20 @@ template <class DF>
 static bool use_big_tiles() { return false; }
 template <>
 bool use_big_tiles<DescArray>() { return true; }
+template <>
+bool use_big_tiles<DescGather>() { return true; }
 
 template <class DF>
 static void launch_tiles(DF df, int batch, int max_m, int max_n, bool tA, bool tB, double alpha, double beta,
                          bool lower, hipStream_t s, int variant) {
+  if (variant >= 3 && !tA && !tB && !lower) {
+    const dim3 grid(cdiv(max_m, 128), cdiv(max_n, 32), batch);
+    if (variant == 3) hipLaunchKernelGGL((k_gemm_skinny<DF, 16>), grid, dim3(256), 0, s, df, alpha, beta);
+    else hipLaunchKernelGGL((k_gemm_skinny<DF, 32>), grid, dim3(256), 0, s, df, alpha, beta);
+    AWG_LAUNCH_CHECK();
+    return;
+  }
+  if (variant >= 3) variant = 2;
   if (variant == 2) {
     dim3 grid(cdiv(max_m, 128), cdiv(max_n, 128), batch);
     if (!tA && !tB) hipLaunchKernelGGL((k_gemm128w8<DF, false, false>), grid, dim3(512), 0, s, df, alpha, beta, (int)lower);
@@ -600,14 +778,18 @@ static void launch_gemm(DF df, int batch, int max_m, int max_n, bool tA, bool tB
   if (batch <= 0 || max_m <= 0 || max_n <= 0) return;
   int variant = (use_big_tiles<DF>() && max_m >= 128) ? 1 : 0;
   if (use_big_tiles<DF>() && tag) {
-    const std::string key = std::string("gemm:") + tag + (tA ? ":T" : ":N") + (tB ? "T" : "N") + ":m=" +
+    const std::string key = std::string("gemm:") + tag + (gathers_a<DF>::value ? "g" : "") + (tA ? ":T" : ":N") +
+                            (tB ? "T" : "N") + ":m=" +
                             std::to_string(max_m) + ":n=" + std::to_string(max_n) + ":batch=" + std::to_string(batch);
     int v = tune_lookup(key);
+    // the skinny kernel is a candidate for untransposed products with N <= 64
+    const int nvar = (!tA && !tB && max_n <= 64) ? 5 : 3;
     if (v < 0 && beta == 0.0 && !lower)
-      v = tune_pick(key, 3, [&](int w) { launch_tiles(df, batch, max_m, max_n, tA, tB, alpha, beta, lower, s, w); }, s);
+      v = tune_pick(key, nvar, [&](int w) { launch_tiles(df, batch, max_m, max_n, tA, tB, alpha, beta, lower, s, w); }, s);
     if (v >= 0) variant = v;
   }
-  static const char* const prefix[3] = {"k_gemm", "k_gemm128", "k_gemm128w8"};
+  if (variant >= 3 && (tA || tB || lower)) variant = 2;
+  static const char* const prefix[5] = {"k_gemm", "k_gemm128", "k_gemm128w8", "k_gemm_skinny", "k_gemm_skinny32"};
   std::string nm = std::string(prefix[variant]) + (gemm_name<DF>(tA, tB) + 6);
   if (tag) nm += std::string(":") + tag;
   KScope kt(nm.c_str(), s, 0.0, flops);
@@ -626,6 +808,22 @@ void syr2k_panel_update(const MatDesc* d_mats, const double* V, const double* W,
 void gemm_batched(const GemmDesc* d_desc, int batch, int max_m, int max_n, bool transA, bool transB,
                   double alpha, double beta, bool lower, hipStream_t s, double flops, const char* tag) {
   launch_gemm(DescArray{d_desc}, batch, max_m, max_n, transA, transB, alpha, beta, lower, s, flops, tag);
+}
+
+void gemm_batched_fixed(const GemmDesc* d_desc, const double* X, const int* idx, const long* off, int batch,
+                        int max_m, int max_n, bool transA, bool transB, double alpha, double beta, hipStream_t s,
+                        int variant) {
+  if (batch <= 0 || max_m <= 0 || max_n <= 0) return;
+  if (X)
+    launch_tiles(DescGather{d_desc, X, idx, off}, batch, max_m, max_n, false, transB, alpha, beta, false, s, variant);
+  else
+    launch_tiles(DescArray{d_desc}, batch, max_m, max_n, transA, transB, alpha, beta, false, s, variant);
+}
+
+void gemm_batched_gather(const GemmDesc* d_desc, const double* X, const int* idx, const long* off, int batch,
+                         int max_m, int max_n, bool transB, double alpha, double beta, hipStream_t s, double flops,
+                         const char* tag) {
+  launch_gemm(DescGather{d_desc, X, idx, off}, batch, max_m, max_n, false, transB, alpha, beta, false, s, flops, tag);
 }
 
 // ---------------------------------------------------------------------------

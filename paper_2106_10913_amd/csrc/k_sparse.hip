@@ -237,6 +237,129 @@ __global__ __launch_bounds__(256) void k_spmm_tiled(int n, const int* __restrict
   *y = (beta == 0.0) ? alpha * acc : alpha * acc + beta * *y;
 }
 
+// One wavefront per row and 128 columns, two per lane (16-byte accesses);
+// the row index is made wave-uniform so that the row pointers, column indices
+// and values come in through scalar loads, leaving one vector load per
+// nonzero.  Blocks of 4 rows are ordered slab-major; with REMAP each XCD
+// sweeps one contiguous row range (as in k_spmm_tiled).  CSR order per row.
+template <bool REMAP>
+__global__ __launch_bounds__(256) void k_spmm_w2(int n, const int* __restrict__ rowptr, const int* __restrict__ col,
+                                                 const double* __restrict__ val, const double2* __restrict__ X,
+                                                 double2* Y, int b2, double alpha, double beta, int nrb) {
+  int L = blockIdx.x;
+  if (REMAP) {
+    const int nb = gridDim.x, q = nb >> 3, r = nb & 7, x = L & 7, j = L >> 3;
+    L = x * q + min(x, r) + j;
+  }
+  const int slab = L / nrb, rb = L - slab * nrb;
+  const int i = __builtin_amdgcn_readfirstlane(rb * 4 + (int)(threadIdx.x >> 6));
+  const int c = slab * 64 + (int)(threadIdx.x & 63);
+  if (i >= n || c >= b2) return;
+  double ax = 0.0, ay = 0.0;
+  const int pe = rowptr[i + 1];
+  int p = rowptr[i];
+  for (; p + 4 <= pe; p += 4) {
+    const int j0 = col[p], j1 = col[p + 1], j2 = col[p + 2], j3 = col[p + 3];
+    const double v0 = val[p], v1 = val[p + 1], v2 = val[p + 2], v3 = val[p + 3];
+    const double2 x0 = X[(long)j0 * b2 + c], x1 = X[(long)j1 * b2 + c], x2 = X[(long)j2 * b2 + c],
+                  x3 = X[(long)j3 * b2 + c];
+    ax += v0 * x0.x;
+    ay += v0 * x0.y;
+    ax += v1 * x1.x;
+    ay += v1 * x1.y;
+    ax += v2 * x2.x;
+    ay += v2 * x2.y;
+    ax += v3 * x3.x;
+    ay += v3 * x3.y;
+  }
+  for (; p < pe; ++p) {
+    const double v = val[p];
+    const double2 x = X[(long)col[p] * b2 + c];
+    ax += v * x.x;
+    ay += v * x.y;
+  }
+  double2* y = Y + (long)i * b2 + c;
+  double2 o;
+  if (beta == 0.0) {
+    o.x = alpha * ax;
+    o.y = alpha * ay;
+  } else {
+    const double2 yo = *y;
+    o.x = alpha * ax + beta * yo.x;
+    o.y = alpha * ay + beta * yo.y;
+  }
+  *y = o;
+}
+
+// k_spmm_w2 with 256 columns per wavefront (two double2 per lane, 64 apart):
+// twice the loads in flight per row for the same scalar index traffic.
+template <bool REMAP>
+__global__ __launch_bounds__(256) void k_spmm_w4(int n, const int* __restrict__ rowptr, const int* __restrict__ col,
+                                                 const double* __restrict__ val, const double2* __restrict__ X,
+                                                 double2* Y, int b2, double alpha, double beta, int nrb) {
+  int L = blockIdx.x;
+  if (REMAP) {
+    const int nb = gridDim.x, q = nb >> 3, r = nb & 7, x = L & 7, j = L >> 3;
+    L = x * q + min(x, r) + j;
+  }
+  const int slab = L / nrb, rb = L - slab * nrb;
+  const int i = __builtin_amdgcn_readfirstlane(rb * 4 + (int)(threadIdx.x >> 6));
+  const int c0 = slab * 128 + (int)(threadIdx.x & 63), c1 = c0 + 64;
+  if (i >= n || c0 >= b2) return;
+  const bool two = c1 < b2;
+  double a0x = 0.0, a0y = 0.0, a1x = 0.0, a1y = 0.0;
+  const int pe = rowptr[i + 1];
+  int p = rowptr[i];
+  for (; p + 2 <= pe; p += 2) {
+    const int j0 = col[p], j1 = col[p + 1];
+    const double v0 = val[p], v1 = val[p + 1];
+    const double2* r0 = X + (long)j0 * b2;
+    const double2* r1 = X + (long)j1 * b2;
+    const double2 x00 = r0[c0], x10 = r1[c0];
+    const double2 x01 = two ? r0[c1] : double2{0.0, 0.0};
+    const double2 x11 = two ? r1[c1] : double2{0.0, 0.0};
+    a0x += v0 * x00.x;
+    a0y += v0 * x00.y;
+    a1x += v0 * x01.x;
+    a1y += v0 * x01.y;
+    a0x += v1 * x10.x;
+    a0y += v1 * x10.y;
+    a1x += v1 * x11.x;
+    a1y += v1 * x11.y;
+  }
+  for (; p < pe; ++p) {
+    const double v = val[p];
+    const double2* r0 = X + (long)col[p] * b2;
+    const double2 x0 = r0[c0];
+    const double2 x1 = two ? r0[c1] : double2{0.0, 0.0};
+    a0x += v * x0.x;
+    a0y += v * x0.y;
+    a1x += v * x1.x;
+    a1y += v * x1.y;
+  }
+  double2* y = Y + (long)i * b2;
+  double2 o;
+  if (beta == 0.0) {
+    o.x = alpha * a0x;
+    o.y = alpha * a0y;
+  } else {
+    const double2 yo = y[c0];
+    o.x = alpha * a0x + beta * yo.x;
+    o.y = alpha * a0y + beta * yo.y;
+  }
+  y[c0] = o;
+  if (!two) return;
+  if (beta == 0.0) {
+    o.x = alpha * a1x;
+    o.y = alpha * a1y;
+  } else {
+    const double2 yo = y[c1];
+    o.x = alpha * a1x + beta * yo.x;
+    o.y = alpha * a1y + beta * yo.y;
+  }
+  y[c1] = o;
+}
+
 // Xs[p, :] = X[sub_idx[p], :]  (row copies)
 __global__ void k_gather(long tot, const int* sub_idx, const double* X, int b, double* Xs) {
   const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -251,24 +374,26 @@ __global__ void k_gather(long tot, const int* sub_idx, const double* X, int b, d
 // index data are loaded once per wavefront.
 __global__ __launch_bounds__(256) void k_gather2(long tot, const int* __restrict__ sub_idx,
                                                  const double2* __restrict__ X, int b2, double2* Xs, int nchunk) {
-  const long w = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const long w = (long)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const long p = w / nchunk;
   if (p >= tot) return;
   const int c = (int)(w - p * nchunk) * 64 + (threadIdx.x & 63);
+  const long src = (long)sub_idx[p] * b2;   // wave-uniform: a scalar load
   if (c >= b2) return;
-  Xs[p * b2 + c] = X[(long)sub_idx[p] * b2 + c];
+  Xs[p * b2 + c] = X[src + c];
 }
 
 __global__ __launch_bounds__(256) void k_scatter2(int n, const int* __restrict__ inv_ptr, const int* __restrict__ inv_sub,
                                                   const int* __restrict__ inv_loc, const long* __restrict__ sub_ptr,
                                                   const double2* __restrict__ Zs, int b2, double2* Y, double alpha,
                                                   double beta, int nchunk) {
-  const long w = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const long w = (long)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const long i = w / nchunk;
   if (i >= n) return;
   const int c = (int)(w - i * nchunk) * 64 + (threadIdx.x & 63);
   if (c >= b2) return;
   double ax = 0.0, ay = 0.0;
+  // the copy list of row i is wave-uniform (scalar loads)
   for (int q = inv_ptr[i]; q < inv_ptr[i + 1]; ++q) {
     const double2 z = Zs[(sub_ptr[inv_sub[q]] + inv_loc[q]) * b2 + c];
     ax += z.x;
@@ -516,8 +641,10 @@ void l_extract(int N, const long* sub_ptr, const int* sub_idx, const int* rowptr
   AWG_LAUNCH_CHECK();
 }
 // SpMM launch variants: 0 = one row x 64 columns per wavefront in hardware
-// order (k_spmm_rm); 1..4 = k_spmm_tiled<SLAB, REMAP>
-constexpr int SPMM_VARIANTS = 5;
+// order (k_spmm_rm); 1..4 = k_spmm_tiled<SLAB, REMAP>; 5, 6 = k_spmm_w2 with
+// and without the XCD renumbering, 7, 8 = k_spmm_w4 with and without it
+// (5..8: even b and 16-byte aligned X, Y only)
+constexpr int SPMM_VARIANTS = 9;
 
 void spmm_variant(int v, int n, const int* rowptr, const int* col, const double* val, const double* X, double* Y,
                   int b, double alpha, double beta, hipStream_t s) {
@@ -527,7 +654,22 @@ void spmm_variant(int v, int n, const int* rowptr, const int* col, const double*
     hipLaunchKernelGGL(kern, dim3(nrb * cdiv(b, slab)), dim3(256), 0, s, n, rowptr, col, val, X, Y, b, alpha, beta,
                        nrb);
   };
+  if (v >= 5 && ((b & 1) || ((uintptr_t)X & 15) || ((uintptr_t)Y & 15))) v = 1;
+  auto w2 = [&](auto kern) {
+    const int nrb = (int)cdiv(n, 4), b2 = b / 2;
+    hipLaunchKernelGGL(kern, dim3(nrb * cdiv(b2, 64)), dim3(256), 0, s, n, rowptr, col, val, (const double2*)X,
+                       (double2*)Y, b2, alpha, beta, nrb);
+  };
+  auto w4 = [&](auto kern) {
+    const int nrb = (int)cdiv(n, 4), b2 = b / 2;
+    hipLaunchKernelGGL(kern, dim3(nrb * cdiv(b2, 128)), dim3(256), 0, s, n, rowptr, col, val, (const double2*)X,
+                       (double2*)Y, b2, alpha, beta, nrb);
+  };
   switch (v) {
+    case 7: w4(k_spmm_w4<true>); break;
+    case 8: w4(k_spmm_w4<false>); break;
+    case 5: w2(k_spmm_w2<true>); break;
+    case 6: w2(k_spmm_w2<false>); break;
     case 1: tiled(k_spmm_tiled<64, true>, 64); break;
     case 2: tiled(k_spmm_tiled<32, true>, 32); break;
     case 3: tiled(k_spmm_tiled<16, true>, 16); break;

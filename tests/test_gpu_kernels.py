@@ -48,6 +48,62 @@ def test_gemm(gpu_lib, tA, tB, mnk):
     assert np.max(np.abs(out - ref)) <= 1e-13 * max(1.0, np.max(np.abs(ref))) * k
 
 
+@pytest.mark.parametrize("mnk", [(300, 30, 200), (130, 64, 2100), (257, 17, 33), (64, 100, 70), (1, 5, 3),
+                                 (200, 1, 129), (150, 40, 16), (129, 33, 48)])
+def test_gemm_variants_bit_identical(gpu_lib, mnk):
+    """Every launch variant the autotuner may pick (64x64 and 128x128 tiles,
+    4 or 8 wavefronts, the LDS-free skinny kernel) gives the same bits, for
+    plain and row-gathered A operands (k > 2048 exercises the gathered index
+    reads beyond the LDS table); the gathered form equals the product with
+    the explicitly gathered matrix, bit for bit."""
+    import torch
+    m, n, k = mnk
+    rng = np.random.default_rng(m + 31 * n + 7 * k)
+    batch = 3
+    rows = 2 * k + 5
+    X = rng.standard_normal((rows, m))
+    idx = rng.integers(0, rows, size=(batch, k)).astype(np.int32)
+    B = rng.standard_normal((batch, k, n))
+    C0 = rng.standard_normal((batch, m, n))
+    Xd = torch.as_tensor(X, device="cuda")
+    Id = torch.as_tensor(idx, device="cuda")
+    Ag = np.stack([X[idx[b]].T for b in range(batch)])          # (batch, m, k)
+    ref = np.stack([-0.5 * (Ag[b] @ B[b]) + 2.0 * C0[b] for b in range(batch)])
+    outs = []
+    for v in range(5):
+        for gathered in (False, True):
+            Cd = to_dev(C0)
+            if gathered:
+                gpu_lib.dense_gemm_ex(Xd, to_dev(B), Cd, alpha=-0.5, beta=2.0, variant=v, arows=Id)
+            else:
+                gpu_lib.dense_gemm_ex(to_dev(Ag), to_dev(B), Cd, alpha=-0.5, beta=2.0, variant=v)
+            outs.append(from_dev(Cd))
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+    assert np.max(np.abs(outs[0] - ref)) <= 1e-13 * max(1.0, np.max(np.abs(ref))) * k
+    # transposed operands: variant 3 falls back to the 8-wavefront tiles
+    for tA, tB in [(True, False), (False, True), (True, True)]:
+        A = rng.standard_normal((batch, k, m) if tA else (batch, m, k))
+        Bt = rng.standard_normal((batch, n, k) if tB else (batch, k, n))
+        res = []
+        for v in range(5):
+            Cd = to_dev(C0)
+            gpu_lib.dense_gemm_ex(to_dev(A), to_dev(Bt), Cd, alpha=1.0, beta=0.0, transA=tA, transB=tB, variant=v)
+            res.append(from_dev(Cd))
+        for o in res[1:]:
+            assert np.array_equal(o, res[0])
+
+
+def test_gemm_ex_rejects_bad_arguments(gpu_lib):
+    import torch
+    from paper_2106_10913_amd.awg import AWGError
+    A = torch.zeros((1, 4, 4), dtype=torch.float64, device="cuda")
+    idx = torch.zeros((1, 4), dtype=torch.int32, device="cuda")
+    for kw in [dict(variant=5), dict(variant=-2), dict(transA=True, arows=idx)]:
+        with pytest.raises(AWGError):
+            gpu_lib.dense_gemm_ex(A, A, A.clone(), **kw)
+
+
 @pytest.mark.parametrize("n", [1, 31, 33, 64, 100, 257])
 def test_potrf(gpu_lib, n):
     rng = np.random.default_rng(n)
@@ -116,7 +172,7 @@ def test_low_eigs_against_eigh(gpu_lib, n):
         assert np.max(np.abs(Pg - Pr), initial=0.0) <= 1e-8
 
 
-@pytest.mark.parametrize("b", [2, 17, 64, 130])
+@pytest.mark.parametrize("b", [2, 17, 64, 130, 300])
 def test_csr_spmm_variants_bit_identical(gpu_lib, b):
     """Every SpMM launch variant (and the autotuned one) gives the same bits,
     within rounding of the exact product; beta != 0 accumulates."""
@@ -134,7 +190,7 @@ def test_csr_spmm_variants_bit_identical(gpu_lib, b):
     Xd = torch.as_tensor(X, device="cuda")
     ref = -0.5 * (A @ X) + 2.0 * Y0
     outs = []
-    for v in [-1, 0, 1, 2, 3, 4]:
+    for v in [-1] + list(range(9)):
         Yd = torch.as_tensor(Y0, device="cuda")
         gpu_lib.csr_spmm(rp, ci, va, Xd, Yd, alpha=-0.5, beta=2.0, variant=v)
         outs.append(Yd.cpu().numpy())
@@ -147,4 +203,4 @@ def test_csr_spmm_variants_bit_identical(gpu_lib, b):
     assert np.max(np.abs(Yd.cpu().numpy() - A @ X)) <= 1e-13 * np.max(np.abs(A @ X))
     rep = gpu_lib.tune_report()
     key = f"spmm:n={n}:nnz={A.nnz}:b={b}"
-    assert key in rep and 0 <= rep[key]["variant"] <= 4 and len(rep[key]["us"]) == 5
+    assert key in rep and 0 <= rep[key]["variant"] <= 8 and len(rep[key]["us"]) == 9
