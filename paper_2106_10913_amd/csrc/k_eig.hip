@@ -59,118 +59,57 @@ struct TrdWork {
   }
 };
 
-// column j = p0 + jj: update from the panel, reflector, d_j, e_j, tau_j
-__global__ __launch_bounds__(256) void k_trd_col(const MatDesc* mats, int p0, int jj, double* dd, double* ee,
-                                                 double* tau, const long* off, double* work, long sumns) {
-  const MatDesc M = mats[blockIdx.x];
-  const int n = M.n;
-  const int j = p0 + jj;
-  if (j > n - 3) return;
-  __shared__ double sh[4];
-  const long o = off[blockIdx.x];
-  TrdWork T(work, sumns, o);
-  double* col = M.A + (long)j * M.ld;
-  // rows j..n-1 of column j minus V[:, t] W[j, t] + W[:, t] V[j, t], t < jj
-  double ss = 0.0;
-  for (int i = j + threadIdx.x; i < n; i += 256) {
-    double a = col[i];
-    for (int t = 0; t < jj; ++t) a -= T.V[i + (long)t * n] * T.W[j + (long)t * n] + T.W[i + (long)t * n] * T.V[j + (long)t * n];
-    col[i] = a;
-    if (i >= j + 2) ss += a * a;
-  }
-  ss = block_sum256(ss, sh);
-  if (threadIdx.x == 0) {
-    const double dkk = col[j], alpha = col[j + 1];
-    dd[o + j] = dkk;
-    if (ss == 0.0) {
-      ee[o + j] = alpha;
-      tau[o + j] = 0.0;
-      sh[0] = 0.0;
-    } else {
-      const double beta = -copysign(sqrt(alpha * alpha + ss), alpha);
-      tau[o + j] = (beta - alpha) / beta;
-      ee[o + j] = beta;
-      sh[0] = 1.0 / (alpha - beta);
-    }
-  }
-  __syncthreads();
-  const double scale = sh[0];
-  for (int i = j + 1 + threadIdx.x; i < n; i += 256) {
-    const double v = (i == j + 1) ? 1.0 : col[i] * scale;
-    col[i] = v;
-    T.V[i + (long)jj * n] = v;
-  }
-  for (int i = threadIdx.x; i <= j; i += 256) T.V[i + (long)jj * n] = 0.0;
-}
-
 // p = A22 v reading only the lower triangle of A22 = A[j+1:, j+1:] (the
 // trailing matrix is kept up to date in its lower triangle only).  A22 is cut
-// into 64 x 64 tiles (I, C), I >= C, one workgroup each; an off-diagonal tile
-// gives the row part A_IC v_C and, by symmetry, the column part A_IC^T v_I;
-// a diagonal tile is mirrored in LDS.  Partial vectors go to
-// part[(I * ntmax + C) * 64 + r] and are summed over C in a fixed order by
-// k_trd_w (deterministic).
+// into 64 x 64 tiles (I, C), I >= C; an off-diagonal tile gives the row part
+// A_IC v_C and, by symmetry, the column part A_IC^T v_I; a diagonal tile is
+// mirrored in LDS.  Partial vectors go to part[(I * ntmax + C) * 64 + r] and
+// are summed over C in a fixed order by k_trd_wx (deterministic).
 constexpr int SYMV_T = 64;
 
-__global__ __launch_bounds__(256) void k_trd_symv_lo(const MatDesc* mats, int p0, int jj, const long* off,
-                                                     double* work, long sumns, double* part, int ntmax) {
-  const MatDesc M = mats[blockIdx.y];
+constexpr int TRD_RB = 256;     // rows per workgroup
+constexpr int TRD_YCH = 512;    // rows per workgroup of the dot products
+
+// partial dot products y[q] = W[:, q]^T v, y[NB + q] = V[:, q]^T v over chunk
+// ch of the rows below j (TRD_YCH rows; matrix b of the batch)
+__device__ inline void trd_wy_chunk(const MatDesc& M, int b, int ch, int p0, int jj, const long* off, double* work,
+                                    long sumns, double* ypart, int nchmax) {
   const int n = M.n;
   const int j = p0 + jj;
-  if (j > n - 3) return;
-  const int base = j + 1, m = n - base;
-  const int nt = (m + SYMV_T - 1) / SYMV_T;
-  const int t = blockIdx.x;
-  if (t >= nt * (nt + 1) / 2) return;
-  int I = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
-  while ((I + 1) * (I + 2) / 2 <= t) ++I;
-  while (I * (I + 1) / 2 > t) --I;
-  const int C = t - I * (I + 1) / 2;
-  TrdWork T(work, sumns, off[blockIdx.y]);
-  const double* v = T.V + (long)jj * n;
-  __shared__ double L[SYMV_T][SYMV_T + 1];
-  __shared__ double vr[SYMV_T], vc[SYMV_T];
-  __shared__ double red[4][SYMV_T];
-  const int tid = threadIdx.x;
-  const int r0 = base + I * SYMV_T, c0 = base + C * SYMV_T;
-  for (int e = tid; e < SYMV_T * SYMV_T; e += 256) {
-    const int r = e % SYMV_T, c = e / SYMV_T;
-    const int gr = r0 + r, gc = c0 + c;
-    double a = 0.0;
-    if (gr < n && gc < n && (I != C || r >= c)) a = M.A[gr + (long)gc * M.ld];
-    L[r][c] = a;
-  }
-  if (tid < SYMV_T) {
-    vr[tid] = (r0 + tid < n) ? v[r0 + tid] : 0.0;
-    vc[tid] = (c0 + tid < n) ? v[c0 + tid] : 0.0;
-  }
-  __syncthreads();
-  if (I == C) {
-    for (int e = tid; e < SYMV_T * SYMV_T; e += 256) {
-      const int r = e % SYMV_T, c = e / SYMV_T;
-      if (r < c) L[r][c] = L[c][r];
+  if (j > n - 3 || ch * TRD_YCH >= n - j - 1) return;
+  TrdWork T(work, sumns, off[b]);
+  const double* __restrict__ v = T.V + (long)jj * n;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int r0 = j + 1 + ch * TRD_YCH, r1 = min(n, r0 + TRD_YCH);
+  constexpr int QW = 2 * TRD_NB / 4;
+  double acc[QW];
+#pragma unroll
+  for (int k = 0; k < QW; ++k) acc[k] = 0.0;
+  for (int i = r0 + lane; i < r1; i += 64) {
+    const double vi = v[i];
+#pragma unroll
+    for (int k = 0; k < QW; ++k) {
+      const int q = wid + 4 * k;
+      if (q < 2 * jj) {
+        const double* __restrict__ c = (q < jj) ? T.W + (long)q * n : T.V + (long)(q - jj) * n;
+        acc[k] += c[i] * vi;
+      }
     }
-    __syncthreads();
   }
-  const int lane = tid & 63, g = tid >> 6;
-  double* out = part + (long)blockIdx.y * ntmax * ntmax * SYMV_T;
-  double a = 0.0;
-  for (int c = g; c < SYMV_T; c += 4) a += L[lane][c] * vc[c];
-  red[g][lane] = a;
-  __syncthreads();
-  if (g == 0) out[((long)I * ntmax + C) * SYMV_T + lane] = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
-  if (I == C) return;
-  __syncthreads();
-  a = 0.0;
-  for (int r = g; r < SYMV_T; r += 4) a += L[r][lane] * vr[r];
-  red[g][lane] = a;
-  __syncthreads();
-  if (g == 0) out[((long)C * ntmax + I) * SYMV_T + lane] = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
+  double* yp = ypart + ((long)b * nchmax + ch) * 2 * TRD_NB;
+#pragma unroll
+  for (int k = 0; k < QW; ++k) {
+    const int q = wid + 4 * k;
+    if (q < 2 * jj) {
+      const double a = wave_sum(acc[k]);
+      if (lane == 0) yp[q < jj ? q : TRD_NB + (q - jj)] = a;
+    }
+  }
 }
 
-// Pipelined form of k_trd_symv_lo: a workgroup walks tiles t = blockIdx.x,
-// blockIdx.x + gridDim.x, ... of its matrix and loads the next tile into
-// registers while it works on the current one in LDS (loads stay in flight).
+// A workgroup walks tiles t = blockIdx.x, blockIdx.x + gxs, ... of its
+// matrix and loads the next tile into registers while it works on the current
+// one in LDS (loads stay in flight).
 __device__ inline void symv_tile_decode(int t, int& I, int& C) {
   I = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
   while ((I + 1) * (I + 2) / 2 <= t) ++I;
@@ -178,9 +117,16 @@ __device__ inline void symv_tile_decode(int t, int& I, int& C) {
   C = t - I * (I + 1) / 2;
 }
 
+// Workgroups gxs and up of the launch compute the panel dot products of the
+// column (trd_wy_chunk) instead, which do not depend on the product.
 __global__ __launch_bounds__(256) void k_trd_symv_pipe(const MatDesc* mats, int p0, int jj, const long* off,
-                                                       double* work, long sumns, double* part, int ntmax) {
+                                                       double* work, long sumns, double* part, int ntmax, int gxs,
+                                                       double* ypart, int nchmax) {
   const MatDesc M = mats[blockIdx.y];
+  if ((int)blockIdx.x >= gxs) {
+    trd_wy_chunk(M, blockIdx.y, blockIdx.x - gxs, p0, jj, off, work, sumns, ypart, nchmax);
+    return;
+  }
   const int n = M.n;
   const int j = p0 + jj;
   if (j > n - 3) return;
@@ -223,7 +169,7 @@ __global__ __launch_bounds__(256) void k_trd_symv_pipe(const MatDesc* mats, int 
       vr[tid] = (r0 + tid < n) ? v[r0 + tid] : 0.0;
       vc[tid] = (c0 + tid < n) ? v[c0 + tid] : 0.0;
     }
-    const int tn = t + gridDim.x;
+    const int tn = t + gxs;
     if (tn < ntiles) load(tn, cur);      // next tile in flight during the work below
     __syncthreads();
     if (I == C) {
@@ -253,97 +199,70 @@ __global__ __launch_bounds__(256) void k_trd_symv_pipe(const MatDesc* mats, int 
   }
 }
 
-// w = tau (p - V (W^T v) - W (V^T v)); w += -tau/2 (w.v) v   (stored as W[:, jj]).
-// The 2 jj dot products are spread over the four wavefronts (one vector at a
-// time per wavefront, lanes over rows); the update loops over rows.
-__global__ __launch_bounds__(256) void k_trd_w(const MatDesc* mats, int p0, int jj, const double* tau,
-                                               const long* off, double* work, long sumns, const double* part,
-                                               int ntmax) {
-  const MatDesc M = mats[blockIdx.x];
-  const int n = M.n;
-  const int j = p0 + jj;
-  if (j > n - 3) return;
-  __shared__ double sh[4];
-  __shared__ double y[2 * TRD_NB];
-  const long o = off[blockIdx.x];
-  TrdWork T(work, sumns, o);
-  const double* __restrict__ v = T.V + (long)jj * n;
-  double* __restrict__ w = T.W + (long)jj * n;
-  const double t = tau[o + j];
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  // y[q] = W[:, q]^T v and y[NB + q] = V[:, q]^T v over rows j+1..n-1: wavefront
-  // wid takes q = wid, wid + 4, ... (at most 2 NB / 4), one pass over the rows
-  // with independent loads for all its q
-  {
-    constexpr int QW = 2 * TRD_NB / 4;
-    double acc[QW];
-#pragma unroll
-    for (int k = 0; k < QW; ++k) acc[k] = 0.0;
-    for (int i = j + 1 + lane; i < n; i += 64) {
-      const double vi = v[i];
-#pragma unroll
-      for (int k = 0; k < QW; ++k) {
-        const int q = wid + 4 * k;
-        if (q < 2 * jj) {
-          const double* __restrict__ col = (q < jj) ? T.W + (long)q * n : T.V + (long)(q - jj) * n;
-          acc[k] += col[i] * vi;
-        }
-      }
-    }
-#pragma unroll
-    for (int k = 0; k < QW; ++k) {
-      const int q = wid + 4 * k;
-      if (q < 2 * jj) {
-        const double a = wave_sum(acc[k]);
-        if (lane == 0) y[q < jj ? q : TRD_NB + (q - jj)] = a;
-      }
-    }
-  }
-  __syncthreads();
-  double sv = 0.0;
-  const double* pp = part + (long)blockIdx.x * ntmax * ntmax * SYMV_T;
-  const int nt = (n - j - 1 + SYMV_T - 1) / SYMV_T;
-  for (int i = j + 1 + threadIdx.x; i < n; i += 256) {
-    const int I = (i - j - 1) / SYMV_T, r = (i - j - 1) % SYMV_T;
-    double x = 0.0;
-    for (int C = 0; C < nt; ++C) x += pp[((long)I * ntmax + C) * SYMV_T + r];
-    for (int q = 0; q < jj; ++q) x -= T.V[i + (long)q * n] * y[q] + T.W[i + (long)q * n] * y[TRD_NB + q];
-    x *= t;
-    w[i] = x;
-    sv += x * v[i];
-  }
-  sv = block_sum256(sv, sh);
-  const double alpha = -0.5 * t * sv;
-  for (int i = j + 1 + threadIdx.x; i < n; i += 256) w[i] += alpha * v[i];
-  for (int i = threadIdx.x; i <= j; i += 256) w[i] = 0.0;
-}
-
 // ---------------------------------------------------------------------------
-// Row-parallel forms of the per-column steps (many workgroups per matrix;
-// the single-workgroup kernels above leave most of the GPU idle when the
-// batch is small).  Reductions go through per-block partial sums added in a
-// fixed order.
+// Row-parallel per-column steps (many workgroups per matrix).  Reductions go
+// through per-block partial sums added in a fixed order.
 // ---------------------------------------------------------------------------
-constexpr int TRD_RB = 256;     // rows per workgroup
-constexpr int TRD_YCH = 512;    // rows per workgroup of the dot products
 
 // column j updated from the panel (rows j..n-1); partial sums of squares of
-// rows >= j + 2; block 0 keeps d_j = A[j][j] and alpha = A[j+1][j]
+// rows >= j + 2; block 0 keeps d_j = A[j][j] and alpha = A[j+1][j].
+// pend: W[:, jj-1] still lacks its final term w += -tau/2 (w.v) v
+// (k_trd_wfix); it is added here, to the rows below j, before use (row j of
+// that column is never read again, so it is corrected on the fly only).  The
+// correction is also made for a matrix whose last reflector was column j-1.
 __global__ __launch_bounds__(256) void k_trd_cu(const MatDesc* mats, int p0, int jj, const long* off, double* work,
-                                                long sumns, double* red, double* aux, int nblkmax) {
+                                                long sumns, double* red, double* aux, int nblkmax, int pend,
+                                                const double* tau, const double* svpart) {
   const MatDesc M = mats[blockIdx.y];
   const int n = M.n;
   const int j = p0 + jj;
-  if (j > n - 3 || (int)blockIdx.x * TRD_RB >= n - j) return;
+  const bool active = j <= n - 3;
+  const bool fix = pend && j - 1 <= n - 3;
+  if ((!active && !fix) || (int)blockIdx.x * TRD_RB >= n - j) return;
   __shared__ double sh[4];
-  TrdWork T(work, sumns, off[blockIdx.y]);
-  double* col = M.A + (long)j * M.ld;
+  __shared__ double alpha_s;
+  const long o = off[blockIdx.y];
+  TrdWork T(work, sumns, o);
+  double alpha = 0.0;
+  if (fix) {
+    if (threadIdx.x == 0) {
+      const int nb = (n - j + TRD_RB - 1) / TRD_RB;    // blocks of k_trd_wx for column j - 1
+      double sv = 0.0;
+      for (int b = 0; b < nb; ++b) sv += svpart[(long)blockIdx.y * nblkmax + b];
+      alpha_s = -0.5 * tau[o + j - 1] * sv;
+    }
+    __syncthreads();
+    alpha = alpha_s;
+  }
   const int i = j + blockIdx.x * TRD_RB + threadIdx.x;
+  const int tp = jj - 1;            // the pending column
+  double* wp = T.W + (long)tp * n;
+  const double* vp = T.V + (long)tp * n;
+  // corrected W[i, tp]; written back below row j, and at row j too when
+  // column j is past this matrix's last reflector (the panel update then
+  // reads that row, and no thread here reads it)
+  double wpi = 0.0;
+  if (fix && i < n) {
+    wpi = wp[i];
+    wpi += alpha * vp[i];
+    if (i > j || !active) wp[i] = wpi;
+  }
+  if (!active) return;
+  double* col = M.A + (long)j * M.ld;
   double ss = 0.0;
   if (i < n) {
+    double wj = 0.0;                // corrected W[j, tp], read by every row
+    if (fix) {
+      wj = wp[j];
+      wj += alpha * vp[j];
+    }
     double a = col[i];
-    for (int t = 0; t < jj; ++t)
-      a -= T.V[i + (long)t * n] * T.W[j + (long)t * n] + T.W[i + (long)t * n] * T.V[j + (long)t * n];
+    for (int t = 0; t < jj; ++t) {
+      const bool p = fix && t == tp;
+      const double wjt = p ? wj : T.W[j + (long)t * n];
+      const double wit = p ? wpi : T.W[i + (long)t * n];
+      a -= T.V[i + (long)t * n] * wjt + wit * T.V[j + (long)t * n];
+    }
     col[i] = a;
     if (i >= j + 2) ss = a * a;
     if (i == j) aux[2 * blockIdx.y] = a;
@@ -399,43 +318,6 @@ __global__ __launch_bounds__(256) void k_trd_cf(const MatDesc* mats, int p0, int
     const double v = (i == j + 1) ? 1.0 : col[i] * scale;
     col[i] = v;
     T.V[i + (long)jj * n] = v;
-  }
-}
-
-// partial dot products y[q] = W[:, q]^T v, y[NB + q] = V[:, q]^T v over a chunk of rows
-__global__ __launch_bounds__(256) void k_trd_wy(const MatDesc* mats, int p0, int jj, const long* off, double* work,
-                                                long sumns, double* ypart, int nchmax) {
-  const MatDesc M = mats[blockIdx.y];
-  const int n = M.n;
-  const int j = p0 + jj;
-  if (j > n - 3 || (int)blockIdx.x * TRD_YCH >= n - j - 1) return;
-  TrdWork T(work, sumns, off[blockIdx.y]);
-  const double* __restrict__ v = T.V + (long)jj * n;
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  const int r0 = j + 1 + blockIdx.x * TRD_YCH, r1 = min(n, r0 + TRD_YCH);
-  constexpr int QW = 2 * TRD_NB / 4;
-  double acc[QW];
-#pragma unroll
-  for (int k = 0; k < QW; ++k) acc[k] = 0.0;
-  for (int i = r0 + lane; i < r1; i += 64) {
-    const double vi = v[i];
-#pragma unroll
-    for (int k = 0; k < QW; ++k) {
-      const int q = wid + 4 * k;
-      if (q < 2 * jj) {
-        const double* __restrict__ c = (q < jj) ? T.W + (long)q * n : T.V + (long)(q - jj) * n;
-        acc[k] += c[i] * vi;
-      }
-    }
-  }
-  double* yp = ypart + ((long)blockIdx.y * nchmax + blockIdx.x) * 2 * TRD_NB;
-#pragma unroll
-  for (int k = 0; k < QW; ++k) {
-    const int q = wid + 4 * k;
-    if (q < 2 * jj) {
-      const double a = wave_sum(acc[k]);
-      if (lane == 0) yp[q < jj ? q : TRD_NB + (q - jj)] = a;
-    }
   }
 }
 
@@ -557,7 +439,7 @@ void sytrd_batched(const MatDesc* d_mats, const std::vector<int>& h_n, double* d
       {
         KScope kt("k_trd_col", s, 0.0, 0.0);
         hipLaunchKernelGGL(k_trd_cu, dim3(gb, batch), dim3(256), 0, s, d_mats, p0, jj, d_off, work, sumns, red.p,
-                           aux.p, nblkmax);
+                           aux.p, nblkmax, jj > 0 ? 1 : 0, tau, svpart.p);
         hipLaunchKernelGGL(k_trd_cf, dim3(gb, batch), dim3(256), 0, s, d_mats, p0, jj, d, e, tau, d_off, work, sumns,
                            red.p, aux.p, nblkmax);
         AWG_LAUNCH_CHECK();
@@ -572,20 +454,22 @@ void sytrd_batched(const MatDesc* d_mats, const std::vector<int>& h_n, double* d
         const int ntiles = std::max(1, ntr * (ntr + 1) / 2);
         // about 4 tiles per workgroup once the trailing matrices are large
         const int gx = ntiles <= 64 ? ntiles : (ntiles + 3) / 4;
+        // plus the workgroups of the panel dot products (none for the first column)
+        const int gwy = jj > 0 ? (int)cdiv(std::max(1, rows), TRD_YCH) : 0;
         KScope kt("k_trd_symv", s, 0.5 * tb, tb / 4.0);
-        hipLaunchKernelGGL(k_trd_symv_pipe, dim3(gx, batch), dim3(256), 0, s, d_mats, p0, jj, d_off, work, sumns,
-                           part.p, ntmax);
+        hipLaunchKernelGGL(k_trd_symv_pipe, dim3(gx + gwy, batch), dim3(256), 0, s, d_mats, p0, jj, d_off, work,
+                           sumns, part.p, ntmax, gx, ypart.p, nchmax);
         AWG_LAUNCH_CHECK();
       }
       {
         KScope ktw("k_trd_w", s, 0.0, 0.0);
-        if (jj > 0)
-          hipLaunchKernelGGL(k_trd_wy, dim3(cdiv(std::max(1, rows), TRD_YCH), batch), dim3(256), 0, s, d_mats, p0, jj,
-                             d_off, work, sumns, ypart.p, nchmax);
         hipLaunchKernelGGL(k_trd_wx, dim3(cdiv(std::max(1, rows), TRD_RB), batch), dim3(256), 0, s, d_mats, p0, jj,
                            tau, d_off, work, sumns, part.p, ntmax, ypart.p, nchmax, svpart.p, nblkmax);
-        hipLaunchKernelGGL(k_trd_wfix, dim3(gb, batch), dim3(256), 0, s, d_mats, p0, jj, tau, d_off, work, sumns,
-                           svpart.p, nblkmax);
+        // the last column of the panel gets its final term here, the others
+        // in the next column's k_trd_cu
+        if (jj == nbp - 1)
+          hipLaunchKernelGGL(k_trd_wfix, dim3(gb, batch), dim3(256), 0, s, d_mats, p0, jj, tau, d_off, work, sumns,
+                             svpart.p, nblkmax);
         AWG_LAUNCH_CHECK();
       }
     }
@@ -726,6 +610,61 @@ void tri_count(const TriEigArgs& a, const double* thr_in, int thr_mode, double e
 // ---------------------------------------------------------------------------
 constexpr int INVIT_SWEEPS = 4;
 constexpr int INVIT_LANES = 64;
+
+// Modified Gram-Schmidt of vector xj (length n, rows lane, lane + 64, ...)
+// against the earlier vectors XT[0..jj), twice, then normalised: the same
+// operations in the same order as the loop over memory in k_tri_vecs, with xj
+// held in registers and the next earlier vector's loads issued before the
+// current dot product is reduced.
+constexpr int MGS_REG_ROWS = 40;   // rows per lane held in registers (n <= 2560)
+
+__device__ inline void mgs_reg(const double* __restrict__ XT, double* __restrict__ xj, int jj, int n, int lane) {
+  double r[MGS_REG_ROWS], qv[MGS_REG_ROWS], qn[MGS_REG_ROWS];
+#pragma unroll
+  for (int t = 0; t < MGS_REG_ROWS; ++t) {
+    const int i = lane + 64 * t;
+    r[t] = i < n ? xj[i] : 0.0;
+  }
+  const int steps = 2 * jj;       // (pass, q) in order
+  if (steps > 0) {
+#pragma unroll
+    for (int t = 0; t < MGS_REG_ROWS; ++t) {
+      const int i = lane + 64 * t;
+      qv[t] = i < n ? XT[i] : 0.0;
+    }
+  }
+  for (int st = 0; st < steps; ++st) {
+    if (st + 1 < steps) {
+      const double* __restrict__ xq = XT + (long)((st + 1) % jj) * n;
+#pragma unroll
+      for (int t = 0; t < MGS_REG_ROWS; ++t) {
+        const int i = lane + 64 * t;
+        qn[t] = i < n ? xq[i] : 0.0;
+      }
+    }
+    double dt = 0.0;
+#pragma unroll
+    for (int t = 0; t < MGS_REG_ROWS; ++t)
+      if (lane + 64 * t < n) dt += qv[t] * r[t];
+    dt = wave_sum(dt);
+#pragma unroll
+    for (int t = 0; t < MGS_REG_ROWS; ++t)
+      if (lane + 64 * t < n) r[t] -= dt * qv[t];
+#pragma unroll
+    for (int t = 0; t < MGS_REG_ROWS; ++t) qv[t] = qn[t];
+  }
+  double nr = 0.0;
+#pragma unroll
+  for (int t = 0; t < MGS_REG_ROWS; ++t)
+    if (lane + 64 * t < n) nr += r[t] * r[t];
+  nr = wave_sum(nr);
+  const double inr = nr > 0.0 ? 1.0 / sqrt(nr) : 0.0;
+#pragma unroll
+  for (int t = 0; t < MGS_REG_ROWS; ++t) {
+    const int i = lane + 64 * t;
+    if (i < n) xj[i] = r[t] * inr;
+  }
+}
 
 // Work per block (doubles): 6 arrays of n x 64, interleaved so that step i of
 // all 64 lanes is one contiguous 512-byte row: u0, u1, u2 (U of the LU with
@@ -875,6 +814,10 @@ __global__ __launch_bounds__(64) void k_tri_vecs(TriEigArgs a, const int* count,
       }
       for (int jj = 0; jj < kc; ++jj) {
         double* __restrict__ xj = XT + (long)jj * n;
+        if (n <= 64 * MGS_REG_ROWS) {
+          mgs_reg(XT, xj, jj, n, lane);
+          continue;
+        }
         for (int pass = 0; pass < 2; ++pass)
           for (int q = 0; q < jj; ++q) {
             const double* __restrict__ xq = XT + (long)q * n;

@@ -139,7 +139,9 @@ def test_trsm(gpu_lib, n, nrhs, trans):
         assert np.max(np.abs(X[b] - ref)) <= 1e-11 * max(1.0, np.max(np.abs(ref)))
 
 
-@pytest.mark.parametrize("n", [1, 2, 3, 40, 97, 200])
+# 700 and 900: more than 64 tiles of 64 x 64 in the trailing matrix, so each
+# workgroup of the symmetric product walks several tiles
+@pytest.mark.parametrize("n", [1, 2, 3, 40, 97, 200, 700, 900])
 def test_low_eigs_against_eigh(gpu_lib, n):
     rng = np.random.default_rng(n)
     batch = 3
