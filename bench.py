@@ -106,9 +106,9 @@ MFMA_KERNELS = ("k_gemm",)
 # were taken on; otherwise the bench reports traffic = null.
 TRAFFIC = {
     "k_gemm128w8<DescArray,N,N>:P": {
-        "bytes_per_launch": 1.6233e10,
+        "bytes_per_launch": 1.6293e10,
         "source": "paper_2106_10913_amd/csrc/k_dense.hip",
-        "sha256": "f6e02f80b505881fdbb25c6124ca466b5e86375f70563d122634727f7a610ef0",
+        "sha256": "9d450b1a95936478607b3d622a07120c296b3651e14154839d5b73082a51cc66",
         "workload": "q1_2d_diffusion_256x256_box8x8_overlap2_tau0.1",
     },
 }
