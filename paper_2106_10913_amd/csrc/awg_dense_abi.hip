@@ -39,7 +39,7 @@ __global__ void k_rowptr_to32(int n, const int64_t* in, int* out) {
 
 namespace awg {
 void spmm_variant(int v, int n, const int* rowptr, const int* col, const double* val, const double* X, double* Y,
-                  int b, double alpha, double beta, hipStream_t s);
+                  int b, double alpha, double beta, hipStream_t s, const int* grp, int ngrp);
 }
 
 extern "C" {
@@ -182,7 +182,7 @@ int awg_dense_low_eigs(int32_t batch, int32_t n, double* A, int32_t lda, int64_t
 
 int awg_csr_spmm(int32_t n, int64_t nnz, const int64_t* rowptr, const int32_t* col, const double* val,
                  const double* X, double* Y, int32_t b, double alpha, double beta, int32_t variant, void* stream) {
-  if (n <= 0 || nnz < 0 || nnz >= (1LL << 31) || b <= 0 || variant < -1 || variant > 8 || !rowptr ||
+  if (n <= 0 || nnz < 0 || nnz >= (1LL << 31) || b <= 0 || variant < -1 || variant > 10 || !rowptr ||
       (nnz && (!col || !val)) || !X || !Y)
     return AWG_ERR_ARG;
   hipStream_t s = (hipStream_t)stream;
@@ -191,10 +191,12 @@ int awg_csr_spmm(int32_t n, int64_t nnz, const int64_t* rowptr, const int32_t* c
     rp.alloc(n + 1);
     hipLaunchKernelGGL(k_rowptr_to32, dim3(cdiv(n + 1, 256)), dim3(256), 0, s, n, rowptr, rp.p);
     AWG_LAUNCH_CHECK();
+    DBuf<int> grp;
+    const int ng = spmm_groups(n, rp, col, grp, s);
     if (variant < 0)
-      l_spmm(n, nnz, rp, col, val, X, Y, b, alpha, beta, s);
+      l_spmm(n, nnz, rp, col, val, X, Y, b, alpha, beta, s, ng ? grp.p : nullptr, ng);
     else
-      spmm_variant(variant, n, rp, col, val, X, Y, b, alpha, beta, s);
+      spmm_variant(variant, n, rp, col, val, X, Y, b, alpha, beta, s, ng ? grp.p : nullptr, ng);
     AWG_HIP(hipStreamSynchronize(s));
   });
 }

@@ -72,8 +72,10 @@ constexpr int TRD_YCH = 512;    // rows per workgroup of the dot products
 
 // partial dot products y[q] = W[:, q]^T v, y[NB + q] = V[:, q]^T v over chunk
 // ch of the rows below j (TRD_YCH rows; matrix b of the batch)
-__device__ inline void trd_wy_chunk(const MatDesc& M, int b, int ch, int p0, int jj, const long* off, double* work,
-                                    long sumns, double* ypart, int nchmax) {
+constexpr int TRD_WYG = 4;      // workgroups per row chunk (each a quarter of the columns)
+
+__device__ inline void trd_wy_chunk(const MatDesc& M, int b, int ch, int cg, int p0, int jj, const long* off,
+                                    double* work, long sumns, double* ypart, int nchmax) {
   const int n = M.n;
   const int j = p0 + jj;
   if (j > n - 3 || ch * TRD_YCH >= n - j - 1) return;
@@ -81,7 +83,12 @@ __device__ inline void trd_wy_chunk(const MatDesc& M, int b, int ch, int p0, int
   const double* __restrict__ v = T.V + (long)jj * n;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int r0 = j + 1 + ch * TRD_YCH, r1 = min(n, r0 + TRD_YCH);
-  constexpr int QW = 2 * TRD_NB / 4;
+  // column q of [W | V] goes to wave slot q % (4 TRD_WYG); a column's sum is
+  // each lane's rows in order and then the wavefront reduction, whichever
+  // wavefront takes it
+  constexpr int NS = 4 * TRD_WYG;
+  constexpr int QW = 2 * TRD_NB / NS;
+  const int slot = cg * 4 + wid;
   double acc[QW];
 #pragma unroll
   for (int k = 0; k < QW; ++k) acc[k] = 0.0;
@@ -89,7 +96,7 @@ __device__ inline void trd_wy_chunk(const MatDesc& M, int b, int ch, int p0, int
     const double vi = v[i];
 #pragma unroll
     for (int k = 0; k < QW; ++k) {
-      const int q = wid + 4 * k;
+      const int q = slot + NS * k;
       if (q < 2 * jj) {
         const double* __restrict__ c = (q < jj) ? T.W + (long)q * n : T.V + (long)(q - jj) * n;
         acc[k] += c[i] * vi;
@@ -99,7 +106,7 @@ __device__ inline void trd_wy_chunk(const MatDesc& M, int b, int ch, int p0, int
   double* yp = ypart + ((long)b * nchmax + ch) * 2 * TRD_NB;
 #pragma unroll
   for (int k = 0; k < QW; ++k) {
-    const int q = wid + 4 * k;
+    const int q = slot + NS * k;
     if (q < 2 * jj) {
       const double a = wave_sum(acc[k]);
       if (lane == 0) yp[q < jj ? q : TRD_NB + (q - jj)] = a;
@@ -107,7 +114,7 @@ __device__ inline void trd_wy_chunk(const MatDesc& M, int b, int ch, int p0, int
   }
 }
 
-// A workgroup walks tiles t = blockIdx.x, blockIdx.x + gxs, ... of its
+// A workgroup walks tiles t = bx, bx + gxs, ... of its
 // matrix and loads the next tile into registers while it works on the current
 // one in LDS (loads stay in flight).
 __device__ inline void symv_tile_decode(int t, int& I, int& C) {
@@ -117,23 +124,26 @@ __device__ inline void symv_tile_decode(int t, int& I, int& C) {
   C = t - I * (I + 1) / 2;
 }
 
-// Workgroups gxs and up of the launch compute the panel dot products of the
-// column (trd_wy_chunk) instead, which do not depend on the product.
+// The first gwy workgroups of the launch compute the panel dot products of
+// the column (trd_wy_chunk), which do not depend on the product; they are
+// dispatched first so that they overlap the product instead of trailing it.
 __global__ __launch_bounds__(256) void k_trd_symv_pipe(const MatDesc* mats, int p0, int jj, const long* off,
                                                        double* work, long sumns, double* part, int ntmax, int gxs,
-                                                       double* ypart, int nchmax) {
+                                                       double* ypart, int nchmax, int gwy) {
   const MatDesc M = mats[blockIdx.y];
-  if ((int)blockIdx.x >= gxs) {
-    trd_wy_chunk(M, blockIdx.y, blockIdx.x - gxs, p0, jj, off, work, sumns, ypart, nchmax);
+  if ((int)blockIdx.x < gwy) {
+    trd_wy_chunk(M, blockIdx.y, blockIdx.x / TRD_WYG, blockIdx.x % TRD_WYG, p0, jj, off, work, sumns, ypart,
+                 nchmax);
     return;
   }
+  const int bx = (int)blockIdx.x - gwy;
   const int n = M.n;
   const int j = p0 + jj;
   if (j > n - 3) return;
   const int base = j + 1, m = n - base;
   const int nt = (m + SYMV_T - 1) / SYMV_T;
   const int ntiles = nt * (nt + 1) / 2;
-  int t = blockIdx.x;
+  int t = bx;
   if (t >= ntiles) return;
   TrdWork T(work, sumns, off[blockIdx.y]);
   const double* v = T.V + (long)jj * n;
@@ -455,10 +465,10 @@ void sytrd_batched(const MatDesc* d_mats, const std::vector<int>& h_n, double* d
         // about 4 tiles per workgroup once the trailing matrices are large
         const int gx = ntiles <= 64 ? ntiles : (ntiles + 3) / 4;
         // plus the workgroups of the panel dot products (none for the first column)
-        const int gwy = jj > 0 ? (int)cdiv(std::max(1, rows), TRD_YCH) : 0;
+        const int gwy = jj > 0 ? TRD_WYG * (int)cdiv(std::max(1, rows), TRD_YCH) : 0;
         KScope kt("k_trd_symv", s, 0.5 * tb, tb / 4.0);
         hipLaunchKernelGGL(k_trd_symv_pipe, dim3(gx + gwy, batch), dim3(256), 0, s, d_mats, p0, jj, d_off, work,
-                           sumns, part.p, ntmax, gx, ypart.p, nchmax);
+                           sumns, part.p, ntmax, gx, ypart.p, nchmax, gwy);
         AWG_LAUNCH_CHECK();
       }
       {

@@ -360,6 +360,95 @@ __global__ __launch_bounds__(256) void k_spmm_w4(int n, const int* __restrict__ 
   y[c1] = o;
 }
 
+// Rows with identical column patterns (the dofs of one node in a vector
+// problem) processed together: one wavefront per group of up to SPMM_GMAX
+// consecutive rows and 128 columns; each X segment is loaded once for the
+// group and each row's nonzeros are summed in CSR order (bit-identical to the
+// per-row kernels).  grp holds the first row of every group and n at the end.
+constexpr int SPMM_GMAX = 4;
+
+__global__ void k_same_pattern(int n, const int* __restrict__ rowptr, const int* __restrict__ col,
+                               unsigned char* same) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  unsigned char eq = 0;
+  if (i > 0) {
+    const int a0 = rowptr[i - 1], a1 = rowptr[i], b1 = rowptr[i + 1];
+    if (a1 - a0 == b1 - a1) {
+      eq = 1;
+      for (int k = 0; k < a1 - a0; ++k)
+        if (col[a0 + k] != col[a1 + k]) {
+          eq = 0;
+          break;
+        }
+    }
+  }
+  same[i] = eq;
+}
+
+template <bool REMAP>
+__global__ __launch_bounds__(256) void k_spmm_grp(int ngrp, const int* __restrict__ grp,
+                                                  const int* __restrict__ rowptr, const int* __restrict__ col,
+                                                  const double* __restrict__ val, const double2* __restrict__ X,
+                                                  double2* Y, int b2, double alpha, double beta, int nrb) {
+  int L = blockIdx.x;
+  if (REMAP) {
+    const int nb = gridDim.x, q = nb >> 3, r = nb & 7, x = L & 7, j = L >> 3;
+    L = x * q + min(x, r) + j;
+  }
+  const int slab = L / nrb, rb = L - slab * nrb;
+  const int gi = __builtin_amdgcn_readfirstlane(rb * 4 + (int)(threadIdx.x >> 6));
+  const int c = slab * 64 + (int)(threadIdx.x & 63);
+  if (gi >= ngrp || c >= b2) return;
+  const int r0 = grp[gi], G = grp[gi + 1] - r0;
+  int p0[SPMM_GMAX];
+#pragma unroll
+  for (int g = 0; g < SPMM_GMAX; ++g) p0[g] = g < G ? rowptr[r0 + g] : 0;
+  const int len = rowptr[r0 + 1] - p0[0];
+  double ax[SPMM_GMAX], ay[SPMM_GMAX];
+#pragma unroll
+  for (int g = 0; g < SPMM_GMAX; ++g) ax[g] = ay[g] = 0.0;
+  int k = 0;
+  for (; k + 2 <= len; k += 2) {
+    const double2 x0 = X[(long)col[p0[0] + k] * b2 + c];
+    const double2 x1 = X[(long)col[p0[0] + k + 1] * b2 + c];
+#pragma unroll
+    for (int g = 0; g < SPMM_GMAX; ++g)
+      if (g < G) {
+        const double v0 = val[p0[g] + k], v1 = val[p0[g] + k + 1];
+        ax[g] += v0 * x0.x;
+        ay[g] += v0 * x0.y;
+        ax[g] += v1 * x1.x;
+        ay[g] += v1 * x1.y;
+      }
+  }
+  for (; k < len; ++k) {
+    const double2 x0 = X[(long)col[p0[0] + k] * b2 + c];
+#pragma unroll
+    for (int g = 0; g < SPMM_GMAX; ++g)
+      if (g < G) {
+        const double v0 = val[p0[g] + k];
+        ax[g] += v0 * x0.x;
+        ay[g] += v0 * x0.y;
+      }
+  }
+#pragma unroll
+  for (int g = 0; g < SPMM_GMAX; ++g)
+    if (g < G) {
+      double2* y = Y + (long)(r0 + g) * b2 + c;
+      double2 o;
+      if (beta == 0.0) {
+        o.x = alpha * ax[g];
+        o.y = alpha * ay[g];
+      } else {
+        const double2 yo = *y;
+        o.x = alpha * ax[g] + beta * yo.x;
+        o.y = alpha * ay[g] + beta * yo.y;
+      }
+      *y = o;
+    }
+}
+
 // Xs[p, :] = X[sub_idx[p], :]  (row copies)
 __global__ void k_gather(long tot, const int* sub_idx, const double* X, int b, double* Xs) {
   const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -642,12 +731,36 @@ void l_extract(int N, const long* sub_ptr, const int* sub_idx, const int* rowptr
 }
 // SpMM launch variants: 0 = one row x 64 columns per wavefront in hardware
 // order (k_spmm_rm); 1..4 = k_spmm_tiled<SLAB, REMAP>; 5, 6 = k_spmm_w2 with
-// and without the XCD renumbering, 7, 8 = k_spmm_w4 with and without it
-// (5..8: even b and 16-byte aligned X, Y only)
-constexpr int SPMM_VARIANTS = 9;
+// and without the XCD renumbering, 7, 8 = k_spmm_w4 with and without it,
+// 9, 10 = k_spmm_grp with and without it (5..10: even b and 16-byte aligned X,
+// Y only; 9, 10 also need the row groups, else they run variant 5)
+constexpr int SPMM_VARIANTS = 11;
+
+int spmm_groups(int n, const int* rowptr, const int* col, DBuf<int>& grp, hipStream_t s) {
+  if (n <= 0) return 0;
+  DBuf<unsigned char> same;
+  same.alloc(n);
+  hipLaunchKernelGGL(k_same_pattern, dim3(cdiv(n, 256)), dim3(256), 0, s, n, rowptr, col, same.p);
+  AWG_LAUNCH_CHECK();
+  const std::vector<unsigned char> h = same.download(s);
+  std::vector<int> starts;
+  starts.reserve(n + 1);
+  int run = 0;
+  for (int i = 0; i < n; ++i) {
+    if (!h[i] || run == SPMM_GMAX) run = 0;
+    if (run == 0) starts.push_back(i);
+    ++run;
+  }
+  const int ng = (int)starts.size();
+  starts.push_back(n);
+  // worth a kernel of its own only when most rows share their pattern
+  if (ng > (3 * n) / 4) return 0;
+  grp.upload(starts, s);
+  return ng;
+}
 
 void spmm_variant(int v, int n, const int* rowptr, const int* col, const double* val, const double* X, double* Y,
-                  int b, double alpha, double beta, hipStream_t s) {
+                  int b, double alpha, double beta, hipStream_t s, const int* grp, int ngrp) {
   auto tiled = [&](auto kern, int slab) {
     const int rpb = 4 * (64 / slab);
     const int nrb = (int)cdiv(n, rpb);
@@ -655,6 +768,7 @@ void spmm_variant(int v, int n, const int* rowptr, const int* col, const double*
                        nrb);
   };
   if (v >= 5 && ((b & 1) || ((uintptr_t)X & 15) || ((uintptr_t)Y & 15))) v = 1;
+  if (v >= 9 && (!grp || ngrp <= 0)) v = 5;
   auto w2 = [&](auto kern) {
     const int nrb = (int)cdiv(n, 4), b2 = b / 2;
     hipLaunchKernelGGL(kern, dim3(nrb * cdiv(b2, 64)), dim3(256), 0, s, n, rowptr, col, val, (const double2*)X,
@@ -665,7 +779,14 @@ void spmm_variant(int v, int n, const int* rowptr, const int* col, const double*
     hipLaunchKernelGGL(kern, dim3(nrb * cdiv(b2, 128)), dim3(256), 0, s, n, rowptr, col, val, (const double2*)X,
                        (double2*)Y, b2, alpha, beta, nrb);
   };
+  auto gw = [&](auto kern) {
+    const int nrb = (int)cdiv(ngrp, 4), b2 = b / 2;
+    hipLaunchKernelGGL(kern, dim3(nrb * cdiv(b2, 64)), dim3(256), 0, s, ngrp, grp, rowptr, col, val,
+                       (const double2*)X, (double2*)Y, b2, alpha, beta, nrb);
+  };
   switch (v) {
+    case 9: gw(k_spmm_grp<true>); break;
+    case 10: gw(k_spmm_grp<false>); break;
     case 7: w4(k_spmm_w4<true>); break;
     case 8: w4(k_spmm_w4<false>); break;
     case 5: w2(k_spmm_w2<true>); break;
@@ -684,19 +805,21 @@ void spmm_variant(int v, int n, const int* rowptr, const int* col, const double*
 // The variant for this shape: measured on the first call with beta = 0 (the
 // timing launches then only overwrite Y with the same values), else cached or 0.
 int spmm_choice(int n, long nnz, const int* rowptr, const int* col, const double* val, const double* X, double* Y,
-                int b, double alpha, double beta, hipStream_t s) {
-  const std::string key = "spmm:n=" + std::to_string(n) + ":nnz=" + std::to_string(nnz) + ":b=" + std::to_string(b);
+                int b, double alpha, double beta, hipStream_t s, const int* grp, int ngrp) {
+  const std::string key = "spmm:n=" + std::to_string(n) + ":nnz=" + std::to_string(nnz) + ":b=" + std::to_string(b) +
+                          ":groups=" + std::to_string(grp ? ngrp : 0);
   const int known = tune_lookup(key);
   if (known >= 0) return known;
   if (beta != 0.0) return 0;
-  return tune_pick(key, SPMM_VARIANTS, [&](int v) { spmm_variant(v, n, rowptr, col, val, X, Y, b, alpha, beta, s); },
+  const int nv = (grp && ngrp > 0) ? SPMM_VARIANTS : SPMM_VARIANTS - 2;
+  return tune_pick(key, nv, [&](int v) { spmm_variant(v, n, rowptr, col, val, X, Y, b, alpha, beta, s, grp, ngrp); },
                    s);
 }
 
 void l_spmm(int n, long nnz, const int* rowptr, const int* col, const double* val, const double* X, double* Y, int b,
-            double alpha, double beta, hipStream_t s) {
+            double alpha, double beta, hipStream_t s, const int* grp, int ngrp) {
   if (n == 0 || b == 0) return;
-  const int v = b == 1 ? 0 : spmm_choice(n, nnz, rowptr, col, val, X, Y, b, alpha, beta, s);
+  const int v = b == 1 ? 0 : spmm_choice(n, nnz, rowptr, col, val, X, Y, b, alpha, beta, s, grp, ngrp);
   KScope kt(b == 1 ? "k_spmv" : "k_spmm_rm", s,
             12.0 * nnz + 4.0 * (n + 1) + 16.0 * n * (double)b + (beta != 0.0 ? 8.0 * n * (double)b : 0.0),
             2.0 * nnz * (double)b);
@@ -705,7 +828,7 @@ void l_spmm(int n, long nnz, const int* rowptr, const int* col, const double* va
     AWG_LAUNCH_CHECK();
     return;
   }
-  spmm_variant(v, n, rowptr, col, val, X, Y, b, alpha, beta, s);
+  spmm_variant(v, n, rowptr, col, val, X, Y, b, alpha, beta, s, grp, ngrp);
 }
 void l_gather(long tot, const int* sub_idx, const double* X, int b, double* Xs, hipStream_t s) {
   if (tot == 0 || b == 0) return;

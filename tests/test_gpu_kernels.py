@@ -174,13 +174,20 @@ def test_low_eigs_against_eigh(gpu_lib, n):
         assert np.max(np.abs(Pg - Pr), initial=0.0) <= 1e-8
 
 
+@pytest.mark.parametrize("vector", [False, True])
 @pytest.mark.parametrize("b", [2, 17, 64, 130, 300])
-def test_csr_spmm_variants_bit_identical(gpu_lib, b):
+def test_csr_spmm_variants_bit_identical(gpu_lib, b, vector):
     """Every SpMM launch variant (and the autotuned one) gives the same bits,
-    within rounding of the exact product; beta != 0 accumulates."""
+    within rounding of the exact product; beta != 0 accumulates.  vector: 3
+    dofs per node with a shared column pattern (rows in groups of 3, the
+    grouped kernel's case), plus rows of a different pattern at the end."""
     import torch
+    import scipy.sparse as sp
     import awg_problems as P
     A = P.q1_2d(m=24, partition="rcb", nparts=4, delta=1).A.tocsr()
+    if vector:
+        A = sp.kron(A, np.array([[4.0, 1.0, 0.5], [1.0, 3.0, 1.0], [0.5, 1.0, 5.0]])).tocsr()
+        A = sp.block_diag([A, sp.random(7, 7, density=0.5, random_state=1) + 10 * sp.eye(7)]).tocsr()
     A.sort_indices()
     n = A.shape[0]
     rng = np.random.default_rng(b)
@@ -192,7 +199,7 @@ def test_csr_spmm_variants_bit_identical(gpu_lib, b):
     Xd = torch.as_tensor(X, device="cuda")
     ref = -0.5 * (A @ X) + 2.0 * Y0
     outs = []
-    for v in [-1] + list(range(9)):
+    for v in [-1] + list(range(11)):
         Yd = torch.as_tensor(Y0, device="cuda")
         gpu_lib.csr_spmm(rp, ci, va, Xd, Yd, alpha=-0.5, beta=2.0, variant=v)
         outs.append(Yd.cpu().numpy())
@@ -204,5 +211,17 @@ def test_csr_spmm_variants_bit_identical(gpu_lib, b):
     gpu_lib.csr_spmm(rp, ci, va, Xd, Yd, alpha=1.0, beta=0.0, variant=-1)
     assert np.max(np.abs(Yd.cpu().numpy() - A @ X)) <= 1e-13 * np.max(np.abs(A @ X))
     rep = gpu_lib.tune_report()
-    key = f"spmm:n={n}:nnz={A.nnz}:b={b}"
-    assert key in rep and 0 <= rep[key]["variant"] <= 8 and len(rep[key]["us"]) == 9
+    same = [i > 0 and np.array_equal(A.indices[A.indptr[i - 1]:A.indptr[i]], A.indices[A.indptr[i]:A.indptr[i + 1]])
+            for i in range(n)]
+    starts, run = 0, 0
+    for i in range(n):
+        if not same[i] or run == 4:
+            run = 0
+        if run == 0:
+            starts += 1
+        run += 1
+    ng = starts if starts <= 3 * n // 4 else 0
+    assert (ng > 0) == vector
+    key = f"spmm:n={n}:nnz={A.nnz}:b={b}:groups={ng}"
+    nv = 11 if ng else 9
+    assert key in rep and 0 <= rep[key]["variant"] < nv and len(rep[key]["us"]) == nv
