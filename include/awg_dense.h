@@ -73,10 +73,10 @@ int awg_dense_low_eigs(int32_t batch, int32_t n, double* A, int32_t lda, int64_t
  * nnz < 2^31) and row-major n x b blocks X, Y (the multi-column product of the
  * W solves).  variant: -1 = the autotuned launch variant for this shape
  * (measured on the first call with beta = 0), 0..10 = a fixed variant (5..10
- * need an even b and 16-byte aligned X and Y, else they run variant 1; 9 and
- * 10 process groups of rows that share a column pattern and run variant 5
- * when fewer than a quarter of the rows do); every variant returns
- * bit-identical results. */
+ * need an even b and 16-byte aligned X and Y, else they run variant 1; 9, 10
+ * process groups of up to 4 consecutive rows on the union of their column
+ * patterns and run variant 5 when grouping would not cut the row count by a
+ * quarter); every variant returns bit-identical results for finite X. */
 int awg_csr_spmm(int32_t n, int64_t nnz, const int64_t* rowptr, const int32_t* col, const double* val,
                  const double* X, double* Y, int32_t b, double alpha, double beta, int32_t variant, void* stream);
 

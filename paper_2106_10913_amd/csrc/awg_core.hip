@@ -169,8 +169,7 @@ struct awg_ctx {
   std::string err = "no error";
   // inputs (copied)
   DBuf<int> rowptr, col;
-  DBuf<int> sgrp;     // groups of rows with identical column patterns (multi-column SpMM)
-  int nsgrp = 0;
+  SpmmGroups sgrp;    // row groups of the multi-column SpMM
   DBuf<double> val;
   std::vector<long> h_subptr;
   std::vector<int> ns;
@@ -514,7 +513,7 @@ void op_aminus(awg_ctx& c, MultiWS& w, const double* X, double* Yo, double beta)
 
 // Y = A_+ X = A X + A_- X (item (i) of the A_+ theorem, Section 3.2)
 void op_aplus(awg_ctx& c, MultiWS& w, const double* X, double* Yo) {
-  l_spmm(c.n, c.nnz, c.rowptr, c.col, c.val, X, Yo, w.b, 1.0, 0.0, c.s, c.sgrp.p, c.nsgrp);
+  l_spmm(c.n, c.nnz, c.rowptr, c.col, c.val, X, Yo, w.b, 1.0, 0.0, c.s, &c.sgrp);
   op_aminus(c, w, X, Yo, 1.0);
 }
 
@@ -707,7 +706,7 @@ void phase_maps(awg_ctx& c, const int64_t* rowptr, const int32_t* col, const dou
   for (int q = 0; q < c.N; ++q) c.sqoff[q + 1] = c.sqoff[q] + (long)c.ns[q] * c.ns[q];
   c.sqtot = c.sqoff[c.N];
   c.d_sqoff.upload(c.sqoff, s);
-  c.nsgrp = spmm_groups((int)c.n, c.rowptr, c.col, c.sgrp, s);   // on the validated pattern
+  spmm_groups((int)c.n, c.nnz, c.rowptr, c.col, c.val, c.sgrp, s);   // on the validated pattern
 }
 
 // Batched eigenvalues below a threshold of dense symmetric blocks (destroys
@@ -1348,7 +1347,7 @@ void phase_EW(awg_ctx& c) {
   DBuf<double> AW, EW;
   AW.alloc((long)c.n * c.nminus);
   EW.alloc((long)c.nminus * c.nminus);
-  l_spmm(c.n, c.nnz, c.rowptr, c.col, c.val, c.W.p, AW.p, c.nminus, 1.0, 0.0, s, c.sgrp.p, c.nsgrp);   // A W
+  l_spmm(c.n, c.nnz, c.rowptr, c.col, c.val, c.W.p, AW.p, c.nminus, 1.0, 0.0, s, &c.sgrp);   // A W
   // E_W = W^T (A W): column-major views W_rm (n_minus x n) and AW_rm -> W_rm AW_rm^T
   DBuf<GemmDesc> g;
   g.upload({GemmDesc{c.W.p, AW.p, EW.p, c.nminus, c.nminus, c.n, c.nminus, c.nminus, c.nminus}}, s);

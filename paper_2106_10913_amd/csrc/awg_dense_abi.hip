@@ -39,7 +39,7 @@ __global__ void k_rowptr_to32(int n, const int64_t* in, int* out) {
 
 namespace awg {
 void spmm_variant(int v, int n, const int* rowptr, const int* col, const double* val, const double* X, double* Y,
-                  int b, double alpha, double beta, hipStream_t s, const int* grp, int ngrp);
+                  int b, double alpha, double beta, hipStream_t s, const SpmmGroups* grp);
 }
 
 extern "C" {
@@ -191,12 +191,12 @@ int awg_csr_spmm(int32_t n, int64_t nnz, const int64_t* rowptr, const int32_t* c
     rp.alloc(n + 1);
     hipLaunchKernelGGL(k_rowptr_to32, dim3(cdiv(n + 1, 256)), dim3(256), 0, s, n, rowptr, rp.p);
     AWG_LAUNCH_CHECK();
-    DBuf<int> grp;
-    const int ng = spmm_groups(n, rp, col, grp, s);
+    SpmmGroups grp;
+    spmm_groups(n, nnz, rp, col, val, grp, s);
     if (variant < 0)
-      l_spmm(n, nnz, rp, col, val, X, Y, b, alpha, beta, s, ng ? grp.p : nullptr, ng);
+      l_spmm(n, nnz, rp, col, val, X, Y, b, alpha, beta, s, &grp);
     else
-      spmm_variant(variant, n, rp, col, val, X, Y, b, alpha, beta, s, ng ? grp.p : nullptr, ng);
+      spmm_variant(variant, n, rp, col, val, X, Y, b, alpha, beta, s, &grp);
     AWG_HIP(hipStreamSynchronize(s));
   });
 }

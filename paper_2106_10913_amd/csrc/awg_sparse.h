@@ -16,15 +16,26 @@ void l_pairs(int n, const int* rowptr, const int* col, const double* val, const 
 void l_pou(long tot, const int* sub_idx, const int* mult, double* dw, hipStream_t s);
 void l_extract(int N, const long* sub_ptr, const int* sub_idx, const int* rowptr, const int* col,
                const double* vals, const MatDesc* mats, hipStream_t s);
-// multi-column vectors are row-major (b contiguous values per row); grp,
-// ngrp (optional): groups of consecutive rows with identical column patterns
-// from spmm_groups, offered to the autotuner as the grouped kernel
+// Groups of up to 4 consecutive rows stored over the union of their column
+// patterns (zeros where a row has no entry), for the grouped SpMM kernel
+struct SpmmGroups {
+  int ng = 0;
+  DBuf<int> start;     // first row of each group, n at the end
+  DBuf<int> uptr;      // offsets of the union patterns in ucol (ng + 1)
+  DBuf<int> ucol;      // union column indices, ascending per group
+  DBuf<long> voff;     // offset of each group's G x |U| value block in gval
+  DBuf<double> gval;   // values, row g of a group at voff + g |U|
+};
+// multi-column vectors are row-major (b contiguous values per row); grp
+// (optional): row groups from spmm_groups, offered to the autotuner
 void l_spmm(int n, long nnz, const int* rowptr, const int* col, const double* val, const double* X, double* Y, int b,
-            double alpha, double beta, hipStream_t s, const int* grp = nullptr, int ngrp = 0);
-// first rows of the groups (at most 4 consecutive rows sharing a column
-// pattern; n appended) into grp; returns the number of groups, or 0 (grp
-// untouched) when fewer than a quarter of the rows share their predecessor's pattern
-int spmm_groups(int n, const int* rowptr, const int* col, DBuf<int>& grp, hipStream_t s);
+            double alpha, double beta, hipStream_t s, const SpmmGroups* grp = nullptr);
+// builds the groups of a validated CSR pattern (columns sorted per row): a
+// group grows while its union pattern stays within 1.4 times its longest
+// row; returns the number of groups, or 0 (g left empty) when grouping would
+// not cut the row count by a quarter
+int spmm_groups(int n, long nnz, const int* rowptr, const int* col, const double* val, SpmmGroups& g,
+                hipStream_t s);
 void l_gather(long tot, const int* sub_idx, const double* X, int b, double* Xs, hipStream_t s);
 void l_scatter(int n, long tot, const int* inv_ptr, const int* inv_sub, const int* inv_loc, const long* sub_ptr,
                const double* Zs, int b, double* Y, double alpha, double beta, hipStream_t s);

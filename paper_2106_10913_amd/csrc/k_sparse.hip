@@ -6,6 +6,9 @@
 // Xs[p * b + c].  The prolongation sum_s R^sT X_s is computed as a gather over
 // the inverse map dof -> (s, local index), so every output is written by one
 // thread and the sum order is fixed (no atomics, bitwise reproducible).
+#include <algorithm>
+#include <iterator>
+
 #include "awg_sparse.h"
 #include "awg_tune.h"
 
@@ -360,37 +363,29 @@ __global__ __launch_bounds__(256) void k_spmm_w4(int n, const int* __restrict__ 
   y[c1] = o;
 }
 
-// Rows with identical column patterns (the dofs of one node in a vector
-// problem) processed together: one wavefront per group of up to SPMM_GMAX
-// consecutive rows and 128 columns; each X segment is loaded once for the
-// group and each row's nonzeros are summed in CSR order (bit-identical to the
-// per-row kernels).  grp holds the first row of every group and n at the end.
 constexpr int SPMM_GMAX = 4;
 
-__global__ void k_same_pattern(int n, const int* __restrict__ rowptr, const int* __restrict__ col,
-                               unsigned char* same) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  unsigned char eq = 0;
-  if (i > 0) {
-    const int a0 = rowptr[i - 1], a1 = rowptr[i], b1 = rowptr[i + 1];
-    if (a1 - a0 == b1 - a1) {
-      eq = 1;
-      for (int k = 0; k < a1 - a0; ++k)
-        if (col[a0 + k] != col[a1 + k]) {
-          eq = 0;
-          break;
-        }
-    }
-  }
-  same[i] = eq;
+// Groups of up to SPMM_GMAX consecutive rows processed on the union of their
+// column patterns (the dofs of one node in a vector problem; neighbouring rows
+// of a stencil): one wavefront per group and 128 columns loads each X segment
+// once for the group.  A row's values are stored densely over the union with
+// zeros where the row has no entry; a zero term leaves a finite sum
+// unchanged, so each row's sum equals the CSR-order sum of the per-row
+// kernels bit for bit (for finite X).
+__global__ void k_fill_gval(long total, const long* __restrict__ gmap, const double* __restrict__ val,
+                            double* gval) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  const long p = gmap[i];
+  gval[i] = p >= 0 ? val[p] : 0.0;
 }
 
 template <bool REMAP>
-__global__ __launch_bounds__(256) void k_spmm_grp(int ngrp, const int* __restrict__ grp,
-                                                  const int* __restrict__ rowptr, const int* __restrict__ col,
-                                                  const double* __restrict__ val, const double2* __restrict__ X,
-                                                  double2* Y, int b2, double alpha, double beta, int nrb) {
+__global__ __launch_bounds__(256) void k_spmm_pad(int ngrp, const int* __restrict__ start,
+                                                  const int* __restrict__ uptr, const int* __restrict__ ucol,
+                                                  const long* __restrict__ voff, const double* __restrict__ gval,
+                                                  const double2* __restrict__ X, double2* Y, int b2, double alpha,
+                                                  double beta, int nrb) {
   int L = blockIdx.x;
   if (REMAP) {
     const int nb = gridDim.x, q = nb >> 3, r = nb & 7, x = L & 7, j = L >> 3;
@@ -400,22 +395,21 @@ __global__ __launch_bounds__(256) void k_spmm_grp(int ngrp, const int* __restric
   const int gi = __builtin_amdgcn_readfirstlane(rb * 4 + (int)(threadIdx.x >> 6));
   const int c = slab * 64 + (int)(threadIdx.x & 63);
   if (gi >= ngrp || c >= b2) return;
-  const int r0 = grp[gi], G = grp[gi + 1] - r0;
-  int p0[SPMM_GMAX];
-#pragma unroll
-  for (int g = 0; g < SPMM_GMAX; ++g) p0[g] = g < G ? rowptr[r0 + g] : 0;
-  const int len = rowptr[r0 + 1] - p0[0];
+  const int r0 = start[gi], G = start[gi + 1] - r0;
+  const int u0 = uptr[gi], len = uptr[gi + 1] - u0;
+  const double* __restrict__ gv = gval + voff[gi];
+  const int* __restrict__ uc = ucol + u0;
   double ax[SPMM_GMAX], ay[SPMM_GMAX];
 #pragma unroll
   for (int g = 0; g < SPMM_GMAX; ++g) ax[g] = ay[g] = 0.0;
   int k = 0;
   for (; k + 2 <= len; k += 2) {
-    const double2 x0 = X[(long)col[p0[0] + k] * b2 + c];
-    const double2 x1 = X[(long)col[p0[0] + k + 1] * b2 + c];
+    const double2 x0 = X[(long)uc[k] * b2 + c];
+    const double2 x1 = X[(long)uc[k + 1] * b2 + c];
 #pragma unroll
     for (int g = 0; g < SPMM_GMAX; ++g)
       if (g < G) {
-        const double v0 = val[p0[g] + k], v1 = val[p0[g] + k + 1];
+        const double v0 = gv[g * len + k], v1 = gv[g * len + k + 1];
         ax[g] += v0 * x0.x;
         ay[g] += v0 * x0.y;
         ax[g] += v1 * x1.x;
@@ -423,11 +417,11 @@ __global__ __launch_bounds__(256) void k_spmm_grp(int ngrp, const int* __restric
       }
   }
   for (; k < len; ++k) {
-    const double2 x0 = X[(long)col[p0[0] + k] * b2 + c];
+    const double2 x0 = X[(long)uc[k] * b2 + c];
 #pragma unroll
     for (int g = 0; g < SPMM_GMAX; ++g)
       if (g < G) {
-        const double v0 = val[p0[g] + k];
+        const double v0 = gv[g * len + k];
         ax[g] += v0 * x0.x;
         ay[g] += v0 * x0.y;
       }
@@ -732,35 +726,70 @@ void l_extract(int N, const long* sub_ptr, const int* sub_idx, const int* rowptr
 // SpMM launch variants: 0 = one row x 64 columns per wavefront in hardware
 // order (k_spmm_rm); 1..4 = k_spmm_tiled<SLAB, REMAP>; 5, 6 = k_spmm_w2 with
 // and without the XCD renumbering, 7, 8 = k_spmm_w4 with and without it,
-// 9, 10 = k_spmm_grp with and without it (5..10: even b and 16-byte aligned X,
+// 9, 10 = k_spmm_pad with and without it (5..10: even b and 16-byte aligned X,
 // Y only; 9, 10 also need the row groups, else they run variant 5)
 constexpr int SPMM_VARIANTS = 11;
 
-int spmm_groups(int n, const int* rowptr, const int* col, DBuf<int>& grp, hipStream_t s) {
-  if (n <= 0) return 0;
-  DBuf<unsigned char> same;
-  same.alloc(n);
-  hipLaunchKernelGGL(k_same_pattern, dim3(cdiv(n, 256)), dim3(256), 0, s, n, rowptr, col, same.p);
-  AWG_LAUNCH_CHECK();
-  const std::vector<unsigned char> h = same.download(s);
-  std::vector<int> starts;
-  starts.reserve(n + 1);
-  int run = 0;
-  for (int i = 0; i < n; ++i) {
-    if (!h[i] || run == SPMM_GMAX) run = 0;
-    if (run == 0) starts.push_back(i);
-    ++run;
+int spmm_groups(int n, long nnz, const int* rowptr, const int* col, const double* val, SpmmGroups& g,
+                hipStream_t s) {
+  g.ng = 0;
+  if (n <= 0 || nnz <= 0) return 0;
+  std::vector<int> rp(n + 1), cl(nnz);
+  AWG_HIP(hipMemcpyAsync(rp.data(), rowptr, sizeof(int) * (n + 1), hipMemcpyDeviceToHost, s));
+  AWG_HIP(hipMemcpyAsync(cl.data(), col, sizeof(int) * nnz, hipMemcpyDeviceToHost, s));
+  AWG_HIP(hipStreamSynchronize(s));
+  std::vector<int> start, uptr{0}, ucol;
+  std::vector<long> voff{0}, gmap;
+  std::vector<int> u, tmp;
+  for (int r = 0; r < n;) {
+    u.assign(cl.begin() + rp[r], cl.begin() + rp[r + 1]);
+    int maxlen = rp[r + 1] - rp[r], G = 1;
+    while (G < SPMM_GMAX && r + G < n) {
+      const int q = r + G, lq = rp[q + 1] - rp[q];
+      tmp.clear();
+      std::set_union(u.begin(), u.end(), cl.begin() + rp[q], cl.begin() + rp[q + 1], std::back_inserter(tmp));
+      const int ml = std::max(maxlen, lq);
+      // at most 40 % more products than the longest row of the group
+      if (ml == 0 || 10L * (long)tmp.size() > 14L * ml) break;
+      u.swap(tmp);
+      maxlen = ml;
+      ++G;
+    }
+    start.push_back(r);
+    ucol.insert(ucol.end(), u.begin(), u.end());
+    uptr.push_back((int)ucol.size());
+    for (int gg = 0; gg < G; ++gg) {
+      int p = rp[r + gg];
+      const int pe = rp[r + gg + 1];
+      for (int k : u) {
+        if (p < pe && cl[p] == k) gmap.push_back(p++);
+        else gmap.push_back(-1);
+      }
+    }
+    voff.push_back((long)gmap.size());
+    r += G;
   }
-  const int ng = (int)starts.size();
-  starts.push_back(n);
-  // worth a kernel of its own only when most rows share their pattern
+  const int ng = (int)start.size();
+  start.push_back(n);
+  // worth a kernel of its own only when groups cut the row count by a quarter
   if (ng > (3 * n) / 4) return 0;
-  grp.upload(starts, s);
+  g.start.upload(start, s);
+  g.uptr.upload(uptr, s);
+  g.ucol.upload(ucol, s);
+  g.voff.upload(voff, s);
+  DBuf<long> dmap;
+  dmap.upload(gmap, s);
+  g.gval.alloc(gmap.size());
+  hipLaunchKernelGGL(k_fill_gval, dim3(cdiv((long)gmap.size(), 256)), dim3(256), 0, s, (long)gmap.size(), dmap.p,
+                     val, g.gval.p);
+  AWG_LAUNCH_CHECK();
+  AWG_HIP(hipStreamSynchronize(s));
+  g.ng = ng;
   return ng;
 }
 
 void spmm_variant(int v, int n, const int* rowptr, const int* col, const double* val, const double* X, double* Y,
-                  int b, double alpha, double beta, hipStream_t s, const int* grp, int ngrp) {
+                  int b, double alpha, double beta, hipStream_t s, const SpmmGroups* grp) {
   auto tiled = [&](auto kern, int slab) {
     const int rpb = 4 * (64 / slab);
     const int nrb = (int)cdiv(n, rpb);
@@ -768,7 +797,7 @@ void spmm_variant(int v, int n, const int* rowptr, const int* col, const double*
                        nrb);
   };
   if (v >= 5 && ((b & 1) || ((uintptr_t)X & 15) || ((uintptr_t)Y & 15))) v = 1;
-  if (v >= 9 && (!grp || ngrp <= 0)) v = 5;
+  if (v >= 9 && (!grp || grp->ng <= 0)) v = 5;
   auto w2 = [&](auto kern) {
     const int nrb = (int)cdiv(n, 4), b2 = b / 2;
     hipLaunchKernelGGL(kern, dim3(nrb * cdiv(b2, 64)), dim3(256), 0, s, n, rowptr, col, val, (const double2*)X,
@@ -780,13 +809,13 @@ void spmm_variant(int v, int n, const int* rowptr, const int* col, const double*
                        (double2*)Y, b2, alpha, beta, nrb);
   };
   auto gw = [&](auto kern) {
-    const int nrb = (int)cdiv(ngrp, 4), b2 = b / 2;
-    hipLaunchKernelGGL(kern, dim3(nrb * cdiv(b2, 64)), dim3(256), 0, s, ngrp, grp, rowptr, col, val,
-                       (const double2*)X, (double2*)Y, b2, alpha, beta, nrb);
+    const int nrb = (int)cdiv(grp->ng, 4), b2 = b / 2;
+    hipLaunchKernelGGL(kern, dim3(nrb * cdiv(b2, 64)), dim3(256), 0, s, grp->ng, grp->start.p, grp->uptr.p,
+                       grp->ucol.p, grp->voff.p, grp->gval.p, (const double2*)X, (double2*)Y, b2, alpha, beta, nrb);
   };
   switch (v) {
-    case 9: gw(k_spmm_grp<true>); break;
-    case 10: gw(k_spmm_grp<false>); break;
+    case 9: gw(k_spmm_pad<true>); break;
+    case 10: gw(k_spmm_pad<false>); break;
     case 7: w4(k_spmm_w4<true>); break;
     case 8: w4(k_spmm_w4<false>); break;
     case 5: w2(k_spmm_w2<true>); break;
@@ -805,21 +834,21 @@ void spmm_variant(int v, int n, const int* rowptr, const int* col, const double*
 // The variant for this shape: measured on the first call with beta = 0 (the
 // timing launches then only overwrite Y with the same values), else cached or 0.
 int spmm_choice(int n, long nnz, const int* rowptr, const int* col, const double* val, const double* X, double* Y,
-                int b, double alpha, double beta, hipStream_t s, const int* grp, int ngrp) {
+                int b, double alpha, double beta, hipStream_t s, const SpmmGroups* grp) {
+  const int ng = grp ? grp->ng : 0;
   const std::string key = "spmm:n=" + std::to_string(n) + ":nnz=" + std::to_string(nnz) + ":b=" + std::to_string(b) +
-                          ":groups=" + std::to_string(grp ? ngrp : 0);
+                          ":groups=" + std::to_string(ng);
   const int known = tune_lookup(key);
   if (known >= 0) return known;
   if (beta != 0.0) return 0;
-  const int nv = (grp && ngrp > 0) ? SPMM_VARIANTS : SPMM_VARIANTS - 2;
-  return tune_pick(key, nv, [&](int v) { spmm_variant(v, n, rowptr, col, val, X, Y, b, alpha, beta, s, grp, ngrp); },
-                   s);
+  const int nv = ng > 0 ? SPMM_VARIANTS : SPMM_VARIANTS - 2;
+  return tune_pick(key, nv, [&](int v) { spmm_variant(v, n, rowptr, col, val, X, Y, b, alpha, beta, s, grp); }, s);
 }
 
 void l_spmm(int n, long nnz, const int* rowptr, const int* col, const double* val, const double* X, double* Y, int b,
-            double alpha, double beta, hipStream_t s, const int* grp, int ngrp) {
+            double alpha, double beta, hipStream_t s, const SpmmGroups* grp) {
   if (n == 0 || b == 0) return;
-  const int v = b == 1 ? 0 : spmm_choice(n, nnz, rowptr, col, val, X, Y, b, alpha, beta, s, grp, ngrp);
+  const int v = b == 1 ? 0 : spmm_choice(n, nnz, rowptr, col, val, X, Y, b, alpha, beta, s, grp);
   KScope kt(b == 1 ? "k_spmv" : "k_spmm_rm", s,
             12.0 * nnz + 4.0 * (n + 1) + 16.0 * n * (double)b + (beta != 0.0 ? 8.0 * n * (double)b : 0.0),
             2.0 * nnz * (double)b);
@@ -828,7 +857,7 @@ void l_spmm(int n, long nnz, const int* rowptr, const int* col, const double* va
     AWG_LAUNCH_CHECK();
     return;
   }
-  spmm_variant(v, n, rowptr, col, val, X, Y, b, alpha, beta, s, grp, ngrp);
+  spmm_variant(v, n, rowptr, col, val, X, Y, b, alpha, beta, s, grp);
 }
 void l_gather(long tot, const int* sub_idx, const double* X, int b, double* Xs, hipStream_t s) {
   if (tot == 0 || b == 0) return;
