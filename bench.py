@@ -155,8 +155,14 @@ def roofline(kt: dict, steps: int, workload: str) -> dict:
     avg_us = rec["ms"] * 1e3 / rec["calls"]
     if name.startswith(MFMA_KERNELS):
         achieved = rec["flops"] / (rec["ms"] * 1e-3) / 1e12
+        # the device's sustained FP64 matrix-core rate (register-only MFMA
+        # chains, no memory traffic), measured in this run beside the
+        # published peak
+        from paper_2106_10913_amd import awg
+        sustained = awg.probe_mfma_f64()
         return {"kernel": name, "bound": "mfma", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
+                "sustained_mfma_peak": round(sustained, 2), "frac_of_sustained": round(achieved / sustained, 4),
                 "traffic": measured_traffic(name, workload),
                 "calls_per_step": rec["calls"] / steps, "avg_launch_us": round(avg_us, 2),
                 "flops_per_launch": rec["flops"] / rec["calls"]}

@@ -80,6 +80,14 @@ int awg_dense_low_eigs(int32_t batch, int32_t n, double* A, int32_t lda, int64_t
 int awg_csr_spmm(int32_t n, int64_t nnz, const int64_t* rowptr, const int32_t* col, const double* val,
                  const double* X, double* Y, int32_t b, double alpha, double beta, int32_t variant, void* stream);
 
+/* Sustained FP64 matrix-core rate of the device in TFLOP/s (*tflops, host):
+ * best of three timed launches of a kernel that runs `iters` rounds of eight
+ * independent v_mfma_f64_16x16x4 accumulations per wavefront, eight
+ * wavefronts per SIMD on every CU, with no memory traffic in the loop (the
+ * practical ceiling of the FP64 GEMMs, beside the published peak).  Returns
+ * AWG_ERR_ARG for iters <= 0 or a null tflops. */
+int awg_probe_mfma_f64(int32_t iters, double* tflops, void* stream);
+
 /* Autotuner of launch variants: enable (default) or disable measurement
  * (disabled: variant 0 everywhere).  Choices persist as JSON lines in the file
  * named by the environment variable AWG_TUNE_CACHE when it is set. */

@@ -28,7 +28,7 @@ EXPORTED = ["awg_default_options", "awg_setup", "awg_apply", "awg_pcg", "awg_sta
             "awg_dense_gemm", "awg_dense_gemm_ex", "awg_dense_potrf", "awg_dense_trsm", "awg_dense_low_eigs",
             "awg_mlp_create", "awg_mlp_num_params", "awg_mlp_get_params", "awg_mlp_set_params", "awg_mlp_forward",
             "awg_mlp_loss_grad", "awg_mlp_get_grads", "awg_mlp_adam_step", "awg_mlp_last_error", "awg_mlp_destroy",
-            "awg_csr_spmm", "awg_autotune", "awg_tune_report", "awg_kernel_timing_filter"]
+            "awg_csr_spmm", "awg_autotune", "awg_tune_report", "awg_kernel_timing_filter", "awg_probe_mfma_f64"]
 MLP_FEATURES = 12
 
 
@@ -95,6 +95,8 @@ def lib():
     L.awg_dense_gemm_ex.argtypes = [i32, i32, i32, i32, i32, i32, dbl, vp, i32, i64, vp, vp, i32, i64, dbl, vp, i32,
                                     i64, i32, vp]
     L.awg_dense_gemm_ex.restype = ctypes.c_int
+    L.awg_probe_mfma_f64.argtypes = [i32, ctypes.POINTER(ctypes.c_double), vp]
+    L.awg_probe_mfma_f64.restype = ctypes.c_int
     L.awg_dense_potrf.argtypes = [i32, i32, vp, i32, i64, vp, vp]
     L.awg_dense_potrf.restype = ctypes.c_int
     L.awg_dense_trsm.argtypes = [i32, i32, i32, i32, vp, i32, i64, vp, i32, i64, vp]
@@ -351,6 +353,15 @@ def dense_gemm_ex(A, B, C, alpha=1.0, beta=0.0, transA=False, transB=False, vari
     if rc:
         raise AWGError(rc, "awg_dense_gemm_ex")
     return C
+
+
+def probe_mfma_f64(iters: int = 4000) -> float:
+    """Sustained FP64 matrix-core rate of the device, TFLOP/s."""
+    out = ctypes.c_double(0.0)
+    rc = lib().awg_probe_mfma_f64(iters, ctypes.byref(out), _stream())
+    if rc:
+        raise AWGError(rc, "awg_probe_mfma_f64")
+    return out.value
 
 
 def dense_potrf(A):

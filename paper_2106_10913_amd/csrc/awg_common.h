@@ -136,6 +136,9 @@ void gemm_batched(const GemmDesc* d_desc, int batch, int max_m, int max_n, bool 
 void gemm_batched_gather(const GemmDesc* d_desc, const double* X, const int* idx, const long* off, int batch,
                          int max_m, int max_n, bool transB, double alpha, double beta, hipStream_t s, double flops,
                          const char* tag);
+// sustained FP64 MFMA rate (TFLOP/s) of the current device, best of 3 timed
+// launches of a register-only MFMA kernel
+double probe_mfma_f64(int iters, hipStream_t s);
 // one fixed launch variant (0..3) of gemm_batched (X == nullptr) or of
 // gemm_batched_gather (transA must then be false)
 void gemm_batched_fixed(const GemmDesc* d_desc, const double* X, const int* idx, const long* off, int batch,

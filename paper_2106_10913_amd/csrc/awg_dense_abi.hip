@@ -201,6 +201,12 @@ int awg_csr_spmm(int32_t n, int64_t nnz, const int64_t* rowptr, const int32_t* c
   });
 }
 
+int awg_probe_mfma_f64(int32_t iters, double* tflops, void* stream) {
+  if (iters <= 0 || !tflops) return AWG_ERR_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  return guarded(s, [&] { *tflops = probe_mfma_f64(iters, s); });
+}
+
 int awg_autotune(int32_t enable) {
   tune_enable(enable != 0);
   return AWG_OK;

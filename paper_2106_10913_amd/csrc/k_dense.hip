@@ -1101,4 +1101,53 @@ void trsm_batched(const MatDesc* d_L, const MatDesc* d_B, const std::vector<int>
   }
 }
 
+// ---------------------------------------------------------------------------
+// sustained FP64 MFMA rate of the device: register-only chains of
+// v_mfma_f64_16x16x4 (8 independent accumulators per wavefront, 8 wavefronts
+// per SIMD on every CU), no memory traffic inside the loop
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_mfma_probe(double* out, int iters, double a0, double b0) {
+  v4d acc[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) acc[i] = (v4d){0.0, 0.0, 0.0, 0.0};
+  const double a = a0 + threadIdx.x * 1e-9, b = b0;
+  for (int it = 0; it < iters; ++it) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[i], 0, 0, 0);
+  }
+  double s = 0.0;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) s += acc[i][0] + acc[i][1] + acc[i][2] + acc[i][3];
+  out[(long)blockIdx.x * blockDim.x + threadIdx.x] = s;
+}
+
+double probe_mfma_f64(int iters, hipStream_t s) {
+  int dev = 0, ncu = 0;
+  AWG_HIP(hipGetDevice(&dev));
+  AWG_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  const int blocks = 8 * ncu, threads = 256;
+  DBuf<double> out;
+  out.alloc((size_t)blocks * threads);
+  hipEvent_t e0, e1;
+  AWG_HIP(hipEventCreate(&e0));
+  AWG_HIP(hipEventCreate(&e1));
+  hipLaunchKernelGGL(k_mfma_probe, dim3(blocks), dim3(threads), 0, s, out.p, 64, 1.0, 1e-3);   // warm-up
+  AWG_LAUNCH_CHECK();
+  double best = 0.0;
+  for (int r = 0; r < 3; ++r) {
+    AWG_HIP(hipEventRecord(e0, s));
+    hipLaunchKernelGGL(k_mfma_probe, dim3(blocks), dim3(threads), 0, s, out.p, iters, 1.0, 1e-3);
+    AWG_LAUNCH_CHECK();
+    AWG_HIP(hipEventRecord(e1, s));
+    AWG_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    AWG_HIP(hipEventElapsedTime(&ms, e0, e1));
+    const double flops = 2.0 * 16 * 16 * 4 * 8.0 * iters * ((double)blocks * threads / 64.0);
+    best = std::max(best, flops / (ms * 1e-3) / 1e12);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return best;
+}
+
 }  // namespace awg

@@ -15,7 +15,7 @@ def declared_symbols():
         if h.endswith(".h"):
             src = open(os.path.join(ROOT, "include", h)).read()
             src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-            names |= set(re.findall(r"\b(awg_[a-z_]+)\s*\(", src))
+            names |= set(re.findall(r"\b(awg_[a-z0-9_]+)\s*\(", src))
     return sorted(names)
 
 
