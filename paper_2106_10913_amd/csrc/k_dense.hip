@@ -169,6 +169,10 @@ struct Syr2kUpdate {
 //   A (16x4): lane l holds A[l % 16][l / 16]
 //   B (4x16): lane l holds B[l / 16][l % 16]
 //   D (16x16): lane l holds D[l/16 + 4*r][l % 16], r = 0..3 (checked on gfx950)
+// The tile kernels pass the B fragment as the first operand and the A
+// fragment as the second, which yields each 16 x 16 block of C transposed
+// (same products, same k order): lane l then holds C[l % 16][l/16 + 4*r], so
+// 16 consecutive lanes store 16 consecutive rows of the column-major C.
 template <class DF, bool TA, bool TB>
 __global__ __launch_bounds__(256) void k_gemm(DF df, double alpha, double beta, int lower) {
   const GemmDesc d = df(blockIdx.z);
@@ -214,10 +218,10 @@ __global__ __launch_bounds__(256) void k_gemm(DF df, double alpha, double beta, 
       const int kr = kk + (lane >> 4), c = lane & 15;
       const double a0 = As[kr][wm + c], a1 = As[kr][wm + 16 + c];
       const double b0 = Bs[kr][wn + c], b1 = Bs[kr][wn + 16 + c];
-      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
-      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
-      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
-      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(b0, a0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(b1, a0, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(b0, a1, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(b1, a1, acc[1][1], 0, 0, 0);
     }
     __syncthreads();
   }
@@ -227,8 +231,8 @@ __global__ __launch_bounds__(256) void k_gemm(DF df, double alpha, double beta, 
     for (int b = 0; b < 2; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int i = m0 + wm + a * 16 + (lane >> 4) + 4 * r;
-        const int j = n0 + wn + b * 16 + (lane & 15);
+        const int i = m0 + wm + a * 16 + (lane & 15);
+        const int j = n0 + wn + b * 16 + (lane >> 4) + 4 * r;
         if (i < d.m && j < d.n) {
           double* c = d.C + i + (long)j * d.ldc;
           const double v = alpha * acc[a][b][r];
@@ -304,7 +308,7 @@ __global__ __launch_bounds__(256) void k_gemm128(DF df, double alpha, double bet
       for (int qa = 0; qa < 4; ++qa)
 #pragma unroll
         for (int qb = 0; qb < 4; ++qb)
-          acc[qa][qb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[qa], b[qb], acc[qa][qb], 0, 0, 0);
+          acc[qa][qb] = __builtin_amdgcn_mfma_f64_16x16x4f64(b[qb], a[qa], acc[qa][qb], 0, 0, 0);
     }
     if (more) sstore(buf ^ 1);
     __syncthreads();
@@ -316,8 +320,8 @@ __global__ __launch_bounds__(256) void k_gemm128(DF df, double alpha, double bet
     for (int qb = 0; qb < 4; ++qb)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int i = m0 + wm + qa * 16 + (lane >> 4) + 4 * r;
-        const int j = n0 + wn + qb * 16 + (lane & 15);
+        const int i = m0 + wm + qa * 16 + (lane & 15);
+        const int j = n0 + wn + qb * 16 + (lane >> 4) + 4 * r;
         if (i < d.m && j < d.n) {
           double* cp = d.C + i + (long)j * d.ldc;
           const double v = alpha * acc[qa][qb][r];
@@ -329,7 +333,9 @@ __global__ __launch_bounds__(256) void k_gemm128(DF df, double alpha, double bet
 // 128x128 tiles with eight wavefronts (2 x 4, each 64 x 32): half the
 // accumulators per lane of k_gemm128, so more wavefronts fit per SIMD to hide
 // the global-load latency.  Same k order and MFMA as the other tile shapes
-// (bit-identical results).
+// (bit-identical results).  The MFMA takes its operands swapped and yields
+// each 16 x 16 block transposed, so that 16 consecutive lanes hold 16
+// consecutive rows of C and store one contiguous 128-byte segment.
 template <class DF, bool TA, bool TB>
 __global__ __launch_bounds__(512, 4) void k_gemm128w8(DF df, double alpha, double beta, int lower) {
   const GemmDesc d = df(blockIdx.z);
@@ -393,7 +399,7 @@ __global__ __launch_bounds__(512, 4) void k_gemm128w8(DF df, double alpha, doubl
       for (int qa = 0; qa < 4; ++qa)
 #pragma unroll
         for (int qb = 0; qb < 2; ++qb)
-          acc[qa][qb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[qa], b[qb], acc[qa][qb], 0, 0, 0);
+          acc[qa][qb] = __builtin_amdgcn_mfma_f64_16x16x4f64(b[qb], a[qa], acc[qa][qb], 0, 0, 0);
     }
     if (more) sstore(buf ^ 1);
     __syncthreads();
@@ -405,8 +411,8 @@ __global__ __launch_bounds__(512, 4) void k_gemm128w8(DF df, double alpha, doubl
     for (int qb = 0; qb < 2; ++qb)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int i = m0 + wm + qa * 16 + (lane >> 4) + 4 * r;
-        const int j = n0 + wn + qb * 16 + (lane & 15);
+        const int i = m0 + wm + qa * 16 + (lane & 15);
+        const int j = n0 + wn + qb * 16 + (lane >> 4) + 4 * r;
         if (i < d.m && j < d.n) {
           double* cp = d.C + i + (long)j * d.ldc;
           const double v = alpha * acc[qa][qb][r];
@@ -579,7 +585,7 @@ __global__ __launch_bounds__(256) void k_gemm128_mix(const GemmDescMix* descs, d
       for (int qa = 0; qa < 4; ++qa)
 #pragma unroll
         for (int qb = 0; qb < 4; ++qb)
-          acc[qa][qb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[qa], b[qb], acc[qa][qb], 0, 0, 0);
+          acc[qa][qb] = __builtin_amdgcn_mfma_f32_16x16x4f32(b[qb], a[qa], acc[qa][qb], 0, 0, 0);
     }
     if (more) sstore(buf ^ 1);
     __syncthreads();
@@ -591,8 +597,8 @@ __global__ __launch_bounds__(256) void k_gemm128_mix(const GemmDescMix* descs, d
     for (int qb = 0; qb < 4; ++qb)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int i = m0 + wm + qa * 16 + 4 * (lane >> 4) + r;
-        const int j = n0 + wn + qb * 16 + (lane & 15);
+        const int i = m0 + wm + qa * 16 + (lane & 15);
+        const int j = n0 + wn + qb * 16 + 4 * (lane >> 4) + r;
         if (i < d.m && j < d.n) {
           double* cp = d.C + i + (long)j * d.ldc;
           const double v = alpha * (double)acc[qa][qb][r];
@@ -663,7 +669,7 @@ __global__ __launch_bounds__(512, 4) void k_gemm128_mix_w8(const GemmDescMix* de
       for (int qa = 0; qa < 4; ++qa)
 #pragma unroll
         for (int qb = 0; qb < 2; ++qb)
-          acc[qa][qb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[qa], b[qb], acc[qa][qb], 0, 0, 0);
+          acc[qa][qb] = __builtin_amdgcn_mfma_f32_16x16x4f32(b[qb], a[qa], acc[qa][qb], 0, 0, 0);
     }
     if (more) sstore(buf ^ 1);
     __syncthreads();
@@ -675,8 +681,8 @@ __global__ __launch_bounds__(512, 4) void k_gemm128_mix_w8(const GemmDescMix* de
     for (int qb = 0; qb < 2; ++qb)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int i = m0 + wm + qa * 16 + 4 * (lane >> 4) + r;
-        const int j = n0 + wn + qb * 16 + (lane & 15);
+        const int i = m0 + wm + qa * 16 + (lane & 15);
+        const int j = n0 + wn + qb * 16 + 4 * (lane >> 4) + r;
         if (i < d.m && j < d.n) {
           double* cp = d.C + i + (long)j * d.ldc;
           const double v = alpha * (double)acc[qa][qb][r];
