@@ -135,7 +135,7 @@ def kernel_rates(kt: dict, top: int = 20) -> dict:
         if name.startswith("graph:") or rec["ms"] <= 0:
             continue
         if name.startswith(MFMA_KERNELS) and rec["flops"] > 0:
-            peak = FP32_PEAK_TFLOPS if "_mix" in name else FP64_PEAK_TFLOPS
+            peak = FP32_PEAK_TFLOPS if ("_mix" in name or "_f32" in name) else FP64_PEAK_TFLOPS
             tf = rec["flops"] / (rec["ms"] * 1e-3) / 1e12
             out[name] = {"TFLOP/s": round(tf, 2), "frac": round(tf / peak, 3), "calls": rec["calls"]}
         elif rec["bytes"] > 0:

@@ -112,6 +112,14 @@ struct GemmDescMix {     // FP64 A, FP32 B, FP64 C (FP32 local operators)
   const int* acol = nullptr;
 };
 
+struct GemmDescF32 {     // FP32 A and B, FP64 C (FP32 local operators, FP32 accumulation)
+  const float* A;
+  const float* B;
+  double* C;
+  int m, n, k;
+  int lda, ldb, ldc;
+};
+
 struct MatDesc {         // one square or rectangular column-major block
   double* A;
   int m, n, ld;
@@ -144,6 +152,10 @@ double probe_mfma_f64(int iters, hipStream_t s);
 void gemm_batched_fixed(const GemmDesc* d_desc, const double* X, const int* idx, const long* off, int batch,
                         int max_m, int max_n, bool transA, bool transB, double alpha, double beta, hipStream_t s,
                         int variant);
+// C = alpha A B + beta C with FP32 A and B (FP32 MFMA and accumulation):
+// the same products and k order as gemm_mix_batched on A rounded to FP32
+void gemm_f32_batched(const GemmDescF32* d_desc, int batch, int max_m, int max_n, double alpha, double beta,
+                      hipStream_t s, double flops);
 // X, idx, off (optional): the same row gather of the A operands as in
 // gemm_batched_gather
 void gemm_mix_batched(const GemmDescMix* d_desc, int batch, int max_m, int max_n, double alpha, double beta,

@@ -157,6 +157,8 @@ struct MultiWS {
   DBuf<double> gvpart;                // split-k partial sums of W^T r (b == 1)
   DBuf<GemmDesc> dVt, dV, dYt, dY, dP, dE0a, dE0b, dWt, dEW, dW;
   DBuf<GemmDescMix> dP32;             // FP32 local operators (b > 1)
+  DBuf<float> Xs32;                   // restricted rows rounded to FP32 (b > 1, FP32 local operators)
+  DBuf<GemmDescF32> dP32f;
   int maxk = 0, maxm = 0, maxns = 0;
   double flV = 0, flY = 0, flP = 0, flE0 = 0, flW = 0, flEW = 0;   // algorithmic flops per product
 };
@@ -448,6 +450,14 @@ void build_ws(awg_ctx& c, MultiWS& w, int b) {
       pm[q] = GemmDescMix{w.Xs.p + so, c.P32.p + c.sqoff[q], w.Os.p + so, b, nsq, nsq, b, nsq, b};
     }
     w.dP32.upload(pm, s);
+    w.Xs32.alloc(c.sumns * b);
+    std::vector<GemmDescF32> pf(c.N);
+    for (int q = 0; q < c.N; ++q) {
+      const int nsq = c.ns[q];
+      const long so = c.h_subptr[q] * b;
+      pf[q] = GemmDescF32{w.Xs32.p + so, c.P32.p + c.sqoff[q], w.Os.p + so, b, nsq, nsq, b, nsq, b};
+    }
+    w.dP32f.upload(pf, s);
   }
   const int n0 = std::max(1, c.n0), nm = std::max(1, c.nminus);
   w.flE0 = 2.0 * c.n0 * (double)c.n0 * b;
@@ -542,10 +552,25 @@ void op_hnn(awg_ctx& c, MultiWS& w, const double* X, double* Yo, bool f32) {
                        c.subptr.p, w.Xs.p, w.Os.p);
     AWG_LAUNCH_CHECK();
   } else if (f32) {
-    restricted_product(c, w, "P32", X, [&](bool fused) {
-      if (fused) gemm_mix_batched(w.dP32, c.N, w.b, w.maxns, 1.0, 0.0, c.s, w.flP, X, c.subidx.p, c.subptr.p);
-      else gemm_mix_batched(w.dP32, c.N, w.b, w.maxns, 1.0, 0.0, c.s, w.flP);
-    });
+    // FP32 local product, three forms with identical results: the restricted
+    // FP64 rows written out or read in place and rounded while staged, or
+    // the rows written out in FP32 (half the operand bytes) for the FP32 GEMM
+    auto run = [&](int v) {
+      if (v == 0) {
+        l_gather(c.sumns, c.subidx, X, w.b, w.Xs, c.s);
+        gemm_mix_batched(w.dP32, c.N, w.b, w.maxns, 1.0, 0.0, c.s, w.flP);
+      } else if (v == 1) {
+        gemm_mix_batched(w.dP32, c.N, w.b, w.maxns, 1.0, 0.0, c.s, w.flP, X, c.subidx.p, c.subptr.p);
+      } else {
+        l_gather_f32(c.sumns, c.subidx, X, w.b, w.Xs32, c.s);
+        gemm_f32_batched(w.dP32f, c.N, w.b, w.maxns, 1.0, 0.0, c.s, w.flP);
+      }
+    };
+    const std::string key = "restrict:P32:b=" + std::to_string(w.b) + ":sumns=" + std::to_string(c.sumns) +
+                            ":N=" + std::to_string(c.N);
+    int v = tune_lookup(key);
+    if (v < 0) v = tune_pick(key, 3, run, c.s);
+    run(v);
   } else if (w.b > 1) {
     bmm_restricted(c, w, w.dP, X, w.maxns, w.maxns, w.flP, "P");
   } else {

@@ -37,6 +37,8 @@ void l_spmm(int n, long nnz, const int* rowptr, const int* col, const double* va
 int spmm_groups(int n, long nnz, const int* rowptr, const int* col, const double* val, SpmmGroups& g,
                 hipStream_t s);
 void l_gather(long tot, const int* sub_idx, const double* X, int b, double* Xs, hipStream_t s);
+// the same rows rounded to FP32 (the operand of the FP32 local products)
+void l_gather_f32(long tot, const int* sub_idx, const double* X, int b, float* Xs, hipStream_t s);
 void l_scatter(int n, long tot, const int* inv_ptr, const int* inv_sub, const int* inv_loc, const long* sub_ptr,
                const double* Zs, int b, double* Y, double alpha, double beta, hipStream_t s);
 // part: DOT_CHUNKS * b scratch doubles

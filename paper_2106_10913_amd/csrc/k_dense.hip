@@ -709,6 +709,94 @@ void gemm_mix_batched(const GemmDescMix* d_desc, int batch, int max_m, int max_n
   run(v);
 }
 
+// FP32 A and B (A already rounded, e.g. by l_gather_f32): 128 x 128 tiles,
+// eight wavefronts of 64 x 32, k staged in LDS 32 deep (half the barriers per
+// flop of the mixed kernels); same MFMA sequence per output as
+// k_gemm128_mix_w8 (bit-identical to it: the k tail past K adds zero products)
+__global__ __launch_bounds__(512, 4) void k_gemm128_f32_w8(const GemmDescF32* descs, double alpha, double beta) {
+  const GemmDescF32 d = descs[blockIdx.z];
+  const int m0 = blockIdx.x * 128, n0 = blockIdx.y * 128;
+  if (m0 >= d.m || n0 >= d.n) return;
+  __shared__ float As[2][32][132];
+  __shared__ float Bs[2][32][132];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wm = (wave & 1) * 64, wn = (wave >> 1) * 32;
+  v4f acc[4][2];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = (v4f){0.f, 0.f, 0.f, 0.f};
+  float ra[8], rb[8];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const int e = tid + r * 512;
+      const int i = e & 127, kk = e >> 7;
+      const int gi = m0 + i, gk = k0 + kk;
+      ra[r] = (gi < d.m && gk < d.k) ? d.A[gi + (long)gk * d.lda] : 0.f;
+      const int kb = e & 31, j = e >> 5;
+      const int gj = n0 + j, gkb = k0 + kb;
+      rb[r] = (gj < d.n && gkb < d.k) ? d.B[gkb + (long)gj * d.ldb] : 0.f;
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const int e = tid + r * 512;
+      As[buf][e >> 7][e & 127] = ra[r];
+      Bs[buf][e & 31][e >> 5] = rb[r];
+    }
+  };
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  int buf = 0;
+  for (int k0 = 0; k0 < d.k; k0 += 32) {
+    const bool more = k0 + 32 < d.k;
+    if (more) gload(k0 + 32);
+#pragma unroll
+    for (int kk = 0; kk < 32; kk += 4) {
+      const int kr = kk + (lane >> 4), c = lane & 15;
+      float a[4], b[2];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) a[q] = As[buf][kr][wm + q * 16 + c];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) b[q] = Bs[buf][kr][wn + q * 16 + c];
+#pragma unroll
+      for (int qa = 0; qa < 4; ++qa)
+#pragma unroll
+        for (int qb = 0; qb < 2; ++qb)
+          acc[qa][qb] = __builtin_amdgcn_mfma_f32_16x16x4f32(b[qb], a[qa], acc[qa][qb], 0, 0, 0);
+    }
+    if (more) sstore(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+#pragma unroll
+  for (int qa = 0; qa < 4; ++qa)
+#pragma unroll
+    for (int qb = 0; qb < 2; ++qb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = m0 + wm + qa * 16 + (lane & 15);
+        const int j = n0 + wn + qb * 16 + 4 * (lane >> 4) + r;
+        if (i < d.m && j < d.n) {
+          double* cp = d.C + i + (long)j * d.ldc;
+          const double v = alpha * (double)acc[qa][qb][r];
+          *cp = (beta == 0.0) ? v : v + beta * *cp;
+        }
+      }
+}
+
+void gemm_f32_batched(const GemmDescF32* d_desc, int batch, int max_m, int max_n, double alpha, double beta,
+                      hipStream_t s, double flops) {
+  if (batch <= 0 || max_m <= 0 || max_n <= 0) return;
+  KScope kt("k_gemm128_f32_w8:P", s, 0.0, flops);
+  hipLaunchKernelGGL(k_gemm128_f32_w8, dim3(cdiv(max_m, 128), cdiv(max_n, 128), batch), dim3(512), 0, s, d_desc,
+                     alpha, beta);
+  AWG_LAUNCH_CHECK();
+}
+
 template <class DF>
 static const char* gemm_name(bool tA, bool tB);
 template <>

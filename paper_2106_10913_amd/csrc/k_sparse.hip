@@ -466,6 +466,28 @@ __global__ __launch_bounds__(256) void k_gather2(long tot, const int* __restrict
   Xs[p * b2 + c] = X[src + c];
 }
 
+// Xs[p, :] = (float) X[sub_idx[p], :] (round to nearest), one wavefront per
+// row segment of 128 columns
+__global__ __launch_bounds__(256) void k_gather2_f32(long tot, const int* __restrict__ sub_idx,
+                                                     const double2* __restrict__ X, int b2, float2* Xs, int nchunk) {
+  const long w = (long)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const long p = w / nchunk;
+  if (p >= tot) return;
+  const int c = (int)(w - p * nchunk) * 64 + (threadIdx.x & 63);
+  const long src = (long)sub_idx[p] * b2;
+  if (c >= b2) return;
+  const double2 x = X[src + c];
+  Xs[p * b2 + c] = make_float2((float)x.x, (float)x.y);
+}
+
+__global__ void k_gather_f32(long tot, const int* sub_idx, const double* X, int b, float* Xs) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= tot * b) return;
+  const long p = e / b;
+  const int c = (int)(e - p * b);
+  Xs[e] = (float)X[(long)sub_idx[p] * b + c];
+}
+
 __global__ __launch_bounds__(256) void k_scatter2(int n, const int* __restrict__ inv_ptr, const int* __restrict__ inv_sub,
                                                   const int* __restrict__ inv_loc, const long* __restrict__ sub_ptr,
                                                   const double2* __restrict__ Zs, int b2, double2* Y, double alpha,
@@ -870,6 +892,19 @@ void l_gather(long tot, const int* sub_idx, const double* X, int b, double* Xs, 
     return;
   }
   hipLaunchKernelGGL(k_gather, dim3(grid1(tot * b)), dim3(256), 0, s, tot, sub_idx, X, b, Xs);
+  AWG_LAUNCH_CHECK();
+}
+void l_gather_f32(long tot, const int* sub_idx, const double* X, int b, float* Xs, hipStream_t s) {
+  if (tot == 0 || b == 0) return;
+  KScope kt("k_gather_f32", s, 12.0 * tot * (double)b + 4.0 * tot, 0.0);
+  if ((b & 1) == 0 && ((uintptr_t)X & 15) == 0 && ((uintptr_t)Xs & 7) == 0) {
+    const int b2 = b / 2, nchunk = (int)cdiv(b2, 64);
+    hipLaunchKernelGGL(k_gather2_f32, dim3(cdiv(tot * nchunk, 4)), dim3(256), 0, s, tot, sub_idx, (const double2*)X,
+                       b2, (float2*)Xs, nchunk);
+    AWG_LAUNCH_CHECK();
+    return;
+  }
+  hipLaunchKernelGGL(k_gather_f32, dim3(grid1(tot * b)), dim3(256), 0, s, tot, sub_idx, X, b, Xs);
   AWG_LAUNCH_CHECK();
 }
 void l_scatter(int n, long tot, const int* inv_ptr, const int* inv_sub, const int* inv_loc, const long* sub_ptr,
