@@ -106,9 +106,9 @@ MFMA_KERNELS = ("k_gemm",)
 # were taken on; otherwise the bench reports traffic = null.
 TRAFFIC = {
     "k_gemm128w8<DescArray,N,N>:P": {
-        "bytes_per_launch": 1.6293e10,
+        "bytes_per_launch": 1.6332e10,
         "source": "paper_2106_10913_amd/csrc/k_dense.hip",
-        "sha256": "9d450b1a95936478607b3d622a07120c296b3651e14154839d5b73082a51cc66",
+        "sha256": "2f70e191bf1ace2881f5bffd7f3534771a233a12c920c1f329f47467c980badf",
         "workload": "q1_2d_diffusion_256x256_box8x8_overlap2_tau0.1",
     },
 }
