@@ -958,16 +958,8 @@ __global__ __launch_bounds__(256) void k_gemv_t(const GemmDesc* descs, double al
   const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (j >= d.m) return;
   const double* a = d.A + (long)j * d.lda;
-  // eight independent partial sums per lane (rows lane + 64 (8t + u)), so
-  // that eight loads are in flight; fixed order, deterministic
-  double p[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  int i = lane;
-  for (; i + 448 < d.k; i += 512) {
-#pragma unroll
-    for (int u = 0; u < 8; ++u) p[u] += a[i + 64 * u] * d.B[i + 64 * u];
-  }
-  for (int u = 0; i < d.k; i += 64, ++u) p[u] += a[i] * d.B[i];
-  double acc = ((p[0] + p[1]) + (p[2] + p[3])) + ((p[4] + p[5]) + (p[6] + p[7]));
+  double acc = 0.0;
+  for (int i = lane; i < d.k; i += 64) acc += a[i] * d.B[i];
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
   if (lane == 0) {
