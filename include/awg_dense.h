@@ -36,14 +36,15 @@ int awg_dense_gemm(int32_t batch, int32_t m, int32_t n, int32_t k, int32_t trans
  * variant: -1 = autotuned (measured on the first call with beta = 0 for this
  * shape), 0 = 64x64 tiles, 1 = 128x128 tiles with 4 wavefronts, 2 = 128x128
  * tiles with 8 wavefronts, 3 and 4 = 32x32 blocks per wavefront without LDS
- * with 16 or 32 k values per load batch (only for transA = transB = 0;
+ * with 16 or 32 k values per load batch, 5 = the same blocks with the B panel
+ * shared by the workgroup through LDS (3..5 only for transA = transB = 0;
  * otherwise variant 2 runs).  Every variant returns bit-identical results.
  * arows: NULL, or a device array of batch x k int32 (requires transA = 0):
  * column j of A_b is then A + arows[b k + j] * lda (strideA is ignored), i.e.
  * row arows[b k + j] of a row-major matrix with lda columns; the caller
  * guarantees that every index addresses memory inside A.
  * Returns AWG_ERR_ARG for negative sizes, null pointers, a variant outside
- * -1..4, or arows with transA = 1. */
+ * -1..5, or arows with transA = 1. */
 int awg_dense_gemm_ex(int32_t batch, int32_t m, int32_t n, int32_t k, int32_t transA, int32_t transB,
                       double alpha, const double* A, int32_t lda, int64_t strideA, const int32_t* arows,
                       const double* B, int32_t ldb, int64_t strideB, double beta, double* C, int32_t ldc,

@@ -64,7 +64,7 @@ int awg_dense_gemm_ex(int32_t batch, int32_t m, int32_t n, int32_t k, int32_t tr
                       double alpha, const double* A, int32_t lda, int64_t strideA, const int32_t* arows,
                       const double* B, int32_t ldb, int64_t strideB, double beta, double* C, int32_t ldc,
                       int64_t strideC, int32_t variant, void* stream) {
-  if (batch <= 0 || m < 0 || n < 0 || k < 0 || !A || !B || !C || variant < -1 || variant > 4 ||
+  if (batch <= 0 || m < 0 || n < 0 || k < 0 || !A || !B || !C || variant < -1 || variant > 5 ||
       (arows && transA))
     return AWG_ERR_ARG;
   hipStream_t s = (hipStream_t)stream;

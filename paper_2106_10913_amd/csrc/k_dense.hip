@@ -506,6 +506,107 @@ __global__ __launch_bounds__(256) void k_gemm_skinny(DF df, double alpha, double
       }
 }
 
+// k_gemm_skinny with the 16 x 32 B panel of each k step loaded once per
+// workgroup into LDS (double-buffered) instead of once per wavefront: the
+// four wavefronts (128 rows of A) share it.  Same MFMA sequence per output.
+template <class DF>
+__global__ __launch_bounds__(256) void k_gemm_skinny_lds(DF df, double alpha, double beta) {
+  const GemmDesc d = df(blockIdx.z);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, tid = threadIdx.x;
+  const int m0 = blockIdx.x * 128 + wave * 32, n0 = blockIdx.y * 32;
+  if (blockIdx.x * 128 >= d.m || n0 >= d.n) return;     // whole workgroup
+  const bool live = m0 < d.m;                          // this wavefront has rows
+  const int r16 = lane & 15, kq = lane >> 4;
+  __shared__ double Bs[2][16][33];
+  v4d acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = (v4d){0.0, 0.0, 0.0, 0.0};
+  auto colofs = [&](int k0, long* o) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int k = k0 + 4 * t + kq;
+      o[t] = k < d.k ? (gathers_a<DF>::value ? (long)d.acol[k] * d.lda : (long)k * d.lda) : -1;
+    }
+  };
+  auto loadA = [&](const long* o, double* ra) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int m = m0 + 16 * q + r16;
+        ra[2 * t + q] = (live && o[t] >= 0 && m < d.m) ? d.A[m + o[t]] : 0.0;
+      }
+  };
+  // B panel element (kb, j) of step k0: thread e = tid + 256 r, kb = e & 15, j = e >> 4
+  auto loadB = [&](int k0, double* rb) {
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      const int e = tid + 256 * r, kb = e & 15, j = e >> 4;
+      const int k = k0 + kb, n = n0 + j;
+      rb[r] = (k < d.k && n < d.n) ? d.B[k + (long)n * d.ldb] : 0.0;
+    }
+  };
+  auto storeB = [&](int buf, const double* rb) {
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      const int e = tid + 256 * r;
+      Bs[buf][e & 15][e >> 4] = rb[r];
+    }
+  };
+  long oc[4], on[4];
+  double ca[8], na[8], rbn[2];
+  colofs(0, oc);
+  loadA(oc, ca);
+  loadB(0, rbn);
+  storeB(0, rbn);
+  colofs(16, on);
+  __syncthreads();
+  int buf = 0;
+  for (int k0 = 0; k0 < d.k; k0 += 16) {
+    const bool more = k0 + 16 < d.k;
+    if (more) {
+      loadA(on, na);
+      loadB(k0 + 16, rbn);
+      colofs(k0 + 32, on);
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      double cb[2];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) cb[q] = Bs[buf][4 * t + kq][16 * q + r16];
+#pragma unroll
+      for (int qa = 0; qa < 2; ++qa)
+#pragma unroll
+        for (int qb = 0; qb < 2; ++qb)
+          acc[qa][qb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ca[2 * t + qa], cb[qb], acc[qa][qb], 0, 0, 0);
+    }
+    if (more) {
+      storeB(buf ^ 1, rbn);
+#pragma unroll
+      for (int r = 0; r < 8; ++r) ca[r] = na[r];
+    }
+    __syncthreads();
+    buf ^= 1;
+  }
+  if (!live) return;
+#pragma unroll
+  for (int qa = 0; qa < 2; ++qa)
+#pragma unroll
+    for (int qb = 0; qb < 2; ++qb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = m0 + qa * 16 + kq + 4 * r;
+        const int j = n0 + qb * 16 + r16;
+        if (i < d.m && j < d.n) {
+          double* cp = d.C + i + (long)j * d.ldc;
+          const double v = alpha * acc[qa][qb][r];
+          *cp = (beta == 0.0) ? v : v + beta * *cp;
+        }
+      }
+}
+
 // ---------------------------------------------------------------------------
 // mixed-precision GEMM for FP32 local operators: C (FP64) = alpha A B + beta C
 // with A FP64 (rounded to FP32 when staged in LDS), B FP32, FP32 MFMA
@@ -829,7 +930,8 @@ static void launch_tiles(DF df, int batch, int max_m, int max_n, bool tA, bool t
   if (variant >= 3 && !tA && !tB && !lower) {
     const dim3 grid(cdiv(max_m, 128), cdiv(max_n, 32), batch);
     if (variant == 3) hipLaunchKernelGGL((k_gemm_skinny<DF, 16>), grid, dim3(256), 0, s, df, alpha, beta);
-    else hipLaunchKernelGGL((k_gemm_skinny<DF, 32>), grid, dim3(256), 0, s, df, alpha, beta);
+    else if (variant == 4) hipLaunchKernelGGL((k_gemm_skinny<DF, 32>), grid, dim3(256), 0, s, df, alpha, beta);
+    else hipLaunchKernelGGL((k_gemm_skinny_lds<DF>), grid, dim3(256), 0, s, df, alpha, beta);
     AWG_LAUNCH_CHECK();
     return;
   }
@@ -877,13 +979,14 @@ static void launch_gemm(DF df, int batch, int max_m, int max_n, bool tA, bool tB
                             std::to_string(max_m) + ":n=" + std::to_string(max_n) + ":batch=" + std::to_string(batch);
     int v = tune_lookup(key);
     // the skinny kernel is a candidate for untransposed products with N <= 64
-    const int nvar = (!tA && !tB && max_n <= 64) ? 5 : 3;
+    const int nvar = (!tA && !tB && max_n <= 64) ? 6 : 3;
     if (v < 0 && beta == 0.0 && !lower)
       v = tune_pick(key, nvar, [&](int w) { launch_tiles(df, batch, max_m, max_n, tA, tB, alpha, beta, lower, s, w); }, s);
     if (v >= 0) variant = v;
   }
   if (variant >= 3 && (tA || tB || lower)) variant = 2;
-  static const char* const prefix[5] = {"k_gemm", "k_gemm128", "k_gemm128w8", "k_gemm_skinny", "k_gemm_skinny32"};
+  static const char* const prefix[6] = {"k_gemm",        "k_gemm128",       "k_gemm128w8",
+                                        "k_gemm_skinny", "k_gemm_skinny32", "k_gemm_skinny_lds"};
   std::string nm = std::string(prefix[variant]) + (gemm_name<DF>(tA, tB) + 6);
   if (tag) nm += std::string(":") + tag;
   KScope kt(nm.c_str(), s, 0.0, flops);

@@ -70,7 +70,7 @@ def test_gemm_variants_bit_identical(gpu_lib, mnk):
     Ag = np.stack([X[idx[b]].T for b in range(batch)])          # (batch, m, k)
     ref = np.stack([-0.5 * (Ag[b] @ B[b]) + 2.0 * C0[b] for b in range(batch)])
     outs = []
-    for v in range(5):
+    for v in range(6):
         for gathered in (False, True):
             Cd = to_dev(C0)
             if gathered:
@@ -86,7 +86,7 @@ def test_gemm_variants_bit_identical(gpu_lib, mnk):
         A = rng.standard_normal((batch, k, m) if tA else (batch, m, k))
         Bt = rng.standard_normal((batch, n, k) if tB else (batch, k, n))
         res = []
-        for v in range(5):
+        for v in range(6):
             Cd = to_dev(C0)
             gpu_lib.dense_gemm_ex(to_dev(A), to_dev(Bt), Cd, alpha=1.0, beta=0.0, transA=tA, transB=tB, variant=v)
             res.append(from_dev(Cd))
@@ -99,7 +99,7 @@ def test_gemm_ex_rejects_bad_arguments(gpu_lib):
     from paper_2106_10913_amd.awg import AWGError
     A = torch.zeros((1, 4, 4), dtype=torch.float64, device="cuda")
     idx = torch.zeros((1, 4), dtype=torch.int32, device="cuda")
-    for kw in [dict(variant=5), dict(variant=-2), dict(transA=True, arows=idx)]:
+    for kw in [dict(variant=6), dict(variant=-2), dict(transA=True, arows=idx)]:
         with pytest.raises(AWGError):
             gpu_lib.dense_gemm_ex(A, A, A.clone(), **kw)
 
