@@ -916,7 +916,17 @@ template <>
 const char* gemm_name<Syr2kUpdate>(bool, bool) { return "k_gemm<Syr2kUpdate,N,T>"; }
 
 // 128x128 tiles pay off for the long-k products with explicit descriptors;
-// the k = 32/64 updates inside the factorisations keep 64x64 tiles
+// the k = 32/64 updates inside the factorisations keep 64x64 tiles unless
+// default_tiles says otherwise (they accumulate into C, so they cannot be
+// timed by repeated launches)
+template <class DF>
+static int default_tiles(int max_m) { return 0; }
+template <>
+int default_tiles<TrsmUpdate>(int max_m) { return max_m >= 128 ? 2 : 0; }
+template <>
+int default_tiles<CholUpdate>(int max_m) { return max_m >= 128 ? 2 : 0; }
+template <>
+int default_tiles<Syr2kUpdate>(int max_m) { return max_m >= 128 ? 2 : 0; }
 template <class DF>
 static bool use_big_tiles() { return false; }
 template <>
@@ -972,7 +982,7 @@ template <class DF>
 static void launch_gemm(DF df, int batch, int max_m, int max_n, bool tA, bool tB, double alpha, double beta,
                         bool lower, hipStream_t s, double flops = 0.0, const char* tag = nullptr) {
   if (batch <= 0 || max_m <= 0 || max_n <= 0) return;
-  int variant = (use_big_tiles<DF>() && max_m >= 128) ? 1 : 0;
+  int variant = (use_big_tiles<DF>() && max_m >= 128) ? 1 : default_tiles<DF>(max_m);
   if (use_big_tiles<DF>() && tag) {
     const std::string key = std::string("gemm:") + tag + (gathers_a<DF>::value ? "g" : "") + (tA ? ":T" : ":N") +
                             (tB ? "T" : "N") + ":m=" +
