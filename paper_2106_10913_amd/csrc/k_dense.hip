@@ -1244,20 +1244,28 @@ constexpr int TRSM_NB = 64;
 // Solve the diagonal block: forward  X_j = L_jj^{-1} B_j
 //                           backward X_j = L_jj^{-T} B_j
 // one wavefront per 64 right-hand sides; L_jj and the B tile live in LDS.
-__global__ __launch_bounds__(64) void k_trsm_diag(const MatDesc* Ls, const MatDesc* Bs, int j, int backward) {
+// 64-row diagonal block of a blocked triangular solve for 64 right-hand
+// sides: the 256 threads load L and X into LDS together (16 independent
+// loads each), the first wavefront substitutes (one column per lane), and all
+// threads store
+__global__ __launch_bounds__(256) void k_trsm_diag(const MatDesc* Ls, const MatDesc* Bs, int j, int backward) {
   const MatDesc l = Ls[blockIdx.y], b = Bs[blockIdx.y];
   const int jb = min(TRSM_NB, l.n - j);
   const int c0 = blockIdx.x * 64;
   if (jb <= 0 || c0 >= b.n) return;
   __shared__ double L[TRSM_NB][TRSM_NB + 1];
   __shared__ double X[TRSM_NB][TRSM_NB + 1];   // X[row][col]
-  const int lane = threadIdx.x;
-  for (int c = 0; c < jb; ++c) L[lane][c] = (lane < jb && lane >= c) ? l.A[(j + lane) + (long)(j + c) * l.ld] : 0.0;
+  const int tid = threadIdx.x;
   const int nc = min(64, b.n - c0);
-  for (int c = 0; c < nc; ++c) X[lane][c] = (lane < jb) ? b.A[(j + lane) + (long)(c0 + c) * b.ld] : 0.0;
+#pragma unroll
+  for (int q = 0; q < TRSM_NB * TRSM_NB / 256; ++q) {
+    const int e = tid + 256 * q, r = e & (TRSM_NB - 1), c = e / TRSM_NB;
+    L[r][c] = (r < jb && c < jb && r >= c) ? l.A[(j + r) + (long)(j + c) * l.ld] : 0.0;
+    X[r][c] = (r < jb && c < nc) ? b.A[(j + r) + (long)(c0 + c) * b.ld] : 0.0;
+  }
   __syncthreads();
-  if (lane < nc) {
-    const int c = lane;
+  if (tid < nc) {
+    const int c = tid;
     if (!backward) {
       for (int r = 0; r < jb; ++r) {
         double v = X[r][c];
@@ -1273,8 +1281,11 @@ __global__ __launch_bounds__(64) void k_trsm_diag(const MatDesc* Ls, const MatDe
     }
   }
   __syncthreads();
-  if (lane < jb)
-    for (int c = 0; c < nc; ++c) b.A[(j + lane) + (long)(c0 + c) * b.ld] = X[lane][c];
+#pragma unroll
+  for (int q = 0; q < TRSM_NB * TRSM_NB / 256; ++q) {
+    const int e = tid + 256 * q, r = e & (TRSM_NB - 1), c = e / TRSM_NB;
+    if (r < jb && c < nc) b.A[(j + r) + (long)(c0 + c) * b.ld] = X[r][c];
+  }
 }
 
 void trsm_batched(const MatDesc* d_L, const MatDesc* d_B, const std::vector<int>& h_n,
@@ -1291,7 +1302,7 @@ void trsm_batched(const MatDesc* d_L, const MatDesc* d_B, const std::vector<int>
   for (int t = 0; t < nblk; ++t) {
     const int blk = trans ? nblk - 1 - t : t;
     const int j = blk * TRSM_NB;
-    hipLaunchKernelGGL(k_trsm_diag, dim3(cdiv(maxc, 64), batch), dim3(64), 0, s, d_L, d_B, j, (int)trans);
+    hipLaunchKernelGGL(k_trsm_diag, dim3(cdiv(maxc, 64), batch), dim3(256), 0, s, d_L, d_B, j, (int)trans);
     AWG_LAUNCH_CHECK();
     const int mrows = trans ? j : maxn - j - TRSM_NB;
     double fl = 0.0;
