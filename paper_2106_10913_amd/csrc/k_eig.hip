@@ -884,7 +884,8 @@ void tri_eigvecs(const TriEigArgs& a, const int* count, const long* lam_off, dou
 // ---------------------------------------------------------------------------
 // back-transformation Z <- H_0 H_1 ... H_{n-3} Z
 // ---------------------------------------------------------------------------
-constexpr int ORM_COLS = 8;
+constexpr int ORM_COLS = 4;     // columns of Z per workgroup (each column's sums are independent of it)
+constexpr int ORM_RPT = 8;      // rows per thread held in registers (n <= 2048), else read twice
 
 __global__ __launch_bounds__(256) void k_ormtr(const MatDesc* mats, const MatDesc* Zs, const double* tau,
                                                const long* off) {
@@ -905,14 +906,35 @@ __global__ __launch_bounds__(256) void k_ormtr(const MatDesc* mats, const MatDes
     const double tj = tau[o + j];
     if (tj == 0.0) continue;
     const double* v = M.A + (long)j * M.ld;    // v[j+1] = 1 stored explicitly
+    const bool inreg = n - (j + 1) <= 256 * ORM_RPT;
+    double vr[ORM_RPT];
+    if (inreg) {
+#pragma unroll
+      for (int u = 0; u < ORM_RPT; ++u) {
+        const int i = j + 1 + threadIdx.x + 256 * u;
+        vr[u] = i < n ? v[i] : 0.0;
+      }
+    }
     double dots[ORM_COLS];
 #pragma unroll
     for (int c = 0; c < ORM_COLS; ++c) dots[c] = 0.0;
-    for (int i = j + 1 + threadIdx.x; i < n; i += 256) {
-      const double vi = v[i];
+    if (inreg) {
 #pragma unroll
-      for (int c = 0; c < ORM_COLS; ++c)
-        if (c < nc) dots[c] += vi * zs[c * n + i];
+      for (int u = 0; u < ORM_RPT; ++u) {
+        const int i = j + 1 + threadIdx.x + 256 * u;
+        if (i < n) {
+#pragma unroll
+          for (int c = 0; c < ORM_COLS; ++c)
+            if (c < nc) dots[c] += vr[u] * zs[c * n + i];
+        }
+      }
+    } else {
+      for (int i = j + 1 + threadIdx.x; i < n; i += 256) {
+        const double vi = v[i];
+#pragma unroll
+        for (int c = 0; c < ORM_COLS; ++c)
+          if (c < nc) dots[c] += vi * zs[c * n + i];
+      }
     }
 #pragma unroll
     for (int c = 0; c < ORM_COLS; ++c) {
@@ -922,11 +944,23 @@ __global__ __launch_bounds__(256) void k_ormtr(const MatDesc* mats, const MatDes
     __syncthreads();
 #pragma unroll
     for (int c = 0; c < ORM_COLS; ++c) dots[c] = tj * ((red[0][c] + red[1][c]) + (red[2][c] + red[3][c]));
-    for (int i = j + 1 + threadIdx.x; i < n; i += 256) {
-      const double vi = v[i];
+    if (inreg) {
 #pragma unroll
-      for (int c = 0; c < ORM_COLS; ++c)
-        if (c < nc) zs[c * n + i] -= dots[c] * vi;
+      for (int u = 0; u < ORM_RPT; ++u) {
+        const int i = j + 1 + threadIdx.x + 256 * u;
+        if (i < n) {
+#pragma unroll
+          for (int c = 0; c < ORM_COLS; ++c)
+            if (c < nc) zs[c * n + i] -= dots[c] * vr[u];
+        }
+      }
+    } else {
+      for (int i = j + 1 + threadIdx.x; i < n; i += 256) {
+        const double vi = v[i];
+#pragma unroll
+        for (int c = 0; c < ORM_COLS; ++c)
+          if (c < nc) zs[c * n + i] -= dots[c] * vi;
+      }
     }
     __syncthreads();
   }
