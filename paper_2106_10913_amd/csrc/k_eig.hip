@@ -619,6 +619,7 @@ void tri_count(const TriEigArgs& a, const double* thr_in, int thr_mode, double e
 // eigenvectors of T by inverse iteration, one lane per eigenvalue
 // ---------------------------------------------------------------------------
 constexpr int INVIT_SWEEPS = 4;
+constexpr int INVIT_PF = 8;       // rows loaded ahead per block in the sweeps
 constexpr int INVIT_LANES = 64;
 
 // Modified Gram-Schmidt of vector xj (length n, rows lane, lane + 64, ...)
@@ -762,40 +763,85 @@ __global__ __launch_bounds__(64) void k_tri_vecs(TriEigArgs a, const int* count,
     }
     for (int sweep = 0; sweep < INVIT_SWEEPS; ++sweep) {
       if (act) {
-        // solve (T - lj I) y = x in place, then scale to unit max norm
-        // forward: the loads of row i+1 are issued before row i is finished
+        // solve (T - lj I) y = x in place, then scale to unit max norm.  The
+        // per-lane arrays exceed the L2, so both sweeps load INVIT_PF rows a
+        // block ahead of their use (the operations and their order are those
+        // of the plain row-by-row sweeps)
         double xi = X[lane];
-        double xn_next = n > 1 ? X[W + lane] : 0.0;
-        double pv_next = PV[lane], lf_next = LF[lane];
-        for (int i = 0; i < n - 1; ++i) {
-          const long o = i * W + lane;
-          double xn = xn_next;
-          const double pv = pv_next, lf = lf_next;
-          if (i + 2 < n) xn_next = X[o + 2 * W];
-          if (i + 1 < n - 1) { pv_next = PV[o + W]; lf_next = LF[o + W]; }
-          if (pv != 0.0) { const double tt = xi; xi = xn; xn = tt; }
-          X[o] = xi;
-          xi = xn - lf * xi;
+        {
+          double xb[INVIT_PF], pb[INVIT_PF], lb[INVIT_PF], xq[INVIT_PF], pq[INVIT_PF], lq[INVIT_PF];
+          auto ldf = [&](int i0, double* xr, double* pr, double* lr) {
+#pragma unroll
+            for (int u = 0; u < INVIT_PF; ++u) {
+              const int i = i0 + u;
+              const bool ok = i < n - 1;
+              xr[u] = ok ? X[(long)(i + 1) * W + lane] : 0.0;
+              pr[u] = ok ? PV[(long)i * W + lane] : 0.0;
+              lr[u] = ok ? LF[(long)i * W + lane] : 0.0;
+            }
+          };
+          ldf(0, xb, pb, lb);
+          for (int i0 = 0; i0 < n - 1; i0 += INVIT_PF) {
+            if (i0 + INVIT_PF < n - 1) ldf(i0 + INVIT_PF, xq, pq, lq);
+#pragma unroll
+            for (int u = 0; u < INVIT_PF; ++u) {
+              const int i = i0 + u;
+              if (i < n - 1) {
+                double xn = xb[u];
+                if (pb[u] != 0.0) { const double tt = xi; xi = xn; xn = tt; }
+                X[(long)i * W + lane] = xi;
+                xi = xn - lb[u] * xi;
+              }
+            }
+#pragma unroll
+            for (int u = 0; u < INVIT_PF; ++u) {
+              xb[u] = xq[u];
+              pb[u] = pq[u];
+              lb[u] = lq[u];
+            }
+          }
         }
         double x1 = xi / U0[(n - 1) * W + lane];
         X[(n - 1) * W + lane] = x1;
         double x2 = 0.0;
         double mx = fabs(x1);
         if (n > 1) {
-          long o = (long)(n - 2) * W + lane;
-          double xo = X[o], u0 = U0[o], u1 = U1[o], u2 = U2[o];
-          for (int i = n - 2; i >= 0; --i) {
-            const double cx = xo, c0 = u0, c1 = u1, c2 = u2;
-            const long oc = o;
-            if (i > 0) {
-              o -= W;
-              xo = X[o]; u0 = U0[o]; u1 = U1[o]; u2 = U2[o];
+          // rows n-2 down to 0 in blocks of INVIT_PF
+          double xb[INVIT_PF], ab[INVIT_PF], bb[INVIT_PF], cb[INVIT_PF];
+          double xq[INVIT_PF], aq[INVIT_PF], bq[INVIT_PF], cq[INVIT_PF];
+          auto ldb = [&](int i0, double* xr, double* a0, double* a1, double* a2) {
+#pragma unroll
+            for (int u = 0; u < INVIT_PF; ++u) {
+              const int i = i0 - u;
+              const long o = (long)i * W + lane;
+              const bool ok = i >= 0;
+              xr[u] = ok ? X[o] : 0.0;
+              a0[u] = ok ? U0[o] : 1.0;
+              a1[u] = ok ? U1[o] : 0.0;
+              a2[u] = ok ? U2[o] : 0.0;
             }
-            const double v = (cx - c1 * x1 - c2 * x2) / c0;
-            X[oc] = v;
-            x2 = x1;
-            x1 = v;
-            mx = fmax(mx, fabs(v));
+          };
+          ldb(n - 2, xb, ab, bb, cb);
+          for (int i0 = n - 2; i0 >= 0; i0 -= INVIT_PF) {
+            if (i0 - INVIT_PF >= 0) ldb(i0 - INVIT_PF, xq, aq, bq, cq);
+#pragma unroll
+            for (int u = 0; u < INVIT_PF; ++u) {
+              const int i = i0 - u;
+              if (i >= 0) {
+                const double v = (xb[u] - bb[u] * x1 - cb[u] * x2) / ab[u];
+                X[(long)i * W + lane] = v;
+                x2 = x1;
+                x1 = v;
+                mx = fmax(mx, fabs(v));
+              }
+            }
+#pragma unroll
+            for (int u = 0; u < INVIT_PF; ++u) {
+              xb[u] = xq[u];
+              ab[u] = aq[u];
+              bb[u] = bq[u];
+              cb[u] = cq[u];
+            }
           }
         }
         const double inv = mx > 0.0 ? 1.0 / mx : 1.0;
