@@ -462,8 +462,8 @@ void sytrd_batched(const MatDesc* d_mats, const std::vector<int>& h_n, double* d
       {
         const int ntr = (rows + SYMV_T - 1) / SYMV_T;
         const int ntiles = std::max(1, ntr * (ntr + 1) / 2);
-        // about 4 tiles per workgroup once the trailing matrices are large
-        const int gx = ntiles <= 64 ? ntiles : (ntiles + 3) / 4;
+        // 2 or 3 tiles per workgroup once the trailing matrices are large
+        const int gx = ntiles <= 64 ? ntiles : ntiles <= 256 ? (ntiles + 1) / 2 : (ntiles + 2) / 3;
         // plus the workgroups of the panel dot products (none for the first column)
         const int gwy = jj > 0 ? TRD_WYG * (int)cdiv(std::max(1, rows), TRD_YCH) : 0;
         KScope kt("k_trd_symv", s, 0.5 * tb, tb / 4.0);
