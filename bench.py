@@ -106,9 +106,9 @@ MFMA_KERNELS = ("k_gemm",)
 # were taken on; otherwise the bench reports traffic = null.
 TRAFFIC = {
     "k_gemm128w8<DescArray,N,N>:P": {
-        "bytes_per_launch": 1.6332e10,
+        "bytes_per_launch": 1.6497e10,
         "source": "paper_2106_10913_amd/csrc/k_dense.hip",
-        "sha256": "2f70e191bf1ace2881f5bffd7f3534771a233a12c920c1f329f47467c980badf",
+        "sha256": "e3b9f6defd90e46378e1fc4904f983553a444a42dbab3df4d02fceb3be0338b8",
         "workload": "q1_2d_diffusion_256x256_box8x8_overlap2_tau0.1",
     },
 }
