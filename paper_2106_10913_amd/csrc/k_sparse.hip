@@ -590,35 +590,100 @@ __global__ void k_copy_mat(const MatDesc* src, const MatDesc* dst) {
 
 // M <- diag(dl) M diag(dr) (dl/dr: per-block vectors at offsets), optional
 // symmetrisation (M + M^T)/2 done by the (r >= c) thread for both entries.
-__global__ void k_scale_sym(const MatDesc* mats, const long* voff, const double* dl, int inv, int symmetrize) {
+// Pairs of 32 x 32 tiles (I, J) and (J, I), I >= J, staged in LDS so that
+// both triangles are read and written coalesced; each element pair
+// (r, c), (c, r) with r >= c gets  a = A_rc, b = A_cr,  a = b = (a + b) / 2 when
+// symmetrising, then both times d_r d_c (or divided by it).  A workgroup
+// walks tile pairs blockIdx.x, blockIdx.x + gridDim.x, ... of its matrix.
+__global__ __launch_bounds__(256) void k_scale_sym(const MatDesc* mats, const long* voff, const double* dl, int inv,
+                                                   int symmetrize) {
   const MatDesc M = mats[blockIdx.y];
   const double* d = dl ? dl + voff[blockIdx.y] : nullptr;
-  const long tot = (long)M.n * M.n;
-  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += (long)gridDim.x * blockDim.x) {
-    const int r = (int)(e % M.n), c = (int)(e / M.n);
-    if (r < c) continue;
-    double a = M.A[r + (long)c * M.ld];
-    double b = M.A[c + (long)r * M.ld];
-    if (symmetrize) { a = 0.5 * (a + b); b = a; }
-    if (d) {
-      const double f = inv ? 1.0 / (d[r] * d[c]) : d[r] * d[c];
-      a *= f;
-      b *= f;
+  const int n = M.n;
+  const int nt = (n + 31) / 32;
+  const int ntiles = nt * (nt + 1) / 2;
+  __shared__ double TA[32][33];
+  __shared__ double TB[32][33];
+  const int tid = threadIdx.x, x = tid & 31, y0 = tid >> 5;
+  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    int I = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+    while ((I + 1) * (I + 2) / 2 <= t) ++I;
+    while (I * (I + 1) / 2 > t) --I;
+    const int J = t - I * (I + 1) / 2;
+    const int r0 = 32 * I, c0 = 32 * J;
+    // TA[x][y] = A[r0 + x][c0 + y], TB[x][y] = A[c0 + x][r0 + y]
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int y = y0 + 8 * u;
+      TA[x][y] = (r0 + x < n && c0 + y < n) ? M.A[(r0 + x) + (long)(c0 + y) * M.ld] : 0.0;
+      TB[x][y] = (c0 + x < n && r0 + y < n) ? M.A[(c0 + x) + (long)(r0 + y) * M.ld] : 0.0;
     }
-    M.A[r + (long)c * M.ld] = a;
-    M.A[c + (long)r * M.ld] = b;
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int rr = x, cc = y0 + 8 * u;
+      const int r = r0 + rr, c = c0 + cc;
+      if (r < n && c < n && r >= c) {
+        double a = TA[rr][cc];
+        double b = TB[cc][rr];
+        if (symmetrize) { a = 0.5 * (a + b); b = a; }
+        if (d) {
+          const double f = inv ? 1.0 / (d[r] * d[c]) : d[r] * d[c];
+          a *= f;
+          b *= f;
+        }
+        TA[rr][cc] = a;
+        TB[cc][rr] = b;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int y = y0 + 8 * u;
+      if (I == J) {
+        // one block: the lower part (x >= y) from TA, the upper part from TB
+        if (r0 + x < n && c0 + y < n) M.A[(r0 + x) + (long)(c0 + y) * M.ld] = x >= y ? TA[x][y] : TB[x][y];
+      } else {
+        if (r0 + x < n && c0 + y < n) M.A[(r0 + x) + (long)(c0 + y) * M.ld] = TA[x][y];
+        if (c0 + x < n && r0 + y < n) M.A[(c0 + x) + (long)(r0 + y) * M.ld] = TB[x][y];
+      }
+    }
+    __syncthreads();
   }
 }
 
-__global__ void k_transpose_inplace(const MatDesc* mats) {
+// In-place transpose by pairs of 32 x 32 tiles (I, J), (J, I), I >= J, staged
+// in LDS (coalesced reads and writes); a workgroup walks tile pairs
+// blockIdx.x, blockIdx.x + gridDim.x, ... of its matrix
+__global__ __launch_bounds__(256) void k_transpose_inplace(const MatDesc* mats) {
   const MatDesc M = mats[blockIdx.y];
-  const long tot = (long)M.n * M.n;
-  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += (long)gridDim.x * blockDim.x) {
-    const int r = (int)(e % M.n), c = (int)(e / M.n);
-    if (r <= c) continue;
-    const double a = M.A[r + (long)c * M.ld];
-    M.A[r + (long)c * M.ld] = M.A[c + (long)r * M.ld];
-    M.A[c + (long)r * M.ld] = a;
+  const int n = M.n;
+  const int nt = (n + 31) / 32;
+  const int ntiles = nt * (nt + 1) / 2;
+  __shared__ double TA[32][33];
+  __shared__ double TB[32][33];
+  const int tid = threadIdx.x, x = tid & 31, y0 = tid >> 5;
+  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    int I = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+    while ((I + 1) * (I + 2) / 2 <= t) ++I;
+    while (I * (I + 1) / 2 > t) --I;
+    const int J = t - I * (I + 1) / 2;
+    const int r0 = 32 * I, c0 = 32 * J;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int y = y0 + 8 * u;
+      TA[x][y] = (r0 + x < n && c0 + y < n) ? M.A[(r0 + x) + (long)(c0 + y) * M.ld] : 0.0;
+      TB[x][y] = (c0 + x < n && r0 + y < n) ? M.A[(c0 + x) + (long)(r0 + y) * M.ld] : 0.0;
+    }
+    __syncthreads();
+    // block (I, J) receives TB transposed, block (J, I) receives TA transposed
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int y = y0 + 8 * u;
+      if (r0 + x < n && c0 + y < n) M.A[(r0 + x) + (long)(c0 + y) * M.ld] = TB[y][x];
+      if (I != J && c0 + x < n && r0 + y < n) M.A[(c0 + x) + (long)(r0 + y) * M.ld] = TA[y][x];
+    }
+    __syncthreads();
   }
 }
 
