@@ -242,6 +242,10 @@ class AWGSetup:
     w_info: dict
     E0_keep: np.ndarray = None    # kept coarse vectors (gram_keep); all unless dependent
     EW_keep: np.ndarray = None
+    Lg: np.ndarray = None         # |strictly negative eigenvalues|, the columns of V_- (Vg)
+    C: np.ndarray = None          # capacitance L_-^{-1} - V_-^T W (H3,inex)
+    C_keep: np.ndarray = None
+    C_cho: tuple = None
 
     @property
     def n(self):
@@ -315,6 +319,33 @@ class AWGSetup:
         if self.n_minus:
             z = z + self.W @ self.EW_solve(self.W.T @ r)
         return z
+
+    # -- the other two second-coarse-space preconditioners (Section 4) ----
+    def C_solve(self, g):
+        """C^+ g for the capacitance C = L_-^{-1} - V_-^T A_+^{-1} V_- (kept columns)."""
+        out = np.zeros_like(g, dtype=np.float64)
+        out[self.C_keep] = sla.cho_solve(self.C_cho, g[self.C_keep])
+        return out
+
+    def apply_inex(self, r, h2=None):
+        """H3,inex r = H2 r + A_+^{-1} V_- C^{-1} V_-^T A_+^{-1} r with W = A_+^{-1} V_-
+        (Theorem on the AWG preconditioner with inexact coarse space, Section 4.2).
+        h2: a replacement for H2 (the pins use the exact A_+^{-1})."""
+        z = (h2 or self.H2)(r)
+        if self.n_minus:
+            z = z + self.W @ self.C_solve(self.W.T @ r)
+        return z
+
+    def apply_hyb(self, r, h2=None):
+        """H3,hyb r = Pi3 H2 Pi3^T r + W (W^T A W)^{-1} W^T r with
+        Pi3 = I - W (W^T A W)^{-1} W^T A (Definition of Pi_3 and H3, Section 4.3):
+        t = E_W^{-1} W^T r, y = H2 (r - A W t), z = y - W E_W^{-1} W^T A y + W t."""
+        if not self.n_minus:
+            return (h2 or self.H2)(r)
+        t = self.EW_solve(self.W.T @ r)
+        y = (h2 or self.H2)(r - self.A @ (self.W @ t))
+        s = self.EW_solve(self.W.T @ (self.A @ y))
+        return y + self.W @ (t - s)
 
 
 def geneo_local(sp_: LocalSplit, Ds: np.ndarray, MB: np.ndarray, tau: float):
@@ -423,6 +454,18 @@ def setup(A: sp.csr_matrix, subs, tau: float, eps0: float = 1e-12, w_solver: str
             st.EW_cho = sla.cho_factor(st.EW[np.ix_(st.EW_keep, st.EW_keep)], lower=True)
         except np.linalg.LinAlgError as e:
             raise OracleError("W^T A W is not positive semi-definite") from e
+        # capacitance of the Woodbury form of A^{-1} = (A_+ - V_- L_- V_-^T)^{-1}
+        # (Theorem on the AWG preconditioner with inexact coarse space, Section
+        # 4.2): C = L_-^{-1} - V_-^T W, with L_- = |strictly negative eigenvalues|
+        Lg = np.concatenate([np.abs(sp_.lam[:sp_.nstrict]) for sp_ in split if sp_.nstrict])
+        st.Lg = Lg
+        C = np.diag(1.0 / Lg) - Vg.T @ st.W
+        st.C = 0.5 * (C + C.T)
+        st.C_keep = gram_keep(st.C)
+        try:
+            st.C_cho = sla.cho_factor(st.C[np.ix_(st.C_keep, st.C_keep)], lower=True)
+        except np.linalg.LinAlgError as e:
+            raise OracleError("the capacitance matrix is not positive semi-definite") from e
     return st
 
 
