@@ -37,6 +37,8 @@ def parse():
     ap.add_argument("--local-prec", default="f64", choices=["f64", "f32"])
     ap.add_argument("--geneo", default="dense", choices=["dense", "subspace"],
                     help="GenEO eigensolver of the timed FP64 form")
+    ap.add_argument("--coarse2", default="ad", choices=["ad", "inex", "hyb"],
+                    help="second-coarse-space preconditioner H3 (both forms); ad is the default line")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fast-form", action="store_true")
     ap.add_argument("--workload", default="q1_2d_256", choices=sorted(WORKLOADS),
@@ -248,7 +250,7 @@ def main():
 
     def step(local_prec=args.local_prec, geneo=args.geneo, init=None):
         solver = awg.Solver(Ad, Sd, tau=w.tau, local_prec=local_prec, geneo=geneo, eig_init=init,
-                            coords=coords if init is not None else None)
+                            coords=coords if init is not None else None, coarse2=args.coarse2)
         _, info = solver.pcg(bd, tol=w.tol, maxit=1000, x=x)
         st = solver.stats()
         solver.close()
@@ -304,7 +306,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOADS[args.workload][1],
                    "n": int(A.shape[0]), "nnz": int(A.nnz), "N": len(w.subs), "tol": w.tol,
-                   "local_prec": args.local_prec},
+                   "local_prec": args.local_prec, "coarse2": args.coarse2},
         "solve": {"iters": info["iters"], "rel_res_true": info["rel_res_true"],
                   "kappa_est": info["lmax_est"] / info["lmin_est"], "n_minus": st["n_minus"], "n0": st["n0"],
                   "w_iters": st["w_iters"]},

@@ -60,6 +60,14 @@ typedef enum {
 
 enum { AWG_LOCAL_F64 = 0, AWG_LOCAL_F32 = 1 };
 enum { AWG_GENEO_DENSE = 0, AWG_GENEO_SUBSPACE = 1 };
+/* second-coarse-space preconditioner H (Section 4), all with the same
+ * W = A_+^{-1} V_-:
+ *   AWG_COARSE2_AD   H3,ad   = H2 + W (W^T A W)^{-1} W^T (Definition of Pi_3 and H3)
+ *   AWG_COARSE2_INEX H3,inex = H2 + W C^{-1} W^T, C = L_-^{-1} - V_-^T W
+ *                    (Theorem on the AWG preconditioner with inexact coarse space)
+ *   AWG_COARSE2_HYB  H3,hyb  = Pi3 H2 Pi3^T + W (W^T A W)^{-1} W^T,
+ *                    Pi3 = I - W (W^T A W)^{-1} W^T A (Definition of Pi_3 and H3) */
+enum { AWG_COARSE2_AD = 0, AWG_COARSE2_INEX = 1, AWG_COARSE2_HYB = 2 };
 
 typedef struct {
   double tau;          /* GenEO threshold of H^NN_hyb(tau); 0 < tau < 1 (Theorem, Section 3.4) */
@@ -95,9 +103,10 @@ typedef struct {
   const double* coords;  /* optional node coordinates of every dof, device,
                             n x coord_dim row-major (features 0-2); NULL (default) */
   int32_t coord_dim;     /* 1..3 when coords is given */
+  int32_t coarse2;       /* AWG_COARSE2_AD (default), AWG_COARSE2_INEX or AWG_COARSE2_HYB */
 } awg_options;
 
-/* Fill *opt with the defaults above (tau = 0.1).  Host pointer. */
+/* Fill every field of *opt with the defaults above (tau = 0.1).  Host pointer. */
 void awg_default_options(awg_options* opt);
 
 /* Build the preconditioner (every setup step runs on the GPU).

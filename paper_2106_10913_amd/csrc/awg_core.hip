@@ -153,6 +153,8 @@ struct MultiWS {
   DBuf<double> Tk;                    // sum k_s x b
   DBuf<double> G0, G1, G2;            // n0 x b
   DBuf<double> H0, H1;                // n_minus x b
+  DBuf<double> R3, H2b;               // hybrid H3: projected residual (n x b), second n_minus x b
+  DBuf<GemmDesc> dWT1, dWtT1, dEW2;   // hybrid H3: W t -> T1, W^T T1 -> H0, E_W^{-1} H0 -> H2b
   DBuf<double> dotpart, dots;         // column dot products
   DBuf<double> gvpart;                // split-k partial sums of W^T r (b == 1)
   DBuf<GemmDesc> dVt, dV, dYt, dY, dP, dE0a, dE0b, dWt, dEW, dW;
@@ -469,6 +471,13 @@ void build_ws(awg_ctx& c, MultiWS& w, int b) {
   gemm_upload(w.dWt, {mk(w.R, c.W, nm, w.H0, c.nminus, c.n, true, b)}, s);
   gemm_upload(w.dEW, {mk(w.H0, c.EWinv, nm, w.H1, c.nminus, c.nminus, false, b)}, s);
   gemm_upload(w.dW, {mk(w.H1, c.W, nm, w.Z, c.n, c.nminus, false, b)}, s);
+  if (c.opt.coarse2 == AWG_COARSE2_HYB && c.nminus > 0) {
+    w.R3.alloc(c.n * (long)b);
+    w.H2b.alloc(std::max(1, c.nminus) * (long)b);
+    gemm_upload(w.dWT1, {mk(w.H1, c.W, nm, w.T1, c.n, c.nminus, false, b)}, s);
+    gemm_upload(w.dWtT1, {mk(w.T1, c.W, nm, w.H0, c.nminus, c.n, true, b)}, s);
+    gemm_upload(w.dEW2, {mk(w.H0, c.EWinv, nm, w.H2b, c.nminus, c.nminus, false, b)}, s);
+  }
 }
 
 // Products with the restricted multi-vector R^q X (b > 1) as their A operand
@@ -589,17 +598,18 @@ namespace {
 // H2 = Pi H^NN Pi^T + R0^T E0^{-1} R0 (Theorem on H^NN_hyb, Section 3.4):
 //   u0 = E0^{-1} R0 r; t = r - A_+ R0^T u0; y = H^NN t;
 //   v = E0^{-1} R0 A_+ y; z = y + R0^T (u0 - v)
-void op_h2(awg_ctx& c, MultiWS& w, bool f32) {
+void op_h2(awg_ctx& c, MultiWS& w, bool f32, const double* rin = nullptr) {
   const int b = w.b;
+  const double* r = rin ? rin : w.R.p;
   if (c.n0 == 0) {
-    op_hnn(c, w, w.R, w.Z, f32);
+    op_hnn(c, w, r, w.Z, f32);
     return;
   }
-  op_r0(c, w, w.R);                                                      // G0 = R0 r
+  op_r0(c, w, r);                                                        // G0 = R0 r
   bmm(w.dE0a, 1, c.n0, c.n0, false, 1.0, 0.0, b, c.s, w.flE0, nullptr, "E0");           // G1 = u0
   op_r0t(c, w, w.T1, 0.0);                                               // T1 = R0^T u0
   op_aplus(c, w, w.T1, w.T2);                                            // T2 = A_+ R0^T u0
-  l_colaxpby(c.n, b, w.R, nullptr, w.T2, nullptr, 1.0, -1.0, c.s);       // T2 = r - T2
+  l_colaxpby(c.n, b, r, nullptr, w.T2, nullptr, 1.0, -1.0, c.s);        // T2 = r - T2
   op_hnn(c, w, w.T2, w.Z, f32);                                          // Z = y
   op_aplus(c, w, w.Z, w.T1);                                             // T1 = A_+ y
   op_r0(c, w, w.T1);                                                     // G0 = R0 A_+ y
@@ -609,7 +619,29 @@ void op_h2(awg_ctx& c, MultiWS& w, bool f32) {
 }
 
 // H = H3,ad = H2 + W (W^T A W)^{-1} W^T (Definition of Pi_3 and H3, Section 4.3)
+// H3,hyb = Pi3 H2 Pi3^T + W E_W^{-1} W^T with Pi3 = I - W E_W^{-1} W^T A
+// (Definition of Pi_3 and H3, Section 4.3): t = E_W^{-1} W^T r,
+// y = H2 (r - A W t), z = y + W (t - E_W^{-1} W^T A y)
+void op_h_hyb(awg_ctx& c, MultiWS& w, bool f32) {
+  const int b = w.b;
+  bmm(w.dWt, 1, c.nminus, c.n, true, 1.0, 0.0, b, c.s, w.flW, w.gvpart.p, "Wt");     // H0 = W^T r
+  bmm(w.dEW, 1, c.nminus, c.nminus, false, 1.0, 0.0, b, c.s, w.flEW, nullptr, "EW");   // H1 = t
+  bmm(w.dWT1, 1, c.n, c.nminus, false, 1.0, 0.0, b, c.s, w.flW, nullptr, "W");         // T1 = W t
+  l_spmm(c.n, c.nnz, c.rowptr, c.col, c.val, w.T1, w.R3, b, 1.0, 0.0, c.s, &c.sgrp);  // R3 = A W t
+  l_colaxpby(c.n, b, w.R, nullptr, w.R3, nullptr, 1.0, -1.0, c.s);                     // R3 = Pi3^T r
+  op_h2(c, w, f32, w.R3);                                                              // Z = y
+  l_spmm(c.n, c.nnz, c.rowptr, c.col, c.val, w.Z, w.T1, b, 1.0, 0.0, c.s, &c.sgrp);   // T1 = A y
+  bmm(w.dWtT1, 1, c.nminus, c.n, true, 1.0, 0.0, b, c.s, w.flW, w.gvpart.p, "Wt");   // H0 = W^T A y
+  bmm(w.dEW2, 1, c.nminus, c.nminus, false, 1.0, 0.0, b, c.s, w.flEW, nullptr, "EW");  // H2b = s
+  l_colaxpby(c.nminus, b, w.H2b, nullptr, w.H1, nullptr, -1.0, 1.0, c.s);             // H1 = t - s
+  bmm(w.dW, 1, c.n, c.nminus, false, 1.0, 1.0, b, c.s, w.flW, nullptr, "W");           // Z += W (t - s)
+}
+
 void op_h(awg_ctx& c, MultiWS& w, bool f32) {
+  if (c.opt.coarse2 == AWG_COARSE2_HYB && c.nminus > 0) {
+    op_h_hyb(c, w, f32);
+    return;
+  }
   op_h2(c, w, f32);
   if (c.nminus == 0) return;
   const int b = w.b;
@@ -1365,9 +1397,57 @@ void phase_W(awg_ctx& c) {
 }
 
 // E_W = W^T A W and its inverse (Definition of H3,ad, Section 4.3)
+// capacitance C = diag(1 / L) - (D + D^T) / 2, D = W^T V_- (n_minus x n_minus)
+__global__ void k_capacitance(int m, const double* D, const double* L, double* C) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long)m * m) return;
+  const int i = (int)(e % m), j = (int)(e / m);
+  const double sym = 0.5 * (D[i + (long)j * m] + D[j + (long)i * m]);
+  C[e] = (i == j ? 1.0 / L[i] : 0.0) - sym;
+}
+
+// C = L_-^{-1} - V_-^T W of H3,inex (Theorem on the AWG preconditioner with
+// inexact coarse space, Section 4.2) and its inverse (kept in EWinv, applied
+// like E_W^{-1}); L_- = |strictly negative eigenvalues| of the columns of V_-
+void phase_capacitance(awg_ctx& c) {
+  hipStream_t s = c.s;
+  const int nm = c.nminus;
+  std::vector<long> gcoff(c.N + 1, 0);
+  for (int q = 0; q < c.N; ++q) gcoff[q + 1] = gcoff[q] + c.kstrict[q];
+  // D[:, gcoff[q] + j] = sum_k W[sub_idx[k], :] V^q[k, j]  (restricted rows of W read in place)
+  DBuf<double> D, C, L;
+  D.alloc((long)nm * nm);
+  C.alloc((long)nm * nm);
+  std::vector<GemmDesc> h(c.N);
+  int maxk = 0;
+  double fl = 0.0;
+  for (int q = 0; q < c.N; ++q) {
+    h[q] = GemmDesc{nullptr, c.V.p + c.LV.eoff[q], D.p + gcoff[q] * nm, nm, c.kstrict[q], c.ns[q], nm, c.ns[q], nm};
+    maxk = std::max(maxk, c.kstrict[q]);
+    fl += 2.0 * nm * (double)c.kstrict[q] * c.ns[q];
+  }
+  DBuf<GemmDesc> dg;
+  dg.upload(h, s);
+  gemm_batched_gather(dg, c.W, c.subidx.p, c.subptr.p, c.N, nm, maxk, false, 1.0, 0.0, s, fl, "VgW");
+  // |lambda| of the strictly negative eigenpairs (the first kstrict of each subdomain)
+  const std::vector<double> lam = c.lamV.download(s);
+  std::vector<double> hl;
+  hl.reserve(nm);
+  for (int q = 0; q < c.N; ++q)
+    for (int j = 0; j < c.kstrict[q]; ++j) hl.push_back(std::fabs(lam[c.LV.coff[q] + j]));
+  L.upload(hl, s);
+  hipLaunchKernelGGL(k_capacitance, dim3(cdiv((long)nm * nm, 256)), dim3(256), 0, s, nm, D.p, L.p, C.p);
+  AWG_LAUNCH_CHECK();
+  c.nminus_dropped = spd_inverse(c, C, nm, c.EWinv, "capacitance matrix L^-1 - V^T W");
+}
+
 void phase_EW(awg_ctx& c) {
   PhaseTimer t(c, "second_coarse_EW");
   if (c.nminus == 0) return;
+  if (c.opt.coarse2 == AWG_COARSE2_INEX) {
+    phase_capacitance(c);
+    return;
+  }
   hipStream_t s = c.s;
   DBuf<double> AW, EW;
   AW.alloc((long)c.n * c.nminus);
@@ -1606,6 +1686,7 @@ std::string stats_json(const awg_ctx& c) {
   arr("kstrict_s", c.kstrict);
   o << ",";
   arr("m_s", c.ms);
+  o << ",\"coarse2\":" << c.opt.coarse2;
   o << ",\"geneo_solver\":" << c.opt.geneo_solver << ",\"eig_fallbacks\":" << c.eig_fallbacks
     << ",\"eig_learned\":" << c.eig_learned << ",\"eig_block\":" << c.opt.eig_block
     << ",\"n0_dropped\":" << c.n0_dropped << ",\"nminus_dropped\":" << c.nminus_dropped << ",";
@@ -1647,6 +1728,10 @@ void awg_default_options(awg_options* opt) {
   opt->eig_maxit = 200;
   opt->eig_seed = 0;
   opt->eig_tol = 1e-10;
+  opt->eig_init = nullptr;
+  opt->coords = nullptr;
+  opt->coord_dim = 0;
+  opt->coarse2 = AWG_COARSE2_AD;
 }
 
 int awg_setup(awg_ctx** out, int64_t n, int64_t nnz, const int64_t* rowptr, const int32_t* col, const double* val,
@@ -1672,7 +1757,8 @@ int awg_setup(awg_ctx** out, int64_t n, int64_t nnz, const int64_t* rowptr, cons
       (o.local_prec != AWG_LOCAL_F64 && o.local_prec != AWG_LOCAL_F32) ||
       (o.geneo_solver != AWG_GENEO_DENSE && o.geneo_solver != AWG_GENEO_SUBSPACE) || o.eig_block < 1 ||
       o.eig_block > SUBSPACE_MAX_BLOCK || o.eig_maxit < 1 || !(o.eig_tol > 0.0) ||
-      (o.coords && (o.coord_dim < 1 || o.coord_dim > 3))) {
+      (o.coords && (o.coord_dim < 1 || o.coord_dim > 3)) ||
+      (o.coarse2 != AWG_COARSE2_AD && o.coarse2 != AWG_COARSE2_INEX && o.coarse2 != AWG_COARSE2_HYB)) {
     g_setup_error = "awg_setup: invalid option value";
     return AWG_ERR_ARG;
   }
