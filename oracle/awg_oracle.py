@@ -13,6 +13,11 @@ preconditioners with adaptive spectral bounds"):
          Pi = I - R0^T E0^{-1} R0 A_+
     H^NN = sum_s R^sT D^s (A^s_+)^dagger D^s R^s      (Definition of H^NN, Section 3.3)
 
+and the other choices: H3,inex and H3,hyb (Section 4) for the second coarse
+space, and for H2 the AS forms H^AS_{+,hyb}(tau_flat) and H^AS_{+,ad}(tau_flat)
+(Theorem on H^AS_{+,hyb/ad}, Section 3.4), H^AS_+ = sum_s R^sT (R^s A_+ R^sT)^{-1} R^s,
+on the same coarse space with tau_flat = 1/tau.
+
 The steps follow the paper's order and notation.  Dense LAPACK (numpy /
 scipy) is used for every local and coarse problem; no iterative
 eigensolver is involved.  Readings where the paper is silent:
@@ -246,6 +251,8 @@ class AWGSetup:
     C: np.ndarray = None          # capacitance L_-^{-1} - V_-^T W (H3,inex)
     C_keep: np.ndarray = None
     C_cho: tuple = None
+    MB: list = None               # M_B^s = R^s A_+ R^sT per subdomain (GenEO pencil, H^AS_+ local blocks)
+    MB_cho: list = None           # their Cholesky factors, formed on first use by H^AS_+
 
     @property
     def n(self):
@@ -313,9 +320,43 @@ class AWGSetup:
         v = self.E0_solve(self.R0T.T @ self.A_plus_mv(y))     # E0^{-1} R0 A_+ y
         return y - self.R0T @ v + self.R0T @ u0               # Pi y + R0^T E0^{-1} R0 r
 
-    def apply(self, r):
-        """H r with H = H3,ad = H2 + W (W^T A W)^{-1} W^T (Definition, Section 4.3)."""
-        z = self.H2(r)
+    # -- one-level H^AS_+ and its two-level forms (Section 3.4) -----------
+    def H_AS_plus(self, X):
+        """H^AS_+ X = sum_s R^sT (R^s A_+ R^sT)^{-1} R^s X: exact local solves
+        with A_+, no partition of unity (one-level preconditioners for A_+,
+        Section 3.3)."""
+        if self.MB_cho is None:
+            self.MB_cho = [sla.cho_factor(0.5 * (M + M.T), lower=True) for M in self.MB]
+        out = np.zeros_like(X, dtype=np.float64)
+        for idx, F in zip(self.subs, self.MB_cho):
+            out[idx] += sla.cho_solve(F, X[idx])
+        return out
+
+    def H2_as_plus_hyb(self, r):
+        """H^AS_{+,hyb}(tau_flat) = Pi H^AS_+ Pi^T + R0^T E0^{-1} R0 (Theorem on
+        H^AS_{+,hyb/ad}, Section 3.4).  Its coarse space V0_{AS,+}(tau_flat) is
+        spanned by the R^sT Y_L(1/tau_flat) of the pencil (D^-1 A^s_+ D^-1,
+        R^s A_+ R^sT): with tau_flat = 1/tau it is the coarse space already
+        built here, so R0 and E0 are shared."""
+        u0 = self.E0_solve(self.R0T.T @ r)
+        t = r - self.A_plus_mv(self.R0T @ u0)
+        y = self.H_AS_plus(t)
+        v = self.E0_solve(self.R0T.T @ self.A_plus_mv(y))
+        return y - self.R0T @ v + self.R0T @ u0
+
+    def H2_as_plus_ad(self, r):
+        """H^AS_{+,ad}(tau_flat) = H^AS_+ + R0^T E0^{-1} R0 (same theorem and coarse space)."""
+        return self.H_AS_plus(r) + self.R0T @ self.E0_solve(self.R0T.T @ r)
+
+    def h2(self, kind: str):
+        """The preconditioner for A_+ named by kind: "nn_hyb" (H^NN_hyb(tau)),
+        "asp_hyb" or "asp_ad" (H^AS_{+,hyb/ad}(1/tau))."""
+        return {"nn_hyb": self.H2, "asp_hyb": self.H2_as_plus_hyb, "asp_ad": self.H2_as_plus_ad}[kind]
+
+    def apply(self, r, h2=None):
+        """H r with H = H3,ad = H2 + W (W^T A W)^{-1} W^T (Definition, Section 4.3).
+        h2: a replacement for H2."""
+        z = (h2 or self.H2)(r)
         if self.n_minus:
             z = z + self.W @ self.EW_solve(self.W.T @ r)
         return z
@@ -397,12 +438,13 @@ def setup(A: sp.csr_matrix, subs, tau: float, eps0: float = 1e-12, w_solver: str
     split = [split_local(local_block(B, idx), eps0) for idx in subs]
 
     # GenEO coarse space (Theorem for H^NN_hyb, Section 3.4)
-    Ys, glam = [], []
+    Ys, glam, MBs = [], [], []
     for s in range(len(subs)):
         MB = local_MB(A, subs, split, s)
         Y, lam = geneo_local(split[s], Ds[s], MB, tau)
         Ys.append(Y)
         glam.append(lam)
+        MBs.append(MB)
     rows, cols, vals = [], [], []
     off = 0
     for idx, Y in zip(subs, Ys):
@@ -416,7 +458,7 @@ def setup(A: sp.csr_matrix, subs, tau: float, eps0: float = 1e-12, w_solver: str
 
     st = AWGSetup(A=A, subs=subs, tau=tau, Ds=Ds, cnt=cnt, B=B, split=split, Y=Ys,
                   geneo_lam=glam, R0T=R0T, E0=None, E0_cho=None, W=np.zeros((n, 0)),
-                  EW=np.zeros((0, 0)), EW_cho=None, Vg=np.zeros((n, 0)), w_info={})
+                  EW=np.zeros((0, 0)), EW_cho=None, Vg=np.zeros((n, 0)), w_info={}, MB=MBs)
     # E0 = R0 A_+ R0^T and its Cholesky factor
     AR0T = st.A_plus_mv(R0T.toarray())
     E0 = np.asarray(R0T.T @ AR0T)
