@@ -52,6 +52,32 @@ def test_paper_table_rows(case):
         assert st.Y[4].shape[1] == cs["selected"]
 
 
+T1 = GOLD["table1_awg_variants"]
+
+
+@pytest.fixture(scope="module")
+def six_layers():
+    w = P.paper_x0(tau=0.1)
+    return w, O.setup(w.A, w.subs, w.tau)
+
+
+@pytest.mark.parametrize("row", T1["rows"], ids=[f"{r['coarse2']}-{r['h2']}" for r in T1["rows"]])
+def test_paper_table1_awg_variants(six_layers, row):
+    """H3,ad and H3,hyb, each with H^NN_hyb(0.1), H^AS_{+,hyb}(10) and
+    H^AS_{+,ad}(10) as H2, on the six-layer problem (Table 1)."""
+    w, st = six_layers
+    assert st.n0 == T1["n0"] and st.n_minus == T1["n_minus"]
+    h2 = st.h2(row["h2"])
+    ap = (lambda r: st.apply(r, h2=h2)) if row["coarse2"] == "ad" else (lambda r: st.apply_hyb(r, h2=h2))
+    res = O.pcg(w.A, w.b, ap, tol=1e-10, norm="preconditioned", maxit=200)
+    assert res.converged
+    lmin, lmax = res.lanczos_extremes()
+    assert abs(lmax / lmin - row["kappa"]) <= 0.03 * row["kappa"]
+    assert abs(res.iters - row["it"]) <= 2
+    assert abs(lmin - row["lmin"]) <= 0.05 * max(1.0, row["lmin"])
+    assert abs(lmax - row["lmax"]) <= 0.05 * row["lmax"]
+
+
 @pytest.mark.parametrize("i", range(5))
 def test_paper_long_domain(i):
     g = GOLD["long_domain"]
