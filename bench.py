@@ -39,6 +39,10 @@ def parse():
                     help="GenEO eigensolver of the timed FP64 form")
     ap.add_argument("--coarse2", default="ad", choices=["ad", "inex", "hyb"],
                     help="second-coarse-space preconditioner H3 (both forms); ad is the default line")
+    ap.add_argument("--h2", default="nn_hyb", choices=["nn_hyb", "asp_hyb", "asp_ad"],
+                    help="two-level preconditioner for A_+ (both forms); nn_hyb is the default line")
+    ap.add_argument("--w-rtol", type=float, default=1e-10,
+                    help="relative residual of the PCG solves for W (the paper's choice is 1e-10)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fast-form", action="store_true")
     ap.add_argument("--workload", default="q1_2d_256", choices=sorted(WORKLOADS),
@@ -250,7 +254,7 @@ def main():
 
     def step(local_prec=args.local_prec, geneo=args.geneo, init=None):
         solver = awg.Solver(Ad, Sd, tau=w.tau, local_prec=local_prec, geneo=geneo, eig_init=init,
-                            coords=coords if init is not None else None, coarse2=args.coarse2)
+                            coords=coords if init is not None else None, coarse2=args.coarse2, w_rtol=args.w_rtol, h2=args.h2)
         _, info = solver.pcg(bd, tol=w.tol, maxit=1000, x=x)
         st = solver.stats()
         solver.close()
@@ -306,7 +310,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOADS[args.workload][1],
                    "n": int(A.shape[0]), "nnz": int(A.nnz), "N": len(w.subs), "tol": w.tol,
-                   "local_prec": args.local_prec, "coarse2": args.coarse2},
+                   "local_prec": args.local_prec, "coarse2": args.coarse2, "h2": args.h2,
+                   "w_rtol": args.w_rtol},
         "solve": {"iters": info["iters"], "rel_res_true": info["rel_res_true"],
                   "kappa_est": info["lmax_est"] / info["lmin_est"], "n_minus": st["n_minus"], "n0": st["n0"],
                   "w_iters": st["w_iters"]},

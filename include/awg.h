@@ -68,9 +68,22 @@ enum { AWG_GENEO_DENSE = 0, AWG_GENEO_SUBSPACE = 1 };
  *   AWG_COARSE2_HYB  H3,hyb  = Pi3 H2 Pi3^T + W (W^T A W)^{-1} W^T,
  *                    Pi3 = I - W (W^T A W)^{-1} W^T A (Definition of Pi_3 and H3) */
 enum { AWG_COARSE2_AD = 0, AWG_COARSE2_INEX = 1, AWG_COARSE2_HYB = 2 };
+/* two-level preconditioner H2 for A_+ inside H (Section 3.4), all on the same
+ * GenEO coarse space R0 (the pencil (D^-1 A^s_+ D^-1, R^s A_+ R^sT) below tau,
+ * which is V0_{AS,+}(tau_flat) with tau_flat = 1/tau):
+ *   AWG_H2_NN_HYB  H^NN_hyb(tau) = Pi H^NN Pi^T + R0^T E0^{-1} R0,
+ *                  H^NN = sum_s R^sT D^s (A^s_+)^+ D^s R^s
+ *                  (Theorem on H^NN_hyb); spectrum of H2 A_+ in [1, N(A_+)/tau]
+ *   AWG_H2_ASP_HYB H^AS_{+,hyb}(1/tau) = Pi H^AS_+ Pi^T + R0^T E0^{-1} R0,
+ *                  H^AS_+ = sum_s R^sT (R^s A_+ R^sT)^{-1} R^s
+ *                  (Theorem on H^AS_{+,hyb/ad}); spectrum in [tau, N(A_+)]
+ *   AWG_H2_ASP_AD  H^AS_{+,ad}(1/tau) = H^AS_+ + R0^T E0^{-1} R0 (same theorem);
+ *                  spectrum in [tau / (1 + 2 N(A_+)), N(A_+) + 1] */
+enum { AWG_H2_NN_HYB = 0, AWG_H2_ASP_HYB = 1, AWG_H2_ASP_AD = 2 };
 
 typedef struct {
-  double tau;          /* GenEO threshold of H^NN_hyb(tau); 0 < tau < 1 (Theorem, Section 3.4) */
+  double tau;          /* GenEO threshold of H^NN_hyb(tau), tau_flat = 1/tau for the
+                          AS forms; 0 < tau < 1 (Theorems, Section 3.4) */
   double zero_tol;     /* eps0: an eigenvalue lambda of B^s is non-positive when
                           lambda <= eps0 * max|lambda(B^s)|; default 1e-12 */
   double w_rtol;       /* relative residual tolerance of the PCG solves with A_+
@@ -104,6 +117,7 @@ typedef struct {
                             n x coord_dim row-major (features 0-2); NULL (default) */
   int32_t coord_dim;     /* 1..3 when coords is given */
   int32_t coarse2;       /* AWG_COARSE2_AD (default), AWG_COARSE2_INEX or AWG_COARSE2_HYB */
+  int32_t h2;            /* AWG_H2_NN_HYB (default), AWG_H2_ASP_HYB or AWG_H2_ASP_AD */
 } awg_options;
 
 /* Fill every field of *opt with the defaults above (tau = 0.1).  Host pointer. */
@@ -167,7 +181,10 @@ int64_t awg_stats(const awg_ctx* ctx, char* buf, size_t cap);
  *   "V_minus"    float64 [sum_s n_s k_s] non-positive eigenvectors of each B^s
  *                                     (n_s x k_s column-major blocks, in subdomain order)
  *   "Y"          float64 [sum_s n_s m_s] GenEO coarse vectors Y^s (same layout)
- *   "P_local"    float64 [sum_s n_s^2] local operators D^s (A^s_+)^+ D^s (n_s x n_s blocks)
+ *   "P_local"    float64 [sum_s n_s^2] local operators of H2 (n_s x n_s blocks):
+ *                                     D^s (A^s_+)^+ D^s, or (R^s A_+ R^sT)^{-1} for the AS forms
+ *   "W"          float64 [n * n_minus] second coarse basis W = A_+^-1 V_- as computed
+ *                                     (PCG to w_rtol), row-major: W[i * n_minus + j]
  * Returns the number of bytes of the array (copying min(cap, size)), or a
  * negative error for an unknown name. */
 int64_t awg_export(const awg_ctx* ctx, const char* name, void* host_buf, size_t cap);

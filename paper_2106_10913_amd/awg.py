@@ -19,6 +19,7 @@ AWG_LOCAL_F64 = 0
 AWG_LOCAL_F32 = 1
 AWG_GENEO_DENSE, AWG_GENEO_SUBSPACE = 0, 1
 COARSE2 = {"ad": 0, "inex": 1, "hyb": 2}     # second-coarse-space preconditioner (awg.h)
+H2 = {"nn_hyb": 0, "asp_hyb": 1, "asp_ad": 2}  # two-level preconditioner for A_+ (awg.h)
 
 STATUS = {0: "AWG_OK", 1: "AWG_NOT_CONVERGED", -1: "AWG_ERR_ARG", -2: "AWG_ERR_NOT_SYMMETRIC",
           -3: "AWG_ERR_PARTITION", -4: "AWG_ERR_MIN_OVERLAP", -5: "AWG_ERR_NOT_SPD", -6: "AWG_ERR_EIGEN",
@@ -38,7 +39,8 @@ class Options(ctypes.Structure):
                 ("w_maxit", ctypes.c_int32), ("local_prec", ctypes.c_int32), ("stream", ctypes.c_void_p),
                 ("geneo_solver", ctypes.c_int32), ("eig_block", ctypes.c_int32), ("eig_maxit", ctypes.c_int32),
                 ("eig_seed", ctypes.c_int32), ("eig_tol", ctypes.c_double), ("eig_init", ctypes.c_void_p),
-                ("coords", ctypes.c_void_p), ("coord_dim", ctypes.c_int32), ("coarse2", ctypes.c_int32)]
+                ("coords", ctypes.c_void_p), ("coord_dim", ctypes.c_int32), ("coarse2", ctypes.c_int32),
+                ("h2", ctypes.c_int32)]
 
 
 class PCGInfo(ctypes.Structure):
@@ -190,7 +192,7 @@ class Solver:
     def __init__(self, A, subs, tau: float = 0.1, local_prec: str = "f64", w_rtol: float = 1e-10,
                  w_maxit: int = 500, zero_tol: float = 1e-12, device: str = "cuda", geneo: str = "dense",
                  eig_block: int = 16, eig_maxit: int = 200, eig_tol: float = 1e-10, eig_seed: int = 0,
-                 eig_init: "MLP | None" = None, coords=None, coarse2: str = "ad"):
+                 eig_init: "MLP | None" = None, coords=None, coarse2: str = "ad", h2: str = "nn_hyb"):
         import torch
         L = lib()
         self._torch = torch
@@ -231,6 +233,9 @@ class Solver:
         if coarse2 not in COARSE2:
             raise ValueError("coarse2 must be one of " + ", ".join(COARSE2))
         opt.coarse2 = COARSE2[coarse2]
+        if h2 not in H2:
+            raise ValueError("h2 must be one of " + ", ".join(H2))
+        opt.h2 = H2[h2]
         opt.eig_block = eig_block
         opt.eig_maxit = eig_maxit
         opt.eig_tol = eig_tol

@@ -552,7 +552,8 @@ void op_r0t(awg_ctx& c, MultiWS& w, double* Yo, double beta, double alpha = 1.0)
   l_scatter(c.n, c.sumns, c.invptr, c.invsub, c.invloc, c.subptr, w.Os, w.b, Yo, alpha, beta, c.s);
 }
 
-// Yo = H^NN X = sum_s R^sT P^s R^s X with P^s = D^s (A^s_+)^+ D^s (Definition of H^NN, Section 3.3)
+// Yo = sum_s R^sT P^s R^s X: H^NN X with P^s = D^s (A^s_+)^+ D^s (Definition of
+// H^NN, Section 3.3), or H^AS_+ X with P^s = (R^s A_+ R^sT)^{-1} (Section 3.4)
 void op_hnn(awg_ctx& c, MultiWS& w, const double* X, double* Yo, bool f32) {
   if (w.b == 1) l_gather(c.sumns, c.subidx, X, w.b, w.Xs, c.s);
   if (f32 && w.b == 1) {
@@ -603,6 +604,14 @@ void op_h2(awg_ctx& c, MultiWS& w, bool f32, const double* rin = nullptr) {
   const double* r = rin ? rin : w.R.p;
   if (c.n0 == 0) {
     op_hnn(c, w, r, w.Z, f32);
+    return;
+  }
+  if (c.opt.h2 == AWG_H2_ASP_AD) {
+    // H^AS_{+,ad} = H^AS_+ + R0^T E0^{-1} R0 (Theorem on H^AS_{+,hyb/ad}, Section 3.4)
+    op_r0(c, w, r);                                                      // G0 = R0 r
+    bmm(w.dE0a, 1, c.n0, c.n0, false, 1.0, 0.0, b, c.s, w.flE0, nullptr, "E0");         // G1 = E0^{-1} R0 r
+    op_hnn(c, w, r, w.Z, f32);                                           // Z = H^AS_+ r
+    op_r0t(c, w, w.Z, 1.0);                                              // Z += R0^T G1
     return;
   }
   op_r0(c, w, r);                                                        // G0 = R0 r
@@ -1125,7 +1134,11 @@ void phase_local(awg_ctx& c) {
     for (int q = 0; q < c.N; ++q) fl += 2.0 * c.ns[q] * (double)c.ns[q] * c.ks[q];
     if (maxk > 0) gemm_batched(dg, c.N, c.maxns, c.maxns, false, true, alpha, 1.0, false, s, fl);
   };
-  {
+  // the AS forms of H2 need D^s (A^s_+)^+ D^s only in the subspace GenEO
+  // solver (it applies the inverse of M_A^s with it)
+  const bool asp = c.opt.h2 != AWG_H2_NN_HYB;
+  const bool nn_formed = !asp || c.opt.geneo_solver == AWG_GENEO_SUBSPACE;
+  if (nn_formed) {
     PhaseTimer t(c, "local_factor");
     // K^s = B^s + V_-(c_s - L_-)V_-^T (spd), c_s = mean diag B^s
     l_diag_mean(d1, c.N, cs, s);
@@ -1145,9 +1158,9 @@ void phase_local(awg_ctx& c) {
     l_scale_cols(dU, c.N, c.LV.d_coff, c.lamV, 1.0, cs, 3, s);
     lowrank_into(X2, -1.0);
     l_scale_sym(d2, c.N, c.subptr, c.dw, false, true, s);
-    std::swap(c.P.p, X2.p);
+    std::swap(c.P.p, X2.p);   // d2 now addresses c.P
     std::swap(c.P.n, X2.n);
-    if (c.opt.local_prec == AWG_LOCAL_F32) {
+    if (c.opt.local_prec == AWG_LOCAL_F32 && !asp) {
       c.P32.alloc(c.sqtot);
       hipLaunchKernelGGL(k_f32_from_f64, dim3(4096), dim3(256), 0, s, (long)c.sqtot, c.P.p, c.P32.p);
       AWG_LAUNCH_CHECK();
@@ -1189,6 +1202,7 @@ void phase_local(awg_ctx& c) {
     trsm_batched(d1, dY, c.ns, c.ms, true, s, nullptr);
     c.n0 = (int)c.LY.cols;
   };
+  bool mb_factored = false;   // d1 holds the Cholesky factor of M_B^s (dense solver), else M_B^s
   {
     PhaseTimer t(c, "geneo");
     build_pencil();
@@ -1198,9 +1212,35 @@ void phase_local(awg_ctx& c) {
       if (c.eig_fallbacks) {
         build_pencil();
         dense_geneo();
+        mb_factored = true;
       }
     } else {
       dense_geneo();
+      mb_factored = true;
+    }
+  }
+  if (asp) {
+    // local operators of H^AS_+: P^s = (R^s A_+ R^sT)^{-1} = (M_B^s)^{-1}
+    // (one-level preconditioners for A_+, Section 3.3), from the factor the
+    // GenEO solve left in d1 or a new one
+    PhaseTimer t(c, "local_factor");
+    if (!mb_factored) {
+      info.zero(s);
+      potrf_batched(d1, c.ns, info, s, nullptr);
+      check_info(c, info, "H^AS_+ local block M_B^s");
+    }
+    l_set_identity(d2, c.N, s);
+    trsm_batched(d1, d2, c.ns, c.ns, false, s, nullptr);
+    trsm_batched(d1, d2, c.ns, c.ns, true, s, nullptr);
+    l_scale_sym(d2, c.N, nullptr, nullptr, false, true, s);
+    if (!nn_formed) {   // d2 still addresses X2
+      std::swap(c.P.p, X2.p);
+      std::swap(c.P.n, X2.n);
+    }
+    if (c.opt.local_prec == AWG_LOCAL_F32) {
+      c.P32.alloc(c.sqtot);
+      hipLaunchKernelGGL(k_f32_from_f64, dim3(4096), dim3(256), 0, s, (long)c.sqtot, c.P.p, c.P32.p);
+      AWG_LAUNCH_CHECK();
     }
   }
 }
@@ -1686,7 +1726,7 @@ std::string stats_json(const awg_ctx& c) {
   arr("kstrict_s", c.kstrict);
   o << ",";
   arr("m_s", c.ms);
-  o << ",\"coarse2\":" << c.opt.coarse2;
+  o << ",\"coarse2\":" << c.opt.coarse2 << ",\"h2\":" << c.opt.h2;
   o << ",\"geneo_solver\":" << c.opt.geneo_solver << ",\"eig_fallbacks\":" << c.eig_fallbacks
     << ",\"eig_learned\":" << c.eig_learned << ",\"eig_block\":" << c.opt.eig_block
     << ",\"n0_dropped\":" << c.n0_dropped << ",\"nminus_dropped\":" << c.nminus_dropped << ",";
@@ -1732,6 +1772,7 @@ void awg_default_options(awg_options* opt) {
   opt->coords = nullptr;
   opt->coord_dim = 0;
   opt->coarse2 = AWG_COARSE2_AD;
+  opt->h2 = AWG_H2_NN_HYB;
 }
 
 int awg_setup(awg_ctx** out, int64_t n, int64_t nnz, const int64_t* rowptr, const int32_t* col, const double* val,
@@ -1758,7 +1799,8 @@ int awg_setup(awg_ctx** out, int64_t n, int64_t nnz, const int64_t* rowptr, cons
       (o.geneo_solver != AWG_GENEO_DENSE && o.geneo_solver != AWG_GENEO_SUBSPACE) || o.eig_block < 1 ||
       o.eig_block > SUBSPACE_MAX_BLOCK || o.eig_maxit < 1 || !(o.eig_tol > 0.0) ||
       (o.coords && (o.coord_dim < 1 || o.coord_dim > 3)) ||
-      (o.coarse2 != AWG_COARSE2_AD && o.coarse2 != AWG_COARSE2_INEX && o.coarse2 != AWG_COARSE2_HYB)) {
+      (o.coarse2 != AWG_COARSE2_AD && o.coarse2 != AWG_COARSE2_INEX && o.coarse2 != AWG_COARSE2_HYB) ||
+      (o.h2 != AWG_H2_NN_HYB && o.h2 != AWG_H2_ASP_HYB && o.h2 != AWG_H2_ASP_AD)) {
     g_setup_error = "awg_setup: invalid option value";
     return AWG_ERR_ARG;
   }
@@ -1845,6 +1887,7 @@ int64_t awg_export(const awg_ctx* c, const char* name, void* buf, size_t cap) {
   else if (nm == "V_minus") { src = c->V.p; bytes = sizeof(double) * c->LV.elems; }
   else if (nm == "Y") { src = c->Y.p; bytes = sizeof(double) * c->LY.elems; }
   else if (nm == "P_local") { src = c->P.p; bytes = sizeof(double) * c->sqtot; }
+  else if (nm == "W") { src = c->W.p; bytes = sizeof(double) * c->n * c->nminus; }
   else if (nm == "ritz_vectors") { src = c->ritzZ.p; bytes = sizeof(double) * c->sumns * c->ritz_q; }
   else if (nm == "ritz_values") { src = c->ritzMu.p; bytes = sizeof(double) * c->N * c->ritz_q; }
   else if (nm == "mlp_features") {
