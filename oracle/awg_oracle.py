@@ -16,7 +16,9 @@ preconditioners with adaptive spectral bounds"):
 and the other choices: H3,inex and H3,hyb (Section 4) for the second coarse
 space, and for H2 the AS forms H^AS_{+,hyb}(tau_flat) and H^AS_{+,ad}(tau_flat)
 (Theorem on H^AS_{+,hyb/ad}, Section 3.4), H^AS_+ = sum_s R^sT (R^s A_+ R^sT)^{-1} R^s,
-on the same coarse space with tau_flat = 1/tau.
+on the same coarse space with tau_flat = 1/tau, and H^AS_hyb(tau_sharp, tau_flat)
+(Theorem on H^AS_hyb, Section 3.4) with local blocks R^s A R^sT and the
+two-pencil coarse space, tau_sharp = tau and tau_flat = 1/tau.
 
 The steps follow the paper's order and notation.  Dense LAPACK (numpy /
 scipy) is used for every local and coarse problem; no iterative
@@ -253,6 +255,7 @@ class AWGSetup:
     C_cho: tuple = None
     MB: list = None               # M_B^s = R^s A_+ R^sT per subdomain (GenEO pencil, H^AS_+ local blocks)
     MB_cho: list = None           # their Cholesky factors, formed on first use by H^AS_+
+    ash: dict = None              # coarse space and local factors of H^AS_hyb, formed on first use
 
     @property
     def n(self):
@@ -348,10 +351,72 @@ class AWGSetup:
         """H^AS_{+,ad}(tau_flat) = H^AS_+ + R0^T E0^{-1} R0 (same theorem and coarse space)."""
         return self.H_AS_plus(r) + self.R0T @ self.E0_solve(self.R0T.T @ r)
 
+    # -- H^AS_hyb(tau_sharp, tau_flat) (Theorem on H^AS_hyb, Section 3.4) --
+    def _as_hyb_space(self):
+        """Coarse space V0_AS(tau_sharp, tau_flat), tau_sharp = tau and
+        tau_flat = 1/tau: per subdomain the columns of
+        Y_L(1/tau_flat, D^-1 A^s_+ D^-1, R^s A R^sT) followed by those of
+        Y_L(tau_sharp, R^s A R^sT, R^s A_+ R^sT); E0 = R0 A_+ R0^T on it (its
+        kept columns as for H^NN_hyb: the union may be dependent)."""
+        if self.ash is not None:
+            return self.ash
+        rows, cols, vals, Ys, chol, m1s = [], [], [], [], [], []
+        off = 0
+        for s, idx in enumerate(self.subs):
+            As = local_block(self.A, idx)
+            As = 0.5 * (As + As.T)
+            Dinv = 1.0 / self.Ds[s]
+            MA = Dinv[:, None] * self.split[s].A_plus() * Dinv[None, :]
+            lam1, Y1 = sla.eigh(0.5 * (MA + MA.T), As)
+            lam2, Y2 = sla.eigh(As, 0.5 * (self.MB[s] + self.MB[s].T))
+            Y = np.concatenate([Y1[:, lam1 < self.tau], Y2[:, lam2 < self.tau]], axis=1)
+            Ys.append(Y)
+            m1s.append(int(np.count_nonzero(lam1 < self.tau)))
+            m = Y.shape[1]
+            rows.append(np.repeat(idx, m))
+            cols.append(np.tile(np.arange(off, off + m), idx.size))
+            vals.append(Y.ravel())
+            off += m
+            chol.append(sla.cho_factor(As, lower=True))
+        R0T = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                            shape=(self.n, off))
+        E0 = np.asarray(R0T.T @ self.A_plus_mv(R0T.toarray()))
+        E0 = 0.5 * (E0 + E0.T)
+        keep = gram_keep(E0)
+        self.ash = dict(Y=Ys, m1=m1s, R0T=R0T, E0=E0, keep=keep,
+                        cho=sla.cho_factor(E0[np.ix_(keep, keep)], lower=True), local=chol)
+        return self.ash
+
+    def H_AS(self, X):
+        """H^AS X = sum_s R^sT (R^s A R^sT)^{-1} R^s X (one-level, Section 3.3)."""
+        c = self._as_hyb_space()
+        out = np.zeros_like(X, dtype=np.float64)
+        for idx, F in zip(self.subs, c["local"]):
+            out[idx] += sla.cho_solve(F, X[idx])
+        return out
+
+    def H2_as_hyb(self, r):
+        """H^AS_hyb(tau_sharp, tau_flat) = Pi_AS H^AS Pi_AS^T + R0^T E0^{-1} R0 on
+        V0_AS(tau_sharp, tau_flat), Pi_AS = I - R0^T E0^{-1} R0 A_+."""
+        c = self._as_hyb_space()
+        R0T = c["R0T"]
+
+        def e0(g):
+            out = np.zeros_like(g, dtype=np.float64)
+            out[c["keep"]] = sla.cho_solve(c["cho"], g[c["keep"]])
+            return out
+        u0 = e0(R0T.T @ r)
+        t = r - self.A_plus_mv(R0T @ u0)
+        y = self.H_AS(t)
+        v = e0(R0T.T @ self.A_plus_mv(y))
+        return y - R0T @ v + R0T @ u0
+
     def h2(self, kind: str):
         """The preconditioner for A_+ named by kind: "nn_hyb" (H^NN_hyb(tau)),
-        "asp_hyb" or "asp_ad" (H^AS_{+,hyb/ad}(1/tau))."""
-        return {"nn_hyb": self.H2, "asp_hyb": self.H2_as_plus_hyb, "asp_ad": self.H2_as_plus_ad}[kind]
+        "asp_hyb" or "asp_ad" (H^AS_{+,hyb/ad}(1/tau)), "as_hyb"
+        (H^AS_hyb(tau, 1/tau))."""
+        return {"nn_hyb": self.H2, "asp_hyb": self.H2_as_plus_hyb, "asp_ad": self.H2_as_plus_ad,
+                "as_hyb": self.H2_as_hyb}[kind]
 
     def apply(self, r, h2=None):
         """H r with H = H3,ad = H2 + W (W^T A W)^{-1} W^T (Definition, Section 4.3).

@@ -1,6 +1,8 @@
 """Pins of the oracle's AS forms of H2, H^AS_{+,hyb}(tau_flat) and
-H^AS_{+,ad}(tau_flat) (Theorem on H^AS_{+,hyb/ad}, Section 3.4), against what
-the paper and the mathematics fix:
+H^AS_{+,ad}(tau_flat) (Theorem on H^AS_{+,hyb/ad}, Section 3.4) and
+H^AS_hyb(tau_sharp, tau_flat) (Theorem on H^AS_hyb, Section 3.4), against what
+the paper and the mathematics fix (the printed Table 1 rows are pinned in
+test_oracle_paper.py):
 
 * the local blocks R^s A_+ R^sT, written as in Remark 4 of Section 4.4, are the
   principal submatrices of the assembled A_+ = sum_s R^sT A^s_+ R^s, and
@@ -12,12 +14,17 @@ the paper and the mathematics fix:
   operator, at tau = 0.1 and at tau = 0.9, where the one-level spectrum
   reaches below 1/tau_flat so that the hybrid bound depends on the coarse part;
 * the coarse part is exact on the coarse space: H2 A_+ R0^T = R0^T for the
-  hybrid form, (H2 - H^AS_+) A_+ R0^T = R0^T for the additive one;
+  hybrid forms, (H2 - H^AS_+) A_+ R0^T = R0^T for the additive one;
+* H^AS is the sum of dense inverses of the principal submatrices of A, each
+  part of the two-pencil coarse basis of H^AS_hyb solves its own pencil with
+  as many vectors as the pencil's inertia below the threshold (LDL^T), and
+  H^AS_hyb obeys its theorem's bound [1/tau_flat, N(A_+)/tau_sharp];
 * with either form as H2, the spectra of H3,ad A and H3,hyb A obey the bounds
   of the theorem on Pi_3 and H3 (Section 4.3) in terms of lambda(H2 A_+).
 """
 import numpy as np
 import pytest
+import scipy.linalg as sla
 
 import awg_problems as P
 from awg_problems import partition as part
@@ -69,6 +76,47 @@ def test_H_AS_plus_is_the_sum_of_local_inverses(case):
     assert np.linalg.norm(got - ref) <= 1e-9 * np.linalg.norm(ref)
 
 
+def test_H_AS_is_the_sum_of_local_inverses_of_A(case):
+    w, st, Ap = case
+    A = w.A.toarray()
+    X = np.random.default_rng(4).standard_normal((A.shape[0], 3))
+    ref = np.zeros_like(X)
+    for idx in st.subs:
+        ref[idx] += np.linalg.inv(A[np.ix_(idx, idx)]) @ X[idx]
+    assert np.linalg.norm(st.H_AS(X) - ref) <= 1e-9 * np.linalg.norm(ref)
+
+
+def inertia_below(MA, MB, t):
+    """Number of eigenvalues of the pencil (MA, MB) below t, MB spd: the
+    negative pivots of an LDL^T of MA - t MB (Sylvester's law of inertia)."""
+    _, D, _ = sla.ldl(MA - t * MB, lower=True)
+    return int(np.count_nonzero(np.linalg.eigvalsh(D) < 0))      # D is block diagonal (1x1 / 2x2)
+
+
+def test_as_hyb_coarse_vectors_solve_their_pencils(case):
+    """Per subdomain, the first m1 coarse vectors are eigenvectors of
+    (D^-1 A^s_+ D^-1, R^s A R^sT) and the rest of (R^s A R^sT, R^s A_+ R^sT),
+    each set as large as the pencil's inertia below its threshold."""
+    w, st, Ap = case
+    c = st._as_hyb_space()
+    A = w.A.toarray()
+    for s, idx in enumerate(st.subs):
+        As = A[np.ix_(idx, idx)]
+        Dinv = 1.0 / st.Ds[s]
+        MA = Dinv[:, None] * st.split[s].A_plus() * Dinv[None, :]
+        MA = 0.5 * (MA + MA.T)
+        MB = Ap[np.ix_(idx, idx)]
+        Y = c["Y"][s]
+        m1 = c["m1"][s]
+        for (P_, Q_), Ys in (((MA, As), Y[:, :m1]), ((As, MB), Y[:, m1:])):
+            assert Ys.shape[1] == inertia_below(P_, Q_, st.tau)
+            if Ys.shape[1]:
+                lam = np.einsum("ij,ij->j", Ys, P_ @ Ys) / np.einsum("ij,ij->j", Ys, Q_ @ Ys)
+                assert np.all(lam < st.tau)
+                res = P_ @ Ys - (Q_ @ Ys) * lam
+                assert np.linalg.norm(res) <= 1e-8 * np.linalg.norm(P_) * np.linalg.norm(Ys)
+
+
 def spectrum(st, apply, M):
     H = O.dense_operator(apply, M.shape[0])
     assert np.linalg.norm(H - H.T) <= 1e-9 * np.linalg.norm(H)
@@ -87,6 +135,9 @@ def test_theorem_bounds(case):
     assert eva.min() >= (1 - TOL) / ((1 + 2 * ncol) * tflat) and eva.max() <= (ncol + 1) * (1 + TOL)
     if st.tau == 0.9:
         assert ev1.min() < 1 / tflat
+    # H^AS_hyb(tau_sharp, tau_flat), tau_sharp = tau: [1/tau_flat, N / tau_sharp]
+    evs = spectrum(st, st.H2_as_hyb, Ap)
+    assert evs.min() >= (1 - TOL) / tflat and evs.max() <= ncol / st.tau * (1 + TOL), (evs.min(), evs.max())
 
 
 def test_coarse_part_is_exact_on_the_coarse_space(case):
@@ -100,9 +151,14 @@ def test_coarse_part_is_exact_on_the_coarse_space(case):
     corr = st.H2_as_plus_ad(X) - st.H_AS_plus(X)
     assert np.linalg.norm(corr - R0T) <= 1e-8 * np.linalg.norm(R0T)
     assert np.linalg.norm(st.H2_as_plus_ad(X) - R0T) > 1e-3 * np.linalg.norm(R0T)
+    # H^AS_hyb on its own coarse space
+    c = st._as_hyb_space()
+    R0s = c["R0T"].toarray()[:, c["keep"]]
+    assert R0s.shape[1] > 0
+    assert np.linalg.norm(st.H2_as_hyb(Ap @ R0s) - R0s) <= 1e-8 * np.linalg.norm(R0s)
 
 
-@pytest.mark.parametrize("kind", ["asp_hyb", "asp_ad"])
+@pytest.mark.parametrize("kind", ["asp_hyb", "asp_ad", "as_hyb"])
 def test_h3_bounds_with_the_as_forms(case, kind):
     w, st, Ap = case
     h2 = st.h2(kind)

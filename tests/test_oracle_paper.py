@@ -63,8 +63,9 @@ def six_layers():
 
 @pytest.mark.parametrize("row", T1["rows"], ids=[f"{r['coarse2']}-{r['h2']}" for r in T1["rows"]])
 def test_paper_table1_awg_variants(six_layers, row):
-    """H3,ad and H3,hyb, each with H^NN_hyb(0.1), H^AS_{+,hyb}(10) and
-    H^AS_{+,ad}(10) as H2, on the six-layer problem (Table 1)."""
+    """The eight AWG rows of Table 1: H3,ad and H3,hyb, each with
+    H^NN_hyb(0.1), H^AS_hyb(0.1, 10), H^AS_{+,hyb}(10) and H^AS_{+,ad}(10) as
+    H2, on the six-layer problem."""
     w, st = six_layers
     assert st.n0 == T1["n0"] and st.n_minus == T1["n_minus"]
     h2 = st.h2(row["h2"])
