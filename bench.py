@@ -39,7 +39,7 @@ def parse():
                     help="GenEO eigensolver of the timed FP64 form")
     ap.add_argument("--coarse2", default="ad", choices=["ad", "inex", "hyb"],
                     help="second-coarse-space preconditioner H3 (both forms); ad is the default line")
-    ap.add_argument("--h2", default="nn_hyb", choices=["nn_hyb", "asp_hyb", "asp_ad"],
+    ap.add_argument("--h2", default="nn_hyb", choices=["nn_hyb", "asp_hyb", "asp_ad", "as_hyb"],
                     help="two-level preconditioner for A_+ (both forms); nn_hyb is the default line")
     ap.add_argument("--w-rtol", type=float, default=1e-10,
                     help="relative residual of the PCG solves for W (the paper's choice is 1e-10)")
@@ -321,19 +321,21 @@ def main():
         # the same workload with FP32 local operators (eigen-setup, coarse
         # spaces, PCG and W recurrences stay FP64), the subspace GenEO solver
         # and the learned start (network trained on other seeds of this family)
+        # (the two-pencil coarse space of as_hyb has the dense GenEO solver only)
+        fgeneo, fnet = ("dense", None) if args.h2 == "as_hyb" else ("subspace", net)
         awg.kernel_times(reset=True)
         awg.kernel_timing(True)
-        step("f32", "subspace", net)
+        step("f32", fgeneo, fnet)
         torch.cuda.synchronize()
         awg.kernel_timing(False)
         kt32 = awg.kernel_times(reset=True)
         t1 = time.perf_counter()
         for i in range(args.steps):
-            info32, st32 = step("f32", "subspace", net)
+            info32, st32 = step("f32", fgeneo, fnet)
         torch.cuda.synchronize()
         ms32 = (time.perf_counter() - t1) * 1e3 / args.steps
-        out["fast_form"] = {"local_prec": "f32", "geneo": "subspace", "eig_learned": st32["eig_learned"],
-                            "network": wfile,
+        out["fast_form"] = {"local_prec": "f32", "geneo": fgeneo, "eig_learned": st32["eig_learned"],
+                            "network": wfile if fnet is not None else None,
                             "eig_iters_max": max(st32["eig_iters"]),
                             "eig_fallbacks": st32["eig_fallbacks"], "ms_per_step": round(ms32, 3),
                             "iters": info32["iters"],

@@ -78,8 +78,14 @@ enum { AWG_COARSE2_AD = 0, AWG_COARSE2_INEX = 1, AWG_COARSE2_HYB = 2 };
  *                  H^AS_+ = sum_s R^sT (R^s A_+ R^sT)^{-1} R^s
  *                  (Theorem on H^AS_{+,hyb/ad}); spectrum in [tau, N(A_+)]
  *   AWG_H2_ASP_AD  H^AS_{+,ad}(1/tau) = H^AS_+ + R0^T E0^{-1} R0 (same theorem);
- *                  spectrum in [tau / (1 + 2 N(A_+)), N(A_+) + 1] */
-enum { AWG_H2_NN_HYB = 0, AWG_H2_ASP_HYB = 1, AWG_H2_ASP_AD = 2 };
+ *                  spectrum in [tau / (1 + 2 N(A_+)), N(A_+) + 1]
+ * and one on a coarse space of its own:
+ *   AWG_H2_AS_HYB  H^AS_hyb(tau, 1/tau) = Pi H^AS Pi^T + R0^T E0^{-1} R0,
+ *                  H^AS = sum_s R^sT (R^s A R^sT)^{-1} R^s, R0 from two pencils
+ *                  per subdomain: (D^-1 A^s_+ D^-1, R^s A R^sT) below tau, then
+ *                  (R^s A R^sT, R^s A_+ R^sT) below tau (Theorem on H^AS_hyb);
+ *                  spectrum in [tau, N(A_+)/tau]; needs AWG_GENEO_DENSE */
+enum { AWG_H2_NN_HYB = 0, AWG_H2_ASP_HYB = 1, AWG_H2_ASP_AD = 2, AWG_H2_AS_HYB = 3 };
 
 typedef struct {
   double tau;          /* GenEO threshold of H^NN_hyb(tau), tau_flat = 1/tau for the
@@ -117,7 +123,7 @@ typedef struct {
                             n x coord_dim row-major (features 0-2); NULL (default) */
   int32_t coord_dim;     /* 1..3 when coords is given */
   int32_t coarse2;       /* AWG_COARSE2_AD (default), AWG_COARSE2_INEX or AWG_COARSE2_HYB */
-  int32_t h2;            /* AWG_H2_NN_HYB (default), AWG_H2_ASP_HYB or AWG_H2_ASP_AD */
+  int32_t h2;            /* AWG_H2_NN_HYB (default), AWG_H2_ASP_HYB, AWG_H2_ASP_AD or AWG_H2_AS_HYB */
 } awg_options;
 
 /* Fill every field of *opt with the defaults above (tau = 0.1).  Host pointer. */
@@ -175,14 +181,16 @@ int64_t awg_stats(const awg_ctx* ctx, char* buf, size_t cap);
 
 /* Copy a named internal array to HOST memory (tests and diagnostics).
  *   "neg_eigs"   float64 [sum_s k_s]  non-positive eigenvalues of each B^s, ascending per s
- *   "geneo_eigs" float64 [sum_s m_s]  selected GenEO eigenvalues, ascending per s
+ *   "geneo_eigs" float64 [sum_s m_s]  selected GenEO eigenvalues, ascending per s (for
+ *                                     AWG_H2_AS_HYB: those of the first pencil, then of the second)
  *   "mult"       int32   [n]          multiplicity of each dof
  *   "pair_count" int32   [nnz]        M_mu on the pattern of A (CSR order)
  *   "V_minus"    float64 [sum_s n_s k_s] non-positive eigenvectors of each B^s
  *                                     (n_s x k_s column-major blocks, in subdomain order)
  *   "Y"          float64 [sum_s n_s m_s] GenEO coarse vectors Y^s (same layout)
  *   "P_local"    float64 [sum_s n_s^2] local operators of H2 (n_s x n_s blocks):
- *                                     D^s (A^s_+)^+ D^s, or (R^s A_+ R^sT)^{-1} for the AS forms
+ *                                     D^s (A^s_+)^+ D^s, (R^s A_+ R^sT)^{-1} for the AS_+ forms,
+ *                                     (R^s A R^sT)^{-1} for AWG_H2_AS_HYB
  *   "W"          float64 [n * n_minus] second coarse basis W = A_+^-1 V_- as computed
  *                                     (PCG to w_rtol), row-major: W[i * n_minus + j]
  * Returns the number of bytes of the array (copying min(cap, size)), or a

@@ -19,7 +19,7 @@ AWG_LOCAL_F64 = 0
 AWG_LOCAL_F32 = 1
 AWG_GENEO_DENSE, AWG_GENEO_SUBSPACE = 0, 1
 COARSE2 = {"ad": 0, "inex": 1, "hyb": 2}     # second-coarse-space preconditioner (awg.h)
-H2 = {"nn_hyb": 0, "asp_hyb": 1, "asp_ad": 2}  # two-level preconditioner for A_+ (awg.h)
+H2 = {"nn_hyb": 0, "asp_hyb": 1, "asp_ad": 2, "as_hyb": 3}  # two-level preconditioner for A_+ (awg.h)
 
 STATUS = {0: "AWG_OK", 1: "AWG_NOT_CONVERGED", -1: "AWG_ERR_ARG", -2: "AWG_ERR_NOT_SYMMETRIC",
           -3: "AWG_ERR_PARTITION", -4: "AWG_ERR_MIN_OVERLAP", -5: "AWG_ERR_NOT_SPD", -6: "AWG_ERR_EIGEN",

@@ -1136,8 +1136,9 @@ void phase_local(awg_ctx& c) {
   };
   // the AS forms of H2 need D^s (A^s_+)^+ D^s only in the subspace GenEO
   // solver (it applies the inverse of M_A^s with it)
-  const bool asp = c.opt.h2 != AWG_H2_NN_HYB;
-  const bool nn_formed = !asp || c.opt.geneo_solver == AWG_GENEO_SUBSPACE;
+  const bool asp = c.opt.h2 == AWG_H2_ASP_HYB || c.opt.h2 == AWG_H2_ASP_AD;
+  const bool ash = c.opt.h2 == AWG_H2_AS_HYB;   // dense GenEO solver only
+  const bool nn_formed = (!asp && !ash) || c.opt.geneo_solver == AWG_GENEO_SUBSPACE;
   if (nn_formed) {
     PhaseTimer t(c, "local_factor");
     // K^s = B^s + V_-(c_s - L_-)V_-^T (spd), c_s = mean diag B^s
@@ -1202,6 +1203,80 @@ void phase_local(awg_ctx& c) {
     trsm_batched(d1, dY, c.ns, c.ms, true, s, nullptr);
     c.n0 = (int)c.LY.cols;
   };
+  // H^AS_hyb(tau_sharp, tau_flat), tau_sharp = tau, tau_flat = 1/tau (Theorem
+  // on H^AS_hyb, Section 3.4): local operators (R^s A R^sT)^{-1} and the
+  // coarse space of two pencils per subdomain, Y_L(tau, D^-1 A^s_+ D^-1,
+  // R^s A R^sT) followed by Y_L(tau, R^s A R^sT, R^s A_+ R^sT)
+  if (ash) {
+    PhaseTimer t(c, "geneo");
+    build_pencil();                                                               // X3 = M_A, X1 = M_B
+    DBuf<double> X4;
+    X4.alloc(c.sqtot);
+    DBuf<MatDesc> d4;
+    d4.upload(square_descs(c, X4), s);
+    X2.zero(s);
+    l_extract(c.N, c.subptr, c.subidx, c.rowptr, c.col, c.val, d2, s);           // R^s A R^sT
+    l_scale_sym(d2, c.N, nullptr, nullptr, false, true, s);
+    l_copy_mat(d2, d4, c.N, s);
+    // Y_L(tau, G, F) with F = L L^T: eigenvectors Z of L^-1 G L^-T below tau,
+    // Y = L^-T Z (F and G destroyed: F holds L)
+    auto pencil = [&](DBuf<MatDesc>& G, DBuf<MatDesc>& F, ColLayout& L, DBuf<double>& Y, DBuf<double>& lam,
+                      const char* what) {
+      info.zero(s);
+      potrf_batched(F, c.ns, info, s, nullptr);
+      check_info(c, info, what);
+      trsm_batched(F, G, c.ns, c.ns, false, s, nullptr);
+      l_transpose_inplace(G, c.N, s);
+      trsm_batched(F, G, c.ns, c.ns, false, s, nullptr);
+      l_scale_sym(G, c.N, nullptr, nullptr, false, true, s);
+      EigOut eo = batched_low_eigs(c, G, 0, c.opt.tau, L, Y, lam, false);
+      c.eig_resid_max.push_back(eo.resid_max);
+      DBuf<MatDesc> dY;
+      dY.upload(col_descs(c, Y, L), s);
+      trsm_batched(F, dY, c.ns, eo.count, true, s, nullptr);
+      return eo.count;
+    };
+    ColLayout L1, L2;
+    DBuf<double> Y1, Y2, lam1, lam2;
+    const std::vector<int> m2 = pencil(d4, d1, L2, Y2, lam2, "GenEO M_B^s");                // (R A R^T, M_B)
+    const std::vector<int> m1 = pencil(d3, d2, L1, Y1, lam1, "local block R^s A R^sT");      // (M_A, R A R^T)
+    std::vector<int> ms(c.N);
+    for (int q = 0; q < c.N; ++q) ms[q] = m1[q] + m2[q];
+    c.LY.build(c.ns, ms, s);
+    c.Y.alloc(std::max<long>(1, c.LY.elems));
+    c.lamY.alloc(std::max<long>(1, c.LY.cols));
+    for (int q = 0; q < c.N; ++q) {
+      const long n1 = (long)c.ns[q] * m1[q], n2 = (long)c.ns[q] * m2[q];
+      if (n1) {
+        AWG_HIP(hipMemcpyAsync(c.Y.p + c.LY.eoff[q], Y1.p + L1.eoff[q], sizeof(double) * n1,
+                               hipMemcpyDeviceToDevice, s));
+        AWG_HIP(hipMemcpyAsync(c.lamY.p + c.LY.coff[q], lam1.p + L1.coff[q], sizeof(double) * m1[q],
+                               hipMemcpyDeviceToDevice, s));
+      }
+      if (n2) {
+        AWG_HIP(hipMemcpyAsync(c.Y.p + c.LY.eoff[q] + n1, Y2.p + L2.eoff[q], sizeof(double) * n2,
+                               hipMemcpyDeviceToDevice, s));
+        AWG_HIP(hipMemcpyAsync(c.lamY.p + c.LY.coff[q] + m1[q], lam2.p + L2.coff[q], sizeof(double) * m2[q],
+                               hipMemcpyDeviceToDevice, s));
+      }
+    }
+    c.ms = ms;
+    c.n0 = (int)c.LY.cols;
+    // P^s = (R^s A R^sT)^{-1} from the factor in d2, into X1 (its factor of M_B is spent)
+    l_set_identity(d1, c.N, s);
+    trsm_batched(d2, d1, c.ns, c.ns, false, s, nullptr);
+    trsm_batched(d2, d1, c.ns, c.ns, true, s, nullptr);
+    l_scale_sym(d1, c.N, nullptr, nullptr, false, true, s);
+    sync(c);   // the host-side layouts and Y1, Y2 end with this scope
+    std::swap(c.P.p, X1.p);
+    std::swap(c.P.n, X1.n);
+    if (c.opt.local_prec == AWG_LOCAL_F32) {
+      c.P32.alloc(c.sqtot);
+      hipLaunchKernelGGL(k_f32_from_f64, dim3(4096), dim3(256), 0, s, (long)c.sqtot, c.P.p, c.P32.p);
+      AWG_LAUNCH_CHECK();
+    }
+    return;
+  }
   bool mb_factored = false;   // d1 holds the Cholesky factor of M_B^s (dense solver), else M_B^s
   {
     PhaseTimer t(c, "geneo");
@@ -1800,7 +1875,8 @@ int awg_setup(awg_ctx** out, int64_t n, int64_t nnz, const int64_t* rowptr, cons
       o.eig_block > SUBSPACE_MAX_BLOCK || o.eig_maxit < 1 || !(o.eig_tol > 0.0) ||
       (o.coords && (o.coord_dim < 1 || o.coord_dim > 3)) ||
       (o.coarse2 != AWG_COARSE2_AD && o.coarse2 != AWG_COARSE2_INEX && o.coarse2 != AWG_COARSE2_HYB) ||
-      (o.h2 != AWG_H2_NN_HYB && o.h2 != AWG_H2_ASP_HYB && o.h2 != AWG_H2_ASP_AD)) {
+      (o.h2 != AWG_H2_NN_HYB && o.h2 != AWG_H2_ASP_HYB && o.h2 != AWG_H2_ASP_AD && o.h2 != AWG_H2_AS_HYB) ||
+      (o.h2 == AWG_H2_AS_HYB && o.geneo_solver != AWG_GENEO_DENSE)) {
     g_setup_error = "awg_setup: invalid option value";
     return AWG_ERR_ARG;
   }

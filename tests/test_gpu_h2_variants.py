@@ -3,8 +3,10 @@ H^AS_{+,hyb/ad}, Section 3.4) against the oracle's H^AS_{+,hyb} and
 H^AS_{+,ad}, through the C ABI: the local operators (R^s A_+ R^sT)^{-1}, the
 applied H (with H3,ad, and one case each with H3,inex and H3,hyb) to the
 tolerance derived from the conditioning of the operators, the PCG iterate to
-1e-10 relative and the iteration count within 1; and the six AWG rows of
-Table 1 that the library builds, on the paper's own test problem."""
+1e-10 relative and the iteration count within 1; the same for
+H^AS_hyb(tau_sharp, tau_flat) (Theorem on H^AS_hyb) with its local blocks
+R^s A R^sT and two-pencil coarse space; and the eight AWG rows of Table 1 on
+the paper's own test problem."""
 import numpy as np
 import pytest
 
@@ -31,16 +33,21 @@ def cases():
 
 CASES = cases()
 # (case, h2, coarse2, geneo)
-COMBOS = [(c, h, "ad", "dense") for c in sorted(CASES) for h in ("asp_hyb", "asp_ad")] + [
+COMBOS = [(c, h, "ad", "dense") for c in sorted(CASES) for h in ("asp_hyb", "asp_ad", "as_hyb")] + [
     ("fd5_32", "asp_hyb", "inex", "dense"), ("fd16_uneven", "asp_ad", "hyb", "dense"),
+    ("q1_2d_32_rcb", "as_hyb", "hyb", "dense"),
     ("q1_2d_32_rcb", "asp_hyb", "ad", "subspace"), ("elast_x0_small", "asp_ad", "ad", "subspace")]
 
 
-def h_rtol(st):
-    """10 eps max(cond(M_B^s), cond(E0), cond(W^T A W)), floor 1e-10."""
+def h_rtol(st, h2):
+    """10 eps max(cond of the local blocks, cond(E0), cond(W^T A W)), floor 1e-10."""
     kap = max(np.linalg.cond(0.5 * (M + M.T)) for M in st.MB)
     if st.n0:
         kap = max(kap, np.linalg.cond(st.E0[np.ix_(st.E0_keep, st.E0_keep)]))
+    if h2 == "as_hyb":
+        c = st._as_hyb_space()
+        kap = max(kap, np.linalg.cond(c["E0"][np.ix_(c["keep"], c["keep"])]),
+                  max(np.linalg.cond(st.A[idx][:, idx].toarray()) for idx in st.subs))
     if st.n_minus:
         kap = max(kap, np.linalg.cond(st.C[np.ix_(st.C_keep, st.C_keep)]),
                   np.linalg.cond(st.EW[np.ix_(st.EW_keep, st.EW_keep)]))
@@ -81,16 +88,20 @@ def oracle_apply(st, h2, coarse2):
 def test_local_operators_and_stats(combo):
     w, st, solver, h2, coarse2 = combo
     s = solver.stats()
-    assert s["h2"] == {"asp_hyb": 1, "asp_ad": 2}[h2]
-    assert s["n0"] == st.n0 and s["n_minus"] == st.n_minus
+    assert s["h2"] == {"asp_hyb": 1, "asp_ad": 2, "as_hyb": 3}[h2]
+    n0 = st._as_hyb_space()["R0T"].shape[1] if h2 == "as_hyb" else st.n0
+    assert s["n0"] == n0 and s["n_minus"] == st.n_minus
+    if h2 == "as_hyb":
+        assert s["m_s"] == [Y.shape[1] for Y in st._as_hyb_space()["Y"]]
     P_loc = solver.export("P_local")
     o = 0
     for idx, MB in zip(st.subs, st.MB):
         n = len(idx)
         Pg = P_loc[o:o + n * n].reshape(n, n)
         o += n * n
-        ref = np.linalg.inv(0.5 * (MB + MB.T))
-        assert np.linalg.norm(Pg - ref) <= 10 * EPS * np.linalg.cond(MB) * np.linalg.norm(ref)
+        M = st.A[idx][:, idx].toarray() if h2 == "as_hyb" else MB
+        ref = np.linalg.inv(0.5 * (M + M.T))
+        assert np.linalg.norm(Pg - ref) <= 10 * EPS * np.linalg.cond(M) * np.linalg.norm(ref)
     assert o == P_loc.size
 
 
@@ -103,7 +114,7 @@ def test_apply_matches_oracle(combo):
         r = rng.standard_normal(w.A.shape[0])
         z = solver.apply(torch.as_tensor(r, device="cuda")).cpu().numpy()
         zr = ap(r)
-        assert np.linalg.norm(z - zr) <= h_rtol(st) * np.linalg.norm(zr)
+        assert np.linalg.norm(z - zr) <= h_rtol(st, h2) * np.linalg.norm(zr)
 
 
 def test_pcg_matches_oracle(combo):
@@ -119,9 +130,13 @@ def test_pcg_matches_oracle(combo):
 
 
 def test_rejects_unknown_h2(gpu_lib):
+    from paper_2106_10913_amd.awg import AWGError
     w = CASES["fd5_32"]
     with pytest.raises(ValueError):
-        gpu_lib.Solver(w.A, w.subs, tau=w.tau, h2="as_hyb")
+        gpu_lib.Solver(w.A, w.subs, tau=w.tau, h2="as")
+    # the two-pencil coarse space has no subspace solver
+    with pytest.raises(AWGError):
+        gpu_lib.Solver(w.A, w.subs, tau=w.tau, h2="as_hyb", geneo="subspace")
 
 
 _T1 = None
@@ -143,13 +158,14 @@ def six_layers():
     return w, O.setup(w.A, w.subs, w.tau)
 
 
-@pytest.mark.parametrize("row", range(6))
+@pytest.mark.parametrize("row", range(8))
 def test_paper_table1_rows_on_gpu(gpu_lib, six_layers, row):
-    """The six AWG rows of Table 1 that the library builds, on the paper's
-    six-layer problem (n = 8064): #V0 and n_- exactly, kappa (Lanczos
-    estimate from the PCG coefficients, stopping at ||r||/||b|| <= 1e-8)
-    within 3 % of the printed value, iterations within 1 of the oracle's
-    with the same stopping test."""
+    """The eight AWG rows of Table 1, on the paper's six-layer problem
+    (n = 8064): #V0 and n_- exactly; stopping at ||r||/||b|| <= 1e-8, the
+    iteration count within 1 and the Lanczos estimate of kappa within 1 % of
+    the oracle's with the same stopping test, and within 5 % of the printed
+    value (the oracle matches the printed values to 3 % with the paper's own
+    stopping test)."""
     import torch
     w, st = six_layers
     T1 = table1()
@@ -162,8 +178,12 @@ def test_paper_table1_rows_on_gpu(gpu_lib, six_layers, row):
     s.close()
     assert info["converged"] == 1
     kappa = info["lmax_est"] / info["lmin_est"]
-    assert abs(kappa - r["kappa"]) <= 0.03 * r["kappa"], (kappa, r["kappa"])
     f = st.h2(r["h2"])
     ap = (lambda v: st.apply(v, h2=f)) if r["coarse2"] == "ad" else (lambda v: st.apply_hyb(v, h2=f))
     ref = O.pcg(w.A, w.b, ap, tol=1e-8, maxit=500)
     assert abs(info["iters"] - ref.iters) <= 1
+    lmin, lmax = ref.lanczos_extremes()
+    assert abs(kappa - lmax / lmin) <= 0.01 * lmax / lmin, (kappa, lmax / lmin)
+    # the printed kappa is the estimate after the paper's own (preconditioned
+    # norm, 1e-10) stopping test; this one stops earlier on ||r||
+    assert abs(kappa - r["kappa"]) <= 0.05 * r["kappa"], (kappa, r["kappa"])
