@@ -382,10 +382,29 @@ class AWGSetup:
                             shape=(self.n, off))
         E0 = np.asarray(R0T.T @ self.A_plus_mv(R0T.toarray()))
         E0 = 0.5 * (E0 + E0.T)
-        keep = gram_keep(E0)
-        self.ash = dict(Y=Ys, m1=m1s, R0T=R0T, E0=E0, keep=keep,
-                        cho=sla.cho_factor(E0[np.ix_(keep, keep)], lower=True), local=chol)
+        # the union of the two pencils' vectors can be numerically dependent
+        # across subdomains with every pivot of E0 well above GRAM_DROP_TOL:
+        # its pseudo-inverse deflates the eigenvectors Z of the Jacobi-scaled
+        # Es = S^-1 E0 S^-1 below 1e-10 instead,
+        #   E0^+ = S^-1 ((Es + Z Z^T)^-1 - Z Z^T) S^-1
+        sc = np.sqrt(np.diag(E0))
+        Es = E0 / sc[:, None] / sc[None, :]
+        lam, V = np.linalg.eigh(Es)
+        Z = V[:, lam < 1e-10]
+        Ms = Es + Z @ Z.T
+        keep = gram_keep(Ms)
+        self.ash = dict(Y=Ys, m1=m1s, R0T=R0T, E0=E0, keep=keep, scale=sc, Z=Z,
+                        cho=sla.cho_factor(Ms[np.ix_(keep, keep)], lower=True), local=chol)
         return self.ash
+
+    def E0_as_solve(self, g):
+        """E0^+ g on the coarse space of H^AS_hyb (deflated pseudo-inverse)."""
+        c = self._as_hyb_space()
+        h = g / c["scale"] if g.ndim == 1 else g / c["scale"][:, None]
+        out = np.zeros_like(h, dtype=np.float64)
+        out[c["keep"]] = sla.cho_solve(c["cho"], h[c["keep"]])
+        out -= c["Z"] @ (c["Z"].T @ h)
+        return out / c["scale"] if g.ndim == 1 else out / c["scale"][:, None]
 
     def H_AS(self, X):
         """H^AS X = sum_s R^sT (R^s A R^sT)^{-1} R^s X (one-level, Section 3.3)."""
@@ -400,11 +419,7 @@ class AWGSetup:
         V0_AS(tau_sharp, tau_flat), Pi_AS = I - R0^T E0^{-1} R0 A_+."""
         c = self._as_hyb_space()
         R0T = c["R0T"]
-
-        def e0(g):
-            out = np.zeros_like(g, dtype=np.float64)
-            out[c["keep"]] = sla.cho_solve(c["cho"], g[c["keep"]])
-            return out
+        e0 = self.E0_as_solve
         u0 = e0(R0T.T @ r)
         t = r - self.A_plus_mv(R0T @ u0)
         y = self.H_AS(t)
