@@ -336,7 +336,7 @@ def main():
         ms32 = (time.perf_counter() - t1) * 1e3 / args.steps
         out["fast_form"] = {"local_prec": "f32", "geneo": fgeneo, "eig_learned": st32["eig_learned"],
                             "network": wfile if fnet is not None else None,
-                            "eig_iters_max": max(st32["eig_iters"]),
+                            "eig_iters_max": max(st32["eig_iters"], default=0),
                             "eig_fallbacks": st32["eig_fallbacks"], "ms_per_step": round(ms32, 3),
                             "iters": info32["iters"],
                             "rel_res_true": info32["rel_res_true"], "n_minus": st32["n_minus"], "n0": st32["n0"],

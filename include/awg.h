@@ -84,7 +84,11 @@ enum { AWG_COARSE2_AD = 0, AWG_COARSE2_INEX = 1, AWG_COARSE2_HYB = 2 };
  *                  H^AS = sum_s R^sT (R^s A R^sT)^{-1} R^s, R0 from two pencils
  *                  per subdomain: (D^-1 A^s_+ D^-1, R^s A R^sT) below tau, then
  *                  (R^s A R^sT, R^s A_+ R^sT) below tau (Theorem on H^AS_hyb);
- *                  spectrum in [tau, N(A_+)/tau]; needs AWG_GENEO_DENSE */
+ *                  spectrum in [tau, N(A_+)/tau]; needs AWG_GENEO_DENSE.  Its
+ *                  E0^+ deflates the eigenvectors of the Jacobi-scaled E0 below
+ *                  1e-10 (the union of two pencils' vectors can be dependent
+ *                  across subdomains); at most 64 such directions, else
+ *                  AWG_ERR_NOT_SPD */
 enum { AWG_H2_NN_HYB = 0, AWG_H2_ASP_HYB = 1, AWG_H2_ASP_AD = 2, AWG_H2_AS_HYB = 3 };
 
 typedef struct {

@@ -15,6 +15,7 @@
 #include <sstream>
 
 #include "awg.h"
+#include "awg_dense.h"
 #include "awg_common.h"
 #include "awg_sparse.h"
 #include "awg_subspace.h"
@@ -1380,6 +1381,57 @@ int spd_inverse(awg_ctx& c, double* M, int n, DBuf<double>& Minv, const char* wh
   return nd;
 }
 
+__global__ void k_sqrt_diag(const double* M, int n, double* d) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) d[i] = sqrt(M[i + (long)i * n]);
+}
+
+// Pseudo-inverse of a Gram matrix E (n x n, destroyed) of a basis whose
+// dependence its Cholesky pivots do not reveal (a combination of many
+// columns, each far from the span of the previous ones): with the Jacobi
+// scaling Es = S^-1 E S^-1 (unit diagonal) and the eigenvectors Z of Es with
+// eigenvalue below 1e-10, E^+ = S^-1 ((Es + Z Z^T)^-1 - Z Z^T) S^-1 (the
+// inverse on the complement of the near-null combinations, zero on them;
+// the inverse itself by spd_inverse).  Returns the number of deflated and
+// deleted directions.
+int deflated_inverse(awg_ctx& c, double* E, int n, DBuf<double>& Einv, const char* what) {
+  hipStream_t s = c.s;
+  constexpr int KMAX = 64;
+  DBuf<double> sc, Et, lam, Z;
+  sc.alloc(n);
+  hipLaunchKernelGGL(k_sqrt_diag, dim3(cdiv(n, 256)), dim3(256), 0, s, E, n, sc.p);
+  AWG_LAUNCH_CHECK();
+  DBuf<long> off0;
+  off0.upload({0L}, s);
+  DBuf<MatDesc> dm;
+  dm.upload({MatDesc{E, n, n, n, 0}}, s);
+  l_scale_sym(dm, 1, off0, sc, true, true, s);                              // Es
+  Et.alloc((long)n * n);
+  AWG_HIP(hipMemcpyAsync(Et.p, E, sizeof(double) * n * n, hipMemcpyDeviceToDevice, s));
+  lam.alloc(KMAX);
+  Z.alloc((long)n * KMAX);
+  int32_t k = 0;
+  const int rc = awg_dense_low_eigs(1, n, Et.p, n, 0, 1e-10, KMAX, &k, lam.p, Z.p, 0, s);
+  if (rc != AWG_OK)
+    throw Error(rc == AWG_ERR_ARG ? AWG_ERR_NOT_SPD : rc,
+                std::string(what) + ": more near-null directions than the deflation keeps (64)");
+  DBuf<GemmDesc> dg;
+  if (k > 0) {
+    dg.upload({GemmDesc{Z.p, Z.p, E, n, n, k, n, n, n}}, s);
+    gemm_batched(dg, 1, n, n, false, true, 1.0, 1.0, false, s, 2.0 * n * (double)n * k);   // Es + Z Z^T
+  }
+  const int nd = spd_inverse(c, E, n, Einv, what);
+  if (k > 0) {
+    dg.upload({GemmDesc{Z.p, Z.p, Einv.p, n, n, k, n, n, n}}, s);
+    gemm_batched(dg, 1, n, n, false, true, -1.0, 1.0, false, s, 2.0 * n * (double)n * k);  // - Z Z^T
+  }
+  DBuf<MatDesc> di;
+  di.upload({MatDesc{Einv.p, n, n, n, 0}}, s);
+  l_scale_sym(di, 1, off0, sc, true, true, s);                              // S^-1 (.) S^-1
+  sync(c);
+  return nd + k;
+}
+
 // number of columns per pass: at most cap (even), balanced over the passes and
 // rounded up to even (16-byte rows for the vectorised gather / scatter); the
 // columns past the total are kept at zero
@@ -1411,7 +1463,10 @@ void phase_coarse0(awg_ctx& c) {
                        (long)c.n0, (long)c.n0, c0, bc);
     AWG_LAUNCH_CHECK();
   }
-  c.n0_dropped = spd_inverse(c, E0, c.n0, c.E0inv, "coarse matrix E0");
+  // the two-pencil basis of H^AS_hyb can be dependent across subdomains in a
+  // way no pivot shows; the other coarse spaces keep the pivoted deletion
+  c.n0_dropped = c.opt.h2 == AWG_H2_AS_HYB ? deflated_inverse(c, E0, c.n0, c.E0inv, "coarse matrix E0")
+                                           : spd_inverse(c, E0, c.n0, c.E0inv, "coarse matrix E0");
 }
 
 // W = A_+^{-1} [R^1T V^1_- | ... ] (strictly negative pairs; Remark 1 and 2,
