@@ -1,8 +1,9 @@
 """FP32 local operators (local_prec = f32): the eigen-setup stays FP64, so the
 coarse spaces are identical; the local products run in FP32 (mixed GEMM in
-the W solves, FP32 GEMV in PCG).  Judged by the true final residual and the
-iteration increase over the FP64 form (no element-wise parity: the operator
-itself differs by FP32 rounding)."""
+the W solves, FP32 GEMV in PCG).  Judged, for every choice of H2, by the
+true final residual and the iteration increase over the FP64 form of the
+same preconditioner (no element-wise parity: the operator itself differs by
+FP32 rounding)."""
 import numpy as np
 import pytest
 
@@ -13,14 +14,20 @@ pytestmark = pytest.mark.gpu
 CASES = {"fd5_32": P.fd5_32, "q1_2d_64": lambda: P.q1_2d(m=64, boxes=(2, 2))}
 
 
+# every choice of H2: the FP32 copy of its local operators is made where
+# each of them is formed
+H2S = ["nn_hyb", "asp_hyb", "asp_ad", "as_hyb"]
+
+
+@pytest.mark.parametrize("h2", H2S)
 @pytest.mark.parametrize("name", sorted(CASES))
-def test_f32_local_converges(gpu_lib, name):
+def test_f32_local_converges(gpu_lib, name, h2):
     import torch
     w = CASES[name]()
-    print(f"\n[gpu case] f32 {name} n={w.A.shape[0]}", flush=True)
+    print(f"\n[gpu case] f32 {name} h2={h2} n={w.A.shape[0]}", flush=True)
     b = torch.as_tensor(w.b, device="cuda")
-    s64 = gpu_lib.Solver(w.A, w.subs, tau=w.tau, local_prec="f64")
-    s32 = gpu_lib.Solver(w.A, w.subs, tau=w.tau, local_prec="f32")
+    s64 = gpu_lib.Solver(w.A, w.subs, tau=w.tau, local_prec="f64", h2=h2)
+    s32 = gpu_lib.Solver(w.A, w.subs, tau=w.tau, local_prec="f32", h2=h2)
     st64, st32 = s64.stats(), s32.stats()
     assert st32["n_minus"] == st64["n_minus"] and st32["n0"] == st64["n0"]
     x64, i64 = s64.pcg(b, tol=w.tol)
