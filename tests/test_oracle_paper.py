@@ -99,6 +99,22 @@ def test_paper_table4_w_tolerance(row):
     assert abs(res.iters - row["it"]) <= 2
 
 
+def test_paper_table4_nu04_exact_w():
+    """Table 4, nu = 0.4, with W to 1e-10: #V0, n_-, kappa and iterations.
+    The 1e-2 row is not compared: there the paper's W solves (preconditioned
+    norm) and these (||r||_2) stop at different iterates."""
+    g = GOLD["table4_nu04"]
+    row = g["rows"][0]
+    w = P.paper_x0(tau=g["tau"], **g["kwargs"])
+    st = O.setup(w.A, w.subs, w.tau, w_solver="pcg", w_rtol=row["w_rtol"])
+    assert st.n0 == g["n0"] and st.n_minus == g["n_minus"]
+    res = O.pcg(w.A, w.b, st.apply, tol=1e-10, norm="preconditioned", maxit=200)
+    assert res.converged
+    lmin, lmax = res.lanczos_extremes()
+    assert abs(lmax / lmin - row["kappa"]) <= 0.03 * row["kappa"]
+    assert abs(res.iters - row["it"]) <= 2
+
+
 @pytest.mark.parametrize("i", range(5))
 def test_paper_long_domain(i):
     g = GOLD["long_domain"]
