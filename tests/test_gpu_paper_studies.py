@@ -108,3 +108,14 @@ def test_long_domain_weak_scaling_beyond_the_table(gpu_lib):
                          kappa=round(kappa, 3), rel_res_true=info["rel_res_true"], converged=info["converged"],
                          setup_ms=round(st["ms"]["total"], 1), total_ms=round(ms, 1)))
     print("[long domain] " + json.dumps(rows), flush=True)
+
+
+def test_table4_nu04_row(gpu_lib):
+    """Table 4, nu = 0.4, W to 1e-10 (the six-layer problem with Poisson
+    ratio 0.4): #V0 and n_- as printed, iterations and kappa against the
+    oracle with the same stopping test."""
+    g = GOLD["table4_nu04"]
+    w = P.paper_x0(tau=g["tau"], **g["kwargs"])
+    print("\n[gpu case] paper problem nu = 0.4 (Table 4)", flush=True)
+    st, info, ms = run_gpu(gpu_lib, w)
+    check_against(w, st, info, g["n0"], g["n_minus"], None)
