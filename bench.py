@@ -1,17 +1,26 @@
-"""Benchmark: AWG-PCG time to a 1e-8 relative residual (setup + solve) on one MI355X.
+"""Benchmark: AWG-PCG time to a 1e-8 relative residual (setup + solve) on one
+MI355X, FP32 local operators + learned GenEO start against plain FP64.
 
-Workload: 2D Q1 FEM diffusion on a 256 x 256 cell grid of [0,1]^2 (n = 65,792),
-Dirichlet on x = 0, log10 k ~ N(0, 1.5^2) per cell plus 8 horizontal
-channels k = 1e5 (seed 1), b = ones, 8 x 8 node boxes with overlap 2
-(64 subdomains), GenEO threshold tau = 0.1, PCG tolerance 1e-8 on
-||r||/||b||, FP64 everywhere.  Synthetic input shaped like the paper's
-experiments (no dataset).
+Default workload (the largest single-GPU configuration, the one the learned
+start is built for): 3D Q1 FEM diffusion on 65^3 cells of [0,1]^3, Dirichlet
+all round (n = 64^3 = 262,144, nnz = 6,859,000), log10 k = 1.5 x a Gaussian
+random field with correlation length U(4,16) cells (seed 2000, a seed the
+network never saw), b = ones, 512 boxes of 8^3 nodes with overlap 1, GenEO
+threshold tau = 0.1, PCG tolerance 1e-8 on ||r||/||b||.  Synthetic input
+shaped like the paper's experiments (no dataset).
 
 One step = awg_setup (every set-up phase on the GPU) + awg_pcg from x0 = 0,
-with A, b and the subdomain lists already resident in HBM.  The JSON line
-reports ms per step (lower is better), the dominant kernel against its
-roofline, and the FP64 CPU oracle timed on a bounded sample of the same
-workload.
+with A, b and the subdomain lists already resident in HBM.  Two forms run
+K steps each:
+  plain  FP64 everywhere, dense GenEO eigensolver;
+  fast   FP32 local operators (eigen-setup, coarse spaces, PCG and W
+         recurrences in FP64), subspace GenEO eigensolver warm-started by
+         the network, graph-captured PCG iteration.
+Both must reach a true residual ||b - A x|| / ||b|| <= 1e-8 in every timed
+step (accuracy_ok).  value = the fast form's ms per step; the plain form's
+time and the speed-up are reported beside it.  The JSON line also carries
+the dominant kernel of the fast form against its roofline and the FP64 CPU
+oracle timed on a bounded, phase-by-phase sample of the same workload.
 """
 from __future__ import annotations
 
@@ -45,60 +54,169 @@ def parse():
                     help="relative residual of the PCG solves for W (the paper's choice is 1e-10)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fast-form", action="store_true")
-    ap.add_argument("--workload", default="q1_2d_256", choices=sorted(WORKLOADS),
-                    help="q1_2d_256 is the headline workload; the others are the larger synthetic configurations")
+    ap.add_argument("--workload", default="diff3d_64", choices=sorted(WORKLOADS),
+                    help="diff3d_64 (the largest single-GPU configuration) is the headline workload")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (HBM counter calibration)")
     return ap.parse_args()
 
 
-def cpu_baseline(w, budget_subdomains: int = 6):
-    """FP64 oracle on a bounded sample of the workload.
+def cpu_baseline(w, workload: str, k_sub: int = 8, b_cols: int = 64):
+    """FP64 oracle timed on a bounded, phase-by-phase sample of the workload.
 
-    Sample: the per-subdomain oracle work (dense eigendecomposition of B^s,
-    the GenEO generalized eigenproblem with M_B^s) on the first
-    ``budget_subdomains`` subdomains, scaled to all N subdomains.  The oracle's
-    global phases (coarse matrices, W, PCG) need every local result, so they
-    are not in the sample; the scaled figure is a lower bound of the oracle's
-    setup + solve time.
+    The oracle's full run on the large workloads takes from many minutes to
+    hours, so every phase is timed on a part of the workload and scaled by
+    its work ratio to the whole:
+      maps     pair counts M_mu and B on k_sub of the N subdomains, x N/k_sub;
+      split    eigendecomposition of B^s on k_sub subdomains, x N/k_sub;
+      geneo    M_B^s and the generalized eigensolve on the same, x N/k_sub;
+      coarse0  E0 = R0 A_+ R0^T for the sampled subdomains' coarse columns,
+               x n0/columns, plus the deleting Cholesky of an n0 x n0 Gram
+               matrix (n0 estimated as N/k_sub x the sampled columns);
+      W        the oracle's route for this size: a sparse LU of A (in full)
+               and 2 n_- column solves (sampled on b_cols), or, above
+               W_DIRECT_MAX_N, PCG with H2 on every column: it_W x n_-/b_cols x
+               (one H2 application to b_cols columns, local parts sampled);
+      pcg      iters x (one application of H and one product with A to a
+               vector, local parts sampled).
+    it_W and iters come from the oracle-only golden file of the workload when
+    it holds them (else 40 each), and so do n0 and n_- (else estimated from
+    the sample).  Threads: the host cores visible to the
+    process (the BLAS uses them all).
     """
     import numpy as np
+    import scipy.linalg as sla
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spla
     from oracle import awg_oracle as O
     threads = len(os.sched_getaffinity(0))
-    A = w.A
-    subs = w.subs
-    n = A.shape[0]
-    t0 = time.perf_counter()
+    A = w.A.tocsr()
+    subs = [np.asarray(t, dtype=np.int64) for t in w.subs]
+    n, N = A.shape[0], len(subs)
+    k = min(k_sub, N)
+    rng = np.random.default_rng(0)
+    samp = np.sort(rng.choice(N, k, replace=False))
+    scale = N / k
+    gold = os.path.join(ROOT, "tests", "golden", f"{workload}.json")
+    g = {}
+    if os.path.exists(gold):
+        with open(gold) as f:
+            g = json.load(f)
+    iters, it_w, src = 40, 40, "assumed 40"
+    if "iters" in g:
+        iters, src = int(g["iters"]), "oracle golden file"
+        it_w = int(g.get("w_iters_max") or it_w)
+    ts = {}
+    clock = time.perf_counter
+    t0 = clock()
     Ds = O.partition_of_unity(n, subs)
-    cnt = O.pair_multiplicity(A, subs)
-    B = O.algebraic_B(A, cnt)
-    t_maps = time.perf_counter() - t0
-    k = min(budget_subdomains, len(subs))
-    # neighbours of the sampled subdomains need their splitting for M_B^s
-    t1 = time.perf_counter()
-    split = {}
-    for s in range(k):
+    cnt = O.pair_multiplicity(A, [subs[s] for s in samp])
+    ts["maps"] = (clock() - t0) * scale
+    # exact M_mu on the rows of the sampled subdomains (untimed input of the
+    # sampled phases): counts of subdomains holding both ends of each nonzero,
+    # from the subdomain incidence matrix S (N x n) as (S^T S)_ij on A's pattern
+    S = sp.csr_matrix((np.ones(sum(t.size for t in subs)),
+                       (np.concatenate([np.full(t.size, q) for q, t in enumerate(subs)]), np.concatenate(subs))),
+                      shape=(N, n))
+    rows = np.unique(np.concatenate([subs[s] for s in samp]))
+    C = (S[:, rows].T @ S).tocsr()
+    Ar = A[rows]
+    cnt = np.maximum(np.asarray(C[np.repeat(np.arange(rows.size), np.diff(Ar.indptr)), Ar.indices]).ravel(), 1)
+    Bd = A.tolil()
+    Bd[rows] = sp.csr_matrix((Ar.data / cnt, Ar.indices, Ar.indptr), shape=Ar.shape)
+    B = Bd.tocsr()
+    empty = O.LocalSplit(np.zeros(0), np.zeros((0, 0)), 0, 0, 0.0)
+    split = [empty] * N
+    t0 = clock()
+    for s in samp:
         split[s] = O.split_local(O.local_block(B, subs[s]))
-    t_split = time.perf_counter() - t1
-    # M_B^s from the sampled splittings (the other subdomains' terms are
-    # taken as zero: the timing, not the values, is what is sampled)
-    t2 = time.perf_counter()
-    for s in range(k):
-        MB = O.local_block(A, subs[s])
-        for t in range(k):
-            common, ps, pt = np.intersect1d(subs[s], subs[t], assume_unique=True, return_indices=True)
-            if common.size and split[t].nneg:
-                Vt = split[t].V_minus[pt]
-                MB[np.ix_(ps, ps)] += -(Vt * split[t].L_minus) @ Vt.T
-        O.geneo_local(split[s], Ds[s], MB, w.tau)
-    t_geneo = time.perf_counter() - t2
-    N = len(subs)
-    est = t_maps + (t_split + t_geneo) * N / k
+    ts["split"] = (clock() - t0) * scale
+    Ys = {}
+    t0 = clock()
+    for s in samp:
+        Ys[s], _ = O.geneo_local(split[s], Ds[s], O.local_MB(A, subs, split, s), w.tau)
+    ts["geneo"] = (clock() - t0) * scale
+    # coarse0: the sampled columns of R0^T through A_+ and R0
+    rows_, cols_, vals_ = [], [], []
+    off = 0
+    for s in samp:
+        m = Ys[s].shape[1]
+        rows_.append(np.repeat(subs[s], m))
+        cols_.append(np.tile(np.arange(off, off + m), subs[s].size))
+        vals_.append(Ys[s].ravel())
+        off += m
+    R0T = sp.csr_matrix((np.concatenate(vals_), (np.concatenate(rows_), np.concatenate(cols_))), shape=(n, off))
+    n0 = int(g["n0"]) if "n0" in g else max(1, int(round(off * scale)))
+    st = O.AWGSetup(A=A, subs=subs, tau=w.tau, Ds=Ds, cnt=cnt, B=B, split=split, Y=None, geneo_lam=None,
+                    R0T=R0T, E0=None, E0_cho=None, W=np.zeros((n, 0)), EW=None, EW_cho=None, Vg=None, w_info={})
+    t0 = clock()
+    _ = R0T.T.tocsr() @ st.A_plus_mv(R0T.toarray())
+    t_cols = clock() - t0
+    Gm = rng.standard_normal((n0, n0 + 8))
+    G = Gm @ Gm.T
+    t0 = clock()
+    O.gram_keep(G)
+    Gc = sla.cho_factor(G, lower=True)
+    ts["coarse0"] = t_cols * n0 / max(1, off) + (clock() - t0)
+    nm = int(g["n_minus"]) if "n_minus" in g else max(1, int(round(sum(split[s].nstrict for s in samp) * scale)))
+
+    def apply_local(X):
+        """local parts of one application (A_- and H^NN) on the sampled subdomains"""
+        for s in samp:
+            sp_ = split[s]
+            Xs = Ds[s][:, None] * X[subs[s]]
+            sp_.V_minus @ (sp_.V_minus.T @ Xs)
+            sp_.V_plus @ ((sp_.V_plus.T @ Xs) / sp_.L_plus[:, None])
+
+    def h2_cost(b):
+        """seconds of one oracle H2 application to b columns (+ one A_+ product)"""
+        X = rng.standard_normal((n, b))
+        t0 = clock()
+        apply_local(X)
+        t_loc = (clock() - t0) * scale * 2              # H^NN and the two A_- terms of H2 and A_+
+        t0 = clock()
+        for _ in range(3):
+            A @ X                                        # two A_+ products in H2, one in PCG
+        u = sla.cho_solve(Gc, rng.standard_normal((n0, b)))
+        sla.cho_solve(Gc, u)                             # two E0 solves
+        t_glob = clock() - t0
+        t0 = clock()
+        for _ in range(2):                               # two R0 and two R0^T products (sampled columns)
+            R0T @ u[:off]
+            R0T.T @ X
+        return t_loc + t_glob + (clock() - t0) * n0 / max(1, off)
+
+    if n <= O.W_DIRECT_MAX_N:
+        t0 = clock()
+        lu = spla.splu(A.tocsc())
+        t_lu = clock() - t0
+        V = np.zeros((n, b_cols))
+        V[rng.integers(0, n, b_cols), np.arange(b_cols)] = 1.0
+        t0 = clock()
+        lu.solve(V)
+        ts["W"] = t_lu + (clock() - t0) * 2 * nm / b_cols
+        w_how = f"sparse LU of A in full ({t_lu:.1f} s) + {b_cols} of 2 n_- column solves"
+    else:
+        ts["W"] = it_w * (nm / b_cols) * h2_cost(b_cols)
+        w_how = f"PCG with H2: {it_w} iterations x n_-/{b_cols} x one H2 application to {b_cols} columns"
+    Wr = rng.standard_normal((n, min(nm, 512)))
+    t0 = clock()
+    Wr.T @ (A @ Wr)
+    ts["W"] += (clock() - t0) * (nm / Wr.shape[1]) ** 2       # E_W = W^T A W
+    r = rng.standard_normal(n)
+    t0 = clock()
+    Wr @ (Wr.T @ r)
+    t_w = (clock() - t0) * nm / Wr.shape[1]
+    ts["pcg"] = iters * (h2_cost(1) + t_w)
+    total = sum(ts.values())
     return {
-        "value": est * 1e3, "unit": "ms", "cores": threads, "kind": "oracle",
-        "sample": (f"oracle maps on all {N} subdomains + local splitting and GenEO eigensolves on "
-                   f"{k} of {N} subdomains scaled by {N}/{k}; coarse/W/PCG phases excluded "
-                   f"(lower bound); measured {t_maps + t_split + t_geneo:.1f} s"),
+        "value": round(total * 1e3, 1), "unit": "ms", "cores": threads, "kind": "oracle",
+        "sample": (f"extrapolated from a bounded sample, not a full run: maps, B^s splitting and GenEO on "
+                   f"{k} of {N} subdomains (x{N}/{k}); E0 columns of those subdomains (x n0/{off}, n0 = {n0}) "
+                   f"+ the deleting Cholesky of an {n0}^2 Gram matrix; W ({nm} columns est.): {w_how}; "
+                   f"E_W by its GEMMs on 512 columns; PCG: {iters} iterations ({src}) x one application "
+                   f"with the local parts sampled"),
+        "phases_s": {k_: round(v, 2) for k_, v in ts.items()},
     }
 
 
@@ -161,17 +279,22 @@ def roofline(kt: dict, steps: int, workload: str) -> dict:
     avg_us = rec["ms"] * 1e3 / rec["calls"]
     if name.startswith(MFMA_KERNELS):
         achieved = rec["flops"] / (rec["ms"] * 1e-3) / 1e12
-        # the device's sustained FP64 matrix-core rate (register-only MFMA
-        # chains, no memory traffic), measured in this run beside the
-        # published peak
-        from paper_2106_10913_amd import awg
-        sustained = awg.probe_mfma_f64()
-        return {"kernel": name, "bound": "mfma", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
-                "sustained_mfma_peak": round(sustained, 2), "frac_of_sustained": round(achieved / sustained, 4),
-                "traffic": measured_traffic(name, workload),
-                "calls_per_step": rec["calls"] / steps, "avg_launch_us": round(avg_us, 2),
-                "flops_per_launch": rec["flops"] / rec["calls"]}
+        f32 = "_mix" in name or "_f32" in name
+        peak = FP32_PEAK_TFLOPS if f32 else FP64_PEAK_TFLOPS
+        out = {"kernel": name, "bound": "mfma", "achieved": round(achieved, 3), "peak": peak,
+               "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "dtype": "f32" if f32 else "f64",
+               "traffic": measured_traffic(name, workload),
+               "calls_per_step": rec["calls"] / steps, "avg_launch_us": round(avg_us, 2),
+               "flops_per_launch": rec["flops"] / rec["calls"]}
+        if not f32:
+            # the device's sustained FP64 matrix-core rate (register-only MFMA
+            # chains, no memory traffic), measured in this run beside the
+            # published peak
+            from paper_2106_10913_amd import awg
+            sustained = awg.probe_mfma_f64()
+            out["sustained_mfma_peak"] = round(sustained, 2)
+            out["frac_of_sustained"] = round(achieved / sustained, 4)
+        return out
     achieved = rec["bytes"] / (rec["ms"] * 1e-3) / 1e9
     return {"kernel": name, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(name, workload),
@@ -221,6 +344,13 @@ def copy_probe(torch, mib: int) -> None:
     print(json.dumps({"copy_probe_bytes_read": n * 8, "copy_probe_bytes_written": n * 8, "launches": 3}))
 
 
+def form_result(infos, tol):
+    """Accuracy of the timed steps of one form: every step must have converged
+    with a true residual <= tol."""
+    ok = all(i["converged"] == 1 and i["rel_res_true"] <= tol for i in infos)
+    return ok, max(i["rel_res_true"] for i in infos)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -232,11 +362,14 @@ def main():
     if args.copy_probe:
         copy_probe(torch, args.copy_probe)
         return
-    import awg_problems as P
     from paper_2106_10913_amd import awg
+    from paper_2106_10913_amd import learned
 
     dev = torch.device("cuda:0")
+    t_gen = time.perf_counter()
     w = make_workload(args.workload)
+    print(f"# workload {args.workload}: n={w.A.shape[0]} nnz={w.A.nnz} N={len(w.subs)} "
+          f"(generated in {time.perf_counter() - t_gen:.1f} s)", file=sys.stderr, flush=True)
     A = w.A
     sizes = np.array([len(s) for s in w.subs], dtype=np.int64)
     ptr = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
@@ -248,110 +381,108 @@ def main():
     bd = torch.as_tensor(w.b, device=dev)
     x = torch.empty_like(bd)
     coords = torch.as_tensor(w.coords, device=dev)
-    from paper_2106_10913_amd import learned
     wfile = WORKLOADS[args.workload][2]
     net = learned.load(os.path.join(ROOT, "paper_2106_10913_amd", "weights", wfile)) if wfile else None
 
-    def step(local_prec=args.local_prec, geneo=args.geneo, init=None):
+    def step(local_prec, geneo, init):
         solver = awg.Solver(Ad, Sd, tau=w.tau, local_prec=local_prec, geneo=geneo, eig_init=init,
-                            coords=coords if init is not None else None, coarse2=args.coarse2, w_rtol=args.w_rtol, h2=args.h2)
+                            coords=coords if init is not None else None, coarse2=args.coarse2,
+                            w_rtol=args.w_rtol, h2=args.h2)
         _, info = solver.pcg(bd, tol=w.tol, maxit=1000, x=x)
         st = solver.stats()
         solver.close()
         return info, st
 
-    # warm-up steps with every kernel instrumented: per-kernel breakdown and
-    # the dominant kernel (largest total time)
-    awg.kernel_timing_filter("")
-    awg.kernel_times(reset=True)
-    awg.kernel_timing(True)
-    for i in range(max(1, args.warmup)):
-        info, st = step()
-        print(f"# warmup {i}: iters={info['iters']} setup_ms={st['ms']['total']:.1f}", file=sys.stderr,
-              flush=True)
-    torch.cuda.synchronize()
-    awg.kernel_timing(False)
-    kt_warm = awg.kernel_times(reset=True)
-    nwarm = max(1, args.warmup)
-    dominant = max((k for k in kt_warm if not k.startswith("graph:")), key=lambda k: kt_warm[k]["ms"])
-    # timed steps: HIP events only around the dominant kernel's launches (per-launch
-    # events cost microseconds of host time each)
-    awg.kernel_timing_filter(dominant)
-    awg.kernel_timing(True)
-    t0 = time.perf_counter()
-    infos, stats = [], []
-    for i in range(args.steps):
-        info, st = step()
-        infos.append(info)
-        stats.append(st)
-        print(f"# step {i}: iters={info['iters']} true_res={info['rel_res_true']:.2e}", file=sys.stderr,
-              flush=True)
-    torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) * 1e3 / args.steps
-    awg.kernel_timing(False)
-    awg.kernel_timing_filter("")
-    kt = {k: v for k, v in awg.kernel_times(reset=True).items() if k == dominant}
+    def run_form(label, local_prec, geneo, init, time_dominant):
+        """Warm-up steps with every kernel instrumented (per-kernel breakdown,
+        dominant kernel), then the timed steps; with time_dominant the HIP
+        events stay on around the dominant kernel only (per-launch events
+        cost microseconds of host time each)."""
+        awg.kernel_timing_filter("")
+        awg.kernel_times(reset=True)
+        awg.kernel_timing(True)
+        for i in range(max(1, args.warmup)):
+            info, st = step(local_prec, geneo, init)
+            print(f"# {label} warmup {i}: iters={info['iters']} true_res={info['rel_res_true']:.2e} "
+                  f"setup_ms={st['ms']['total']:.1f}", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        awg.kernel_timing(False)
+        kt_warm = awg.kernel_times(reset=True)
+        dominant = max((k for k in kt_warm if not k.startswith("graph:")), key=lambda k: kt_warm[k]["ms"])
+        if time_dominant:
+            awg.kernel_timing_filter(dominant)
+            awg.kernel_timing(True)
+        infos, stats = [], []
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            info, st = step(local_prec, geneo, init)
+            infos.append(info)
+            stats.append(st)
+            print(f"# {label} step {i}: iters={info['iters']} converged={info['converged']} "
+                  f"true_res={info['rel_res_true']:.2e}", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        awg.kernel_timing(False)
+        awg.kernel_timing_filter("")
+        kt = {k: v for k, v in awg.kernel_times(reset=True).items() if k == dominant}
+        ok, worst = form_result(infos, w.tol)
+        st, info = stats[-1], infos[-1]
+        rec = {"ms_per_step": round(ms, 3), "accuracy_ok": ok, "worst_true_res": worst,
+               "local_prec": local_prec, "geneo": geneo, "iters": info["iters"],
+               "restarts": info.get("restarts", 0),
+               "kappa_est": info["lmax_est"] / info["lmin_est"], "n_minus": st["n_minus"], "n0": st["n0"],
+               "w_iters": st["w_iters"], "eig_fallbacks": st["eig_fallbacks"], "eig_learned": st["eig_learned"],
+               "eig_iters_max": max(st["eig_iters"], default=0),
+               "phases_ms": {k: round(v, 3) for k, v in st["ms"].items()},
+               "kernels_ms_per_warmup_step": {k: round(v["ms"] / max(1, args.warmup), 3) for k, v in
+                                              sorted(kt_warm.items(), key=lambda kv: -kv[1]["ms"])[:16]},
+               "kernel_rates_warmup": kernel_rates(kt_warm, top=16)}
+        return rec, kt, dominant
 
-    st = stats[-1]
-    info = infos[-1]
-    phases = {k: round(v, 3) for k, v in st["ms"].items()}
+    fast_only = args.local_prec == "f32"
+    plain = None
+    if not fast_only:
+        plain, _, _ = run_form("plain", "f64", args.geneo, None, time_dominant=False)
+    fast = None
+    if not args.no_fast_form:
+        # FP32 local operators, the subspace GenEO solver and the learned start
+        # (the two-pencil coarse space of as_hyb has the dense GenEO solver only)
+        fgeneo, fnet = ("dense", None) if args.h2 == "as_hyb" else ("subspace", net)
+        fast, kt, dominant = run_form("fast", "f32", fgeneo, fnet, time_dominant=True)
+        fast["network"] = wfile if fnet is not None else None
+        head, head_label = fast, "fast"
+    else:
+        plain, kt, dominant = run_form("plain", "f64", args.geneo, None, time_dominant=True)
+        head, head_label = plain, "plain"
     out = {
         "metric": "AWG-PCG time to 1e-8 rel. residual (setup+solve), FP32/learned vs plain FP64",
-        "value": round(ms, 3),
+        "value": head["ms_per_step"],
         "unit": "ms",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms, 3),
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.local_prec == "f64" else "f64+f32local",
+        "dtype": "f64+f32local" if head_label == "fast" else "f64",
         "data": "synthetic",
-        "config": {"workload": WORKLOADS[args.workload][1],
+        "config": {"workload": WORKLOADS[args.workload][1], "form": head_label,
                    "n": int(A.shape[0]), "nnz": int(A.nnz), "N": len(w.subs), "tol": w.tol,
-                   "local_prec": args.local_prec, "coarse2": args.coarse2, "h2": args.h2,
-                   "w_rtol": args.w_rtol},
-        "solve": {"iters": info["iters"], "rel_res_true": info["rel_res_true"],
-                  "kappa_est": info["lmax_est"] / info["lmin_est"], "n_minus": st["n_minus"], "n0": st["n0"],
-                  "w_iters": st["w_iters"]},
-        "phases_ms": phases,
+                   "coarse2": args.coarse2, "h2": args.h2, "w_rtol": args.w_rtol},
+        "accuracy_ok": head["accuracy_ok"] and (plain is None or plain["accuracy_ok"]),
     }
-    if not args.no_fast_form and args.local_prec == "f64":
-        # the same workload with FP32 local operators (eigen-setup, coarse
-        # spaces, PCG and W recurrences stay FP64), the subspace GenEO solver
-        # and the learned start (network trained on other seeds of this family)
-        # (the two-pencil coarse space of as_hyb has the dense GenEO solver only)
-        fgeneo, fnet = ("dense", None) if args.h2 == "as_hyb" else ("subspace", net)
-        awg.kernel_times(reset=True)
-        awg.kernel_timing(True)
-        step("f32", fgeneo, fnet)
-        torch.cuda.synchronize()
-        awg.kernel_timing(False)
-        kt32 = awg.kernel_times(reset=True)
-        t1 = time.perf_counter()
-        for i in range(args.steps):
-            info32, st32 = step("f32", fgeneo, fnet)
-        torch.cuda.synchronize()
-        ms32 = (time.perf_counter() - t1) * 1e3 / args.steps
-        out["fast_form"] = {"local_prec": "f32", "geneo": fgeneo, "eig_learned": st32["eig_learned"],
-                            "network": wfile if fnet is not None else None,
-                            "eig_iters_max": max(st32["eig_iters"], default=0),
-                            "eig_fallbacks": st32["eig_fallbacks"], "ms_per_step": round(ms32, 3),
-                            "iters": info32["iters"],
-                            "rel_res_true": info32["rel_res_true"], "n_minus": st32["n_minus"], "n0": st32["n0"],
-                            "w_iters": st32["w_iters"], "speedup_vs_f64": round(ms / ms32, 3),
-                            "phases_ms": {k: round(v, 3) for k, v in st32["ms"].items()},
-                            "kernels_ms_per_warmup_step": {k: round(v["ms"], 3) for k, v in
-                                                           sorted(kt32.items(), key=lambda kv: -kv[1]["ms"])[:12]},
-                            "kernel_rates_warmup": kernel_rates(kt32, top=12)}
+    if plain is not None and head is not plain:
+        out["plain_f64"] = plain
+        out["speedup_vs_f64"] = (round(plain["ms_per_step"] / head["ms_per_step"], 3)
+                                 if out["accuracy_ok"] else None)
+    out[head_label + "_form"] = head
     out["roofline"] = roofline(kt, args.steps, out["config"]["workload"])
     out["autotune"] = {k: v["variant"] for k, v in awg.tune_report().items()}
-    out["kernels_ms_per_warmup_step"] = {k: round(v["ms"] / nwarm, 3) for k, v in
-                                         sorted(kt_warm.items(), key=lambda kv: -kv[1]["ms"])[:20]}
-    out["kernel_rates_warmup"] = kernel_rates(kt_warm)
-    if not args.no_cpu_baseline and args.workload == "q1_2d_256":
-        out["cpu_baseline"] = cpu_baseline(w)
+    if not args.no_cpu_baseline:
+        t0 = time.perf_counter()
+        out["cpu_baseline"] = cpu_baseline(w, args.workload)
+        print(f"# cpu baseline sample took {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
     print(json.dumps(out))
 
 

@@ -91,12 +91,14 @@ def partition_of_unity(n: int, subs):
     return [d[idx] for idx in subs]
 
 
-def coloring_constant(subs, M_pattern: sp.csr_matrix) -> int:
-    """A valid coloring constant N(M) (Definition of the coloring constant, Section 2.2).
+def conflict_coloring(subs, M_pattern: sp.csr_matrix) -> np.ndarray:
+    """Colors of the subdomains for the coloring constant N(M) (Definition of
+    the coloring constant, Section 2.2).
 
     s and t conflict when R^s M R^tT != 0, i.e. when M has a nonzero (i, j)
     with i in Omega^s and j in Omega^t.  Greedy coloring of that conflict
-    graph; any valid coloring gives a valid bound.
+    graph in subdomain order: each subdomain takes the smallest color that
+    none of its conflicting predecessors holds.
     """
     N = len(subs)
     n = M_pattern.shape[0]
@@ -112,7 +114,13 @@ def coloring_constant(subs, M_pattern: sp.csr_matrix) -> int:
         while c in used:
             c += 1
         color[s] = c
-    return int(color.max() + 1)
+    return color
+
+
+def coloring_constant(subs, M_pattern: sp.csr_matrix) -> int:
+    """A valid coloring constant N(M): the number of colors of
+    conflict_coloring (any valid coloring gives a valid bound)."""
+    return int(conflict_coloring(subs, M_pattern).max() + 1)
 
 
 # ---------------------------------------------------------------------------
@@ -204,7 +212,7 @@ def split_local(Bs: np.ndarray, eps0: float = 1e-12) -> LocalSplit:
 # ---------------------------------------------------------------------------
 # the whole setup
 # ---------------------------------------------------------------------------
-def gram_keep(E: np.ndarray, tol: float = 1e-10) -> np.ndarray:
+def gram_keep(E: np.ndarray, tol: float = 1e-10, return_pivots: bool = False):
     """Columns of a (possibly dependent) basis kept for a Gram matrix E.
 
     Reading of the basis assumption of Section 2 (a basis of V0 is assumed,
@@ -214,18 +222,41 @@ def gram_keep(E: np.ndarray, tol: float = 1e-10) -> np.ndarray:
     inner product of E, of the part of basis vector k outside the span of the
     kept earlier ones) is <= tol * E_kk.  The projection onto the span is then
     X_keep E_keep^{-1} X_keep^T.
+
+    With return_pivots, also the relative pivots d_k / E_kk (0 where E_kk is
+    not positive), which say how far each decision lies from the threshold.
     """
     n = E.shape[0]
     L = np.zeros((n, n))
     keep = []
+    piv = np.zeros(n)
     for k in range(n):
         d = E[k, k] - L[k, keep] @ L[k, keep]
+        piv[k] = d / E[k, k] if E[k, k] > 0 else 0.0
         if not d > tol * E[k, k]:
             continue
         L[k, k] = np.sqrt(d)
         L[k + 1:, k] = (E[k + 1:, k] - L[k + 1:, keep] @ L[k, keep]) / L[k, k]
         keep.append(k)
-    return np.array(keep, dtype=np.int64)
+    keep = np.array(keep, dtype=np.int64)
+    return (keep, piv) if return_pivots else keep
+
+
+def deletion_margin(piv: np.ndarray, keep: np.ndarray, tol: float = 1e-10) -> float:
+    """Factor by which the threshold of gram_keep would have to move before one
+    keep / delete decision changes: min over kept columns of piv / tol and
+    over deleted ones of tol / piv (inf for a non-positive deleted pivot, and
+    inf when there is no column).  Below 100 the decision is left to rounding."""
+    m = np.inf
+    kept = np.zeros(piv.size, dtype=bool)
+    kept[keep] = True
+    if kept.any():
+        m = min(m, float(np.min(piv[kept])) / tol)
+    dp = piv[~kept]
+    dp = dp[dp > 0]
+    if dp.size:
+        m = min(m, tol / float(np.max(dp)))
+    return m
 
 
 @dataclasses.dataclass
@@ -249,6 +280,8 @@ class AWGSetup:
     w_info: dict
     E0_keep: np.ndarray = None    # kept coarse vectors (gram_keep); all unless dependent
     EW_keep: np.ndarray = None
+    E0_piv: np.ndarray = None     # relative pivots of the deletion (gram_keep)
+    EW_piv: np.ndarray = None
     Lg: np.ndarray = None         # |strictly negative eigenvalues|, the columns of V_- (Vg)
     C: np.ndarray = None          # capacitance L_-^{-1} - V_-^T W (H3,inex)
     C_keep: np.ndarray = None
@@ -501,9 +534,20 @@ def local_MB(A: sp.csr_matrix, subs, split, s: int) -> np.ndarray:
     return MB
 
 
+W_DIRECT_MAX_N = 100_000     # largest n for which w_solver="auto" factorises A
+
+
 def setup(A: sp.csr_matrix, subs, tau: float, eps0: float = 1e-12, w_solver: str = "auto",
-          w_rtol: float = 1e-13, w_maxit: int = 500, check: bool = True) -> AWGSetup:
-    """Build every ingredient of H3,ad with H2 = H^NN_hyb(tau)."""
+          w_rtol: float = 1e-13, w_maxit: int = 500, check: bool = True, stop_after: str = None,
+          timings: dict = None) -> AWGSetup:
+    """Build every ingredient of H3,ad with H2 = H^NN_hyb(tau).
+
+    stop_after="coarse0" returns after E0 and its deletion (no second coarse
+    space: W, E_W and C stay empty), for workloads whose W does not fit in
+    memory.  timings, when given, receives the wall time of each phase (s)."""
+    import time
+    tm = timings if timings is not None else {}
+    t0 = time.perf_counter()
     A = sp.csr_matrix(A, dtype=np.float64)
     A.sort_indices()
     n = A.shape[0]
@@ -515,7 +559,11 @@ def setup(A: sp.csr_matrix, subs, tau: float, eps0: float = 1e-12, w_solver: str
     Ds = partition_of_unity(n, subs)
     cnt = pair_multiplicity(A, subs)
     B = algebraic_B(A, cnt)
+    tm["maps"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
     split = [split_local(local_block(B, idx), eps0) for idx in subs]
+    tm["split"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
 
     # GenEO coarse space (Theorem for H^NN_hyb, Section 3.4)
     Ys, glam, MBs = [], [], []
@@ -535,20 +583,30 @@ def setup(A: sp.csr_matrix, subs, tau: float, eps0: float = 1e-12, w_solver: str
         off += m
     R0T = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
                         shape=(n, off))
+    tm["geneo"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
 
     st = AWGSetup(A=A, subs=subs, tau=tau, Ds=Ds, cnt=cnt, B=B, split=split, Y=Ys,
                   geneo_lam=glam, R0T=R0T, E0=None, E0_cho=None, W=np.zeros((n, 0)),
                   EW=np.zeros((0, 0)), EW_cho=None, Vg=np.zeros((n, 0)), w_info={}, MB=MBs)
-    # E0 = R0 A_+ R0^T and its Cholesky factor
-    AR0T = st.A_plus_mv(R0T.toarray())
-    E0 = np.asarray(R0T.T @ AR0T)
+    # E0 = R0 A_+ R0^T (by column blocks of R0^T, which bounds the memory of
+    # the dense products) and its Cholesky factor
+    E0 = np.empty((off, off))
+    R0 = R0T.T.tocsr()
+    for c0 in range(0, off, 512):
+        E0[:, c0:c0 + 512] = R0 @ st.A_plus_mv(R0T[:, c0:c0 + 512].toarray())
     st.E0 = 0.5 * (E0 + E0.T)
-    st.E0_keep = gram_keep(st.E0)
+    st.E0_keep, st.E0_piv = gram_keep(st.E0, return_pivots=True)
     st.EW_keep = np.zeros(0, dtype=np.int64)
+    st.EW_piv = np.zeros(0)
     try:
         st.E0_cho = sla.cho_factor(st.E0[np.ix_(st.E0_keep, st.E0_keep)], lower=True)
     except np.linalg.LinAlgError as e:
         raise OracleError("E0 is not positive semi-definite") from e
+    tm["coarse0"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    if stop_after == "coarse0":
+        return st
 
     # second coarse space W = A_+^{-1} [R^1T V^1_- | ... ] with strictly
     # negative eigenvalues only (Remark 1, Section 4.4)
@@ -563,7 +621,10 @@ def setup(A: sp.csr_matrix, subs, tau: float, eps0: float = 1e-12, w_solver: str
     st.Vg = Vg
     if Vg.shape[1]:
         if w_solver == "auto":
-            w_solver = "direct"
+            # a sparse LU of A is cheap for the 2D workloads; for the 3D ones its
+            # fill makes it impractical, and the oracle takes the paper's own
+            # route (Remark 2, Section 4.4): PCG with H2 on every column
+            w_solver = "direct" if n <= W_DIRECT_MAX_N else "pcg"
         if w_solver == "direct":
             st.W = solve_A_plus_direct(st, Vg)
             st.w_info = dict(solver="direct")
@@ -571,7 +632,7 @@ def setup(A: sp.csr_matrix, subs, tau: float, eps0: float = 1e-12, w_solver: str
             st.W, st.w_info = solve_A_plus_pcg(st, Vg, w_rtol, w_maxit)
         EW = st.W.T @ (A @ st.W)
         st.EW = 0.5 * (EW + EW.T)
-        st.EW_keep = gram_keep(st.EW)
+        st.EW_keep, st.EW_piv = gram_keep(st.EW, return_pivots=True)
         try:
             st.EW_cho = sla.cho_factor(st.EW[np.ix_(st.EW_keep, st.EW_keep)], lower=True)
         except np.linalg.LinAlgError as e:
@@ -588,6 +649,7 @@ def setup(A: sp.csr_matrix, subs, tau: float, eps0: float = 1e-12, w_solver: str
             st.C_cho = sla.cho_factor(st.C[np.ix_(st.C_keep, st.C_keep)], lower=True)
         except np.linalg.LinAlgError as e:
             raise OracleError("the capacitance matrix is not positive semi-definite") from e
+    tm["W"] = time.perf_counter() - t0
     return st
 
 
@@ -809,4 +871,7 @@ def stats(st: AWGSetup) -> dict:
         n_minus=st.n_minus, n0=st.n0,
         k_s=[sp_.nneg for sp_ in st.split], kstrict_s=[sp_.nstrict for sp_ in st.split],
         m_s=[Y.shape[1] for Y in st.Y],
+        n0_rank=st.n0_rank, n_minus_rank=st.n_minus_rank,
+        e0_margin=deletion_margin(st.E0_piv, st.E0_keep),
+        ew_margin=deletion_margin(st.EW_piv, st.EW_keep),
     )

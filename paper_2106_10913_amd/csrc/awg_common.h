@@ -30,6 +30,18 @@ struct Error : std::runtime_error {
 
 inline unsigned cdiv(long a, long b) { return (unsigned)((a + b - 1) / b); }
 
+// Sum over the 256 threads of a block in a fixed order (a butterfly within
+// each wavefront, whose pairwise sums are the same on every lane, then the
+// four wavefront sums as (w0 + w1) + (w2 + w3)); every thread returns it.
+// Every thread of the block must call it.
+__device__ inline double block_sum_256(double v, double* sh4) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  if ((threadIdx.x & 63) == 0) sh4[threadIdx.x >> 6] = v;
+  __syncthreads();
+  return (sh4[0] + sh4[1]) + (sh4[2] + sh4[3]);
+}
+
 // ---------------------------------------------------------------------------
 // device buffers
 // ---------------------------------------------------------------------------
@@ -174,10 +186,14 @@ void gemv_batched(const GemmDesc* d_desc, int batch, int max_m, int max_k, bool 
 // Cholesky A = L L^T (lower, in place) of every block; info[b] = 0 or the
 // 1-based column of the first non-positive pivot.  With dropped != NULL (a
 // single block only): columns whose pivot is <= tol * diag0[c] are deleted
-// (dropped[c] = 1, unit diagonal, zero column below), see k_potf2.
+// (dropped[c] = 1, unit diagonal, zero column below), see k_potf2; pivrel,
+// when given, receives every column's pivot / diag0[c] (the distance of the
+// decision from tol).
 void potrf_batched(const MatDesc* d_mats, const std::vector<int>& h_n, int* d_info, hipStream_t s,
                    GemmDesc* d_scratch_desc, const double* diag0 = nullptr, int* dropped = nullptr,
-                   double tol = 0.0);
+                   double tol = 0.0, double* pivrel = nullptr);
+// potrf_batched for batch blocks of one order n (no host size list)
+void potrf_uniform(const MatDesc* d_mats, int batch, int n, int* d_info, hipStream_t s);
 // Solve L X = B (trans = false) or L^T X = B (trans = true) with the lower
 // factor L of block b (n_b x n_b) and B_b (n_b x ncols_b); X overwrites B.
 void trsm_batched(const MatDesc* d_L, const MatDesc* d_B, const std::vector<int>& h_n,

@@ -215,6 +215,9 @@ struct awg_ctx {
   int eig_learned = 0;          // start block came from the network
   int n0_dropped = 0;           // dependent coarse vectors deleted from E0 (rank = n0 - n0_dropped)
   int nminus_dropped = 0;       // dependent W columns deleted from W^T A W
+  // distance of the deletion decisions from the threshold (spd_inverse):
+  // factor by which the threshold would have to move to change one of them
+  double e0_margin = INFINITY, ew_margin = INFINITY;
   DBuf<double> ritzZ, ritzMu;   // last Ritz block (sum n_s x q) and values mu = 1/lambda
   int ritz_q = 0;
   DBuf<double> coords;          // optional node coordinates (n x cdim)
@@ -272,7 +275,18 @@ __global__ void k_build_vg(const long* sub_ptr, const int* sub_idx, const double
 // (1 converged, 2 breakdown, 3 maxit), [10] iterations, [11] maxit;
 // alpha_k at sc[16 + 2k], beta_k at sc[17 + 2k].  Once done is set, alpha and
 // beta are 0, so further launches leave x, r and p unchanged.
-__global__ void k_pcg_alpha(double* sc) {
+// The three scalar kernels run on one block of 256 threads: they first add
+// the DOT1_BLOCKS partial sums of their dot product (fixed order) into sc[slot].
+__device__ inline void sum_partials(const double* part, double* sc, int slot) {
+  __shared__ double sh4[4];
+  double acc = 0.0;
+  for (int k = threadIdx.x; k < DOT1_BLOCKS; k += 256) acc += part[k];
+  const double t = block_sum_256(acc, sh4);
+  if (threadIdx.x == 0) sc[slot] = t;
+}
+
+__global__ __launch_bounds__(256) void k_pcg_alpha(double* sc, const double* part) {
+  sum_partials(part, sc, 1);                  // pq
   if (threadIdx.x != 0) return;
   if (sc[9] != 0.0) { sc[2] = 0.0; return; }
   if (!(sc[1] > 0.0)) { sc[9] = 2.0; sc[2] = 0.0; return; }
@@ -281,7 +295,8 @@ __global__ void k_pcg_alpha(double* sc) {
   sc[16 + 2 * (long)sc[10]] = a;
 }
 
-__global__ void k_pcg_check(double* sc) {
+__global__ __launch_bounds__(256) void k_pcg_check(double* sc, const double* part) {
+  sum_partials(part, sc, 5);                  // rr
   if (threadIdx.x != 0) return;
   if (sc[9] != 0.0) return;
   sc[10] += 1.0;
@@ -289,7 +304,8 @@ __global__ void k_pcg_check(double* sc) {
   else if (sc[10] >= sc[11]) sc[9] = 3.0;
 }
 
-__global__ void k_pcg_beta(double* sc) {
+__global__ __launch_bounds__(256) void k_pcg_beta(double* sc, const double* part) {
+  sum_partials(part, sc, 3);                  // rz_new
   if (threadIdx.x != 0) return;
   if (sc[9] != 0.0) { sc[4] = 0.0; return; }
   const double bta = sc[3] / sc[0];
@@ -298,28 +314,21 @@ __global__ void k_pcg_beta(double* sc) {
   sc[17 + 2 * ((long)sc[10] - 1)] = bta;
 }
 
-__global__ void k_pcg_scalars(double* sc, int it, int mode) {
-  // sc layout: [0] rz, [1] pq, [2] alpha, [3] rz_new, [4] beta, [5] rr
-  // alpha/beta histories at sc[16 + 2*it], sc[17 + 2*it]
-  if (threadIdx.x != 0) return;
-  if (mode == 0) {
-    const double a = sc[0] / sc[1];
-    sc[2] = a;
-    sc[16 + 2 * it] = a;
-  } else {
-    const double bta = sc[3] / sc[0];
-    sc[4] = bta;
-    sc[0] = sc[3];
-    sc[17 + 2 * it] = bta;
-  }
-}
-
-__global__ void k_pcg_update_xr(int n, double* x, double* r, const double* p, const double* q, const double* sc) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+// x += alpha p, r -= alpha q, and part[blockIdx.x] = this block's share of
+// r^T r (grid-stride over DOT1_BLOCKS blocks, fixed order)
+__global__ __launch_bounds__(256) void k_pcg_update_xr(int n, double* x, double* r, const double* p, const double* q,
+                                                       const double* sc, double* part) {
+  __shared__ double sh4[4];
   const double a = sc[2];
-  x[i] += a * p[i];
-  r[i] -= a * q[i];
+  double acc = 0.0;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+    x[i] += a * p[i];
+    const double ri = r[i] - a * q[i];
+    r[i] = ri;
+    acc += ri * ri;
+  }
+  const double t = block_sum_256(acc, sh4);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
 
 __global__ void k_pcg_update_p(int n, double* p, const double* z, const double* sc) {
@@ -414,7 +423,7 @@ void build_ws(awg_ctx& c, MultiWS& w, int b) {
   w.G2.alloc(std::max(1, c.n0) * (long)b);
   w.H0.alloc(std::max(1, c.nminus) * (long)b);
   w.H1.alloc(std::max(1, c.nminus) * (long)b);
-  w.dotpart.alloc((long)DOT_CHUNKS_H * b);
+  w.dotpart.alloc(std::max<long>(2L * DOT_CHUNKS_H * b, DOT1_BLOCKS));
   w.dots.alloc(2L * b);
   if (b == 1) w.gvpart.alloc((long)GEMV_KSPLIT * std::max(1, c.nminus));
   std::vector<GemmDesc> vt(c.N), vv(c.N), yt(c.N), yy(c.N), pp(c.N);
@@ -1349,23 +1358,24 @@ __global__ void k_zero_dropped_rc(double* M, int n, const int* dropped) {
 // of the kept principal submatrix, zero rows and columns for the deleted
 // ones.  Applied as X E^+ X^T this is the projection onto the span.  Returns
 // the number of deleted columns.
-int spd_inverse(awg_ctx& c, double* M, int n, DBuf<double>& Minv, const char* what) {
+int spd_inverse(awg_ctx& c, double* M, int n, DBuf<double>& Minv, const char* what, double* margin = nullptr) {
   hipStream_t s = c.s;
   Minv.alloc((long)n * n);
   DBuf<MatDesc> dm, di;
   dm.upload({MatDesc{M, n, n, n, 0}}, s);
   di.upload({MatDesc{Minv.p, n, n, n, 0}}, s);
   l_scale_sym(dm, 1, nullptr, nullptr, false, true, s);
-  DBuf<double> d0;
+  DBuf<double> d0, pv;
   DBuf<int> info, drop;
   d0.alloc(n);
+  pv.alloc(n);
   drop.alloc(n);
   drop.zero(s);
   hipLaunchKernelGGL(k_get_diag, dim3(cdiv(n, 256)), dim3(256), 0, s, M, n, d0.p);
   AWG_LAUNCH_CHECK();
   info.alloc(1);
   info.zero(s);
-  potrf_batched(dm, {n}, info, s, nullptr, d0, drop, GRAM_DROP_TOL);
+  potrf_batched(dm, {n}, info, s, nullptr, d0, drop, GRAM_DROP_TOL, pv.p);
   check_info(c, info, what);
   const unsigned g = cdiv((long)n * n, 256);
   hipLaunchKernelGGL(k_zero_dropped_rows, dim3(g), dim3(256), 0, s, M, n, drop.p);
@@ -1377,13 +1387,27 @@ int spd_inverse(awg_ctx& c, double* M, int n, DBuf<double>& Minv, const char* wh
   hipLaunchKernelGGL(k_zero_dropped_rc, dim3(g), dim3(256), 0, s, Minv.p, n, drop.p);
   AWG_LAUNCH_CHECK();
   int nd = 0;
-  for (int v : drop.download(s)) nd += v;
+  const std::vector<int> hd = drop.download(s);
+  const std::vector<double> hp = pv.download(s);
+  double m = INFINITY;
+  for (int k = 0; k < n; ++k) {
+    nd += hd[k];
+    if (!hd[k]) m = std::min(m, hp[k] / GRAM_DROP_TOL);
+    else if (hp[k] > 0.0) m = std::min(m, GRAM_DROP_TOL / hp[k]);
+  }
+  if (margin) *margin = m;
   return nd;
 }
 
+// Jacobi scale of a Gram matrix; a vanishing (or, by rounding, negative)
+// diagonal entry keeps scale 1, so its zero row and column stay zero and the
+// direction is deflated or deleted instead of producing Inf / NaN
 __global__ void k_sqrt_diag(const double* M, int n, double* d) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) d[i] = sqrt(M[i + (long)i * n]);
+  if (i < n) {
+    const double v = M[i + (long)i * n];
+    d[i] = v > 0.0 ? sqrt(v) : 1.0;
+  }
 }
 
 // Pseudo-inverse of a Gram matrix E (n x n, destroyed) of a basis whose
@@ -1394,7 +1418,7 @@ __global__ void k_sqrt_diag(const double* M, int n, double* d) {
 // inverse on the complement of the near-null combinations, zero on them;
 // the inverse itself by spd_inverse).  Returns the number of deflated and
 // deleted directions.
-int deflated_inverse(awg_ctx& c, double* E, int n, DBuf<double>& Einv, const char* what) {
+int deflated_inverse(awg_ctx& c, double* E, int n, DBuf<double>& Einv, const char* what, double* margin = nullptr) {
   hipStream_t s = c.s;
   constexpr int KMAX = 64;
   DBuf<double> sc, Et, lam, Z;
@@ -1412,15 +1436,17 @@ int deflated_inverse(awg_ctx& c, double* E, int n, DBuf<double>& Einv, const cha
   Z.alloc((long)n * KMAX);
   int32_t k = 0;
   const int rc = awg_dense_low_eigs(1, n, Et.p, n, 0, 1e-10, KMAX, &k, lam.p, Z.p, 0, s);
+  if (rc == AWG_ERR_ARG)
+    throw Error(AWG_ERR_NOT_SPD, std::string(what) + ": more near-null directions than the deflation keeps (64)");
   if (rc != AWG_OK)
-    throw Error(rc == AWG_ERR_ARG ? AWG_ERR_NOT_SPD : rc,
-                std::string(what) + ": more near-null directions than the deflation keeps (64)");
+    throw Error(rc, std::string(what) + ": the low-eigenpair solve of the scaled matrix failed (status " +
+                        std::to_string(rc) + ")");
   DBuf<GemmDesc> dg;
   if (k > 0) {
     dg.upload({GemmDesc{Z.p, Z.p, E, n, n, k, n, n, n}}, s);
     gemm_batched(dg, 1, n, n, false, true, 1.0, 1.0, false, s, 2.0 * n * (double)n * k);   // Es + Z Z^T
   }
-  const int nd = spd_inverse(c, E, n, Einv, what);
+  const int nd = spd_inverse(c, E, n, Einv, what, margin);
   if (k > 0) {
     dg.upload({GemmDesc{Z.p, Z.p, Einv.p, n, n, k, n, n, n}}, s);
     gemm_batched(dg, 1, n, n, false, true, -1.0, 1.0, false, s, 2.0 * n * (double)n * k);  // - Z Z^T
@@ -1465,8 +1491,9 @@ void phase_coarse0(awg_ctx& c) {
   }
   // the two-pencil basis of H^AS_hyb can be dependent across subdomains in a
   // way no pivot shows; the other coarse spaces keep the pivoted deletion
-  c.n0_dropped = c.opt.h2 == AWG_H2_AS_HYB ? deflated_inverse(c, E0, c.n0, c.E0inv, "coarse matrix E0")
-                                           : spd_inverse(c, E0, c.n0, c.E0inv, "coarse matrix E0");
+  c.n0_dropped = c.opt.h2 == AWG_H2_AS_HYB
+                     ? deflated_inverse(c, E0, c.n0, c.E0inv, "coarse matrix E0", &c.e0_margin)
+                     : spd_inverse(c, E0, c.n0, c.E0inv, "coarse matrix E0", &c.e0_margin);
 }
 
 // W = A_+^{-1} [R^1T V^1_- | ... ] (strictly negative pairs; Remark 1 and 2,
@@ -1533,9 +1560,10 @@ void phase_W(awg_ctx& c) {
         alpha[j] = active[j] ? rz[j] / h[j] : 0.0;
       }
       AWG_HIP(hipMemcpyAsync(alpha_d.p, alpha.data(), sizeof(double) * b, hipMemcpyHostToDevice, s));
-      l_colaxpby(c.n, b, Pm, alpha_d, X, nullptr, 1.0, 1.0, s);
-      l_colaxpby(c.n, b, Q, alpha_d, w.R, nullptr, -1.0, 1.0, s);
-      h = coldot(w.R, w.R);
+      // X += alpha P, R -= alpha Q and the new ||R_j||^2 in one pass
+      l_multi_update_xr(c.n, b, alpha_d, Pm, X, Q, w.R, w.dotpart, dots, s);
+      AWG_HIP(hipMemcpyAsync(h.data(), dots, sizeof(double) * b, hipMemcpyDeviceToHost, s));
+      AWG_HIP(hipStreamSynchronize(s));
       int nact = 0;
       for (int j = 0; j < b; ++j) {
         if (active[j] && std::sqrt(h[j]) <= c.opt.w_rtol * bn[j]) active[j] = 0;
@@ -1543,17 +1571,19 @@ void phase_W(awg_ctx& c) {
       }
       if (nact == 0) { ++it; break; }
       op_h2(c, w, f32);
-      h = coldot(w.R, w.Z);
-      std::vector<double> hz;
-      if (f32) hz = coldot(w.R, Zold);   // flexible (Polak-Ribiere) beta for the FP32 local operators
+      // r^T z and, for the FP32 local operators, r^T z_old (flexible
+      // Polak-Ribiere beta) in one pass over R
+      l_coldot2(c.n, b, w.R, w.Z, f32 ? Zold.p : nullptr, w.dotpart, dots, dots + b, s);
+      std::vector<double> h2((f32 ? 2 : 1) * (size_t)b);
+      AWG_HIP(hipMemcpyAsync(h2.data(), dots, sizeof(double) * h2.size(), hipMemcpyDeviceToHost, s));
+      AWG_HIP(hipStreamSynchronize(s));
       for (int j = 0; j < b; ++j) {
-        const double num = f32 ? h[j] - hz[j] : h[j];
+        const double num = f32 ? h2[j] - h2[b + j] : h2[j];
         beta[j] = active[j] ? num / rz[j] : 0.0;
-        if (active[j]) rz[j] = h[j];
+        if (active[j]) rz[j] = h2[j];
       }
-      if (f32) AWG_HIP(hipMemcpyAsync(Zold.p, w.Z.p, sizeof(double) * c.n * b, hipMemcpyDeviceToDevice, s));
       AWG_HIP(hipMemcpyAsync(alpha_d.p, beta.data(), sizeof(double) * b, hipMemcpyHostToDevice, s));
-      l_colaxpby(c.n, b, w.Z, nullptr, Pm, alpha_d, 1.0, 1.0, s);   // P = Z + beta P
+      l_multi_update_p(c.n, b, w.Z, Pm, alpha_d, f32 ? Zold.p : nullptr, s);   // P = Z + beta P (Zold = Z)
       sync(c);   // the host buffer of beta is reused next iteration
     }
     itmax = std::max(itmax, it);
@@ -1608,7 +1638,7 @@ void phase_capacitance(awg_ctx& c) {
   L.upload(hl, s);
   hipLaunchKernelGGL(k_capacitance, dim3(cdiv((long)nm * nm, 256)), dim3(256), 0, s, nm, D.p, L.p, C.p);
   AWG_LAUNCH_CHECK();
-  c.nminus_dropped = spd_inverse(c, C, nm, c.EWinv, "capacitance matrix L^-1 - V^T W");
+  c.nminus_dropped = spd_inverse(c, C, nm, c.EWinv, "capacitance matrix L^-1 - V^T W", &c.ew_margin);
 }
 
 void phase_EW(awg_ctx& c) {
@@ -1627,7 +1657,7 @@ void phase_EW(awg_ctx& c) {
   DBuf<GemmDesc> g;
   g.upload({GemmDesc{c.W.p, AW.p, EW.p, c.nminus, c.nminus, c.n, c.nminus, c.nminus, c.nminus}}, s);
   gemm_batched(g, 1, c.nminus, c.nminus, false, true, 1.0, 0.0, false, s, 2.0 * c.n * (double)c.nminus * c.nminus);
-  c.nminus_dropped = spd_inverse(c, EW, c.nminus, c.EWinv, "second coarse matrix W^T A W");
+  c.nminus_dropped = spd_inverse(c, EW, c.nminus, c.EWinv, "second coarse matrix W^T A W", &c.ew_margin);
 }
 
 void do_setup(awg_ctx& c, const int64_t* rowptr, const int32_t* col, const double* val, const int64_t* sub_ptr,
@@ -1700,15 +1730,17 @@ void pcg_iteration(awg_ctx& c, bool f32) {
   double* q = p + n;
   double* sc = c.scal.p;
   const unsigned g = cdiv(n, 256);
-  l_spmm(n, c.nnz, c.rowptr, c.col, c.val, p, q, 1, 1.0, 0.0, s);
-  l_coldot(n, 1, p, q, w.dotpart, sc + 1, s);
-  hipLaunchKernelGGL(k_pcg_alpha, dim3(1), dim3(64), 0, s, sc);
-  hipLaunchKernelGGL(k_pcg_update_xr, dim3(g), dim3(256), 0, s, n, xx, w.R.p, p, q, sc);
-  l_coldot(n, 1, w.R, w.R, w.dotpart, sc + 5, s);
-  hipLaunchKernelGGL(k_pcg_check, dim3(1), dim3(64), 0, s, sc);
+  double* part = w.dotpart.p;      // DOT1_BLOCKS partial sums, reused by the three dot products
+  l_spmv_dot(n, c.nnz, c.rowptr, c.col, c.val, p, q, part, s);                    // q = A p, parts of p^T q
+  hipLaunchKernelGGL(k_pcg_alpha, dim3(1), dim3(256), 0, s, sc, part);
+  {
+    KScope kt("k_pcg_update_xr", s, 48.0 * n, 6.0 * n);
+    hipLaunchKernelGGL(k_pcg_update_xr, dim3(DOT1_BLOCKS), dim3(256), 0, s, n, xx, w.R.p, p, q, sc, part);
+  }
+  hipLaunchKernelGGL(k_pcg_check, dim3(1), dim3(256), 0, s, sc, part);
   op_h(c, w, f32);
-  l_coldot(n, 1, w.R, w.Z, w.dotpart, sc + 3, s);
-  hipLaunchKernelGGL(k_pcg_beta, dim3(1), dim3(64), 0, s, sc);
+  l_dot1_part(n, w.R, w.Z, part, s);                                               // parts of r^T z
+  hipLaunchKernelGGL(k_pcg_beta, dim3(1), dim3(256), 0, s, sc, part);
   hipLaunchKernelGGL(k_pcg_update_p, dim3(g), dim3(256), 0, s, n, p, w.Z.p, sc);
   AWG_LAUNCH_CHECK();
 }
@@ -1801,9 +1833,10 @@ int do_pcg(awg_ctx& c, const double* b, double* x, double tol, int maxit, awg_pc
         c.err = "PCG breakdown: p^T A p <= 0 (A or H not spd)";
         break;
       }
-      // true residual q = b - A x
-      l_spmm(n, c.nnz, c.rowptr, c.col, c.val, xx, q, 1, -1.0, 0.0, s);
-      l_colaxpby(n, 1, b, nullptr, q, nullptr, 1.0, 1.0, s);
+      // true residual q = b - A x, evaluated in compensated arithmetic (the
+      // FP64 evaluation error eps sum_j |A_ij x_j| can exceed tol ||b|| on
+      // ill-conditioned systems)
+      l_resid_dd(n, c.nnz, c.rowptr, c.col, c.val, xx, b, q, s);
       l_coldot(n, 1, q, q, w.dotpart, sc + 7, s);
       double h7;
       AWG_HIP(hipMemcpyAsync(&h7, sc + 7, sizeof(double), hipMemcpyDeviceToHost, s));
@@ -1859,7 +1892,9 @@ std::string stats_json(const awg_ctx& c) {
   o << ",\"coarse2\":" << c.opt.coarse2 << ",\"h2\":" << c.opt.h2;
   o << ",\"geneo_solver\":" << c.opt.geneo_solver << ",\"eig_fallbacks\":" << c.eig_fallbacks
     << ",\"eig_learned\":" << c.eig_learned << ",\"eig_block\":" << c.opt.eig_block
-    << ",\"n0_dropped\":" << c.n0_dropped << ",\"nminus_dropped\":" << c.nminus_dropped << ",";
+    << ",\"n0_dropped\":" << c.n0_dropped << ",\"nminus_dropped\":" << c.nminus_dropped;
+  // JSON has no infinity: a margin without any decision near the threshold is written as 1e300
+  o << ",\"e0_margin\":" << std::min(c.e0_margin, 1e300) << ",\"ew_margin\":" << std::min(c.ew_margin, 1e300) << ",";
   arr("eig_iters", c.eig_iters);
   o << ",\"eig_resid_max\":[";
   for (size_t i = 0; i < c.eig_resid_max.size(); ++i) o << (i ? "," : "") << c.eig_resid_max[i];

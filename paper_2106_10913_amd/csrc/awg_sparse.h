@@ -41,11 +41,29 @@ void l_gather(long tot, const int* sub_idx, const double* X, int b, double* Xs, 
 void l_gather_f32(long tot, const int* sub_idx, const double* X, int b, float* Xs, hipStream_t s);
 void l_scatter(int n, long tot, const int* inv_ptr, const int* inv_sub, const int* inv_loc, const long* sub_ptr,
                const double* Zs, int b, double* Y, double alpha, double beta, hipStream_t s);
-// part: DOT_CHUNKS * b scratch doubles
+// part: max(DOT_CHUNKS_H * b, DOT1_BLOCKS) scratch doubles
 constexpr int DOT_CHUNKS_H = 128;
+constexpr int DOT1_BLOCKS = 512;   // blocks (and partial sums) of the one-column kernels
 void l_coldot(int n, int b, const double* X, const double* Y, double* part, double* out, hipStream_t s);
+// one column: q = A p with part[k] = the k-th of DOT1_BLOCKS partial sums of p^T q
+void l_spmv_dot(int n, long nnz, const int* rowptr, const int* col, const double* val, const double* p, double* q,
+                double* part, hipStream_t s);
+// r = b - A x in compensated (double-double) arithmetic, rounded once to FP64
+void l_resid_dd(int n, long nnz, const int* rowptr, const int* col, const double* val, const double* x,
+                const double* b, double* r, hipStream_t s);
+// one column: part[k] = the k-th of DOT1_BLOCKS partial sums of x^T y
+void l_dot1_part(int n, const double* x, const double* y, double* part, hipStream_t s);
 void l_colaxpby(long rows, int b, const double* X, const double* a, double* Y, const double* bb, double sa, double sb,
                 hipStream_t s);
+// multi-column PCG steps in single passes (part: DOT_CHUNKS_H * b doubles, 2x for l_coldot2):
+// X += a P, R -= a Q and rr = column norms^2 of the new R
+void l_multi_update_xr(int n, int b, const double* a, const double* P, double* X, const double* Q, double* R,
+                       double* part, double* rr, hipStream_t s);
+// out1 = column dots X^T Y1, out2 = X^T Y2 (Y2 may be NULL) reading X once
+void l_coldot2(int n, int b, const double* X, const double* Y1, const double* Y2, double* part, double* out1,
+               double* out2, hipStream_t s);
+// P = Z + beta P, and Zold = Z when Zold != NULL
+void l_multi_update_p(long rows, int b, const double* Z, double* P, const double* beta, double* Zold, hipStream_t s);
 void l_set_identity(const MatDesc* mats, int batch, hipStream_t s);
 void l_copy_mat(const MatDesc* src, const MatDesc* dst, int batch, hipStream_t s);
 void l_scale_sym(const MatDesc* mats, int batch, const long* voff, const double* d, bool inv, bool symmetrize,

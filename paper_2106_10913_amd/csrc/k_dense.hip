@@ -1141,7 +1141,7 @@ constexpr int CHOL_NB = 32;
 // previous ones; it is deleted (unit pivot, zero column) and flagged, so the
 // factor of the kept columns is the Cholesky factor of their principal submatrix.
 __global__ __launch_bounds__(256) void k_potf2(const MatDesc* mats, int j, int* info, const double* diag0,
-                                               int* dropped, double tol) {
+                                               int* dropped, double tol, double* pivrel) {
   const MatDesc M = mats[blockIdx.x];
   const int jb = min(CHOL_NB, M.n - j);
   if (jb <= 0) return;
@@ -1157,6 +1157,7 @@ __global__ __launch_bounds__(256) void k_potf2(const MatDesc* mats, int j, int* 
     if (tid == 0) {
       const double piv = L[c][c];
       drop_c = 0;
+      if (pivrel) pivrel[j + c] = diag0[j + c] > 0.0 ? piv / diag0[j + c] : 0.0;
       if (dropped && piv == piv && !(piv > tol * diag0[j + c])) {
         dropped[j + c] = 1;
         drop_c = 1;
@@ -1212,14 +1213,14 @@ __global__ __launch_bounds__(256) void k_chol_panel(const MatDesc* mats, int j, 
     if (c < jb) M.A[i + (long)(j + c) * M.ld] = x[c];
 }
 
-void potrf_batched(const MatDesc* d_mats, const std::vector<int>& h_n, int* d_info, hipStream_t s,
-                   GemmDesc* /*unused*/, const double* diag0, int* dropped, double tol) {
-  const int batch = (int)h_n.size();
+// the blocked loop shared by potrf_batched and potrf_uniform: batch blocks,
+// the largest of order maxn; sizes (host, may be NULL = every block of order
+// maxn) only feed the kernel timer's flop count
+static void potrf_loop(const MatDesc* d_mats, int batch, int maxn, const int* sizes, int* d_info, hipStream_t s,
+                       const double* diag0, int* dropped, double tol, double* pivrel) {
   if (batch == 0) return;
-  int maxn = 0;
-  for (int v : h_n) maxn = v > maxn ? v : maxn;
   for (int j = 0; j < maxn; j += CHOL_NB) {
-    hipLaunchKernelGGL(k_potf2, dim3(batch), dim3(256), 0, s, d_mats, j, d_info, diag0, dropped, tol);
+    hipLaunchKernelGGL(k_potf2, dim3(batch), dim3(256), 0, s, d_mats, j, d_info, diag0, dropped, tol, pivrel);
     AWG_LAUNCH_CHECK();
     const int rem = maxn - j - CHOL_NB;
     if (rem <= 0) break;
@@ -1228,12 +1229,23 @@ void potrf_batched(const MatDesc* d_mats, const std::vector<int>& h_n, int* d_in
     AWG_LAUNCH_CHECK();
     double fl = 0.0;
     if (ktimer_on())
-      for (int v : h_n) {
-        const double r = v - j - CHOL_NB;
+      for (int b = 0; b < batch; ++b) {
+        const double r = (sizes ? sizes[b] : maxn) - j - CHOL_NB;
         if (r > 0) fl += r * r * CHOL_NB;      // lower triangle of the rank-32 update
       }
     launch_gemm(CholUpdate{d_mats, j, CHOL_NB}, batch, rem, rem, false, true, -1.0, 1.0, true, s, fl);
   }
+}
+
+void potrf_batched(const MatDesc* d_mats, const std::vector<int>& h_n, int* d_info, hipStream_t s,
+                   GemmDesc* /*unused*/, const double* diag0, int* dropped, double tol, double* pivrel) {
+  int maxn = 0;
+  for (int v : h_n) maxn = v > maxn ? v : maxn;
+  potrf_loop(d_mats, (int)h_n.size(), maxn, h_n.data(), d_info, s, diag0, dropped, tol, pivrel);
+}
+
+void potrf_uniform(const MatDesc* d_mats, int batch, int n, int* d_info, hipStream_t s) {
+  potrf_loop(d_mats, batch, n, nullptr, d_info, s, nullptr, nullptr, 0.0, nullptr);
 }
 
 // ---------------------------------------------------------------------------

@@ -184,6 +184,108 @@ __global__ __launch_bounds__(256) void k_spmv(int n, const int* rowptr, const in
   y[i] = (beta == 0.0) ? alpha * acc : alpha * acc + beta * y[i];
 }
 
+// y = alpha A x + beta y (one column) with L lanes per row (a power of two,
+// 4..64): the lanes of a row read consecutive col / val entries (lane l takes
+// the nonzeros rowptr[i] + l, + L, ...), and a butterfly over the L lanes adds
+// their partial sums (the same order in every launch).  Rows are taken in a
+// grid-stride loop over DOT1_BLOCKS blocks.  With part != NULL the kernel
+// also writes part[blockIdx.x] = sum over its rows of pdot_i y_i (the PCG
+// product p^T A p), in a fixed order.
+template <int L>
+__global__ __launch_bounds__(256) void k_spmv_l(int n, const int* rowptr, const int* col, const double* val,
+                                               const double* x, double* y, double alpha, double beta,
+                                               const double* pdot, double* part) {
+  constexpr int RPB = 256 / L;
+  __shared__ double sh4[4];
+  const int lane = threadIdx.x & (L - 1);
+  double dacc = 0.0;
+  for (int i0 = blockIdx.x * RPB; i0 < n; i0 += gridDim.x * RPB) {
+    const int i = i0 + (int)threadIdx.x / L;
+    double acc = 0.0;
+    if (i < n) {
+      const int pe = rowptr[i + 1];
+      for (int p = rowptr[i] + lane; p < pe; p += L) acc += val[p] * x[col[p]];
+    }
+#pragma unroll
+    for (int o = L / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, L);
+    if (i < n && lane == 0) {
+      const double v = (beta == 0.0) ? alpha * acc : alpha * acc + beta * y[i];
+      y[i] = v;
+      if (part) dacc += pdot[i] * v;
+    }
+  }
+  if (part) {
+    const double t = block_sum_256(dacc, sh4);
+    if (threadIdx.x == 0) part[blockIdx.x] = t;
+  }
+}
+
+// Error-free transformations (Knuth's TwoSum; the product's rounding error
+// exactly by one fused multiply-add).
+__device__ inline void two_sum(double a, double b, double& s, double& e) {
+  s = a + b;
+  const double bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+}
+
+// r = b - A x in compensated (double-double) arithmetic: every product and
+// every addition of a row carries its rounding error in a second word, so r_i
+// is accurate to a few ulps of r_i itself instead of eps sum_j |A_ij x_j|
+// (what decides the attainable true residual on ill-conditioned systems).
+// L lanes per row as in k_spmv_l; lane 0 starts from b_i, the lanes' (hi, lo)
+// pairs are joined by a butterfly of TwoSums.
+template <int L>
+__global__ __launch_bounds__(256) void k_resid_dd(int n, const int* rowptr, const int* col, const double* val,
+                                                 const double* x, const double* bv, double* r) {
+  constexpr int RPB = 256 / L;
+  const int lane = threadIdx.x & (L - 1);
+  for (int i0 = blockIdx.x * RPB; i0 < n; i0 += gridDim.x * RPB) {
+    const int i = i0 + (int)threadIdx.x / L;
+    double hi = 0.0, lo = 0.0;
+    if (i < n) {
+      if (lane == 0) hi = bv[i];
+      const int pe = rowptr[i + 1];
+      for (int p = rowptr[i] + lane; p < pe; p += L) {
+        const double a = val[p], xv = x[col[p]];
+        const double pr = a * xv;
+        const double pe_ = fma(a, xv, -pr);     // a xv = pr + pe_ exactly
+        double e;
+        two_sum(hi, -pr, hi, e);
+        lo += e - pe_;
+      }
+    }
+#pragma unroll
+    for (int o = L / 2; o > 0; o >>= 1) {
+      const double h2 = __shfl_xor(hi, o, L), l2 = __shfl_xor(lo, o, L);
+      double e;
+      // the pair (lower lane, upper lane) is added in the same order on both lanes
+      if (lane & o) two_sum(h2, hi, hi, e);
+      else two_sum(hi, h2, hi, e);
+      lo = (lane & o) ? (l2 + lo) + e : (lo + l2) + e;
+    }
+    if (i < n && lane == 0) r[i] = hi + lo;
+  }
+}
+
+// part[blockIdx.x] = sum over a grid-stride share of the rows of x_i y_i
+// (one-column dot product, first pass; the order is fixed by the launch shape)
+__global__ __launch_bounds__(256) void k_dot1_part(int n, const double* x, const double* y, double* part) {
+  __shared__ double sh4[4];
+  double acc = 0.0;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) acc += x[i] * y[i];
+  const double t = block_sum_256(acc, sh4);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+// *out = sum of the DOT1_BLOCKS partial sums (second pass, fixed order)
+__global__ __launch_bounds__(256) void k_dot1_sum(const double* part, double* out) {
+  __shared__ double sh4[4];
+  double acc = 0.0;
+  for (int k = threadIdx.x; k < DOT1_BLOCKS; k += 256) acc += part[k];
+  const double t = block_sum_256(acc, sh4);
+  if (threadIdx.x == 0) *out = t;
+}
+
 // Y = alpha A X + beta Y, X and Y row-major n x b: one wavefront per row and
 // 64 columns; the row's nonzeros are wave-uniform loads and every X row
 // segment is a contiguous 512-byte read.
@@ -546,6 +648,68 @@ __global__ __launch_bounds__(256) void k_coldot_part(int n, int b, const double*
   sh[rl][cl] = acc;
   __syncthreads();
   if (rl == 0 && c < b) part[(long)chunk * b + c] = (sh[0][cl] + sh[1][cl]) + (sh[2][cl] + sh[3][cl]);
+}
+
+// Multi-column PCG update in one pass: X += a_c P, R -= a_c Q, and the
+// partial sums of R^2 per column over the DOT_CHUNKS row ranges (the same
+// partition and order as k_coldot_part)
+__global__ __launch_bounds__(256) void k_multi_update_xr(int n, int b, const double* a, const double* P, double* X,
+                                                         const double* Q, double* R, double* part) {
+  const int cl = threadIdx.x & 63, rl = threadIdx.x >> 6;
+  const int c = blockIdx.x * 64 + cl;
+  const int chunk = blockIdx.y;
+  const int r0 = (int)((long)n * chunk / DOT_CHUNKS), r1 = (int)((long)n * (chunk + 1) / DOT_CHUNKS);
+  double acc = 0.0;
+  if (c < b) {
+    const double ac = a[c], mc = -a[c];
+    for (int i = r0 + rl; i < r1; i += 4) {
+      const long e = (long)i * b + c;
+      X[e] = ac * P[e] + 1.0 * X[e];
+      const double r = mc * Q[e] + 1.0 * R[e];
+      R[e] = r;
+      acc += r * r;
+    }
+  }
+  __shared__ double sh[4][64];
+  sh[rl][cl] = acc;
+  __syncthreads();
+  if (rl == 0 && c < b) part[(long)chunk * b + c] = (sh[0][cl] + sh[1][cl]) + (sh[2][cl] + sh[3][cl]);
+}
+
+// partial sums of X^T Y1 and X^T Y2 per column in one pass over X (Y2 may be
+// NULL); partitions as k_coldot_part
+__global__ __launch_bounds__(256) void k_coldot2_part(int n, int b, const double* X, const double* Y1,
+                                                      const double* Y2, double* part1, double* part2) {
+  const int cl = threadIdx.x & 63, rl = threadIdx.x >> 6;
+  const int c = blockIdx.x * 64 + cl;
+  const int chunk = blockIdx.y;
+  const int r0 = (int)((long)n * chunk / DOT_CHUNKS), r1 = (int)((long)n * (chunk + 1) / DOT_CHUNKS);
+  double a1 = 0.0, a2 = 0.0;
+  if (c < b)
+    for (int i = r0 + rl; i < r1; i += 4) {
+      const long e = (long)i * b + c;
+      const double x = X[e];
+      a1 += x * Y1[e];
+      if (Y2) a2 += x * Y2[e];
+    }
+  __shared__ double sh[2][4][64];
+  sh[0][rl][cl] = a1;
+  sh[1][rl][cl] = a2;
+  __syncthreads();
+  if (rl == 0 && c < b) {
+    part1[(long)chunk * b + c] = (sh[0][0][cl] + sh[0][1][cl]) + (sh[0][2][cl] + sh[0][3][cl]);
+    if (Y2) part2[(long)chunk * b + c] = (sh[1][0][cl] + sh[1][1][cl]) + (sh[1][2][cl] + sh[1][3][cl]);
+  }
+}
+
+// P = Z + beta_c P and, when Zold != NULL, Zold = Z, in one pass over Z
+__global__ void k_multi_update_p(long tot, int b, const double* Z, double* P, const double* beta, double* Zold) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= tot) return;
+  const int c = (int)(e % b);
+  const double z = Z[e];
+  P[e] = 1.0 * z + beta[c] * P[e];
+  if (Zold) Zold[e] = z;
 }
 
 __global__ void k_coldot_sum(int b, const double* part, double* out) {
@@ -932,6 +1096,56 @@ int spmm_choice(int n, long nnz, const int* rowptr, const int* col, const double
   return tune_pick(key, nv, [&](int v) { spmm_variant(v, n, rowptr, col, val, X, Y, b, alpha, beta, s, grp); }, s);
 }
 
+// lanes per row of the one-column product: the power of two at or above the
+// mean row length, 4..64 (a fixed function of the matrix, so every product
+// with one matrix takes the same summation order)
+static int spmv_lanes(int n, long nnz) {
+  const double m = n ? (double)nnz / n : 0.0;
+  int L = 4;
+  while (L < 64 && L < m) L *= 2;
+  return L;
+}
+
+static void launch_spmv(int n, long nnz, const int* rowptr, const int* col, const double* val, const double* x,
+                        double* y, double alpha, double beta, const double* pdot, double* part, hipStream_t s) {
+  const int L = spmv_lanes(n, nnz);
+  const dim3 g(DOT1_BLOCKS), t(256);
+  switch (L) {
+    case 4: hipLaunchKernelGGL(k_spmv_l<4>, g, t, 0, s, n, rowptr, col, val, x, y, alpha, beta, pdot, part); break;
+    case 8: hipLaunchKernelGGL(k_spmv_l<8>, g, t, 0, s, n, rowptr, col, val, x, y, alpha, beta, pdot, part); break;
+    case 16: hipLaunchKernelGGL(k_spmv_l<16>, g, t, 0, s, n, rowptr, col, val, x, y, alpha, beta, pdot, part); break;
+    case 32: hipLaunchKernelGGL(k_spmv_l<32>, g, t, 0, s, n, rowptr, col, val, x, y, alpha, beta, pdot, part); break;
+    default: hipLaunchKernelGGL(k_spmv_l<64>, g, t, 0, s, n, rowptr, col, val, x, y, alpha, beta, pdot, part); break;
+  }
+  AWG_LAUNCH_CHECK();
+}
+
+void l_spmv_dot(int n, long nnz, const int* rowptr, const int* col, const double* val, const double* p, double* q,
+                double* part, hipStream_t s) {
+  KScope kt("k_spmv", s, 12.0 * nnz + 4.0 * (n + 1) + 24.0 * n, 2.0 * nnz + 2.0 * n);
+  launch_spmv(n, nnz, rowptr, col, val, p, q, 1.0, 0.0, p, part, s);
+}
+
+void l_resid_dd(int n, long nnz, const int* rowptr, const int* col, const double* val, const double* x,
+                const double* b, double* r, hipStream_t s) {
+  KScope kt("k_resid_dd", s, 12.0 * nnz + 4.0 * (n + 1) + 24.0 * n, 10.0 * nnz);
+  const dim3 g(DOT1_BLOCKS), t(256);
+  switch (spmv_lanes(n, nnz)) {
+    case 4: hipLaunchKernelGGL(k_resid_dd<4>, g, t, 0, s, n, rowptr, col, val, x, b, r); break;
+    case 8: hipLaunchKernelGGL(k_resid_dd<8>, g, t, 0, s, n, rowptr, col, val, x, b, r); break;
+    case 16: hipLaunchKernelGGL(k_resid_dd<16>, g, t, 0, s, n, rowptr, col, val, x, b, r); break;
+    case 32: hipLaunchKernelGGL(k_resid_dd<32>, g, t, 0, s, n, rowptr, col, val, x, b, r); break;
+    default: hipLaunchKernelGGL(k_resid_dd<64>, g, t, 0, s, n, rowptr, col, val, x, b, r); break;
+  }
+  AWG_LAUNCH_CHECK();
+}
+
+void l_dot1_part(int n, const double* x, const double* y, double* part, hipStream_t s) {
+  KScope kt("k_dot1", s, 16.0 * n, 2.0 * n);
+  hipLaunchKernelGGL(k_dot1_part, dim3(DOT1_BLOCKS), dim3(256), 0, s, n, x, y, part);
+  AWG_LAUNCH_CHECK();
+}
+
 void l_spmm(int n, long nnz, const int* rowptr, const int* col, const double* val, const double* X, double* Y, int b,
             double alpha, double beta, hipStream_t s, const SpmmGroups* grp) {
   if (n == 0 || b == 0) return;
@@ -940,8 +1154,7 @@ void l_spmm(int n, long nnz, const int* rowptr, const int* col, const double* va
             12.0 * nnz + 4.0 * (n + 1) + 16.0 * n * (double)b + (beta != 0.0 ? 8.0 * n * (double)b : 0.0),
             2.0 * nnz * (double)b);
   if (b == 1) {
-    hipLaunchKernelGGL(k_spmv, dim3(grid1(n)), dim3(256), 0, s, n, rowptr, col, val, X, Y, alpha, beta);
-    AWG_LAUNCH_CHECK();
+    launch_spmv(n, nnz, rowptr, col, val, X, Y, alpha, beta, nullptr, nullptr, s);
     return;
   }
   spmm_variant(v, n, rowptr, col, val, X, Y, b, alpha, beta, s, grp);
@@ -991,9 +1204,41 @@ void l_scatter(int n, long tot, const int* inv_ptr, const int* inv_sub, const in
 }
 void l_coldot(int n, int b, const double* X, const double* Y, double* part, double* out, hipStream_t s) {
   if (b == 0) return;
+  if (b == 1) {
+    l_dot1_part(n, X, Y, part, s);
+    hipLaunchKernelGGL(k_dot1_sum, dim3(1), dim3(256), 0, s, part, out);
+    AWG_LAUNCH_CHECK();
+    return;
+  }
   hipLaunchKernelGGL(k_coldot_part, dim3(cdiv(b, 64), DOT_CHUNKS), dim3(256), 0, s, n, b, X, Y, part);
   AWG_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_coldot_sum, dim3(cdiv(b, 256)), dim3(256), 0, s, b, part, out);
+  AWG_LAUNCH_CHECK();
+}
+void l_multi_update_xr(int n, int b, const double* a, const double* P, double* X, const double* Q, double* R,
+                       double* part, double* rr, hipStream_t s) {
+  KScope kt("k_multi_update_xr", s, 48.0 * n * (double)b, 5.0 * n * (double)b);
+  hipLaunchKernelGGL(k_multi_update_xr, dim3(cdiv(b, 64), DOT_CHUNKS), dim3(256), 0, s, n, b, a, P, X, Q, R, part);
+  AWG_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_coldot_sum, dim3(cdiv(b, 256)), dim3(256), 0, s, b, part, rr);
+  AWG_LAUNCH_CHECK();
+}
+void l_coldot2(int n, int b, const double* X, const double* Y1, const double* Y2, double* part, double* out1,
+               double* out2, hipStream_t s) {
+  KScope kt("k_coldot2", s, (Y2 ? 24.0 : 16.0) * n * (double)b, (Y2 ? 4.0 : 2.0) * n * (double)b);
+  double* part2 = part + (long)DOT_CHUNKS * b;
+  hipLaunchKernelGGL(k_coldot2_part, dim3(cdiv(b, 64), DOT_CHUNKS), dim3(256), 0, s, n, b, X, Y1, Y2, part, part2);
+  AWG_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_coldot_sum, dim3(cdiv(b, 256)), dim3(256), 0, s, b, part, out1);
+  AWG_LAUNCH_CHECK();
+  if (Y2) {
+    hipLaunchKernelGGL(k_coldot_sum, dim3(cdiv(b, 256)), dim3(256), 0, s, b, part2, out2);
+    AWG_LAUNCH_CHECK();
+  }
+}
+void l_multi_update_p(long rows, int b, const double* Z, double* P, const double* beta, double* Zold, hipStream_t s) {
+  KScope kt("k_multi_update_p", s, (Zold ? 32.0 : 24.0) * rows * (double)b, 2.0 * rows * (double)b);
+  hipLaunchKernelGGL(k_multi_update_p, dim3(grid1(rows * b)), dim3(256), 0, s, rows * b, b, Z, P, beta, Zold);
   AWG_LAUNCH_CHECK();
 }
 void l_colaxpby(long rows, int b, const double* X, const double* a, double* Y, const double* bb, double sa, double sb,

@@ -16,12 +16,13 @@ from oracle import awg_oracle as O
 
 pytestmark = pytest.mark.gpu
 GOLD_PATH = os.path.join(os.path.dirname(__file__), "golden", "q1_2d_256.json")
+X_PATH = os.path.join(os.path.dirname(__file__), "golden", "q1_2d_256_x.npy")
 
 
 @pytest.fixture(scope="module")
 def run(gpu_lib):
     import torch
-    if not os.path.exists(GOLD_PATH):
+    if not os.path.exists(GOLD_PATH) or not os.path.exists(X_PATH):
         pytest.skip("golden file missing")
     gold = json.load(open(GOLD_PATH))
     w = P.q1_2d(256)
@@ -40,14 +41,26 @@ def test_coarse_sizes_exact(run):
 
 
 def test_pcg_iterate_and_count(run):
+    """The whole iterate against the oracle's (stored by the oracle-only
+    script): ||x - x_oracle|| <= 1e-10 ||x_oracle||, iterations within 1."""
     w, gold, solver, x, info = run
     assert info["converged"] == 1
     assert abs(info["iters"] - gold["iters"]) <= 1
-    xs = x[np.array(gold["x_idx"])]
-    ref = np.array(gold["x_val"])
-    # sampled entries against the oracle, scaled by the oracle's ||x||
-    assert np.max(np.abs(xs - ref)) <= 1e-10 * gold["x_norm"]
-    assert info["rel_res_true"] <= 2 * w.tol
+    xo = np.load(X_PATH)
+    err = np.linalg.norm(x - xo) / np.linalg.norm(xo)
+    s = solver.stats()
+    print(f"[full-size parity] ||x - x_o|| / ||x_o|| = {err:.3e}; deletion margins: oracle "
+          f"{gold['e0_margin']:.3g}/{gold['ew_margin']:.3g}, gpu {s['e0_margin']:.3g}/{s['ew_margin']:.3g}",
+          flush=True)
+    m = min(gold["e0_margin"], gold["ew_margin"], s["e0_margin"], s["ew_margin"])
+    if m < 100:
+        # a coarse deletion decision within 100x of its threshold: which
+        # near-dependent vector spans the coarse space is decided by rounding
+        print(f"[parity unpinned] deletion margin {m:.3g} < 100: x held to the PCG tolerance", flush=True)
+        assert err <= 1e-8
+    else:
+        assert err <= 1e-10
+    assert info["rel_res_true"] <= w.tol
 
 
 def coloring_constant_Aplus(subs, n):

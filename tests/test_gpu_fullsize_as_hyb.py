@@ -6,9 +6,14 @@ tests/golden/q1_2d_256_as_hyb.json by tests/golden/make_q1_2d_256_as_hyb.py
 On this workload the union of the two pencils' vectors has one near-null
 combination across subdomains (Jacobi-scaled E0 eigenvalue 2e-14): both
 sides deflate it.  Checked: the coarse dimensions and the deflated count
-exactly, the iteration count within 1, the Lanczos estimates within 1e-3,
-and 256 sampled entries of the iterate within 10 eps cond(deflated scaled E0)
-of the oracle's (the accuracy to which either side can apply E0^+)."""
+exactly, the iteration count within 1, the Lanczos estimates within 1e-3.
+
+The iterate is parity unpinned here: the kept coarse matrix has cond ~ 4e8
+after the deflation, so either side applies E0^+ only to about eps * cond
+~ 1e-7 relative, far above the 1e-10 bar.  The whole iterate is compared
+with the oracle's (stored as .npy) and the measured difference is printed;
+the assertion is the sanity bound 10 eps cond(deflated scaled E0), not the
+stated bar."""
 import json
 import os
 
@@ -20,12 +25,15 @@ import awg_problems as P
 pytestmark = pytest.mark.gpu
 
 GOLD_PATH = os.path.join(os.path.dirname(__file__), "golden", "q1_2d_256_as_hyb.json")
+X_PATH = os.path.join(os.path.dirname(__file__), "golden", "q1_2d_256_as_hyb_x.npy")
 EPS = np.finfo(np.float64).eps
 
 
 @pytest.fixture(scope="module")
 def run(gpu_lib):
     import torch
+    if not os.path.exists(GOLD_PATH) or not os.path.exists(X_PATH):
+        pytest.skip("golden file missing")
     gold = json.load(open(GOLD_PATH))
     w = P.q1_2d(256)
     print(f"\n[gpu case] q1_2d 256^2, 64 subdomains, h2=as_hyb n={w.A.shape[0]}", flush=True)
@@ -50,6 +58,10 @@ def test_pcg_iterate_and_count(run):
     assert abs(info["lmax_est"] - gold["lmax"]) <= 1e-3 * gold["lmax"]
     assert abs(info["lmin_est"] - gold["lmin"]) <= 1e-3 * gold["lmin"]
     bar = max(1e-10, 10 * EPS * gold["cond_E0_scaled_deflated"])
-    xs = x[np.array(gold["x_idx"])]
-    assert np.max(np.abs(xs - np.array(gold["x_val"]))) <= bar * gold["x_norm"]
-    assert info["rel_res_true"] <= 2 * w.tol
+    xo = np.load(X_PATH)
+    err = np.linalg.norm(x - xo) / np.linalg.norm(xo)
+    print(f"[parity unpinned] as_hyb full size: ||x - x_o|| / ||x_o|| = {err:.3e} "
+          f"(cond of the deflated scaled E0 {gold['cond_E0_scaled_deflated']:.3g}, "
+          f"deflation margin {gold['deflation_margin']:.3g})", flush=True)
+    assert err <= bar
+    assert info["rel_res_true"] <= w.tol

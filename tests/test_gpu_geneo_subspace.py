@@ -78,7 +78,9 @@ def test_pcg_matches_dense_path(trio, gpu_lib):
     x, info = sub.pcg(b, tol=w.tol, maxit=500)
     ref = O.pcg(w.A, w.b, st.apply, tol=w.tol)
     assert info["converged"] == 1 and abs(info["iters"] - ref.iters) <= 1
-    assert np.linalg.norm(x.cpu().numpy() - ref.x) <= 1e-8 * np.linalg.norm(ref.x)
+    err = np.linalg.norm(x.cpu().numpy() - ref.x) / np.linalg.norm(ref.x)
+    print(f"[parity] subspace GenEO: ||x - x_o|| / ||x_o|| = {err:.3e}", flush=True)
+    assert err <= 1e-8
     assert info["rel_res_true"] <= 2 * w.tol
 
 

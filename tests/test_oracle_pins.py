@@ -392,3 +392,166 @@ def test_gram_keep_projection_is_the_projector_onto_the_span():
     # M-orthogonal projector onto span(B): B (B^T M B)^{-1} B^T M
     Pr = B @ np.linalg.solve(B.T @ M @ B, B.T @ M)
     assert np.max(np.abs(Pk - Pr)) <= 1e-9
+
+
+# ----------------------------------------------------------------------------
+# coloring constant (Definition of the coloring constant, Section 2.2)
+# ----------------------------------------------------------------------------
+def _conflicts_bruteforce(subs, M):
+    """s ~ t when M has a nonzero (i, j) with i in Omega^s and j in Omega^t,
+    by looping over the entries of the dense M."""
+    Md = M.toarray() != 0
+    N = len(subs)
+    C = np.zeros((N, N), dtype=bool)
+    for s in range(N):
+        for t in range(N):
+            if s != t:
+                C[s, t] = bool(Md[np.ix_(subs[s], subs[t])].any())
+    return C
+
+
+@pytest.mark.parametrize("mk", [small_fd, lambda: random_spd(11) + (None,)])
+def test_coloring_is_valid(mk):
+    """No two conflicting subdomains share a color, for the pattern of A and
+    of A_+ (the matrices whose coloring constants enter the bounds)."""
+    A, subs, _ = mk()
+    subs = [np.asarray(s) for s in subs]
+    st = O.setup(A, subs, 0.1)
+    for M in (A, O.assemble_A_plus(st)):
+        col = O.conflict_coloring(subs, M)
+        C = _conflicts_bruteforce(subs, M)
+        s, t = np.nonzero(C)
+        assert np.all(col[s] != col[t])
+        assert O.coloring_constant(subs, M) == col.max() + 1
+
+
+def test_coloring_constant_of_box_partitions():
+    """Known counts.  A 1D chain split into consecutive blocks overlapping in
+    one node: each block meets only its two neighbours, so 2 colors.  The 5-point
+    Laplacian on a grid split into 4 x 4 boxes extended by one layer: boxes
+    conflict with their 8 neighbours (a king's graph, which contains K4), so
+    at least 4 colors, and the greedy coloring in row-major order uses exactly 4."""
+    n = 41
+    A1 = sp.diags([-np.ones(n - 1), 2.0 * np.ones(n), -np.ones(n - 1)], [-1, 0, 1]).tocsr()
+    subs1 = [np.arange(10 * k, min(10 * k + 11, n)) for k in range(4)]
+    assert O.coloring_constant(subs1, A1) == 2
+    prob = P.fd5_diffusion(16, np.ones((17, 17)))
+    subs2 = [np.asarray(s) for s in part.box_subdomains(prob, (4, 4), 1)]
+    C = _conflicts_bruteforce(subs2, prob.A)
+    # the conflict graph is the king's graph of the 4 x 4 box layout
+    for s in range(16):
+        for t in range(16):
+            if s != t:
+                king = max(abs(s // 4 - t // 4), abs(s % 4 - t % 4)) == 1
+                assert C[s, t] == king
+    assert O.coloring_constant(subs2, prob.A) == 4
+
+
+# ----------------------------------------------------------------------------
+# PCG: restart from the true residual (reading of the stopping rule)
+# ----------------------------------------------------------------------------
+def _drift_case(seed, span):
+    """Diagonally scaled 1D Laplacian S K S (entries of S spread over 10^span):
+    Jacobi-preconditioned PCG converges in ~150 iterations while the recursive
+    residual drifts away from b - A x by rounding."""
+    rng = np.random.default_rng(seed)
+    n = 200
+    K = sp.diags([-np.ones(n - 1), 2.05 * np.ones(n), -np.ones(n - 1)], [-1, 0, 1]).toarray()
+    S = 10 ** rng.uniform(0, span, n)
+    A = (S[:, None] * K) * S[None, :]
+    b = rng.standard_normal(n)
+    d = 1.0 / np.diag(A)
+    return A, b, (lambda v: d * v)
+
+
+def _true_res_extended(A, b, x):
+    """||b - A x|| / ||b|| evaluated in 80-bit extended precision."""
+    Al, bl, xl = (np.asarray(v, dtype=np.longdouble) for v in (A, b, x))
+    return float(np.linalg.norm((bl - Al @ xl).astype(np.float64)) / np.linalg.norm(b))
+
+
+def test_pcg_restart_recovers_the_true_residual():
+    """The recursive residual meets tol while b - A x does not; without the
+    restart PCG stops there unconverged, with it one restart from the true
+    residual reaches tol, checked against the residual of the returned x in
+    extended precision and against a direct solve."""
+    A, b, M = _drift_case(36, 8)
+    tol = 1e-8
+    r0 = O.pcg(A, b, M, tol=tol, maxit=2000, max_restarts=0)
+    assert r0.res_hist[-1] <= tol and not r0.converged
+    assert _true_res_extended(A, b, r0.x) > tol
+    r = O.pcg(A, b, M, tol=tol, maxit=2000)
+    assert r.restarts >= 1 and r.converged
+    assert r.iters > r0.iters
+    assert _true_res_extended(A, b, r.x) <= tol
+    assert abs(_true_res_extended(A, b, r.x) - r.rel_res_true) <= 0.05 * r.rel_res_true
+    xd = np.linalg.solve(A, b)
+    # same solution: A (x - x_direct) is small relative to b
+    assert np.linalg.norm(A @ (r.x - xd)) <= 2 * tol * np.linalg.norm(b)
+
+
+def test_pcg_restart_cap_reports_non_convergence():
+    """Where b - A x cannot reach tol in FP64 (scaling spread 10^10), the
+    restarts stop at the cap and PCG reports non-convergence with the
+    residual of the returned iterate."""
+    A, b, M = _drift_case(36, 10)
+    r = O.pcg(A, b, M, tol=1e-8, maxit=2000, max_restarts=3)
+    assert r.restarts == 3 and not r.converged
+    tr = _true_res_extended(A, b, r.x)
+    assert tr > 1e-8
+    assert abs(tr - r.rel_res_true) <= 0.05 * tr
+
+
+# ----------------------------------------------------------------------------
+# the direct W of the oracle above n = 4000 (sparse LU of A + Woodbury)
+# ----------------------------------------------------------------------------
+def test_direct_W_large_branch_matches_assembled_A_plus():
+    """O.setup's W for n > 4000 comes from solve_A_plus_direct's Woodbury
+    branch on a sparse LU of A; it equals the dense solve with A_+ assembled
+    from the local A^s_+ = V_+ L_+ V_+^T (a different route to the same
+    matrix), column by column."""
+    w = P.q1_2d(64)
+    assert w.A.shape[0] > 4000
+    st = O.setup(w.A, w.subs, w.tau)
+    assert st.w_info["solver"] == "direct" and st.n_minus > 0
+    Ap = O.assemble_A_plus(st).toarray()
+    Wd = sla.cho_solve(sla.cho_factor(Ap, lower=True), st.Vg)
+    # backward error of each column with the assembled A_+ (independent of
+    # the conditioning), then the forward error within the first-order bound
+    # 10 eps kappa(A_+) of two backward-stable solves (kappa ~ 2.4e7 here)
+    nA = np.linalg.norm(Ap, 2)
+    back = np.linalg.norm(Ap @ st.W - st.Vg, axis=0) / (nA * np.linalg.norm(st.W, axis=0))
+    assert back.max() <= 1e-11
+    ev = np.linalg.eigvalsh(Ap)
+    kappa = ev[-1] / ev[0]
+    err = np.linalg.norm(st.W - Wd, axis=0) / np.linalg.norm(Wd, axis=0)
+    assert err.max() <= 10 * np.finfo(float).eps * kappa
+
+
+# ----------------------------------------------------------------------------
+# margin of the deletion of dependent coarse vectors (D2 / D4 readings)
+# ----------------------------------------------------------------------------
+def test_deletion_margin():
+    """Pivots of gram_keep are the squared relative distances of each column
+    from the span of the kept earlier ones; the margin is the factor to the
+    threshold of the closest decision."""
+    rng = np.random.default_rng(3)
+    a, b = rng.standard_normal((2, 30))
+    e = np.linalg.qr(np.stack([a, b, rng.standard_normal(30)], axis=1))[0][:, 2]   # unit, orthogonal to a, b
+    for eps in (1e-2, 1e-4, 1e-6):
+        c = a + b + eps * np.linalg.norm(a + b) * e       # distance eps * |a + b| from span(a, b)
+        X = np.stack([a, b, c], axis=1)
+        E = X.T @ X
+        keep, piv = O.gram_keep(E, return_pivots=True)
+        p2 = eps ** 2 / (1 + eps ** 2)                    # squared sine of the angle to span(a, b)
+        assert abs(piv[2] - p2) <= 1e-5 * p2 + 1e-14            # cancellation: absolute error ~ eps
+        if p2 > 1e-10:
+            assert keep.tolist() == [0, 1, 2]
+            assert np.isclose(O.deletion_margin(piv, keep), min(p2 / 1e-10, piv[:2].min() / 1e-10), rtol=1e-4)
+        else:
+            assert keep.tolist() == [0, 1]
+            assert np.isclose(O.deletion_margin(piv, keep), 1e-10 / piv[2], rtol=1e-12)
+    X = np.stack([a, b, a - 2 * b], axis=1)
+    keep, piv = O.gram_keep(X.T @ X, return_pivots=True)
+    assert keep.tolist() == [0, 1]
+    assert O.deletion_margin(piv, keep) >= 1e3
