@@ -56,6 +56,21 @@ int awg_dense_gemm_ex(int32_t batch, int32_t m, int32_t n, int32_t k, int32_t tr
 int awg_dense_potrf(int32_t batch, int32_t n, double* A, int32_t lda, int64_t strideA, int32_t* info_host,
                     void* stream);
 
+/* awg_dense_potrf for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): it calls no hipMalloc, hipFree or allocating library routine.
+ * The block descriptors and the info array live in a static device array of
+ * the library (4096 x 28 bytes, 112 KiB, one copy per device, held until the
+ * process ends), so batch <= AWG_NOALLOC_MAX_BATCH; a larger batch returns
+ * AWG_ERR_ARG before any work.  Otherwise the same arguments, factors (bit
+ * for bit), info_host (may be NULL) and return values as awg_dense_potrf.
+ * The array belongs to the current device (stream must be on it) and keeps
+ * the last call's contents; calls that overlap on one device (several host
+ * threads or streams) share it and race, so the caller serialises them. */
+#define AWG_NOALLOC_MAX_BATCH 4096
+int awg_dense_potrf_noalloc(int32_t batch, int32_t n, double* A, int32_t lda, int64_t strideA,
+                            int32_t* info_host, void* stream);
+
 /* B_b <- L_b^{-1} B_b (trans = 0) or L_b^{-T} B_b (trans = 1), L_b lower n x n,
  * B_b n x nrhs. */
 int awg_dense_trsm(int32_t batch, int32_t n, int32_t nrhs, int32_t trans, const double* L, int32_t ldl,

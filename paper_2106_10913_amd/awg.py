@@ -27,11 +27,13 @@ STATUS = {0: "AWG_OK", 1: "AWG_NOT_CONVERGED", -1: "AWG_ERR_ARG", -2: "AWG_ERR_N
 
 EXPORTED = ["awg_default_options", "awg_setup", "awg_apply", "awg_pcg", "awg_stats", "awg_export",
             "awg_last_error", "awg_destroy", "awg_kernel_timing", "awg_kernel_times", "awg_pcg_graph",
-            "awg_dense_gemm", "awg_dense_gemm_ex", "awg_dense_potrf", "awg_dense_trsm", "awg_dense_low_eigs",
+            "awg_dense_gemm", "awg_dense_gemm_ex", "awg_dense_potrf", "awg_dense_potrf_noalloc", "awg_dense_trsm",
+            "awg_dense_low_eigs",
             "awg_mlp_create", "awg_mlp_num_params", "awg_mlp_get_params", "awg_mlp_set_params", "awg_mlp_forward",
             "awg_mlp_loss_grad", "awg_mlp_get_grads", "awg_mlp_adam_step", "awg_mlp_last_error", "awg_mlp_destroy",
             "awg_csr_spmm", "awg_autotune", "awg_tune_report", "awg_kernel_timing_filter", "awg_probe_mfma_f64"]
 MLP_FEATURES = 12
+NOALLOC_MAX_BATCH = 4096     # AWG_NOALLOC_MAX_BATCH (awg_dense.h)
 
 
 class Options(ctypes.Structure):
@@ -102,6 +104,8 @@ def lib():
     L.awg_probe_mfma_f64.restype = ctypes.c_int
     L.awg_dense_potrf.argtypes = [i32, i32, vp, i32, i64, vp, vp]
     L.awg_dense_potrf.restype = ctypes.c_int
+    L.awg_dense_potrf_noalloc.argtypes = [i32, i32, vp, i32, i64, vp, vp]
+    L.awg_dense_potrf_noalloc.restype = ctypes.c_int
     L.awg_dense_trsm.argtypes = [i32, i32, i32, i32, vp, i32, i64, vp, i32, i64, vp]
     L.awg_dense_trsm.restype = ctypes.c_int
     L.awg_dense_low_eigs.argtypes = [i32, i32, vp, i32, i64, dbl, i32, vp, vp, vp, i64, vp]
@@ -380,6 +384,17 @@ def dense_potrf(A):
     rc = lib().awg_dense_potrf(batch, n, A.data_ptr(), n, n * n, info.ctypes.data, _stream())
     if rc not in (0, -5):
         raise AWGError(rc, "awg_dense_potrf")
+    return info
+
+
+def dense_potrf_noalloc(A):
+    """dense_potrf through the entry point that allocates no device memory
+    (batch <= NOALLOC_MAX_BATCH); returns the info array."""
+    batch, n, _ = A.shape
+    info = np.zeros(batch, dtype=np.int32)
+    rc = lib().awg_dense_potrf_noalloc(batch, n, A.data_ptr(), n, n * n, info.ctypes.data, _stream())
+    if rc not in (0, -5):
+        raise AWGError(rc, "awg_dense_potrf_noalloc")
     return info
 
 

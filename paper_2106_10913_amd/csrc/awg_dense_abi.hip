@@ -1,6 +1,7 @@
 // C ABI of the batched dense building blocks (include/awg_dense.h).
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 
 #include "awg.h"
 #include "awg_common.h"
@@ -33,6 +34,50 @@ int guarded(hipStream_t s, F&& f) {
 __global__ void k_rowptr_to32(int n, const int64_t* in, int* out) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i <= n) out[i] = (int)in[i];
+}
+
+// ---------------------------------------------------------------------------
+// awg_dense_potrf_noalloc: the block descriptors and the info array of one
+// call live in `scratch`, a static device array of this library (one copy
+// per device, held until the process ends).  In host code `scratch` names a
+// host-side stand-in, never the device memory: every host use goes through
+// the device address that hipGetSymbolAddress returns, cached per device.
+// ---------------------------------------------------------------------------
+constexpr int NOALLOC_MAX_BATCH = AWG_NOALLOC_MAX_BATCH;
+constexpr size_t NOALLOC_DESC_BYTES = sizeof(MatDesc) * NOALLOC_MAX_BATCH;
+constexpr size_t NOALLOC_BYTES = NOALLOC_DESC_BYTES + sizeof(int) * NOALLOC_MAX_BATCH;
+static_assert(sizeof(MatDesc) == 24, "scratch size stated in awg_dense.h");
+static_assert(NOALLOC_DESC_BYTES % 256 == 0, "info array must start 256-byte aligned");
+
+__device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+unsigned char* g_scratch_ptr[MAX_DEVICES] = {};
+
+// device address of `scratch` on the current device (looked up once per device)
+unsigned char* scratch_on_current_device() {
+  int dev = 0;
+  AWG_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= MAX_DEVICES) throw Error(AWG_ERR_ARG, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    AWG_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) throw Error(AWG_ERR_HIP, "hipGetSymbolAddress returned a null address");
+    g_scratch_ptr[dev] = (unsigned char*)p;
+  }
+  return g_scratch_ptr[dev];
+}
+
+// descriptors of a uniform batch, and a cleared info array (the array keeps
+// the previous call's values)
+__global__ void k_uniform_desc(MatDesc* d, int* info, double* A, int batch, int n, int lda, long stride) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < batch) {
+    d[b] = MatDesc{A + b * stride, n, n, lda, 0};
+    info[b] = 0;
+  }
 }
 
 }  // namespace
@@ -106,6 +151,38 @@ int awg_dense_potrf(int32_t batch, int32_t n, double* A, int32_t lda, int64_t st
     for (int b = 0; b < batch; ++b) {
       if (info_host) info_host[b] = h[b];
       bad |= h[b] != 0;
+    }
+  });
+  return rc ? rc : (bad ? AWG_ERR_NOT_SPD : AWG_OK);
+}
+
+int awg_dense_potrf_noalloc(int32_t batch, int32_t n, double* A, int32_t lda, int64_t strideA,
+                            int32_t* info_host, void* stream) {
+  if (batch <= 0 || batch > NOALLOC_MAX_BATCH || n <= 0 || lda < n || !A) return AWG_ERR_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  bool bad = false;
+  int rc = guarded(s, [&] {
+    unsigned char* base = scratch_on_current_device();
+    MatDesc* d = (MatDesc*)base;
+    int* info = (int*)(base + NOALLOC_DESC_BYTES);
+    hipLaunchKernelGGL(k_uniform_desc, dim3(cdiv(batch, 256)), dim3(256), 0, s, d, info, A, batch, n, lda,
+                       (long)strideA);
+    AWG_LAUNCH_CHECK();
+    potrf_uniform(d, batch, n, info, s);
+    if (info_host) {
+      AWG_HIP(hipMemcpyAsync(info_host, info, sizeof(int32_t) * batch, hipMemcpyDeviceToHost, s));
+      AWG_HIP(hipStreamSynchronize(s));
+      for (int b = 0; b < batch; ++b) bad |= info_host[b] != 0;
+    } else {
+      // only the failure flag of the whole batch is needed: read the entries
+      // in chunks through a small host array
+      int32_t chunk[256];
+      for (int b0 = 0; b0 < batch; b0 += 256) {
+        const int m = std::min(256, batch - b0);
+        AWG_HIP(hipMemcpyAsync(chunk, info + b0, sizeof(int32_t) * m, hipMemcpyDeviceToHost, s));
+        AWG_HIP(hipStreamSynchronize(s));
+        for (int b = 0; b < m; ++b) bad |= chunk[b] != 0;
+      }
     }
   });
   return rc ? rc : (bad ? AWG_ERR_NOT_SPD : AWG_OK);

@@ -53,3 +53,14 @@ def test_default_options_and_setup_argument_errors():
     assert L.awg_apply(None, None, None) == -1
     assert L.awg_stats(None, None, 0) == -1
     L.awg_destroy(None)
+
+
+def test_noalloc_potrf_rejects_batches_beyond_its_scratch():
+    """The entry point without device allocation checks its batch limit on the
+    host, before any GPU work (no GPU needed)."""
+    L = awg.lib()
+    fake = ctypes.c_void_p(16)
+    assert L.awg_dense_potrf_noalloc(awg.NOALLOC_MAX_BATCH + 1, 4, fake, 4, 16, None, None) == -1
+    assert L.awg_dense_potrf_noalloc(0, 4, fake, 4, 16, None, None) == -1
+    assert L.awg_dense_potrf_noalloc(1, 4, fake, 3, 16, None, None) == -1
+    assert L.awg_dense_potrf_noalloc(1, 4, None, 4, 16, None, None) == -1
