@@ -344,6 +344,29 @@ def copy_probe(torch, mib: int) -> None:
     print(json.dumps({"copy_probe_bytes_read": n * 8, "copy_probe_bytes_written": n * 8, "launches": 3}))
 
 
+def setup_work(w, st) -> dict:
+    """Algorithmic set-up flops of one step: per subdomain n_s^3/3 (Cholesky of
+    K^s) + n_s^3/3 (Cholesky of M_B^s) + n_s^3 (the dense transforms) +
+    it_eig 2 n_s^2 b (subspace GenEO iterations, b columns), then
+    it_W n_- [2 sum n_s^2 + 3 . 2 nnz + 8 sum n_s k_s + 8 sum n_s m_s] for the
+    W solves, 2 n n_-^2 for E_W and (n0^3 + n_-^3)/3 for the coarse
+    factorisations.  Of these, the W local products 2 sum n_s^2 n_- it_W run
+    on FP32 matrix cores in the fast form."""
+    import numpy as np
+    ns = np.array([len(t) for t in w.subs], dtype=np.float64)
+    ks = np.array(st["k_s"], dtype=np.float64)
+    ms = np.array(st["m_s"], dtype=np.float64)
+    nnz, n = float(w.A.nnz), float(w.A.shape[0])
+    nm, n0, itw = float(st["n_minus"]), float(st["n0"]), float(st["w_iters"])
+    it_eig = float(max(st["eig_iters"], default=0))
+    local = float(np.sum(ns ** 3 / 3 * 2 + ns ** 3 + it_eig * 2 * ns ** 2 * st.get("eig_block", 16)))
+    w_local = itw * nm * 2 * float(np.sum(ns ** 2))
+    w_rest = itw * nm * (6 * nnz + 8 * float(np.sum(ns * ks)) + 8 * float(np.sum(ns * ms)))
+    coarse = 2 * n * nm ** 2 + (n0 ** 3 + nm ** 3) / 3
+    return {"local": local, "w_local_product": w_local, "w_rest": w_rest, "coarse": coarse,
+            "total": local + w_local + w_rest + coarse}
+
+
 def form_result(infos, tol):
     """Accuracy of the timed steps of one form: every step must have converged
     with a true residual <= tol."""
@@ -427,11 +450,21 @@ def main():
         kt = {k: v for k, v in awg.kernel_times(reset=True).items() if k == dominant}
         ok, worst = form_result(infos, w.tol)
         st, info = stats[-1], infos[-1]
+        wk = setup_work(w, st)
+        f32w = local_prec == "f32"
+        # time the set-up would take with every flop at its matrix-core peak
+        # (the W local products at the FP32 peak in the FP32 form)
+        t_peak = ((wk["total"] - (wk["w_local_product"] if f32w else 0.0)) / (FP64_PEAK_TFLOPS * 1e12)
+                  + (wk["w_local_product"] / (FP32_PEAK_TFLOPS * 1e12) if f32w else 0.0))
         rec = {"ms_per_step": round(ms, 3), "accuracy_ok": ok, "worst_true_res": worst,
+               "setup_roofline": {"flops": wk, "setup_ms": round(st["ms"]["total"], 3),
+                                  "ms_at_peak": round(t_peak * 1e3, 3),
+                                  "frac": round(t_peak * 1e3 / st["ms"]["total"], 4)},
                "local_prec": local_prec, "geneo": geneo, "iters": info["iters"],
                "restarts": info.get("restarts", 0),
                "kappa_est": info["lmax_est"] / info["lmin_est"], "n_minus": st["n_minus"], "n0": st["n0"],
-               "w_iters": st["w_iters"], "eig_fallbacks": st["eig_fallbacks"], "eig_learned": st["eig_learned"],
+               "w_iters": st["w_iters"], "w_iters_mean": st.get("w_iters_mean"),
+               "eig_fallbacks": st["eig_fallbacks"], "eig_learned": st["eig_learned"],
                "eig_iters_max": max(st["eig_iters"], default=0),
                "phases_ms": {k: round(v, 3) for k, v in st["ms"].items()},
                "kernels_ms_per_warmup_step": {k: round(v["ms"] / max(1, args.warmup), 3) for k, v in

@@ -175,6 +175,17 @@ struct awg_ctx {
   // inputs (copied)
   DBuf<int> rowptr, col;
   SpmmGroups sgrp;    // row groups of the multi-column SpMM
+  // multi-column A_+ and R0^T products as sparse products: [A | V_-] (V_-
+  // the n x sum_s k_s prolongation of the V^s) applied to [X; |L_-| V^T R X],
+  // and R0^T itself (n x n0) applied to the coarse coefficients
+  DBuf<int> aug_rp, aug_col, y_rp, y_col;
+  DBuf<double> aug_val, y_val;
+  long aug_nnz = 0, y_nnz = 0;
+  // their restrictions V_-^T and R0 as CSR (one-column products of the PCG)
+  DBuf<int> vt_rp, vt_col, yt_rp, yt_col;
+  DBuf<double> vt_val, yt_val;
+  long vt_nnz = 0, yt_nnz = 0;
+  SpmmGroups aug_grp, y_grp;
   DBuf<double> val;
   std::vector<long> h_subptr;
   std::vector<int> ns;
@@ -208,6 +219,7 @@ struct awg_ctx {
   }
   std::map<std::string, double> tms;
   int w_iters = 0;
+  double w_iters_mean = 0.0;    // mean over the W columns of their iteration counts
   double w_time = 0.0;
   std::vector<double> eig_resid_max;
   std::vector<int> eig_iters;   // subspace GenEO: iteration of convergence per subdomain
@@ -235,6 +247,14 @@ __global__ void k_scale_rows(double* T, const double* lam, long rows, int b) {
   const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= rows * b) return;
   T[e] *= fabs(lam[e / b]);
+}
+
+// the same scaled rows written to dst (the coefficient rows appended to the
+// multi-vector of a [A | V_-] product)
+__global__ void k_scale_rows_to(const double* T, const double* lam, long rows, int b, double* dst) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= rows * b) return;
+  dst[e] = T[e] * fabs(lam[e / b]);
 }
 
 // G (n0 x b, row-major) = columns c0 .. c0+b-1 of the identity
@@ -412,8 +432,10 @@ void build_ws(awg_ctx& c, MultiWS& w, int b) {
   w.b = b;
   const long n = c.n;
   w.R.alloc(n * b);
-  w.Z.alloc(n * b);
-  w.T1.alloc(n * b);
+  // T1 and Z are inputs of A_+ products: LV.cols extra rows hold the
+  // coefficient rows of the [A | V_-] product
+  w.Z.alloc((n + c.LV.cols) * b);
+  w.T1.alloc((n + c.LV.cols) * b);
   w.T2.alloc(n * b);
   w.Xs.alloc(c.sumns * b);
   w.Os.alloc(c.sumns * b);
@@ -540,9 +562,24 @@ void op_aminus(awg_ctx& c, MultiWS& w, const double* X, double* Yo, double beta)
   l_scatter(c.n, c.sumns, c.invptr, c.invsub, c.invloc, c.subptr, w.Os, b, Yo, 1.0, beta, c.s);
 }
 
-// Y = A_+ X = A X + A_- X (item (i) of the A_+ theorem, Section 3.2)
-void op_aplus(awg_ctx& c, MultiWS& w, const double* X, double* Yo) {
-  l_spmm(c.n, c.nnz, c.rowptr, c.col, c.val, X, Yo, w.b, 1.0, 0.0, c.s, &c.sgrp);
+// Y = A_+ X = A X + A_- X (item (i) of the A_+ theorem, Section 3.2).  For
+// b > 1: T = V^T R X by the restricted GEMMs, its rows scaled by |L_-| and
+// written below X (X has LV.cols extra rows), then one sparse product with
+// [A | V_-], so the prolongation of the A_- term costs no pass of its own.
+void op_aplus(awg_ctx& c, MultiWS& w, double* X, double* Yo) {
+  const int b = w.b;
+  if (c.aug_nnz > 0) {
+    if (b > 1)
+      bmm_restricted(c, w, w.dVt, X, w.maxk, w.maxns, w.flV, "Vt");
+    else
+      l_spmm((int)c.LV.cols, c.vt_nnz, c.vt_rp, c.vt_col, c.vt_val, X, w.Tk, 1, 1.0, 0.0, c.s);
+    hipLaunchKernelGGL(k_scale_rows_to, dim3(cdiv(c.LV.cols * b, 256)), dim3(256), 0, c.s, w.Tk.p, c.lamV.p,
+                       (long)c.LV.cols, b, X + c.n * (long)b);
+    AWG_LAUNCH_CHECK();
+    l_spmm(c.n, c.aug_nnz, c.aug_rp, c.aug_col, c.aug_val, X, Yo, b, 1.0, 0.0, c.s, &c.aug_grp, "k_spmm:A+");
+    return;
+  }
+  l_spmm(c.n, c.nnz, c.rowptr, c.col, c.val, X, Yo, b, 1.0, 0.0, c.s, &c.sgrp);
   op_aminus(c, w, X, Yo, 1.0);
 }
 
@@ -552,12 +589,20 @@ void op_r0(awg_ctx& c, MultiWS& w, const double* X) {
     bmm_restricted(c, w, w.dYt, X, w.maxm, w.maxns, w.flY, "Yt");
     return;
   }
+  if (c.yt_nnz > 0) {
+    l_spmm((int)c.LY.cols, c.yt_nnz, c.yt_rp, c.yt_col, c.yt_val, X, w.G0, 1, 1.0, 0.0, c.s);
+    return;
+  }
   l_gather(c.sumns, c.subidx, X, w.b, w.Xs, c.s);
   bmm(w.dYt, c.N, w.maxm, w.maxns, false, 1.0, 0.0, w.b, c.s, w.flY, nullptr, "Yt");
 }
 
-// Yo = beta Yo + alpha R0^T G1
+// Yo = beta Yo + alpha R0^T G1 (b > 1: a sparse product with R0^T in CSR)
 void op_r0t(awg_ctx& c, MultiWS& w, double* Yo, double beta, double alpha = 1.0) {
+  if (c.y_nnz > 0) {
+    l_spmm(c.n, c.y_nnz, c.y_rp, c.y_col, c.y_val, w.G1, Yo, w.b, alpha, beta, c.s, &c.y_grp, "k_spmm:R0T");
+    return;
+  }
   bmm(w.dY, c.N, w.maxns, w.maxm, true, 1.0, 0.0, w.b, c.s, w.flY, nullptr, "Y");
   l_scatter(c.n, c.sumns, c.invptr, c.invsub, c.invloc, c.subptr, w.Os, w.b, Yo, alpha, beta, c.s);
 }
@@ -782,7 +827,7 @@ void phase_maps(awg_ctx& c, const int64_t* rowptr, const int32_t* col, const dou
   for (int q = 0; q < c.N; ++q) c.sqoff[q + 1] = c.sqoff[q] + (long)c.ns[q] * c.ns[q];
   c.sqtot = c.sqoff[c.N];
   c.d_sqoff.upload(c.sqoff, s);
-  spmm_groups((int)c.n, c.nnz, c.rowptr, c.col, c.val, c.sgrp, s);   // on the validated pattern
+  spmm_groups_defer((int)c.n, c.nnz, c.rowptr, c.col, c.val, c.sgrp);   // on the validated pattern
 }
 
 // Batched eigenvalues below a threshold of dense symmetric blocks (destroys
@@ -1467,9 +1512,30 @@ int balanced_chunk(int total, int cap) {
   return std::min(cap, b + (b & 1));
 }
 
+// CSR forms of [A | V_-] and R0^T for the multi-column products (built once
+// V^s and Y^s are known)
+void build_prolongations(awg_ctx& c) {
+  hipStream_t s = c.s;
+  if (c.LV.cols > 0) {
+    c.aug_nnz = l_aug_csr((int)c.n, c.rowptr, c.col, c.val, c.invptr, c.invsub, c.invloc, c.subptr, c.LV.d_eoff,
+                          c.LV.d_coff, c.V, c.aug_rp, c.aug_col, c.aug_val, s);
+    spmm_groups_defer((int)c.n, c.aug_nnz, c.aug_rp, c.aug_col, c.aug_val, c.aug_grp);
+    c.vt_nnz = l_aug_csr_t(c.N, c.LV.cols, c.subptr, c.subidx, c.LV.d_eoff, c.LV.d_coff, c.V, c.vt_rp, c.vt_col,
+                           c.vt_val, s);
+  }
+  if (c.n0 > 0) {
+    c.y_nnz = l_aug_csr((int)c.n, nullptr, nullptr, nullptr, c.invptr, c.invsub, c.invloc, c.subptr, c.LY.d_eoff,
+                        c.LY.d_coff, c.Y, c.y_rp, c.y_col, c.y_val, s);
+    spmm_groups_defer((int)c.n, c.y_nnz, c.y_rp, c.y_col, c.y_val, c.y_grp);
+    c.yt_nnz = l_aug_csr_t(c.N, c.LY.cols, c.subptr, c.subidx, c.LY.d_eoff, c.LY.d_coff, c.Y, c.yt_rp, c.yt_col,
+                           c.yt_val, s);
+  }
+}
+
 // E0 = R0 A_+ R0^T and its inverse (Theorem on H^NN_hyb, Section 3.4)
 void phase_coarse0(awg_ctx& c) {
   PhaseTimer t(c, "coarse0");
+  build_prolongations(c);
   if (c.n0 == 0) return;
   hipStream_t s = c.s;
   const int b = balanced_chunk(c.n0, 2048);
@@ -1516,7 +1582,7 @@ void phase_W(awg_ctx& c) {
   build_ws(c, w, b);
   DBuf<double> X, Pm, Q;
   X.alloc((long)c.n * b);
-  Pm.alloc((long)c.n * b);
+  Pm.alloc(((long)c.n + c.LV.cols) * b);     // input of A_+ products (coefficient rows below)
   Q.alloc((long)c.n * b);
   double* dots = w.dots.p;
   DBuf<double> alpha_d;
@@ -1524,6 +1590,7 @@ void phase_W(awg_ctx& c) {
   std::vector<double> bn(b), rz(b), alpha(b), beta(b);
   std::vector<char> active(b);
   int itmax = 0;
+  double colits = 0.0;
   auto coldot = [&](const double* A, const double* B) {
     l_coldot(c.n, b, A, B, w.dotpart, dots, s);
     std::vector<double> h(b);
@@ -1566,7 +1633,10 @@ void phase_W(awg_ctx& c) {
       AWG_HIP(hipStreamSynchronize(s));
       int nact = 0;
       for (int j = 0; j < b; ++j) {
-        if (active[j] && std::sqrt(h[j]) <= c.opt.w_rtol * bn[j]) active[j] = 0;
+        if (active[j] && std::sqrt(h[j]) <= c.opt.w_rtol * bn[j]) {
+          active[j] = 0;
+          colits += it + 1;
+        }
         nact += active[j];
       }
       if (nact == 0) { ++it; break; }
@@ -1594,6 +1664,7 @@ void phase_W(awg_ctx& c) {
     AWG_LAUNCH_CHECK();
   }
   c.w_iters = itmax;
+  c.w_iters_mean = colits / std::max(1, c.nminus);
 }
 
 // E_W = W^T A W and its inverse (Definition of H3,ad, Section 4.3)
@@ -1882,7 +1953,7 @@ std::string stats_json(const awg_ctx& c) {
     o << "]";
   };
   o << "{\"n\":" << c.n << ",\"nnz\":" << c.nnz << ",\"N\":" << c.N << ",\"sum_ns\":" << c.sumns
-    << ",\"n_minus\":" << c.nminus << ",\"n0\":" << c.n0 << ",\"w_iters\":" << c.w_iters
+    << ",\"n_minus\":" << c.nminus << ",\"n0\":" << c.n0 << ",\"w_iters\":" << c.w_iters << ",\"w_iters_mean\":" << c.w_iters_mean
     << ",\"local_prec\":" << c.opt.local_prec << ",\"tau\":" << c.opt.tau << ",";
   arr("k_s", c.ks);
   o << ",";

@@ -19,6 +19,15 @@ void l_extract(int N, const long* sub_ptr, const int* sub_idx, const int* rowptr
 // Groups of up to 4 consecutive rows stored over the union of their column
 // patterns (zeros where a row has no entry), for the grouped SpMM kernel
 struct SpmmGroups {
+  // pattern to build the groups from when they are first needed (the host
+  // analysis of every row costs tens of ms on large matrices and is skipped
+  // when the autotuner's choice for a shape is already another variant)
+  bool pending = false;
+  int n = 0;
+  long nnz = 0;
+  const int* rowptr = nullptr;
+  const int* col = nullptr;
+  const double* val = nullptr;
   int ng = 0;
   DBuf<int> start;     // first row of each group, n at the end
   DBuf<int> uptr;      // offsets of the union patterns in ucol (ng + 1)
@@ -28,14 +37,18 @@ struct SpmmGroups {
 };
 // multi-column vectors are row-major (b contiguous values per row); grp
 // (optional): row groups from spmm_groups, offered to the autotuner
+// (the CSR may have more columns than rows: X then has one row per column);
+// label: name under which the kernel timer records the launch
 void l_spmm(int n, long nnz, const int* rowptr, const int* col, const double* val, const double* X, double* Y, int b,
-            double alpha, double beta, hipStream_t s, const SpmmGroups* grp = nullptr);
+            double alpha, double beta, hipStream_t s, const SpmmGroups* grp = nullptr, const char* label = nullptr);
 // builds the groups of a validated CSR pattern (columns sorted per row): a
 // group grows while its union pattern stays within 1.4 times its longest
 // row; returns the number of groups, or 0 (g left empty) when grouping would
 // not cut the row count by a quarter
 int spmm_groups(int n, long nnz, const int* rowptr, const int* col, const double* val, SpmmGroups& g,
                 hipStream_t s);
+// defer spmm_groups on this pattern until a product needs the groups
+void spmm_groups_defer(int n, long nnz, const int* rowptr, const int* col, const double* val, SpmmGroups& g);
 void l_gather(long tot, const int* sub_idx, const double* X, int b, double* Xs, hipStream_t s);
 // the same rows rounded to FP32 (the operand of the FP32 local products)
 void l_gather_f32(long tot, const int* sub_idx, const double* X, int b, float* Xs, hipStream_t s);
@@ -43,11 +56,22 @@ void l_scatter(int n, long tot, const int* inv_ptr, const int* inv_sub, const in
                const double* Zs, int b, double* Y, double alpha, double beta, hipStream_t s);
 // part: max(DOT_CHUNKS_H * b, DOT1_BLOCKS) scratch doubles
 constexpr int DOT_CHUNKS_H = 128;
-constexpr int DOT1_BLOCKS = 512;   // blocks (and partial sums) of the one-column kernels
+constexpr int DOT1_BLOCKS = 2048;  // blocks (and partial sums) of the one-column kernels
 void l_coldot(int n, int b, const double* X, const double* Y, double* part, double* out, hipStream_t s);
 // one column: q = A p with part[k] = the k-th of DOT1_BLOCKS partial sums of p^T q
 void l_spmv_dot(int n, long nnz, const int* rowptr, const int* col, const double* val, const double* p, double* q,
                 double* part, hipStream_t s);
+// CSR (arp, acol, aval) of [A | L] (rowptr != NULL: columns of L shifted by
+// n) or of L alone: L the n x sum_s k_s prolongation of the per-subdomain
+// n_s x k_s column-major blocks B + eoff[s] (k_s = coff[s+1] - coff[s]),
+// column coff[s] + j = R^sT B^s e_j; returns its number of entries
+long l_aug_csr(int n, const int* rowptr, const int* col, const double* val, const int* inv_ptr, const int* inv_sub,
+               const int* inv_loc, const long* sub_ptr, const long* eoff, const long* coff, const double* B,
+               DBuf<int>& arp, DBuf<int>& acol, DBuf<double>& aval, hipStream_t s);
+// CSR (rp, tcol, tval) of L^T (ncols = sum_s k_s rows, n columns) for the
+// same prolongation; returns its number of entries
+long l_aug_csr_t(int N, long ncols, const long* sub_ptr, const int* sub_idx, const long* eoff, const long* coff,
+                 const double* B, DBuf<int>& rp, DBuf<int>& tcol, DBuf<double>& tval, hipStream_t s);
 // r = b - A x in compensated (double-double) arithmetic, rounded once to FP64
 void l_resid_dd(int n, long nnz, const int* rowptr, const int* col, const double* val, const double* x,
                 const double* b, double* r, hipStream_t s);

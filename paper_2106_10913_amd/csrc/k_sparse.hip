@@ -267,6 +267,70 @@ __global__ __launch_bounds__(256) void k_resid_dd(int n, const int* rowptr, cons
   }
 }
 
+// CSR of [A | L] (rowptr != NULL) or of L alone, where L is the n x sum_s k_s
+// prolongation of per-subdomain bases: column coff[s] + j of L is
+// R^sT B^s e_j (B^s the n_s x k_s column-major block at B + eoff[s]).  Row i
+// holds A's entries of row i, then for every (s, l) holding i (inverse map,
+// ascending s) the entries B^s[l, j], j < k_s, at columns colbase + coff[s] + j
+// (colbase = n with A, 0 without): the columns stay ascending.
+__global__ void k_aug_count(int n, const int* rowptr, const int* inv_ptr, const int* inv_sub, const long* coff,
+                            int* cnt) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int c = rowptr ? rowptr[i + 1] - rowptr[i] : 0;
+  for (int q = inv_ptr[i]; q < inv_ptr[i + 1]; ++q) {
+    const int sd = inv_sub[q];
+    c += (int)(coff[sd + 1] - coff[sd]);
+  }
+  cnt[i] = c;
+}
+
+__global__ void k_aug_fill(int n, const int* rowptr, const int* col, const double* val, const int* inv_ptr,
+                           const int* inv_sub, const int* inv_loc, const long* sub_ptr, const long* eoff,
+                           const long* coff, const double* B, int colbase, const int* arp, int* acol, double* aval) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int o = arp[i];
+  if (rowptr)
+    for (int p = rowptr[i]; p < rowptr[i + 1]; ++p, ++o) {
+      acol[o] = col[p];
+      aval[o] = val[p];
+    }
+  for (int q = inv_ptr[i]; q < inv_ptr[i + 1]; ++q) {
+    const int sd = inv_sub[q];
+    const long ns = sub_ptr[sd + 1] - sub_ptr[sd];
+    const double* bp = B + eoff[sd] + inv_loc[q];
+    for (long j = coff[sd]; j < coff[sd + 1]; ++j, ++o) {
+      acol[o] = colbase + (int)j;
+      aval[o] = bp[(j - coff[sd]) * ns];
+    }
+  }
+}
+
+// CSR of L^T (sum_s k_s x n) for the prolongation L above: row coff[s] + j
+// holds the n_s entries B^s[l, j] at columns sub_idx[sub_ptr[s] + l]
+// (ascending, the index lists being sorted)
+__global__ void k_augt_count(int N, const long* sub_ptr, const long* coff, int* cnt) {
+  const int sd = blockIdx.x * blockDim.x + threadIdx.x;
+  if (sd >= N) return;
+  for (long j = coff[sd]; j < coff[sd + 1]; ++j) cnt[j] = (int)(sub_ptr[sd + 1] - sub_ptr[sd]);
+}
+
+__global__ void k_augt_fill(const long* sub_ptr, const int* sub_idx, const long* eoff, const long* coff,
+                            const double* B, const int* rp, int* tcol, double* tval) {
+  const int sd = blockIdx.x;
+  const long a = sub_ptr[sd];
+  const int ns = (int)(sub_ptr[sd + 1] - a);
+  for (long j = coff[sd]; j < coff[sd + 1]; ++j) {
+    const int o = rp[j];
+    const double* bp = B + eoff[sd] + (j - coff[sd]) * ns;
+    for (int l = threadIdx.x; l < ns; l += blockDim.x) {
+      tcol[o + l] = sub_idx[a + l];
+      tval[o + l] = bp[l];
+    }
+  }
+}
+
 // part[blockIdx.x] = sum over a grid-stride share of the rows of x_i y_i
 // (one-column dot product, first pass; the order is fixed by the launch shape)
 __global__ __launch_bounds__(256) void k_dot1_part(int n, const double* x, const double* y, double* part) {
@@ -1039,8 +1103,28 @@ int spmm_groups(int n, long nnz, const int* rowptr, const int* col, const double
   return ng;
 }
 
+void spmm_groups_defer(int n, long nnz, const int* rowptr, const int* col, const double* val, SpmmGroups& g) {
+  g.ng = 0;
+  g.pending = true;
+  g.n = n;
+  g.nnz = nnz;
+  g.rowptr = rowptr;
+  g.col = col;
+  g.val = val;
+}
+
+// builds deferred groups (the groups are a cache of the pattern: building
+// them does not change what the owner holds, hence the const interface)
+static void ensure_groups(const SpmmGroups* grp, hipStream_t s) {
+  if (!grp || !grp->pending) return;
+  SpmmGroups* g = const_cast<SpmmGroups*>(grp);
+  g->pending = false;
+  spmm_groups(g->n, g->nnz, g->rowptr, g->col, g->val, *g, s);
+}
+
 void spmm_variant(int v, int n, const int* rowptr, const int* col, const double* val, const double* X, double* Y,
                   int b, double alpha, double beta, hipStream_t s, const SpmmGroups* grp) {
+  if (v >= 9) ensure_groups(grp, s);
   auto tiled = [&](auto kern, int slab) {
     const int rpb = 4 * (64 / slab);
     const int nrb = (int)cdiv(n, rpb);
@@ -1086,13 +1170,13 @@ void spmm_variant(int v, int n, const int* rowptr, const int* col, const double*
 // timing launches then only overwrite Y with the same values), else cached or 0.
 int spmm_choice(int n, long nnz, const int* rowptr, const int* col, const double* val, const double* X, double* Y,
                 int b, double alpha, double beta, hipStream_t s, const SpmmGroups* grp) {
-  const int ng = grp ? grp->ng : 0;
   const std::string key = "spmm:n=" + std::to_string(n) + ":nnz=" + std::to_string(nnz) + ":b=" + std::to_string(b) +
-                          ":groups=" + std::to_string(ng);
+                          ":grouped=" + std::to_string(grp != nullptr);
   const int known = tune_lookup(key);
   if (known >= 0) return known;
   if (beta != 0.0) return 0;
-  const int nv = ng > 0 ? SPMM_VARIANTS : SPMM_VARIANTS - 2;
+  ensure_groups(grp, s);
+  const int nv = grp && grp->ng > 0 ? SPMM_VARIANTS : SPMM_VARIANTS - 2;
   return tune_pick(key, nv, [&](int v) { spmm_variant(v, n, rowptr, col, val, X, Y, b, alpha, beta, s, grp); }, s);
 }
 
@@ -1140,6 +1224,44 @@ void l_resid_dd(int n, long nnz, const int* rowptr, const int* col, const double
   AWG_LAUNCH_CHECK();
 }
 
+long l_aug_csr(int n, const int* rowptr, const int* col, const double* val, const int* inv_ptr, const int* inv_sub,
+               const int* inv_loc, const long* sub_ptr, const long* eoff, const long* coff, const double* B,
+               DBuf<int>& arp, DBuf<int>& acol, DBuf<double>& aval, hipStream_t s) {
+  DBuf<int> cnt;
+  cnt.alloc(n);
+  arp.alloc(n + 1);
+  hipLaunchKernelGGL(k_aug_count, dim3(grid1(n)), dim3(256), 0, s, n, rowptr, inv_ptr, inv_sub, coff, cnt.p);
+  AWG_LAUNCH_CHECK();
+  l_scan(n, cnt, arp, s);
+  int tot = 0;
+  AWG_HIP(hipMemcpyAsync(&tot, arp.p + n, sizeof(int), hipMemcpyDeviceToHost, s));
+  AWG_HIP(hipStreamSynchronize(s));
+  acol.alloc(std::max(1, tot));
+  aval.alloc(std::max(1, tot));
+  hipLaunchKernelGGL(k_aug_fill, dim3(grid1(n)), dim3(256), 0, s, n, rowptr, col, val, inv_ptr, inv_sub, inv_loc,
+                     sub_ptr, eoff, coff, B, rowptr ? n : 0, arp.p, acol.p, aval.p);
+  AWG_LAUNCH_CHECK();
+  return tot;
+}
+
+long l_aug_csr_t(int N, long ncols, const long* sub_ptr, const int* sub_idx, const long* eoff, const long* coff,
+                 const double* B, DBuf<int>& rp, DBuf<int>& tcol, DBuf<double>& tval, hipStream_t s) {
+  DBuf<int> cnt;
+  cnt.alloc(std::max(1L, ncols));
+  rp.alloc(ncols + 1);
+  hipLaunchKernelGGL(k_augt_count, dim3(cdiv(N, 256)), dim3(256), 0, s, N, sub_ptr, coff, cnt.p);
+  AWG_LAUNCH_CHECK();
+  l_scan((int)ncols, cnt, rp, s);
+  int tot = 0;
+  AWG_HIP(hipMemcpyAsync(&tot, rp.p + ncols, sizeof(int), hipMemcpyDeviceToHost, s));
+  AWG_HIP(hipStreamSynchronize(s));
+  tcol.alloc(std::max(1, tot));
+  tval.alloc(std::max(1, tot));
+  hipLaunchKernelGGL(k_augt_fill, dim3(N), dim3(256), 0, s, sub_ptr, sub_idx, eoff, coff, B, rp.p, tcol.p, tval.p);
+  AWG_LAUNCH_CHECK();
+  return tot;
+}
+
 void l_dot1_part(int n, const double* x, const double* y, double* part, hipStream_t s) {
   KScope kt("k_dot1", s, 16.0 * n, 2.0 * n);
   hipLaunchKernelGGL(k_dot1_part, dim3(DOT1_BLOCKS), dim3(256), 0, s, n, x, y, part);
@@ -1147,10 +1269,10 @@ void l_dot1_part(int n, const double* x, const double* y, double* part, hipStrea
 }
 
 void l_spmm(int n, long nnz, const int* rowptr, const int* col, const double* val, const double* X, double* Y, int b,
-            double alpha, double beta, hipStream_t s, const SpmmGroups* grp) {
+            double alpha, double beta, hipStream_t s, const SpmmGroups* grp, const char* label) {
   if (n == 0 || b == 0) return;
   const int v = b == 1 ? 0 : spmm_choice(n, nnz, rowptr, col, val, X, Y, b, alpha, beta, s, grp);
-  KScope kt(b == 1 ? "k_spmv" : "k_spmm_rm", s,
+  KScope kt(b == 1 ? "k_spmv" : (label ? label : "k_spmm_rm"), s,
             12.0 * nnz + 4.0 * (n + 1) + 16.0 * n * (double)b + (beta != 0.0 ? 8.0 * n * (double)b : 0.0),
             2.0 * nnz * (double)b);
   if (b == 1) {

@@ -42,31 +42,57 @@ def run_gpu(gpu_lib, w):
     return st, info, ms
 
 
-def check_against(w, st, info, n0, n_minus, kappa_printed):
+ROWS_PATH = os.path.join(os.path.dirname(__file__), "golden", "paper_rows_oracle.json")
+ROWS = json.load(open(ROWS_PATH)) if os.path.exists(ROWS_PATH) else {}
+
+
+def check_against(w, st, info, n0, n_minus, kappa_printed, ref=None):
+    """Integers exactly; iterations within 1 and kappa within 1 % of the
+    oracle's with the same stopping test (ref: the oracle's stored results,
+    written by tests/golden/make_paper_rows.py; else the oracle is run)."""
     assert st["n0"] == n0 and st["n_minus"] == n_minus
     assert info["converged"] == 1
     kappa = info["lmax_est"] / info["lmin_est"]
-    ost = O.setup(w.A, w.subs, w.tau)
-    ref = O.pcg(w.A, w.b, ost.apply, tol=TOL, maxit=2000)
-    lmin, lmax = ref.lanczos_extremes()
-    assert abs(info["iters"] - ref.iters) <= 1, (info["iters"], ref.iters)
-    assert abs(kappa - lmax / lmin) <= 0.01 * lmax / lmin, (kappa, lmax / lmin)
+    if ref is None:
+        ost = O.setup(w.A, w.subs, w.tau)
+        r = O.pcg(w.A, w.b, ost.apply, tol=TOL, maxit=2000)
+        lmin, lmax = r.lanczos_extremes()
+        ref = {"iters": r.iters, "kappa": lmax / lmin}
+    assert abs(info["iters"] - ref["iters"]) <= 1, (info["iters"], ref["iters"])
+    assert abs(kappa - ref["kappa"]) <= 0.01 * ref["kappa"], (kappa, ref["kappa"])
     if kappa_printed is not None:
         assert abs(kappa - kappa_printed) <= 0.03 * kappa_printed, (kappa, kappa_printed)
     return kappa
 
 
-@pytest.mark.parametrize("case", GOLD["cases"], ids=[c["name"] for c in GOLD["cases"]])
-def test_tables_2_3_5_rows(gpu_lib, case):
+def paper_row(case):
     kw = dict(case["kwargs"])
     if "layers" in kw:
         kw["layers"] = LAYERS[kw["layers"]]
-    w = P.paper_x0(tau=case["tau"], **kw)
+    return P.paper_x0(tau=case["tau"], **kw)
+
+
+@pytest.mark.parametrize("case", GOLD["cases"], ids=[c["name"] for c in GOLD["cases"]])
+def test_tables_2_3_5_rows(gpu_lib, case):
+    w = paper_row(case)
     print(f"\n[gpu case] paper problem {case['name']} ({case['cite']})", flush=True)
     st, info, ms = run_gpu(gpu_lib, w)
     # the printed kappa comes from the paper's own stopping test (1e-10 on the
     # preconditioned norm); the oracle reproduces it with that test
-    check_against(w, st, info, case["n0"], case["n_minus"], None)
+    check_against(w, st, info, case["n0"], case["n_minus"], None, ROWS.get(case["name"]))
+
+
+@pytest.mark.parametrize("case", GOLD.get("not_reproduced", []), ids=[c["name"] for c in GOLD.get("not_reproduced", [])])
+def test_rows_the_oracle_does_not_reproduce(gpu_lib, case):
+    """A printed row the oracle does not reproduce (Table 2, nu = 0.45): the
+    library is held to the oracle's integers, iterations and kappa."""
+    if case["name"] not in ROWS:
+        pytest.skip("oracle results not stored")
+    ref = ROWS[case["name"]]
+    w = paper_row(case)
+    print(f"\n[gpu case] paper problem {case['name']} ({case['cite']}; not reproduced by the oracle)", flush=True)
+    st, info, ms = run_gpu(gpu_lib, w)
+    check_against(w, st, info, ref["n0"], ref["n_minus"], None, ref)
 
 
 def long_domain_checks(st, info):
