@@ -166,8 +166,14 @@ void gemm_batched_fixed(const GemmDesc* d_desc, const double* X, const int* idx,
                         int variant);
 // C = alpha A B + beta C with FP32 A and B (FP32 MFMA and accumulation):
 // the same products and k order as gemm_mix_batched on A rounded to FP32
+// tiles/ntiles/grid (optional): the list of a persistent launch from
+// f32_tile_list, offered to the autotuner beside the plain grid (same bits)
 void gemm_f32_batched(const GemmDescF32* d_desc, int batch, int max_m, int max_n, double alpha, double beta,
-                      hipStream_t s, double flops);
+                      hipStream_t s, double flops, const int* tiles = nullptr, int ntiles = 0, int grid = 0);
+// tile list (host) of the persistent local-product launch for batch entries
+// of sizes m x n with inner dimension k; returns its grid size
+int f32_tile_list(const std::vector<int>& m, const std::vector<int>& n, const std::vector<int>& k, int wgs_per_xcd,
+                  std::vector<int>& tiles);
 // X, idx, off (optional): the same row gather of the A operands as in
 // gemm_batched_gather
 void gemm_mix_batched(const GemmDescMix* d_desc, int batch, int max_m, int max_n, double alpha, double beta,

@@ -162,6 +162,9 @@ struct MultiWS {
   DBuf<GemmDescMix> dP32;             // FP32 local operators (b > 1)
   DBuf<float> Xs32;                   // restricted rows rounded to FP32 (b > 1, FP32 local operators)
   DBuf<GemmDescF32> dP32f;
+  DBuf<GemmDesc> dCu, dCt, dAYt;      // C u0, C^T (..), (A R0^T)^T y (precomputed A_+ R0^T, b > 1)
+  DBuf<int> tilesP32;                 // tile list of the persistent FP32 local product
+  int ntilesP32 = 0, gridP32 = 0;
   int maxk = 0, maxm = 0, maxns = 0;
   double flV = 0, flY = 0, flP = 0, flE0 = 0, flW = 0, flEW = 0;   // algorithmic flops per product
 };
@@ -181,6 +184,22 @@ struct awg_ctx {
   DBuf<int> aug_rp, aug_col, y_rp, y_col;
   DBuf<double> aug_val, y_val;
   long aug_nnz = 0, y_nnz = 0;
+  // A_+ R0^T precomputed for H2 on many columns: the extended sets
+  // N(Omega^s) (support of A R^sT), AY^s = A[N_s, Omega^s] Y^s, the CSR of
+  // [A R0^T | V_-] (n x (n0 + sum k_s)) and C = V_-^T R0^T (sum k_s x n0,
+  // column-major), so that A_+ R0^T u = [A R0^T | V_-][u; |L_-| C u] and
+  // R0 A_+ y = (A R0^T)^T y + C^T |L_-| V_-^T R y
+  bool ap_ok = false;
+  std::vector<long> h_extptr;
+  DBuf<long> extptr;
+  DBuf<int> extidx;
+  ColLayout LAY;
+  DBuf<double> AY, Cmat;
+  DBuf<int> apv_rp, apv_col;
+  DBuf<double> apv_val;
+  long apv_nnz = 0;
+  SpmmGroups apv_grp;
+  double flAY1 = 0.0;          // 2 sum_s |N_s| m_s (flops per column of the (A R0^T)^T product)
   // their restrictions V_-^T and R0 as CSR (one-column products of the PCG)
   DBuf<int> vt_rp, vt_col, yt_rp, yt_col;
   DBuf<double> vt_val, yt_val;
@@ -441,7 +460,7 @@ void build_ws(awg_ctx& c, MultiWS& w, int b) {
   w.Os.alloc(c.sumns * b);
   w.Tk.alloc(std::max<long>(1, c.LV.cols) * b);
   w.G0.alloc(std::max(1, c.n0) * (long)b);
-  w.G1.alloc(std::max(1, c.n0) * (long)b);
+  w.G1.alloc((std::max(1, c.n0) + c.LV.cols) * (long)b);   // u0 and, below, |L_-| C u0
   w.G2.alloc(std::max(1, c.n0) * (long)b);
   w.H0.alloc(std::max(1, c.nminus) * (long)b);
   w.H1.alloc(std::max(1, c.nminus) * (long)b);
@@ -492,6 +511,15 @@ void build_ws(awg_ctx& c, MultiWS& w, int b) {
       pf[q] = GemmDescF32{w.Xs32.p + so, c.P32.p + c.sqoff[q], w.Os.p + so, b, nsq, nsq, b, nsq, b};
     }
     w.dP32f.upload(pf, s);
+    // persistent, size-bucketed launch of the local product: two 512-thread
+    // workgroups per CU, tiles dealt to the XCDs by subdomain
+    int dev = 0, cus = 0;
+    AWG_HIP(hipGetDevice(&dev));
+    AWG_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    std::vector<int> tl;
+    w.gridP32 = f32_tile_list(std::vector<int>(c.N, b), c.ns, c.ns, std::max(1, 2 * cus / 8), tl);
+    w.ntilesP32 = (int)tl.size();
+    w.tilesP32.upload(tl, s);
   }
   const int n0 = std::max(1, c.n0), nm = std::max(1, c.nminus);
   w.flE0 = 2.0 * c.n0 * (double)c.n0 * b;
@@ -503,6 +531,17 @@ void build_ws(awg_ctx& c, MultiWS& w, int b) {
   gemm_upload(w.dWt, {mk(w.R, c.W, nm, w.H0, c.nminus, c.n, true, b)}, s);
   gemm_upload(w.dEW, {mk(w.H0, c.EWinv, nm, w.H1, c.nminus, c.nminus, false, b)}, s);
   gemm_upload(w.dW, {mk(w.H1, c.W, nm, w.Z, c.n, c.nminus, false, b)}, s);
+  if (c.ap_ok && b > 1) {
+    const int nk = (int)c.LV.cols;
+    gemm_upload(w.dCu, {mk(w.G1, c.Cmat, nk, w.G1.p + (long)c.n0 * b, nk, c.n0, true, b)}, s);
+    gemm_upload(w.dCt, {mk(w.Tk, c.Cmat, nk, w.G0, c.n0, nk, false, b)}, s);
+    std::vector<GemmDesc> ay(c.N);
+    for (int q = 0; q < c.N; ++q) {
+      const int ne = (int)(c.h_extptr[q + 1] - c.h_extptr[q]);
+      ay[q] = mk(w.Xs, c.AY.p + c.LAY.eoff[q], ne, w.G0.p + c.LY.coff[q] * b, c.ms[q], ne, false, b);
+    }
+    gemm_upload(w.dAYt, ay, s);
+  }
   if (c.opt.coarse2 == AWG_COARSE2_HYB && c.nminus > 0) {
     w.R3.alloc(c.n * (long)b);
     w.H2b.alloc(std::max(1, c.nminus) * (long)b);
@@ -628,7 +667,7 @@ void op_hnn(awg_ctx& c, MultiWS& w, const double* X, double* Yo, bool f32) {
         gemm_mix_batched(w.dP32, c.N, w.b, w.maxns, 1.0, 0.0, c.s, w.flP, X, c.subidx.p, c.subptr.p);
       } else {
         l_gather_f32(c.sumns, c.subidx, X, w.b, w.Xs32, c.s);
-        gemm_f32_batched(w.dP32f, c.N, w.b, w.maxns, 1.0, 0.0, c.s, w.flP);
+        gemm_f32_batched(w.dP32f, c.N, w.b, w.maxns, 1.0, 0.0, c.s, w.flP, w.tilesP32, w.ntilesP32, w.gridP32);
       }
     };
     const std::string key = "restrict:P32:b=" + std::to_string(w.b) + ":sumns=" + std::to_string(c.sumns) +
@@ -671,6 +710,30 @@ void op_h2(awg_ctx& c, MultiWS& w, bool f32, const double* rin = nullptr) {
   }
   op_r0(c, w, r);                                                        // G0 = R0 r
   bmm(w.dE0a, 1, c.n0, c.n0, false, 1.0, 0.0, b, c.s, w.flE0, nullptr, "E0");           // G1 = u0
+  if (b > 1 && c.ap_ok) {
+    // with A_+ R0^T precomputed: two coarse-sized GEMMs and one sparse
+    // product with small sources in place of R0^T, A_+ and R0 on n x b blocks
+    const long nk = c.LV.cols;
+    const double flC = 2.0 * nk * c.n0 * b;
+    double* tail = w.G1.p + (long)c.n0 * b;
+    bmm(w.dCu, 1, (int)nk, c.n0, true, 1.0, 0.0, b, c.s, flC, nullptr, "Cu");         // C u0 below u0
+    hipLaunchKernelGGL(k_scale_rows, dim3(cdiv(nk * b, 256)), dim3(256), 0, c.s, tail, c.lamV.p, nk, b);
+    AWG_LAUNCH_CHECK();
+    l_spmm(c.n, c.apv_nnz, c.apv_rp, c.apv_col, c.apv_val, w.G1, w.T2, b, 1.0, 0.0, c.s, &c.apv_grp,
+           "k_spmm:AR0T");                                                             // T2 = A_+ R0^T u0
+    l_colaxpby(c.n, b, r, nullptr, w.T2, nullptr, 1.0, -1.0, c.s);                    // T2 = r - T2
+    op_hnn(c, w, w.T2, w.Z, f32);                                                      // Z = y
+    gemm_batched_gather(w.dAYt, w.Z, c.extidx, c.extptr, c.N, b, w.maxm, false, 1.0, 0.0, c.s, c.flAY1 * b,
+                        "AYt");                                                        // G0 = (A R0^T)^T y
+    bmm_restricted(c, w, w.dVt, w.Z, w.maxk, w.maxns, w.flV, "Vt");                  // Tk = V^T R y
+    hipLaunchKernelGGL(k_scale_rows, dim3(cdiv(nk * b, 256)), dim3(256), 0, c.s, w.Tk.p, c.lamV.p, nk, b);
+    AWG_LAUNCH_CHECK();
+    bmm(w.dCt, 1, c.n0, (int)nk, false, 1.0, 1.0, b, c.s, flC, nullptr, "Ct");       // G0 += C^T |L| V^T R y
+    bmm(w.dE0b, 1, c.n0, c.n0, false, 1.0, 0.0, b, c.s, w.flE0, nullptr, "E0");      // G2 = v
+    l_colaxpby(c.n0, b, w.G2, nullptr, w.G1, nullptr, -1.0, 1.0, c.s);               // G1 = u0 - v
+    op_r0t(c, w, w.Z, 1.0);                                                            // Z += R0^T (u0 - v)
+    return;
+  }
   op_r0t(c, w, w.T1, 0.0);                                               // T1 = R0^T u0
   op_aplus(c, w, w.T1, w.T2);                                            // T2 = A_+ R0^T u0
   l_colaxpby(c.n, b, r, nullptr, w.T2, nullptr, 1.0, -1.0, c.s);        // T2 = r - T2
@@ -1018,14 +1081,14 @@ int geneo_subspace(awg_ctx& c, const double* MB, double* MA) {
   int it = 0, nconv = 0;
   std::vector<int> hconv(N, 0), hflag(N, 0);
   for (it = 1; it <= c.opt.eig_maxit; ++it) {
-    gemm_batched(dg1, N, c.maxns, q, false, false, 1.0, 0.0, false, s, flMB);     // BX = M_B X
-    gemm_batched(dg2, N, c.maxns, q, false, false, 1.0, 0.0, false, s, flMB);     // Y = G BX
+    gemm_batched(dg1, N, c.maxns, q, false, false, 1.0, 0.0, false, s, flMB, "eigMB");   // BX = M_B X
+    gemm_batched(dg2, N, c.maxns, q, false, false, 1.0, 0.0, false, s, flMB, "eigG");    // Y = G BX
     project(dg3, dg4);                                                              // Y = Pi_B Y
     gemm_batched(dg5, N, q, q, true, false, 1.0, 0.0, false, s);                    // S0 = X^T M_B X
     gemm_batched(dg6, N, q, q, true, false, 1.0, 0.0, false, s);                    // S1 = X^T M_B T X
     l_rr_small(N, q, S0, S1, Cq, mu, flag, s);
-    gemm_batched(dg7, N, c.maxns, q, false, false, 1.0, 0.0, false, s);             // Z = X C
-    gemm_batched(dg8, N, c.maxns, q, false, false, 1.0, 0.0, false, s);             // T Z = Y C
+    gemm_batched(dg7, N, c.maxns, q, false, false, 1.0, 0.0, false, s, 0.0, "eigXC");    // Z = X C
+    gemm_batched(dg8, N, c.maxns, q, false, false, 1.0, 0.0, false, s, 0.0, "eigYC");    // T Z = Y C
     l_ritz_resid(N, c.subptr, q, Z, TZ, mu, X, res, conv, nsel, tau, window, c.opt.eig_tol, tol_far, s);
     AWG_HIP(hipMemcpyAsync(hconv.data(), conv.p, sizeof(int) * N, hipMemcpyDeviceToHost, s));
     sync(c);
@@ -1518,17 +1581,72 @@ void build_prolongations(awg_ctx& c) {
   hipStream_t s = c.s;
   if (c.LV.cols > 0) {
     c.aug_nnz = l_aug_csr((int)c.n, c.rowptr, c.col, c.val, c.invptr, c.invsub, c.invloc, c.subptr, c.LV.d_eoff,
-                          c.LV.d_coff, c.V, c.aug_rp, c.aug_col, c.aug_val, s);
+                          c.LV.d_coff, c.V, (int)c.n, c.aug_rp, c.aug_col, c.aug_val, s);
     spmm_groups_defer((int)c.n, c.aug_nnz, c.aug_rp, c.aug_col, c.aug_val, c.aug_grp);
     c.vt_nnz = l_aug_csr_t(c.N, c.LV.cols, c.subptr, c.subidx, c.LV.d_eoff, c.LV.d_coff, c.V, c.vt_rp, c.vt_col,
                            c.vt_val, s);
   }
   if (c.n0 > 0) {
     c.y_nnz = l_aug_csr((int)c.n, nullptr, nullptr, nullptr, c.invptr, c.invsub, c.invloc, c.subptr, c.LY.d_eoff,
-                        c.LY.d_coff, c.Y, c.y_rp, c.y_col, c.y_val, s);
+                        c.LY.d_coff, c.Y, 0, c.y_rp, c.y_col, c.y_val, s);
     spmm_groups_defer((int)c.n, c.y_nnz, c.y_rp, c.y_col, c.y_val, c.y_grp);
     c.yt_nnz = l_aug_csr_t(c.N, c.LY.cols, c.subptr, c.subidx, c.LY.d_eoff, c.LY.d_coff, c.Y, c.yt_rp, c.yt_col,
                            c.yt_val, s);
+  }
+  // A_+ R0^T for H2 on many columns (the bitsets of the extended sets take
+  // N n / 8 bytes while they are built)
+  c.ap_ok = false;
+  if (c.n0 > 0 && c.LV.cols > 0 && (double)c.N * (double)c.n / 8.0 <= 1.0e9) {
+    const int n = (int)c.n;
+    const long next = l_ext_sets(c.N, n, c.subptr, c.subidx, c.rowptr, c.col, c.h_extptr, c.extptr, c.extidx, s);
+    std::vector<int> ne(c.N);
+    c.flAY1 = 0.0;
+    for (int t = 0; t < c.N; ++t) {
+      ne[t] = (int)(c.h_extptr[t + 1] - c.h_extptr[t]);
+      c.flAY1 += 2.0 * ne[t] * c.ms[t];
+    }
+    c.LAY.build(ne, c.ms, s);
+    c.AY.alloc(std::max<long>(1, c.LAY.elems));
+    l_ext_ay(c.N, c.extptr, c.extidx, c.subptr, c.subidx, c.rowptr, c.col, c.val, c.Y, c.LY.d_eoff, c.LY.d_coff,
+             c.LAY.d_eoff, c.AY, s);
+    // inverse map of the extended sets, the CSR of A R0^T, then [A R0^T | V_-]
+    DBuf<int> em, einvptr, einvsub, einvloc, fill;
+    em.alloc(n);
+    em.zero(s);
+    l_mult(next, c.extidx, em, s);
+    einvptr.alloc(n + 1);
+    l_scan(n, em, einvptr, s);
+    fill.alloc(n);
+    fill.zero(s);
+    einvsub.alloc(std::max(1L, next));
+    einvloc.alloc(std::max(1L, next));
+    l_fill_inv(c.N, c.extptr, c.extidx, einvptr, fill, einvsub, einvloc, s);
+    l_sort_inv(n, einvptr, einvsub, einvloc, s);
+    DBuf<int> arp, acol;
+    DBuf<double> aval;
+    l_aug_csr(n, nullptr, nullptr, nullptr, einvptr, einvsub, einvloc, c.extptr, c.LAY.d_eoff, c.LAY.d_coff, c.AY, 0,
+              arp, acol, aval, s);
+    c.apv_nnz = l_aug_csr(n, arp, acol, aval, c.invptr, c.invsub, c.invloc, c.subptr, c.LV.d_eoff, c.LV.d_coff, c.V,
+                          c.n0, c.apv_rp, c.apv_col, c.apv_val, s);
+    spmm_groups_defer(n, c.apv_nnz, c.apv_rp, c.apv_col, c.apv_val, c.apv_grp);
+    // C = V_-^T R0^T: the rows of R0 (CSR of its transpose) applied to the dense
+    // V_-, i.e. R0 V_- (n0 x sum k_s row-major) = C column-major
+    // (in slabs of at most 256 columns of V_-)
+    const long nk = c.LV.cols, cw = std::min<long>(nk, 256);
+    DBuf<double> Vd, Cs;
+    Vd.alloc((size_t)n * cw);
+    Cs.alloc((size_t)c.n0 * cw);
+    c.Cmat.alloc((size_t)c.n0 * nk);
+    for (long c0 = 0; c0 < nk; c0 += cw) {
+      const long w = std::min(cw, nk - c0);
+      AWG_HIP(hipMemsetAsync(Vd.p, 0, sizeof(double) * n * (size_t)w, s));
+      l_lowrank_dense(n, c.invptr, c.invsub, c.invloc, c.subptr, c.LV.d_eoff, c.LV.d_coff, c.V, c0, w, Vd, s);
+      l_spmm(c.n0, c.yt_nnz, c.yt_rp, c.yt_col, c.yt_val, Vd, Cs, (int)w, 1.0, 0.0, s);
+      AWG_HIP(hipMemcpy2DAsync(c.Cmat.p + c0, sizeof(double) * nk, Cs.p, sizeof(double) * w, sizeof(double) * w,
+                               c.n0, hipMemcpyDeviceToDevice, s));
+    }
+    sync(c);
+    c.ap_ok = true;
   }
 }
 

@@ -67,7 +67,20 @@ void l_spmv_dot(int n, long nnz, const int* rowptr, const int* col, const double
 // column coff[s] + j = R^sT B^s e_j; returns its number of entries
 long l_aug_csr(int n, const int* rowptr, const int* col, const double* val, const int* inv_ptr, const int* inv_sub,
                const int* inv_loc, const long* sub_ptr, const long* eoff, const long* coff, const double* B,
-               DBuf<int>& arp, DBuf<int>& acol, DBuf<double>& aval, hipStream_t s);
+               int colbase, DBuf<int>& arp, DBuf<int>& acol, DBuf<double>& aval, hipStream_t s);
+// extended index sets N(Omega^s) = {i : A_ij != 0 for some j in Omega^s},
+// ascending, concatenated (h_ext_ptr: host copy of the offsets); returns their total size
+long l_ext_sets(int N, int n, const long* sub_ptr, const int* sub_idx, const int* rowptr, const int* col,
+                std::vector<long>& h_ext_ptr, DBuf<long>& ext_ptr, DBuf<int>& ext_idx, hipStream_t s);
+// AY^s = A[N(Omega^s), Omega^s] Y^s, |N_s| x m_s column-major blocks at AY + ay_eoff[s]
+void l_ext_ay(int N, const long* ext_ptr, const int* ext_idx, const long* sub_ptr, const int* sub_idx,
+              const int* rowptr, const int* col, const double* val, const double* Y, const long* y_eoff,
+              const long* y_coff, const long* ay_eoff, double* AY, hipStream_t s);
+// D (n x ld row-major, zero on entry) = columns c0 .. c0 + ld - 1 of the
+// dense prolongation of the blocks B + eoff[s]
+void l_lowrank_dense(int n, const int* inv_ptr, const int* inv_sub, const int* inv_loc, const long* sub_ptr,
+                     const long* eoff, const long* coff, const double* B, long c0, long ld, double* D,
+                     hipStream_t s);
 // CSR (rp, tcol, tval) of L^T (ncols = sum_s k_s rows, n columns) for the
 // same prolongation; returns its number of entries
 long l_aug_csr_t(int N, long ncols, const long* sub_ptr, const int* sub_idx, const long* eoff, const long* coff,

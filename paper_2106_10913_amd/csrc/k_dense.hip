@@ -814,10 +814,7 @@ void gemm_mix_batched(const GemmDescMix* d_desc, int batch, int max_m, int max_n
 // eight wavefronts of 64 x 32, k staged in LDS 32 deep (half the barriers per
 // flop of the mixed kernels); same MFMA sequence per output as
 // k_gemm128_mix_w8 (bit-identical to it: the k tail past K adds zero products)
-__global__ __launch_bounds__(512, 4) void k_gemm128_f32_w8(const GemmDescF32* descs, double alpha, double beta) {
-  const GemmDescF32 d = descs[blockIdx.z];
-  const int m0 = blockIdx.x * 128, n0 = blockIdx.y * 128;
-  if (m0 >= d.m || n0 >= d.n) return;
+__device__ __forceinline__ void gemm128_f32_w8_tile(const GemmDescF32& d, double alpha, double beta, int m0, int n0) {
   __shared__ float As[2][32][132];
   __shared__ float Bs[2][32][132];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -889,13 +886,90 @@ __global__ __launch_bounds__(512, 4) void k_gemm128_f32_w8(const GemmDescF32* de
       }
 }
 
+__global__ __launch_bounds__(512, 4) void k_gemm128_f32_w8(const GemmDescF32* descs, double alpha, double beta) {
+  const GemmDescF32 d = descs[blockIdx.z];
+  const int m0 = blockIdx.x * 128, n0 = blockIdx.y * 128;
+  if (m0 >= d.m || n0 >= d.n) return;
+  gemm128_f32_w8_tile(d, alpha, beta, m0, n0);
+}
+
+// Persistent form: a fixed grid whose workgroup w takes the tiles
+// tiles[w], tiles[w + G], ... (G = gridDim.x) of a list built by
+// f32_tile_list (code = batch entry << 12 | m tile << 6 | n tile, -1 =
+// padding).  The same tile computation as k_gemm128_f32_w8 (bit-identical).
+__global__ __launch_bounds__(512, 4) void k_gemm128_f32_w8_persist(const GemmDescF32* descs, double alpha,
+                                                                   double beta, const int* tiles, int ntiles) {
+  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const int code = tiles[t];
+    if (code < 0) continue;
+    const GemmDescF32 d = descs[code >> 12];
+    __syncthreads();            // the previous tile's LDS reads are done
+    gemm128_f32_w8_tile(d, alpha, beta, ((code >> 6) & 63) * 128, (code & 63) * 128);
+  }
+}
+
+// Tile list of the persistent launch: the batch entries are sized by their
+// work (tiles x k), sorted by it (size buckets, largest first) and dealt to
+// the 8 XCDs, each to the least loaded one; each XCD's workgroups (those
+// with w = x mod 8, which the hardware places on XCD x) sweep the tiles of
+// the entries dealt to it, so one entry's operands are re-read through one
+// XCD's L2.  Returns the grid size (0 and an empty list when a size does not
+// fit the tile code); tiles (host) gets the list.
+int f32_tile_list(const std::vector<int>& m, const std::vector<int>& n, const std::vector<int>& k, int wgs_per_xcd,
+                  std::vector<int>& tiles) {
+  constexpr int XCD = 8;
+  const int batch = (int)m.size();
+  tiles.clear();
+  for (int b = 0; b < batch; ++b)     // the code holds 6 bits per tile index
+    if (cdiv(m[b], 128) > 64 || cdiv(n[b], 128) > 64 || batch >= (1 << 19)) return 0;
+  std::vector<int> order(batch);
+  std::vector<double> work(batch);
+  for (int b = 0; b < batch; ++b) {
+    order[b] = b;
+    work[b] = (double)cdiv(m[b], 128) * cdiv(n[b], 128) * std::max(1, k[b]);
+  }
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work[a] > work[b]; });
+  std::vector<std::vector<int>> q(XCD);
+  std::vector<double> load(XCD, 0.0);
+  for (int b : order) {
+    const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    load[x] += work[b];
+    for (int tn = 0; tn < (int)cdiv(n[b], 128); ++tn)
+      for (int tm = 0; tm < (int)cdiv(m[b], 128); ++tm) q[x].push_back(b << 12 | tm << 6 | tn);
+  }
+  size_t rounds = 0;
+  for (auto& v : q) rounds = std::max(rounds, (v.size() + wgs_per_xcd - 1) / wgs_per_xcd);
+  const int G = XCD * wgs_per_xcd;
+  tiles.assign(rounds * G, -1);
+  for (int x = 0; x < XCD; ++x)
+    for (size_t i = 0; i < q[x].size(); ++i) {
+      const size_t r = i / wgs_per_xcd, l = i % wgs_per_xcd;
+      tiles[r * G + l * XCD + x] = q[x][i];
+    }
+  return G;
+}
+
 void gemm_f32_batched(const GemmDescF32* d_desc, int batch, int max_m, int max_n, double alpha, double beta,
-                      hipStream_t s, double flops) {
+                      hipStream_t s, double flops, const int* tiles, int ntiles, int grid) {
   if (batch <= 0 || max_m <= 0 || max_n <= 0) return;
+  auto run = [&](int v) {
+    if (v == 1)
+      hipLaunchKernelGGL(k_gemm128_f32_w8_persist, dim3(grid), dim3(512), 0, s, d_desc, alpha, beta, tiles, ntiles);
+    else
+      hipLaunchKernelGGL(k_gemm128_f32_w8, dim3(cdiv(max_m, 128), cdiv(max_n, 128), batch), dim3(512), 0, s, d_desc,
+                         alpha, beta);
+    AWG_LAUNCH_CHECK();
+  };
+  int v = 0;
+  if (tiles && ntiles > 0) {
+    const std::string key = "gemm_f32:P:m=" + std::to_string(max_m) + ":n=" + std::to_string(max_n) +
+                            ":batch=" + std::to_string(batch);
+    v = tune_lookup(key);
+    if (v < 0 && beta == 0.0) v = tune_pick(key, 2, run, s);
+    if (v < 0) v = 0;
+  }
   KScope kt("k_gemm128_f32_w8:P", s, 0.0, flops);
-  hipLaunchKernelGGL(k_gemm128_f32_w8, dim3(cdiv(max_m, 128), cdiv(max_n, 128), batch), dim3(512), 0, s, d_desc,
-                     alpha, beta);
-  AWG_LAUNCH_CHECK();
+  run(v);
 }
 
 template <class DF>

@@ -331,6 +331,117 @@ __global__ void k_augt_fill(const long* sub_ptr, const int* sub_idx, const long*
   }
 }
 
+// Extended index sets N(Omega^s) = {i : A_ij != 0 for some j in Omega^s} (the
+// support of A R^sT), as one bitset over the dofs per subdomain (words
+// 32-bit words each; A is symmetric, so row j holds the neighbours of j).
+__global__ void k_ext_mark(const long* sub_ptr, const int* sub_idx, const int* rowptr, const int* col, long words,
+                           unsigned* bits) {
+  const int sd = blockIdx.x;
+  unsigned* b = bits + (long)sd * words;
+  for (long e = sub_ptr[sd] + threadIdx.x; e < sub_ptr[sd + 1]; e += blockDim.x) {
+    const int j = sub_idx[e];
+    for (int p = rowptr[j]; p < rowptr[j + 1]; ++p) {
+      const int i = col[p];
+      atomicOr(b + (i >> 5), 1u << (i & 31));
+    }
+  }
+}
+
+// |N(Omega^s)| (mode 0) or the sorted list at ext_idx + ext_ptr[s] (mode 1):
+// each thread a contiguous range of words, a prefix over the threads in
+// order, so the list comes out ascending
+__global__ __launch_bounds__(256) void k_ext_list(long words, const unsigned* bits, int mode, int* cnt,
+                                                  const long* ext_ptr, int* ext_idx) {
+  __shared__ int pre[257];
+  const int sd = blockIdx.x;
+  const unsigned* b = bits + (long)sd * words;
+  const long chunk = (words + 255) / 256;
+  const long w0 = min(words, (long)threadIdx.x * chunk), w1 = min(words, w0 + chunk);
+  int c = 0;
+  for (long w = w0; w < w1; ++w) c += __popc(b[w]);
+  pre[threadIdx.x + 1] = c;
+  if (threadIdx.x == 0) pre[0] = 0;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int t = 1; t <= 256; ++t) pre[t] += pre[t - 1];
+  __syncthreads();
+  if (mode == 0) {
+    if (threadIdx.x == 0) cnt[sd] = pre[256];
+    return;
+  }
+  int o = pre[threadIdx.x];
+  int* out = ext_idx + ext_ptr[sd];
+  for (long w = w0; w < w1; ++w) {
+    unsigned v = b[w];
+    while (v) {
+      const int bit = __ffs(v) - 1;
+      out[o++] = (int)(w * 32 + bit);
+      v &= v - 1;
+    }
+  }
+}
+
+// AY^s = A[N(Omega^s), Omega^s] Y^s (|N_s| x m_s, column-major at ay + ay_eoff[s]):
+// row e of the block is sum over the nonzeros A_ij of row i = N(Omega^s)[e]
+// with j in Omega^s (CSR order) of A_ij Y^s[l(j), :], l(j) found by bisection
+// in the sorted list of Omega^s
+__global__ __launch_bounds__(256) void k_ext_ay(const long* ext_ptr, const int* ext_idx, const long* sub_ptr,
+                                                const int* sub_idx, const int* rowptr, const int* col,
+                                                const double* val, const double* Y, const long* y_eoff,
+                                                const long* y_coff, const long* ay_eoff, double* AY) {
+  const int sd = blockIdx.x;
+  const long a = sub_ptr[sd];
+  const int ns = (int)(sub_ptr[sd + 1] - a);
+  const long e0 = ext_ptr[sd];
+  const int ne = (int)(ext_ptr[sd + 1] - e0);
+  const int m = (int)(y_coff[sd + 1] - y_coff[sd]);
+  const double* Ys = Y + y_eoff[sd];
+  double* AYs = AY + ay_eoff[sd];
+  for (int e = threadIdx.x; e < ne; e += blockDim.x) {
+    const int i = ext_idx[e0 + e];
+    for (int j0 = 0; j0 < m; j0 += 8) {
+      double acc[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc[u] = 0.0;
+      for (int p = rowptr[i]; p < rowptr[i + 1]; ++p) {
+        const int j = col[p];
+        int lo = 0, hi = ns - 1, l = -1;
+        while (lo <= hi) {
+          const int mid = (lo + hi) >> 1;
+          const int v = sub_idx[a + mid];
+          if (v == j) { l = mid; break; }
+          if (v < j) lo = mid + 1; else hi = mid - 1;
+        }
+        if (l < 0) continue;
+        const double aij = val[p];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          if (j0 + u < m) acc[u] += aij * Ys[l + (long)(j0 + u) * ns];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (j0 + u < m) AYs[e + (long)(j0 + u) * ne] = acc[u];
+    }
+  }
+}
+
+// columns c0 .. c0 + ld - 1 of the dense row-major copy of a per-subdomain
+// low-rank prolongation (the rows of every V^s at the columns coff[s] ..),
+// as an n x ld row-major block; D must be zero on entry
+__global__ void k_lowrank_dense(int n, const int* inv_ptr, const int* inv_sub, const int* inv_loc,
+                                const long* sub_ptr, const long* eoff, const long* coff, const double* B, long c0,
+                                long ld, double* D) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int q = inv_ptr[i]; q < inv_ptr[i + 1]; ++q) {
+    const int sd = inv_sub[q];
+    const long ns = sub_ptr[sd + 1] - sub_ptr[sd];
+    const double* bp = B + eoff[sd] + inv_loc[q];
+    const long j0 = max(coff[sd], c0), j1 = min(coff[sd + 1], c0 + ld);
+    for (long j = j0; j < j1; ++j) D[(long)i * ld + (j - c0)] = bp[(j - coff[sd]) * ns];
+  }
+}
+
 // part[blockIdx.x] = sum over a grid-stride share of the rows of x_i y_i
 // (one-column dot product, first pass; the order is fixed by the launch shape)
 __global__ __launch_bounds__(256) void k_dot1_part(int n, const double* x, const double* y, double* part) {
@@ -1174,10 +1285,18 @@ int spmm_choice(int n, long nnz, const int* rowptr, const int* col, const double
                           ":grouped=" + std::to_string(grp != nullptr);
   const int known = tune_lookup(key);
   if (known >= 0) return known;
-  if (beta != 0.0) return 0;
   ensure_groups(grp, s);
   const int nv = grp && grp->ng > 0 ? SPMM_VARIANTS : SPMM_VARIANTS - 2;
-  return tune_pick(key, nv, [&](int v) { spmm_variant(v, n, rowptr, col, val, X, Y, b, alpha, beta, s, grp); }, s);
+  // a product that accumulates (beta != 0) is measured into a scratch output,
+  // so the trial launches leave Y as it was (the variants differ only in the
+  // order of the rows and columns they take, not in the final write)
+  DBuf<double> tmp;
+  double* Yt = Y;
+  if (beta != 0.0) {
+    tmp.alloc((size_t)n * b);
+    Yt = tmp.p;
+  }
+  return tune_pick(key, nv, [&](int v) { spmm_variant(v, n, rowptr, col, val, X, Yt, b, alpha, 0.0, s, grp); }, s);
 }
 
 // lanes per row of the one-column product: the power of two at or above the
@@ -1226,7 +1345,7 @@ void l_resid_dd(int n, long nnz, const int* rowptr, const int* col, const double
 
 long l_aug_csr(int n, const int* rowptr, const int* col, const double* val, const int* inv_ptr, const int* inv_sub,
                const int* inv_loc, const long* sub_ptr, const long* eoff, const long* coff, const double* B,
-               DBuf<int>& arp, DBuf<int>& acol, DBuf<double>& aval, hipStream_t s) {
+               int colbase, DBuf<int>& arp, DBuf<int>& acol, DBuf<double>& aval, hipStream_t s) {
   DBuf<int> cnt;
   cnt.alloc(n);
   arp.alloc(n + 1);
@@ -1239,7 +1358,7 @@ long l_aug_csr(int n, const int* rowptr, const int* col, const double* val, cons
   acol.alloc(std::max(1, tot));
   aval.alloc(std::max(1, tot));
   hipLaunchKernelGGL(k_aug_fill, dim3(grid1(n)), dim3(256), 0, s, n, rowptr, col, val, inv_ptr, inv_sub, inv_loc,
-                     sub_ptr, eoff, coff, B, rowptr ? n : 0, arp.p, acol.p, aval.p);
+                     sub_ptr, eoff, coff, B, colbase, arp.p, acol.p, aval.p);
   AWG_LAUNCH_CHECK();
   return tot;
 }
@@ -1260,6 +1379,45 @@ long l_aug_csr_t(int N, long ncols, const long* sub_ptr, const int* sub_idx, con
   hipLaunchKernelGGL(k_augt_fill, dim3(N), dim3(256), 0, s, sub_ptr, sub_idx, eoff, coff, B, rp.p, tcol.p, tval.p);
   AWG_LAUNCH_CHECK();
   return tot;
+}
+
+long l_ext_sets(int N, int n, const long* sub_ptr, const int* sub_idx, const int* rowptr, const int* col,
+                std::vector<long>& h_ext_ptr, DBuf<long>& ext_ptr, DBuf<int>& ext_idx, hipStream_t s) {
+  const long words = cdiv(n, 32);
+  DBuf<unsigned> bits;
+  bits.alloc((size_t)N * words);
+  bits.zero(s);
+  hipLaunchKernelGGL(k_ext_mark, dim3(N), dim3(256), 0, s, sub_ptr, sub_idx, rowptr, col, words, bits.p);
+  AWG_LAUNCH_CHECK();
+  DBuf<int> cnt;
+  cnt.alloc(N);
+  hipLaunchKernelGGL(k_ext_list, dim3(N), dim3(256), 0, s, words, bits.p, 0, cnt.p, nullptr, nullptr);
+  AWG_LAUNCH_CHECK();
+  const std::vector<int> hc = cnt.download(s);
+  h_ext_ptr.assign(N + 1, 0);
+  for (int t = 0; t < N; ++t) h_ext_ptr[t + 1] = h_ext_ptr[t] + hc[t];
+  ext_ptr.upload(h_ext_ptr, s);
+  ext_idx.alloc(std::max(1L, h_ext_ptr[N]));
+  hipLaunchKernelGGL(k_ext_list, dim3(N), dim3(256), 0, s, words, bits.p, 1, nullptr, ext_ptr.p, ext_idx.p);
+  AWG_LAUNCH_CHECK();
+  AWG_HIP(hipStreamSynchronize(s));
+  return h_ext_ptr[N];
+}
+
+void l_ext_ay(int N, const long* ext_ptr, const int* ext_idx, const long* sub_ptr, const int* sub_idx,
+              const int* rowptr, const int* col, const double* val, const double* Y, const long* y_eoff,
+              const long* y_coff, const long* ay_eoff, double* AY, hipStream_t s) {
+  hipLaunchKernelGGL(k_ext_ay, dim3(N), dim3(256), 0, s, ext_ptr, ext_idx, sub_ptr, sub_idx, rowptr, col, val, Y,
+                     y_eoff, y_coff, ay_eoff, AY);
+  AWG_LAUNCH_CHECK();
+}
+
+void l_lowrank_dense(int n, const int* inv_ptr, const int* inv_sub, const int* inv_loc, const long* sub_ptr,
+                     const long* eoff, const long* coff, const double* B, long c0, long ld, double* D,
+                     hipStream_t s) {
+  hipLaunchKernelGGL(k_lowrank_dense, dim3(grid1(n)), dim3(256), 0, s, n, inv_ptr, inv_sub, inv_loc, sub_ptr, eoff,
+                     coff, B, c0, ld, D);
+  AWG_LAUNCH_CHECK();
 }
 
 void l_dot1_part(int n, const double* x, const double* y, double* part, hipStream_t s) {
