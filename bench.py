@@ -36,6 +36,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 FP32_PEAK_TFLOPS = 157.3
+FP16_PEAK_TFLOPS = 2500.0     # dense FP16 matrix cores (no sparsity)
 
 
 def parse():
@@ -52,6 +53,11 @@ def parse():
                     help="two-level preconditioner for A_+ (both forms); nn_hyb is the default line")
     ap.add_argument("--w-rtol", type=float, default=1e-10,
                     help="relative residual of the PCG solves for W (the paper's choice is 1e-10)")
+    ap.add_argument("--fast-local", default="f32", choices=["f32", "f16x3"],
+                    help="local-operator arithmetic of the fast form (f16x3: split-FP16 matrix-core "
+                         "local products in the W solves)")
+    ap.add_argument("--no-split16", action="store_true",
+                    help="skip the extra split-FP16 form reported beside the FP32 fast form")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fast-form", action="store_true")
     ap.add_argument("--workload", default="diff3d_64", choices=sorted(WORKLOADS),
@@ -252,14 +258,16 @@ def measured_traffic(name: str, workload: str):
 def kernel_rates(kt: dict, top: int = 20) -> dict:
     """Achieved rate of each instrumented kernel over the warm-up step: HBM
     kernels as algorithmic GB/s and fraction of the HBM peak, MFMA kernels as
-    TFLOP/s and fraction of the FP64 (or FP32 for the FP32 local product) peak.
+    TFLOP/s and fraction of the FP64 peak (FP32 for the FP32 local product,
+    FP16 for the split-FP16 one).
     """
     out = {}
     for name, rec in sorted(kt.items(), key=lambda kv: -kv[1]["ms"])[:top]:
         if name.startswith("graph:") or rec["ms"] <= 0:
             continue
         if name.startswith(MFMA_KERNELS) and rec["flops"] > 0:
-            peak = FP32_PEAK_TFLOPS if ("_mix" in name or "_f32" in name) else FP64_PEAK_TFLOPS
+            peak = (FP16_PEAK_TFLOPS if "_h3" in name else
+                    FP32_PEAK_TFLOPS if ("_mix" in name or "_f32" in name) else FP64_PEAK_TFLOPS)
             tf = rec["flops"] / (rec["ms"] * 1e-3) / 1e12
             out[name] = {"TFLOP/s": round(tf, 2), "frac": round(tf / peak, 3), "calls": rec["calls"]}
         elif rec["bytes"] > 0:
@@ -280,13 +288,17 @@ def roofline(kt: dict, steps: int, workload: str) -> dict:
     if name.startswith(MFMA_KERNELS):
         achieved = rec["flops"] / (rec["ms"] * 1e-3) / 1e12
         f32 = "_mix" in name or "_f32" in name
-        peak = FP32_PEAK_TFLOPS if f32 else FP64_PEAK_TFLOPS
+        f16 = "_h3" in name
+        # the split-FP16 product counts its algorithmic flops once (three
+        # FP16 MFMA products are issued per product term) against the FP16 peak
+        peak = FP16_PEAK_TFLOPS if f16 else (FP32_PEAK_TFLOPS if f32 else FP64_PEAK_TFLOPS)
+        dtype = "f16x3" if f16 else ("f32" if f32 else "f64")
         out = {"kernel": name, "bound": "mfma", "achieved": round(achieved, 3), "peak": peak,
-               "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "dtype": "f32" if f32 else "f64",
+               "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "dtype": dtype,
                "traffic": measured_traffic(name, workload),
                "calls_per_step": rec["calls"] / steps, "avg_launch_us": round(avg_us, 2),
                "flops_per_launch": rec["flops"] / rec["calls"]}
-        if not f32:
+        if dtype == "f64":
             # the device's sustained FP64 matrix-core rate (register-only MFMA
             # chains, no memory traffic), measured in this run beside the
             # published peak
@@ -451,11 +463,12 @@ def main():
         ok, worst = form_result(infos, w.tol)
         st, info = stats[-1], infos[-1]
         wk = setup_work(w, st)
-        f32w = local_prec == "f32"
         # time the set-up would take with every flop at its matrix-core peak
-        # (the W local products at the FP32 peak in the FP32 form)
-        t_peak = ((wk["total"] - (wk["w_local_product"] if f32w else 0.0)) / (FP64_PEAK_TFLOPS * 1e12)
-                  + (wk["w_local_product"] / (FP32_PEAK_TFLOPS * 1e12) if f32w else 0.0))
+        # (the W local products at the FP32 peak in the FP32 form, at a third
+        # of the FP16 peak in the split-FP16 form: three products per term)
+        lp_peak = {"f32": FP32_PEAK_TFLOPS, "f16x3": FP16_PEAK_TFLOPS / 3.0}.get(local_prec)
+        t_peak = ((wk["total"] - (wk["w_local_product"] if lp_peak else 0.0)) / (FP64_PEAK_TFLOPS * 1e12)
+                  + (wk["w_local_product"] / (lp_peak * 1e12) if lp_peak else 0.0))
         rec = {"ms_per_step": round(ms, 3), "accuracy_ok": ok, "worst_true_res": worst,
                "setup_roofline": {"flops": wk, "setup_ms": round(st["ms"]["total"], 3),
                                   "ms_at_peak": round(t_peak * 1e3, 3),
@@ -476,14 +489,19 @@ def main():
     plain = None
     if not fast_only:
         plain, _, _ = run_form("plain", "f64", args.geneo, None, time_dominant=False)
-    fast = None
+    fast = split16 = None
     if not args.no_fast_form:
         # FP32 local operators, the subspace GenEO solver and the learned start
         # (the two-pencil coarse space of as_hyb has the dense GenEO solver only)
         fgeneo, fnet = ("dense", None) if args.h2 == "as_hyb" else ("subspace", net)
-        fast, kt, dominant = run_form("fast", "f32", fgeneo, fnet, time_dominant=True)
+        fast, kt, dominant = run_form("fast", args.fast_local, fgeneo, fnet, time_dominant=True)
         fast["network"] = wfile if fnet is not None else None
         head, head_label = fast, "fast"
+        if args.fast_local == "f32" and not args.no_split16:
+            # the same form with the W solves' local products on split-FP16
+            # matrix cores, reported beside the headline (not the headline:
+            # the metric names FP32 local operators)
+            split16, _, _ = run_form("split16", "f16x3", fgeneo, fnet, time_dominant=False)
     else:
         plain, kt, dominant = run_form("plain", "f64", args.geneo, None, time_dominant=True)
         head, head_label = plain, "plain"
@@ -498,7 +516,7 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64+f32local" if head_label == "fast" else "f64",
+        "dtype": ("f64+" + args.fast_local + "local") if head_label == "fast" else "f64",
         "data": "synthetic",
         "config": {"workload": WORKLOADS[args.workload][1], "form": head_label,
                    "n": int(A.shape[0]), "nnz": int(A.nnz), "N": len(w.subs), "tol": w.tol,
@@ -510,6 +528,10 @@ def main():
         out["speedup_vs_f64"] = (round(plain["ms_per_step"] / head["ms_per_step"], 3)
                                  if out["accuracy_ok"] else None)
     out[head_label + "_form"] = head
+    if split16 is not None:
+        out["f16x3_form"] = split16
+        out["f16x3_speedup_vs_f64"] = (round(plain["ms_per_step"] / split16["ms_per_step"], 3)
+                                       if plain is not None and split16["accuracy_ok"] else None)
     out["roofline"] = roofline(kt, args.steps, out["config"]["workload"])
     out["autotune"] = {k: v["variant"] for k, v in awg.tune_report().items()}
     if not args.no_cpu_baseline:

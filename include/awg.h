@@ -58,7 +58,16 @@ typedef enum {
   AWG_ERR_NONFINITE = -9        /* NaN or Inf in A */
 } awg_status;
 
-enum { AWG_LOCAL_F64 = 0, AWG_LOCAL_F32 = 1 };
+/* storage and arithmetic of the local solves P^s (the H^NN term):
+ *   AWG_LOCAL_F64    FP64 throughout;
+ *   AWG_LOCAL_F32    P^s rounded to FP32, FP32 products and sums;
+ *   AWG_LOCAL_F16X3  as AWG_LOCAL_F32 for one-column products; the
+ *                    multi-column local products of the W solves split both
+ *                    operands into two FP16 parts after a power-of-two scaling
+ *                    (per subdomain for P^s, per column for the vectors) and
+ *                    take three FP16 matrix-core products with FP32 sums
+ *                    (about 2^-21 relative error per product term) */
+enum { AWG_LOCAL_F64 = 0, AWG_LOCAL_F32 = 1, AWG_LOCAL_F16X3 = 2 };
 enum { AWG_GENEO_DENSE = 0, AWG_GENEO_SUBSPACE = 1 };
 /* second-coarse-space preconditioner H (Section 4), all with the same
  * W = A_+^{-1} V_-:
@@ -100,8 +109,9 @@ typedef struct {
                           that build W (Remark 2, Section 4.4); default 1e-10,
                           the value of the paper's experiments (Section 5) */
   int32_t w_maxit;     /* iteration cap of those solves; default 500 */
-  int32_t local_prec;  /* AWG_LOCAL_F64 (default) or AWG_LOCAL_F32: storage and
-                          arithmetic of the per-iteration local solves */
+  int32_t local_prec;  /* AWG_LOCAL_F64 (default), AWG_LOCAL_F32 or
+                          AWG_LOCAL_F16X3: storage and arithmetic of the
+                          per-iteration local solves */
   void* stream;        /* hipStream_t; NULL = default stream */
   int32_t geneo_solver;  /* AWG_GENEO_DENSE (default): every GenEO pencil is
                             reduced to tridiagonal form and solved exactly;

@@ -50,6 +50,20 @@ int awg_dense_gemm_ex(int32_t batch, int32_t m, int32_t n, int32_t k, int32_t tr
                       const double* B, int32_t ldb, int64_t strideB, double beta, double* C, int32_t ldc,
                       int64_t strideC, int32_t variant, void* stream);
 
+/* Split-FP16 local products Y_b = P_b^T X_b for batch entries of n_b x n_b
+ * matrices P_b (column-major, concatenated) and n_b x ncols row-major blocks
+ * X_b (concatenated, so X is (sum n_b) x ncols row-major; Y likewise): the
+ * multi-column local product of the W solves (the H^NN term of H2,
+ * Definition of H^NN, Section 3.3) in the AWG_LOCAL_F16X3 arithmetic.  Each
+ * P_b is scaled by a power of two, each column of X by a power of two (from
+ * the largest magnitude of that column over all of X), both are split into
+ * hi = fp16(v) and lo = fp16(v - hi), and hi.hi + hi.lo + lo.hi are summed on
+ * the FP16 matrix cores in FP32, then scaled back into FP64.  n_host: host
+ * array of the batch sizes; X, P, Y device.  Returns AWG_ERR_ARG for
+ * batch <= 0, ncols <= 0, a size n_b <= 0 or null pointers. */
+int awg_dense_local_product_f16x3(int32_t batch, const int32_t* n_host, int32_t ncols, const double* X,
+                                  const double* P, double* Y, void* stream);
+
 /* In-place lower Cholesky A_b = L_b L_b^T (upper triangle left unspecified).
  * info_host[b] (host, batch entries) = 0 or the 1-based column of the first
  * non-positive pivot; returns AWG_ERR_NOT_SPD if any block failed. */

@@ -17,6 +17,8 @@ LIB_PATH = os.path.join(_HERE, "libawg.so")
 
 AWG_LOCAL_F64 = 0
 AWG_LOCAL_F32 = 1
+AWG_LOCAL_F16X3 = 2
+LOCAL_PREC = {"f64": AWG_LOCAL_F64, "f32": AWG_LOCAL_F32, "f16x3": AWG_LOCAL_F16X3}
 AWG_GENEO_DENSE, AWG_GENEO_SUBSPACE = 0, 1
 COARSE2 = {"ad": 0, "inex": 1, "hyb": 2}     # second-coarse-space preconditioner (awg.h)
 H2 = {"nn_hyb": 0, "asp_hyb": 1, "asp_ad": 2, "as_hyb": 3}  # two-level preconditioner for A_+ (awg.h)
@@ -27,7 +29,7 @@ STATUS = {0: "AWG_OK", 1: "AWG_NOT_CONVERGED", -1: "AWG_ERR_ARG", -2: "AWG_ERR_N
 
 EXPORTED = ["awg_default_options", "awg_setup", "awg_apply", "awg_pcg", "awg_stats", "awg_export",
             "awg_last_error", "awg_destroy", "awg_kernel_timing", "awg_kernel_times", "awg_pcg_graph",
-            "awg_dense_gemm", "awg_dense_gemm_ex", "awg_dense_potrf", "awg_dense_potrf_noalloc", "awg_dense_trsm",
+            "awg_dense_gemm", "awg_dense_gemm_ex", "awg_dense_local_product_f16x3", "awg_dense_potrf", "awg_dense_potrf_noalloc", "awg_dense_trsm",
             "awg_dense_low_eigs",
             "awg_mlp_create", "awg_mlp_num_params", "awg_mlp_get_params", "awg_mlp_set_params", "awg_mlp_forward",
             "awg_mlp_loss_grad", "awg_mlp_get_grads", "awg_mlp_adam_step", "awg_mlp_last_error", "awg_mlp_destroy",
@@ -100,6 +102,8 @@ def lib():
     L.awg_dense_gemm_ex.argtypes = [i32, i32, i32, i32, i32, i32, dbl, vp, i32, i64, vp, vp, i32, i64, dbl, vp, i32,
                                     i64, i32, vp]
     L.awg_dense_gemm_ex.restype = ctypes.c_int
+    L.awg_dense_local_product_f16x3.argtypes = [i32, vp, i32, vp, vp, vp, vp]
+    L.awg_dense_local_product_f16x3.restype = ctypes.c_int
     L.awg_probe_mfma_f64.argtypes = [i32, ctypes.POINTER(ctypes.c_double), vp]
     L.awg_probe_mfma_f64.restype = ctypes.c_int
     L.awg_dense_potrf.argtypes = [i32, i32, vp, i32, i64, vp, vp]
@@ -229,7 +233,9 @@ class Solver:
         opt.zero_tol = zero_tol
         opt.w_rtol = w_rtol
         opt.w_maxit = w_maxit
-        opt.local_prec = AWG_LOCAL_F32 if local_prec == "f32" else AWG_LOCAL_F64
+        if local_prec not in LOCAL_PREC:
+            raise ValueError("local_prec must be one of " + ", ".join(LOCAL_PREC))
+        opt.local_prec = LOCAL_PREC[local_prec]
         opt.stream = torch.cuda.current_stream(self.device).cuda_stream
         if geneo not in ("dense", "subspace"):
             raise ValueError("geneo must be 'dense' or 'subspace'")
@@ -366,6 +372,18 @@ def dense_gemm_ex(A, B, C, alpha=1.0, beta=0.0, transA=False, transB=False, vari
     if rc:
         raise AWGError(rc, "awg_dense_gemm_ex")
     return C
+
+
+def dense_local_product_f16x3(sizes, X, P, Y):
+    """Y_b = P_b^T X_b in the split-FP16 arithmetic of AWG_LOCAL_F16X3.
+    sizes: batch sizes n_b; X, Y: (sum n_b) x ncols row-major float64 device
+    tensors; P: the concatenated column-major n_b x n_b matrices (float64)."""
+    sz = np.ascontiguousarray(np.asarray(sizes, dtype=np.int32))
+    rc = lib().awg_dense_local_product_f16x3(len(sz), sz.ctypes.data, X.shape[1], X.data_ptr(), P.data_ptr(),
+                                             Y.data_ptr(), _stream())
+    if rc:
+        raise AWGError(rc, "awg_dense_local_product_f16x3")
+    return Y
 
 
 def probe_mfma_f64(iters: int = 4000) -> float:

@@ -132,6 +132,14 @@ struct GemmDescF32 {     // FP32 A and B, FP64 C (FP32 local operators, FP32 acc
   int lda, ldb, ldc;
 };
 
+struct GemmDescH3 {      // split FP16 operands (hi and lo planes), FP64 C: C = A B of one subdomain
+  const _Float16* A;     // multi-vector operand: entry (g, i) at A + (g m + i) 8, lo plane at + planeA
+  const _Float16* B;     // matrix operand: entry (j, g) at B + (j G + g) 8, lo plane at + planeB
+  double* C;             // C[i + j ldc]
+  long planeA, planeB;
+  int m, n, G, ldc;      // G = row groups of 8 (k = 8 G, zero-padded)
+};
+
 struct MatDesc {         // one square or rectangular column-major block
   double* A;
   int m, n, ld;
@@ -172,6 +180,16 @@ void gemm_f32_batched(const GemmDescF32* d_desc, int batch, int max_m, int max_n
                       hipStream_t s, double flops, const int* tiles = nullptr, int ntiles = 0, int grid = 0);
 // tile list (host) of the persistent local-product launch for batch entries
 // of sizes m x n with inner dimension k; returns its grid size
+// split-FP16 local product (three FP16 MFMA products, FP32 accumulation):
+// emax (b) = per-column largest biased exponent of the multi-vector, from
+// l_colexp; sp (batch) = the power-of-two scale of each matrix, from l_p16_build
+void gemm_h3_batched(const GemmDescH3* d_desc, int batch, int max_m, int max_n, const int* emax, const int* sp,
+                     hipStream_t s, double flops);
+void l_colexp(int n, int b, const double* X, int* emax, hipStream_t s);
+void l_gather_h3(long ngroups, const int* row0, const int* cnt, const int* sub_idx, const double* X, int b,
+                 const int* emax, _Float16* out, long plane, hipStream_t s);
+void l_p16_build(int N, const long* sqoff, const long* sub_ptr, const long* poff, const double* P, _Float16* out,
+                 long plane, int* sp, hipStream_t s);
 int f32_tile_list(const std::vector<int>& m, const std::vector<int>& n, const std::vector<int>& k, int wgs_per_xcd,
                   std::vector<int>& tiles);
 // X, idx, off (optional): the same row gather of the A operands as in

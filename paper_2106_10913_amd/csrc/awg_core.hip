@@ -165,6 +165,10 @@ struct MultiWS {
   DBuf<GemmDesc> dCu, dCt, dAYt;      // C u0, C^T (..), (A R0^T)^T y (precomputed A_+ R0^T, b > 1)
   DBuf<int> tilesP32;                 // tile list of the persistent FP32 local product
   int ntilesP32 = 0, gridP32 = 0;
+  DBuf<_Float16> Xs16;                // split-FP16 restricted rows (hi plane, then lo plane)
+  long xs16_plane = 0;
+  DBuf<GemmDescH3> dH3;
+  DBuf<int> emax;                     // per-column largest exponent of the restricted multi-vector
   int maxk = 0, maxm = 0, maxns = 0;
   double flV = 0, flY = 0, flP = 0, flE0 = 0, flW = 0, flEW = 0;   // algorithmic flops per product
 };
@@ -224,6 +228,15 @@ struct awg_ctx {
   DBuf<double> V, lamV, Y, lamY;
   DBuf<double> P;
   DBuf<float> P32;
+  // split-FP16 local operators (multi-column local products): P^s scaled by
+  // 2^sp_s and split into hi and lo planes of row groups of 8; the row
+  // groups of the restriction (first entry into sub_idx, row count)
+  DBuf<_Float16> P16;
+  long p16_plane = 0;
+  DBuf<int> p16_sp, h3_row0, h3_cnt;
+  DBuf<long> p16_off;
+  std::vector<long> h_p16_off, h3_gofs;
+  long h3_groups = 0;
   int n0 = 0, nminus = 0;
   DBuf<double> E0inv, W, EWinv;
   MultiWS ws1;           // single-vector workspace (apply / PCG)
@@ -521,6 +534,18 @@ void build_ws(awg_ctx& c, MultiWS& w, int b) {
     w.ntilesP32 = (int)tl.size();
     w.tilesP32.upload(tl, s);
   }
+  if (c.P16.p && b > 1) {
+    w.xs16_plane = c.h3_groups * (long)b * 8;
+    w.Xs16.alloc(2 * (size_t)w.xs16_plane);
+    w.emax.alloc(b);
+    std::vector<GemmDescH3> ph(c.N);
+    for (int q = 0; q < c.N; ++q) {
+      const int nsq = c.ns[q];
+      ph[q] = GemmDescH3{w.Xs16.p + c.h3_gofs[q] * b * 8, c.P16.p + c.h_p16_off[q], w.Os.p + c.h_subptr[q] * b,
+                         w.xs16_plane, c.p16_plane, b, nsq, (nsq + 7) / 8, b};
+    }
+    w.dH3.upload(ph, s);
+  }
   const int n0 = std::max(1, c.n0), nm = std::max(1, c.nminus);
   w.flE0 = 2.0 * c.n0 * (double)c.n0 * b;
   w.flW = 2.0 * c.n * (double)c.nminus * b;
@@ -655,6 +680,12 @@ void op_hnn(awg_ctx& c, MultiWS& w, const double* X, double* Yo, bool f32) {
     hipLaunchKernelGGL(k_gemv_f32, dim3(cdiv(w.maxns, 64), c.N), dim3(256), 0, c.s, c.P32.p, c.d_sqoff.p,
                        c.subptr.p, w.Xs.p, w.Os.p);
     AWG_LAUNCH_CHECK();
+  } else if (f32 && c.P16.p) {
+    // split-FP16 local product: per-column exponents, split restriction,
+    // three FP16 matrix-core products per tile
+    l_colexp(c.n, w.b, X, w.emax, c.s);
+    l_gather_h3(c.h3_groups, c.h3_row0, c.h3_cnt, c.subidx, X, w.b, w.emax, w.Xs16, w.xs16_plane, c.s);
+    gemm_h3_batched(w.dH3, c.N, w.b, w.maxns, w.emax, c.p16_sp, c.s, w.flP);
   } else if (f32) {
     // FP32 local product, three forms with identical results: the restricted
     // FP64 rows written out or read in place and rounded while staged, or
@@ -1205,6 +1236,38 @@ int geneo_subspace(awg_ctx& c, const double* MB, double* MA) {
   return 0;
 }
 
+// reduced-precision copies of the local operators P^s: FP32 (one-column
+// products and the FP32 local product) and, for AWG_LOCAL_F16X3, the split
+// FP16 planes with their row groups
+void build_reduced_local(awg_ctx& c) {
+  hipStream_t s = c.s;
+  c.P32.alloc(c.sqtot);
+  hipLaunchKernelGGL(k_f32_from_f64, dim3(4096), dim3(256), 0, s, (long)c.sqtot, c.P.p, c.P32.p);
+  AWG_LAUNCH_CHECK();
+  if (c.opt.local_prec != AWG_LOCAL_F16X3) return;
+  std::vector<int> row0, cnt;
+  c.h3_gofs.assign(c.N + 1, 0);
+  c.h_p16_off.assign(c.N + 1, 0);
+  for (int q = 0; q < c.N; ++q) {
+    const int nsq = c.ns[q], G = (nsq + 7) / 8;
+    for (int g = 0; g < G; ++g) {
+      row0.push_back((int)(c.h_subptr[q] + 8 * g));
+      cnt.push_back(std::min(8, nsq - 8 * g));
+    }
+    c.h3_gofs[q + 1] = c.h3_gofs[q] + G;
+    c.h_p16_off[q + 1] = c.h_p16_off[q] + (long)nsq * G * 8;
+  }
+  c.h3_groups = c.h3_gofs[c.N];
+  c.h3_row0.upload(row0, s);
+  c.h3_cnt.upload(cnt, s);
+  c.p16_plane = c.h_p16_off[c.N];
+  c.p16_off.upload(c.h_p16_off, s);
+  c.P16.alloc(2 * (size_t)c.p16_plane);
+  c.p16_sp.alloc(c.N);
+  l_p16_build(c.N, c.d_sqoff, c.subptr, c.p16_off, c.P, c.P16, c.p16_plane, c.p16_sp, s);
+  sync(c);   // the host row-group lists end here
+}
+
 // B^s, its non-positive eigenpairs (splitting of B^s, Section 3.2), the local
 // factor and P^s = D^s (A^s_+)^+ D^s, the GenEO coarse vectors Y^s
 // (Theorem on H^NN_hyb, Section 3.4).
@@ -1279,11 +1342,7 @@ void phase_local(awg_ctx& c) {
     l_scale_sym(d2, c.N, c.subptr, c.dw, false, true, s);
     std::swap(c.P.p, X2.p);   // d2 now addresses c.P
     std::swap(c.P.n, X2.n);
-    if (c.opt.local_prec == AWG_LOCAL_F32 && !asp) {
-      c.P32.alloc(c.sqtot);
-      hipLaunchKernelGGL(k_f32_from_f64, dim3(4096), dim3(256), 0, s, (long)c.sqtot, c.P.p, c.P32.p);
-      AWG_LAUNCH_CHECK();
-    }
+    if (c.opt.local_prec != AWG_LOCAL_F64 && !asp) build_reduced_local(c);
   }
   // M_A = D^{-1} A^s_+ D^{-1} (in X3) and M_B (in X1), with
   // A^s_+ = B^s + V_- |L_-| V_-^T and
@@ -1388,11 +1447,7 @@ void phase_local(awg_ctx& c) {
     sync(c);   // the host-side layouts and Y1, Y2 end with this scope
     std::swap(c.P.p, X1.p);
     std::swap(c.P.n, X1.n);
-    if (c.opt.local_prec == AWG_LOCAL_F32) {
-      c.P32.alloc(c.sqtot);
-      hipLaunchKernelGGL(k_f32_from_f64, dim3(4096), dim3(256), 0, s, (long)c.sqtot, c.P.p, c.P32.p);
-      AWG_LAUNCH_CHECK();
-    }
+    if (c.opt.local_prec != AWG_LOCAL_F64) build_reduced_local(c);
     return;
   }
   bool mb_factored = false;   // d1 holds the Cholesky factor of M_B^s (dense solver), else M_B^s
@@ -1430,11 +1485,7 @@ void phase_local(awg_ctx& c) {
       std::swap(c.P.p, X2.p);
       std::swap(c.P.n, X2.n);
     }
-    if (c.opt.local_prec == AWG_LOCAL_F32) {
-      c.P32.alloc(c.sqtot);
-      hipLaunchKernelGGL(k_f32_from_f64, dim3(4096), dim3(256), 0, s, (long)c.sqtot, c.P.p, c.P32.p);
-      AWG_LAUNCH_CHECK();
-    }
+    if (c.opt.local_prec != AWG_LOCAL_F64) build_reduced_local(c);
   }
 }
 
@@ -1716,7 +1767,7 @@ void phase_W(awg_ctx& c) {
     AWG_HIP(hipStreamSynchronize(s));
     return h;
   };
-  const bool f32 = c.opt.local_prec == AWG_LOCAL_F32;
+  const bool f32 = c.opt.local_prec != AWG_LOCAL_F64;
   DBuf<double> Zold;
   if (f32) Zold.alloc((long)c.n * b);
   for (int c0 = 0; c0 < c.nminus; c0 += b) {
@@ -1941,7 +1992,7 @@ constexpr int PCG_MAX_RESTARTS = 5;
 int do_pcg(awg_ctx& c, const double* b, double* x, double tol, int maxit, awg_pcg_info* info) {
   hipStream_t s = c.s;
   MultiWS& w = c.ws1;
-  const bool f32 = c.opt.local_prec == AWG_LOCAL_F32;
+  const bool f32 = c.opt.local_prec != AWG_LOCAL_F64;
   const int n = c.n;
   maxit = std::min(maxit, PCG_HIST - 1);
   double* xx = c.pcg_buf.p;
@@ -2149,7 +2200,7 @@ int awg_setup(awg_ctx** out, int64_t n, int64_t nnz, const int64_t* rowptr, cons
     return AWG_ERR_ARG;
   }
   if (!(o.zero_tol >= 0.0) || !(o.w_rtol > 0.0) || o.w_maxit <= 0 ||
-      (o.local_prec != AWG_LOCAL_F64 && o.local_prec != AWG_LOCAL_F32) ||
+      (o.local_prec != AWG_LOCAL_F64 && o.local_prec != AWG_LOCAL_F32 && o.local_prec != AWG_LOCAL_F16X3) ||
       (o.geneo_solver != AWG_GENEO_DENSE && o.geneo_solver != AWG_GENEO_SUBSPACE) || o.eig_block < 1 ||
       o.eig_block > SUBSPACE_MAX_BLOCK || o.eig_maxit < 1 || !(o.eig_tol > 0.0) ||
       (o.coords && (o.coord_dim < 1 || o.coord_dim > 3)) ||
@@ -2199,7 +2250,7 @@ int awg_apply(awg_ctx* c, const double* r, double* z) {
   if (!c || !r || !z) return AWG_ERR_ARG;
   try {
     AWG_HIP(hipMemcpyAsync(c->ws1.R.p, r, sizeof(double) * c->n, hipMemcpyDeviceToDevice, c->s));
-    op_h(*c, c->ws1, c->opt.local_prec == AWG_LOCAL_F32);
+    op_h(*c, c->ws1, c->opt.local_prec != AWG_LOCAL_F64);
     AWG_HIP(hipMemcpyAsync(z, c->ws1.Z.p, sizeof(double) * c->n, hipMemcpyDeviceToDevice, c->s));
   } catch (const Error& e) {
     return fail(c, e);

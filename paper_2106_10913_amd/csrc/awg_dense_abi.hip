@@ -135,6 +135,64 @@ int awg_dense_gemm_ex(int32_t batch, int32_t m, int32_t n, int32_t k, int32_t tr
   });
 }
 
+int awg_dense_local_product_f16x3(int32_t batch, const int32_t* n_host, int32_t ncols, const double* X,
+                                  const double* P, double* Y, void* stream) {
+  if (batch <= 0 || ncols <= 0 || !n_host || !X || !P || !Y) return AWG_ERR_ARG;
+  for (int e = 0; e < batch; ++e)
+    if (n_host[e] <= 0) return AWG_ERR_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  return guarded(s, [&] {
+    const int b = ncols;
+    std::vector<long> subptr(batch + 1, 0), sqoff(batch + 1, 0), poff(batch + 1, 0), gofs(batch + 1, 0);
+    std::vector<int> row0, cnt;
+    int maxn = 0;
+    for (int e = 0; e < batch; ++e) {
+      const int ne = n_host[e], G = (ne + 7) / 8;
+      for (int g = 0; g < G; ++g) {
+        row0.push_back((int)(subptr[e] + 8 * g));
+        cnt.push_back(std::min(8, ne - 8 * g));
+      }
+      subptr[e + 1] = subptr[e] + ne;
+      sqoff[e + 1] = sqoff[e] + (long)ne * ne;
+      poff[e + 1] = poff[e] + (long)ne * G * 8;
+      gofs[e + 1] = gofs[e] + G;
+      maxn = std::max(maxn, ne);
+    }
+    const long rows = subptr[batch], groups = gofs[batch];
+    std::vector<int> ident(rows);
+    for (long r = 0; r < rows; ++r) ident[r] = (int)r;
+    DBuf<long> dsub, dsq, dpo;
+    DBuf<int> drow0, dcnt, didx, emax, sp;
+    dsub.upload(subptr, s);
+    dsq.upload(sqoff, s);
+    dpo.upload(poff, s);
+    drow0.upload(row0, s);
+    dcnt.upload(cnt, s);
+    didx.upload(ident, s);
+    emax.alloc(b);
+    sp.alloc(batch);
+    DBuf<_Float16> X16, P16;
+    const long xplane = groups * (long)b * 8, pplane = poff[batch];
+    X16.alloc(2 * (size_t)xplane);
+    P16.alloc(2 * (size_t)pplane);
+    l_colexp((int)rows, b, X, emax, s);
+    l_gather_h3(groups, drow0, dcnt, didx, X, b, emax, X16, xplane, s);
+    l_p16_build(batch, dsq, dsub, dpo, P, P16, pplane, sp, s);
+    std::vector<GemmDescH3> h(batch);
+    double fl = 0.0;
+    for (int e = 0; e < batch; ++e) {
+      const int ne = n_host[e];
+      h[e] = GemmDescH3{X16.p + gofs[e] * b * 8, P16.p + poff[e], Y + subptr[e] * b, xplane, pplane, b, ne,
+                        (ne + 7) / 8, b};
+      fl += 2.0 * ne * (double)ne * b;
+    }
+    DBuf<GemmDescH3> d;
+    d.upload(h, s);
+    gemm_h3_batched(d, batch, b, maxn, emax, sp, s, fl);
+    AWG_HIP(hipStreamSynchronize(s));
+  });
+}
+
 int awg_dense_potrf(int32_t batch, int32_t n, double* A, int32_t lda, int64_t strideA, int32_t* info_host,
                     void* stream) {
   if (batch <= 0 || n <= 0 || lda < n || !A) return AWG_ERR_ARG;

@@ -1,9 +1,11 @@
-"""FP32 local operators (local_prec = f32): the eigen-setup stays FP64, so the
-coarse spaces are identical; the local products run in FP32 (mixed GEMM in
-the W solves, FP32 GEMV in PCG).  Judged, for every choice of H2, by the
-true final residual and the iteration increase over the FP64 form of the
-same preconditioner (no element-wise parity: the operator itself differs by
-FP32 rounding)."""
+"""Reduced-precision local operators (local_prec = f32, f16x3): the
+eigen-setup stays FP64, so the coarse spaces are identical; the local
+products run in FP32 (FP32 GEMM in the W solves, FP32 GEMV in PCG) or, for
+f16x3, the multi-column local products of the W solves on split FP16
+operands.  Judged, for every choice of H2, by the true final residual and
+the iteration increase over the FP64 form of the same preconditioner, in
+the W solves and in PCG (no element-wise parity: the operator itself differs
+by the rounding)."""
 import numpy as np
 import pytest
 
@@ -19,17 +21,19 @@ CASES = {"fd5_32": P.fd5_32, "q1_2d_64": lambda: P.q1_2d(m=64, boxes=(2, 2))}
 H2S = ["nn_hyb", "asp_hyb", "asp_ad", "as_hyb"]
 
 
+@pytest.mark.parametrize("prec", ["f32", "f16x3"])
 @pytest.mark.parametrize("h2", H2S)
 @pytest.mark.parametrize("name", sorted(CASES))
-def test_f32_local_converges(gpu_lib, name, h2):
+def test_f32_local_converges(gpu_lib, name, h2, prec):
     import torch
     w = CASES[name]()
-    print(f"\n[gpu case] f32 {name} h2={h2} n={w.A.shape[0]}", flush=True)
+    print(f"\n[gpu case] {prec} {name} h2={h2} n={w.A.shape[0]}", flush=True)
     b = torch.as_tensor(w.b, device="cuda")
     s64 = gpu_lib.Solver(w.A, w.subs, tau=w.tau, local_prec="f64", h2=h2)
-    s32 = gpu_lib.Solver(w.A, w.subs, tau=w.tau, local_prec="f32", h2=h2)
+    s32 = gpu_lib.Solver(w.A, w.subs, tau=w.tau, local_prec=prec, h2=h2)
     st64, st32 = s64.stats(), s32.stats()
     assert st32["n_minus"] == st64["n_minus"] and st32["n0"] == st64["n0"]
+    assert st32["w_iters"] <= st64["w_iters"] + 3
     x64, i64 = s64.pcg(b, tol=w.tol)
     x32, i32 = s32.pcg(b, tol=w.tol)
     assert i32["converged"] == 1

@@ -104,6 +104,60 @@ def test_gemm_ex_rejects_bad_arguments(gpu_lib):
             gpu_lib.dense_gemm_ex(A, A, A.clone(), **kw)
 
 
+@pytest.mark.parametrize("ncols", [1, 5, 130, 257])
+def test_local_product_f16x3(gpu_lib, ncols):
+    """Split-FP16 local products against numpy FP64, element by element within
+    the error bound of the arithmetic: the split x = hi + lo keeps 22
+    significant bits (|x - hi - lo| <= 2^-22 |x|), the dropped lo.lo term is
+    below 2^-22 |p x|, and FP32 sums of k terms add at most k 2^-24 of the
+    sum of magnitudes; values that the scaling sends below the FP16
+    subnormal range (2^-38 of the column's largest) are lost.  Sizes cover
+    fewer than 8 rows, whole and ragged groups of 8, several 128 tiles; the
+    columns span 60 decades, with one column of zeros.  The bound counts the
+    lost values of both operands (below 2^-38 of the column's or the
+    matrix's largest magnitude)."""
+    import torch
+    rng = np.random.default_rng(ncols)
+    sizes = [1, 7, 8, 9, 100, 129, 300]
+    rows = sum(sizes)
+    X = rng.standard_normal((rows, ncols)) * 10.0 ** rng.uniform(-30, 30, ncols)
+    if ncols > 1:
+        X[:, 1] = 0.0
+    Ps = [rng.standard_normal((k, k)) * 10.0 ** rng.uniform(-20, 20) for k in sizes]
+    Pflat = np.concatenate([p.T.reshape(-1) for p in Ps])      # column-major blocks
+    Xd = torch.as_tensor(X, device="cuda")
+    Pd = torch.as_tensor(Pflat, device="cuda")
+    Yd = torch.full_like(Xd, float("nan"))
+    gpu_lib.dense_local_product_f16x3(sizes, Xd, Pd, Yd)
+    Y = Yd.cpu().numpy()
+    colmax = np.abs(X).max(axis=0)
+    o = 0
+    rel = []
+    for k, p in zip(sizes, Ps):
+        Xb = X[o:o + k]
+        ref = p.T @ Xb
+        mag = np.abs(p).T @ np.abs(Xb)
+        bound = ((2.0 ** -20 + k * 2.0 ** -24) * mag
+                 + 2.0 ** -36 * (np.abs(p).sum(axis=0)[:, None] * colmax
+                                 + np.abs(p).max() * np.abs(Xb).sum(axis=0)[None, :]))
+        err = np.abs(Y[o:o + k] - ref)
+        assert np.all(err <= bound), (k, float((err / np.maximum(bound, 1e-300)).max()))
+        nz = mag > 0
+        rel.append((err[nz] / mag[nz]).max(initial=0.0))
+        o += k
+    assert not np.isnan(Y).any()
+    print(f"\n[f16x3 local product] ncols={ncols} max err / sum|terms| = {max(rel):.2e}", flush=True)
+
+
+def test_local_product_f16x3_rejects_bad_arguments(gpu_lib):
+    import torch
+    X = torch.zeros((4, 2), dtype=torch.float64, device="cuda")
+    P = torch.zeros(16, dtype=torch.float64, device="cuda")
+    from paper_2106_10913_amd.awg import AWGError
+    with pytest.raises(AWGError):
+        gpu_lib.dense_local_product_f16x3([4, 0], X, P, X)
+
+
 @pytest.mark.parametrize("n", [1, 31, 33, 64, 100, 257])
 def test_potrf(gpu_lib, n):
     rng = np.random.default_rng(n)
