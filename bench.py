@@ -88,12 +88,14 @@ def cpu_baseline(w, workload: str, k_sub: int = 8, b_cols: int = 64):
     it_W and iters come from the oracle-only golden file of the workload when
     it holds them (else 40 each), and so do n0 and n_- (else estimated from
     the sample).  Threads: the host cores visible to the
-    process (the BLAS uses them all).
+    process (the BLAS uses them all).  Beside the extrapolation, the smallest
+    configuration is run by the oracle in full and timed (full_runs).
     """
     import numpy as np
     import scipy.linalg as sla
     import scipy.sparse as sp
     import scipy.sparse.linalg as spla
+    import awg_problems as P
     from oracle import awg_oracle as O
     threads = len(os.sched_getaffinity(0))
     A = w.A.tocsr()
@@ -215,8 +217,21 @@ def cpu_baseline(w, workload: str, k_sub: int = 8, b_cols: int = 64):
     t_w = (clock() - t0) * nm / Wr.shape[1]
     ts["pcg"] = iters * (h2_cost(1) + t_w)
     total = sum(ts.values())
+    # the smallest configuration (32x32 five-point diffusion, 16 subdomains)
+    # run by the oracle in full (set-up and PCG), timed in the same run
+    full = []
+    for label, make in (("fd5_32 (n = 1024, 16 subdomains)", P.fd5_32),):
+        ws = make()
+        t0 = clock()
+        sts = O.setup(ws.A, ws.subs, ws.tau)
+        t_set = clock() - t0
+        t0 = clock()
+        res = O.pcg(ws.A, ws.b, sts.apply, tol=ws.tol, maxit=1000)
+        full.append({"workload": label, "setup_s": round(t_set, 3), "pcg_s": round(clock() - t0, 3),
+                     "iters": res.iters, "n": int(ws.A.shape[0])})
     return {
         "value": round(total * 1e3, 1), "unit": "ms", "cores": threads, "kind": "oracle",
+        "full_runs": full,
         "sample": (f"extrapolated from a bounded sample, not a full run: maps, B^s splitting and GenEO on "
                    f"{k} of {N} subdomains (x{N}/{k}); E0 columns of those subdomains (x n0/{off}, n0 = {n0}) "
                    f"+ the deleting Cholesky of an {n0}^2 Gram matrix; W ({nm} columns est.): {w_how}; "

@@ -828,8 +828,10 @@ __global__ __launch_bounds__(256) void k_coldot_part(int n, int b, const double*
 // Multi-column PCG update in one pass: X += a_c P, R -= a_c Q, and the
 // partial sums of R^2 per column over the DOT_CHUNKS row ranges (the same
 // partition and order as k_coldot_part)
-__global__ __launch_bounds__(256) void k_multi_update_xr(int n, int b, const double* a, const double* P, double* X,
-                                                         const double* Q, double* R, double* part) {
+__global__ __launch_bounds__(256) void k_multi_update_xr(int n, int b, const double* __restrict__ a,
+                                                         const double* __restrict__ P, double* __restrict__ X,
+                                                         const double* __restrict__ Q, double* __restrict__ R,
+                                                         double* __restrict__ part) {
   const int cl = threadIdx.x & 63, rl = threadIdx.x >> 6;
   const int c = blockIdx.x * 64 + cl;
   const int chunk = blockIdx.y;
@@ -837,7 +839,29 @@ __global__ __launch_bounds__(256) void k_multi_update_xr(int n, int b, const dou
   double acc = 0.0;
   if (c < b) {
     const double ac = a[c], mc = -a[c];
-    for (int i = r0 + rl; i < r1; i += 4) {
+    int i = r0 + rl;
+    // four rows per step with every load issued first (the same rows, and
+    // the same order of the sum of squares, as one row per step)
+    for (; i + 12 < r1; i += 16) {
+      double p[4], x[4], q[4], rr[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const long e = (long)(i + 4 * u) * b + c;
+        p[u] = P[e];
+        x[u] = X[e];
+        q[u] = Q[e];
+        rr[u] = R[e];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const long e = (long)(i + 4 * u) * b + c;
+        X[e] = ac * p[u] + 1.0 * x[u];
+        const double r = mc * q[u] + 1.0 * rr[u];
+        R[e] = r;
+        acc += r * r;
+      }
+    }
+    for (; i < r1; i += 4) {
       const long e = (long)i * b + c;
       X[e] = ac * P[e] + 1.0 * X[e];
       const double r = mc * Q[e] + 1.0 * R[e];
@@ -853,20 +877,39 @@ __global__ __launch_bounds__(256) void k_multi_update_xr(int n, int b, const dou
 
 // partial sums of X^T Y1 and X^T Y2 per column in one pass over X (Y2 may be
 // NULL); partitions as k_coldot_part
-__global__ __launch_bounds__(256) void k_coldot2_part(int n, int b, const double* X, const double* Y1,
-                                                      const double* Y2, double* part1, double* part2) {
+__global__ __launch_bounds__(256) void k_coldot2_part(int n, int b, const double* __restrict__ X,
+                                                      const double* __restrict__ Y1, const double* __restrict__ Y2,
+                                                      double* __restrict__ part1, double* __restrict__ part2) {
   const int cl = threadIdx.x & 63, rl = threadIdx.x >> 6;
   const int c = blockIdx.x * 64 + cl;
   const int chunk = blockIdx.y;
   const int r0 = (int)((long)n * chunk / DOT_CHUNKS), r1 = (int)((long)n * (chunk + 1) / DOT_CHUNKS);
   double a1 = 0.0, a2 = 0.0;
-  if (c < b)
-    for (int i = r0 + rl; i < r1; i += 4) {
+  if (c < b) {
+    int i = r0 + rl;
+    // four rows per step, loads first, sums in row order
+    for (; i + 12 < r1; i += 16) {
+      double x[4], y1[4], y2[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const long e = (long)(i + 4 * u) * b + c;
+        x[u] = X[e];
+        y1[u] = Y1[e];
+        y2[u] = Y2 ? Y2[e] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        a1 += x[u] * y1[u];
+        if (Y2) a2 += x[u] * y2[u];
+      }
+    }
+    for (; i < r1; i += 4) {
       const long e = (long)i * b + c;
       const double x = X[e];
       a1 += x * Y1[e];
       if (Y2) a2 += x * Y2[e];
     }
+  }
   __shared__ double sh[2][4][64];
   sh[0][rl][cl] = a1;
   sh[1][rl][cl] = a2;
