@@ -250,11 +250,11 @@ MFMA_KERNELS = ("k_gemm",)
 # (factors 2.0 and 1.0).  Valid only for the kernel source and workload they
 # were taken on; otherwise the bench reports traffic = null.
 TRAFFIC = {
-    "k_gemm128w8<DescArray,N,N>:P": {
-        "bytes_per_launch": 1.6497e10,
+    "k_gemm128_f32_w8:P": {
+        "bytes_per_launch": 5.2950e10,
         "source": "paper_2106_10913_amd/csrc/k_dense.hip",
-        "sha256": "e3b9f6defd90e46378e1fc4904f983553a444a42dbab3df4d02fceb3be0338b8",
-        "workload": "q1_2d_diffusion_256x256_box8x8_overlap2_tau0.1",
+        "sha256": "d755ee10f5293f9da217c8f3e0a220be93f1c13bad885d626cc6ecc32d61263f",
+        "workload": "q1_diffusion_64^3_grf_box8^3_overlap1_tau0.1",
     },
 }
 
@@ -492,6 +492,7 @@ def main():
                "restarts": info.get("restarts", 0),
                "kappa_est": info["lmax_est"] / info["lmin_est"], "n_minus": st["n_minus"], "n0": st["n0"],
                "w_iters": st["w_iters"], "w_iters_mean": st.get("w_iters_mean"),
+               "w_compactions": st.get("w_compactions"),
                "eig_fallbacks": st["eig_fallbacks"], "eig_learned": st["eig_learned"],
                "eig_iters_max": max(st["eig_iters"], default=0),
                "phases_ms": {k: round(v, 3) for k, v in st["ms"].items()},
