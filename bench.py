@@ -435,12 +435,17 @@ def main():
     net = learned.load(os.path.join(ROOT, "paper_2106_10913_amd", "weights", wfile)) if wfile else None
 
     def step(local_prec, geneo, init):
+        t0 = time.perf_counter()
         solver = awg.Solver(Ad, Sd, tau=w.tau, local_prec=local_prec, geneo=geneo, eig_init=init,
                             coords=coords if init is not None else None, coarse2=args.coarse2,
                             w_rtol=args.w_rtol, h2=args.h2)
+        t1 = time.perf_counter()
         _, info = solver.pcg(bd, tol=w.tol, maxit=1000, x=x)
         st = solver.stats()
+        t2 = time.perf_counter()
         solver.close()
+        torch.cuda.synchronize()
+        st["wall_ms"] = {"setup": (t1 - t0) * 1e3, "pcg": (t2 - t1) * 1e3, "close": (time.perf_counter() - t2) * 1e3}
         return info, st
 
     def run_form(label, local_prec, geneo, init, time_dominant):
@@ -464,11 +469,17 @@ def main():
             awg.kernel_timing(True)
         infos, stats = [], []
         t0 = time.perf_counter()
+        step_ms = []
         for i in range(args.steps):
+            ts = time.perf_counter()
             info, st = step(local_prec, geneo, init)
+            step_ms.append((time.perf_counter() - ts) * 1e3)
             infos.append(info)
             stats.append(st)
-            print(f"# {label} step {i}: iters={info['iters']} converged={info['converged']} "
+            wm = st["wall_ms"]
+            print(f"# {label} step {i}: {step_ms[-1]:.1f} ms (set-up {wm['setup']:.1f}, phases "
+                  f"{st['ms']['total']:.1f}, W {st['ms'].get('second_coarse_W', 0.0):.1f}, pcg {wm['pcg']:.1f}, "
+                  f"close {wm['close']:.1f}) iters={info['iters']} converged={info['converged']} "
                   f"true_res={info['rel_res_true']:.2e}", file=sys.stderr, flush=True)
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) * 1e3 / args.steps
@@ -484,7 +495,8 @@ def main():
         lp_peak = {"f32": FP32_PEAK_TFLOPS, "f16x3": FP16_PEAK_TFLOPS / 3.0}.get(local_prec)
         t_peak = ((wk["total"] - (wk["w_local_product"] if lp_peak else 0.0)) / (FP64_PEAK_TFLOPS * 1e12)
                   + (wk["w_local_product"] / (lp_peak * 1e12) if lp_peak else 0.0))
-        rec = {"ms_per_step": round(ms, 3), "accuracy_ok": ok, "worst_true_res": worst,
+        rec = {"ms_per_step": round(ms, 3), "step_ms": [round(v, 1) for v in step_ms],
+               "accuracy_ok": ok, "worst_true_res": worst,
                "setup_roofline": {"flops": wk, "setup_ms": round(st["ms"]["total"], 3),
                                   "ms_at_peak": round(t_peak * 1e3, 3),
                                   "frac": round(t_peak * 1e3 / st["ms"]["total"], 4)},

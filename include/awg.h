@@ -188,6 +188,13 @@ int awg_pcg(awg_ctx* ctx, const double* b, double* x, double tol, int32_t maxit,
  * iterations launched after convergence leave x unchanged. */
 int awg_pcg_graph(awg_ctx* ctx, int32_t enable);
 
+/* The multi-column PCG that builds W (Remark 2, Section 4.4) moves its
+ * active columns to narrower multi-vectors as columns converge (default,
+ * enable != 0); every column is computed independently of the others and of
+ * its position, so W is the same bit for bit either way.  Process-wide;
+ * applies to setups started afterwards.  Returns 0. */
+int awg_w_compaction(int32_t enable);
+
 /* JSON description of the setup (n, N, n_minus, n0, per-subdomain counts,
  * per-phase times in ms).  buf: host buffer of cap bytes.  Returns the
  * number of bytes needed (excluding the terminator) or a negative error. */

@@ -29,6 +29,7 @@ STATUS = {0: "AWG_OK", 1: "AWG_NOT_CONVERGED", -1: "AWG_ERR_ARG", -2: "AWG_ERR_N
 
 EXPORTED = ["awg_default_options", "awg_setup", "awg_apply", "awg_pcg", "awg_stats", "awg_export",
             "awg_last_error", "awg_destroy", "awg_kernel_timing", "awg_kernel_times", "awg_pcg_graph",
+            "awg_w_compaction",
             "awg_dense_gemm", "awg_dense_gemm_ex", "awg_dense_local_product_f16x3", "awg_dense_potrf", "awg_dense_potrf_noalloc", "awg_dense_trsm",
             "awg_dense_low_eigs",
             "awg_mlp_create", "awg_mlp_num_params", "awg_mlp_get_params", "awg_mlp_set_params", "awg_mlp_forward",
@@ -90,6 +91,8 @@ def lib():
     L.awg_destroy.restype = None
     L.awg_pcg_graph.argtypes = [vp, i32]
     L.awg_pcg_graph.restype = ctypes.c_int
+    L.awg_w_compaction.argtypes = [i32]
+    L.awg_w_compaction.restype = ctypes.c_int
     L.awg_kernel_timing_filter.argtypes = [ctypes.c_char_p]
     L.awg_kernel_timing_filter.restype = ctypes.c_int
     L.awg_kernel_timing.argtypes = [i32]
@@ -384,6 +387,12 @@ def dense_local_product_f16x3(sizes, X, P, Y):
     if rc:
         raise AWGError(rc, "awg_dense_local_product_f16x3")
     return Y
+
+
+def w_compaction(enable: bool) -> None:
+    """Process-wide switch of the column compaction in the W solves (on by
+    default; W is the same bit for bit either way)."""
+    lib().awg_w_compaction(int(enable))
 
 
 def probe_mfma_f64(iters: int = 4000) -> float:

@@ -64,6 +64,12 @@ struct DBuf {
     AWG_HIP(hipMalloc((void**)&p, count * sizeof(T)));
     n = count;
   }
+  // keep the allocation when it holds count elements already (the W
+  // solves narrow their multi-vectors without reallocating them)
+  void ensure(size_t count) {
+    if (p && n >= count) return;
+    alloc(count);
+  }
   void zero(hipStream_t s) {
     if (p) AWG_HIP(hipMemsetAsync(p, 0, n * sizeof(T), s));
   }

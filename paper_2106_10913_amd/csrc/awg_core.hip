@@ -252,6 +252,7 @@ struct awg_ctx {
   std::map<std::string, double> tms;
   int w_iters = 0;
   double w_iters_mean = 0.0;    // mean over the W columns of their iteration counts
+  int w_compactions = 0;        // narrowings of the W solves' multi-vectors
   double w_time = 0.0;
   std::vector<double> eig_resid_max;
   std::vector<int> eig_iters;   // subspace GenEO: iteration of convergence per subdomain
@@ -304,6 +305,25 @@ __global__ void k_copy_cols(const double* src, int b, double* dst, long ldd, lon
   const long r = e / bc;
   const int c = (int)(e % bc);
   dst[r * ldd + c0 + c] = src[r * b + c];
+}
+
+// dst (rows x bn, row-major) = the columns perm[0 .. bn) of src (rows x bo)
+__global__ void k_gather_cols(long rows, int bo, const double* src, int bn, const int* perm, double* dst) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= rows * bn) return;
+  const long r = e / bn;
+  const int j = (int)(e - r * bn);
+  dst[e] = src[r * bo + perm[j]];
+}
+
+// W[:, dst[j]] = X[:, pos[j]] for j < cnt (X rows x b, W rows x ldw, row-major)
+__global__ void k_copy_cols_list(long rows, int b, const double* X, const int* pos, const int* dst, int cnt,
+                                 double* W, long ldw) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= rows * cnt) return;
+  const long r = e / cnt;
+  const int j = (int)(e - r * cnt);
+  W[r * ldw + dst[j]] = X[r * b + pos[j]];
 }
 
 // right-hand sides of W, row-major n x b: column gc = g0_s + j - c0 holds
@@ -463,22 +483,22 @@ void build_ws(awg_ctx& c, MultiWS& w, int b) {
   hipStream_t s = c.s;
   w.b = b;
   const long n = c.n;
-  w.R.alloc(n * b);
+  w.R.ensure(n * b);
   // T1 and Z are inputs of A_+ products: LV.cols extra rows hold the
   // coefficient rows of the [A | V_-] product
-  w.Z.alloc((n + c.LV.cols) * b);
-  w.T1.alloc((n + c.LV.cols) * b);
-  w.T2.alloc(n * b);
-  w.Xs.alloc(c.sumns * b);
-  w.Os.alloc(c.sumns * b);
-  w.Tk.alloc(std::max<long>(1, c.LV.cols) * b);
-  w.G0.alloc(std::max(1, c.n0) * (long)b);
-  w.G1.alloc((std::max(1, c.n0) + c.LV.cols) * (long)b);   // u0 and, below, |L_-| C u0
-  w.G2.alloc(std::max(1, c.n0) * (long)b);
-  w.H0.alloc(std::max(1, c.nminus) * (long)b);
-  w.H1.alloc(std::max(1, c.nminus) * (long)b);
-  w.dotpart.alloc(std::max<long>(2L * DOT_CHUNKS_H * b, DOT1_BLOCKS));
-  w.dots.alloc(2L * b);
+  w.Z.ensure((n + c.LV.cols) * b);
+  w.T1.ensure((n + c.LV.cols) * b);
+  w.T2.ensure(n * b);
+  w.Xs.ensure(c.sumns * b);
+  w.Os.ensure(c.sumns * b);
+  w.Tk.ensure(std::max<long>(1, c.LV.cols) * b);
+  w.G0.ensure(std::max(1, c.n0) * (long)b);
+  w.G1.ensure((std::max(1, c.n0) + c.LV.cols) * (long)b);   // u0 and, below, |L_-| C u0
+  w.G2.ensure(std::max(1, c.n0) * (long)b);
+  w.H0.ensure(std::max(1, c.nminus) * (long)b);
+  w.H1.ensure(std::max(1, c.nminus) * (long)b);
+  w.dotpart.ensure(std::max<long>(2L * DOT_CHUNKS_H * b, DOT1_BLOCKS));
+  w.dots.ensure(2L * b);
   if (b == 1) w.gvpart.alloc((long)GEMV_KSPLIT * std::max(1, c.nminus));
   std::vector<GemmDesc> vt(c.N), vv(c.N), yt(c.N), yy(c.N), pp(c.N);
   w.maxk = w.maxm = w.maxns = 0;
@@ -516,7 +536,7 @@ void build_ws(awg_ctx& c, MultiWS& w, int b) {
       pm[q] = GemmDescMix{w.Xs.p + so, c.P32.p + c.sqoff[q], w.Os.p + so, b, nsq, nsq, b, nsq, b};
     }
     w.dP32.upload(pm, s);
-    w.Xs32.alloc(c.sumns * b);
+    w.Xs32.ensure(c.sumns * b);
     std::vector<GemmDescF32> pf(c.N);
     for (int q = 0; q < c.N; ++q) {
       const int nsq = c.ns[q];
@@ -536,8 +556,8 @@ void build_ws(awg_ctx& c, MultiWS& w, int b) {
   }
   if (c.P16.p && b > 1) {
     w.xs16_plane = c.h3_groups * (long)b * 8;
-    w.Xs16.alloc(2 * (size_t)w.xs16_plane);
-    w.emax.alloc(b);
+    w.Xs16.ensure(2 * (size_t)w.xs16_plane);
+    w.emax.ensure(b);
     std::vector<GemmDescH3> ph(c.N);
     for (int q = 0; q < c.N; ++q) {
       const int nsq = c.ns[q];
@@ -568,8 +588,8 @@ void build_ws(awg_ctx& c, MultiWS& w, int b) {
     gemm_upload(w.dAYt, ay, s);
   }
   if (c.opt.coarse2 == AWG_COARSE2_HYB && c.nminus > 0) {
-    w.R3.alloc(c.n * (long)b);
-    w.H2b.alloc(std::max(1, c.nminus) * (long)b);
+    w.R3.ensure(c.n * (long)b);
+    w.H2b.ensure(std::max(1, c.nminus) * (long)b);
     gemm_upload(w.dWT1, {mk(w.H1, c.W, nm, w.T1, c.n, c.nminus, false, b)}, s);
     gemm_upload(w.dWtT1, {mk(w.T1, c.W, nm, w.H0, c.nminus, c.n, true, b)}, s);
     gemm_upload(w.dEW2, {mk(w.H0, c.EWinv, nm, w.H2b, c.nminus, c.nminus, false, b)}, s);
@@ -809,6 +829,10 @@ void op_h(awg_ctx& c, MultiWS& w, bool f32) {
 }
 
 void sync(awg_ctx& c) { AWG_HIP(hipStreamSynchronize(c.s)); }
+
+// compaction of the converged columns of the W solves (process-wide switch,
+// for the test that compares the two)
+int g_w_compaction = 1;
 
 struct PhaseTimer {
   awg_ctx& c;
@@ -1746,32 +1770,56 @@ void phase_W(awg_ctx& c) {
   DBuf<long> dgcoff;
   dgcoff.upload(gcoff, s);
   c.W.alloc((long)c.n * c.nminus);
-  const int b = balanced_chunk(c.nminus, 2048);
+  const int b0 = balanced_chunk(c.nminus, 2048);
   MultiWS w;
-  build_ws(c, w, b);
-  DBuf<double> X, Pm, Q;
-  X.alloc((long)c.n * b);
-  Pm.alloc(((long)c.n + c.LV.cols) * b);     // input of A_+ products (coefficient rows below)
-  Q.alloc((long)c.n * b);
-  double* dots = w.dots.p;
+  build_ws(c, w, b0);
+  DBuf<double> X, Pm, Q, Zold, tmp;
   DBuf<double> alpha_d;
-  alpha_d.alloc(b);
-  std::vector<double> bn(b), rz(b), alpha(b), beta(b);
-  std::vector<char> active(b);
+  alpha_d.alloc(b0);
+  const bool f32 = c.opt.local_prec != AWG_LOCAL_F64;
   int itmax = 0;
   double colits = 0.0;
-  auto coldot = [&](const double* A, const double* B) {
-    l_coldot(c.n, b, A, B, w.dotpart, dots, s);
-    std::vector<double> h(b);
-    AWG_HIP(hipMemcpyAsync(h.data(), dots, sizeof(double) * b, hipMemcpyDeviceToHost, s));
-    AWG_HIP(hipStreamSynchronize(s));
-    return h;
+  // the multi-vectors at the current width b (columns compacted as they converge)
+  // (allocated once at the full width; narrower widths reuse them)
+  auto alloc_vectors = [&](int b) {
+    X.ensure((long)c.n * b);
+    Pm.ensure(((long)c.n + c.LV.cols) * b);     // input of A_+ products (coefficient rows below)
+    Q.ensure((long)c.n * b);
+    if (f32) Zold.ensure((long)c.n * b);
+    tmp.ensure(((long)c.n + c.LV.cols) * b);    // target of the column compaction
   };
-  const bool f32 = c.opt.local_prec != AWG_LOCAL_F64;
-  DBuf<double> Zold;
-  if (f32) Zold.alloc((long)c.n * b);
-  for (int c0 = 0; c0 < c.nminus; c0 += b) {
-    const int bc = std::min(b, c.nminus - c0);
+  alloc_vectors(b0);
+  DBuf<int> dpos, ddst;
+  // write the columns pos[] of X (width b) into W at the original columns dst[]
+  auto write_cols = [&](int b, const std::vector<int>& pos, const std::vector<int>& dst) {
+    if (pos.empty()) return;
+    dpos.upload(pos, s);
+    ddst.upload(dst, s);
+    hipLaunchKernelGGL(k_copy_cols_list, dim3(cdiv((long)c.n * pos.size(), 256)), dim3(256), 0, s, (long)c.n, b,
+                       X.p, dpos.p, ddst.p, (int)pos.size(), c.W.p, (long)c.nminus);
+    AWG_LAUNCH_CHECK();
+    sync(c);   // pos / dst are host vectors of the caller
+  };
+  for (int c0 = 0; c0 < c.nminus; c0 += b0) {
+    const int bc = std::min(b0, c.nminus - c0);
+    int b = b0;
+    if (w.b != b0) {
+      build_ws(c, w, b0);
+      alloc_vectors(b0);
+    }
+    double* dots = w.dots.p;
+    // colid[j]: the W column held at position j (-1: padding)
+    std::vector<int> colid(b);
+    for (int j = 0; j < b; ++j) colid[j] = j < bc ? c0 + j : -1;
+    auto coldot = [&](const double* A, const double* B) {
+      l_coldot(c.n, b, A, B, w.dotpart, dots, s);
+      std::vector<double> h(b);
+      AWG_HIP(hipMemcpyAsync(h.data(), dots, sizeof(double) * b, hipMemcpyDeviceToHost, s));
+      AWG_HIP(hipStreamSynchronize(s));
+      return h;
+    };
+    std::vector<double> bn(b), rz(b), alpha(b), beta(b);
+    std::vector<char> active(b);
     w.R.zero(s);
     hipLaunchKernelGGL(k_build_vg, dim3(64, c.N), dim3(256), 0, s, c.subptr.p, c.subidx.p, c.V.p, c.LV.d_eoff.p,
                        dgcoff.p, w.R.p, c0, b);
@@ -1809,6 +1857,60 @@ void phase_W(awg_ctx& c) {
         nact += active[j];
       }
       if (nact == 0) { ++it; break; }
+      // compaction: once a quarter of the width (at least 128 columns) has
+      // converged, the converged columns are written to W and the active ones
+      // moved to the front of narrower multi-vectors.  Every kernel computes
+      // each column independently of the others and of its position, so the
+      // iterates are those of the full width, bit for bit.
+      const int bnew = nact + (nact & 1);   // even widths keep the 16-byte paths
+      if (g_w_compaction && b - bnew >= std::max(128, b / 4)) {
+        std::vector<int> pos, dst, perm;
+        for (int j = 0; j < b; ++j) {
+          if (active[j]) perm.push_back(j);
+          else if (colid[j] >= 0) { pos.push_back(j); dst.push_back(colid[j]); }
+        }
+        write_cols(b, pos, dst);
+        for (int j = 0; (int)perm.size() < bnew; ++j)   // padding: an inactive position
+          if (!active[j]) perm.push_back(j);
+        DBuf<int> dperm;
+        dperm.upload(perm, s);
+        // each multi-vector is gathered into the spare buffer, which then
+        // takes its place (every buffer keeps its full-width allocation)
+        auto gather = [&](DBuf<double>& A) {
+          if (tmp.n < A.n) tmp.alloc(A.n);
+          hipLaunchKernelGGL(k_gather_cols, dim3(cdiv((long)c.n * bnew, 256)), dim3(256), 0, s, (long)c.n, b, A.p,
+                             bnew, dperm.p, tmp.p);
+          AWG_LAUNCH_CHECK();
+          std::swap(A.p, tmp.p);
+          std::swap(A.n, tmp.n);
+        };
+        gather(Pm);   // the largest first: the spare buffer then fits every other one
+        gather(X);
+        gather(w.R);
+        if (f32) gather(Zold);
+        sync(c);
+        build_ws(c, w, bnew);   // descriptors at the new width; R and the buffers are kept
+        dots = w.dots.p;
+        std::vector<int> cid(bnew), act(bnew);
+        std::vector<double> bn2(bnew), rz2(bnew);
+        for (int j = 0; j < bnew; ++j) {
+          const int o = perm[j];
+          const bool pad = j >= nact;
+          cid[j] = pad ? -1 : colid[o];
+          act[j] = pad ? 0 : 1;
+          bn2[j] = bn[o];
+          rz2[j] = rz[o];
+        }
+        colid.swap(cid);
+        bn.swap(bn2);
+        rz.swap(rz2);
+        active.assign(act.begin(), act.end());
+        b = bnew;
+        ++c.w_compactions;
+        alpha.assign(b, 0.0);
+        beta.assign(b, 0.0);
+        h.assign(b, 0.0);
+      }
       op_h2(c, w, f32);
       // r^T z and, for the FP32 local operators, r^T z_old (flexible
       // Polak-Ribiere beta) in one pass over R
@@ -1826,11 +1928,15 @@ void phase_W(awg_ctx& c) {
       sync(c);   // the host buffer of beta is reused next iteration
     }
     itmax = std::max(itmax, it);
-    for (int j = 0; j < bc; ++j)
+    for (int j = 0; j < b; ++j)
       if (active[j]) throw Error(AWG_ERR_NOT_SPD, "PCG with A_+ for W did not converge within w_maxit");
-    hipLaunchKernelGGL(k_copy_cols, dim3(cdiv((long)c.n * bc, 256)), dim3(256), 0, s, X.p, b, c.W.p, (long)c.nminus,
-                       (long)c.n, c0, bc);
-    AWG_LAUNCH_CHECK();
+    std::vector<int> pos, dst;
+    for (int j = 0; j < b; ++j)
+      if (colid[j] >= 0) {
+        pos.push_back(j);
+        dst.push_back(colid[j]);
+      }
+    write_cols(b, pos, dst);
   }
   c.w_iters = itmax;
   c.w_iters_mean = colits / std::max(1, c.nminus);
@@ -2122,7 +2228,7 @@ std::string stats_json(const awg_ctx& c) {
     o << "]";
   };
   o << "{\"n\":" << c.n << ",\"nnz\":" << c.nnz << ",\"N\":" << c.N << ",\"sum_ns\":" << c.sumns
-    << ",\"n_minus\":" << c.nminus << ",\"n0\":" << c.n0 << ",\"w_iters\":" << c.w_iters << ",\"w_iters_mean\":" << c.w_iters_mean
+    << ",\"n_minus\":" << c.nminus << ",\"n0\":" << c.n0 << ",\"w_iters\":" << c.w_iters << ",\"w_iters_mean\":" << c.w_iters_mean << ",\"w_compactions\":" << c.w_compactions
     << ",\"local_prec\":" << c.opt.local_prec << ",\"tau\":" << c.opt.tau << ",";
   arr("k_s", c.ks);
   o << ",";
@@ -2323,6 +2429,11 @@ int64_t awg_export(const awg_ctx* c, const char* name, void* buf, size_t cap) {
 }
 
 const char* awg_last_error(const awg_ctx* c) { return c ? c->err.c_str() : g_setup_error.c_str(); }
+
+int awg_w_compaction(int32_t enable) {
+  g_w_compaction = enable != 0;
+  return AWG_OK;
+}
 
 int awg_pcg_graph(awg_ctx* c, int32_t enable) {
   if (!c) return AWG_ERR_ARG;
