@@ -478,7 +478,9 @@ def main():
             stats.append(st)
             wm = st["wall_ms"]
             print(f"# {label} step {i}: {step_ms[-1]:.1f} ms (set-up {wm['setup']:.1f}, phases "
-                  f"{st['ms']['total']:.1f}, W {st['ms'].get('second_coarse_W', 0.0):.1f}, pcg {wm['pcg']:.1f}, "
+                  f"{st['ms']['total']:.1f}, W {st['ms'].get('second_coarse_W', 0.0):.1f} (alloc "
+                  f"{st['ms'].get('alloc:second_coarse_W', 0.0):.1f}), coarse0 {st['ms'].get('coarse0', 0.0):.1f} "
+                  f"(alloc {st['ms'].get('alloc:coarse0', 0.0):.1f}), pcg {wm['pcg']:.1f}, "
                   f"close {wm['close']:.1f}) iters={info['iters']} converged={info['converged']} "
                   f"true_res={info['rel_res_true']:.2e}", file=sys.stderr, flush=True)
         torch.cuda.synchronize()
@@ -496,6 +498,8 @@ def main():
         t_peak = ((wk["total"] - (wk["w_local_product"] if lp_peak else 0.0)) / (FP64_PEAK_TFLOPS * 1e12)
                   + (wk["w_local_product"] / (lp_peak * 1e12) if lp_peak else 0.0))
         rec = {"ms_per_step": round(ms, 3), "step_ms": [round(v, 1) for v in step_ms],
+               "step_phases_ms": [{k: round(v, 1) for k, v in s_["ms"].items()} for s_ in stats],
+               "step_eig_fallbacks": [s_["eig_fallbacks"] for s_ in stats],
                "accuracy_ok": ok, "worst_true_res": worst,
                "setup_roofline": {"flops": wk, "setup_ms": round(st["ms"]["total"], 3),
                                   "ms_at_peak": round(t_peak * 1e3, 3),

@@ -195,6 +195,14 @@ int awg_pcg_graph(awg_ctx* ctx, int32_t enable);
  * applies to setups started afterwards.  Returns 0. */
 int awg_w_compaction(int32_t enable);
 
+/* Device memory released by the library (awg_destroy, the work buffers of a
+ * set-up) is kept in a process-wide cache and reused by later allocations of
+ * a similar size on the same device, so repeated set-ups allocate nothing
+ * from the driver.  This call returns every cached block to the driver
+ * (the device is synchronised first) and stores the number of bytes freed in
+ * *bytes_out when it is not NULL.  Returns 0. */
+int awg_free_cached_memory(uint64_t* bytes_out);
+
 /* JSON description of the setup (n, N, n_minus, n0, per-subdomain counts,
  * per-phase times in ms).  buf: host buffer of cap bytes.  Returns the
  * number of bytes needed (excluding the terminator) or a negative error. */

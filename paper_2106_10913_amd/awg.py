@@ -29,7 +29,7 @@ STATUS = {0: "AWG_OK", 1: "AWG_NOT_CONVERGED", -1: "AWG_ERR_ARG", -2: "AWG_ERR_N
 
 EXPORTED = ["awg_default_options", "awg_setup", "awg_apply", "awg_pcg", "awg_stats", "awg_export",
             "awg_last_error", "awg_destroy", "awg_kernel_timing", "awg_kernel_times", "awg_pcg_graph",
-            "awg_w_compaction",
+            "awg_w_compaction", "awg_free_cached_memory",
             "awg_dense_gemm", "awg_dense_gemm_ex", "awg_dense_local_product_f16x3", "awg_dense_potrf", "awg_dense_potrf_noalloc", "awg_dense_trsm",
             "awg_dense_low_eigs",
             "awg_mlp_create", "awg_mlp_num_params", "awg_mlp_get_params", "awg_mlp_set_params", "awg_mlp_forward",
@@ -93,6 +93,8 @@ def lib():
     L.awg_pcg_graph.restype = ctypes.c_int
     L.awg_w_compaction.argtypes = [i32]
     L.awg_w_compaction.restype = ctypes.c_int
+    L.awg_free_cached_memory.argtypes = [vp]
+    L.awg_free_cached_memory.restype = ctypes.c_int
     L.awg_kernel_timing_filter.argtypes = [ctypes.c_char_p]
     L.awg_kernel_timing_filter.restype = ctypes.c_int
     L.awg_kernel_timing.argtypes = [i32]
@@ -387,6 +389,14 @@ def dense_local_product_f16x3(sizes, X, P, Y):
     if rc:
         raise AWGError(rc, "awg_dense_local_product_f16x3")
     return Y
+
+
+def free_cached_memory() -> int:
+    """Return the library's cached device blocks to the driver; the number of
+    bytes freed."""
+    out = ctypes.c_uint64(0)
+    lib().awg_free_cached_memory(ctypes.byref(out))
+    return int(out.value)
 
 
 def w_compaction(enable: bool) -> None:

@@ -45,6 +45,22 @@ __device__ inline double block_sum_256(double v, double* sh4) {
 // ---------------------------------------------------------------------------
 // device buffers
 // ---------------------------------------------------------------------------
+// wall time (ms) spent in the device allocations and frees of DBuf,
+// process-wide; the set-up reports its share per phase
+extern double g_alloc_ms;
+double alloc_clock_ms();
+
+// Device memory of DBuf goes through a process-wide cache: a freed block is
+// kept (after a device synchronisation, as hipFree does) and handed out again
+// to a later allocation of at most its size and at least half of it, on the
+// same device.  Repeated set-ups then allocate nothing from the driver, whose
+// large allocations and frees took up to seconds on some calls.  An
+// allocation that fails empties the cache and retries; dev_cache_trim returns
+// every cached block to the driver.
+void* dev_alloc(size_t bytes);
+void dev_free(void* p, size_t bytes);
+size_t dev_cache_trim();
+
 template <class T>
 struct DBuf {
   T* p = nullptr;
@@ -54,14 +70,20 @@ struct DBuf {
   DBuf& operator=(const DBuf&) = delete;
   ~DBuf() { release(); }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p) {
+      const double t = alloc_clock_ms();
+      dev_free(p, n * sizeof(T));
+      g_alloc_ms += alloc_clock_ms() - t;
+    }
     p = nullptr;
     n = 0;
   }
   void alloc(size_t count) {
     release();
     if (count == 0) return;
-    AWG_HIP(hipMalloc((void**)&p, count * sizeof(T)));
+    const double t = alloc_clock_ms();
+    p = (T*)dev_alloc(count * sizeof(T));
+    g_alloc_ms += alloc_clock_ms() - t;
     n = count;
   }
   // keep the allocation when it holds count elements already (the W

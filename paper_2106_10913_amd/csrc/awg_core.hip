@@ -12,6 +12,7 @@
 #include <cstring>
 #include <functional>
 #include <map>
+#include <mutex>
 #include <sstream>
 
 #include "awg.h"
@@ -105,6 +106,70 @@ std::string ktimer_json(bool reset) {
   o << "}";
   if (reset) g_kt_acc.clear();
   return o.str();
+}
+
+double g_alloc_ms = 0.0;
+double alloc_clock_ms() {
+  using namespace std::chrono;
+  return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+namespace {
+struct CachedBlock {
+  void* p;
+  size_t bytes;
+  int dev;
+};
+std::mutex g_cache_mu;
+std::vector<CachedBlock> g_cache;
+}  // namespace
+
+void* dev_alloc(size_t bytes) {
+  int dev = 0;
+  AWG_HIP(hipGetDevice(&dev));
+  {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    int best = -1;
+    for (int i = 0; i < (int)g_cache.size(); ++i) {
+      const CachedBlock& b = g_cache[i];
+      if (b.dev == dev && b.bytes >= bytes && b.bytes / 2 <= bytes && (best < 0 || b.bytes < g_cache[best].bytes))
+        best = i;
+    }
+    if (best >= 0) {
+      void* p = g_cache[best].p;
+      g_cache.erase(g_cache.begin() + best);
+      return p;
+    }
+  }
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    dev_cache_trim();
+    AWG_HIP(hipMalloc(&p, bytes));
+  }
+  return p;
+}
+
+void dev_free(void* p, size_t bytes) {
+  if (!p) return;
+  // queued work of any stream may still use the block
+  (void)hipDeviceSynchronize();
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  g_cache.push_back(CachedBlock{p, bytes, dev});
+}
+
+size_t dev_cache_trim() {
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  size_t tot = 0;
+  if (!g_cache.empty()) (void)hipDeviceSynchronize();
+  for (const CachedBlock& b : g_cache) {
+    (void)hipFree(b.p);
+    tot += b.bytes;
+  }
+  g_cache.clear();
+  return tot;
 }
 }  // namespace awg
 
@@ -834,17 +899,21 @@ void sync(awg_ctx& c) { AWG_HIP(hipStreamSynchronize(c.s)); }
 // for the test that compares the two)
 int g_w_compaction = 1;
 
+// wall time of a set-up phase, and (key "alloc:<phase>") the part of it
+// spent in device allocations and frees
 struct PhaseTimer {
   awg_ctx& c;
   std::string name;
-  double t0;
+  double t0, a0;
   PhaseTimer(awg_ctx& c_, const char* nm) : c(c_), name(nm) {
     sync(c);
     t0 = now_ms();
+    a0 = g_alloc_ms;
   }
   ~PhaseTimer() {
     (void)hipStreamSynchronize(c.s);
     c.tms[name] += now_ms() - t0;
+    c.tms["alloc:" + name] += g_alloc_ms - a0;
   }
 };
 
@@ -2429,6 +2498,12 @@ int64_t awg_export(const awg_ctx* c, const char* name, void* buf, size_t cap) {
 }
 
 const char* awg_last_error(const awg_ctx* c) { return c ? c->err.c_str() : g_setup_error.c_str(); }
+
+int awg_free_cached_memory(uint64_t* bytes_out) {
+  const size_t b = dev_cache_trim();
+  if (bytes_out) *bytes_out = (uint64_t)b;
+  return AWG_OK;
+}
 
 int awg_w_compaction(int32_t enable) {
   g_w_compaction = enable != 0;
