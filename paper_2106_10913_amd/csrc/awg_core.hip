@@ -2056,6 +2056,15 @@ void phase_capacitance(awg_ctx& c) {
   c.nminus_dropped = spd_inverse(c, C, nm, c.EWinv, "capacitance matrix L^-1 - V^T W", &c.ew_margin);
 }
 
+// out[i] = sum over q < parts of part[q * len + i], in the order of q
+__global__ void k_sum_parts(long len, int parts, const double* part, double* out) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= len) return;
+  double acc = 0.0;
+  for (int q = 0; q < parts; ++q) acc += part[(long)q * len + i];
+  out[i] = acc;
+}
+
 void phase_EW(awg_ctx& c) {
   PhaseTimer t(c, "second_coarse_EW");
   if (c.nminus == 0) return;
@@ -2068,10 +2077,25 @@ void phase_EW(awg_ctx& c) {
   AW.alloc((long)c.n * c.nminus);
   EW.alloc((long)c.nminus * c.nminus);
   l_spmm(c.n, c.nnz, c.rowptr, c.col, c.val, c.W.p, AW.p, c.nminus, 1.0, 0.0, s, &c.sgrp);   // A W
-  // E_W = W^T (A W): column-major views W_rm (n_minus x n) and AW_rm -> W_rm AW_rm^T
+  // E_W = W^T (A W): column-major views W_rm (n_minus x n) and AW_rm -> W_rm AW_rm^T,
+  // the long k = n split into KS ranges (batch entries writing partial
+  // products, summed in a fixed order) so that the launch fills the device
+  const int KS = (int)std::max<long>(1, std::min<long>(16, c.n / 4096));
+  const long nm2 = (long)c.nminus * c.nminus;
+  DBuf<double> part;
+  part.alloc(nm2 * KS);
+  std::vector<GemmDesc> hg(KS);
+  for (int q = 0; q < KS; ++q) {
+    const long k0 = (long)c.n * q / KS, k1 = (long)c.n * (q + 1) / KS;
+    hg[q] = GemmDesc{c.W.p + k0 * c.nminus, AW.p + k0 * c.nminus, part.p + q * nm2, c.nminus, c.nminus,
+                     (int)(k1 - k0), c.nminus, c.nminus, c.nminus};
+  }
   DBuf<GemmDesc> g;
-  g.upload({GemmDesc{c.W.p, AW.p, EW.p, c.nminus, c.nminus, c.n, c.nminus, c.nminus, c.nminus}}, s);
-  gemm_batched(g, 1, c.nminus, c.nminus, false, true, 1.0, 0.0, false, s, 2.0 * c.n * (double)c.nminus * c.nminus);
+  g.upload(hg, s);
+  gemm_batched(g, KS, c.nminus, c.nminus, false, true, 1.0, 0.0, false, s, 2.0 * c.n * (double)c.nminus * c.nminus,
+               "EW");
+  hipLaunchKernelGGL(k_sum_parts, dim3(cdiv(nm2, 256)), dim3(256), 0, s, nm2, KS, part.p, EW.p);
+  AWG_LAUNCH_CHECK();
   c.nminus_dropped = spd_inverse(c, EW, c.nminus, c.EWinv, "second coarse matrix W^T A W", &c.ew_margin);
 }
 
