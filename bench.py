@@ -51,6 +51,8 @@ def parse():
                     help="second-coarse-space preconditioner H3 (both forms); ad is the default line")
     ap.add_argument("--h2", default="nn_hyb", choices=["nn_hyb", "asp_hyb", "asp_ad", "as_hyb"],
                     help="two-level preconditioner for A_+ (both forms); nn_hyb is the default line")
+    ap.add_argument("--w-h2", default="asp_ad", choices=["asp_ad", "asp_hyb", "nn_hyb"],
+                    help="preconditioner of the W solves (with h2 = nn_hyb); nn_hyb is H2 itself")
     ap.add_argument("--w-rtol", type=float, default=1e-10,
                     help="relative residual of the PCG solves for W (the paper's choice is 1e-10)")
     ap.add_argument("--fast-local", default="f32", choices=["f32", "f16x3"],
@@ -438,7 +440,7 @@ def main():
         t0 = time.perf_counter()
         solver = awg.Solver(Ad, Sd, tau=w.tau, local_prec=local_prec, geneo=geneo, eig_init=init,
                             coords=coords if init is not None else None, coarse2=args.coarse2,
-                            w_rtol=args.w_rtol, h2=args.h2)
+                            w_rtol=args.w_rtol, h2=args.h2, w_h2=args.w_h2)
         t1 = time.perf_counter()
         _, info = solver.pcg(bd, tol=w.tol, maxit=1000, x=x)
         st = solver.stats()
@@ -552,7 +554,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOADS[args.workload][1], "form": head_label,
                    "n": int(A.shape[0]), "nnz": int(A.nnz), "N": len(w.subs), "tol": w.tol,
-                   "coarse2": args.coarse2, "h2": args.h2, "w_rtol": args.w_rtol},
+                   "coarse2": args.coarse2, "h2": args.h2, "w_h2": args.w_h2 if args.h2 == "nn_hyb" else args.h2,
+                   "w_rtol": args.w_rtol},
         "accuracy_ok": head["accuracy_ok"] and (plain is None or plain["accuracy_ok"]),
     }
     if plain is not None and head is not plain:

@@ -138,6 +138,15 @@ typedef struct {
   int32_t coord_dim;     /* 1..3 when coords is given */
   int32_t coarse2;       /* AWG_COARSE2_AD (default), AWG_COARSE2_INEX or AWG_COARSE2_HYB */
   int32_t h2;            /* AWG_H2_NN_HYB (default), AWG_H2_ASP_HYB, AWG_H2_ASP_AD or AWG_H2_AS_HYB */
+  int32_t w_h2;          /* preconditioner of the PCG solves with A_+ that build
+                            W (Remark 2, Section 4.4) when h2 = AWG_H2_NN_HYB:
+                            AWG_H2_ASP_AD (default), AWG_H2_ASP_HYB or
+                            AWG_H2_NN_HYB (H2 itself).  Any SPD preconditioner
+                            of A_+ gives the same W to w_rtol; H^AS_+,ad(1/tau)
+                            (Theorem on H^AS_+,hyb/ad, Section 3.4) shares R0
+                            and E0 with H^NN_hyb(tau) and costs one coarse solve
+                            and one local pass per application.  With any other
+                            h2 the W solves use h2 itself. */
 } awg_options;
 
 /* Fill every field of *opt with the defaults above (tau = 0.1).  Host pointer. */

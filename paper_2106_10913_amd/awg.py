@@ -45,7 +45,7 @@ class Options(ctypes.Structure):
                 ("geneo_solver", ctypes.c_int32), ("eig_block", ctypes.c_int32), ("eig_maxit", ctypes.c_int32),
                 ("eig_seed", ctypes.c_int32), ("eig_tol", ctypes.c_double), ("eig_init", ctypes.c_void_p),
                 ("coords", ctypes.c_void_p), ("coord_dim", ctypes.c_int32), ("coarse2", ctypes.c_int32),
-                ("h2", ctypes.c_int32)]
+                ("h2", ctypes.c_int32), ("w_h2", ctypes.c_int32)]
 
 
 class PCGInfo(ctypes.Structure):
@@ -205,7 +205,8 @@ class Solver:
     def __init__(self, A, subs, tau: float = 0.1, local_prec: str = "f64", w_rtol: float = 1e-10,
                  w_maxit: int = 500, zero_tol: float = 1e-12, device: str = "cuda", geneo: str = "dense",
                  eig_block: int = 16, eig_maxit: int = 200, eig_tol: float = 1e-10, eig_seed: int = 0,
-                 eig_init: "MLP | None" = None, coords=None, coarse2: str = "ad", h2: str = "nn_hyb"):
+                 eig_init: "MLP | None" = None, coords=None, coarse2: str = "ad", h2: str = "nn_hyb",
+                 w_h2: str = "asp_ad"):
         import torch
         L = lib()
         self._torch = torch
@@ -251,6 +252,9 @@ class Solver:
         if h2 not in H2:
             raise ValueError("h2 must be one of " + ", ".join(H2))
         opt.h2 = H2[h2]
+        if w_h2 not in ("nn_hyb", "asp_hyb", "asp_ad"):
+            raise ValueError("w_h2 must be one of nn_hyb, asp_hyb, asp_ad")
+        opt.w_h2 = H2[w_h2]
         opt.eig_block = eig_block
         opt.eig_maxit = eig_maxit
         opt.eig_tol = eig_tol

@@ -214,6 +214,8 @@ constexpr double GRAM_DROP_TOL = 1e-10;
 
 struct MultiWS {
   int b = 0;
+  int h2mode = 0;       // AWG_H2_* applied by op_h2 on this workspace
+  bool wops = false;    // local products with the W solves' operators
   DBuf<double> R, Z, T1, T2;          // n x b
   DBuf<double> Xs, Os;                // sum n_s x b (restricted rows, subdomain order)
   DBuf<double> Tk;                    // sum k_s x b
@@ -299,6 +301,14 @@ struct awg_ctx {
   DBuf<_Float16> P16;
   long p16_plane = 0;
   DBuf<int> p16_sp, h3_row0, h3_cnt;
+  // the local operators of the preconditioner of the W solves when it is not
+  // H2 itself (w_h2 with h2 = H^NN_hyb): P^s = (R^s A_+ R^sT)^{-1} of
+  // H^AS_+ and their reduced-precision copies
+  int wmode = 0;          // AWG_H2_* of the W solves
+  DBuf<double> Pw;
+  DBuf<float> P32w;
+  DBuf<_Float16> P16w;
+  DBuf<int> p16_sp_w;
   DBuf<long> p16_off;
   std::vector<long> h_p16_off, h3_gofs;
   long h3_groups = 0;
@@ -544,7 +554,14 @@ void bmm(const DBuf<GemmDesc>& d, int batch, int maxout, int maxk, bool transM, 
 void gemm_upload(DBuf<GemmDesc>& d, const std::vector<GemmDesc>& h, hipStream_t s) { d.upload(h, s); }
 
 // build the b-column workspace and its descriptors
-void build_ws(awg_ctx& c, MultiWS& w, int b) {
+void build_ws(awg_ctx& c, MultiWS& w, int b, bool wops = false) {
+  // the W solves may run their own preconditioner (c.wmode) with its own
+  // local operators; everything else applies H2 as chosen (c.opt.h2)
+  w.wops = wops && c.wmode != c.opt.h2;
+  w.h2mode = wops ? c.wmode : c.opt.h2;
+  const DBuf<double>& Pl = w.wops ? c.Pw : c.P;
+  const DBuf<float>& P32l = w.wops ? c.P32w : c.P32;
+  const DBuf<_Float16>& P16l = w.wops ? c.P16w : c.P16;
   hipStream_t s = c.s;
   w.b = b;
   const long n = c.n;
@@ -586,19 +603,19 @@ void build_ws(awg_ctx& c, MultiWS& w, int b) {
     vv[q] = mk(w.Tk.p + c.LV.coff[q] * b, Vq, nsq, w.Os.p + so, nsq, kq, true, b);
     yt[q] = mk(xs, Yq, nsq, w.G0.p + c.LY.coff[q] * b, mq, nsq, false, b);
     yy[q] = mk(w.G1.p + c.LY.coff[q] * b, Yq, nsq, w.Os.p + so, nsq, mq, true, b);
-    pp[q] = mk(xs, c.P.p + c.sqoff[q], nsq, w.Os.p + so, nsq, nsq, false, b);
+    pp[q] = mk(xs, Pl.p + c.sqoff[q], nsq, w.Os.p + so, nsq, nsq, false, b);
   }
   gemm_upload(w.dVt, vt, s);
   gemm_upload(w.dV, vv, s);
   gemm_upload(w.dYt, yt, s);
   gemm_upload(w.dY, yy, s);
   gemm_upload(w.dP, pp, s);
-  if (c.P32.p && b > 1) {
+  if (P32l.p && b > 1) {
     std::vector<GemmDescMix> pm(c.N);
     for (int q = 0; q < c.N; ++q) {
       const int nsq = c.ns[q];
       const long so = c.h_subptr[q] * b;
-      pm[q] = GemmDescMix{w.Xs.p + so, c.P32.p + c.sqoff[q], w.Os.p + so, b, nsq, nsq, b, nsq, b};
+      pm[q] = GemmDescMix{w.Xs.p + so, P32l.p + c.sqoff[q], w.Os.p + so, b, nsq, nsq, b, nsq, b};
     }
     w.dP32.upload(pm, s);
     w.Xs32.ensure(c.sumns * b);
@@ -606,7 +623,7 @@ void build_ws(awg_ctx& c, MultiWS& w, int b) {
     for (int q = 0; q < c.N; ++q) {
       const int nsq = c.ns[q];
       const long so = c.h_subptr[q] * b;
-      pf[q] = GemmDescF32{w.Xs32.p + so, c.P32.p + c.sqoff[q], w.Os.p + so, b, nsq, nsq, b, nsq, b};
+      pf[q] = GemmDescF32{w.Xs32.p + so, P32l.p + c.sqoff[q], w.Os.p + so, b, nsq, nsq, b, nsq, b};
     }
     w.dP32f.upload(pf, s);
     // persistent, size-bucketed launch of the local product: two 512-thread
@@ -619,14 +636,14 @@ void build_ws(awg_ctx& c, MultiWS& w, int b) {
     w.ntilesP32 = (int)tl.size();
     w.tilesP32.upload(tl, s);
   }
-  if (c.P16.p && b > 1) {
+  if (P16l.p && b > 1) {
     w.xs16_plane = c.h3_groups * (long)b * 8;
     w.Xs16.ensure(2 * (size_t)w.xs16_plane);
     w.emax.ensure(b);
     std::vector<GemmDescH3> ph(c.N);
     for (int q = 0; q < c.N; ++q) {
       const int nsq = c.ns[q];
-      ph[q] = GemmDescH3{w.Xs16.p + c.h3_gofs[q] * b * 8, c.P16.p + c.h_p16_off[q], w.Os.p + c.h_subptr[q] * b,
+      ph[q] = GemmDescH3{w.Xs16.p + c.h3_gofs[q] * b * 8, P16l.p + c.h_p16_off[q], w.Os.p + c.h_subptr[q] * b,
                          w.xs16_plane, c.p16_plane, b, nsq, (nsq + 7) / 8, b};
     }
     w.dH3.upload(ph, s);
@@ -765,12 +782,12 @@ void op_hnn(awg_ctx& c, MultiWS& w, const double* X, double* Yo, bool f32) {
     hipLaunchKernelGGL(k_gemv_f32, dim3(cdiv(w.maxns, 64), c.N), dim3(256), 0, c.s, c.P32.p, c.d_sqoff.p,
                        c.subptr.p, w.Xs.p, w.Os.p);
     AWG_LAUNCH_CHECK();
-  } else if (f32 && c.P16.p) {
+  } else if (f32 && w.dH3.p) {
     // split-FP16 local product: per-column exponents, split restriction,
     // three FP16 matrix-core products per tile
     l_colexp(c.n, w.b, X, w.emax, c.s);
     l_gather_h3(c.h3_groups, c.h3_row0, c.h3_cnt, c.subidx, X, w.b, w.emax, w.Xs16, w.xs16_plane, c.s);
-    gemm_h3_batched(w.dH3, c.N, w.b, w.maxns, w.emax, c.p16_sp, c.s, w.flP);
+    gemm_h3_batched(w.dH3, c.N, w.b, w.maxns, w.emax, w.wops ? c.p16_sp_w : c.p16_sp, c.s, w.flP);
   } else if (f32) {
     // FP32 local product, three forms with identical results: the restricted
     // FP64 rows written out or read in place and rounded while staged, or
@@ -816,7 +833,7 @@ void op_h2(awg_ctx& c, MultiWS& w, bool f32, const double* rin = nullptr) {
     op_hnn(c, w, r, w.Z, f32);
     return;
   }
-  if (c.opt.h2 == AWG_H2_ASP_AD) {
+  if (w.h2mode == AWG_H2_ASP_AD) {
     // H^AS_{+,ad} = H^AS_+ + R0^T E0^{-1} R0 (Theorem on H^AS_{+,hyb/ad}, Section 3.4)
     op_r0(c, w, r);                                                      // G0 = R0 r
     bmm(w.dE0a, 1, c.n0, c.n0, false, 1.0, 0.0, b, c.s, w.flE0, nullptr, "E0");         // G1 = E0^{-1} R0 r
@@ -1332,10 +1349,11 @@ int geneo_subspace(awg_ctx& c, const double* MB, double* MA) {
 // reduced-precision copies of the local operators P^s: FP32 (one-column
 // products and the FP32 local product) and, for AWG_LOCAL_F16X3, the split
 // FP16 planes with their row groups
-void build_reduced_local(awg_ctx& c) {
+void build_reduced_local(awg_ctx& c, const DBuf<double>& P, DBuf<float>& P32, DBuf<_Float16>& P16,
+                         DBuf<int>& sp) {
   hipStream_t s = c.s;
-  c.P32.alloc(c.sqtot);
-  hipLaunchKernelGGL(k_f32_from_f64, dim3(4096), dim3(256), 0, s, (long)c.sqtot, c.P.p, c.P32.p);
+  P32.alloc(c.sqtot);
+  hipLaunchKernelGGL(k_f32_from_f64, dim3(4096), dim3(256), 0, s, (long)c.sqtot, P.p, P32.p);
   AWG_LAUNCH_CHECK();
   if (c.opt.local_prec != AWG_LOCAL_F16X3) return;
   std::vector<int> row0, cnt;
@@ -1355,11 +1373,12 @@ void build_reduced_local(awg_ctx& c) {
   c.h3_cnt.upload(cnt, s);
   c.p16_plane = c.h_p16_off[c.N];
   c.p16_off.upload(c.h_p16_off, s);
-  c.P16.alloc(2 * (size_t)c.p16_plane);
-  c.p16_sp.alloc(c.N);
-  l_p16_build(c.N, c.d_sqoff, c.subptr, c.p16_off, c.P, c.P16, c.p16_plane, c.p16_sp, s);
+  P16.alloc(2 * (size_t)c.p16_plane);
+  sp.alloc(c.N);
+  l_p16_build(c.N, c.d_sqoff, c.subptr, c.p16_off, P, P16, c.p16_plane, sp, s);
   sync(c);   // the host row-group lists end here
 }
+void build_reduced_local(awg_ctx& c) { build_reduced_local(c, c.P, c.P32, c.P16, c.p16_sp); }
 
 // B^s, its non-positive eigenpairs (splitting of B^s, Section 3.2), the local
 // factor and P^s = D^s (A^s_+)^+ D^s, the GenEO coarse vectors Y^s
@@ -1579,6 +1598,25 @@ void phase_local(awg_ctx& c) {
       std::swap(c.P.n, X2.n);
     }
     if (c.opt.local_prec != AWG_LOCAL_F64) build_reduced_local(c);
+  }
+  if (c.wmode != c.opt.h2) {
+    // the W solves' H^AS_+ operators beside H^NN: P^s_w = (M_B^s)^{-1} from the
+    // factor the dense GenEO solve left in d1, or a new one of M_B^s
+    PhaseTimer t(c, "local_factor");
+    if (!mb_factored) {
+      info.zero(s);
+      potrf_batched(d1, c.ns, info, s, nullptr);
+      check_info(c, info, "H^AS_+ local block M_B^s");
+    }
+    c.Pw.alloc(c.sqtot);
+    DBuf<MatDesc> dw;
+    dw.upload(square_descs(c, c.Pw), s);
+    l_set_identity(dw, c.N, s);
+    trsm_batched(d1, dw, c.ns, c.ns, false, s, nullptr);
+    trsm_batched(d1, dw, c.ns, c.ns, true, s, nullptr);
+    l_scale_sym(dw, c.N, nullptr, nullptr, false, true, s);
+    if (c.opt.local_prec != AWG_LOCAL_F64) build_reduced_local(c, c.Pw, c.P32w, c.P16w, c.p16_sp_w);
+    sync(c);
   }
 }
 
@@ -1841,7 +1879,7 @@ void phase_W(awg_ctx& c) {
   c.W.alloc((long)c.n * c.nminus);
   const int b0 = balanced_chunk(c.nminus, 2048);
   MultiWS w;
-  build_ws(c, w, b0);
+  build_ws(c, w, b0, true);
   DBuf<double> X, Pm, Q, Zold, tmp;
   DBuf<double> alpha_d;
   alpha_d.alloc(b0);
@@ -1873,7 +1911,7 @@ void phase_W(awg_ctx& c) {
     const int bc = std::min(b0, c.nminus - c0);
     int b = b0;
     if (w.b != b0) {
-      build_ws(c, w, b0);
+      build_ws(c, w, b0, true);
       alloc_vectors(b0);
     }
     double* dots = w.dots.p;
@@ -1958,7 +1996,7 @@ void phase_W(awg_ctx& c) {
         gather(w.R);
         if (f32) gather(Zold);
         sync(c);
-        build_ws(c, w, bnew);   // descriptors at the new width; R and the buffers are kept
+        build_ws(c, w, bnew, true);   // descriptors at the new width; R and the buffers are kept
         dots = w.dots.p;
         std::vector<int> cid(bnew), act(bnew);
         std::vector<double> bn2(bnew), rz2(bnew);
@@ -2328,7 +2366,7 @@ std::string stats_json(const awg_ctx& c) {
   arr("kstrict_s", c.kstrict);
   o << ",";
   arr("m_s", c.ms);
-  o << ",\"coarse2\":" << c.opt.coarse2 << ",\"h2\":" << c.opt.h2;
+  o << ",\"coarse2\":" << c.opt.coarse2 << ",\"h2\":" << c.opt.h2 << ",\"w_h2\":" << c.wmode;
   o << ",\"geneo_solver\":" << c.opt.geneo_solver << ",\"eig_fallbacks\":" << c.eig_fallbacks
     << ",\"eig_learned\":" << c.eig_learned << ",\"eig_block\":" << c.opt.eig_block
     << ",\"n0_dropped\":" << c.n0_dropped << ",\"nminus_dropped\":" << c.nminus_dropped;
@@ -2377,6 +2415,7 @@ void awg_default_options(awg_options* opt) {
   opt->coord_dim = 0;
   opt->coarse2 = AWG_COARSE2_AD;
   opt->h2 = AWG_H2_NN_HYB;
+  opt->w_h2 = AWG_H2_ASP_AD;
 }
 
 int awg_setup(awg_ctx** out, int64_t n, int64_t nnz, const int64_t* rowptr, const int32_t* col, const double* val,
@@ -2405,6 +2444,7 @@ int awg_setup(awg_ctx** out, int64_t n, int64_t nnz, const int64_t* rowptr, cons
       (o.coords && (o.coord_dim < 1 || o.coord_dim > 3)) ||
       (o.coarse2 != AWG_COARSE2_AD && o.coarse2 != AWG_COARSE2_INEX && o.coarse2 != AWG_COARSE2_HYB) ||
       (o.h2 != AWG_H2_NN_HYB && o.h2 != AWG_H2_ASP_HYB && o.h2 != AWG_H2_ASP_AD && o.h2 != AWG_H2_AS_HYB) ||
+      (o.w_h2 != AWG_H2_NN_HYB && o.w_h2 != AWG_H2_ASP_HYB && o.w_h2 != AWG_H2_ASP_AD) ||
       (o.h2 == AWG_H2_AS_HYB && o.geneo_solver != AWG_GENEO_DENSE)) {
     g_setup_error = "awg_setup: invalid option value";
     return AWG_ERR_ARG;
@@ -2419,6 +2459,7 @@ int awg_setup(awg_ctx** out, int64_t n, int64_t nnz, const int64_t* rowptr, cons
     return AWG_ERR_OOM;
   }
   c->opt = o;
+  c->wmode = o.h2 == AWG_H2_NN_HYB ? o.w_h2 : o.h2;
   c->s = (hipStream_t)o.stream;
   c->n = (int)n;
   c->nnz = (int)nnz;

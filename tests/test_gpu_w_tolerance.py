@@ -2,8 +2,9 @@
 residual of the PCG solves for W = A_+^-1 V_- hardly changes the condition
 number of H3,ad A down to 1e-2, and only mildly at 1e-1).
 
-Through the C ABI, for each tolerance: every column of the exported W meets
-its stopping test against the oracle's assembled A_+ and the GPU's own V_- (the
+Through the C ABI, for each tolerance: every column of the exported W (its
+solves preconditioned by H^AS_+,ad, the default) meets its stopping test
+against the oracle's assembled A_+ and the GPU's own V_- (the
 recursive residual that the GPU tests differs from the true one by at most a
 few eps * cond(A_+)); the outer PCG still converges to its tolerance.  On the
 paper's own problem, down to 1e-2 kappa stays that of its table."""
@@ -109,7 +110,9 @@ def test_paper_table4_on_gpu(gpu_lib):
         if row["w_rtol"] > 1e-2:
             continue
         print(f"\n[gpu case] six-layer problem, w_rtol={row['w_rtol']:g}", flush=True)
-        s = gpu_lib.Solver(w.A, w.subs, tau=w.tau, w_rtol=row["w_rtol"])
+        # the W solves preconditioned by H2 itself, as the table's were (at a
+        # loose tolerance W depends on the preconditioner of its solves)
+        s = gpu_lib.Solver(w.A, w.subs, tau=w.tau, w_rtol=row["w_rtol"], w_h2="nn_hyb")
         st = s.stats()
         assert st["n0"] == T4["n0"] and st["n_minus"] == T4["n_minus"]
         _, info = s.pcg(b, tol=1e-8, maxit=500)
