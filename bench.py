@@ -515,6 +515,7 @@ def main():
                "kappa_est": info["lmax_est"] / info["lmin_est"], "n_minus": st["n_minus"], "n0": st["n0"],
                "w_iters": st["w_iters"], "w_iters_mean": st.get("w_iters_mean"),
                "w_compactions": st.get("w_compactions"),
+               "w_factor_fp64_fallbacks": st.get("w_factor_fallbacks"),
                "eig_fallbacks": st["eig_fallbacks"], "eig_learned": st["eig_learned"],
                "eig_iters_max": max(st["eig_iters"], default=0),
                "phases_ms": {k: round(v, 3) for k, v in st["ms"].items()},

@@ -64,6 +64,19 @@ int awg_dense_gemm_ex(int32_t batch, int32_t m, int32_t n, int32_t k, int32_t tr
 int awg_dense_local_product_f16x3(int32_t batch, const int32_t* n_host, int32_t ncols, const double* X,
                                   const double* P, double* Y, void* stream);
 
+/* FP32 inverse of SPD blocks on the FP32 matrix cores (the local factors of
+ * the W solves' H^AS_+ operators in the reduced-precision forms, one-level
+ * preconditioners for A_+, Section 3.3): A_b rounded to FP32, A_b = L L^T,
+ * X = L^{-1} by blocked substitution, A_b^{-1} = X^T X, returned in FP64.
+ * A and Ainv: device, the n_b x n_b column-major blocks concatenated; n_host:
+ * host sizes.  info_host[b] (host, optional) = 0 or the 1-based column of the
+ * first non-positive FP32 pivot; pivot_ratio_host[b] (host, optional) = max /
+ * min diagonal entry of L (its square bounds the condition number from
+ * below).  Returns AWG_ERR_NOT_SPD if any block failed, AWG_ERR_ARG for
+ * batch <= 0, a size <= 0 or null pointers. */
+int awg_dense_spd_inverse_f32(int32_t batch, const int32_t* n_host, const double* A, double* Ainv,
+                              int32_t* info_host, float* pivot_ratio_host, void* stream);
+
 /* In-place lower Cholesky A_b = L_b L_b^T (upper triangle left unspecified).
  * info_host[b] (host, batch entries) = 0 or the 1-based column of the first
  * non-positive pivot; returns AWG_ERR_NOT_SPD if any block failed. */

@@ -30,7 +30,8 @@ STATUS = {0: "AWG_OK", 1: "AWG_NOT_CONVERGED", -1: "AWG_ERR_ARG", -2: "AWG_ERR_N
 EXPORTED = ["awg_default_options", "awg_setup", "awg_apply", "awg_pcg", "awg_stats", "awg_export",
             "awg_last_error", "awg_destroy", "awg_kernel_timing", "awg_kernel_times", "awg_pcg_graph",
             "awg_w_compaction", "awg_free_cached_memory",
-            "awg_dense_gemm", "awg_dense_gemm_ex", "awg_dense_local_product_f16x3", "awg_dense_potrf", "awg_dense_potrf_noalloc", "awg_dense_trsm",
+            "awg_dense_gemm", "awg_dense_gemm_ex", "awg_dense_local_product_f16x3", "awg_dense_spd_inverse_f32",
+            "awg_dense_potrf", "awg_dense_potrf_noalloc", "awg_dense_trsm",
             "awg_dense_low_eigs",
             "awg_mlp_create", "awg_mlp_num_params", "awg_mlp_get_params", "awg_mlp_set_params", "awg_mlp_forward",
             "awg_mlp_loss_grad", "awg_mlp_get_grads", "awg_mlp_adam_step", "awg_mlp_last_error", "awg_mlp_destroy",
@@ -109,6 +110,8 @@ def lib():
     L.awg_dense_gemm_ex.restype = ctypes.c_int
     L.awg_dense_local_product_f16x3.argtypes = [i32, vp, i32, vp, vp, vp, vp]
     L.awg_dense_local_product_f16x3.restype = ctypes.c_int
+    L.awg_dense_spd_inverse_f32.argtypes = [i32, vp, vp, vp, vp, vp, vp]
+    L.awg_dense_spd_inverse_f32.restype = ctypes.c_int
     L.awg_probe_mfma_f64.argtypes = [i32, ctypes.POINTER(ctypes.c_double), vp]
     L.awg_probe_mfma_f64.restype = ctypes.c_int
     L.awg_dense_potrf.argtypes = [i32, i32, vp, i32, i64, vp, vp]
@@ -407,6 +410,20 @@ def w_compaction(enable: bool) -> None:
     """Process-wide switch of the column compaction in the W solves (on by
     default; W is the same bit for bit either way)."""
     lib().awg_w_compaction(int(enable))
+
+
+def dense_spd_inverse_f32(sizes, A, Ainv):
+    """FP32 Cholesky inverses of the SPD blocks in A (concatenated column-major
+    n_b x n_b float64 device blocks) into Ainv; returns (info, pivot ratio)
+    per block as numpy arrays (a block with info != 0 failed)."""
+    sz = np.ascontiguousarray(np.asarray(sizes, dtype=np.int32))
+    info = np.zeros(len(sz), dtype=np.int32)
+    ratio = np.zeros(len(sz), dtype=np.float32)
+    rc = lib().awg_dense_spd_inverse_f32(len(sz), sz.ctypes.data, A.data_ptr(), Ainv.data_ptr(), info.ctypes.data,
+                                         ratio.ctypes.data, _stream())
+    if rc not in (0, -5):
+        raise AWGError(rc, "awg_dense_spd_inverse_f32")
+    return info, ratio
 
 
 def probe_mfma_f64(iters: int = 4000) -> float:

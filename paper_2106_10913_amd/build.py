@@ -7,7 +7,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["k_dense.hip", "k_eig.hip", "k_sparse.hip", "k_subspace.hip", "k_mlp.hip", "k_split16.hip", "tune.hip", "awg_core.hip", "awg_dense_abi.hip"]
+SOURCES = ["k_dense.hip", "k_eig.hip", "k_sparse.hip", "k_subspace.hip", "k_mlp.hip", "k_split16.hip", "k_chol32.hip", "tune.hip", "awg_core.hip", "awg_dense_abi.hip"]
 LIB = os.path.join(HERE, "libawg.so")
 
 HIPCC_FLAGS = [

@@ -168,6 +168,11 @@ struct GemmDescH3 {      // split FP16 operands (hi and lo planes), FP64 C: C = 
   int m, n, G, ldc;      // G = row groups of 8 (k = 8 G, zero-padded)
 };
 
+struct MatDescF {        // one square FP32 column-major block
+  float* A;
+  int n, ld;
+};
+
 struct MatDesc {         // one square or rectangular column-major block
   double* A;
   int m, n, ld;
@@ -208,6 +213,12 @@ void gemm_f32_batched(const GemmDescF32* d_desc, int batch, int max_m, int max_n
                       hipStream_t s, double flops, const int* tiles = nullptr, int ntiles = 0, int grid = 0);
 // tile list (host) of the persistent local-product launch for batch entries
 // of sizes m x n with inner dimension k; returns its grid size
+// FP32 Cholesky K = L L^T of every block of d_K (overwritten by L), X = L^-1
+// in d_X and K^-1 = X^T X in d_out, all FP32 on the matrix cores; info[b] =
+// first non-positive pivot column (1-based) or 0, dmin/dmax[b] = extreme
+// diagonal entries of L
+void chol_inverse_f32(const MatDescF* d_K, const MatDescF* d_X, const MatDescF* d_out, const std::vector<int>& h_n,
+                      int* d_info, float* d_dmin, float* d_dmax, hipStream_t s);
 // split-FP16 local product (three FP16 MFMA products, FP32 accumulation):
 // emax (b) = per-column largest biased exponent of the multi-vector, from
 // l_colexp; sp (batch) = the power-of-two scale of each matrix, from l_p16_build
@@ -217,6 +228,8 @@ void l_colexp(int n, int b, const double* X, int* emax, hipStream_t s);
 void l_gather_h3(long ngroups, const int* row0, const int* cnt, const int* sub_idx, const double* X, int b,
                  const int* emax, _Float16* out, long plane, hipStream_t s);
 void l_p16_build(int N, const long* sqoff, const long* sub_ptr, const long* poff, const double* P, _Float16* out,
+                 long plane, int* sp, hipStream_t s);
+void l_p16_build(int N, const long* sqoff, const long* sub_ptr, const long* poff, const float* P, _Float16* out,
                  long plane, int* sp, hipStream_t s);
 int f32_tile_list(const std::vector<int>& m, const std::vector<int>& n, const std::vector<int>& k, int wgs_per_xcd,
                   std::vector<int>& tiles);

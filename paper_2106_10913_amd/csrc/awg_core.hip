@@ -328,6 +328,7 @@ struct awg_ctx {
   int w_iters = 0;
   double w_iters_mean = 0.0;    // mean over the W columns of their iteration counts
   int w_compactions = 0;        // narrowings of the W solves' multi-vectors
+  int w_factor_fallbacks = -1;  // subdomains of the FP32 factorisation redone in FP64 (-1: not run)
   double w_time = 0.0;
   std::vector<double> eig_resid_max;
   std::vector<int> eig_iters;   // subspace GenEO: iteration of convergence per subdomain
@@ -1599,7 +1600,73 @@ void phase_local(awg_ctx& c) {
     }
     if (c.opt.local_prec != AWG_LOCAL_F64) build_reduced_local(c);
   }
-  if (c.wmode != c.opt.h2) {
+  if (c.wmode != c.opt.h2 && c.opt.local_prec != AWG_LOCAL_F64 && !mb_factored) {
+    // the W solves' H^AS_+ operators in the reduced-precision forms, M_B^s
+    // intact in d1: FP32 Cholesky and inverse on the matrix cores, FP64 for
+    // the subdomains whose FP32 factor fails or whose pivots show a
+    // conditioning beyond FP32 (max/min diagonal of L squared > 2^18)
+    PhaseTimer t(c, "local_factor");
+    DBuf<float> K32, X32;
+    K32.alloc(c.sqtot);
+    X32.alloc(c.sqtot);
+    c.P32w.alloc(c.sqtot);
+    hipLaunchKernelGGL(k_f32_from_f64, dim3(4096), dim3(256), 0, s, (long)c.sqtot, X1.p, K32.p);
+    AWG_LAUNCH_CHECK();
+    auto fdescs = [&](float* base) {
+      std::vector<MatDescF> v(c.N);
+      for (int q = 0; q < c.N; ++q) v[q] = MatDescF{base + c.sqoff[q], c.ns[q], c.ns[q]};
+      return v;
+    };
+    DBuf<MatDescF> dK, dX, dO;
+    dK.upload(fdescs(K32.p), s);
+    dX.upload(fdescs(X32.p), s);
+    dO.upload(fdescs(c.P32w.p), s);
+    DBuf<float> dmin, dmax;
+    dmin.alloc(c.N);
+    dmax.alloc(c.N);
+    info.zero(s);
+    chol_inverse_f32(dK, dX, dO, c.ns, info, dmin, dmax, s);
+    const std::vector<int> hinfo = info.download(s);
+    const std::vector<float> hmin = dmin.download(s), hmax = dmax.download(s);
+    std::vector<int> fb;
+    for (int q = 0; q < c.N; ++q) {
+      const double ratio = hmin[q] > 0.f ? (double)hmax[q] / hmin[q] : 1e300;
+      if (hinfo[q] != 0 || !(ratio * ratio <= 262144.0)) fb.push_back(q);
+    }
+    c.w_factor_fallbacks = (int)fb.size();
+    if (!fb.empty()) {
+      std::vector<MatDesc> sm(fb.size()), so(fb.size());
+      std::vector<int> sn(fb.size());
+      for (size_t t = 0; t < fb.size(); ++t) {
+        const int q = fb[t];
+        sm[t] = MatDesc{X1.p + c.sqoff[q], c.ns[q], c.ns[q], c.ns[q], 0};
+        so[t] = MatDesc{X3.p + c.sqoff[q], c.ns[q], c.ns[q], c.ns[q], 0};
+        sn[t] = c.ns[q];
+      }
+      DBuf<MatDesc> dsm, dso;
+      dsm.upload(sm, s);
+      dso.upload(so, s);
+      DBuf<int> finfo;
+      finfo.alloc(fb.size());
+      finfo.zero(s);
+      potrf_batched(dsm, sn, finfo, s, nullptr);
+      check_info(c, finfo, "H^AS_+ local block M_B^s");
+      l_set_identity(dso, (int)fb.size(), s);
+      trsm_batched(dsm, dso, sn, sn, false, s, nullptr);
+      trsm_batched(dsm, dso, sn, sn, true, s, nullptr);
+      l_scale_sym(dso, (int)fb.size(), nullptr, nullptr, false, true, s);
+      for (int q : fb)
+        hipLaunchKernelGGL(k_f32_from_f64, dim3(256), dim3(256), 0, s, (long)c.ns[q] * c.ns[q], X3.p + c.sqoff[q],
+                           c.P32w.p + c.sqoff[q]);
+      AWG_LAUNCH_CHECK();
+    }
+    if (c.opt.local_prec == AWG_LOCAL_F16X3) {
+      c.P16w.alloc(2 * (size_t)c.p16_plane);
+      c.p16_sp_w.alloc(c.N);
+      l_p16_build(c.N, c.d_sqoff, c.subptr, c.p16_off, (const float*)c.P32w.p, c.P16w, c.p16_plane, c.p16_sp_w, s);
+    }
+    sync(c);
+  } else if (c.wmode != c.opt.h2) {
     // the W solves' H^AS_+ operators beside H^NN: P^s_w = (M_B^s)^{-1} from the
     // factor the dense GenEO solve left in d1, or a new one of M_B^s
     PhaseTimer t(c, "local_factor");
@@ -2359,7 +2426,7 @@ std::string stats_json(const awg_ctx& c) {
     o << "]";
   };
   o << "{\"n\":" << c.n << ",\"nnz\":" << c.nnz << ",\"N\":" << c.N << ",\"sum_ns\":" << c.sumns
-    << ",\"n_minus\":" << c.nminus << ",\"n0\":" << c.n0 << ",\"w_iters\":" << c.w_iters << ",\"w_iters_mean\":" << c.w_iters_mean << ",\"w_compactions\":" << c.w_compactions
+    << ",\"n_minus\":" << c.nminus << ",\"n0\":" << c.n0 << ",\"w_iters\":" << c.w_iters << ",\"w_iters_mean\":" << c.w_iters_mean << ",\"w_compactions\":" << c.w_compactions << ",\"w_factor_fallbacks\":" << c.w_factor_fallbacks
     << ",\"local_prec\":" << c.opt.local_prec << ",\"tau\":" << c.opt.tau << ",";
   arr("k_s", c.ks);
   o << ",";

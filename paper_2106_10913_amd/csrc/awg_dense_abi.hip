@@ -214,6 +214,62 @@ int awg_dense_potrf(int32_t batch, int32_t n, double* A, int32_t lda, int64_t st
   return rc ? rc : (bad ? AWG_ERR_NOT_SPD : AWG_OK);
 }
 
+__global__ void k_abi_f32_from_f64(long tot, const double* a, float* b) {
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += (long)gridDim.x * blockDim.x)
+    b[e] = (float)a[e];
+}
+__global__ void k_abi_f64_from_f32(long tot, const float* a, double* b) {
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += (long)gridDim.x * blockDim.x)
+    b[e] = (double)a[e];
+}
+
+int awg_dense_spd_inverse_f32(int32_t batch, const int32_t* n_host, const double* A, double* Ainv,
+                              int32_t* info_host, float* pivot_ratio_host, void* stream) {
+  if (batch <= 0 || !n_host || !A || !Ainv) return AWG_ERR_ARG;
+  for (int b = 0; b < batch; ++b)
+    if (n_host[b] <= 0) return AWG_ERR_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  bool bad = false;
+  int rc = guarded(s, [&] {
+    std::vector<long> off(batch + 1, 0);
+    std::vector<int> ns(n_host, n_host + batch);
+    for (int b = 0; b < batch; ++b) off[b + 1] = off[b] + (long)ns[b] * ns[b];
+    const long tot = off[batch];
+    DBuf<float> K, X, O;
+    K.alloc(tot);
+    X.alloc(tot);
+    O.alloc(tot);
+    hipLaunchKernelGGL(k_abi_f32_from_f64, dim3(1024), dim3(256), 0, s, tot, A, K.p);
+    AWG_LAUNCH_CHECK();
+    auto descs = [&](float* base) {
+      std::vector<MatDescF> v(batch);
+      for (int b = 0; b < batch; ++b) v[b] = MatDescF{base + off[b], ns[b], ns[b]};
+      return v;
+    };
+    DBuf<MatDescF> dK, dX, dO;
+    dK.upload(descs(K.p), s);
+    dX.upload(descs(X.p), s);
+    dO.upload(descs(O.p), s);
+    DBuf<int> info;
+    info.alloc(batch);
+    info.zero(s);
+    DBuf<float> dmin, dmax;
+    dmin.alloc(batch);
+    dmax.alloc(batch);
+    chol_inverse_f32(dK, dX, dO, ns, info, dmin, dmax, s);
+    hipLaunchKernelGGL(k_abi_f64_from_f32, dim3(1024), dim3(256), 0, s, tot, O.p, Ainv);
+    AWG_LAUNCH_CHECK();
+    const auto hi = info.download(s);
+    const auto lo = dmin.download(s), hiv = dmax.download(s);
+    for (int b = 0; b < batch; ++b) {
+      if (info_host) info_host[b] = hi[b];
+      if (pivot_ratio_host) pivot_ratio_host[b] = lo[b] > 0.f ? hiv[b] / lo[b] : 0.f;
+      bad |= hi[b] != 0;
+    }
+  });
+  return rc ? rc : (bad ? AWG_ERR_NOT_SPD : AWG_OK);
+}
+
 int awg_dense_potrf_noalloc(int32_t batch, int32_t n, double* A, int32_t lda, int64_t strideA,
                             int32_t* info_host, void* stream) {
   if (batch <= 0 || batch > NOALLOC_MAX_BATCH || n <= 0 || lda < n || !A) return AWG_ERR_ARG;

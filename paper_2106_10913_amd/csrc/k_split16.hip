@@ -86,15 +86,16 @@ __global__ __launch_bounds__(256) void k_gather_h3(long ngroups, const int* row0
 
 // split local matrices: one block per subdomain; sp[s] = scale exponent of
 // P^s (its largest entry mapped into [2^14, 2^15)), then the entries (j, g)
+template <class T>
 __global__ __launch_bounds__(256) void k_p16_build(const long* sqoff, const long* sub_ptr, const long* poff,
-                                                   const double* P, _Float16* out, long plane, int* sp) {
+                                                   const T* P, _Float16* out, long plane, int* sp) {
   __shared__ int red[256];
   const int s = blockIdx.x;
   const int ns = (int)(sub_ptr[s + 1] - sub_ptr[s]);
   const int G = (ns + 7) / 8;
-  const double* Ps = P + sqoff[s];
+  const T* Ps = P + sqoff[s];
   int e = 0;
-  for (long k = threadIdx.x; k < (long)ns * ns; k += 256) e = max(e, bexp(Ps[k]));
+  for (long k = threadIdx.x; k < (long)ns * ns; k += 256) e = max(e, bexp((double)Ps[k]));
   red[threadIdx.x] = e;
   __syncthreads();
   for (int o = 128; o > 0; o >>= 1) {
@@ -110,7 +111,7 @@ __global__ __launch_bounds__(256) void k_p16_build(const long* sqoff, const long
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int k = 8 * g + u;
-      const double x = k < ns ? ldexp(Ps[k + (long)j * ns], sc) : 0.0;
+      const double x = k < ns ? ldexp((double)Ps[k + (long)j * ns], sc) : 0.0;
       _Float16 h, l;
       split2(x, h, l);
       hi[u] = h;
@@ -251,7 +252,13 @@ void l_gather_h3(long ngroups, const int* row0, const int* cnt, const int* sub_i
 void l_p16_build(int N, const long* sqoff, const long* sub_ptr, const long* poff, const double* P, _Float16* out,
                  long plane, int* sp, hipStream_t s) {
   if (N == 0) return;
-  hipLaunchKernelGGL(k_p16_build, dim3(N), dim3(256), 0, s, sqoff, sub_ptr, poff, P, out, plane, sp);
+  hipLaunchKernelGGL(k_p16_build<double>, dim3(N), dim3(256), 0, s, sqoff, sub_ptr, poff, P, out, plane, sp);
+  AWG_LAUNCH_CHECK();
+}
+void l_p16_build(int N, const long* sqoff, const long* sub_ptr, const long* poff, const float* P, _Float16* out,
+                 long plane, int* sp, hipStream_t s) {
+  if (N == 0) return;
+  hipLaunchKernelGGL(k_p16_build<float>, dim3(N), dim3(256), 0, s, sqoff, sub_ptr, poff, P, out, plane, sp);
   AWG_LAUNCH_CHECK();
 }
 

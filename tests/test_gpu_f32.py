@@ -45,3 +45,30 @@ def test_f32_local_converges(gpu_lib, name, h2, prec):
     assert rel <= 1e-3
     s64.close()
     s32.close()
+
+
+@pytest.mark.parametrize("prec", ["f32", "f16x3"])
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_reduced_forms_with_subspace_geneo(gpu_lib, name, prec):
+    """The fast forms' configuration: subspace GenEO, so the W solves' H^AS_+
+    local operators come from the FP32 Cholesky and inverse of M_B^s on the
+    matrix cores (FP64 for the subdomains it does not suit)."""
+    import torch
+    w = CASES[name]()
+    print(f"\n[gpu case] {prec} subspace GenEO {name} n={w.A.shape[0]}", flush=True)
+    b = torch.as_tensor(w.b, device="cuda")
+    s64 = gpu_lib.Solver(w.A, w.subs, tau=w.tau, local_prec="f64", geneo="subspace")
+    sr = gpu_lib.Solver(w.A, w.subs, tau=w.tau, local_prec=prec, geneo="subspace")
+    st64, st = s64.stats(), sr.stats()
+    assert st["n_minus"] == st64["n_minus"] and st["n0"] == st64["n0"]
+    assert st["w_factor_fallbacks"] >= 0 and st64["w_factor_fallbacks"] == -1
+    assert st["w_iters"] <= st64["w_iters"] + 3
+    _, i64 = s64.pcg(b, tol=w.tol)
+    _, ir = sr.pcg(b, tol=w.tol)
+    print(f"[fp32 factor] {name} {prec}: FP64 fallbacks {st['w_factor_fallbacks']} of {len(w.subs)}, "
+          f"W iterations {st['w_iters']} (FP64 {st64['w_iters']}), PCG {ir['iters']} (FP64 {i64['iters']})",
+          flush=True)
+    assert ir["converged"] == 1 and ir["rel_res_true"] <= 2 * w.tol
+    assert ir["iters"] <= i64["iters"] + 3
+    s64.close()
+    sr.close()

@@ -8,12 +8,11 @@ combination across subdomains (Jacobi-scaled E0 eigenvalue 2e-14): both
 sides deflate it.  Checked: the coarse dimensions and the deflated count
 exactly, the iteration count within 1, the Lanczos estimates within 1e-3.
 
-The iterate is parity unpinned here: the kept coarse matrix has cond ~ 4e8
-after the deflation, so either side applies E0^+ only to about eps * cond
-~ 1e-7 relative, far above the 1e-10 bar.  The whole iterate is compared
-with the oracle's (stored as .npy) and the measured difference is printed;
-the assertion is the sanity bound 10 eps cond(deflated scaled E0), not the
-stated bar."""
+The whole iterate is compared with the oracle's (stored as .npy): to the
+stated 1e-10 when the deflation decision has a margin of at least 100 (the
+oracle's stored margin is 129; measured 3.7e-12), else the case is parity
+unpinned and held to 10 eps cond(deflated scaled E0) (the kept coarse matrix
+has cond ~ 4e8 after the deflation)."""
 import json
 import os
 
@@ -57,11 +56,13 @@ def test_pcg_iterate_and_count(run):
     assert abs(info["iters"] - gold["iters"]) <= 1
     assert abs(info["lmax_est"] - gold["lmax"]) <= 1e-3 * gold["lmax"]
     assert abs(info["lmin_est"] - gold["lmin"]) <= 1e-3 * gold["lmin"]
-    bar = max(1e-10, 10 * EPS * gold["cond_E0_scaled_deflated"])
     xo = np.load(X_PATH)
     err = np.linalg.norm(x - xo) / np.linalg.norm(xo)
-    print(f"[parity unpinned] as_hyb full size: ||x - x_o|| / ||x_o|| = {err:.3e} "
+    pinned = gold["deflation_margin"] >= 100
+    print(f"[{'parity' if pinned else 'parity unpinned'}] as_hyb full size: ||x - x_o|| / ||x_o|| = {err:.3e} "
           f"(cond of the deflated scaled E0 {gold['cond_E0_scaled_deflated']:.3g}, "
           f"deflation margin {gold['deflation_margin']:.3g})", flush=True)
-    assert err <= bar
+    # the stated bar where the deflation decision has a margin of 100;
+    # otherwise the sanity bound 10 eps cond(deflated scaled E0)
+    assert err <= (1e-10 if pinned else max(1e-10, 10 * EPS * gold["cond_E0_scaled_deflated"]))
     assert info["rel_res_true"] <= w.tol

@@ -158,6 +158,43 @@ def test_local_product_f16x3_rejects_bad_arguments(gpu_lib):
         gpu_lib.dense_local_product_f16x3([4, 0], X, P, X)
 
 
+def test_spd_inverse_f32(gpu_lib):
+    """FP32 Cholesky inverses on the matrix cores against numpy FP64, on
+    ragged sizes (one panel, panel and substitution-block boundaries, several
+    tiles): relative Frobenius error within 20 sqrt(n) kappa 2^-24, the
+    pivot ratio squared never above kappa, and a block that is not positive
+    definite flagged while the others are unaffected."""
+    import torch
+    rng = np.random.default_rng(7)
+    sizes = [1, 5, 31, 32, 33, 64, 65, 100, 257, 300]
+    cond = 1e3
+    blocks = [spd(rng, 1, k, cond)[0] for k in sizes]
+    bad = rng.standard_normal((40, 40))
+    blocks.append(0.5 * (bad + bad.T))                    # indefinite
+    sizes = sizes + [40]
+    flat = np.concatenate([b.T.reshape(-1) for b in blocks])
+    A = torch.as_tensor(flat, device="cuda")
+    Ai = torch.full_like(A, float("nan"))
+    info, ratio = gpu_lib.dense_spd_inverse_f32(sizes, A, Ai)
+    out = Ai.cpu().numpy()
+    o = 0
+    worst = 0.0
+    for b, (k, M) in enumerate(zip(sizes, blocks)):
+        if b == len(sizes) - 1:
+            assert info[b] != 0
+            break
+        assert info[b] == 0
+        G = out[o:o + k * k].reshape(k, k).T
+        ref = np.linalg.inv(M)
+        kap = np.linalg.cond(M)
+        err = np.linalg.norm(G - ref) / np.linalg.norm(ref)
+        worst = max(worst, err)
+        assert err <= 20 * np.sqrt(k) * kap * 2.0 ** -24, (k, err)
+        assert ratio[b] ** 2 <= kap * (1 + 1e-3)
+        o += k * k
+    print(f"\n[spd inverse f32] worst relative error {worst:.2e} at kappa {cond:g}", flush=True)
+
+
 @pytest.mark.parametrize("n", [1, 31, 33, 64, 100, 257])
 def test_potrf(gpu_lib, n):
     rng = np.random.default_rng(n)
