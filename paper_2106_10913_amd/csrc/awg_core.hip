@@ -2181,7 +2181,9 @@ void phase_EW(awg_ctx& c) {
   DBuf<double> AW, EW;
   AW.alloc((long)c.n * c.nminus);
   EW.alloc((long)c.nminus * c.nminus);
-  l_spmm(c.n, c.nnz, c.rowptr, c.col, c.val, c.W.p, AW.p, c.nminus, 1.0, 0.0, s, &c.sgrp);   // A W
+  // A W, once per set-up: without the row groups, whose construction would
+  // cost more than the one product gains from them
+  l_spmm(c.n, c.nnz, c.rowptr, c.col, c.val, c.W.p, AW.p, c.nminus, 1.0, 0.0, s, nullptr, "k_spmm:AW");
   // E_W = W^T (A W): column-major views W_rm (n_minus x n) and AW_rm -> W_rm AW_rm^T,
   // the long k = n split into KS ranges (batch entries writing partial
   // products, summed in a fixed order) so that the launch fills the device

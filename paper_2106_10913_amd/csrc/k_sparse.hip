@@ -1322,6 +1322,8 @@ void spmm_variant(int v, int n, const int* rowptr, const int* col, const double*
 
 // The variant for this shape: measured on the first call with beta = 0 (the
 // timing launches then only overwrite Y with the same values), else cached or 0.
+constexpr long SPMM_GROUP_MAX_NNZ = 2000000;
+
 int spmm_choice(int n, long nnz, const int* rowptr, const int* col, const double* val, const double* X, double* Y,
                 int b, double alpha, double beta, hipStream_t s, const SpmmGroups* grp) {
   const std::string key = "spmm:n=" + std::to_string(n) + ":nnz=" + std::to_string(nnz) + ":b=" + std::to_string(b) +
@@ -1472,6 +1474,10 @@ void l_dot1_part(int n, const double* x, const double* y, double* part, hipStrea
 void l_spmm(int n, long nnz, const int* rowptr, const int* col, const double* val, const double* X, double* Y, int b,
             double alpha, double beta, hipStream_t s, const SpmmGroups* grp, const char* label) {
   if (n == 0 || b == 0) return;
+  // row groups are built on the host from the pattern, once per matrix; above
+  // SPMM_GROUP_MAX_NNZ that costs more than the grouped variants can save over
+  // the products of one set-up, so such matrices use the other variants
+  if (grp && grp->pending && nnz > SPMM_GROUP_MAX_NNZ) grp = nullptr;
   const int v = b == 1 ? 0 : spmm_choice(n, nnz, rowptr, col, val, X, Y, b, alpha, beta, s, grp);
   KScope kt(b == 1 ? "k_spmv" : (label ? label : "k_spmm_rm"), s,
             12.0 * nnz + 4.0 * (n + 1) + 16.0 * n * (double)b + (beta != 0.0 ? 8.0 * n * (double)b : 0.0),
