@@ -71,6 +71,9 @@ struct DBuf {
   ~DBuf() { release(); }
   void release() {
     if (p) {
+      // the wait for queued work that may still use the block is not
+      // allocation time
+      (void)hipDeviceSynchronize();
       const double t = alloc_clock_ms();
       dev_free(p, n * sizeof(T));
       g_alloc_ms += alloc_clock_ms() - t;

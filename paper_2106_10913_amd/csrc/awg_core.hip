@@ -775,8 +775,10 @@ void op_r0t(awg_ctx& c, MultiWS& w, double* Yo, double beta, double alpha = 1.0)
 }
 
 // Yo = sum_s R^sT P^s R^s X: H^NN X with P^s = D^s (A^s_+)^+ D^s (Definition of
-// H^NN, Section 3.3), or H^AS_+ X with P^s = (R^s A_+ R^sT)^{-1} (Section 3.4)
-void op_hnn(awg_ctx& c, MultiWS& w, const double* X, double* Yo, bool f32) {
+// H^NN, Section 3.3), or H^AS_+ X with P^s = (R^s A_+ R^sT)^{-1} (Section 3.4);
+// with add_r0t, Yo = that + R0^T G1 (the coarse prolongation added while the
+// local results are scattered, for b > 1 where the one-pass kernel applies)
+void op_hnn(awg_ctx& c, MultiWS& w, const double* X, double* Yo, bool f32, bool add_r0t = false) {
   if (w.b == 1) l_gather(c.sumns, c.subidx, X, w.b, w.Xs, c.s);
   if (f32 && w.b == 1) {
     KScope kt("k_gemv_f32", c.s, 4.0 * c.sqtot, 2.0 * c.sqtot);
@@ -814,7 +816,12 @@ void op_hnn(awg_ctx& c, MultiWS& w, const double* X, double* Yo, bool f32) {
   } else {
     bmm(w.dP, c.N, w.maxns, w.maxns, false, 1.0, 0.0, w.b, c.s, w.flP, nullptr, "P");
   }
+  if (add_r0t && w.b > 1 && c.y_nnz > 0 &&
+      l_scatter_prolong(c.n, c.sumns, c.invptr, c.invsub, c.invloc, c.subptr, w.Os, w.b, c.n0, c.y_nnz, c.y_rp,
+                        c.y_col, c.y_val, w.G1, Yo, c.s))
+    return;
   l_scatter(c.n, c.sumns, c.invptr, c.invsub, c.invloc, c.subptr, w.Os, w.b, Yo, 1.0, 0.0, c.s);
+  if (add_r0t) op_r0t(c, w, Yo, 1.0);
 }
 
 }  // namespace
@@ -838,8 +845,7 @@ void op_h2(awg_ctx& c, MultiWS& w, bool f32, const double* rin = nullptr) {
     // H^AS_{+,ad} = H^AS_+ + R0^T E0^{-1} R0 (Theorem on H^AS_{+,hyb/ad}, Section 3.4)
     op_r0(c, w, r);                                                      // G0 = R0 r
     bmm(w.dE0a, 1, c.n0, c.n0, false, 1.0, 0.0, b, c.s, w.flE0, nullptr, "E0");         // G1 = E0^{-1} R0 r
-    op_hnn(c, w, r, w.Z, f32);                                           // Z = H^AS_+ r
-    op_r0t(c, w, w.Z, 1.0);                                              // Z += R0^T G1
+    op_hnn(c, w, r, w.Z, f32, true);                                     // Z = H^AS_+ r + R0^T G1
     return;
   }
   op_r0(c, w, r);                                                        // G0 = R0 r
@@ -1959,7 +1965,9 @@ void phase_W(awg_ctx& c) {
     X.ensure((long)c.n * b);
     Pm.ensure(((long)c.n + c.LV.cols) * b);     // input of A_+ products (coefficient rows below)
     Q.ensure((long)c.n * b);
-    if (f32) Zold.ensure((long)c.n * b);
+    // Zold takes turns with the workspace's Z (same size), so it needs the
+    // coefficient rows below the n rows that op_aplus may write into Z
+    if (f32) Zold.ensure(((long)c.n + c.LV.cols) * b);
     tmp.ensure(((long)c.n + c.LV.cols) * b);    // target of the column compaction
   };
   alloc_vectors(b0);
@@ -2006,9 +2014,12 @@ void phase_W(awg_ctx& c) {
     X.zero(s);
     op_h2(c, w, f32);
     AWG_HIP(hipMemcpyAsync(Pm.p, w.Z.p, sizeof(double) * c.n * b, hipMemcpyDeviceToDevice, s));
-    if (f32) AWG_HIP(hipMemcpyAsync(Zold.p, w.Z.p, sizeof(double) * c.n * b, hipMemcpyDeviceToDevice, s));
     h = coldot(w.R, w.Z);
     for (int j = 0; j < b; ++j) rz[j] = h[j];
+    if (f32) {
+      std::swap(w.Z.p, Zold.p);   // Zold = Z
+      std::swap(w.Z.n, Zold.n);
+    }
     int it = 0;
     for (; it < c.opt.w_maxit; ++it) {
       op_aplus(c, w, Pm, Q);
@@ -2098,7 +2109,13 @@ void phase_W(awg_ctx& c) {
         if (active[j]) rz[j] = h2[j];
       }
       AWG_HIP(hipMemcpyAsync(alpha_d.p, beta.data(), sizeof(double) * b, hipMemcpyHostToDevice, s));
-      l_multi_update_p(c.n, b, w.Z, Pm, alpha_d, f32 ? Zold.p : nullptr, s);   // P = Z + beta P (Zold = Z)
+      l_multi_update_p(c.n, b, w.Z, Pm, alpha_d, nullptr, s);   // P = Z + beta P
+      if (f32) {
+        // this Z is the next iteration's Zold: the two buffers trade places
+        // (no descriptor of the W solves' operators holds the address of Z)
+        std::swap(w.Z.p, Zold.p);
+        std::swap(w.Z.n, Zold.n);
+      }
       sync(c);   // the host buffer of beta is reused next iteration
     }
     itmax = std::max(itmax, it);

@@ -54,6 +54,12 @@ void l_gather(long tot, const int* sub_idx, const double* X, int b, double* Xs, 
 void l_gather_f32(long tot, const int* sub_idx, const double* X, int b, float* Xs, hipStream_t s);
 void l_scatter(int n, long tot, const int* inv_ptr, const int* inv_sub, const int* inv_loc, const long* sub_ptr,
                const double* Zs, int b, double* Y, double alpha, double beta, hipStream_t s);
+// Y = (scatter of Zs) + A G for a CSR matrix A (n x m) and G (m x b) in one
+// pass (b > 1); false, with nothing launched, where its 16-byte paths do not
+// apply (odd b or unaligned buffers): the caller then runs the two steps
+bool l_scatter_prolong(int n, long tot, const int* inv_ptr, const int* inv_sub, const int* inv_loc,
+                       const long* sub_ptr, const double* Zs, int b, int m, long nnz, const int* rowptr, const int* col,
+                       const double* val, const double* G, double* Y, hipStream_t s);
 // part: max(DOT_CHUNKS_H * b, DOT1_BLOCKS) scratch doubles
 constexpr int DOT_CHUNKS_H = 128;
 constexpr int DOT1_BLOCKS = 2048;  // blocks (and partial sums) of the one-column kernels
