@@ -794,6 +794,43 @@ __global__ __launch_bounds__(256) void k_scatter2(int n, const int* __restrict__
   *y = o;
 }
 
+// Y[i, :] = sum over (s, l) holding i of Zs[sub_off[s] + l, :]
+//           + sum_p val[p] G[col[p], :]   (p over row i of a CSR matrix)
+// The prolongation of the local products and a sparse product added to it in
+// one pass, so Y is written once instead of written, read and written again.
+// Per element the same operations in the same order as k_scatter2 with
+// alpha = 1, beta = 0 followed by the SpMM kernels with alpha = beta = 1
+// (both sums from zero, the second in CSR order, then their sum).
+__global__ __launch_bounds__(256) void k_scatter_prolong2(
+    int n, const int* __restrict__ inv_ptr, const int* __restrict__ inv_sub, const int* __restrict__ inv_loc,
+    const long* __restrict__ sub_ptr, const double2* __restrict__ Zs, int b2, const int* __restrict__ rowptr,
+    const int* __restrict__ col, const double* __restrict__ val, const double2* __restrict__ G,
+    double2* __restrict__ Y, int nchunk) {
+  const long w = (long)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const long i = w / nchunk;
+  if (i >= n) return;
+  const int c = (int)(w - i * nchunk) * 64 + (threadIdx.x & 63);
+  if (c >= b2) return;
+  double ax = 0.0, ay = 0.0;
+  for (int q = inv_ptr[i]; q < inv_ptr[i + 1]; ++q) {
+    const double2 z = Zs[(sub_ptr[inv_sub[q]] + inv_loc[q]) * b2 + c];
+    ax += z.x;
+    ay += z.y;
+  }
+  double gx = 0.0, gy = 0.0;
+  const int pe = rowptr[i + 1];
+  for (int p = rowptr[i]; p < pe; ++p) {
+    const double v = val[p];
+    const double2 g = G[(long)col[p] * b2 + c];
+    gx += v * g.x;
+    gy += v * g.y;
+  }
+  double2 o;
+  o.x = gx + ax;
+  o.y = gy + ay;
+  Y[i * b2 + c] = o;
+}
+
 // Y[i, :] = beta Y[i, :] + alpha sum over (s, l) holding i of Zs[sub_off[s] + l, :]
 __global__ void k_scatter(int n, const int* inv_ptr, const int* inv_sub, const int* inv_loc, const long* sub_ptr,
                           const double* Zs, int b, double* Y, double alpha, double beta) {
@@ -808,8 +845,10 @@ __global__ void k_scatter(int n, const int* inv_ptr, const int* inv_sub, const i
 }
 
 // per-column dot products of row-major X, Y (n x b), two passes with a fixed
-// order: partial sums over DOT_CHUNKS row ranges, then their sum.
-constexpr int DOT_CHUNKS = 128;
+// order: partial sums over DOT_CHUNKS row ranges, then their sum.  The row
+// ranges do not depend on b, so every column's result is independent of the
+// width.
+constexpr int DOT_CHUNKS = DOT_CHUNKS_H;
 __global__ __launch_bounds__(256) void k_coldot_part(int n, int b, const double* X, const double* Y,
                                                      double* part) {
   const int cl = threadIdx.x & 63, rl = threadIdx.x >> 6;
@@ -1530,6 +1569,22 @@ void l_scatter(int n, long tot, const int* inv_ptr, const int* inv_sub, const in
   hipLaunchKernelGGL(k_scatter, dim3(grid1((long)n * b)), dim3(256), 0, s, n, inv_ptr, inv_sub, inv_loc, sub_ptr, Zs,
                      b, Y, alpha, beta);
   AWG_LAUNCH_CHECK();
+}
+bool l_scatter_prolong(int n, long tot, const int* inv_ptr, const int* inv_sub, const int* inv_loc,
+                       const long* sub_ptr, const double* Zs, int b, int m, long nnz, const int* rowptr, const int* col,
+                       const double* val, const double* G, double* Y, hipStream_t s) {
+  if (n == 0 || b == 0) return true;
+  if ((b & 1) || ((uintptr_t)Zs & 15) || ((uintptr_t)Y & 15) || ((uintptr_t)G & 15)) return false;
+  KScope kt("k_scatter_prolong", s,
+            8.0 * (double)tot * b + 8.0 * tot + 8.0 * (n + 1) + 12.0 * nnz + 8.0 * (double)m * b +
+                8.0 * n * (double)b,
+            (double)tot * b + 2.0 * nnz * (double)b);
+  const int b2 = b / 2, nchunk = (int)cdiv(b2, 64);
+  hipLaunchKernelGGL(k_scatter_prolong2, dim3(cdiv((long)n * nchunk, 4)), dim3(256), 0, s, n, inv_ptr, inv_sub,
+                     inv_loc, sub_ptr, (const double2*)Zs, b2, rowptr, col, val, (const double2*)G, (double2*)Y,
+                     nchunk);
+  AWG_LAUNCH_CHECK();
+  return true;
 }
 void l_coldot(int n, int b, const double* X, const double* Y, double* part, double* out, hipStream_t s) {
   if (b == 0) return;
