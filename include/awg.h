@@ -178,6 +178,8 @@ typedef struct {
   double lmin_est;        /* extreme Ritz values of HA from the PCG coefficients */
   double lmax_est;        /* (of the first run of the recurrence) */
   int32_t restarts;       /* restarts from the true residual (see awg_pcg) */
+  int32_t iters_first;    /* iterations of the first run of the recurrence
+                             (the coefficients of lmin_est, lmax_est) */
 } awg_pcg_info;
 
 /* PCG (Saad, Section 9.2) from x0 = 0 with the AWG preconditioner; stops at

@@ -52,7 +52,7 @@ class Options(ctypes.Structure):
 class PCGInfo(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("converged", ctypes.c_int32), ("rel_res", ctypes.c_double),
                 ("rel_res_true", ctypes.c_double), ("lmin_est", ctypes.c_double),
-                ("lmax_est", ctypes.c_double), ("restarts", ctypes.c_int32)]
+                ("lmax_est", ctypes.c_double), ("restarts", ctypes.c_int32), ("iters_first", ctypes.c_int32)]
 
 
 class AWGError(RuntimeError):

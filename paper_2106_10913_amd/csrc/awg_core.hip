@@ -580,7 +580,7 @@ void build_ws(awg_ctx& c, MultiWS& w, int b, bool wops = false) {
   w.G2.ensure(std::max(1, c.n0) * (long)b);
   w.H0.ensure(std::max(1, c.nminus) * (long)b);
   w.H1.ensure(std::max(1, c.nminus) * (long)b);
-  w.dotpart.ensure(std::max<long>(2L * DOT_CHUNKS_H * b, DOT1_BLOCKS));
+  w.dotpart.ensure(std::max<long>(std::max<long>(2L * DOT_CHUNKS_H * b, rb_part_size((int)n, b)), DOT1_BLOCKS));
   w.dots.ensure(2L * b);
   if (b == 1) w.gvpart.alloc((long)GEMV_KSPLIT * std::max(1, c.nminus));
   std::vector<GemmDesc> vt(c.N), vv(c.N), yt(c.N), yy(c.N), pp(c.N);
@@ -774,6 +774,11 @@ void op_r0t(awg_ctx& c, MultiWS& w, double* Yo, double beta, double alpha = 1.0)
   l_scatter(c.n, c.sumns, c.invptr, c.invsub, c.invloc, c.subptr, w.Os, w.b, Yo, alpha, beta, c.s);
 }
 
+// tuning key of the FP32 local product at width b
+std::string p32_key(const awg_ctx& c, int b) {
+  return "restrict:P32:b=" + std::to_string(b) + ":sumns=" + std::to_string(c.sumns) + ":N=" + std::to_string(c.N);
+}
+
 // Yo = sum_s R^sT P^s R^s X: H^NN X with P^s = D^s (A^s_+)^+ D^s (Definition of
 // H^NN, Section 3.3), or H^AS_+ X with P^s = (R^s A_+ R^sT)^{-1} (Section 3.4);
 // with add_r0t, Yo = that + R0^T G1 (the coarse prolongation added while the
@@ -806,8 +811,7 @@ void op_hnn(awg_ctx& c, MultiWS& w, const double* X, double* Yo, bool f32, bool 
         gemm_f32_batched(w.dP32f, c.N, w.b, w.maxns, 1.0, 0.0, c.s, w.flP, w.tilesP32, w.ntilesP32, w.gridP32);
       }
     };
-    const std::string key = "restrict:P32:b=" + std::to_string(w.b) + ":sumns=" + std::to_string(c.sumns) +
-                            ":N=" + std::to_string(c.N);
+    const std::string key = p32_key(c, w.b);
     int v = tune_lookup(key);
     if (v < 0) v = tune_pick(key, 3, run, c.s);
     run(v);
@@ -2334,6 +2338,7 @@ int do_pcg(awg_ctx& c, const double* b, double* x, double tol, int maxit, awg_pc
   awg_pcg_info inf{};
   int status = AWG_OK;
   int it = 0;
+  int first_seg = -1;     // iterations of the first segment (Lanczos estimates)
   if (bn == 0.0 || maxit <= 0) {
     inf.converged = bn == 0.0;
     inf.rel_res = bn == 0.0 ? 0.0 : 1.0;
@@ -2373,7 +2378,6 @@ int do_pcg(awg_ctx& c, const double* b, double* x, double tol, int maxit, awg_pc
       c.s = user;
     }
     double hs[12];
-    int first_seg = -1;     // iterations of the first segment (Lanczos estimates)
     for (;;) {
       for (;;) {
         for (int k = 0; k < PCG_AHEAD; ++k) {
@@ -2431,6 +2435,7 @@ int do_pcg(awg_ctx& c, const double* b, double* x, double tol, int maxit, awg_pc
     }
   }
   inf.iters = it;
+  inf.iters_first = first_seg < 0 ? it : first_seg;
   if (status == AWG_OK && !inf.converged) status = AWG_NOT_CONVERGED;
   if (info) *info = inf;
   return status;

@@ -61,7 +61,7 @@ bool l_scatter_prolong(int n, long tot, const int* inv_ptr, const int* inv_sub, 
                        const long* sub_ptr, const double* Zs, int b, int m, long nnz, const int* rowptr, const int* col,
                        const double* val, const double* G, double* Y, hipStream_t s);
 // part: max(DOT_CHUNKS_H * b, DOT1_BLOCKS) scratch doubles
-constexpr int DOT_CHUNKS_H = 128;
+constexpr int DOT_CHUNKS_H = 256;
 constexpr int DOT1_BLOCKS = 2048;  // blocks (and partial sums) of the one-column kernels
 void l_coldot(int n, int b, const double* X, const double* Y, double* part, double* out, hipStream_t s);
 // one column: q = A p with part[k] = the k-th of DOT1_BLOCKS partial sums of p^T q
@@ -98,7 +98,9 @@ void l_resid_dd(int n, long nnz, const int* rowptr, const int* col, const double
 void l_dot1_part(int n, const double* x, const double* y, double* part, hipStream_t s);
 void l_colaxpby(long rows, int b, const double* X, const double* a, double* Y, const double* bb, double sa, double sb,
                 hipStream_t s);
-// multi-column PCG steps in single passes (part: DOT_CHUNKS_H * b doubles, 2x for l_coldot2):
+// scratch doubles that l_multi_update_xr and l_coldot2 need in part
+long rb_part_size(int n, int b);
+// multi-column PCG steps in single passes (part: rb_part_size(n, b) doubles):
 // X += a P, R -= a Q and rr = column norms^2 of the new R
 void l_multi_update_xr(int n, int b, const double* a, const double* P, double* X, const double* Q, double* R,
                        double* part, double* rr, hipStream_t s);

@@ -847,7 +847,7 @@ __global__ void k_scatter(int n, const int* inv_ptr, const int* inv_sub, const i
 // per-column dot products of row-major X, Y (n x b), two passes with a fixed
 // order: partial sums over DOT_CHUNKS row ranges, then their sum.  The row
 // ranges do not depend on b, so every column's result is independent of the
-// width.
+// width; 256 of them keep several blocks per compute unit down to b = 64.
 constexpr int DOT_CHUNKS = DOT_CHUNKS_H;
 __global__ __launch_bounds__(256) void k_coldot_part(int n, int b, const double* X, const double* Y,
                                                      double* part) {
@@ -866,7 +866,7 @@ __global__ __launch_bounds__(256) void k_coldot_part(int n, int b, const double*
 
 // Multi-column PCG update in one pass: X += a_c P, R -= a_c Q, and the
 // partial sums of R^2 per column over the DOT_CHUNKS row ranges (the same
-// partition and order as k_coldot_part)
+// partition and order as k_coldot_part); the form for b > RB_MAXB
 __global__ __launch_bounds__(256) void k_multi_update_xr(int n, int b, const double* __restrict__ a,
                                                          const double* __restrict__ P, double* __restrict__ X,
                                                          const double* __restrict__ Q, double* __restrict__ R,
@@ -957,6 +957,123 @@ __global__ __launch_bounds__(256) void k_coldot2_part(int n, int b, const double
     part1[(long)chunk * b + c] = (sh[0][0][cl] + sh[0][1][cl]) + (sh[0][2][cl] + sh[0][3][cl]);
     if (Y2) part2[(long)chunk * b + c] = (sh[1][0][cl] + sh[1][1][cl]) + (sh[1][2][cl] + sh[1][3][cl]);
   }
+}
+
+// ---------------------------------------------------------------------------
+// Row-block forms of the W solves' multi-column steps (b <= RB_MAXB).  Block j
+// takes rows [RB_ROWS j, RB_ROWS j + RB_ROWS); its wavefront w the rows
+// RB_ROWS j + w + 4 t, each swept whole (every column, 64 at a time), so the
+// block streams consecutive rows of every operand (rows of up to 16 KB, which
+// the 64-column slabs of k_multi_update_xr only touch in 512-byte pieces:
+// 5.0 against 3.7 TB/s at b = 1652).  Per column a block's partial sum is
+// (s0 + s1) + (s2 + s3) over its wavefronts' sums in row order; the partials
+// are then summed in a fixed order (k_rbsum1, k_rbsum2).  No step depends on
+// b or on the position of the column, so a column's results are the same at
+// any width.
+constexpr int RB_ROWS = 128;
+constexpr int RB_MAXB = 2048;
+constexpr int RB_G = 32;   // groups of block partials summed by k_rbsum1
+
+template <int NK>
+__global__ __launch_bounds__(256) void k_xr_rb(int n, int b, const double* __restrict__ a,
+                                               const double* __restrict__ P, double* __restrict__ X,
+                                               const double* __restrict__ Q, double* __restrict__ R,
+                                               double* __restrict__ part) {
+  const int cl = threadIdx.x & 63;
+  const int rl = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int r0 = blockIdx.x * RB_ROWS, r1 = min(n, r0 + RB_ROWS);
+  double acc[NK];
+#pragma unroll
+  for (int k = 0; k < NK; ++k) acc[k] = 0.0;
+  for (int i = r0 + rl; i < r1; i += 4) {
+    const long base = (long)i * b;
+#pragma unroll
+    for (int k = 0; k < NK; ++k) {
+      const int c = cl + 64 * k;
+      if (c < b) {
+        const long e = base + c;
+        const double ac = a[c];
+        X[e] = ac * P[e] + 1.0 * X[e];
+        const double r = -ac * Q[e] + 1.0 * R[e];
+        R[e] = r;
+        acc[k] += r * r;
+      }
+    }
+  }
+  __shared__ double sh[4][64];
+#pragma unroll
+  for (int k = 0; k < NK; ++k) {
+    sh[rl][cl] = acc[k];
+    __syncthreads();
+    const int c = cl + 64 * k;
+    if (rl == 0 && c < b) part[(long)blockIdx.x * b + c] = (sh[0][cl] + sh[1][cl]) + (sh[2][cl] + sh[3][cl]);
+    __syncthreads();
+  }
+}
+
+// partial sums of X^T Y1 and X^T Y2 (Y2 may be NULL) per row block, as k_xr_rb
+template <int NK>
+__global__ __launch_bounds__(256) void k_coldot2_rb(int n, int b, const double* __restrict__ X,
+                                                    const double* __restrict__ Y1, const double* __restrict__ Y2,
+                                                    double* __restrict__ part1, double* __restrict__ part2) {
+  const int cl = threadIdx.x & 63;
+  const int rl = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int r0 = blockIdx.x * RB_ROWS, r1 = min(n, r0 + RB_ROWS);
+  double a1[NK], a2[NK];
+#pragma unroll
+  for (int k = 0; k < NK; ++k) a1[k] = a2[k] = 0.0;
+  for (int i = r0 + rl; i < r1; i += 4) {
+    const long base = (long)i * b;
+#pragma unroll
+    for (int k = 0; k < NK; ++k) {
+      const int c = cl + 64 * k;
+      if (c < b) {
+        const long e = base + c;
+        const double x = X[e];
+        a1[k] += x * Y1[e];
+        if (Y2) a2[k] += x * Y2[e];
+      }
+    }
+  }
+  __shared__ double sh[2][4][64];
+#pragma unroll
+  for (int k = 0; k < NK; ++k) {
+    sh[0][rl][cl] = a1[k];
+    sh[1][rl][cl] = a2[k];
+    __syncthreads();
+    const int c = cl + 64 * k;
+    if (rl == 0 && c < b) {
+      part1[(long)blockIdx.x * b + c] = (sh[0][0][cl] + sh[0][1][cl]) + (sh[0][2][cl] + sh[0][3][cl]);
+      if (Y2) part2[(long)blockIdx.x * b + c] = (sh[1][0][cl] + sh[1][1][cl]) + (sh[1][2][cl] + sh[1][3][cl]);
+    }
+    __syncthreads();
+  }
+}
+
+// first stage of the fixed-order sum of nb block partials per column: group g
+// of RB_G takes the partials [g nb / RB_G, (g + 1) nb / RB_G), its wavefront w
+// every fourth of them in order, then (s0 + s1) + (s2 + s3)
+__global__ __launch_bounds__(256) void k_rbsum1(int b, int nb, const double* __restrict__ part,
+                                                double* __restrict__ part2) {
+  const int cl = threadIdx.x & 63, rl = threadIdx.x >> 6;
+  const int c = blockIdx.x * 64 + cl, g = blockIdx.y;
+  const int j0 = (int)((long)nb * g / RB_G), j1 = (int)((long)nb * (g + 1) / RB_G);
+  double acc = 0.0;
+  if (c < b)
+    for (int j = j0 + rl; j < j1; j += 4) acc += part[(long)j * b + c];
+  __shared__ double sh[4][64];
+  sh[rl][cl] = acc;
+  __syncthreads();
+  if (rl == 0 && c < b) part2[(long)g * b + c] = (sh[0][cl] + sh[1][cl]) + (sh[2][cl] + sh[3][cl]);
+}
+
+// second stage: the RB_G group sums of each column in order
+__global__ void k_rbsum2(int b, const double* __restrict__ part2, double* __restrict__ out) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= b) return;
+  double acc = 0.0;
+  for (int g = 0; g < RB_G; ++g) acc += part2[(long)g * b + c];
+  out[c] = acc;
 }
 
 // P = Z + beta_c P and, when Zold != NULL, Zold = Z, in one pass over Z
@@ -1599,9 +1716,33 @@ void l_coldot(int n, int b, const double* X, const double* Y, double* part, doub
   hipLaunchKernelGGL(k_coldot_sum, dim3(cdiv(b, 256)), dim3(256), 0, s, b, part, out);
   AWG_LAUNCH_CHECK();
 }
+long rb_part_size(int n, int b) { return (2L * cdiv(n, RB_ROWS) + 2L * RB_G) * b; }
+
+// the fixed-order sum of the nb block partials in part into out (b columns);
+// part2 holds RB_G * b doubles
+static void rb_sum(int b, int nb, const double* part, double* part2, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_rbsum1, dim3(cdiv(b, 64), RB_G), dim3(256), 0, s, b, nb, part, part2);
+  AWG_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_rbsum2, dim3(cdiv(b, 256)), dim3(256), 0, s, b, part2, out);
+  AWG_LAUNCH_CHECK();
+}
+
 void l_multi_update_xr(int n, int b, const double* a, const double* P, double* X, const double* Q, double* R,
                        double* part, double* rr, hipStream_t s) {
   KScope kt("k_multi_update_xr", s, 48.0 * n * (double)b, 5.0 * n * (double)b);
+  if (b <= RB_MAXB && n > 0) {
+    const int nb = (int)cdiv(n, RB_ROWS), nk = (int)cdiv(b, 64);
+    auto go = [&](auto kern) {
+      hipLaunchKernelGGL(kern, dim3(nb), dim3(256), 0, s, n, b, a, P, X, Q, R, part);
+      AWG_LAUNCH_CHECK();
+    };
+    if (nk <= 4) go(k_xr_rb<4>);
+    else if (nk <= 8) go(k_xr_rb<8>);
+    else if (nk <= 16) go(k_xr_rb<16>);
+    else go(k_xr_rb<32>);
+    rb_sum(b, nb, part, part + (long)nb * b, rr, s);
+    return;
+  }
   hipLaunchKernelGGL(k_multi_update_xr, dim3(cdiv(b, 64), DOT_CHUNKS), dim3(256), 0, s, n, b, a, P, X, Q, R, part);
   AWG_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_coldot_sum, dim3(cdiv(b, 256)), dim3(256), 0, s, b, part, rr);
@@ -1610,6 +1751,22 @@ void l_multi_update_xr(int n, int b, const double* a, const double* P, double* X
 void l_coldot2(int n, int b, const double* X, const double* Y1, const double* Y2, double* part, double* out1,
                double* out2, hipStream_t s) {
   KScope kt("k_coldot2", s, (Y2 ? 24.0 : 16.0) * n * (double)b, (Y2 ? 4.0 : 2.0) * n * (double)b);
+  if (b <= RB_MAXB && n > 0) {
+    const int nb = (int)cdiv(n, RB_ROWS), nk = (int)cdiv(b, 64);
+    double* p2 = part + (long)nb * b;
+    double* g = part + 2L * nb * b;   // RB_G * b for each of the two sums
+    auto go = [&](auto kern) {
+      hipLaunchKernelGGL(kern, dim3(nb), dim3(256), 0, s, n, b, X, Y1, Y2, part, p2);
+      AWG_LAUNCH_CHECK();
+    };
+    if (nk <= 4) go(k_coldot2_rb<4>);
+    else if (nk <= 8) go(k_coldot2_rb<8>);
+    else if (nk <= 16) go(k_coldot2_rb<16>);
+    else go(k_coldot2_rb<32>);
+    rb_sum(b, nb, part, g, out1, s);
+    if (Y2) rb_sum(b, nb, p2, g + (long)RB_G * b, out2, s);
+    return;
+  }
   double* part2 = part + (long)DOT_CHUNKS * b;
   hipLaunchKernelGGL(k_coldot2_part, dim3(cdiv(b, 64), DOT_CHUNKS), dim3(256), 0, s, n, b, X, Y1, Y2, part, part2);
   AWG_LAUNCH_CHECK();
