@@ -195,6 +195,28 @@ def paper_x0(E1: float = 1e11, E2: float = 1e7, nu: float = 0.3, layers=SIX_LAYE
     return Workload(prob, subs, tau, 1e-10, "paper_x0", dict(E1=E1, E2=E2, nu=nu))
 
 
+def paper_x0_refined(hinv: int, per_unit: int, E1: float = 1e11, E2: float = 1e7, nu: float = 0.3,
+                     layers=SIX_LAYERS, tau: float = 0.1, L: int = 3):
+    """The problem of paper_x0 on a finer mesh (h = 1/hinv) with every unit
+    square cut into per_unit x per_unit box subdomains (N = (L per_unit)^2)
+    sharing only their interface nodes, so the subdomain size stays that of
+    the paper's mesh when hinv = 21 per_unit."""
+    h = 1.0 / hinv
+    m = L * hinv
+    cen = cell_centroids((m, m), h)
+    Ecell = _layer_E(cen[:, 1], layers, E1, E2)
+    prob = fem.q1_elasticity((m, m), h, Ecell, nu, (0.0, -9.81),
+                             lambda xyz: xyz[:, 0] < 0.5 * h, name=f"paper_x0_h{hinv}_b{per_unit}")
+    lo, hi = [], []
+    d = 1.0 / per_unit
+    for by in range(L * per_unit):
+        for bx in range(L * per_unit):
+            lo.append((bx * d, by * d))
+            hi.append(((bx + 1) * d, (by + 1) * d))
+    subs = part.closed_box_subdomains(prob, lo, hi)
+    return Workload(prob, subs, tau, 1e-10, f"paper_x0_h{hinv}_b{per_unit}", dict(E1=E1, E2=E2, nu=nu))
+
+
 def paper_long(N: int, tau: float = 0.1, hinv: int = 14, E1: float = 1e11, E2: float = 1e7,
                nu: float = 0.3):
     """Long domain [0,N]x[0,1] with two hard layers, h = 1/14 (Section 5)."""
