@@ -253,23 +253,28 @@ MFMA_KERNELS = ("k_gemm",)
 # were taken on; otherwise the bench reports traffic = null.
 TRAFFIC = {
     "k_gemm128_f32_w8:P": {
-        "bytes_per_launch": 5.2950e10,
+        # FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (copy calibration) summed over
+        # the launches of one timed step (widths b = 1652 x 32, 944, 418,
+        # 166 x 2, 16 x 2); per launch = this / the step's launch count (the
+        # tuner may run the two b = 16 launches, 0.25 % of the bytes, in the
+        # persistent variant instead)
+        "bytes_per_step": 1.7438e12,
         "source": "paper_2106_10913_amd/csrc/k_dense.hip",
-        "sha256": "d755ee10f5293f9da217c8f3e0a220be93f1c13bad885d626cc6ecc32d61263f",
+        "sha256": "5c0d19796b853ef1bb1de4d0fb4c14e5f643733b8a350e70b968f4a873fd59e5",
         "workload": "q1_diffusion_64^3_grf_box8^3_overlap1_tau0.1",
     },
 }
 
 
-def measured_traffic(name: str, workload: str):
+def measured_traffic(name: str, workload: str, calls_per_step: float):
     import hashlib
     rec = TRAFFIC.get(name)
-    if rec is None or rec["workload"] != workload:
+    if rec is None or rec["workload"] != workload or calls_per_step <= 0:
         return None
     with open(os.path.join(ROOT, rec["source"]), "rb") as f:
         if hashlib.sha256(f.read()).hexdigest() != rec["sha256"]:
             return None
-    return rec["bytes_per_launch"]
+    return rec["bytes_per_step"] / calls_per_step
 
 
 def kernel_rates(kt: dict, top: int = 20) -> dict:
@@ -312,7 +317,7 @@ def roofline(kt: dict, steps: int, workload: str) -> dict:
         dtype = "f16x3" if f16 else ("f32" if f32 else "f64")
         out = {"kernel": name, "bound": "mfma", "achieved": round(achieved, 3), "peak": peak,
                "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "dtype": dtype,
-               "traffic": measured_traffic(name, workload),
+               "traffic": measured_traffic(name, workload, rec["calls"] / steps),
                "calls_per_step": rec["calls"] / steps, "avg_launch_us": round(avg_us, 2),
                "flops_per_launch": rec["flops"] / rec["calls"]}
         if dtype == "f64":
@@ -326,7 +331,8 @@ def roofline(kt: dict, steps: int, workload: str) -> dict:
         return out
     achieved = rec["bytes"] / (rec["ms"] * 1e-3) / 1e9
     return {"kernel": name, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(name, workload),
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": measured_traffic(name, workload, rec["calls"] / steps),
             "calls_per_step": rec["calls"] / steps,
             "avg_launch_us": round(avg_us, 2), "bytes_per_launch": rec["bytes"] / rec["calls"]}
 

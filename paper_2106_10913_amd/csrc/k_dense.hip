@@ -968,7 +968,7 @@ void gemm_f32_batched(const GemmDescF32* d_desc, int batch, int max_m, int max_n
     if (v < 0 && beta == 0.0) v = tune_pick(key, 2, run, s);
     if (v < 0) v = 0;
   }
-  KScope kt("k_gemm128_f32_w8:P", s, 0.0, flops);
+  KScope kt(v == 1 ? "k_gemm128_f32_w8_persist:P" : "k_gemm128_f32_w8:P", s, 0.0, flops);
   run(v);
 }
 
