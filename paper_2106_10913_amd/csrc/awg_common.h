@@ -54,9 +54,12 @@ double alloc_clock_ms();
 // kept (after a device synchronisation, as hipFree does) and handed out again
 // to a later allocation of at most its size and at least half of it, on the
 // same device.  Repeated set-ups then allocate nothing from the driver, whose
-// large allocations and frees took up to seconds on some calls.  An
-// allocation that fails empties the cache and retries; dev_cache_trim returns
-// every cached block to the driver.
+// large allocations and frees took up to seconds on some calls.  The cache
+// holds at most half of the device's memory (oldest blocks freed first), and
+// before a new block is taken from the driver it is emptied when less than
+// 16 GB would stay free for other allocators (the caller's framework, the
+// runtime's queues and kernel scratch).  An allocation that fails empties the
+// cache and retries; dev_cache_trim returns every cached block to the driver.
 void* dev_alloc(size_t bytes);
 void dev_free(void* p, size_t bytes);
 size_t dev_cache_trim();

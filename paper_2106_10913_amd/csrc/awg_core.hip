@@ -121,7 +121,26 @@ struct CachedBlock {
   int dev;
 };
 std::mutex g_cache_mu;
-std::vector<CachedBlock> g_cache;
+std::vector<CachedBlock> g_cache;   // oldest first
+size_t g_cache_bytes = 0;
+// device memory left to other allocators (the caller's framework, the
+// runtime's queues and kernel scratch) before a new block is taken from the
+// driver: the cache is emptied first when less than this would remain free
+constexpr size_t CACHE_HEADROOM = size_t(16) << 30;
+
+// frees cached blocks, oldest first, until at most keep bytes stay cached
+// (the caller holds g_cache_mu)
+size_t trim_locked(size_t keep) {
+  size_t freed = 0, i = 0;
+  if (g_cache_bytes > keep && !g_cache.empty()) (void)hipDeviceSynchronize();
+  for (; i < g_cache.size() && g_cache_bytes > keep; ++i) {
+    (void)hipFree(g_cache[i].p);
+    g_cache_bytes -= g_cache[i].bytes;
+    freed += g_cache[i].bytes;
+  }
+  g_cache.erase(g_cache.begin(), g_cache.begin() + i);
+  return freed;
+}
 }  // namespace
 
 void* dev_alloc(size_t bytes) {
@@ -137,9 +156,13 @@ void* dev_alloc(size_t bytes) {
     }
     if (best >= 0) {
       void* p = g_cache[best].p;
+      g_cache_bytes -= g_cache[best].bytes;
       g_cache.erase(g_cache.begin() + best);
       return p;
     }
+    size_t fr = 0, tot = 0;
+    if (!g_cache.empty() && hipMemGetInfo(&fr, &tot) == hipSuccess && fr < bytes + CACHE_HEADROOM)
+      trim_locked(0);
   }
   void* p = nullptr;
   if (hipMalloc(&p, bytes) != hipSuccess) {
@@ -158,18 +181,15 @@ void dev_free(void* p, size_t bytes) {
   (void)hipGetDevice(&dev);
   std::lock_guard<std::mutex> lk(g_cache_mu);
   g_cache.push_back(CachedBlock{p, bytes, dev});
+  g_cache_bytes += bytes;
+  // at most half of the device stays cached
+  size_t fr = 0, tot = 0;
+  if (hipMemGetInfo(&fr, &tot) == hipSuccess && g_cache_bytes > tot / 2) trim_locked(tot / 2);
 }
 
 size_t dev_cache_trim() {
   std::lock_guard<std::mutex> lk(g_cache_mu);
-  size_t tot = 0;
-  if (!g_cache.empty()) (void)hipDeviceSynchronize();
-  for (const CachedBlock& b : g_cache) {
-    (void)hipFree(b.p);
-    tot += b.bytes;
-  }
-  g_cache.clear();
-  return tot;
+  return trim_locked(0);
 }
 }  // namespace awg
 

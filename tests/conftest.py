@@ -21,3 +21,18 @@ def gpu_lib():
         pytest.skip("no GPU visible")
     from paper_2106_10913_amd import awg
     return awg
+
+
+@pytest.fixture(autouse=True, scope="module")
+def _release_device_memory():
+    """After each module that used the GPU: return the library's cached device
+    blocks and torch's cached blocks to the driver, so one module's large
+    set-ups do not crowd the device for the next."""
+    yield
+    awg = sys.modules.get("paper_2106_10913_amd.awg")
+    torch = sys.modules.get("torch")
+    if awg is None or torch is None or not torch.cuda.is_initialized():
+        return
+    torch.cuda.synchronize()
+    awg.free_cached_memory()
+    torch.cuda.empty_cache()
