@@ -46,6 +46,19 @@ def main():
     print(f"{args.workload}: n={w.A.shape[0]} nnz={w.A.nnz} N={len(w.subs)} (generated in {t_gen:.1f} s)",
           flush=True)
     tm = {}
+    if args.full:
+        # progress of the W solves (one line per block of columns; the oracle's
+        # arithmetic is untouched)
+        inner = O.pcg_multi
+
+        def pcg_multi_logged(*a, **k):
+            t0 = time.perf_counter()
+            X, its = inner(*a, **k)
+            print(f"  W block of {a[2].shape[1]} columns: iterations max {int(its.max())}, "
+                  f"{time.perf_counter() - t0:.0f} s", flush=True)
+            return X, its
+
+        O.pcg_multi = pcg_multi_logged
     st = O.setup(w.A, w.subs, w.tau, stop_after=None if args.full else "coarse0", timings=tm)
     s = O.stats(st)
     nm = sum(sp_.nstrict for sp_ in st.split)
